@@ -1,0 +1,486 @@
+/*
+ * nis_oracle.c -- plain FP64 CPU oracle of the neural in-scattering hot path
+ * (Fang, Feng, Cui, "A real-time rendering method for high albedo anisotropic
+ * materials with multiple scattering", arXiv 2401.14051).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the reference the HIP library is
+ * checked against.  It is called only from the test-suite, the smoke check and
+ * the benchmark's CPU-baseline leg; the library never links, loads or calls it,
+ * and it shares no code, header, table or helper with the library.
+ *
+ * Everything is computed in double precision with plain loops in the order the
+ * method defines it: no blocking, no fusion, no reordering beyond the
+ * definitions below.  Inputs (density grid, points, directions, weights) are
+ * the float32 values the library receives, promoted to double.
+ *
+ * Conventions (readings of the paper, where it is silent):
+ *  - the medium fills the unit cube [0,1]^3; voxel (ix,iy,iz) of a level with
+ *    edge n has its centre at ((i+1/2)/n); arrays are [z][y][x], x fastest;
+ *  - extinction is mu_t(x) = sigma_t * rho(x) (Sec. III.C.1, eq. 15);
+ *  - l is the unit vector towards the distant light (eq. 16), omega the unit
+ *    camera-ray direction; the single-scatter cosine is omega . l;
+ *  - interpolation is index-clamped multilinear: i0 = floor(c), w = c - i0,
+ *    value = (1-w) A[clamp(i0)] + w A[clamp(i0+1)] along each axis.
+ *
+ * Parity pins: every function is checked in the CPU test-suite against closed
+ * forms, invariants, library routines or brute force (see the tests).  The
+ * end-to-end value of a random network has no printed value in the paper and
+ * is pinned through those parts plus zero- and selector-weight probes.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OM_LAYERS 12          /* 8 diffuse + 4 highlight template layers */
+#define OM_DIFFUSE 8
+#define OM_SITES 225          /* 9 (along the light) x 5 x 5 lattice sites */
+#define OM_FEAT 80            /* 16 channels x 5 positions after the CNN */
+#define OM_STATS 8            /* squeeze vector of eq. (24) */
+#define OM_DESC (OM_LAYERS * (OM_FEAT + OM_STATS) + 1)
+#define OM_GROUP (216 + 8 + 3456 + 16 + 64 + 4 + 64 + 16)
+
+static const double OM_PI = 3.14159265358979323846;
+
+typedef struct {
+    int n, levels;
+    int64_t *off;           /* offset of level m in rho */
+    double *rho;            /* density pyramid, all levels */
+    int has_light;
+    double l[3];            /* unit vector towards the light */
+    int a, b, c, sigma;     /* dominant axis, lateral axes, sign of l_a */
+    double sb, sc;          /* lateral shear l_b/|l_a|, l_c/|l_a| */
+    int *ulo, *uhi, *vlo, *vhi;
+    double **D;             /* path density per level, [J][V][U] */
+} om_medium;
+
+/* ------------------------------------------------------------------ */
+/* Henyey-Greenstein phase function, Sec. III.B.3 eq. (5).  The printed
+ * denominator "1+g^2.2g cos" is read as 1 + g^2 - 2 g cos(theta).          */
+double om_hg(double g, double mu)
+{
+    double den = 1.0 + g * g - 2.0 * g * mu;
+    return (1.0 - g * g) / (4.0 * OM_PI * den * sqrt(den));
+}
+
+static int clampi(int i, int lo, int hi) { return i < lo ? lo : (i > hi ? hi : i); }
+
+/* ------------------------------------------------------------------ */
+/* Density pyramid, Sec. III.B.1: the grid is down-sampled level by level to
+ * 1^3 with the 2x2x2 box mean (the filter the paper leaves unstated).      */
+om_medium *om_create(const float *rho0, int n)
+{
+    if (n < 1 || (n & (n - 1)) != 0) return NULL;
+    om_medium *M = (om_medium *)calloc(1, sizeof(om_medium));
+    int L = 1;
+    while ((1 << (L - 1)) < n) L++;
+    M->n = n;
+    M->levels = L;
+    M->off = (int64_t *)calloc((size_t)L + 1, sizeof(int64_t));
+    for (int m = 0; m < L; m++) {
+        int64_t nm = n >> m;
+        M->off[m + 1] = M->off[m] + nm * nm * nm;
+    }
+    M->rho = (double *)malloc((size_t)M->off[L] * sizeof(double));
+    for (int64_t i = 0; i < (int64_t)n * n * n; i++) M->rho[i] = (double)rho0[i];
+    for (int m = 0; m + 1 < L; m++) {
+        int nf = n >> m, nc = n >> (m + 1);
+        const double *f = M->rho + M->off[m];
+        double *cc = M->rho + M->off[m + 1];
+        for (int z = 0; z < nc; z++)
+            for (int y = 0; y < nc; y++)
+                for (int x = 0; x < nc; x++) {
+                    double s = 0.0;
+                    for (int dz = 0; dz < 2; dz++)
+                        for (int dy = 0; dy < 2; dy++)
+                            for (int dx = 0; dx < 2; dx++)
+                                s += f[((int64_t)(2 * z + dz) * nf + (2 * y + dy)) * nf + (2 * x + dx)];
+                    cc[((int64_t)z * nc + y) * nc + x] = s / 8.0;
+                }
+    }
+    M->ulo = (int *)calloc((size_t)L, sizeof(int));
+    M->uhi = (int *)calloc((size_t)L, sizeof(int));
+    M->vlo = (int *)calloc((size_t)L, sizeof(int));
+    M->vhi = (int *)calloc((size_t)L, sizeof(int));
+    M->D = (double **)calloc((size_t)L, sizeof(double *));
+    return M;
+}
+
+void om_free(om_medium *M)
+{
+    if (!M) return;
+    for (int m = 0; m < M->levels; m++) free(M->D[m]);
+    free(M->D); free(M->ulo); free(M->uhi); free(M->vlo); free(M->vhi);
+    free(M->rho); free(M->off); free(M);
+}
+
+int om_levels(const om_medium *M) { return M->levels; }
+int64_t om_level_offset(const om_medium *M, int m) { return M->off[m]; }
+const double *om_pyramid(const om_medium *M) { return M->rho; }
+
+/* value of level m at integer voxel (x,y,z) with index clamping */
+static double vox(const om_medium *M, int m, int x, int y, int z)
+{
+    int nm = M->n >> m;
+    x = clampi(x, 0, nm - 1); y = clampi(y, 0, nm - 1); z = clampi(z, 0, nm - 1);
+    return M->rho[M->off[m] + ((int64_t)z * nm + y) * nm + x];
+}
+
+/* ------------------------------------------------------------------ */
+/* Light frame: the sweep runs along the dominant axis a of l (lowest index on
+ * ties), with sigma = sign(l_a), lateral axes (b,c) ascending and shears
+ * s = l_lateral / |l_a|.  Slice J = 0 is the slice nearest the light.      */
+static int slice_index(const om_medium *M, int nm, int J) { return M->sigma > 0 ? nm - 1 - J : J; }
+
+static void ray_range(double s, int nm, int *lo, int *hi)
+{
+    double a = (nm - 1) * s;
+    *lo = (int)floor(a < 0.0 ? a : 0.0) - 1;
+    *hi = (int)ceil((double)(nm - 1) + (a > 0.0 ? a : 0.0)) + 1;
+}
+
+/* bilinear density on slice ia of level m at lateral index coordinates (u,v)
+ * along axes (b,c); zero when (u,v) lies outside [-1/2, nm-1/2]^2.          */
+static double slice_sample(const om_medium *M, int m, int ia, double u, double v)
+{
+    int nm = M->n >> m;
+    if (u < -0.5 || u > nm - 0.5 || v < -0.5 || v > nm - 0.5) return 0.0;
+    int iu = (int)floor(u), iv = (int)floor(v);
+    double wu = u - iu, wv = v - iv;
+    double acc = 0.0;
+    for (int dv = 0; dv < 2; dv++)
+        for (int du = 0; du < 2; du++) {
+            int idx[3];
+            idx[M->a] = ia;
+            idx[M->b] = iu + du;
+            idx[M->c] = iv + dv;
+            double w = (du ? wu : 1.0 - wu) * (dv ? wv : 1.0 - wv);
+            acc += w * vox(M, m, idx[0], idx[1], idx[2]);
+        }
+    return acc;
+}
+
+/* Graded transmittance fields, Sec. III.B.1 eq. (1): the path integral of
+ * density from each point towards the light is stored, unscaled by the
+ * coefficient, as a path density D_m(U,V,J) on light-sheared rays: ray (U,V)
+ * crosses slice J at lateral coordinates (U - J sb, V - J sc), and
+ *   D_m(U,V,J) = ds_m * ( sum_{J'<J} r(U,V,J') + r(U,V,J)/2 ),
+ * ds_m = h_m / |l_a|, a trapezoid rule from the light-facing face plane.    */
+int om_set_light(om_medium *M, const float dir[3])
+{
+    double l[3] = {dir[0], dir[1], dir[2]};
+    double nrm = sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]);
+    if (!(nrm > 0.0) || !isfinite(nrm)) return -1;
+    for (int i = 0; i < 3; i++) M->l[i] = l[i] / nrm;
+    int a = 0;
+    for (int i = 1; i < 3; i++)
+        if (fabs(M->l[i]) > fabs(M->l[a])) a = i;
+    M->a = a;
+    M->b = a == 0 ? 1 : 0;
+    M->c = a == 2 ? 1 : 2;
+    M->sigma = M->l[a] > 0.0 ? 1 : -1;
+    M->sb = M->l[M->b] / fabs(M->l[a]);
+    M->sc = M->l[M->c] / fabs(M->l[a]);
+    for (int m = 0; m < M->levels; m++) {
+        int nm = M->n >> m;
+        ray_range(M->sb, nm, &M->ulo[m], &M->uhi[m]);
+        ray_range(M->sc, nm, &M->vlo[m], &M->vhi[m]);
+        int nu = M->uhi[m] - M->ulo[m] + 1, nv = M->vhi[m] - M->vlo[m] + 1;
+        free(M->D[m]);
+        M->D[m] = (double *)malloc((size_t)nu * nv * nm * sizeof(double));
+        double ds = (1.0 / nm) / fabs(M->l[a]);
+        for (int V = M->vlo[m]; V <= M->vhi[m]; V++)
+            for (int U = M->ulo[m]; U <= M->uhi[m]; U++) {
+                double sum = 0.0;
+                for (int J = 0; J < nm; J++) {
+                    double r = slice_sample(M, m, slice_index(M, nm, J), U - J * M->sb, V - J * M->sc);
+                    M->D[m][((int64_t)J * nv + (V - M->vlo[m])) * nu + (U - M->ulo[m])] = ds * (sum + 0.5 * r);
+                    sum += r;
+                }
+            }
+    }
+    M->has_light = 1;
+    return 0;
+}
+
+/* frame[0..3] = a, b, c, sigma; shear[0..1] = sb, sc; l[0..2] */
+void om_light_frame(const om_medium *M, int *frame, double *shear, double *l)
+{
+    frame[0] = M->a; frame[1] = M->b; frame[2] = M->c; frame[3] = M->sigma;
+    shear[0] = M->sb; shear[1] = M->sc;
+    for (int i = 0; i < 3; i++) l[i] = M->l[i];
+}
+
+/* dims[0..4] = U_lo, U_hi, V_lo, V_hi, n_J */
+const double *om_path_density(const om_medium *M, int m, int *dims)
+{
+    dims[0] = M->ulo[m]; dims[1] = M->uhi[m]; dims[2] = M->vlo[m]; dims[3] = M->vhi[m];
+    dims[4] = M->n >> m;
+    return M->D[m];
+}
+
+/* ------------------------------------------------------------------ */
+/* Density at a point x of the unit cube at level m: zero outside the closed
+ * cube, otherwise index-clamped trilinear at grid coordinates x*n_m - 1/2.  */
+double om_sample_rho(const om_medium *M, int m, const double x[3])
+{
+    int nm = M->n >> m;
+    for (int i = 0; i < 3; i++)
+        if (x[i] < 0.0 || x[i] > 1.0) return 0.0;
+    double gx = x[0] * nm - 0.5, gy = x[1] * nm - 0.5, gz = x[2] * nm - 0.5;
+    int ix = (int)floor(gx), iy = (int)floor(gy), iz = (int)floor(gz);
+    double wx = gx - ix, wy = gy - iy, wz = gz - iz;
+    double acc = 0.0;
+    for (int dz = 0; dz < 2; dz++)
+        for (int dy = 0; dy < 2; dy++)
+            for (int dx = 0; dx < 2; dx++) {
+                double w = (dx ? wx : 1.0 - wx) * (dy ? wy : 1.0 - wy) * (dz ? wz : 1.0 - wz);
+                acc += w * vox(M, m, ix + dx, iy + dy, iz + dz);
+            }
+    return acc;
+}
+
+/* Path density towards the light at x, level m: x is mapped to sheared ray
+ * coordinates (U_f, V_f, J_f) and D_m is interpolated trilinearly with index
+ * clamping over its ray and slice ranges.                                   */
+double om_sample_D(const om_medium *M, int m, const double x[3])
+{
+    int nm = M->n >> m;
+    double g[3];
+    for (int i = 0; i < 3; i++) g[i] = x[i] * nm - 0.5;
+    double Jf = M->sigma > 0 ? (nm - 1) - g[M->a] : g[M->a];
+    double Uf = g[M->b] + Jf * M->sb;
+    double Vf = g[M->c] + Jf * M->sc;
+    int nu = M->uhi[m] - M->ulo[m] + 1, nv = M->vhi[m] - M->vlo[m] + 1;
+    int iu = (int)floor(Uf), iv = (int)floor(Vf), ij = (int)floor(Jf);
+    double wu = Uf - iu, wv = Vf - iv, wj = Jf - ij;
+    double acc = 0.0;
+    for (int dj = 0; dj < 2; dj++)
+        for (int dv = 0; dv < 2; dv++)
+            for (int du = 0; du < 2; du++) {
+                int U = clampi(iu + du, M->ulo[m], M->uhi[m]) - M->ulo[m];
+                int V = clampi(iv + dv, M->vlo[m], M->vhi[m]) - M->vlo[m];
+                int J = clampi(ij + dj, 0, nm - 1);
+                double w = (du ? wu : 1.0 - wu) * (dv ? wv : 1.0 - wv) * (dj ? wj : 1.0 - wj);
+                acc += w * M->D[m][((int64_t)J * nv + V) * nu + U];
+            }
+    return acc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Template lattice (Sec. III.B.2, in the light-aligned 12 x (5x5x9) form):
+ * site t = ((q+4)*5 + (j+2))*5 + (i+2) has offset o = i e_b + j e_c + q l/|l_a|
+ * and, in layer k, position p + 2^k h_0 o.  Layers 0-7 form the diffuse
+ * group, 8-11 the highlight group; layer k samples level min(k, L-1).      */
+static void site_offset(const om_medium *M, int t, double o[3])
+{
+    int q = t / 25 - 4, j = (t / 5) % 5 - 2, i = t % 5 - 2;
+    double la = fabs(M->l[M->a]);
+    for (int d = 0; d < 3; d++) o[d] = q * M->l[d] / la;
+    o[M->b] += i;
+    o[M->c] += j;
+}
+
+/* Per-point features of every layer (Sec. III.B.2-4, eq. 1, 8, 15, 24):
+ *   tbar[p][k][t] graded transmittance exp(-lam^(m+1) sigma_t D_m(site)),
+ *   rho [p][k][t] density at the site,
+ *   phi [p][t]    log1p of the phase feature HG(w.d_t) HG(d_t.l), d_t = o/|o|
+ *                 (HG(w.l) at the centre site),
+ *   stats[p][k][8] = mean rho, mean phi, mean tbar, max rho, max phi,
+ *                 max tbar, g, alpha = acos(w.l),
+ *   tp[p] = exp(-sigma_t D_0(p)) (eq. 15), f0[p] = HG(w.l) tp[p] (eq. 19).
+ * Any output pointer may be NULL.                                           */
+void om_features(const om_medium *M, double sigma_t, double g, double lam,
+                 const float *pts, const float *dirs, int64_t np,
+                 double *tbar, double *rho, double *phi, double *stats,
+                 double *tp, double *f0)
+{
+    int L = M->levels;
+    double h0 = 1.0 / M->n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < np; p++) {
+        double x[3], w[3];
+        for (int d = 0; d < 3; d++) { x[d] = pts[3 * p + d]; w[d] = dirs[3 * p + d]; }
+        double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        for (int d = 0; d < 3; d++) w[d] /= wn;
+        double wl = w[0] * M->l[0] + w[1] * M->l[1] + w[2] * M->l[2];
+        double alpha = acos(wl < -1.0 ? -1.0 : (wl > 1.0 ? 1.0 : wl));
+        double ph[OM_SITES];
+        double phmean = 0.0, phmax = -INFINITY;
+        for (int t = 0; t < OM_SITES; t++) {
+            double o[3];
+            site_offset(M, t, o);
+            double on = sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+            double P;
+            if (on == 0.0) {
+                P = om_hg(g, wl);
+            } else {
+                double wd = (w[0] * o[0] + w[1] * o[1] + w[2] * o[2]) / on;
+                double dl = (o[0] * M->l[0] + o[1] * M->l[1] + o[2] * M->l[2]) / on;
+                P = om_hg(g, wd) * om_hg(g, dl);
+            }
+            ph[t] = log1p(P);
+            phmean += ph[t];
+            if (ph[t] > phmax) phmax = ph[t];
+            if (phi) phi[p * OM_SITES + t] = ph[t];
+        }
+        phmean /= OM_SITES;
+        for (int k = 0; k < OM_LAYERS; k++) {
+            int m = k < L - 1 ? k : L - 1;
+            double scale = ldexp(h0, k);
+            double coef = pow(lam, m + 1) * sigma_t;
+            double rs = 0.0, rm = -INFINITY, ts = 0.0, tm = -INFINITY;
+            for (int t = 0; t < OM_SITES; t++) {
+                double o[3], s[3];
+                site_offset(M, t, o);
+                for (int d = 0; d < 3; d++) s[d] = x[d] + scale * o[d];
+                double r = om_sample_rho(M, m, s);
+                double T = exp(-coef * om_sample_D(M, m, s));
+                if (rho) rho[(p * OM_LAYERS + k) * OM_SITES + t] = r;
+                if (tbar) tbar[(p * OM_LAYERS + k) * OM_SITES + t] = T;
+                rs += r; ts += T;
+                if (r > rm) rm = r;
+                if (T > tm) tm = T;
+            }
+            if (stats) {
+                double *v = stats + (p * OM_LAYERS + k) * OM_STATS;
+                v[0] = rs / OM_SITES; v[1] = phmean; v[2] = ts / OM_SITES;
+                v[3] = rm; v[4] = phmax; v[5] = tm; v[6] = g; v[7] = alpha;
+            }
+        }
+        double T0 = exp(-sigma_t * om_sample_D(M, 0, x));
+        if (tp) tp[p] = T0;
+        if (f0) f0[p] = om_hg(g, wl) * T0;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Network.  Parameter block layout (this file's own): for each of the two
+ * groups (diffuse, highlight): w1[8][1][3][3][3], b1[8], w2[16][8][3][3][3],
+ * b2[16], s1[4][16], c1[4], s2[16][4], c2[16]; then for each backbone layer
+ * A_i[out][in] followed by beta_i[out].                                      */
+
+/* 3D-CNN over one layer's transmittance lattice (Sec. III.B.1, Fig. 3): the
+ * 9x5x5 lattice (depth q, height j, width i) goes through conv 3^3 valid
+ * 1->8, ReLU, conv 3^3 valid 8->16, ReLU, giving H[16][5].  Convolution is
+ * cross-correlation with bias.  Then squeeze-excitation channel attention
+ * (Sec. III.C.4, eq. 24-26, with the standard two-FC excitation, ratio 4):
+ * z = mean over the 5 positions, e = sigmoid(s2 relu(s1 z + c1) + c2),
+ * out[c*5+pos] = e[c] * H[c][pos].                                           */
+void om_cnn_se(const double *grp, const double *lattice, double *out80)
+{
+    const double *w1 = grp, *b1 = w1 + 216, *w2 = b1 + 8, *b2 = w2 + 3456;
+    const double *s1 = b2 + 16, *c1 = s1 + 64, *s2 = c1 + 4, *c2 = s2 + 64;
+    double y1[8][7][3][3];
+    for (int o = 0; o < 8; o++)
+        for (int z = 0; z < 7; z++)
+            for (int y = 0; y < 3; y++)
+                for (int x = 0; x < 3; x++) {
+                    double acc = b1[o];
+                    for (int dz = 0; dz < 3; dz++)
+                        for (int dy = 0; dy < 3; dy++)
+                            for (int dx = 0; dx < 3; dx++)
+                                acc += w1[(o * 3 + dz) * 9 + dy * 3 + dx] *
+                                       lattice[((z + dz) * 5 + (y + dy)) * 5 + (x + dx)];
+                    y1[o][z][y][x] = acc > 0.0 ? acc : 0.0;
+                }
+    double H[16][5];
+    for (int o = 0; o < 16; o++)
+        for (int z = 0; z < 5; z++) {
+            double acc = b2[o];
+            for (int c = 0; c < 8; c++)
+                for (int dz = 0; dz < 3; dz++)
+                    for (int dy = 0; dy < 3; dy++)
+                        for (int dx = 0; dx < 3; dx++)
+                            acc += w2[(((o * 8 + c) * 3 + dz) * 3 + dy) * 3 + dx] * y1[c][z + dz][dy][dx];
+            H[o][z] = acc > 0.0 ? acc : 0.0;
+        }
+    double zc[16], hid[4], e[16];
+    for (int c = 0; c < 16; c++) {
+        double s = 0.0;
+        for (int z = 0; z < 5; z++) s += H[c][z];
+        zc[c] = s / 5.0;
+    }
+    for (int r = 0; r < 4; r++) {
+        double acc = c1[r];
+        for (int c = 0; c < 16; c++) acc += s1[r * 16 + c] * zc[c];
+        hid[r] = acc > 0.0 ? acc : 0.0;
+    }
+    for (int c = 0; c < 16; c++) {
+        double acc = c2[c];
+        for (int r = 0; r < 4; r++) acc += s2[c * 4 + r] * hid[r];
+        e[c] = 1.0 / (1.0 + exp(-acc));
+    }
+    for (int c = 0; c < 16; c++)
+        for (int z = 0; z < 5; z++) out80[c * 5 + z] = e[c] * H[c][z];
+}
+
+/* Descriptor of one point: for k = 0..11 the 80 attention-weighted CNN
+ * features of layer k (weights of its group) followed by its squeeze vector,
+ * then the albedo: 12*88 + 1 = 1057 entries.                                */
+void om_descriptor(const double *params, const double *tbar, const double *stats,
+                   double albedo, double *desc)
+{
+    for (int k = 0; k < OM_LAYERS; k++) {
+        const double *grp = params + (k < OM_DIFFUSE ? 0 : OM_GROUP);
+        om_cnn_se(grp, tbar + k * OM_SITES, desc + k * (OM_FEAT + OM_STATS));
+        for (int s = 0; s < OM_STATS; s++)
+            desc[k * (OM_FEAT + OM_STATS) + OM_FEAT + s] = stats[k * OM_STATS + s];
+    }
+    desc[OM_DESC - 1] = albedo;
+}
+
+/* Backbone (Sec. III.C.2, Fig. 6, in MLP form): n_linear Linear layers of
+ * width `width`, ReLU after all but the last; returns the scalar output y.  */
+double om_mlp(const double *params, int width, int n_linear, const double *desc)
+{
+    const double *A = params + 2 * OM_GROUP;
+    double *h = (double *)malloc(sizeof(double) * (width > OM_DESC ? width : OM_DESC));
+    double *nx = (double *)malloc(sizeof(double) * width);
+    memcpy(h, desc, sizeof(double) * OM_DESC);
+    int din = OM_DESC;
+    double y = 0.0;
+    for (int li = 0; li < n_linear; li++) {
+        int dout = li == n_linear - 1 ? 1 : width;
+        const double *beta = A + (int64_t)dout * din;
+        for (int o = 0; o < dout; o++) {
+            double acc = beta[o];
+            for (int i = 0; i < din; i++) acc += A[(int64_t)o * din + i] * h[i];
+            nx[o] = (li == n_linear - 1) ? acc : (acc > 0.0 ? acc : 0.0);
+        }
+        A = beta + dout;
+        if (li == n_linear - 1) y = nx[0];
+        else memcpy(h, nx, sizeof(double) * dout);
+        din = dout;
+    }
+    free(h);
+    free(nx);
+    return y;
+}
+
+/* Whole query: radiance L = I (HG(w.l) T(p) + F), with the network output
+ * decoded from the log space of the loss (Sec. III.C.3, eq. 21, gamma = 4):
+ * F = albedo^gamma * expm1(y).  F0 = HG(w.l) T(p) I is the single-scatter
+ * term of the scattering-order series (eq. 19).  y_out/fhat_out may be NULL. */
+void om_query(const om_medium *M, double sigma_t, double albedo, double g, double lam,
+              double gamma, double radiance, const double *params, int width, int n_linear,
+              const float *pts, const float *dirs, int64_t np,
+              double *L_out, double *y_out, double *fhat_out, double *desc_out)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t p = 0; p < np; p++) {
+        double *tb = (double *)malloc(sizeof(double) * OM_LAYERS * OM_SITES);
+        double st[OM_LAYERS * OM_STATS];
+        double f0;
+        double *desc = desc_out ? desc_out + p * OM_DESC : (double *)malloc(sizeof(double) * OM_DESC);
+        om_features(M, sigma_t, g, lam, pts + 3 * p, dirs + 3 * p, 1, tb, NULL, NULL, st, NULL, &f0);
+        om_descriptor(params, tb, st, albedo, desc);
+        double y = om_mlp(params, width, n_linear, desc);
+        double F = pow(albedo, gamma) * expm1(y);
+        L_out[p] = radiance * (f0 + F);
+        if (y_out) y_out[p] = y;
+        if (fhat_out) fhat_out[p] = F;
+        if (!desc_out) free(desc);
+        free(tb);
+    }
+}

@@ -1,0 +1,491 @@
+"""Pins of the FP64 oracle against closed forms, library routines, brute force
+and invariants -- never against a retyping of its own formulas.
+
+Each test names the passage of the paper the pinned part follows.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.ndimage
+import torch
+
+from oracle import oracle
+from workloads import camera, medium, weights
+
+G_VALUES = (0.0, 0.5, 0.85, 0.9, 0.95, -0.6)
+
+
+# --------------------------------------------------------------------------
+# Henyey-Greenstein phase, Sec. III.B.3 eq. (5)
+
+@pytest.mark.parametrize("g", G_VALUES)
+def test_hg_normalises_over_the_sphere(g):
+    # a phase function integrates to one over the sphere: 2 pi int_{-1}^{1} f dmu = 1
+    val, _ = scipy.integrate.quad(lambda mu: oracle.hg(g, mu), -1.0, 1.0, limit=400,
+                                  epsabs=1e-13, epsrel=1e-12)
+    assert abs(2.0 * math.pi * val - 1.0) < 1e-9
+
+
+@pytest.mark.parametrize("g", G_VALUES)
+def test_hg_mean_cosine_is_g(g):
+    # the asymmetry parameter is the mean scattering cosine (text after eq. 5)
+    val, _ = scipy.integrate.quad(lambda mu: mu * oracle.hg(g, mu), -1.0, 1.0, limit=400,
+                                  epsabs=1e-13, epsrel=1e-12)
+    assert abs(2.0 * math.pi * val - g) < 1e-9
+
+
+@pytest.mark.parametrize("g", G_VALUES)
+def test_hg_forward_backward_closed_forms(g):
+    assert oracle.hg(g, 1.0) == pytest.approx((1 + g) / (4 * math.pi * (1 - g) ** 2), rel=1e-12)
+    assert oracle.hg(g, -1.0) == pytest.approx((1 - g) / (4 * math.pi * (1 + g) ** 2), rel=1e-12)
+
+
+def test_hg_isotropic_special_case():
+    # eq. (7): g = 0 is the isotropic phase 1/(4 pi)
+    for mu in np.linspace(-1, 1, 11):
+        assert oracle.hg(0.0, mu) == pytest.approx(1.0 / (4.0 * math.pi), rel=1e-15)
+
+
+def test_hg_golden_table():
+    # independently computed values of eq. (5) at mu = +1, -1, 0
+    rows = np.loadtxt(oracle_golden("hg_values.txt"))
+    for g, fwd, bwd, side in rows:
+        assert oracle.hg(g, 1.0) == pytest.approx(fwd, rel=1e-5)
+        assert oracle.hg(g, -1.0) == pytest.approx(bwd, rel=1e-5)
+        assert oracle.hg(g, 0.0) == pytest.approx(side, rel=1e-5)
+
+
+def oracle_golden(name):
+    import os
+    return os.path.join(os.path.dirname(__file__), "golden", name)
+
+
+# --------------------------------------------------------------------------
+# Density pyramid, Sec. III.B.1 (box filter down to 1^3)
+
+def test_pyramid_level_count_and_box_mean():
+    rho = medium.fbm_cloud(16, seed=3)
+    M = oracle.Medium(rho)
+    assert M.levels == 5                       # 16, 8, 4, 2, 1
+    ref = rho.astype(np.float64)
+    for m in range(1, M.levels):
+        n = ref.shape[0] // 2
+        ref = ref.reshape(n, 2, n, 2, n, 2).mean(axis=(1, 3, 5))
+        np.testing.assert_allclose(M.level(m), ref, rtol=1e-13, atol=0)
+
+
+def test_pyramid_conserves_mass():
+    rho = medium.fbm_cloud(32, seed=5)
+    M = oracle.Medium(rho)
+    mass = [M.level(m).sum() * (2.0 ** m / 32) ** 3 for m in range(M.levels)]
+    np.testing.assert_allclose(mass, mass[0], rtol=1e-12)
+
+
+def test_pyramid_keeps_constant_grid_constant():
+    M = oracle.Medium(medium.constant(8, 0.37))
+    for m in range(M.levels):
+        np.testing.assert_allclose(M.level(m), np.float32(0.37), rtol=1e-15)
+
+
+def test_rejects_non_power_of_two():
+    with pytest.raises(ValueError):
+        oracle.Medium(np.zeros((12, 12, 12), np.float32))
+
+
+# --------------------------------------------------------------------------
+# Light frame and graded transmittance fields, eq. (1) and eq. (15)
+
+def test_light_frame_dominant_axis_and_ties():
+    M = oracle.Medium(medium.constant(4, 1.0))
+    M.set_light((0.3, 0.9, 0.3))
+    fr = M.light_frame()
+    assert (fr["a"], fr["b"], fr["c"], fr["sigma"]) == (1, 0, 2, 1)
+    assert fr["sb"] == pytest.approx(1.0 / 3.0, rel=1e-7)
+    M.set_light((1.0, -1.0, 0.5))               # tie |x| = |y| -> lowest index
+    fr = M.light_frame()
+    assert (fr["a"], fr["b"], fr["c"], fr["sigma"]) == (0, 1, 2, 1)
+    M.set_light((0.2, 0.1, -3.0))
+    fr = M.light_frame()
+    assert (fr["a"], fr["b"], fr["c"], fr["sigma"]) == (2, 0, 1, -1)
+    with pytest.raises(ValueError):
+        M.set_light((0.0, 0.0, 0.0))
+
+
+@pytest.mark.parametrize("light", [(0.3, 0.9, 0.3), (-0.7, 0.2, 0.4), (0.1, -0.3, -0.95)])
+def test_homogeneous_slab_path_density(light):
+    # rho == c: inside the box every sample equals c * ds * (J + 1/2)
+    c, n = float(np.float32(0.6)), 16          # the grid holds float32 values
+    M = oracle.Medium(medium.constant(n, c))
+    M.set_light(light)
+    fr = M.light_frame()
+    la = abs(fr["l"][fr["a"]])
+    D, (ulo, uhi, vlo, vhi) = M.path_density(0)
+    ds = (1.0 / n) / la
+    for J in range(n):
+        for V in range(vlo, vhi + 1):
+            for U in range(ulo, uhi + 1):
+                # the ray stays inside laterally for all slices up to J
+                ok = all(-0.5 <= U - Jp * fr["sb"] <= n - 0.5 and -0.5 <= V - Jp * fr["sc"] <= n - 0.5
+                         for Jp in range(J + 1))
+                if ok:
+                    assert D[J, V - vlo, U - ulo] == pytest.approx(c * ds * (J + 0.5), rel=1e-13)
+
+
+@pytest.mark.parametrize("light", [(0.3, 0.9, 0.3), (0.2, -0.1, 0.8)])
+def test_homogeneous_slab_transmittance_closed_form(light):
+    # eq. (15) for a homogeneous medium: T = exp(-sigma_t c d), d the distance
+    # from x to the light-facing face along l (rays that leave through that face)
+    c, n, sigma_t = 0.5, 32, 8.0                # 0.5 is exact in float32
+    M = oracle.Medium(medium.constant(n, c))
+    M.set_light(light)
+    fr = M.light_frame()
+    l = fr["l"]
+    rng = np.random.default_rng(0)
+    checked = 0
+    for x in rng.random((400, 3)) * 0.8 + 0.1:
+        face = 1.0 if l[fr["a"]] > 0 else 0.0
+        t = (face - x[fr["a"]]) / l[fr["a"]]
+        exitp = (x + t * l)[[fr["b"], fr["c"]]]     # lateral exit coordinates
+        if np.all((exitp >= 1.0 / n) & (exitp <= 1 - 1.0 / n)):
+            d = t
+            assert M.sample_D(0, x) == pytest.approx(c * d, rel=1e-12)
+            f = M.features(sigma_t, 0.5, 1.0, x[None].astype(np.float32),
+                           np.array([[0, 0, -1]], np.float32))
+            # tp uses the float32-rounded point; compare with its own distance
+            xf = x.astype(np.float32).astype(np.float64)
+            tf = (face - xf[fr["a"]]) / l[fr["a"]]
+            assert f["tp"][0] == pytest.approx(math.exp(-sigma_t * c * tf), rel=1e-12)
+            checked += 1
+    assert checked > 50
+
+
+@pytest.mark.parametrize("light,axis", [((0, 1, 0), 1), ((0, -1, 0), 1), ((1, 0, 0), 0),
+                                        ((0, 0, -1), 2)])
+def test_axis_aligned_light_reduces_to_cumsum(light, axis):
+    # with zero shear each ray is one voxel column: D = ds (cumsum - own/2)
+    rho = medium.fbm_cloud(16, seed=2)
+    M = oracle.Medium(rho)
+    M.set_light(light)
+    sign = np.sign(sum(light))
+    for m in range(M.levels):
+        lev = M.level(m)
+        nm = lev.shape[0]
+        D, (ulo, uhi, vlo, vhi) = M.path_density(m)
+        assert (ulo, uhi, vlo, vhi) == (-1, nm, -1, nm)
+        # move the sweep axis first ([z][y][x] -> numpy axis 2 - axis), light side first
+        col = np.moveaxis(lev, 2 - axis, 0)
+        if sign > 0:
+            col = col[::-1]
+        ref = (np.cumsum(col, axis=0) - 0.5 * col) / nm
+        # remaining numpy axes are (c, b) = ascending lateral axes reversed
+        got = D[:, 1:nm + 1, 1:nm + 1]
+        np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-15)
+        assert np.all(D[:, 0, :] == 0) and np.all(D[:, :, 0] == 0)
+
+
+def _analytic_rho(x, y, z):
+    return 0.55 + 0.25 * np.sin(2.1 * x + 0.7) * np.cos(1.7 * y - 0.3) + 0.15 * np.sin(2.9 * z + 1.1)
+
+
+def _grid_of(fn, n):
+    c = (np.arange(n) + 0.5) / n
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    return fn(x, y, z).astype(np.float32)
+
+
+def test_path_density_converges_to_ray_integral():
+    # brute force: the continuous optical depth of a smooth field along the
+    # ray to the light-facing face, by adaptive quadrature; the discrete
+    # sheared trapezoid must approach it at second order
+    light = np.array([0.3, 0.9, 0.3])
+    l = light / np.linalg.norm(light)
+    rng = np.random.default_rng(17)
+    pts = np.column_stack([rng.uniform(0.25, 0.45, 16), rng.uniform(0.05, 0.6, 16),
+                           rng.uniform(0.25, 0.45, 16)])
+    ref = []
+    for x in pts:
+        t1 = (1.0 - x[1]) / l[1]
+        f = lambda t: _analytic_rho(*(x + t * l))
+        ref.append(scipy.integrate.quad(f, 0.0, t1, epsabs=1e-13, epsrel=1e-13)[0])
+    ns = (8, 16, 32, 64)
+    errs = []
+    for n in ns:
+        M = oracle.Medium(_grid_of(_analytic_rho, n))
+        M.set_light(light)
+        e = np.array([M.sample_D(0, x) - r for x, r in zip(pts, ref)])
+        errs.append(np.sqrt(np.mean(e * e)))
+    slope = -np.polyfit(np.log(ns), np.log(errs), 1)[0]
+    assert errs[-1] < 1e-4, errs
+    assert slope > 1.8, (errs, slope)
+
+
+# --------------------------------------------------------------------------
+# Template sampling, Sec. III.B.2-4 (light-aligned 12 x 5x5x9 lattice)
+
+def _site_offsets(l):
+    """Lattice offsets o_t in site order for light l (dominant axis a)."""
+    a = int(np.argmax(np.abs(l)))
+    b, c = [i for i in range(3) if i != a]
+    out = []
+    for q in range(-4, 5):
+        for j in range(-2, 3):
+            for i in range(-2, 3):
+                o = q * l / abs(l[a])
+                o = o.copy()
+                o[b] += i
+                o[c] += j
+                out.append(o)
+    return np.array(out)
+
+
+def test_site_density_matches_scipy_trilinear():
+    # site densities against scipy's linear map_coordinates with edge clamping
+    rho = medium.fbm_cloud(32, seed=4)
+    M = oracle.Medium(rho)
+    l = np.array([0.35, -0.8, 0.45])
+    l /= np.linalg.norm(l)
+    M.set_light(l.astype(np.float32))
+    lf = M.light_frame()["l"]
+    pts, dirs = camera.random_points(6, seed=11, lo=0.2, hi=0.8)
+    f = M.features(8.0, 0.7, 0.6, pts, dirs)
+    offs = _site_offsets(lf)
+    for p in range(len(pts)):
+        for k in range(12):
+            m = min(k, M.levels - 1)
+            lev = M.level(m)
+            nm = lev.shape[0]
+            s = pts[p].astype(np.float64)[None, :] + (2.0 ** k / 32) * offs
+            g = s * nm - 0.5
+            vals = scipy.ndimage.map_coordinates(lev, [g[:, 2], g[:, 1], g[:, 0]], order=1,
+                                                 mode="nearest", prefilter=False)
+            inside = np.all((s >= 0) & (s <= 1), axis=1)
+            np.testing.assert_allclose(f["rho"][p, k], np.where(inside, vals, 0.0),
+                                       rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("light", [(0, 1, 0), (0, 0, -1)])
+def test_axis_aligned_sites_hit_raw_voxels(light):
+    # p at a level-m voxel centre, zero shear: the sites of layer m sit on
+    # level-m voxel centres, so every feature is a raw array entry
+    rho = medium.fbm_cloud(16, seed=9)
+    M = oracle.Medium(rho)
+    M.set_light(light)
+    sigma_t, lam = 8.0, 0.6
+    a = int(np.argmax(np.abs(light)))
+    sgn = np.sign(sum(light))
+    b, c = [i for i in range(3) if i != a]
+    for m in range(3):
+        nm = 16 >> m
+        I = np.array([nm // 2 - 1, nm // 2, nm // 2 - 1 + (nm > 2)])
+        p = ((I + 0.5) / nm).astype(np.float32)
+        f = M.features(sigma_t, 0.5, lam, p[None], np.array([[1, 0, 0]], np.float32))
+        D, (ulo, uhi, vlo, vhi) = M.path_density(m)
+        lev = M.level(m)
+        t = 0
+        for q in range(-4, 5):
+            for j in range(-2, 3):
+                for i in range(-2, 3):
+                    v = I.copy()
+                    v[a] += int(q * sgn)
+                    v[b] += i
+                    v[c] += j
+                    if np.all((v >= 0) & (v < nm)):
+                        r = lev[v[2], v[1], v[0]]
+                        J = nm - 1 - v[a] if sgn > 0 else v[a]
+                        T = math.exp(-lam ** (m + 1) * sigma_t * D[J, v[c] - vlo, v[b] - ulo])
+                        assert f["rho"][0, m, t] == pytest.approx(r, rel=1e-13, abs=1e-15)
+                        assert f["tbar"][0, m, t] == pytest.approx(T, rel=1e-12)
+                    t += 1
+
+
+def test_phase_features_closed_forms():
+    # sites on the light axis have d = +-l; lateral sites d = +-e_b, +-e_c
+    M = oracle.Medium(medium.constant(8, 0.3))
+    l = np.array([0.2, 0.3, 0.9])
+    l /= np.linalg.norm(l)
+    M.set_light(l.astype(np.float32))
+    lf = M.light_frame()["l"]
+    g = 0.8
+    w = np.array([0.6, -0.48, 0.64], np.float32)
+    wf = w.astype(np.float64) / np.linalg.norm(w.astype(np.float64))
+    f = M.features(8.0, g, 0.6, np.array([[0.5, 0.5, 0.5]], np.float32), w[None])
+    phi = f["phi"][0]
+    hg = lambda mu: (1 - g * g) / (4 * math.pi * (1 + g * g - 2 * g * mu) ** 1.5)
+    site = lambda q, j, i: ((q + 4) * 5 + (j + 2)) * 5 + (i + 2)
+    wl = float(wf @ lf)
+    # toward the light: d = l, so P = HG(w.l) HG(1); away: d = -l, P = HG(-w.l) HG(-1)
+    assert math.expm1(phi[site(2, 0, 0)]) == pytest.approx(hg(wl) * (1 + g) / (4 * math.pi * (1 - g) ** 2), rel=1e-12)
+    assert math.expm1(phi[site(-3, 0, 0)]) == pytest.approx(hg(-wl) * (1 - g) / (4 * math.pi * (1 + g) ** 2), rel=1e-12)
+    # centre site: the single-scatter phase HG(w.l)
+    assert math.expm1(phi[site(0, 0, 0)]) == pytest.approx(hg(wl), rel=1e-12)
+    # lateral site along +b (b = x for a = z): d = e_x
+    assert math.expm1(phi[site(0, 0, 1)]) == pytest.approx(hg(wf[0]) * hg(lf[0]), rel=1e-12)
+    assert math.expm1(phi[site(0, -1, 0)]) == pytest.approx(hg(-wf[1]) * hg(-lf[1]), rel=1e-12)
+    # squeeze vector: alpha and g entries
+    assert f["stats"][0, 0, 6] == g
+    assert f["stats"][0, 0, 7] == pytest.approx(math.acos(wl), rel=1e-12)
+
+
+def test_isotropic_phase_features():
+    M = oracle.Medium(medium.constant(8, 0.3))
+    M.set_light((0.3, 0.9, 0.3))
+    pts, dirs = camera.random_points(4, seed=1)
+    f = M.features(8.0, 0.0, 0.6, pts, dirs)
+    iso = 1.0 / (4 * math.pi)
+    expect = np.full(225, math.log1p(iso * iso))
+    expect[112] = math.log1p(iso)
+    for p in range(4):
+        np.testing.assert_allclose(f["phi"][p], expect, rtol=1e-14)
+
+
+def test_squeeze_statistics_are_layer_means_and_maxima():
+    M = oracle.Medium(medium.fbm_cloud(16, seed=8))
+    M.set_light((0.5, 0.2, -0.8))
+    pts, dirs = camera.random_points(3, seed=3, lo=0.3, hi=0.7)
+    f = M.features(8.0, 0.6, 0.6, pts, dirs)
+    st = f["stats"]
+    np.testing.assert_allclose(st[:, :, 0], f["rho"].mean(axis=2), rtol=1e-13)
+    np.testing.assert_allclose(st[:, :, 2], f["tbar"].mean(axis=2), rtol=1e-13)
+    np.testing.assert_allclose(st[:, :, 3], f["rho"].max(axis=2), rtol=0)
+    np.testing.assert_allclose(st[:, :, 5], f["tbar"].max(axis=2), rtol=0)
+    np.testing.assert_allclose(st[:, :, 1], f["phi"].mean(axis=1)[:, None].repeat(12, 1), rtol=1e-13)
+    np.testing.assert_allclose(st[:, :, 4], f["phi"].max(axis=1)[:, None].repeat(12, 1), rtol=0)
+
+
+# --------------------------------------------------------------------------
+# 3D-CNN (Fig. 3), squeeze-excitation (eq. 24-26) and backbone (Fig. 6)
+
+def _torch_cnn_se(grp, lattice):
+    x = torch.tensor(lattice, dtype=torch.float64).reshape(1, 1, 9, 5, 5)
+    t = lambda k: torch.tensor(np.asarray(grp[k], np.float64))
+    y = torch.relu(torch.nn.functional.conv3d(x, t("w1"), t("b1")))
+    H = torch.relu(torch.nn.functional.conv3d(y, t("w2"), t("b2")))[0, :, :, 0, 0]   # [16][5]
+    z = H.mean(dim=1)
+    e = torch.sigmoid(t("s2") @ torch.relu(t("s1") @ z + t("c1")) + t("c2"))
+    return (e[:, None] * H).reshape(-1).numpy()
+
+
+def test_cnn_se_matches_torch_conv3d():
+    params = weights.he_init(32, 3, seed=4, bias_scale=0.3)
+    rng = np.random.default_rng(0)
+    for group in ("diffuse", "highlight"):
+        for _ in range(8):
+            lat = rng.random(225)
+            got = oracle.cnn_se(params, group, lat)
+            ref = _torch_cnn_se(params["groups"][group], lat)
+            np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-14)
+
+
+def test_se_with_zero_excitation_halves_features():
+    params = weights.he_init(32, 3, seed=4, bias_scale=0.3)
+    grp = params["groups"]["diffuse"]
+    for k in ("s1", "c1", "s2", "c2"):
+        grp[k] = np.zeros_like(grp[k])
+    lat = np.random.default_rng(1).random(225)
+    x = torch.tensor(lat).reshape(1, 1, 9, 5, 5)
+    t = lambda k: torch.tensor(np.asarray(grp[k], np.float64))
+    H = torch.relu(torch.nn.functional.conv3d(torch.relu(torch.nn.functional.conv3d(
+        x, t("w1"), t("b1"))), t("w2"), t("b2")))[0, :, :, 0, 0]
+    np.testing.assert_allclose(oracle.cnn_se(params, "diffuse", lat), 0.5 * H.reshape(-1).numpy(),
+                               rtol=1e-12, atol=1e-14)
+
+
+def test_descriptor_layout_and_mlp_match_numpy():
+    params = weights.he_init(24, 4, seed=6, bias_scale=0.2)
+    rng = np.random.default_rng(2)
+    tbar = rng.random((12, 225))
+    stats = rng.random((12, 8))
+    desc = oracle.descriptor(params, tbar, stats, 0.93)
+    assert desc.shape == (1057,) and desc[-1] == 0.93
+    for k in range(12):
+        grp = params["groups"]["diffuse" if k < 8 else "highlight"]
+        np.testing.assert_allclose(desc[k * 88:k * 88 + 80], _torch_cnn_se(grp, tbar[k]),
+                                   rtol=1e-12, atol=1e-14)
+        np.testing.assert_array_equal(desc[k * 88 + 80:k * 88 + 88], stats[k])
+    h = desc
+    for i, (A, b) in enumerate(zip(params["A"], params["beta"])):
+        h = A.astype(np.float64) @ h + b.astype(np.float64)
+        if i < len(params["A"]) - 1:
+            h = np.maximum(h, 0.0)
+    assert oracle.mlp(params, desc) == pytest.approx(h[0], rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Whole query: eq. (19) single-scatter term, eq. (21) decode
+
+def _small_setup(n=16, seed=0):
+    rho = medium.fbm_cloud(n, seed=seed)
+    M = oracle.Medium(rho)
+    M.set_light((0.3, 0.9, 0.3))
+    pts, dirs = camera.random_points(24, seed=21, lo=0.05, hi=0.95)
+    return M, pts, dirs
+
+
+def test_zero_weights_give_single_scatter_closed_form():
+    M, pts, dirs = _small_setup()
+    params = weights.zeros_like(weights.he_init(16, 3))
+    out = M.query(params, pts, dirs, sigma_t=8.0, albedo=0.99, g=0.85, radiance=2.5)
+    l = M.light_frame()["l"]
+    for p in range(len(pts)):
+        w = dirs[p].astype(np.float64)
+        w /= np.linalg.norm(w)
+        mu = float(w @ l)
+        hg = (1 - 0.85 ** 2) / (4 * math.pi * (1 + 0.85 ** 2 - 2 * 0.85 * mu) ** 1.5)
+        T = math.exp(-8.0 * M.sample_D(0, pts[p].astype(np.float64)))
+        assert out["y"][p] == 0.0 and out["F"][p] == 0.0
+        assert out["L"][p] == pytest.approx(2.5 * hg * T, rel=1e-12)
+
+
+@pytest.mark.parametrize("entry", [0, 37, 79, 80, 85, 87, 88 * 5 + 12, 88 * 9 + 83, 88 * 11 + 87, 1056])
+def test_selector_weights_return_one_descriptor_entry(entry):
+    M, pts, dirs = _small_setup()
+    params = weights.he_init(8, 4, seed=3)
+    for A in params["A"]:
+        A[:] = 0.0
+    params["A"][0][0, entry] = 1.0
+    params["A"][1][0, 0] = 1.0
+    params["A"][2][0, 0] = 1.0
+    params["A"][3][0, 0] = 1.0
+    out = M.query(params, pts, dirs, sigma_t=8.0, albedo=0.99, g=0.85, want_desc=True)
+    np.testing.assert_array_equal(out["y"], out["desc"][:, entry])
+    np.testing.assert_allclose(out["F"], 0.99 ** 4 * np.expm1(out["y"]), rtol=1e-15)
+
+
+def test_radiance_is_linear_in_light_intensity():
+    M, pts, dirs = _small_setup()
+    params = weights.he_init(16, 3, seed=2)
+    a = M.query(params, pts, dirs, 8.0, 0.99, 0.85, radiance=1.0)["L"]
+    b = M.query(params, pts, dirs, 8.0, 0.99, 0.85, radiance=4.0)["L"]
+    np.testing.assert_array_equal(4.0 * a, b)
+
+
+def test_mirroring_the_dominant_axis_is_invariant():
+    # flip the grid along y, mirror the light and the points: same radiance
+    rho = medium.fbm_cloud(16, seed=12)
+    params = weights.he_init(16, 3, seed=2, bias_scale=0.1)
+    rng = np.random.default_rng(5)
+    pts = (np.floor(rng.random((20, 3)) * 2 ** 20) / 2 ** 20).astype(np.float32)
+    dirs = rng.standard_normal((20, 3)).astype(np.float32)
+    A = oracle.Medium(rho)
+    A.set_light((0.3, 0.9, 0.3))
+    B = oracle.Medium(np.ascontiguousarray(rho[:, ::-1, :]))
+    B.set_light((0.3, -0.9, 0.3))
+    pm, dm = pts.copy(), dirs.copy()
+    pm[:, 1] = 1.0 - pm[:, 1]
+    dm[:, 1] = -dm[:, 1]
+    a = A.query(params, pts, dirs, 8.0, 0.99, 0.85)
+    b = B.query(params, pm, dm, 8.0, 0.99, 0.85)
+    np.testing.assert_allclose(a["L"], b["L"], rtol=1e-12)
+    np.testing.assert_allclose(a["y"], b["y"], rtol=1e-12)
+
+
+def test_batch_order_invariance():
+    M, pts, dirs = _small_setup()
+    params = weights.he_init(16, 3, seed=2)
+    full = M.query(params, pts, dirs, 8.0, 0.99, 0.85)["L"]
+    perm = np.random.default_rng(3).permutation(len(pts))
+    part = M.query(params, pts[perm], dirs[perm], 8.0, 0.99, 0.85)["L"]
+    np.testing.assert_array_equal(full[perm], part)
