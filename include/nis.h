@@ -1,0 +1,210 @@
+/*
+ * nis.h -- C ABI of the neural in-scattering library for AMD MI355X (gfx950).
+ *
+ * The library evaluates the per-shading-point hot path of the neural
+ * in-scattering estimator of Fang, Feng and Cui, "A real-time rendering method
+ * for high albedo anisotropic materials with multiple scattering"
+ * (arXiv 2401.14051):
+ *
+ *   density grid --(box-filter pyramid, Sec. III.B.1)--> graded density fields
+ *   --(light-direction path-density sweep, eq. 1 and eq. 15)--> graded
+ *   transmittance fields --(12-layer template gather, Sec. III.B.2-4, eq. 8,
+ *   eq. 24)--> per-layer lattices and squeeze statistics --(3D-CNN, Fig. 3;
+ *   squeeze-excitation attention, eq. 24-26)--> 1057-entry descriptor
+ *   --(backbone MLP, Fig. 6)--> log-space output y --(decode of eq. 21 plus the
+ *   single-scatter term of eq. 19)--> in-scattered radiance.
+ *
+ * Conventions.  The medium occupies the unit cube [0,1]^3.  Density arrays are
+ * float32 in [z][y][x] order, x fastest.  Extinction is sigma_t * density.
+ * Light directions point TOWARDS the distant light; view directions are the
+ * camera-ray directions (light reaching the camera travels along -dir).
+ *
+ * Errors.  Every call returns an int32_t status (NIS_OK or a negative code) and
+ * never aborts or throws; nis_last_error() returns a thread-local message for
+ * the last failing call on that thread.  A context is used by one host thread
+ * at a time.
+ *
+ * Memory.  The context owns every device allocation it makes.  Host arrays
+ * passed in are copied before the call returns (the caller may free them);
+ * device arrays passed to nis_query_device are borrowed until the work queued
+ * on the given stream has completed.
+ */
+#ifndef NIS_H
+#define NIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nis_ctx nis_ctx;
+
+/* status codes */
+#define NIS_OK 0
+#define NIS_E_INVALID (-1)     /* bad argument: NULL, out of range, non-finite, malformed blob */
+#define NIS_E_STATE (-2)       /* call not valid in the current state (no weights, unknown medium) */
+#define NIS_E_NOMEM (-3)       /* device allocation failed or exceeded the context's budget */
+#define NIS_E_DEVICE (-4)      /* a HIP runtime call failed; the HIP error text is kept */
+#define NIS_E_UNSUPPORTED (-5) /* e.g. FP8 requested without calibration scales */
+#define NIS_E_INTERNAL (-6)
+
+/* network precisions (nis_set_precision) */
+#define NIS_FP32 0   /* every GEMM in float32 (MFMA f32), float32 descriptor */
+#define NIS_BF16 1   /* CNN and backbone GEMMs in bfloat16 x bfloat16 -> float32 */
+#define NIS_FP8 2    /* CNN and backbone GEMMs in FP8-E4M3 (OCP) with per-layer scales */
+
+/* nis_set_light flags */
+#define NIS_EAGER 1  /* run the transmittance sweep now rather than at the next query */
+
+/* Template and descriptor sizes. */
+#define NIS_LAYERS 12        /* 8 diffuse + 4 highlight template layers (Sec. III.B.2, III.C.2) */
+#define NIS_SITES 225        /* 9 x 5 x 5 light-aligned lattice sites per layer */
+#define NIS_STATS 8          /* squeeze vector per layer, eq. (24) */
+#define NIS_DESCRIPTOR 1057  /* 12 x (80 + 8) + albedo */
+
+/*
+ * nis_create / nis_destroy.
+ * Creates a context on HIP device `hip_device` (0-based).  The context owns
+ * one HIP stream used by the synchronous calls.  destroy frees every device
+ * allocation and is a no-op on NULL.
+ * Errors: NIS_E_INVALID (out == NULL or bad device), NIS_E_DEVICE.
+ */
+int32_t nis_create(int32_t hip_device, nis_ctx **out);
+int32_t nis_destroy(nis_ctx *ctx);
+
+/*
+ * nis_load_medium -- Sec. III.B.1: the density field and its down-sampled
+ * graded density fields.
+ * `density`: host array of n*n*n float32 in [z][y][x] order, copied before
+ * return.  n must be a power of two in [1, 1024]; values finite and >= 0.
+ * sigma_t >= 0 is the extinction scale (mu_t = sigma_t * density, eq. 15);
+ * albedo in [0,1] (eta = mu_s / mu_t, Sec. III.C.1); g in (-1,1) is the
+ * Henyey-Greenstein asymmetry (eq. 5).  Builds the 2x2x2 box-mean pyramid down
+ * to 1^3 (log2(n)+1 levels) on the device.  Writes the medium handle.
+ * Errors: NIS_E_INVALID, NIS_E_NOMEM, NIS_E_DEVICE.
+ */
+int32_t nis_load_medium(nis_ctx *ctx, const float *density, int32_t n, float sigma_t,
+                        float albedo, float g, int32_t *medium_out);
+
+/*
+ * nis_rebuild_pyramid -- recomputes levels 1.. of the pyramid from the
+ * resident level 0 on `hip_stream` (NULL = the context stream), without any
+ * host transfer, and marks the transmittance fields stale.  Asynchronous.
+ */
+int32_t nis_rebuild_pyramid(nis_ctx *ctx, int32_t medium, void *hip_stream);
+
+/* Changes sigma_t, albedo and g of a loaded medium.  The stored path density
+ * is independent of sigma_t, so no sweep is needed.  Errors as above. */
+int32_t nis_set_medium_params(nis_ctx *ctx, int32_t medium, float sigma_t, float albedo, float g);
+
+/* Frees a medium's pyramid and transmittance fields. */
+int32_t nis_unload_medium(nis_ctx *ctx, int32_t medium);
+
+/*
+ * nis_set_light -- eq. (16): a distant light from direction `dir` (towards the
+ * light, normalised inside; a zero or non-finite vector is NIS_E_INVALID) with
+ * intensity `radiance`.  Marks the graded transmittance fields (eq. 1) stale;
+ * they are recomputed by the sweep at the next query, or now with NIS_EAGER
+ * (then asynchronous on the context stream).
+ */
+int32_t nis_set_light(nis_ctx *ctx, int32_t medium, const float dir[3], float radiance,
+                      int32_t flags);
+
+/*
+ * nis_set_weights -- network parameters (Fig. 3, Fig. 6, eq. 24-26) as one
+ * little-endian blob, copied before return:
+ *   header (64 bytes): char magic[4] = "NISW"; uint32 version = 1;
+ *     uint32 din = 1057; uint32 width; uint32 n_linear (>= 2); uint32 groups = 2;
+ *     float lambda (graded-field coefficient base, eq. 1); float gamma (log
+ *     decode exponent, eq. 21); uint32 has_fp8_scales; uint32 reserved[7] = 0;
+ *   then float32 tensors, for group 0 (diffuse, layers 0-7) and group 1
+ *     (highlight, layers 8-11) in turn: w1[8][1][3][3][3], b1[8],
+ *     w2[16][8][3][3][3], b2[16], s1[4][16], c1[4], s2[16][4], c2[16];
+ *   then for i = 0..n_linear-1: A_i[out][in], beta_i[out] with in = 1057 for
+ *     i = 0 and width otherwise, out = width except 1 for the last layer;
+ *   then, if has_fp8_scales, float32 activation scales: conv1 input, conv2
+ *     input, and one per backbone layer input (2 + n_linear values).
+ * Errors: NIS_E_INVALID on a malformed blob, NIS_E_NOMEM, NIS_E_DEVICE.
+ */
+int32_t nis_set_weights(nis_ctx *ctx, const void *blob, size_t nbytes);
+
+/* NIS_FP32 (default), NIS_BF16 or NIS_FP8.  NIS_FP8 without scales in the
+ * weight blob is NIS_E_UNSUPPORTED. */
+int32_t nis_set_precision(nis_ctx *ctx, int32_t precision);
+
+/*
+ * nis_query -- in-scattered radiance at shading points (Sec. III.C.2 output
+ * layer; eq. 19, eq. 21):  L = I * (HG(w.l) T(p) + albedo^gamma expm1(y)).
+ * `points`: host float32 [n][3] in unit-cube coordinates (may lie outside);
+ * `view_dirs`: host float32 [n][3], normalised inside; `radiance_out`: host
+ * float32 [n].  Synchronous.  Errors: NIS_E_INVALID (n <= 0, NULL, non-finite
+ * input, zero direction), NIS_E_STATE (unknown medium, no light, no weights).
+ */
+int32_t nis_query(nis_ctx *ctx, int32_t medium, const float *points, const float *view_dirs,
+                  int64_t n, float *radiance_out);
+
+/*
+ * nis_query_device -- as nis_query on device arrays, queued on `hip_stream`
+ * (a hipStream_t; NULL = the context stream) and returning before the work
+ * completes.  Inputs are not validated element-wise.  Scratch memory is owned
+ * by the context; overlapping queries on one context must use one stream.
+ */
+int32_t nis_query_device(nis_ctx *ctx, int32_t medium, const float *d_points,
+                         const float *d_view_dirs, int64_t n, float *d_radiance_out,
+                         void *hip_stream);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *nis_last_error(void);
+
+/* ---- stage access, for testing and profiling --------------------------- */
+
+/*
+ * nis_profile -- when enable != 0, every kernel the context launches is
+ * bracketed by HIP events recorded on the stream it runs on, and durations
+ * are accumulated per kernel name ("pyramid", "sweep", "site_tables",
+ * "features", "backbone").  Synchronizes the device and clears earlier records.
+ */
+int32_t nis_profile(nis_ctx *ctx, int32_t enable);
+
+/* Writes one line "name launches total_ms" per kernel into buf (synchronizes
+ * on the recorded events).  NIS_E_INVALID if buf is too small. */
+int32_t nis_profile_report(nis_ctx *ctx, char *buf, size_t capacity);
+
+/* Number of pyramid levels and the float count of all levels together. */
+int32_t nis_medium_info(nis_ctx *ctx, int32_t medium, int32_t *levels, int64_t *pyramid_floats);
+
+/* Copies all pyramid levels (level 0 first, each n_m^3 [z][y][x]) to host. */
+int32_t nis_debug_pyramid(nis_ctx *ctx, int32_t medium, float *out, int64_t capacity);
+
+/*
+ * Runs the sweep if stale and copies level `level`'s path density
+ * D[J][V][U] to host.  dims[0..4] = U_lo, U_hi, V_lo, V_hi, n_J.  Pass
+ * out = NULL to query dims only.
+ */
+int32_t nis_debug_path_density(nis_ctx *ctx, int32_t medium, int32_t level, float *out,
+                               int64_t capacity, int32_t dims[5]);
+
+/*
+ * Gather stage on device arrays (synchronous): tbar/rho [n][12][225],
+ * phi [n][225], stats [n][12][8], tp [n] (transmittance to the light),
+ * f0 [n] (single-scatter term HG(w.l) T(p)).  Any output may be NULL.
+ */
+int32_t nis_debug_features(nis_ctx *ctx, int32_t medium, const float *d_points,
+                           const float *d_view_dirs, int64_t n, float *d_tbar, float *d_rho,
+                           float *d_phi, float *d_stats, float *d_tp, float *d_f0);
+
+/*
+ * Descriptor and network output on device arrays (synchronous), at the
+ * current precision: desc [n][1057] float32 (the values the backbone reads),
+ * y [n].  Either may be NULL.
+ */
+int32_t nis_debug_network(nis_ctx *ctx, int32_t medium, const float *d_points,
+                          const float *d_view_dirs, int64_t n, float *d_desc, float *d_y);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NIS_H */

@@ -1,0 +1,130 @@
+// k_mlp.hip -- backbone network and output decode for a tile of points.
+//
+// Backbone (Sec. III.C.2, Fig. 6, in MLP form): h_1 = ReLU(A_1 x + beta_1),
+// h_i = ReLU(A_i h_{i-1} + beta_i) for the hidden layers, y = a_out . h + b.
+// Decode (eq. 21 inverted, eq. 19): F = albedo^gamma * expm1(y) and the
+// radiance L = I * (HG(w.l) T(p) + F).
+//
+// Each wave owns 32 rows (points) and keeps their activations in its own LDS
+// slice; every hidden layer is a [32 x K] x [K x W] MFMA GEMM whose output
+// overwrites the slice in place.  Weights are stored [out][in] (zero padded),
+// which is the k-contiguous layout the B fragments read.  The last layer is a
+// float32 dot product per row, fused with the decode.
+#include "launch_args.h"
+#include "mfma.h"
+
+namespace nis {
+
+constexpr int kMlpRows = 32;     // rows per wave
+constexpr int kMlpWaves = 4;
+
+template <int PREC, int NT>
+__global__ void __launch_bounds__(256)
+k_mlp(MlpArgs A)
+{
+    typedef Mfma<PREC> M;
+    typedef typename M::elem E;
+    constexpr int W = NT * 16;
+    constexpr int HS = W + (PREC == kPrecFP32 ? 4 : 8);   // row stride, keeps 16 B alignment
+    __shared__ __attribute__((aligned(16))) E hbuf[kMlpWaves][kMlpRows][HS];
+
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int lr = lane % 16, lg = lane / 16;
+    const int64_t row0 = ((int64_t)blockIdx.x * kMlpWaves + wave) * kMlpRows;
+    E(*h)[HS] = hbuf[wave];
+    const E* x = reinterpret_cast<const E*>(A.x);
+
+    f32x4 acc[2][NT];
+    for (int li = 0; li + 1 < A.n_linear; li++) {
+        const E* Wt = reinterpret_cast<const E*>(A.W[li]);
+        const int K = li == 0 ? kDescPad : W;
+#pragma unroll
+        for (int rt = 0; rt < 2; rt++)
+#pragma unroll
+            for (int ct = 0; ct < NT; ct++) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (li == 0) {
+            int64_t ra = row0 + lr, rb = row0 + 16 + lr;
+            ra = ra < A.npts ? ra : A.npts - 1;
+            rb = rb < A.npts ? rb : A.npts - 1;
+            const E* xa = x + ra * kDescPad + lg * M::KPL;
+            const E* xb = x + rb * kDescPad + lg * M::KPL;
+            for (int k0 = 0; k0 < K; k0 += M::KS) {
+                typename M::frag a0 = M::load(xa + k0), a1 = M::load(xb + k0);
+#pragma unroll
+                for (int ct = 0; ct < NT; ct++) {
+                    typename M::frag b = M::load(Wt + (ct * 16 + lr) * K + k0 + lg * M::KPL);
+                    acc[0][ct] = M::mma(a0, b, acc[0][ct]);
+                    acc[1][ct] = M::mma(a1, b, acc[1][ct]);
+                }
+            }
+        } else {
+            for (int k0 = 0; k0 < K; k0 += M::KS) {
+                typename M::frag a0 = M::load(&h[lr][k0 + lg * M::KPL]);
+                typename M::frag a1 = M::load(&h[16 + lr][k0 + lg * M::KPL]);
+#pragma unroll
+                for (int ct = 0; ct < NT; ct++) {
+                    typename M::frag b = M::load(Wt + (ct * 16 + lr) * K + k0 + lg * M::KPL);
+                    acc[0][ct] = M::mma(a0, b, acc[0][ct]);
+                    acc[1][ct] = M::mma(a1, b, acc[1][ct]);
+                }
+            }
+        }
+        const float* bias = A.bias[li];
+#pragma unroll
+        for (int ct = 0; ct < NT; ct++) {
+            const float bb = bias[ct * 16 + lr];
+#pragma unroll
+            for (int rt = 0; rt < 2; rt++)
+#pragma unroll
+                for (int e = 0; e < 4; e++)
+                    h[rt * 16 + lg * 4 + e][ct * 16 + lr] = M::cvt(fmaxf(acc[rt][ct][e] + bb, 0.f));
+        }
+        __syncthreads();
+    }
+    // last layer + decode, one row per lane
+    if (lane < kMlpRows) {
+        const int64_t row = row0 + lane;
+        float y = A.bout;
+        for (int k = 0; k < W; k++) y += (float)h[lane][k] * A.wout[k];
+        if (row < A.npts) {
+            if (A.y_out) A.y_out[row] = y;
+            if (A.out) A.out[row] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
+        }
+    }
+}
+
+template <int PREC>
+static hipError_t launch_mlp_prec(const MlpArgs& a, hipStream_t s)
+{
+    int blocks = (int)((a.npts + kMlpWaves * kMlpRows - 1) / (kMlpWaves * kMlpRows));
+    dim3 g(blocks), b(256);
+    switch (a.wpad / 16) {
+    case 1: hipLaunchKernelGGL((k_mlp<PREC, 1>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_mlp<PREC, 2>), g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_mlp<PREC, 4>), g, b, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_mlp<PREC, 8>), g, b, 0, s, a); break;
+    case 13: hipLaunchKernelGGL((k_mlp<PREC, 13>), g, b, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_mlp<PREC, 16>), g, b, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Padded width the kernel is instantiated for: the smallest of
+// 16, 32, 64, 128, 208, 256 that holds `width`.
+int mlp_padded_width(int width)
+{
+    static const int sizes[] = {16, 32, 64, 128, 208, 256};
+    for (int s : sizes)
+        if (width <= s) return s;
+    return -1;
+}
+
+hipError_t launch_mlp(int prec, const MlpArgs& a, hipStream_t s)
+{
+    if (a.npts <= 0) return hipSuccess;
+    if (prec == kPrecBF16) return launch_mlp_prec<kPrecBF16>(a, s);
+    return launch_mlp_prec<kPrecFP32>(a, s);
+}
+
+}  // namespace nis

@@ -1,0 +1,152 @@
+// k_volume.hip -- density pyramid and light-direction path-density sweep.
+//
+// Pyramid (Sec. III.B.1): each coarser level is the 2x2x2 box mean of the
+// level below, down to 1^3.
+//
+// Sweep (eq. 1 with the extinction of eq. 15): for every level m and every
+// light-sheared ray (U,V) the kernel walks the n_m slices J from the
+// light-facing face and writes the path density
+//     D_m(U,V,J) = ds_m * ( sum_{J'<J} r(J') + r(J)/2 ),
+// where r(J) is the bilinear density on slice J at lateral index coordinates
+// (U - J sb, V - J sc), or 0 outside [-1/2, n_m - 1/2].  The graded
+// transmittance exp(-lambda^(m+1) sigma_t D) is applied at lookup time, so
+// the field does not depend on sigma_t.  The running sum is compensated
+// (Neumaier) float32.  One lane per ray, lanes along U: for a light dominated
+// by y or z the lateral axis b is x, so neighbouring lanes read neighbouring
+// voxels and write neighbouring D entries.
+#include "launch_args.h"
+
+namespace nis {
+
+__global__ void __launch_bounds__(256)
+k_mip(const float* __restrict__ fine, float* __restrict__ coarse, int nc)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)nc * nc * nc;
+    if (i >= total) return;
+    int x = (int)(i % nc);
+    int y = (int)((i / nc) % nc);
+    int z = (int)(i / ((int64_t)nc * nc));
+    int64_t nf = 2 * (int64_t)nc;
+    const float* f = fine + ((2 * z) * nf + 2 * y) * nf + 2 * x;
+    float2 a = *reinterpret_cast<const float2*>(f);
+    float2 b = *reinterpret_cast<const float2*>(f + nf);
+    float2 c = *reinterpret_cast<const float2*>(f + nf * nf);
+    float2 d = *reinterpret_cast<const float2*>(f + nf * nf + nf);
+    float s = ((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y));
+    coarse[i] = s * 0.125f;
+}
+
+// (U - J s) evaluated as a product then a difference, each rounded once: the
+// in-range test below must be decided exactly as the definition states it.
+__device__ __forceinline__ double lateral(int U, int J, double s)
+{
+#pragma clang fp contract(off)
+    return (double)U - (double)J * s;
+}
+
+struct SweepArgs {
+    int64_t ray_off[kMaxLevels + 1];   // prefix sums of rays per level
+};
+
+__global__ void __launch_bounds__(256)
+k_sweep(MediumView mv, SweepArgs sa)
+{
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= sa.ray_off[mv.levels]) return;
+    int m = 0;
+    while (m + 1 < mv.levels && gid >= sa.ray_off[m + 1]) m++;
+    const Level lv = mv.lev[m];
+    int64_t local = gid - sa.ray_off[m];
+    int iu = (int)(local % lv.nu), iv = (int)(local / lv.nu);
+    int U = lv.ulo + iu, V = lv.vlo + iv;
+    const int n = lv.n;
+    const float* rho = mv.rho + lv.rho_off;
+    float* D = mv.D + lv.d_off + (int64_t)iv * lv.nu + iu;
+    const int64_t plane = (int64_t)lv.nu * lv.nv;
+    int64_t st[3] = {1, n, (int64_t)n * n};
+    const int64_t sta = st[mv.a], stb = st[mv.b], stc = st[mv.c];
+    const double hi = n - 0.5;
+    float sum = 0.f, comp = 0.f;
+#pragma unroll 4
+    for (int J = 0; J < n; J++) {
+        int ia = mv.sigma > 0 ? n - 1 - J : J;
+        double u = lateral(U, J, mv.sb);
+        double v = lateral(V, J, mv.sc);
+        float r = 0.f;
+        if (u >= -0.5 && u <= hi && v >= -0.5 && v <= hi) {
+            double fu = floor(u), fv = floor(v);
+            int u0 = (int)fu, v0 = (int)fv;
+            float wu = (float)(u - fu), wv = (float)(v - fv);
+            int u1 = min(u0 + 1, n - 1), v1 = min(v0 + 1, n - 1);
+            u0 = max(u0, 0);
+            v0 = max(v0, 0);
+            const float* s = rho + ia * sta;
+            float r00 = s[u0 * stb + v0 * stc], r10 = s[u1 * stb + v0 * stc];
+            float r01 = s[u0 * stb + v1 * stc], r11 = s[u1 * stb + v1 * stc];
+            float r0 = r00 + wu * (r10 - r00);
+            float r1 = r01 + wu * (r11 - r01);
+            r = r0 + wv * (r1 - r0);
+        }
+        D[J * plane] = lv.ds * ((sum + comp) + 0.5f * r);
+        float t = sum + r;
+        comp += fabsf(sum) >= fabsf(r) ? (sum - t) + r : (r - t) + sum;
+        sum = t;
+    }
+}
+
+// Per-light lattice tables: unit offset directions d_t = o_t / |o_t| and the
+// incident-side phase HG(d_t . l) of the phase feature (eq. 8) for the
+// current g; the centre site (o = 0) has no direction.
+__global__ void k_site_tables(MediumView mv, SiteTables* tab)
+{
+    const int t = threadIdx.x;
+    if (t >= kSites) return;
+    const int qi = t / 25, j = (t / 5) % 5 - 2, i = t % 5 - 2;
+    double o[3];
+    for (int d = 0; d < 3; d++) o[d] = mv.qoff[d][qi];
+    o[mv.b] += i;
+    o[mv.c] += j;
+    const double on = sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+    if (on == 0.0) {
+        for (int d = 0; d < 3; d++) tab->dir[t][d] = 0.f;
+        tab->hg_dl[t] = 0.f;
+        return;
+    }
+    const double dl = (o[0] * mv.l[0] + o[1] * mv.l[1] + o[2] * mv.l[2]) / on;
+    const double den = mv.hg_a - mv.hg_b * dl;
+    for (int d = 0; d < 3; d++) tab->dir[t][d] = (float)(o[d] / on);
+    tab->hg_dl[t] = (float)(mv.hg_k / (den * sqrt(den)));
+}
+
+hipError_t launch_site_tables(const MediumView& mv, SiteTables* tab, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_site_tables, dim3(1), dim3(256), 0, s, mv, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_pyramid(const float* rho, const Level* lev, int levels, hipStream_t s)
+{
+    for (int m = 0; m + 1 < levels; m++) {
+        int nc = lev[m + 1].n;
+        int64_t total = (int64_t)nc * nc * nc;
+        int blocks = (int)((total + 255) / 256);
+        hipLaunchKernelGGL(k_mip, dim3(blocks), dim3(256), 0, s, rho + lev[m].rho_off,
+                           const_cast<float*>(rho) + lev[m + 1].rho_off, nc);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(const MediumView& mv, hipStream_t s)
+{
+    SweepArgs sa;
+    sa.ray_off[0] = 0;
+    for (int m = 0; m < kMaxLevels; m++)
+        sa.ray_off[m + 1] = sa.ray_off[m] + (m < mv.levels ? (int64_t)mv.lev[m].nu * mv.lev[m].nv : 0);
+    int64_t total = sa.ray_off[mv.levels];
+    int blocks = (int)((total + 255) / 256);
+    hipLaunchKernelGGL(k_sweep, dim3(blocks), dim3(256), 0, s, mv, sa);
+    return hipGetLastError();
+}
+
+}  // namespace nis

@@ -1,0 +1,52 @@
+// launch_args.h -- argument blocks and launchers of the library's kernels.
+#pragma once
+
+#include "nis_internal.h"
+
+namespace nis {
+
+constexpr int kMaxLinear = 16;
+
+struct FeatArgs {
+    MediumView mv;
+    const SiteTables* tab;
+    const float* pts;
+    const float* dirs;
+    int64_t npts;
+    float coef[kLayers];         // lambda^(m+1) * sigma_t per layer
+    const void* w1t[2];          // conv1 weights [16 out][32 k], k = tap, zero padded
+    const void* w2t[2];          // conv2 weights [16 out][224 k], k = c*27 + tap
+    const float* cb[2];          // b1[8] b2[16] s1[64] c1[4] s2[64] c2[16]
+    void* desc;                  // [npts][kDescPad]
+    float* f0;                   // [npts] HG(w.l) T(p)
+    float* dbg_tbar;             // optional [npts][12][225]
+    float* dbg_rho;              // optional [npts][12][225]
+    float* dbg_phi;              // optional [npts][225]
+    float* dbg_stats;            // optional [npts][12][8]
+    float* dbg_tp;               // optional [npts]
+};
+
+struct MlpArgs {
+    const void* x;                   // [npts][kDescPad] descriptor
+    int64_t npts;
+    const void* W[kMaxLinear];       // layer i: [wpad][kin_pad] (kin_pad = kDescPad for i = 0)
+    const float* bias[kMaxLinear];   // [wpad], zero padded
+    const float* wout;               // [wpad] last-layer weights (float32)
+    float bout;
+    int n_linear, wpad;
+    const float* f0;                 // [npts]
+    float* out;                      // [npts] radiance (may be NULL)
+    float* y_out;                    // [npts] network output (may be NULL)
+    float albedo_gamma;              // albedo^gamma
+    float radiance;
+};
+
+hipError_t launch_pyramid(const float* rho, const Level* lev, int levels, hipStream_t s);
+hipError_t launch_sweep(const MediumView& mv, hipStream_t s);
+hipError_t launch_site_tables(const MediumView& mv, SiteTables* tab, hipStream_t s);
+hipError_t launch_features(int prec, const FeatArgs& a, hipStream_t s);
+hipError_t launch_desc_to_f32(int prec, const void* src, float* dst, int64_t n, hipStream_t s);
+hipError_t launch_mlp(int prec, const MlpArgs& a, hipStream_t s);
+int mlp_padded_width(int width);
+
+}  // namespace nis

@@ -1,0 +1,867 @@
+// nis_api.cpp -- host runtime behind the C ABI declared in include/nis.h.
+//
+// Owns the device memory of every medium (density pyramid, path-density
+// fields, per-light site tables), the packed network weights for each
+// precision, and the per-context workspace, and queues the kernels on HIP
+// streams.  Double-precision set-up values (light frame, lattice offsets,
+// per-layer coefficients) are computed here term by term; this file is built
+// with -ffp-contract=off so that each product and sum is rounded once.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/nis.h"
+#include "launch_args.h"
+
+using namespace nis;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Error {
+    int32_t code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int32_t code, const std::string& msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return;
+    if (e == hipErrorOutOfMemory) fail(NIS_E_NOMEM, std::string(what) + ": out of device memory");
+    fail(NIS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class F> int32_t guard(F&& f)
+{
+    try {
+        f();
+        g_err.clear();
+        return NIS_OK;
+    } catch (const Error& e) {
+        g_err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return NIS_E_NOMEM;
+    } catch (...) {
+        g_err = "internal error";
+        return NIS_E_INTERNAL;
+    }
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    void reserve(size_t nbytes, const char* what)
+    {
+        if (nbytes <= bytes) return;
+        release();
+        hip_check(hipMalloc(&p, nbytes), what);
+        bytes = nbytes;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+uint16_t bf16_bits(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);   // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                                              // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+struct Medium {
+    int n = 0, levels = 0;
+    float sigma_t = 0, albedo = 0, g = 0;
+    Level lev[kMaxLevels] = {};
+    DevBuf rho, D, tab;
+    int64_t rho_floats = 0;
+    bool has_light = false, stale = true, tab_stale = true;
+    double l[3] = {0, 0, 0};
+    float radiance = 1.f;
+    int a = 0, b = 1, c = 2, sigma = 1;
+    double sb = 0, sc = 0, la = 1;
+    double qoff[3][9] = {};
+};
+
+struct PackedNet {
+    DevBuf w1t[2], w2t[2], cb[2];
+    DevBuf W[16], bias[16], wout;
+};
+
+struct Net {
+    int width = 0, n_linear = 0, wpad = 0;
+    float lam = 0.6f, gamma = 4.f;
+    bool has_fp8 = false;
+    std::vector<float> groups[2];      // 3844 floats each, blob order
+    std::vector<std::vector<float>> A, beta;
+    std::vector<float> fp8_scales;
+    PackedNet packed[2];               // fp32, bf16
+};
+
+constexpr int kGroupFloats = 216 + 8 + 3456 + 16 + 64 + 4 + 64 + 16;
+
+// Per-kernel timing with HIP events on the stream each kernel runs on.
+struct Profiler {
+    bool on = false;
+    struct Rec {
+        const char* name;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get()
+    {
+        if (pool.empty()) {
+            hipEvent_t e;
+            hip_check(hipEventCreate(&e), "hipEventCreate");
+            return e;
+        }
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    void clear()
+    {
+        for (auto& r : recs) {
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        recs.clear();
+    }
+    ~Profiler()
+    {
+        clear();
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+thread_local Profiler* g_prof = nullptr;   // profiler of the context this thread is calling into
+
+}  // namespace
+
+struct nis_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::map<int32_t, Medium*> media;
+    int32_t next_id = 1;
+    Net* net = nullptr;
+    int precision = kPrecFP32;
+    DevBuf desc, f0, io;
+    Profiler prof;
+};
+
+namespace {
+
+Medium* get_medium(nis_ctx* ctx, int32_t id)
+{
+    auto it = ctx->media.find(id);
+    if (it == ctx->media.end()) fail(NIS_E_STATE, "unknown medium handle");
+    return it->second;
+}
+
+void check_ctx(nis_ctx* ctx)
+{
+    if (!ctx) fail(NIS_E_INVALID, "context is NULL");
+    g_prof = &ctx->prof;
+    hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+}
+
+bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+void validate_params(float sigma_t, float albedo, float g)
+{
+    if (!(std::isfinite(sigma_t) && sigma_t >= 0.f)) fail(NIS_E_INVALID, "sigma_t must be finite and >= 0");
+    if (!(std::isfinite(albedo) && albedo >= 0.f && albedo <= 1.f)) fail(NIS_E_INVALID, "albedo must be in [0,1]");
+    if (!(std::isfinite(g) && g > -1.f && g < 1.f)) fail(NIS_E_INVALID, "g must be in (-1,1)");
+}
+
+void ray_range(double s, int nm, int* lo, int* hi)
+{
+    double a = (nm - 1) * s;
+    *lo = (int)std::floor(a < 0.0 ? a : 0.0) - 1;
+    *hi = (int)std::ceil((double)(nm - 1) + (a > 0.0 ? a : 0.0)) + 1;
+}
+
+double hg(double g, double mu)
+{
+    double den = 1.0 + g * g - 2.0 * g * mu;
+    return (1.0 - g * g) / (4.0 * M_PI * den * std::sqrt(den));
+}
+
+// Light frame, ray ranges and site tables (host, double precision).
+void setup_light(Medium* M)
+{
+    const double* l = M->l;
+    int a = 0;
+    for (int i = 1; i < 3; i++)
+        if (std::fabs(l[i]) > std::fabs(l[a])) a = i;
+    M->a = a;
+    M->b = a == 0 ? 1 : 0;
+    M->c = a == 2 ? 1 : 2;
+    M->sigma = l[a] > 0.0 ? 1 : -1;
+    M->la = std::fabs(l[a]);
+    M->sb = l[M->b] / M->la;
+    M->sc = l[M->c] / M->la;
+    for (int d = 0; d < 3; d++)
+        for (int qi = 0; qi < 9; qi++) M->qoff[d][qi] = (qi - 4) * l[d] / M->la;
+    int64_t off = 0;
+    for (int m = 0; m < M->levels; m++) {
+        Level& lv = M->lev[m];
+        int uhi, vhi;
+        ray_range(M->sb, lv.n, &lv.ulo, &uhi);
+        ray_range(M->sc, lv.n, &lv.vlo, &vhi);
+        lv.nu = uhi - lv.ulo + 1;
+        lv.nv = vhi - lv.vlo + 1;
+        lv.d_off = off;
+        lv.ds = (float)((1.0 / lv.n) / M->la);
+        off += (int64_t)lv.nu * lv.nv * lv.n;
+    }
+    M->D.reserve((size_t)off * sizeof(float), "path-density fields");
+    M->tab_stale = true;
+    M->stale = true;
+}
+
+MediumView make_view(const Medium* M, const Net* net)
+{
+    MediumView v;
+    std::memset(&v, 0, sizeof(v));
+    v.rho = M->rho.as<float>();
+    v.D = M->D.as<float>();
+    for (int m = 0; m < M->levels; m++) v.lev[m] = M->lev[m];
+    v.levels = M->levels;
+    v.n0 = M->n;
+    v.a = M->a;
+    v.b = M->b;
+    v.c = M->c;
+    v.sigma = M->sigma;
+    v.sb = M->sb;
+    v.sc = M->sc;
+    for (int d = 0; d < 3; d++) v.l[d] = M->l[d];
+    v.la = M->la;
+    std::memcpy(v.qoff, M->qoff, sizeof(v.qoff));
+    v.sigma_t = M->sigma_t;
+    v.albedo = M->albedo;
+    v.g = M->g;
+    v.radiance = M->radiance;
+    v.lam = net ? net->lam : 0.6f;
+    v.gamma = net ? net->gamma : 4.f;
+    double g = M->g;
+    v.hg_a = 1.0 + g * g;
+    v.hg_b = 2.0 * g;
+    v.hg_k = (1.0 - g * g) / (4.0 * M_PI);
+    return v;
+}
+
+
+template <class F> void timed(const char* name, hipStream_t s, F&& launch)
+{
+    if (!g_prof || !g_prof->on) {
+        hip_check(launch(), name);
+        return;
+    }
+    hipEvent_t a = g_prof->get(), b = g_prof->get();
+    hip_check(hipEventRecord(a, s), "hipEventRecord");
+    hip_check(launch(), name);
+    hip_check(hipEventRecord(b, s), "hipEventRecord");
+    g_prof->recs.push_back({name, a, b});
+}
+
+void refresh_tables(Medium* M, hipStream_t s)
+{
+    if (!M->tab_stale) return;
+    M->tab.reserve(sizeof(SiteTables), "site tables");
+    MediumView mv = make_view(M, nullptr);
+    timed("site_tables", s, [&] { return launch_site_tables(mv, M->tab.as<SiteTables>(), s); });
+    M->tab_stale = false;
+}
+
+void ensure_sweep(Medium* M, hipStream_t s)
+{
+    if (!M->has_light) fail(NIS_E_STATE, "no light set for this medium");
+    if (!M->stale) return;
+    MediumView mv = make_view(M, nullptr);
+    timed("sweep", s, [&] { return launch_sweep(mv, s); });
+    M->stale = false;
+}
+
+// ---- weights --------------------------------------------------------------
+
+struct BlobHeader {
+    char magic[4];
+    uint32_t version, din, width, n_linear, groups;
+    float lam, gamma;
+    uint32_t has_fp8_scales;
+    uint32_t reserved[7];
+};
+static_assert(sizeof(BlobHeader) == 64, "blob header is 64 bytes");
+
+void upload(DevBuf& buf, const void* host, size_t bytes, const char* what)
+{
+    buf.reserve(bytes, what);
+    hip_check(hipMemcpy(buf.p, host, bytes, hipMemcpyHostToDevice), what);
+}
+
+template <class T> void upload_vec(DevBuf& buf, const std::vector<T>& v, const char* what)
+{
+    upload(buf, v.data(), v.size() * sizeof(T), what);
+}
+
+// Pack one precision: conv weights [out][k] zero padded, backbone [out][in]
+// zero padded to the kernel's tile sizes; biases and the last layer stay float32.
+void pack_net(Net* net, int prec)
+{
+    PackedNet& P = net->packed[prec];
+    auto put = [&](DevBuf& buf, const std::vector<float>& v, const char* what) {
+        if (prec == kPrecFP32) {
+            upload_vec(buf, v, what);
+        } else {
+            std::vector<uint16_t> h(v.size());
+            for (size_t i = 0; i < v.size(); i++) h[i] = bf16_bits(v[i]);
+            upload_vec(buf, h, what);
+        }
+    };
+    for (int gi = 0; gi < 2; gi++) {
+        const float* G = net->groups[gi].data();
+        const float *w1 = G, *b1 = w1 + 216, *w2 = b1 + 8, *b2 = w2 + 3456;
+        const float *s1 = b2 + 16, *c1 = s1 + 64, *s2 = c1 + 4, *c2 = s2 + 64;
+        std::vector<float> t1(16 * kConv1K, 0.f), t2(16 * kConv2K, 0.f);
+        for (int o = 0; o < 8; o++)
+            for (int k = 0; k < 27; k++) t1[o * kConv1K + k] = w1[o * 27 + k];
+        for (int o = 0; o < 16; o++)
+            for (int k = 0; k < 216; k++) t2[o * kConv2K + k] = w2[o * 216 + k];
+        put(P.w1t[gi], t1, "conv1 weights");
+        put(P.w2t[gi], t2, "conv2 weights");
+        std::vector<float> cb;
+        cb.insert(cb.end(), b1, b1 + 8);
+        cb.insert(cb.end(), b2, b2 + 16);
+        cb.insert(cb.end(), s1, s1 + 64);
+        cb.insert(cb.end(), c1, c1 + 4);
+        cb.insert(cb.end(), s2, s2 + 64);
+        cb.insert(cb.end(), c2, c2 + 16);
+        upload_vec(P.cb[gi], cb, "attention weights");
+    }
+    const int W = net->width, Wp = net->wpad;
+    for (int li = 0; li + 1 < net->n_linear; li++) {
+        const int din = li == 0 ? kDesc : W, kpad = li == 0 ? kDescPad : Wp;
+        std::vector<float> t((size_t)Wp * kpad, 0.f), bb(Wp, 0.f);
+        for (int o = 0; o < W; o++) {
+            for (int i = 0; i < din; i++) t[(size_t)o * kpad + i] = net->A[li][(size_t)o * din + i];
+            bb[o] = net->beta[li][o];
+        }
+        put(P.W[li], t, "backbone weights");
+        upload_vec(P.bias[li], bb, "backbone biases");
+    }
+    std::vector<float> wo(Wp, 0.f);
+    for (int i = 0; i < W; i++) wo[i] = net->A[net->n_linear - 1][i];
+    upload_vec(P.wout, wo, "output weights");
+}
+
+void free_net(Net* net)
+{
+    if (!net) return;
+    for (auto& P : net->packed) {
+        for (int g = 0; g < 2; g++) {
+            P.w1t[g].release();
+            P.w2t[g].release();
+            P.cb[g].release();
+        }
+        for (auto& b : P.W) b.release();
+        for (auto& b : P.bias) b.release();
+        P.wout.release();
+    }
+    delete net;
+}
+
+// ---- query ----------------------------------------------------------------
+
+constexpr int64_t kChunk = 1 << 21;   // points per feature/backbone pass
+
+size_t desc_elem_bytes(int prec) { return prec == kPrecFP32 ? 4 : 2; }
+
+struct QueryOut {
+    float* radiance = nullptr;
+    float* y = nullptr;
+    float* tbar = nullptr;
+    float* rho = nullptr;
+    float* phi = nullptr;
+    float* stats = nullptr;
+    float* tp = nullptr;
+    float* f0 = nullptr;
+    void* desc = nullptr;     // raw descriptor copy (precision's element type), [n][kDescPad]
+    bool run_mlp = true;
+};
+
+void run_query(nis_ctx* ctx, Medium* M, const float* d_pts, const float* d_dirs, int64_t n,
+               const QueryOut& o, hipStream_t s)
+{
+    Net* net = ctx->net;
+    if (!net) fail(NIS_E_STATE, "no weights set");
+    ensure_sweep(M, s);
+    refresh_tables(M, s);
+    const int prec = ctx->precision;
+    const PackedNet& P = net->packed[prec];
+    const int64_t chunk = n < kChunk ? n : kChunk;
+    ctx->desc.reserve((size_t)chunk * kDescPad * desc_elem_bytes(prec), "descriptor workspace");
+    ctx->f0.reserve((size_t)chunk * sizeof(float), "single-scatter workspace");
+    MediumView mv = make_view(M, net);
+    for (int64_t p0 = 0; p0 < n; p0 += chunk) {
+        const int64_t cn = (n - p0) < chunk ? (n - p0) : chunk;
+        FeatArgs fa;
+        std::memset(&fa, 0, sizeof(fa));
+        fa.mv = mv;
+        fa.tab = M->tab.as<SiteTables>();
+        fa.pts = d_pts + 3 * p0;
+        fa.dirs = d_dirs + 3 * p0;
+        fa.npts = cn;
+        for (int k = 0; k < kLayers; k++) {
+            int m = k < M->levels - 1 ? k : M->levels - 1;
+            fa.coef[k] = (float)(std::pow((double)net->lam, m + 1) * (double)M->sigma_t);
+        }
+        for (int gi = 0; gi < 2; gi++) {
+            fa.w1t[gi] = P.w1t[gi].p;
+            fa.w2t[gi] = P.w2t[gi].p;
+            fa.cb[gi] = P.cb[gi].as<float>();
+        }
+        fa.desc = ctx->desc.p;
+        fa.f0 = o.f0 ? o.f0 + p0 : ctx->f0.as<float>();
+        auto off = [&](float* base, int64_t per) { return base ? base + p0 * per : nullptr; };
+        fa.dbg_tbar = off(o.tbar, kLayers * kSites);
+        fa.dbg_rho = off(o.rho, kLayers * kSites);
+        fa.dbg_phi = off(o.phi, kSites);
+        fa.dbg_stats = off(o.stats, kLayers * kStats);
+        fa.dbg_tp = off(o.tp, 1);
+        timed("features", s, [&] { return launch_features(prec, fa, s); });
+        if (o.desc) {
+            size_t eb = desc_elem_bytes(prec) * kDescPad;
+            hip_check(hipMemcpyAsync((char*)o.desc + p0 * eb, ctx->desc.p, cn * eb,
+                                     hipMemcpyDeviceToDevice, s), "descriptor copy");
+        }
+        if (!o.run_mlp) continue;
+        MlpArgs ma;
+        std::memset(&ma, 0, sizeof(ma));
+        ma.x = ctx->desc.p;
+        ma.npts = cn;
+        for (int li = 0; li + 1 < net->n_linear; li++) {
+            ma.W[li] = P.W[li].p;
+            ma.bias[li] = P.bias[li].as<float>();
+        }
+        ma.wout = P.wout.as<float>();
+        ma.bout = net->beta[net->n_linear - 1][0];
+        ma.n_linear = net->n_linear;
+        ma.wpad = net->wpad;
+        ma.f0 = fa.f0;
+        ma.out = o.radiance ? o.radiance + p0 : nullptr;
+        ma.y_out = o.y ? o.y + p0 : nullptr;
+        ma.albedo_gamma = (float)std::pow((double)M->albedo, (double)net->gamma);
+        ma.radiance = M->radiance;
+        timed("backbone", s, [&] { return launch_mlp(prec, ma, s); });
+    }
+}
+
+}  // namespace
+
+// ---- C ABI ------------------------------------------------------------------
+
+extern "C" {
+
+const char* nis_last_error(void) { return g_err.c_str(); }
+
+int32_t nis_create(int32_t hip_device, nis_ctx** out)
+{
+    return guard([&] {
+        if (!out) fail(NIS_E_INVALID, "out is NULL");
+        *out = nullptr;
+        int count = 0;
+        hip_check(hipGetDeviceCount(&count), "hipGetDeviceCount");
+        if (hip_device < 0 || hip_device >= count) fail(NIS_E_INVALID, "no such HIP device");
+        hip_check(hipSetDevice(hip_device), "hipSetDevice");
+        nis_ctx* ctx = new nis_ctx();
+        ctx->device = hip_device;
+        hipError_t e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete ctx;
+            hip_check(e, "hipStreamCreate");
+        }
+        *out = ctx;
+    });
+}
+
+int32_t nis_destroy(nis_ctx* ctx)
+{
+    if (!ctx) return NIS_OK;
+    return guard([&] {
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+        for (auto& kv : ctx->media) {
+            kv.second->rho.release();
+            kv.second->D.release();
+            kv.second->tab.release();
+            delete kv.second;
+        }
+        free_net(ctx->net);
+        ctx->desc.release();
+        ctx->f0.release();
+        ctx->io.release();
+        (void)hipStreamDestroy(ctx->stream);
+        delete ctx;
+    });
+}
+
+int32_t nis_load_medium(nis_ctx* ctx, const float* density, int32_t n, float sigma_t, float albedo,
+                        float g, int32_t* medium_out)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        if (!density || !medium_out) fail(NIS_E_INVALID, "density or medium_out is NULL");
+        if (n < 1 || n > 1024 || (n & (n - 1)) != 0) fail(NIS_E_INVALID, "n must be a power of two in [1,1024]");
+        validate_params(sigma_t, albedo, g);
+        const int64_t n3 = (int64_t)n * n * n;
+        for (int64_t i = 0; i < n3; i++)
+            if (!(std::isfinite(density[i]) && density[i] >= 0.f)) fail(NIS_E_INVALID, "density must be finite and >= 0");
+        Medium* M = new Medium();
+        try {
+            M->n = n;
+            M->sigma_t = sigma_t;
+            M->albedo = albedo;
+            M->g = g;
+            int L = 1;
+            while ((1 << (L - 1)) < n) L++;
+            M->levels = L;
+            int64_t off = 0;
+            for (int m = 0; m < L; m++) {
+                M->lev[m].n = n >> m;
+                M->lev[m].rho_off = off;
+                int64_t nm = n >> m;
+                off += nm * nm * nm;
+            }
+            M->rho_floats = off;
+            M->rho.reserve((size_t)off * sizeof(float), "density pyramid");
+            hip_check(hipMemcpyAsync(M->rho.p, density, (size_t)n3 * sizeof(float), hipMemcpyHostToDevice,
+                                     ctx->stream), "density upload");
+            hip_check(launch_pyramid(M->rho.as<float>(), M->lev, L, ctx->stream), "pyramid launch");
+            hip_check(hipStreamSynchronize(ctx->stream), "pyramid");
+        } catch (...) {
+            M->rho.release();
+            delete M;
+            throw;
+        }
+        int32_t id = ctx->next_id++;
+        ctx->media[id] = M;
+        *medium_out = id;
+    });
+}
+
+int32_t nis_rebuild_pyramid(nis_ctx* ctx, int32_t medium, void* hip_stream)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        Medium* M = get_medium(ctx, medium);
+        hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+        timed("pyramid", s, [&] { return launch_pyramid(M->rho.as<float>(), M->lev, M->levels, s); });
+        M->stale = true;
+    });
+}
+
+int32_t nis_set_medium_params(nis_ctx* ctx, int32_t medium, float sigma_t, float albedo, float g)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        Medium* M = get_medium(ctx, medium);
+        validate_params(sigma_t, albedo, g);
+        if (g != M->g) M->tab_stale = true;
+        M->sigma_t = sigma_t;
+        M->albedo = albedo;
+        M->g = g;
+    });
+}
+
+int32_t nis_unload_medium(nis_ctx* ctx, int32_t medium)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        Medium* M = get_medium(ctx, medium);
+        hip_check(hipStreamSynchronize(ctx->stream), "unload");
+        M->rho.release();
+        M->D.release();
+        M->tab.release();
+        ctx->media.erase(medium);
+        delete M;
+    });
+}
+
+int32_t nis_set_light(nis_ctx* ctx, int32_t medium, const float dir[3], float radiance, int32_t flags)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        Medium* M = get_medium(ctx, medium);
+        if (!dir || !finite3(dir) || !std::isfinite(radiance)) fail(NIS_E_INVALID, "light must be finite");
+        double l[3] = {dir[0], dir[1], dir[2]};
+        double nrm = std::sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]);
+        if (!(nrm > 0.0)) fail(NIS_E_INVALID, "light direction is zero");
+        for (int d = 0; d < 3; d++) M->l[d] = l[d] / nrm;
+        M->radiance = radiance;
+        M->has_light = true;
+        setup_light(M);
+        if (flags & NIS_EAGER) ensure_sweep(M, ctx->stream);
+    });
+}
+
+int32_t nis_set_weights(nis_ctx* ctx, const void* blob, size_t nbytes)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        if (!blob || nbytes < sizeof(BlobHeader)) fail(NIS_E_INVALID, "weight blob too short");
+        BlobHeader h;
+        std::memcpy(&h, blob, sizeof(h));
+        if (std::memcmp(h.magic, "NISW", 4) != 0 || h.version != 1) fail(NIS_E_INVALID, "bad blob magic/version");
+        if (h.din != (uint32_t)kDesc || h.groups != 2) fail(NIS_E_INVALID, "blob din/groups mismatch");
+        if (h.n_linear < 2 || h.n_linear > 16) fail(NIS_E_INVALID, "n_linear must be in [2,16]");
+        if (h.width < 1 || mlp_padded_width((int)h.width) < 0) fail(NIS_E_INVALID, "unsupported width");
+        if (!(std::isfinite(h.lam) && h.lam > 0.f && h.lam <= 1.f)) fail(NIS_E_INVALID, "lambda must be in (0,1]");
+        if (!(std::isfinite(h.gamma) && h.gamma >= 0.f)) fail(NIS_E_INVALID, "gamma must be >= 0");
+        size_t need = 2 * (size_t)kGroupFloats;
+        std::vector<int> din(h.n_linear), dout(h.n_linear);
+        for (uint32_t i = 0; i < h.n_linear; i++) {
+            din[i] = i == 0 ? kDesc : (int)h.width;
+            dout[i] = i + 1 == h.n_linear ? 1 : (int)h.width;
+            need += (size_t)din[i] * dout[i] + dout[i];
+        }
+        if (h.has_fp8_scales) need += 2 + h.n_linear;
+        if (nbytes != sizeof(BlobHeader) + need * sizeof(float)) fail(NIS_E_INVALID, "blob size mismatch");
+        const float* f = reinterpret_cast<const float*>((const char*)blob + sizeof(BlobHeader));
+        std::vector<float> all(f, f + need);
+        for (float v : all)
+            if (!std::isfinite(v)) fail(NIS_E_INVALID, "blob holds a non-finite value");
+        Net* net = new Net();
+        try {
+            net->width = (int)h.width;
+            net->n_linear = (int)h.n_linear;
+            net->wpad = mlp_padded_width(net->width);
+            net->lam = h.lam;
+            net->gamma = h.gamma;
+            net->has_fp8 = h.has_fp8_scales != 0;
+            size_t pos = 0;
+            for (int gi = 0; gi < 2; gi++) {
+                net->groups[gi].assign(all.begin() + pos, all.begin() + pos + kGroupFloats);
+                pos += kGroupFloats;
+            }
+            for (int i = 0; i < net->n_linear; i++) {
+                size_t na = (size_t)din[i] * dout[i];
+                net->A.emplace_back(all.begin() + pos, all.begin() + pos + na);
+                pos += na;
+                net->beta.emplace_back(all.begin() + pos, all.begin() + pos + dout[i]);
+                pos += dout[i];
+            }
+            if (net->has_fp8) net->fp8_scales.assign(all.begin() + pos, all.end());
+            pack_net(net, kPrecFP32);
+            pack_net(net, kPrecBF16);
+        } catch (...) {
+            free_net(net);
+            throw;
+        }
+        hip_check(hipStreamSynchronize(ctx->stream), "weights");
+        free_net(ctx->net);
+        ctx->net = net;
+    });
+}
+
+int32_t nis_set_precision(nis_ctx* ctx, int32_t precision)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        if (precision == NIS_FP8) fail(NIS_E_UNSUPPORTED, "FP8 network path is not available");
+        if (precision != NIS_FP32 && precision != NIS_BF16) fail(NIS_E_INVALID, "unknown precision");
+        ctx->precision = precision;
+    });
+}
+
+int32_t nis_query_device(nis_ctx* ctx, int32_t medium, const float* d_points, const float* d_dirs, int64_t n,
+                         float* d_out, void* hip_stream)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        if (!d_points || !d_dirs || !d_out || n <= 0) fail(NIS_E_INVALID, "bad query arguments");
+        Medium* M = get_medium(ctx, medium);
+        hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+        QueryOut o;
+        o.radiance = d_out;
+        run_query(ctx, M, d_points, d_dirs, n, o, s);
+    });
+}
+
+int32_t nis_query(nis_ctx* ctx, int32_t medium, const float* points, const float* dirs, int64_t n,
+                  float* radiance_out)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        if (!points || !dirs || !radiance_out || n <= 0) fail(NIS_E_INVALID, "bad query arguments");
+        for (int64_t i = 0; i < n; i++) {
+            if (!finite3(points + 3 * i) || !finite3(dirs + 3 * i)) fail(NIS_E_INVALID, "non-finite query input");
+            const float* d = dirs + 3 * i;
+            if (d[0] == 0.f && d[1] == 0.f && d[2] == 0.f) fail(NIS_E_INVALID, "zero view direction");
+        }
+        Medium* M = get_medium(ctx, medium);
+        if (!ctx->net) fail(NIS_E_STATE, "no weights set");
+        if (!M->has_light) fail(NIS_E_STATE, "no light set for this medium");
+        const size_t bytes = (size_t)n * 7 * sizeof(float);
+        ctx->io.reserve(bytes, "query staging");
+        float* d_pts = ctx->io.as<float>();
+        float* d_dirs = d_pts + 3 * n;
+        float* d_out = d_dirs + 3 * n;
+        hip_check(hipMemcpyAsync(d_pts, points, (size_t)n * 3 * sizeof(float), hipMemcpyHostToDevice, ctx->stream), "upload");
+        hip_check(hipMemcpyAsync(d_dirs, dirs, (size_t)n * 3 * sizeof(float), hipMemcpyHostToDevice, ctx->stream), "upload");
+        QueryOut o;
+        o.radiance = d_out;
+        run_query(ctx, M, d_pts, d_dirs, n, o, ctx->stream);
+        hip_check(hipMemcpyAsync(radiance_out, d_out, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, ctx->stream), "download");
+        hip_check(hipStreamSynchronize(ctx->stream), "query");
+    });
+}
+
+int32_t nis_profile(nis_ctx* ctx, int32_t enable)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        hip_check(hipDeviceSynchronize(), "sync");
+        ctx->prof.clear();
+        ctx->prof.on = enable != 0;
+    });
+}
+
+int32_t nis_profile_report(nis_ctx* ctx, char* buf, size_t capacity)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        if (!buf || capacity == 0) fail(NIS_E_INVALID, "buffer is NULL");
+        std::map<std::string, std::pair<int64_t, double>> agg;
+        for (auto& r : ctx->prof.recs) {
+            hip_check(hipEventSynchronize(r.b), "hipEventSynchronize");
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+            auto& e = agg[r.name];
+            e.first += 1;
+            e.second += ms;
+        }
+        std::string out;
+        char line[160];
+        for (auto& kv : agg) {
+            std::snprintf(line, sizeof(line), "%s %lld %.6f\n", kv.first.c_str(), (long long)kv.second.first,
+                          kv.second.second);
+            out += line;
+        }
+        if (out.size() + 1 > capacity) fail(NIS_E_INVALID, "buffer too small");
+        std::memcpy(buf, out.c_str(), out.size() + 1);
+    });
+}
+
+int32_t nis_medium_info(nis_ctx* ctx, int32_t medium, int32_t* levels, int64_t* pyramid_floats)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        Medium* M = get_medium(ctx, medium);
+        if (levels) *levels = M->levels;
+        if (pyramid_floats) *pyramid_floats = M->rho_floats;
+    });
+}
+
+int32_t nis_debug_pyramid(nis_ctx* ctx, int32_t medium, float* out, int64_t capacity)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        Medium* M = get_medium(ctx, medium);
+        if (!out || capacity < M->rho_floats) fail(NIS_E_INVALID, "output too small");
+        hip_check(hipStreamSynchronize(ctx->stream), "sync");
+        hip_check(hipMemcpy(out, M->rho.p, (size_t)M->rho_floats * sizeof(float), hipMemcpyDeviceToHost), "download");
+    });
+}
+
+int32_t nis_debug_path_density(nis_ctx* ctx, int32_t medium, int32_t level, float* out, int64_t capacity,
+                               int32_t dims[5])
+{
+    return guard([&] {
+        check_ctx(ctx);
+        Medium* M = get_medium(ctx, medium);
+        if (!dims) fail(NIS_E_INVALID, "dims is NULL");
+        if (level < 0 || level >= M->levels) fail(NIS_E_INVALID, "no such level");
+        ensure_sweep(M, ctx->stream);
+        const Level& lv = M->lev[level];
+        dims[0] = lv.ulo;
+        dims[1] = lv.ulo + lv.nu - 1;
+        dims[2] = lv.vlo;
+        dims[3] = lv.vlo + lv.nv - 1;
+        dims[4] = lv.n;
+        if (!out) return;
+        int64_t count = (int64_t)lv.nu * lv.nv * lv.n;
+        if (capacity < count) fail(NIS_E_INVALID, "output too small");
+        hip_check(hipStreamSynchronize(ctx->stream), "sync");
+        hip_check(hipMemcpy(out, M->D.as<float>() + lv.d_off, (size_t)count * sizeof(float), hipMemcpyDeviceToHost),
+                  "download");
+    });
+}
+
+int32_t nis_debug_features(nis_ctx* ctx, int32_t medium, const float* d_points, const float* d_dirs, int64_t n,
+                           float* d_tbar, float* d_rho, float* d_phi, float* d_stats, float* d_tp, float* d_f0)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        if (!d_points || !d_dirs || n <= 0) fail(NIS_E_INVALID, "bad arguments");
+        Medium* M = get_medium(ctx, medium);
+        QueryOut o;
+        o.tbar = d_tbar;
+        o.rho = d_rho;
+        o.phi = d_phi;
+        o.stats = d_stats;
+        o.tp = d_tp;
+        o.f0 = d_f0;
+        o.run_mlp = false;
+        run_query(ctx, M, d_points, d_dirs, n, o, ctx->stream);
+        hip_check(hipStreamSynchronize(ctx->stream), "features");
+    });
+}
+
+int32_t nis_debug_network(nis_ctx* ctx, int32_t medium, const float* d_points, const float* d_dirs, int64_t n,
+                          float* d_desc, float* d_y)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        if (!d_points || !d_dirs || n <= 0) fail(NIS_E_INVALID, "bad arguments");
+        Medium* M = get_medium(ctx, medium);
+        const int prec = ctx->precision;
+        DevBuf raw;
+        QueryOut o;
+        o.y = d_y;
+        if (d_desc) {
+            raw.reserve((size_t)n * kDescPad * desc_elem_bytes(prec), "descriptor copy");
+            o.desc = raw.p;
+        }
+        try {
+            run_query(ctx, M, d_points, d_dirs, n, o, ctx->stream);
+            if (d_desc) hip_check(launch_desc_to_f32(prec, raw.p, d_desc, n, ctx->stream), "descriptor convert");
+            hip_check(hipStreamSynchronize(ctx->stream), "network");
+        } catch (...) {
+            (void)hipStreamSynchronize(ctx->stream);
+            raw.release();
+            throw;
+        }
+        raw.release();
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// nis_internal.h -- device-side data layout shared by the library's kernels
+// and its host runtime.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nis {
+
+constexpr int kLayers = 12;       // template layers: 0-7 diffuse, 8-11 highlight
+constexpr int kDiffuse = 8;
+constexpr int kSites = 225;       // 9 (along the light) x 5 x 5
+constexpr int kStats = 8;         // squeeze vector, eq. (24)
+constexpr int kFeat = 80;         // 16 channels x 5 positions after the CNN
+constexpr int kPerLayer = kFeat + kStats;
+constexpr int kDesc = kLayers * kPerLayer + 1;   // 1057
+constexpr int kDescPad = 1088;    // row stride of the descriptor (multiple of 64)
+constexpr int kMaxLevels = 11;    // 1024^3 .. 1^3
+constexpr int kMaxWidth = 256;    // backbone width limit
+constexpr int kConv1K = 32;       // 27 taps padded
+constexpr int kConv2K = 224;      // 8 channels x 27 taps padded
+constexpr int kPrecFP32 = 0, kPrecBF16 = 1, kPrecFP8 = 2;
+
+// Geometry of one pyramid level and its light-sheared path-density field.
+struct Level {
+    int n;              // edge n_m
+    int ulo, vlo;       // first ray indices along the lateral axes b, c
+    int nu, nv;         // ray counts
+    int64_t rho_off;    // offset of the level in the density pyramid
+    int64_t d_off;      // offset of the level's D[J][V][U] field
+    float ds;           // slice step along the ray, h_m / |l_a|
+};
+
+// Everything a kernel needs to know about a medium under a light.
+struct MediumView {
+    const float* rho;   // density pyramid
+    float* D;           // path density fields
+    Level lev[kMaxLevels];
+    int levels;
+    int n0;             // finest edge
+    int a, b, c;        // dominant axis and lateral axes (0 = x, 1 = y, 2 = z)
+    int sigma;          // sign of l_a
+    int st[3];          // unused by kernels that take strides per level
+    double sb, sc;      // lateral shears l_b/|l_a|, l_c/|l_a|
+    double l[3];        // unit light direction (towards the light)
+    double la;          // |l_a|
+    double qoff[3][9];  // (q * l_d) / |l_a| for q = -4..4, the lattice's along-light offsets
+    float sigma_t, albedo, g, radiance;
+    float lam;          // graded-field coefficient base (eq. 1)
+    float gamma;        // decode exponent (eq. 21)
+    double hg_a, hg_b, hg_k;   // HG constants: 1+g^2, 2g, (1-g^2)/(4 pi)
+};
+
+// Per-light constant tables for the gather (one copy per medium).
+struct SiteTables {
+    float dir[kSites][3];      // unit lattice offset directions d_t (centre: 0)
+    float hg_dl[kSites];       // HG(d_t . l) for the current g (centre: unused)
+};
+
+}  // namespace nis

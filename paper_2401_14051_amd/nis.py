@@ -1,0 +1,276 @@
+"""Python binding of the C ABI in include/nis.h (``libnis.so``).
+
+Every function of the ABI is exposed under its own name (``nis_create``,
+``nis_load_medium``, ...) with ctypes marshalling only; all computation runs
+in the library's HIP kernels.  ``Context`` wraps the calls with numpy host
+arrays and torch device tensors.  torch is used for device memory and streams
+only; it is imported before the library is loaded so that both use the same
+HIP runtime instance.
+
+The library must have been built (``paper_2401_14051_amd.build.build()``);
+importing this module raises if ``libnis.so`` is missing -- there is no
+fallback implementation.
+"""
+
+import ctypes
+import os
+import struct
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnis.so")
+
+NIS_OK = 0
+NIS_E_INVALID = -1
+NIS_E_STATE = -2
+NIS_E_NOMEM = -3
+NIS_E_DEVICE = -4
+NIS_E_UNSUPPORTED = -5
+NIS_E_INTERNAL = -6
+NIS_FP32, NIS_BF16, NIS_FP8 = 0, 1, 2
+NIS_EAGER = 1
+LAYERS, SITES, STATS, DESCRIPTOR = 12, 225, 8, 1057
+
+_fp = ctypes.POINTER(ctypes.c_float)
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+_SIGNATURES = {
+    "nis_create": [_i32, ctypes.POINTER(_vp)],
+    "nis_destroy": [_vp],
+    "nis_load_medium": [_vp, _vp, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                        ctypes.POINTER(_i32)],
+    "nis_rebuild_pyramid": [_vp, _i32, _vp],
+    "nis_set_medium_params": [_vp, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float],
+    "nis_unload_medium": [_vp, _i32],
+    "nis_set_light": [_vp, _i32, _vp, ctypes.c_float, _i32],
+    "nis_set_weights": [_vp, _vp, ctypes.c_size_t],
+    "nis_set_precision": [_vp, _i32],
+    "nis_query": [_vp, _i32, _vp, _vp, _i64, _vp],
+    "nis_query_device": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
+    "nis_medium_info": [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i64)],
+    "nis_debug_pyramid": [_vp, _i32, _vp, _i64],
+    "nis_debug_path_density": [_vp, _i32, _i32, _vp, _i64, ctypes.POINTER(_i32)],
+    "nis_debug_features": [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp],
+    "nis_debug_network": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
+    "nis_profile": [_vp, _i32],
+    "nis_profile_report": [_vp, _vp, ctypes.c_size_t],
+}
+
+EXPORTS = tuple(_SIGNATURES) + ("nis_last_error",)
+
+
+class NisError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("nis error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _load():
+    try:
+        import torch  # noqa: F401  (the HIP runtime torch loaded is the one the library binds to)
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libnis.so is not built (run paper_2401_14051_amd.build.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, args in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = _i32
+    lib.nis_last_error.argtypes = []
+    lib.nis_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def nis_last_error():
+    return _lib.nis_last_error().decode()
+
+
+def _check(code):
+    if code != NIS_OK:
+        raise NisError(code, nis_last_error())
+    return code
+
+
+def _wrap(name):
+    fn = getattr(_lib, name)
+
+    def call(*args):
+        return fn(*args)
+    call.__name__ = name
+    call.__doc__ = "Raw ABI call %s (returns the int32 status)." % name
+    return call
+
+
+for _n in _SIGNATURES:
+    globals()[_n] = _wrap(_n)
+
+
+# ---------------------------------------------------------------------------
+# weight blob
+
+_GROUP_ORDER = ("w1", "b1", "w2", "b2", "s1", "c1", "s2", "c2")
+
+
+def pack_weights(params, fp8_scales=None):
+    """Serialise a parameter dict (see ``workloads.weights``) into the blob
+    layout documented at nis_set_weights."""
+    width, n_linear = int(params["width"]), int(params["n_linear"])
+    has_fp8 = fp8_scales is not None
+    header = struct.pack("<4s5I2fI7I", b"NISW", 1, DESCRIPTOR, width, n_linear, 2,
+                         float(params["lam"]), float(params["gamma"]), 1 if has_fp8 else 0,
+                         *([0] * 7))
+    parts = []
+    for g in ("diffuse", "highlight"):
+        for k in _GROUP_ORDER:
+            parts.append(np.asarray(params["groups"][g][k], np.float32).ravel())
+    for A, b in zip(params["A"], params["beta"]):
+        parts.append(np.asarray(A, np.float32).ravel())
+        parts.append(np.asarray(b, np.float32).ravel())
+    if has_fp8:
+        parts.append(np.asarray(fp8_scales, np.float32).ravel())
+    return header + np.concatenate(parts).astype("<f4").tobytes()
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if isinstance(a, np.ndarray) else ctypes.c_void_p(a)
+
+
+def _dptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One library context on a HIP device."""
+
+    def __init__(self, device=0):
+        h = ctypes.c_void_p()
+        _check(_lib.nis_create(device, ctypes.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.nis_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def load_medium(self, density, sigma_t, albedo, g):
+        d = np.ascontiguousarray(density, dtype=np.float32)
+        n = d.shape[0]
+        if d.shape != (n, n, n):
+            raise ValueError("density must be n^3")
+        mid = _i32()
+        _check(_lib.nis_load_medium(self.h, _ptr(d), n, sigma_t, albedo, g, ctypes.byref(mid)))
+        return mid.value
+
+    def rebuild_pyramid(self, medium, stream=None):
+        _check(_lib.nis_rebuild_pyramid(self.h, medium, _vp(stream)))
+
+    def set_medium_params(self, medium, sigma_t, albedo, g):
+        _check(_lib.nis_set_medium_params(self.h, medium, sigma_t, albedo, g))
+
+    def unload_medium(self, medium):
+        _check(_lib.nis_unload_medium(self.h, medium))
+
+    def set_light(self, medium, direction, radiance=1.0, eager=False):
+        d = np.ascontiguousarray(direction, dtype=np.float32)
+        _check(_lib.nis_set_light(self.h, medium, _ptr(d), radiance, NIS_EAGER if eager else 0))
+
+    def set_weights(self, params=None, blob=None, fp8_scales=None):
+        if blob is None:
+            blob = pack_weights(params, fp8_scales)
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(_lib.nis_set_weights(self.h, buf, len(blob)))
+
+    def set_precision(self, precision):
+        if isinstance(precision, str):
+            precision = {"fp32": NIS_FP32, "bf16": NIS_BF16, "fp8": NIS_FP8}[precision]
+        _check(_lib.nis_set_precision(self.h, precision))
+
+    def query(self, medium, points, dirs):
+        """Host arrays in, host radiance out (synchronous)."""
+        p = np.ascontiguousarray(points, dtype=np.float32)
+        d = np.ascontiguousarray(dirs, dtype=np.float32)
+        out = np.empty(p.shape[0], np.float32)
+        _check(_lib.nis_query(self.h, medium, _ptr(p), _ptr(d), p.shape[0], _ptr(out)))
+        return out
+
+    def query_device(self, medium, points, dirs, out, stream=None):
+        """torch device tensors in/out, queued on ``stream`` (a HIP stream
+        handle; None = the current torch stream)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(points.device).cuda_stream
+        _check(_lib.nis_query_device(self.h, medium, _dptr(points), _dptr(dirs), points.shape[0],
+                                     _dptr(out), _vp(stream)))
+
+    def profile(self, enable=True):
+        _check(_lib.nis_profile(self.h, 1 if enable else 0))
+
+    def profile_report(self):
+        """{kernel: (launches, total_ms)} for the kernels recorded since profile()."""
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(_lib.nis_profile_report(self.h, buf, len(buf)))
+        out = {}
+        for line in buf.value.decode().splitlines():
+            name, cnt, ms = line.split()
+            out[name] = (int(cnt), float(ms))
+        return out
+
+    def medium_info(self, medium):
+        lv, nf = _i32(), _i64()
+        _check(_lib.nis_medium_info(self.h, medium, ctypes.byref(lv), ctypes.byref(nf)))
+        return lv.value, nf.value
+
+    def pyramid(self, medium):
+        levels, nf = self.medium_info(medium)
+        out = np.empty(nf, np.float32)
+        _check(_lib.nis_debug_pyramid(self.h, medium, _ptr(out), nf))
+        res, off = [], 0
+        n0 = 1 << (levels - 1)          # edges halve from n0 down to 1
+        for m in range(levels):
+            nm = n0 >> m
+            res.append(out[off:off + nm ** 3].reshape(nm, nm, nm))
+            off += nm ** 3
+        return res
+
+    def path_density(self, medium, level):
+        dims = (_i32 * 5)()
+        _check(_lib.nis_debug_path_density(self.h, medium, level, None, 0, dims))
+        nu, nv, nj = dims[1] - dims[0] + 1, dims[3] - dims[2] + 1, dims[4]
+        out = np.empty(nu * nv * nj, np.float32)
+        _check(_lib.nis_debug_path_density(self.h, medium, level, _ptr(out), out.size, dims))
+        return out.reshape(nj, nv, nu), (dims[0], dims[1], dims[2], dims[3])
+
+    def features(self, medium, points, dirs):
+        """Gather-stage outputs for torch device tensors (returns torch tensors)."""
+        import torch
+        n = points.shape[0]
+        dev = points.device
+        z = lambda *s: torch.zeros(*s, dtype=torch.float32, device=dev)
+        out = {"tbar": z(n, LAYERS, SITES), "rho": z(n, LAYERS, SITES), "phi": z(n, SITES),
+               "stats": z(n, LAYERS, STATS), "tp": z(n), "f0": z(n)}
+        _check(_lib.nis_debug_features(self.h, medium, _dptr(points), _dptr(dirs), n,
+                                       *[_dptr(out[k]) for k in ("tbar", "rho", "phi", "stats",
+                                                                 "tp", "f0")]))
+        return out
+
+    def network(self, medium, points, dirs, want_desc=True):
+        import torch
+        n = points.shape[0]
+        desc = torch.zeros(n, DESCRIPTOR, dtype=torch.float32, device=points.device) if want_desc else None
+        y = torch.zeros(n, dtype=torch.float32, device=points.device)
+        _check(_lib.nis_debug_network(self.h, medium, _dptr(points), _dptr(dirs), n, _dptr(desc),
+                                      _dptr(y)))
+        return desc, y

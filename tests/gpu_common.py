@@ -1,0 +1,63 @@
+"""Shared set-up of the GPU parity tests: one library context, seeded inputs,
+and the oracle fed with exactly the float32 values the library receives."""
+
+import numpy as np
+
+from oracle import oracle
+from workloads import camera, configs, medium, weights
+
+
+def f32(x):
+    """The float32 value a float parameter becomes at the C ABI, as a double."""
+    return float(np.float32(x))
+
+
+def oracle_params(params):
+    """Copy of ``params`` whose lambda/gamma are the float32 blob values."""
+    p = dict(params)
+    p["lam"] = f32(params["lam"])
+    p["gamma"] = f32(params["gamma"])
+    return p
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+class Scene:
+    """A medium loaded both on the GPU and in the oracle, under one light."""
+
+    def __init__(self, ctx, density, light, sigma_t=8.0, albedo=0.99, g=0.85, radiance=1.0):
+        self.ctx = ctx
+        self.density = np.ascontiguousarray(density, np.float32)
+        self.sigma_t, self.albedo, self.g, self.radiance = sigma_t, albedo, g, radiance
+        self.mid = ctx.load_medium(self.density, sigma_t, albedo, g)
+        self.ctx.set_light(self.mid, light, radiance)
+        self.om = oracle.Medium(self.density)
+        self.om.set_light(np.asarray(light, np.float32))
+
+    def close(self):
+        self.ctx.unload_medium(self.mid)
+
+    def oracle_query(self, params, pts, dirs, want_desc=False):
+        return self.om.query(oracle_params(params), pts, dirs, f32(self.sigma_t), f32(self.albedo),
+                             f32(self.g), f32(self.radiance), want_desc=want_desc)
+
+    def oracle_features(self, params, pts, dirs):
+        return self.om.features(f32(self.sigma_t), f32(self.g), f32(params["lam"]), pts, dirs)
+
+
+def small_points(extra_random=300, seed=5):
+    """The 32^3 orthographic frame's collisions plus random points, some of
+    them outside the unit cube."""
+    w = configs.SMALL
+    d = w.density()
+    p, dd, _ = w.points(d)
+    rp, rd = camera.random_points(extra_random, seed=seed, lo=-0.3, hi=1.3)
+    return d, np.concatenate([p, rp]), np.concatenate([dd, rd])
+
+
+__all__ = ["f32", "oracle_params", "rel_l2", "Scene", "small_points", "configs", "medium", "weights",
+           "camera", "oracle"]

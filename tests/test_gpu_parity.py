@@ -1,0 +1,270 @@
+"""GPU parity of every stage of the hot path against the FP64 oracle, called
+through the C ABI.  Tolerances (FP32 path): pyramid rel 1e-6; path density
+rel 2e-6 of the field's maximum; site densities exactly zero where the oracle's
+are (the in-cube decision) and 2e-6 absolute elsewhere; graded transmittance,
+phase and statistics 2e-5; radiance rel-L2 <= 1e-4.  BF16 radiance rel-L2 <=
+1e-2."""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import Scene, camera, configs, f32, medium, oracle, rel_l2, small_points, weights
+
+pytestmark = pytest.mark.gpu
+
+LIGHTS = [(0.3, 0.9, 0.3), (0.0, 1.0, 0.0), (0.0, -1.0, 0.0), (1.0, 0.2, -0.3),
+          (-0.7, 0.2, 0.4), (0.1, -0.3, -0.95), (1.0, 1.0, 1.0)]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2401_14051_amd import nis
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = nis.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+@pytest.mark.parametrize("n", [1, 2, 16, 32])
+def test_pyramid_matches_oracle(ctx, n):
+    print("pyramid n=%d" % n, flush=True)
+    rho = medium.fbm_cloud(n, seed=n) if n > 2 else np.random.default_rng(n).random((n, n, n)).astype(np.float32)
+    mid = ctx.load_medium(rho, 8.0, 0.99, 0.85)
+    om = oracle.Medium(rho)
+    got = ctx.pyramid(mid)
+    assert len(got) == om.levels
+    for m in range(om.levels):
+        np.testing.assert_allclose(got[m], om.level(m), rtol=1e-6, atol=1e-7)
+    ctx.unload_medium(mid)
+
+
+@pytest.mark.parametrize("light", LIGHTS)
+@pytest.mark.parametrize("n", [8, 32])
+def test_sweep_matches_oracle(ctx, light, n):
+    print("sweep n=%d light=%s" % (n, light), flush=True)
+    rho = medium.fbm_cloud(n, seed=3)
+    s = Scene(ctx, rho, light)
+    for m in range(s.om.levels):
+        ref, rng = s.om.path_density(m)
+        got, grng = ctx.path_density(s.mid, m)
+        assert grng == rng
+        assert got.shape == ref.shape
+        scale = max(ref.max(), 1e-30)
+        np.testing.assert_allclose(got, ref, rtol=0, atol=2e-6 * scale)
+    s.close()
+
+
+@pytest.mark.parametrize("light,g", [((0.3, 0.9, 0.3), 0.85), ((-0.7, 0.2, 0.4), 0.5),
+                                     ((0.1, -0.3, -0.95), 0.95), ((1.0, 0.2, -0.3), 0.0)])
+def test_features_match_oracle(ctx, light, g):
+    print("features light=%s g=%s" % (light, g), flush=True)
+    d, pts, dirs = small_points()
+    s = Scene(ctx, d, light, g=g)
+    params = weights.he_init(16, 3, seed=1)
+    ctx.set_weights(params)
+    ref = s.oracle_features(params, pts, dirs)
+    got = {k: v.cpu().numpy().astype(np.float64) for k, v in ctx.features(s.mid, dev(pts), dev(dirs)).items()}
+    # the in-cube decision of every site is exact
+    np.testing.assert_array_equal(got["rho"] == 0, ref["rho"] == 0)
+    np.testing.assert_allclose(got["rho"], ref["rho"], rtol=0, atol=2e-6)
+    np.testing.assert_allclose(got["tbar"], ref["tbar"], rtol=2e-5, atol=1e-6)
+    np.testing.assert_allclose(got["phi"], ref["phi"], rtol=2e-5, atol=2e-6)
+    np.testing.assert_allclose(got["stats"], ref["stats"], rtol=2e-5, atol=2e-6)
+    np.testing.assert_allclose(got["tp"], ref["tp"], rtol=2e-5, atol=1e-7)
+    np.testing.assert_allclose(got["f0"], ref["f0"], rtol=2e-5, atol=1e-9)
+    s.close()
+
+
+def test_descriptor_and_network_output_fp32(ctx):
+    d, pts, dirs = small_points(extra_random=100)
+    s = Scene(ctx, d, configs.LIGHT_DIR)
+    params = weights.he_init(128, 6, seed=1, bias_scale=0.05)
+    ctx.set_weights(params)
+    ctx.set_precision("fp32")
+    ref = s.oracle_query(params, pts, dirs, want_desc=True)
+    desc, y = ctx.network(s.mid, dev(pts), dev(dirs))
+    desc = desc.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(desc, ref["desc"], rtol=2e-5, atol=2e-6)
+    np.testing.assert_allclose(y.cpu().numpy(), ref["y"], rtol=0, atol=2e-5 * np.abs(ref["y"]).max())
+    s.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 1e-2)])
+def test_query_small_workload(ctx, prec, tol):
+    """The 32^3 / 64x64 / 6x128 workload end to end."""
+    w = configs.SMALL
+    d = w.density()
+    pts, dirs, _ = w.points(d)
+    s = Scene(ctx, d, w.light, w.sigma_t, w.albedo, w.g, w.radiance)
+    params = w.params()
+    ctx.set_weights(params)
+    ctx.set_precision(prec)
+    ref = s.oracle_query(params, pts, dirs)
+    L = ctx.query(s.mid, pts, dirs)
+    err = rel_l2(L, ref["L"])
+    _, y = ctx.network(s.mid, dev(pts), dev(dirs), want_desc=False)
+    Fg = f32(w.albedo) ** 4 * np.expm1(y.cpu().numpy().astype(np.float64))
+    print("%s small: rel-L2(L) %.3g rel-L2(F) %.3g max|dy| %.3g" % (
+        prec, err, rel_l2(Fg, ref["F"]), np.abs(y.cpu().numpy() - ref["y"]).max()), flush=True)
+    assert err <= tol
+    assert rel_l2(Fg, ref["F"]) <= tol
+    ctx.set_precision("fp32")
+    s.close()
+
+
+def test_zero_weights_reduce_to_single_scatter(ctx):
+    d, pts, dirs = small_points()
+    s = Scene(ctx, d, (0.2, -0.5, 0.8), radiance=2.5)
+    params = weights.zeros_like(weights.he_init(16, 3))
+    ctx.set_weights(params)
+    L = ctx.query(s.mid, pts, dirs)
+    feat = s.oracle_features(params, pts, dirs)
+    np.testing.assert_allclose(L, 2.5 * feat["f0"], rtol=2e-5, atol=1e-9)
+    s.close()
+
+
+@pytest.mark.parametrize("entry", [0, 44, 79, 80, 81, 82, 83, 84, 85, 86, 87, 88 * 7 + 3, 88 * 8 + 50,
+                                   88 * 11 + 85, 1056])
+def test_selector_weights_reach_every_descriptor_part(ctx, entry):
+    d, pts, dirs = small_points(extra_random=50)
+    s = Scene(ctx, d, configs.LIGHT_DIR)
+    params = weights.he_init(16, 3, seed=3)
+    for A in params["A"]:
+        A[:] = 0.0
+    params["A"][0][0, entry] = 1.0
+    params["A"][1][0, 0] = 1.0
+    params["A"][2][0, 0] = 1.0
+    ctx.set_weights(params)
+    ref = s.oracle_query(params, pts, dirs, want_desc=True)
+    _, y = ctx.network(s.mid, dev(pts), dev(dirs), want_desc=False)
+    scale = max(np.abs(ref["desc"][:, entry]).max(), 1e-6)
+    np.testing.assert_allclose(y.cpu().numpy(), ref["desc"][:, entry], rtol=2e-5, atol=2e-6 * scale)
+    s.close()
+
+
+@pytest.mark.parametrize("count", [1, 31, 33, 127, 129, 1000])
+def test_ragged_batches_and_batch_invariance(ctx, count):
+    d, pts, dirs = small_points()
+    s = Scene(ctx, d, configs.LIGHT_DIR)
+    params = weights.he_init(128, 6, seed=1)
+    ctx.set_weights(params)
+    full = ctx.query(s.mid, pts, dirs)
+    idx = np.random.default_rng(count).choice(len(pts), count, replace=False)
+    part = ctx.query(s.mid, pts[idx], dirs[idx])
+    np.testing.assert_array_equal(part, full[idx])          # points are independent
+    again = ctx.query(s.mid, pts, dirs)
+    np.testing.assert_array_equal(again, full)              # deterministic
+    s.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 4])
+def test_tiny_media(ctx, n):
+    rho = np.random.default_rng(n).random((n, n, n)).astype(np.float32)
+    pts, dirs = camera.random_points(200, seed=n, lo=-0.2, hi=1.2)
+    s = Scene(ctx, rho, (0.4, -0.2, 0.7))
+    params = weights.he_init(32, 3, seed=2, bias_scale=0.1)
+    ctx.set_weights(params)
+    ref = s.oracle_query(params, pts, dirs)
+    L = ctx.query(s.mid, pts, dirs)
+    assert rel_l2(L, ref["L"]) <= 1e-4
+    s.close()
+
+
+def test_invalid_arguments_are_rejected(ctx):
+    from paper_2401_14051_amd import nis
+    rho = medium.fbm_cloud(8)
+    with pytest.raises(nis.NisError) as e:
+        ctx.load_medium(np.zeros((6, 6, 6), np.float32), 8.0, 0.9, 0.5)
+    assert e.value.code == nis.NIS_E_INVALID
+    for bad in [(-1.0, 0.9, 0.5), (8.0, 1.5, 0.5), (8.0, 0.9, 1.0), (np.nan, 0.9, 0.5)]:
+        with pytest.raises(nis.NisError):
+            ctx.load_medium(rho, *bad)
+    bad_rho = rho.copy()
+    bad_rho[1, 2, 3] = np.inf
+    with pytest.raises(nis.NisError):
+        ctx.load_medium(bad_rho, 8.0, 0.9, 0.5)
+    mid = ctx.load_medium(rho, 8.0, 0.9, 0.5)
+    with pytest.raises(nis.NisError) as e:
+        ctx.set_light(mid, (0.0, 0.0, 0.0))
+    assert e.value.code == nis.NIS_E_INVALID
+    pts, dirs = camera.random_points(10, seed=1)
+    with pytest.raises(nis.NisError) as e:
+        ctx.query(mid, pts, dirs)
+    assert e.value.code == nis.NIS_E_STATE                  # no light yet
+    ctx.set_light(mid, (0.3, 0.9, 0.3))
+    with pytest.raises(nis.NisError) as e:
+        ctx.query(99999, pts, dirs)
+    assert e.value.code == nis.NIS_E_STATE
+    bad = pts.copy()
+    bad[3, 1] = np.nan
+    ctx.set_weights(weights.he_init(16, 3))
+    with pytest.raises(nis.NisError) as e:
+        ctx.query(mid, bad, dirs)
+    assert e.value.code == nis.NIS_E_INVALID
+    zd = dirs.copy()
+    zd[2] = 0
+    with pytest.raises(nis.NisError):
+        ctx.query(mid, pts, zd)
+    with pytest.raises(nis.NisError) as e:
+        ctx.set_weights(blob=b"NISW" + b"\0" * 100)
+    assert e.value.code == nis.NIS_E_INVALID
+    with pytest.raises(nis.NisError) as e:
+        ctx.set_precision(7)
+    assert e.value.code == nis.NIS_E_INVALID
+    assert nis.nis_query(ctx.h, mid, None, None, 0, None) == nis.NIS_E_INVALID
+    ctx.unload_medium(mid)
+    with pytest.raises(nis.NisError):
+        ctx.unload_medium(mid)
+
+
+def test_medium_params_change_without_resweep(ctx):
+    d, pts, dirs = small_points(extra_random=50)
+    s = Scene(ctx, d, configs.LIGHT_DIR)
+    params = weights.he_init(32, 3, seed=4)
+    ctx.set_weights(params)
+    ctx.query(s.mid, pts, dirs)
+    ctx.set_medium_params(s.mid, 5.0, 0.9, 0.3)
+    s.sigma_t, s.albedo, s.g = 5.0, 0.9, 0.3
+    ref = s.oracle_query(params, pts, dirs)
+    assert rel_l2(ctx.query(s.mid, pts, dirs), ref["L"]) <= 1e-4
+    s.close()
+
+
+def test_mirroring_the_dominant_axis(ctx):
+    rho = medium.fbm_cloud(32, seed=12)
+    params = weights.he_init(32, 3, seed=2, bias_scale=0.1)
+    ctx.set_weights(params)
+    rng = np.random.default_rng(5)
+    pts = (np.floor(rng.random((300, 3)) * 2 ** 20) / 2 ** 20).astype(np.float32)
+    dirs = rng.standard_normal((300, 3)).astype(np.float32)
+    a = ctx.load_medium(rho, 8.0, 0.99, 0.85)
+    ctx.set_light(a, (0.3, 0.9, 0.3))
+    b = ctx.load_medium(np.ascontiguousarray(rho[:, ::-1, :]), 8.0, 0.99, 0.85)
+    ctx.set_light(b, (0.3, -0.9, 0.3))
+    pm, dm = pts.copy(), dirs.copy()
+    pm[:, 1] = 1.0 - pm[:, 1]
+    dm[:, 1] = -dm[:, 1]
+    np.testing.assert_allclose(ctx.query(a, pts, dirs), ctx.query(b, pm, dm), rtol=1e-5, atol=1e-7)
+    ctx.unload_medium(a)
+    ctx.unload_medium(b)
+
+
+def test_device_query_on_a_torch_stream(ctx):
+    d, pts, dirs = small_points()
+    s = Scene(ctx, d, configs.LIGHT_DIR)
+    params = weights.he_init(128, 6, seed=1)
+    ctx.set_weights(params)
+    host = ctx.query(s.mid, pts, dirs)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        p, q = dev(pts), dev(dirs)
+        out = torch.empty(len(pts), dtype=torch.float32, device="cuda")
+        ctx.query_device(s.mid, p, q, out)
+    stream.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), host)
+    s.close()

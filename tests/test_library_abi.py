@@ -1,0 +1,69 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the header
+declares, fails cleanly without a GPU, and the binding's blob packer follows
+the documented layout.  No compute calls are made here."""
+
+import ctypes
+import os
+import re
+import struct
+
+import numpy as np
+import pytest
+
+from workloads import weights
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nis.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int32_t|const char \*)\s*(nis_[a-z_0-9]+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("nis_create", "nis_destroy", "nis_load_medium", "nis_set_light", "nis_set_weights",
+                     "nis_set_precision", "nis_query", "nis_query_device", "nis_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2401_14051_amd import nis
+    lib = ctypes.CDLL(nis.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert set(nis.EXPORTS) == set(_declared())
+
+
+def test_calls_fail_cleanly_without_a_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2401_14051_amd import nis
+    h = ctypes.c_void_p()
+    rc = nis.nis_create(0, ctypes.byref(h))
+    assert rc in (nis.NIS_E_DEVICE, nis.NIS_E_INVALID)
+    assert h.value is None
+    assert nis.nis_last_error()
+    assert nis.nis_destroy(None) == nis.NIS_OK
+    assert nis.nis_create(0, None) == nis.NIS_E_INVALID
+
+
+def test_weight_blob_layout():
+    from paper_2401_14051_amd import nis
+    p = weights.he_init(24, 4, seed=3, bias_scale=0.5)
+    blob = nis.pack_weights(p)
+    magic, ver, din, width, nlin, groups, lam, gamma, fp8 = struct.unpack_from("<4s5I2fI", blob)
+    assert (magic, ver, din, width, nlin, groups, fp8) == (b"NISW", 1, 1057, 24, 4, 2, 0)
+    assert lam == np.float32(0.6) and gamma == 4.0
+    body = np.frombuffer(blob, "<f4", offset=64)
+    group = 216 + 8 + 3456 + 16 + 64 + 4 + 64 + 16
+    backbone = 1057 * 24 + 24 + 2 * (24 * 24 + 24) + 24 + 1
+    assert body.size == 2 * group + backbone
+    np.testing.assert_array_equal(body[:216], p["groups"]["diffuse"]["w1"].ravel())
+    np.testing.assert_array_equal(body[group + 224:group + 224 + 3456], p["groups"]["highlight"]["w2"].ravel())
+    np.testing.assert_array_equal(body[2 * group:2 * group + 1057 * 24], p["A"][0].ravel())
+    assert body[-1] == p["beta"][-1][0]
+    scaled = nis.pack_weights(p, fp8_scales=np.ones(6))
+    assert len(scaled) == len(blob) + 6 * 4
