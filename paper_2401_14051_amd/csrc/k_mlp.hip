@@ -25,7 +25,8 @@ k_mlp(MlpArgs A)
     typedef Mfma<PREC> M;
     typedef typename M::elem E;
     constexpr int W = NT * 16;
-    constexpr int HS = W + (PREC == kPrecFP32 ? 4 : 8);   // row stride, keeps 16 B alignment
+    constexpr int KH = hidden_k(PREC, W);                   // K of the hidden layers (zero padded)
+    constexpr int HS = KH + (PREC == kPrecFP32 ? 4 : 8);   // row stride, keeps 16 B alignment
     __shared__ __attribute__((aligned(16))) E hbuf[kMlpWaves][kMlpRows][HS];
 
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -34,10 +35,14 @@ k_mlp(MlpArgs A)
     E(*h)[HS] = hbuf[wave];
     const E* x = reinterpret_cast<const E*>(A.x);
 
+    // activation columns W..KH-1 only ever meet zero weights; keep them finite
+    if constexpr (KH > W) {
+        for (int e = lane; e < kMlpRows * (KH - W); e += 64) h[e / (KH - W)][W + e % (KH - W)] = M::zero();
+    }
     f32x4 acc[2][NT];
     for (int li = 0; li + 1 < A.n_linear; li++) {
         const E* Wt = reinterpret_cast<const E*>(A.W[li]);
-        const int K = li == 0 ? kDescPad : W;
+        const int K = li == 0 ? kDescPad : KH;
 #pragma unroll
         for (int rt = 0; rt < 2; rt++)
 #pragma unroll
@@ -109,6 +114,9 @@ static hipError_t launch_mlp_prec(const MlpArgs& a, hipStream_t s)
     }
     return hipGetLastError();
 }
+
+// K of the hidden layers for a padded width: a multiple of the MFMA K step.
+int mlp_hidden_k(int prec, int wpad) { return hidden_k(prec, wpad); }
 
 // Padded width the kernel is instantiated for: the smallest of
 // 16, 32, 64, 128, 208, 256 that holds `width`.

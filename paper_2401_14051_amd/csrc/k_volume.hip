@@ -109,13 +109,13 @@ __global__ void k_site_tables(MediumView mv, SiteTables* tab)
     o[mv.c] += j;
     const double on = sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
     if (on == 0.0) {
-        for (int d = 0; d < 3; d++) tab->dir[t][d] = 0.f;
+        for (int d = 0; d < 3; d++) tab->dir[t][d] = 0.0;
         tab->hg_dl[t] = 0.f;
         return;
     }
     const double dl = (o[0] * mv.l[0] + o[1] * mv.l[1] + o[2] * mv.l[2]) / on;
     const double den = mv.hg_a - mv.hg_b * dl;
-    for (int d = 0; d < 3; d++) tab->dir[t][d] = (float)(o[d] / on);
+    for (int d = 0; d < 3; d++) tab->dir[t][d] = o[d] / on;
     tab->hg_dl[t] = (float)(mv.hg_k / (den * sqrt(den)));
 }
 

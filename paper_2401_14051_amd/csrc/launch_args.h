@@ -48,5 +48,13 @@ hipError_t launch_features(int prec, const FeatArgs& a, hipStream_t s);
 hipError_t launch_desc_to_f32(int prec, const void* src, float* dst, int64_t n, hipStream_t s);
 hipError_t launch_mlp(int prec, const MlpArgs& a, hipStream_t s);
 int mlp_padded_width(int width);
+int mlp_hidden_k(int prec, int wpad);
+
+// K of the backbone's hidden layers: the padded width rounded up to the MFMA
+// K step (4 for FP32, 32 for BF16); the extra weight columns are zero.
+__host__ __device__ constexpr int hidden_k(int prec, int wpad)
+{
+    return prec == kPrecFP32 ? wpad : (wpad + 31) / 32 * 32;
+}
 
 }  // namespace nis

@@ -231,6 +231,8 @@ void setup_light(Medium* M)
         lv.nv = vhi - lv.vlo + 1;
         lv.d_off = off;
         lv.ds = (float)((1.0 / lv.n) / M->la);
+        if ((int64_t)lv.nu * lv.nv * lv.n >= ((int64_t)1 << 31))
+            fail(NIS_E_UNSUPPORTED, "path-density field of one level exceeds 2^31 entries for this light");
         off += (int64_t)lv.nu * lv.nv * lv.n;
     }
     M->D.reserve((size_t)off * sizeof(float), "path-density fields");
@@ -344,8 +346,11 @@ void pack_net(Net* net, int prec)
         std::vector<float> t1(16 * kConv1K, 0.f), t2(16 * kConv2K, 0.f);
         for (int o = 0; o < 8; o++)
             for (int k = 0; k < 27; k++) t1[o * kConv1K + k] = w1[o * 27 + k];
+        // conv2 K order is tap-major (k = tap * 8 + input channel), matching the
+        // channels-fastest layout of the conv1 output the kernel reads
         for (int o = 0; o < 16; o++)
-            for (int k = 0; k < 216; k++) t2[o * kConv2K + k] = w2[o * 216 + k];
+            for (int ci = 0; ci < 8; ci++)
+                for (int tap = 0; tap < 27; tap++) t2[o * kConv2K + tap * 8 + ci] = w2[(o * 8 + ci) * 27 + tap];
         put(P.w1t[gi], t1, "conv1 weights");
         put(P.w2t[gi], t2, "conv2 weights");
         std::vector<float> cb;
@@ -359,7 +364,7 @@ void pack_net(Net* net, int prec)
     }
     const int W = net->width, Wp = net->wpad;
     for (int li = 0; li + 1 < net->n_linear; li++) {
-        const int din = li == 0 ? kDesc : W, kpad = li == 0 ? kDescPad : Wp;
+        const int din = li == 0 ? kDesc : W, kpad = li == 0 ? kDescPad : mlp_hidden_k(prec, Wp);
         std::vector<float> t((size_t)Wp * kpad, 0.f), bb(Wp, 0.f);
         for (int o = 0; o < W; o++) {
             for (int i = 0; i < din; i++) t[(size_t)o * kpad + i] = net->A[li][(size_t)o * din + i];

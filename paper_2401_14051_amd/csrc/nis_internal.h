@@ -53,7 +53,7 @@ struct MediumView {
 
 // Per-light constant tables for the gather (one copy per medium).
 struct SiteTables {
-    float dir[kSites][3];      // unit lattice offset directions d_t (centre: 0)
+    double dir[kSites][3];     // unit lattice offset directions d_t (centre: 0)
     float hg_dl[kSites];       // HG(d_t . l) for the current g (centre: unused)
 };
 

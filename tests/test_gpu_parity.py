@@ -117,6 +117,33 @@ def test_query_small_workload(ctx, prec, tol):
     s.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("width", [16, 24, 100, 200, 256])
+def test_backbone_widths(ctx, width, prec):
+    """Every padded backbone width, including widths whose padding is not a
+    multiple of the MFMA K step.  FP32: radiance rel-L2 <= 1e-4.  BF16: these
+    random networks put y near 0, where a relative radiance error says little,
+    so the bound is on y itself: |dy| <= 0.04, about ten bfloat16 unit
+    roundoffs (2^-8) for four layers with activations of order one."""
+    d, pts, dirs = small_points(extra_random=100)
+    s = Scene(ctx, d, configs.LIGHT_DIR)
+    params = weights.he_init(width, 4, seed=width, bias_scale=0.05)
+    ctx.set_weights(params)
+    ctx.set_precision(prec)
+    ref = s.oracle_query(params, pts, dirs)
+    _, y = ctx.network(s.mid, dev(pts), dev(dirs), want_desc=False)
+    L = ctx.query(s.mid, pts, dirs)
+    ctx.set_precision("fp32")
+    print("width %d %s: rel-L2(L) %.3g max|dy| %.3g" % (
+        width, prec, rel_l2(L, ref["L"]), np.abs(y.cpu().numpy() - ref["y"]).max()), flush=True)
+    assert np.all(np.isfinite(L))
+    if prec == "fp32":
+        assert rel_l2(L, ref["L"]) <= 1e-4
+    else:
+        assert np.abs(y.cpu().numpy() - ref["y"]).max() <= 0.04
+    s.close()
+
+
 def test_zero_weights_reduce_to_single_scatter(ctx):
     d, pts, dirs = small_points()
     s = Scene(ctx, d, (0.2, -0.5, 0.8), radiance=2.5)
