@@ -28,6 +28,11 @@ HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 VALU_FP32_TFLOPS = 78.6   # 256 CUs x 64 lanes x 2 FLOP x 2.4 GHz, without packed FP32
 
+# Algorithmic FP32 vector work of the gather per shading point: 12 layers x 225
+# sites, each two trilinear interpolations (7 lerps of 2 FLOP), one exponent
+# (2) and four running statistics (4); plus 225 phase features (12 each).
+GATHER_FLOP_PER_POINT = 12 * 225 * (2 * 14 + 2 + 4) + 225 * 12
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -39,6 +44,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=131072,
                     help="points of the frame the oracle is timed on (0 = skip)")
     ap.add_argument("--parity-sample", type=int, default=2048)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this size (for scaling HBM counters)")
     ap.add_argument("--compare-fp32", action="store_true", default=True)
     ap.add_argument("--no-compare-fp32", dest="compare_fp32", action="store_false")
     return ap.parse_args()
@@ -56,9 +63,24 @@ def kernel_work(wl, levels, level_geom, npts, width, n_linear, prec):
         "pyramid": {"bytes": 4 * sum(vox[:-1]) + 4 * sum(vox[1:])},
         "sweep": {"bytes": 4 * sum(vox) + 4 * samples},
         "site_tables": {"bytes": 225 * 16},
-        "features": {"bytes": npts * (24 + 4 + 1088 * esize), "flops": npts * conv_flop},
+        "features": {"bytes": npts * (24 + 4 + 1088 * esize), "flops": npts * conv_flop,
+                     "valu_flops": npts * GATHER_FLOP_PER_POINT},
         "backbone": {"bytes": npts * (1088 * esize + 8), "flops": npts * mlp_flop},
     }
+
+
+def measured_traffic(kernel, prec, workload):
+    """HBM bytes per launch from the committed counter summary of this kernel,
+    if it was taken on the current source; else None."""
+    from paper_2401_14051_amd import rocprof_summary
+    path = os.path.join(ROOT, "profiles", "%s_%s_%s_traffic.json" % (kernel, workload, prec))
+    if not os.path.exists(path) or kernel not in rocprof_summary.KERNEL_SOURCES:
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != rocprof_summary.source_hash(kernel):
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def main():
@@ -127,6 +149,15 @@ def main():
                                                                  res[prec]["kernels"].items()}),
               file=sys.stderr, flush=True)
 
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     # parity on a seeded sample, against the FP64 oracle
     from oracle import oracle
     f32 = lambda x: float(np.float32(x))
@@ -179,15 +210,24 @@ def main():
         if "flops" in w:
             ent["TFLOPs"] = w["flops"] / (t_ms * 1e-3) / 1e12
             ent["mfma_frac"] = ent["TFLOPs"] / MFMA_PEAK_TFLOPS[prec]
+        if "valu_flops" in w:
+            ent["valu_TFLOPs"] = w["valu_flops"] / (t_ms * 1e-3) / 1e12
+            ent["valu_frac"] = ent["valu_TFLOPs"] / VALU_FP32_TFLOPS
         kernels[k] = ent
     dom = max(res[prec]["kernels"], key=lambda k: res[prec]["kernels"][k])
     dk = kernels[dom]
-    if "flops" in work.get(dom, {}):
+    if dom == "features":
+        # the gather's interpolation arithmetic runs on the vector ALUs; the two
+        # small convolutions (conv_flop) run on MFMA and are reported beside it
+        roof = {"kernel": dom, "bound": "alu", "achieved": dk["valu_TFLOPs"], "peak": VALU_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": dk["valu_frac"], "traffic": None}
+    elif "flops" in work.get(dom, {}):
         roof = {"kernel": dom, "bound": "mfma", "achieved": dk["TFLOPs"], "peak": MFMA_PEAK_TFLOPS[prec],
                 "unit": "TFLOP/s", "frac": dk["mfma_frac"], "traffic": None}
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": dk["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": dk["hbm_frac"], "traffic": None}
+    roof["traffic"] = measured_traffic(dom, prec, args.workload)
 
     line = {
         "metric": "shading points/sec (1080p frame of a 256^3 fBm cloud, light change every frame)",

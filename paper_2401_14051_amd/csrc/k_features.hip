@@ -40,6 +40,7 @@ constexpr int kRows = 45;                 // site rows per point and layer
 constexpr int kLatStride = 232;           // 225 sites + padding
 constexpr int kY1Pos = 64;                // 63 conv1 positions + 1
 constexpr int kSmallLevel = 4096;         // floats of a level staged whole in LDS
+constexpr int kBufferFlags = 0x00020000;  // buffer resource word 3 for gfx9-family raw loads
 
 struct PointLayer {           // per point and layer
     int iu, iv, ij, ia0;      // sheared base indices (path density) and light-axis base (density)
@@ -303,8 +304,9 @@ k_features(FeatArgs A)
         __syncthreads();
 
         // ---- gather: rows of 5 sites ---------------------------------------------
-        // one instantiation per address space, so loads are ds_read or global_load
-        auto gather = [&](const float* __restrict__ gD, const float* __restrict__ gR) __attribute__((always_inline)) {
+        // One instantiation per source: LDS for whole small levels, raw buffer
+        // loads (32-bit offsets, immediate offsets along a row) for the others.
+        auto gather = [&](auto ldD, auto ldR) __attribute__((always_inline)) {
         for (int R = tid; R < kTP * kRows; R += 256) {
             const int pt = R / kRows, r = R % kRows;
             const int qi = r / 5, jj = r % 5;
@@ -313,41 +315,49 @@ k_features(FeatArgs A)
             const SlabParams S = sp[pt][qi];
             float Dv[5], Rv[5];
             // path density rows: J = ij - c q (+1), V = iv + c j (+1), U = iu + c i (+1)
-            {
-                const int J0 = P.ij - c * q, V0 = P.iv + c * j - lv.vlo, U0 = P.iu - 2 * c - lv.ulo;
-                const bool inside = c == 1 && J0 >= 0 && J0 + 1 < nm && V0 >= 0 && V0 + 1 < lv.nv && U0 >= 0 &&
-                                    U0 + 5 < lv.nu;
+            if (c == 1) {
+                const int J0 = P.ij - q, V0 = P.iv + j - lv.vlo, U0 = P.iu - 2 - lv.ulo;
+                const bool inside = J0 >= 0 && J0 + 1 < nm && V0 >= 0 && V0 + 1 < lv.nv && U0 >= 0 && U0 + 5 < lv.nu;
                 float a0[6], a1[6], b0[6], b1[6];
                 if (inside) {
-                    const float* p00 = gD + (J0 * lv.nv + V0) * lv.nu + U0;
-                    load6(p00, a0);
-                    load6(p00 + lv.nu, b0);
-                    load6(p00 + plane, a1);
-                    load6(p00 + plane + lv.nu, b1);
+                    const int o = (J0 * lv.nv + V0) * lv.nu + U0;
+#pragma unroll
+                    for (int u = 0; u < 6; u++) {
+                        a0[u] = ldD(o + u);
+                        b0[u] = ldD(o + lv.nu + u);
+                        a1[u] = ldD(o + plane + u);
+                        b1[u] = ldD(o + plane + lv.nu + u);
+                    }
                 } else {
                     const int j0 = clampi(J0, 0, nm - 1) * plane, j1 = clampi(J0 + 1, 0, nm - 1) * plane;
                     const int v0 = clampi(V0, 0, lv.nv - 1) * lv.nu, v1 = clampi(V0 + 1, 0, lv.nv - 1) * lv.nu;
 #pragma unroll
                     for (int u = 0; u < 6; u++) {
                         const int uc = clampi(U0 + u, 0, lv.nu - 1);
-                        a0[u] = gD[j0 + v0 + uc];
-                        b0[u] = gD[j0 + v1 + uc];
-                        a1[u] = gD[j1 + v0 + uc];
-                        b1[u] = gD[j1 + v1 + uc];
+                        a0[u] = ldD(j0 + v0 + uc);
+                        b0[u] = ldD(j0 + v1 + uc);
+                        a1[u] = ldD(j1 + v0 + uc);
+                        b1[u] = ldD(j1 + v1 + uc);
                     }
                 }
-                if (c == 1) {
-                    row5(a0, a1, b0, b1, P.wj, P.wv, P.wu, Dv);
-                } else {
-                    // c > 1 only on the single-voxel level: sites are c apart in U
+                row5(a0, a1, b0, b1, P.wj, P.wv, P.wu, Dv);
+            } else {
+                // c > 1 only on the single-voxel level (one slice): sites are c apart
+                const int v0 = clampi(P.iv + c * j - lv.vlo, 0, lv.nv - 1) * lv.nu;
+                const int v1 = clampi(P.iv + c * j + 1 - lv.vlo, 0, lv.nv - 1) * lv.nu;
 #pragma unroll
-                    for (int i = 0; i < 5; i++)
-                        Dv[i] = sample_D(gD, lv, P.iu + c * (i - 2), P.iv + c * j, P.ij - c * q, P.wu, P.wv, P.wj);
+                for (int i = 0; i < 5; i++) {
+                    const int u0 = clampi(P.iu + c * (i - 2) - lv.ulo, 0, lv.nu - 1);
+                    const int u1 = clampi(P.iu + c * (i - 2) + 1 - lv.ulo, 0, lv.nu - 1);
+                    const float d0 = lerpf(ldD(v0 + u0), ldD(v0 + u1), P.wu);
+                    const float d1 = lerpf(ldD(v1 + u0), ldD(v1 + u1), P.wu);
+                    const float dd = lerpf(d0, d1, P.wv);
+                    Dv[i] = lerpf(dd, dd, P.wj);
                 }
             }
             // density rows: a = ia0 + c q sigma (+1), c-axis ic0(q) + c j (+1), b-axis ib0(q) + c i (+1)
             if (nm == 1) {
-                const float r0 = gR[0];
+                const float r0 = ldR(0);
 #pragma unroll
                 for (int i = 0; i < 5; i++) Rv[i] = r0;
             } else {
@@ -356,21 +366,24 @@ k_features(FeatArgs A)
                                     stb == 1;
                 float a0[6], a1[6], b0[6], b1[6];
                 if (inside) {
-                    const float* p00 = gR + A0 * sta + C0 * stc + B0;
-                    load6(p00, a0);
-                    load6(p00 + sta, a1);
-                    load6(p00 + stc, b0);
-                    load6(p00 + sta + stc, b1);
+                    const int o = A0 * sta + C0 * stc + B0;
+#pragma unroll
+                    for (int u = 0; u < 6; u++) {
+                        a0[u] = ldR(o + u);
+                        a1[u] = ldR(o + sta + u);
+                        b0[u] = ldR(o + stc + u);
+                        b1[u] = ldR(o + sta + stc + u);
+                    }
                 } else {
                     const int x0 = clampi(A0, 0, nm - 1) * sta, x1 = clampi(A0 + 1, 0, nm - 1) * sta;
                     const int z0 = clampi(C0, 0, nm - 1) * stc, z1 = clampi(C0 + 1, 0, nm - 1) * stc;
 #pragma unroll
                     for (int u = 0; u < 6; u++) {
                         const int bc = clampi(B0 + u, 0, nm - 1) * stb;
-                        a0[u] = gR[x0 + z0 + bc];
-                        a1[u] = gR[x1 + z0 + bc];
-                        b0[u] = gR[x0 + z1 + bc];
-                        b1[u] = gR[x1 + z1 + bc];
+                        a0[u] = ldR(x0 + z0 + bc);
+                        a1[u] = ldR(x1 + z0 + bc);
+                        b0[u] = ldR(x0 + z1 + bc);
+                        b1[u] = ldR(x1 + z1 + bc);
                     }
                 }
                 row5(a0, a1, b0, b1, P.wa, S.wc, S.wb, Rv);
@@ -379,7 +392,7 @@ k_features(FeatArgs A)
             const int64_t p = tile0 + pt;
 #pragma unroll
             for (int i = 0; i < 5; i++) {
-                const float T = expf(-coef * Dv[i]);
+                const float T = __expf(-coef * Dv[i]);
                 const float rv = ((S.mask >> 10) & (S.mask >> i) & (S.mask >> (jj + 5)) & 1) ? Rv[i] : 0.f;
                 lat[pt][r * 5 + i] = M::cvt(T);
                 rs += rv;
@@ -397,10 +410,18 @@ k_features(FeatArgs A)
             part[R][3] = tmx;
         }
         };
-        if (small)
-            gather(small_lvl, small_lvl + dsize);
-        else
-            gather(mv.D + lv.d_off, mv.rho + lv.rho_off);
+        if (small) {
+            const float* sD = small_lvl;
+            const float* sR = small_lvl + dsize;
+            gather([&](int o) { return sD[o]; }, [&](int o) { return sR[o]; });
+        } else {
+            const __amdgpu_buffer_rsrc_t rD =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(mv.D + lv.d_off), 0, dsize * 4, kBufferFlags);
+            const __amdgpu_buffer_rsrc_t rR =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(mv.rho + lv.rho_off), 0, rsize * 4, kBufferFlags);
+            gather([&](int o) { return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rD, o * 4, 0, 0)); },
+                   [&](int o) { return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rR, o * 4, 0, 0)); });
+        }
         __syncthreads();
 
         // ---- per-point statistics (eq. 24) ----------------------------------------

@@ -5,18 +5,23 @@
 // Decode (eq. 21 inverted, eq. 19): F = albedo^gamma * expm1(y) and the
 // radiance L = I * (HG(w.l) T(p) + F).
 //
-// Each wave owns 32 rows (points) and keeps their activations in its own LDS
-// slice; every hidden layer is a [32 x K] x [K x W] MFMA GEMM whose output
-// overwrites the slice in place.  Weights are stored [out][in] (zero padded),
-// which is the k-contiguous layout the B fragments read.  The last layer is a
-// float32 dot product per row, fused with the decode.
+// Each wave owns ROWS points (64 in BF16, 32 in FP32) and keeps their
+// activations in its own LDS slice; every hidden layer is a [ROWS x K] x
+// [K x W] MFMA GEMM whose output overwrites the slice in place.  Weights are
+// stored pre-arranged in MFMA B-fragment order: for output tile ct and K step
+// kc, the 64 lanes' fragments are one contiguous block, so a wave loads each
+// fragment with fully used cache lines and every fragment feeds ROWS/16 MFMAs.
+// The last layer is a float32 dot product per row, fused with the decode.
 #include "launch_args.h"
 #include "mfma.h"
 
 namespace nis {
 
-constexpr int kMlpRows = 32;     // rows per wave
 constexpr int kMlpWaves = 4;
+
+template <int PREC> struct MlpShape {
+    static constexpr int ROWS = PREC == kPrecFP32 ? 32 : 64;   // rows per wave
+};
 
 template <int PREC, int NT>
 __global__ void __launch_bounds__(256)
@@ -24,62 +29,72 @@ k_mlp(MlpArgs A)
 {
     typedef Mfma<PREC> M;
     typedef typename M::elem E;
+    constexpr int ROWS = MlpShape<PREC>::ROWS;
+    constexpr int RT = ROWS / 16;                           // row tiles per wave
     constexpr int W = NT * 16;
     constexpr int KH = hidden_k(PREC, W);                   // K of the hidden layers (zero padded)
     constexpr int HS = KH + (PREC == kPrecFP32 ? 4 : 8);   // row stride, keeps 16 B alignment
-    __shared__ __attribute__((aligned(16))) E hbuf[kMlpWaves][kMlpRows][HS];
+    constexpr int FRAG = 64 * M::KPL;                       // elements of one B-fragment block
+    __shared__ __attribute__((aligned(16))) E hbuf[kMlpWaves][ROWS][HS];
 
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int lr = lane % 16, lg = lane / 16;
-    const int64_t row0 = ((int64_t)blockIdx.x * kMlpWaves + wave) * kMlpRows;
+    const int64_t row0 = ((int64_t)blockIdx.x * kMlpWaves + wave) * ROWS;
     E(*h)[HS] = hbuf[wave];
     const E* x = reinterpret_cast<const E*>(A.x);
 
     // activation columns W..KH-1 only ever meet zero weights; keep them finite
     if constexpr (KH > W) {
-        for (int e = lane; e < kMlpRows * (KH - W); e += 64) h[e / (KH - W)][W + e % (KH - W)] = M::zero();
+        for (int e = lane; e < ROWS * (KH - W); e += 64) h[e / (KH - W)][W + e % (KH - W)] = M::zero();
     }
-    f32x4 acc[2][NT];
+    f32x4 acc[RT][NT];
     for (int li = 0; li + 1 < A.n_linear; li++) {
-        const E* Wt = reinterpret_cast<const E*>(A.W[li]);
+        const E* Wf = reinterpret_cast<const E*>(A.W[li]) + lane * M::KPL;
         const int K = li == 0 ? kDescPad : KH;
+        const int KC = K / M::KS;
 #pragma unroll
-        for (int rt = 0; rt < 2; rt++)
+        for (int rt = 0; rt < RT; rt++)
 #pragma unroll
             for (int ct = 0; ct < NT; ct++) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
         if (li == 0) {
-            int64_t ra = row0 + lr, rb = row0 + 16 + lr;
-            ra = ra < A.npts ? ra : A.npts - 1;
-            rb = rb < A.npts ? rb : A.npts - 1;
-            const E* xa = x + ra * kDescPad + lg * M::KPL;
-            const E* xb = x + rb * kDescPad + lg * M::KPL;
-            for (int k0 = 0; k0 < K; k0 += M::KS) {
-                typename M::frag a0 = M::load(xa + k0), a1 = M::load(xb + k0);
+            const E* xr[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; rt++) {
+                int64_t r = row0 + rt * 16 + lr;
+                r = r < A.npts ? r : A.npts - 1;
+                xr[rt] = x + r * kDescPad + lg * M::KPL;
+            }
+            for (int kc = 0; kc < KC; kc++) {
+                typename M::frag a[RT];
+#pragma unroll
+                for (int rt = 0; rt < RT; rt++) a[rt] = M::load(xr[rt] + kc * M::KS);
 #pragma unroll
                 for (int ct = 0; ct < NT; ct++) {
-                    typename M::frag b = M::load(Wt + (ct * 16 + lr) * K + k0 + lg * M::KPL);
-                    acc[0][ct] = M::mma(a0, b, acc[0][ct]);
-                    acc[1][ct] = M::mma(a1, b, acc[1][ct]);
+                    typename M::frag b = M::load(Wf + (ct * KC + kc) * FRAG);
+#pragma unroll
+                    for (int rt = 0; rt < RT; rt++) acc[rt][ct] = M::mma(a[rt], b, acc[rt][ct]);
                 }
             }
         } else {
-            for (int k0 = 0; k0 < K; k0 += M::KS) {
-                typename M::frag a0 = M::load(&h[lr][k0 + lg * M::KPL]);
-                typename M::frag a1 = M::load(&h[16 + lr][k0 + lg * M::KPL]);
+            for (int kc = 0; kc < KC; kc++) {
+                typename M::frag a[RT];
+#pragma unroll
+                for (int rt = 0; rt < RT; rt++) a[rt] = M::load(&h[rt * 16 + lr][kc * M::KS + lg * M::KPL]);
 #pragma unroll
                 for (int ct = 0; ct < NT; ct++) {
-                    typename M::frag b = M::load(Wt + (ct * 16 + lr) * K + k0 + lg * M::KPL);
-                    acc[0][ct] = M::mma(a0, b, acc[0][ct]);
-                    acc[1][ct] = M::mma(a1, b, acc[1][ct]);
+                    typename M::frag b = M::load(Wf + (ct * KC + kc) * FRAG);
+#pragma unroll
+                    for (int rt = 0; rt < RT; rt++) acc[rt][ct] = M::mma(a[rt], b, acc[rt][ct]);
                 }
             }
         }
+        __syncthreads();   // every lane's reads of h precede the in-place overwrite
         const float* bias = A.bias[li];
 #pragma unroll
         for (int ct = 0; ct < NT; ct++) {
             const float bb = bias[ct * 16 + lr];
 #pragma unroll
-            for (int rt = 0; rt < 2; rt++)
+            for (int rt = 0; rt < RT; rt++)
 #pragma unroll
                 for (int e = 0; e < 4; e++)
                     h[rt * 16 + lg * 4 + e][ct * 16 + lr] = M::cvt(fmaxf(acc[rt][ct][e] + bb, 0.f));
@@ -87,10 +102,10 @@ k_mlp(MlpArgs A)
         __syncthreads();
     }
     // last layer + decode, one row per lane
-    if (lane < kMlpRows) {
-        const int64_t row = row0 + lane;
+    for (int rr = lane; rr < ROWS; rr += 64) {
+        const int64_t row = row0 + rr;
         float y = A.bout;
-        for (int k = 0; k < W; k++) y += (float)h[lane][k] * A.wout[k];
+        for (int k = 0; k < W; k++) y += (float)h[rr][k] * A.wout[k];
         if (row < A.npts) {
             if (A.y_out) A.y_out[row] = y;
             if (A.out) A.out[row] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
@@ -101,7 +116,8 @@ k_mlp(MlpArgs A)
 template <int PREC>
 static hipError_t launch_mlp_prec(const MlpArgs& a, hipStream_t s)
 {
-    int blocks = (int)((a.npts + kMlpWaves * kMlpRows - 1) / (kMlpWaves * kMlpRows));
+    constexpr int per = kMlpWaves * MlpShape<PREC>::ROWS;
+    int blocks = (int)((a.npts + per - 1) / per);
     dim3 g(blocks), b(256);
     switch (a.wpad / 16) {
     case 1: hipLaunchKernelGGL((k_mlp<PREC, 1>), g, b, 0, s, a); break;
@@ -117,6 +133,10 @@ static hipError_t launch_mlp_prec(const MlpArgs& a, hipStream_t s)
 
 // K of the hidden layers for a padded width: a multiple of the MFMA K step.
 int mlp_hidden_k(int prec, int wpad) { return hidden_k(prec, wpad); }
+
+// MFMA K step and elements per lane of a B fragment for a precision.
+int mlp_k_step(int prec) { return prec == kPrecFP32 ? Mfma<kPrecFP32>::KS : Mfma<kPrecBF16>::KS; }
+int mlp_k_per_lane(int prec) { return prec == kPrecFP32 ? Mfma<kPrecFP32>::KPL : Mfma<kPrecBF16>::KPL; }
 
 // Padded width the kernel is instantiated for: the smallest of
 // 16, 32, 64, 128, 208, 256 that holds `width`.

@@ -49,6 +49,8 @@ hipError_t launch_desc_to_f32(int prec, const void* src, float* dst, int64_t n, 
 hipError_t launch_mlp(int prec, const MlpArgs& a, hipStream_t s);
 int mlp_padded_width(int width);
 int mlp_hidden_k(int prec, int wpad);
+int mlp_k_step(int prec);       // K per MFMA instruction
+int mlp_k_per_lane(int prec);   // K elements a lane holds in one B fragment
 
 // K of the backbone's hidden layers: the padded width rounded up to the MFMA
 // K step (4 for FP32, 32 for BF16); the extra weight columns are zero.

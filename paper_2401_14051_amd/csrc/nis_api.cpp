@@ -370,7 +370,17 @@ void pack_net(Net* net, int prec)
             for (int i = 0; i < din; i++) t[(size_t)o * kpad + i] = net->A[li][(size_t)o * din + i];
             bb[o] = net->beta[li][o];
         }
-        put(P.W[li], t, "backbone weights");
+        // B-fragment order: block (ct, kc) holds, for lane l = r + 16 g, the
+        // elements W[ct*16 + r][kc*KS + g*KPL + e], e < KPL, contiguously
+        const int KS = mlp_k_step(prec), KPL = mlp_k_per_lane(prec), KC = kpad / KS;
+        std::vector<float> f(t.size());
+        size_t pos = 0;
+        for (int ct = 0; ct < Wp / 16; ct++)
+            for (int kc = 0; kc < KC; kc++)
+                for (int l = 0; l < 64; l++)
+                    for (int e = 0; e < KPL; e++)
+                        f[pos++] = t[(size_t)(ct * 16 + l % 16) * kpad + kc * KS + (l / 16) * KPL + e];
+        put(P.W[li], f, "backbone weights");
         upload_vec(P.bias[li], bb, "backbone biases");
     }
     std::vector<float> wo(Wp, 0.f);

@@ -1,0 +1,120 @@
+"""Summaries of rocprofv3 result databases (the SQLite ``*_results.db``).
+
+Kernel timings:
+    python -m paper_2401_14051_amd.rocprof_summary times DB [--title T --command C] > out.md
+
+HBM traffic of a kernel from two counter runs (FETCH_SIZE, then WRITE_SIZE),
+scaled by what the same counters read for a plain copy kernel of known size:
+    python -m paper_2401_14051_amd.rocprof_summary traffic --fetch DB1 --write DB2 \\
+        --kernel k_features --copy-kernel elementwise --copy-bytes B > out.json
+
+The traffic summary records a hash of the kernel's source files, so that the
+benchmark reports it only while the kernel is unchanged.
+"""
+
+import argparse
+import collections
+import hashlib
+import json
+import os
+import sqlite3
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# sources each measured kernel depends on
+KERNEL_SOURCES = {
+    "features": ["csrc/k_features.hip", "csrc/mfma.h", "csrc/launch_args.h", "csrc/nis_internal.h"],
+    "backbone": ["csrc/k_mlp.hip", "csrc/mfma.h", "csrc/launch_args.h", "csrc/nis_internal.h"],
+    "sweep": ["csrc/k_volume.hip", "csrc/launch_args.h", "csrc/nis_internal.h"],
+}
+
+
+def source_hash(kernel):
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_times(db):
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, count(*), avg(duration), min(duration), max(duration), sum(duration) "
+                       "from kernels group by name order by sum(duration) desc").fetchall()
+    return rows
+
+
+def counters(db, counter):
+    """{kernel name: [value per dispatch]} of one counter."""
+    con = sqlite3.connect(db)
+    out = collections.defaultdict(list)
+    for name, val in con.execute("select kernel_name, value from counters_collection where counter_name = ? "
+                                 "order by dispatch_id", (counter,)):
+        out[name].append(val)
+    return out
+
+
+def pick(d, key):
+    hits = [k for k in d if key in k]
+    if len(hits) != 1:
+        raise SystemExit("kernel %r matches %r" % (key, hits))
+    return d[hits[0]]
+
+
+def cmd_times(a):
+    rows = kernel_times(a.db)
+    total = sum(r[5] for r in rows)
+    print("# %s\n" % (a.title or "Kernel times"))
+    if a.command:
+        print("Command:\n\n```\n%s\n```\n" % a.command)
+    print("| kernel | calls | avg (us) | min (us) | max (us) | total (us) | share |")
+    print("|---|---|---|---|---|---|---|")
+    for name, n, avg, mn, mx, tot in rows:
+        print("| `%s` | %d | %.1f | %.1f | %.1f | %.1f | %.1f%% |" % (name[:80], n, avg / 1e3, mn / 1e3, mx / 1e3,
+                                                                     tot / 1e3, 100.0 * tot / total))
+
+
+def cmd_traffic(a):
+    fetch = counters(a.fetch, "FETCH_SIZE")
+    write = counters(a.write, "WRITE_SIZE")
+    cf = pick(fetch, a.copy_kernel)
+    cw = pick(write, a.copy_kernel)
+    kf = pick(fetch, a.kernel)
+    kw = pick(write, a.kernel)
+    # counters are in KiB per dispatch; the copy kernel moves copy_bytes each way
+    f_scale = a.copy_bytes / (1024.0 * max(cf))
+    w_scale = a.copy_bytes / (1024.0 * max(cw))
+    fetch_b = 1024.0 * sum(kf) / len(kf) * f_scale
+    write_b = 1024.0 * sum(kw) / len(kw) * w_scale
+    out = {"kernel": a.name, "source_hash": source_hash(a.name), "fetch_bytes_per_launch": fetch_b,
+           "write_bytes_per_launch": write_b, "traffic_bytes_per_launch": fetch_b + write_b,
+           "copy_calibration": {"kernel": a.copy_kernel, "bytes": a.copy_bytes,
+                                "fetch_kib": max(cf), "write_kib": max(cw),
+                                "fetch_scale": f_scale, "write_scale": w_scale},
+           "raw_kib": {"fetch": kf, "write": kw}, "commands": a.command}
+    json.dump(out, sys.stdout, indent=1)
+    print()
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("times")
+    t.add_argument("db")
+    t.add_argument("--title")
+    t.add_argument("--command")
+    r = sub.add_parser("traffic")
+    r.add_argument("--fetch", required=True)
+    r.add_argument("--write", required=True)
+    r.add_argument("--kernel", required=True, help="substring of the measured kernel's name")
+    r.add_argument("--name", required=True, choices=sorted(KERNEL_SOURCES))
+    r.add_argument("--copy-kernel", required=True)
+    r.add_argument("--copy-bytes", type=float, required=True)
+    r.add_argument("--command", action="append", default=[])
+    a = ap.parse_args(argv)
+    {"times": cmd_times, "traffic": cmd_traffic}[a.cmd](a)
+
+
+if __name__ == "__main__":
+    main()
