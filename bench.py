@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16"])
+    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--workload", default="frame", choices=["frame", "large", "small"])
     ap.add_argument("--cpu-sample", type=int, default=131072,
                     help="points of the frame the oracle is timed on (0 = skip)")
@@ -53,7 +53,7 @@ def parse():
 
 def kernel_work(wl, levels, level_geom, npts, width, n_linear, prec):
     """Algorithmic bytes / FLOPs per launch of each kernel."""
-    esize = {"fp32": 4, "bf16": 2}[prec]
+    esize = {"fp32": 4, "bf16": 2, "fp8": 2}[prec]     # the FP8 path stores the descriptor in BF16
     n0 = wl.n
     vox = [(n0 >> m) ** 3 for m in range(levels)]
     samples = sum(nu * nv * n for (nu, nv, n) in level_geom)
@@ -134,7 +134,8 @@ def main():
         return ms, wall
 
     res = {}
-    precs = [args.precision] + (["fp32"] if args.compare_fp32 and args.precision != "fp32" else [])
+    precs = [args.precision] + ([p for p in ("bf16", "fp8", "fp32") if p != args.precision]
+                                if args.compare_fp32 else [])
     for prec in precs:
         ms, wall = run(prec, args.steps, args.warmup)
         ctx.profile(True)

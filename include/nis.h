@@ -47,13 +47,15 @@ typedef struct nis_ctx nis_ctx;
 #define NIS_E_STATE (-2)       /* call not valid in the current state (no weights, unknown medium) */
 #define NIS_E_NOMEM (-3)       /* device allocation failed or exceeded the context's budget */
 #define NIS_E_DEVICE (-4)      /* a HIP runtime call failed; the HIP error text is kept */
-#define NIS_E_UNSUPPORTED (-5) /* e.g. FP8 requested without calibration scales */
+#define NIS_E_UNSUPPORTED (-5) /* a valid request the library cannot serve (field too large) */
 #define NIS_E_INTERNAL (-6)
 
 /* network precisions (nis_set_precision) */
 #define NIS_FP32 0   /* every GEMM in float32 (MFMA f32), float32 descriptor */
 #define NIS_BF16 1   /* CNN and backbone GEMMs in bfloat16 x bfloat16 -> float32 */
-#define NIS_FP8 2    /* CNN and backbone GEMMs in FP8-E4M3 (OCP) with per-layer scales */
+#define NIS_FP8 2    /* backbone GEMMs in FP8-E4M3 (OCP) x E4M3 -> float32, with one
+                        weight scale per output column and one activation scale per
+                        shading point and layer; CNN and descriptor in BF16 */
 
 /* nis_set_light flags */
 #define NIS_EAGER 1  /* run the transmittance sweep now rather than at the next query */
@@ -130,8 +132,11 @@ int32_t nis_set_light(nis_ctx *ctx, int32_t medium, const float dir[3], float ra
  */
 int32_t nis_set_weights(nis_ctx *ctx, const void *blob, size_t nbytes);
 
-/* NIS_FP32 (default), NIS_BF16 or NIS_FP8.  NIS_FP8 without scales in the
- * weight blob is NIS_E_UNSUPPORTED. */
+/* NIS_FP32 (default), NIS_BF16 or NIS_FP8.  The FP8 path needs no calibration:
+ * weight scales (column absmax / 448) are fixed at nis_set_weights and each
+ * point's activation scale is its own row absmax, so results do not depend on
+ * the batch.  The blob's optional fp8 scale block is accepted and unused.
+ * Errors: NIS_E_INVALID for an unknown precision. */
 int32_t nis_set_precision(nis_ctx *ctx, int32_t precision);
 
 /*

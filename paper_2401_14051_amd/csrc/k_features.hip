@@ -236,6 +236,7 @@ k_features(FeatArgs A)
         }
     E* desc = reinterpret_cast<E*>(A.desc);
 
+    float row_absmax = 0.f;   // thread (point, o): max |stored entry| of its point so far
     for (int k = 0; k < kLayers; k++) {
         const int m = k < mv.levels - 1 ? k : mv.levels - 1;
         const Level lv = mv.lev[m];
@@ -518,13 +519,26 @@ k_features(FeatArgs A)
             gate[pt][o] = 1.f / (1.f + expf(-s));
             // descriptor entries of layer k: 5 features of channel o, and stat o
             const int64_t pp = tile0 + pt;
+            float lmax = 0.f;
+            E q[6];
+#pragma unroll
+            for (int z = 0; z < 5; z++) {
+                q[z] = M::cvt(gate[pt][o] * H[pt][o][z]);
+                lmax = fmaxf(lmax, fabsf((float)q[z]));
+            }
+            q[5] = M::cvt(o < kStats ? pstat[pt][o] : 0.f);
+            lmax = fmaxf(lmax, fabsf((float)q[5]));
             if (pp < A.npts) {
                 E* d = desc + pp * kDescPad + k * kPerLayer;
 #pragma unroll
-                for (int z = 0; z < 5; z++) d[o * 5 + z] = M::cvt(gate[pt][o] * H[pt][o][z]);
-                if (o < kStats) d[kFeat + o] = M::cvt(pstat[pt][o]);
+                for (int z = 0; z < 5; z++) d[o * 5 + z] = q[z];
+                if (o < kStats) d[kFeat + o] = q[5];
                 if (DBG && o < kStats) A.dbg_stats[(pp * kLayers + k) * kStats + o] = pstat[pt][o];
             }
+            // running maximum |entry| of the point's stored descriptor (the 16
+            // threads of a point are 16 consecutive lanes of one wave)
+            for (int s = 1; s < 16; s <<= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, s));
+            row_absmax = fmaxf(row_absmax, lmax);
         }
     }
     // albedo entry and zero padding
@@ -533,6 +547,8 @@ k_features(FeatArgs A)
         const int64_t pp = tile0 + pt;
         if (pp < A.npts) desc[pp * kDescPad + f] = M::cvt(f == kDesc - 1 ? mv.albedo : 0.f);
     }
+    if (A.rowmax && tid % 16 == 0 && tile0 + tid / 16 < A.npts)
+        A.rowmax[tile0 + tid / 16] = fmaxf(row_absmax, fabsf((float)M::cvt(mv.albedo)));
 }
 
 // Widen a descriptor of the given precision to float32 [n][1057].
@@ -549,7 +565,7 @@ __global__ void k_desc_to_f32(const void* src, float* dst, int64_t n)
 hipError_t launch_desc_to_f32(int prec, const void* src, float* dst, int64_t n, hipStream_t s)
 {
     int blocks = (int)((n * kDesc + 255) / 256);
-    if (prec == kPrecBF16)
+    if (prec == kPrecBF16 || prec == kPrecFP8)
         hipLaunchKernelGGL(k_desc_to_f32<kPrecBF16>, dim3(blocks), dim3(256), 0, s, src, dst, n);
     else
         hipLaunchKernelGGL(k_desc_to_f32<kPrecFP32>, dim3(blocks), dim3(256), 0, s, src, dst, n);
@@ -563,7 +579,8 @@ hipError_t launch_features(int prec, const FeatArgs& a, hipStream_t s)
     const bool dbg = a.dbg_tbar || a.dbg_rho || a.dbg_phi || a.dbg_stats || a.dbg_tp;
     if (dbg && !(a.dbg_tbar && a.dbg_rho && a.dbg_phi && a.dbg_stats && a.dbg_tp))
         return hipErrorInvalidValue;   // the debug variant writes every stage output
-    if (prec == kPrecBF16) {
+    // the FP8 path runs the CNN and stores the descriptor in BF16
+    if (prec == kPrecBF16 || prec == kPrecFP8) {
         if (dbg) hipLaunchKernelGGL((k_features<kPrecBF16, true>), dim3(blocks), dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_features<kPrecBF16, false>), dim3(blocks), dim3(256), 0, s, a);
     } else {

@@ -113,6 +113,159 @@ k_mlp(MlpArgs A)
     }
 }
 
+// FP8 backbone.  Every GEMM is E4M3 x E4M3 -> FP32 on MFMA with two scales:
+// one per output column of the weights (absmax / 448, fixed at set_weights)
+// and one per row of the activations (absmax / 448 of that point's layer
+// input, computed here), so a point's result never depends on the others in
+// its batch.  The descriptor arrives in BF16 with its row maxima and is
+// quantised while it is loaded; hidden activations are stored in LDS as E4M3.
+template <int NT>
+__global__ void __launch_bounds__(256)
+k_mlp_fp8(MlpArgs A)
+{
+    typedef Mfma<kPrecFP8> M;
+    constexpr int ROWS = 64, RT = 4;
+    constexpr int W = NT * 16;
+    constexpr int KH = hidden_k(kPrecFP8, W);
+    constexpr int K0 = input_k(kPrecFP8);
+    constexpr int HS = KH + 16;                  // bytes per activation row
+    constexpr int FRAG = 64 * M::KPL;
+    // scaling to 447.5 keeps every rounded code finite (the conversion does not saturate)
+    constexpr float kTarget = 447.5f;
+    __shared__ __attribute__((aligned(16))) uint8_t hbuf[kMlpWaves][ROWS][HS];
+    __shared__ float rsc[kMlpWaves][ROWS];      // dequantisation scale of each row's activations
+
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int lr = lane % 16, lg = lane / 16;
+    const int64_t row0 = ((int64_t)blockIdx.x * kMlpWaves + wave) * ROWS;
+    uint8_t(*h)[HS] = hbuf[wave];
+    float* rs = rsc[wave];
+    const __bf16* x = reinterpret_cast<const __bf16*>(A.x);
+
+    if constexpr (KH > W) {
+        for (int e = lane; e < ROWS * (KH - W); e += 64) h[e / (KH - W)][W + e % (KH - W)] = 0;
+    }
+    // row scales of the descriptor
+    float qs[RT];
+    const __bf16* xr[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++) {
+        int64_t r = row0 + rt * 16 + lr;
+        r = r < A.npts ? r : A.npts - 1;
+        xr[rt] = x + r * kDescPad + lg * M::KPL;
+        const float m = A.rowmax[r];
+        qs[rt] = m > 0.f ? kTarget / m : 1.f;
+        if (lg == 0) rs[rt * 16 + lr] = m > 0.f ? m / kTarget : 1.f;
+    }
+    __syncthreads();
+
+    f32x4 acc[RT][NT];
+    for (int li = 0; li + 1 < A.n_linear; li++) {
+        const uint8_t* Wf = reinterpret_cast<const uint8_t*>(A.W[li]) + lane * M::KPL;
+        const int K = li == 0 ? K0 : KH;
+        const int KC = K / M::KS;
+#pragma unroll
+        for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+            for (int ct = 0; ct < NT; ct++) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int kc = 0; kc < KC; kc++) {
+            typename M::frag a[RT];
+            if (li == 0) {
+                const bool valid = kc * M::KS + lg * M::KPL < kDescPad;
+#pragma unroll
+                for (int rt = 0; rt < RT; rt++) {
+                    if (valid) {
+                        const bf16x8* src = reinterpret_cast<const bf16x8*>(xr[rt] + kc * M::KS);
+#pragma unroll
+                        for (int v = 0; v < 4; v++) {
+                            const bf16x8 u = src[v];
+                            a[rt][2 * v] = pack_fp8x4_inrange((float)u[0] * qs[rt], (float)u[1] * qs[rt],
+                                                              (float)u[2] * qs[rt], (float)u[3] * qs[rt]);
+                            a[rt][2 * v + 1] = pack_fp8x4_inrange((float)u[4] * qs[rt], (float)u[5] * qs[rt],
+                                                                  (float)u[6] * qs[rt], (float)u[7] * qs[rt]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < 8; v++) a[rt][v] = 0;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int rt = 0; rt < RT; rt++) a[rt] = M::load(&h[rt * 16 + lr][kc * M::KS + lg * M::KPL]);
+            }
+#pragma unroll
+            for (int ct = 0; ct < NT; ct++) {
+                typename M::frag b = M::load(Wf + (ct * KC + kc) * FRAG);
+#pragma unroll
+                for (int rt = 0; rt < RT; rt++) acc[rt][ct] = M::mma(a[rt], b, acc[rt][ct]);
+            }
+        }
+        __syncthreads();   // every lane's reads of h and rs precede their overwrite
+        const float* bias = A.bias[li];
+        const float* wsc = A.wscale[li];
+#pragma unroll
+        for (int rt = 0; rt < RT; rt++) {
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int row = rt * 16 + lg * 4 + e;
+                const float din = rs[row];
+                float m = 0.f;
+#pragma unroll
+                for (int ct = 0; ct < NT; ct++) {
+                    const int col = ct * 16 + lr;
+                    const float v = fmaxf(acc[rt][ct][e] * din * wsc[col] + bias[col], 0.f);
+                    acc[rt][ct][e] = v;
+                    m = fmaxf(m, v);
+                }
+                for (int o = 1; o < 16; o <<= 1) m = fmaxf(m, __shfl_xor(m, o));
+                const float q = m > 0.f ? kTarget / m : 1.f;
+#pragma unroll
+                for (int ct = 0; ct < NT; ct++) {
+                    const int w = __builtin_amdgcn_cvt_pk_fp8_f32(acc[rt][ct][e] * q, 0.f, 0, false);
+                    h[row][ct * 16 + lr] = (uint8_t)(w & 0xff);
+                }
+                // the row's 16 lanes read rs[row] above, in this wave, before this write
+                if (lr == 0) rs[row] = m > 0.f ? m / kTarget : 1.f;
+            }
+        }
+        __syncthreads();
+    }
+    // last layer + decode, one row per lane
+    for (int rr = lane; rr < ROWS; rr += 64) {
+        const int64_t row = row0 + rr;
+        float y = 0.f;
+        for (int k = 0; k < W; k++) y += __builtin_amdgcn_cvt_f32_fp8((int)h[rr][k], 0) * A.wout[k];
+        y = A.bout + y * rs[rr];
+        if (row < A.npts) {
+            if (A.y_out) A.y_out[row] = y;
+            if (A.out) A.out[row] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
+        }
+    }
+}
+
+template <int NT>
+static void launch_fp8_nt(const MlpArgs& a, dim3 g, dim3 b, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_mlp_fp8<NT>), g, b, 0, s, a);
+}
+
+static hipError_t launch_mlp_fp8(const MlpArgs& a, hipStream_t s)
+{
+    constexpr int per = kMlpWaves * 64;
+    int blocks = (int)((a.npts + per - 1) / per);
+    dim3 g(blocks), b(256);
+    switch (a.wpad / 16) {
+    case 1: launch_fp8_nt<1>(a, g, b, s); break;
+    case 2: launch_fp8_nt<2>(a, g, b, s); break;
+    case 4: launch_fp8_nt<4>(a, g, b, s); break;
+    case 8: launch_fp8_nt<8>(a, g, b, s); break;
+    case 13: launch_fp8_nt<13>(a, g, b, s); break;
+    case 16: launch_fp8_nt<16>(a, g, b, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <int PREC>
 static hipError_t launch_mlp_prec(const MlpArgs& a, hipStream_t s)
 {
@@ -135,8 +288,14 @@ static hipError_t launch_mlp_prec(const MlpArgs& a, hipStream_t s)
 int mlp_hidden_k(int prec, int wpad) { return hidden_k(prec, wpad); }
 
 // MFMA K step and elements per lane of a B fragment for a precision.
-int mlp_k_step(int prec) { return prec == kPrecFP32 ? Mfma<kPrecFP32>::KS : Mfma<kPrecBF16>::KS; }
-int mlp_k_per_lane(int prec) { return prec == kPrecFP32 ? Mfma<kPrecFP32>::KPL : Mfma<kPrecBF16>::KPL; }
+int mlp_k_step(int prec)
+{
+    return prec == kPrecFP32 ? Mfma<kPrecFP32>::KS : prec == kPrecBF16 ? Mfma<kPrecBF16>::KS : Mfma<kPrecFP8>::KS;
+}
+int mlp_k_per_lane(int prec)
+{
+    return prec == kPrecFP32 ? Mfma<kPrecFP32>::KPL : prec == kPrecBF16 ? Mfma<kPrecBF16>::KPL : Mfma<kPrecFP8>::KPL;
+}
 
 // Padded width the kernel is instantiated for: the smallest of
 // 16, 32, 64, 128, 208, 256 that holds `width`.
@@ -151,6 +310,7 @@ int mlp_padded_width(int width)
 hipError_t launch_mlp(int prec, const MlpArgs& a, hipStream_t s)
 {
     if (a.npts <= 0) return hipSuccess;
+    if (prec == kPrecFP8) return launch_mlp_fp8(a, s);
     if (prec == kPrecBF16) return launch_mlp_prec<kPrecBF16>(a, s);
     return launch_mlp_prec<kPrecFP32>(a, s);
 }

@@ -24,6 +24,7 @@ struct FeatArgs {
     float* dbg_phi;              // optional [npts][225]
     float* dbg_stats;            // optional [npts][12][8]
     float* dbg_tp;               // optional [npts]
+    float* rowmax;               // optional [npts]: max |entry| of each stored descriptor row
 };
 
 struct MlpArgs {
@@ -31,6 +32,8 @@ struct MlpArgs {
     int64_t npts;
     const void* W[kMaxLinear];       // layer i: [wpad][kin_pad] (kin_pad = kDescPad for i = 0)
     const float* bias[kMaxLinear];   // [wpad], zero padded
+    const float* wscale[kMaxLinear]; // FP8 only: per-output-column weight scale [wpad]
+    const float* rowmax;             // FP8 only: max |x| of each descriptor row [npts]
     const float* wout;               // [wpad] last-layer weights (float32)
     float bout;
     int n_linear, wpad;
@@ -56,7 +59,13 @@ int mlp_k_per_lane(int prec);   // K elements a lane holds in one B fragment
 // K step (4 for FP32, 32 for BF16); the extra weight columns are zero.
 __host__ __device__ constexpr int hidden_k(int prec, int wpad)
 {
-    return prec == kPrecFP32 ? wpad : (wpad + 31) / 32 * 32;
+    return prec == kPrecFP32 ? wpad : prec == kPrecBF16 ? (wpad + 31) / 32 * 32 : (wpad + 127) / 128 * 128;
+}
+
+// K of the backbone's first layer: the descriptor padded to the MFMA K step.
+__host__ __device__ constexpr int input_k(int prec)
+{
+    return prec == kPrecFP8 ? (kDescPad + 127) / 128 * 128 : kDescPad;
 }
 
 }  // namespace nis

@@ -102,7 +102,7 @@ struct Medium {
 
 struct PackedNet {
     DevBuf w1t[2], w2t[2], cb[2];
-    DevBuf W[16], bias[16], wout;
+    DevBuf W[16], bias[16], wscale[16], wout;
 };
 
 struct Net {
@@ -112,7 +112,7 @@ struct Net {
     std::vector<float> groups[2];      // 3844 floats each, blob order
     std::vector<std::vector<float>> A, beta;
     std::vector<float> fp8_scales;
-    PackedNet packed[2];               // fp32, bf16
+    PackedNet packed[3];               // fp32, bf16, fp8
 };
 
 constexpr int kGroupFloats = 216 + 8 + 3456 + 16 + 64 + 4 + 64 + 16;
@@ -163,7 +163,7 @@ struct nis_ctx {
     int32_t next_id = 1;
     Net* net = nullptr;
     int precision = kPrecFP32;
-    DevBuf desc, f0, io;
+    DevBuf desc, f0, rowmax, io;
     Profiler prof;
 };
 
@@ -325,14 +325,47 @@ template <class T> void upload_vec(DevBuf& buf, const std::vector<T>& v, const c
     upload(buf, v.data(), v.size() * sizeof(T), what);
 }
 
-// Pack one precision: conv weights [out][k] zero padded, backbone [out][in]
-// zero padded to the kernel's tile sizes; biases and the last layer stay float32.
+// OCP E4M3FN code of f with round-to-nearest-even, saturating at +-448
+// (1 sign bit, 4 exponent bits with bias 7, 3 mantissa bits; 0x7f is NaN).
+uint8_t fp8_e4m3(float f)
+{
+    const uint8_t sign = std::signbit(f) ? 0x80 : 0x00;
+    const float a = std::fabs(f);
+    if (std::isnan(f)) return 0x7f;
+    if (a >= 464.f) return sign | 0x7e;
+    int e;
+    std::frexp(a, &e);                 // a in [2^(e-1), 2^e)
+    int E = e - 1 + 7;                 // biased exponent of a normal encoding
+    if (a == 0.f) return sign;
+    if (E >= 1) {
+        float r = std::nearbyint(std::ldexp(a, 3 - (e - 1)));   // 8 <= r <= 16
+        if (r == 16.f) {
+            r = 8.f;
+            E += 1;
+        }
+        if (E > 15 || (E == 15 && r > 14.f)) return sign | 0x7e;
+        return sign | (uint8_t)(E << 3) | (uint8_t)((int)r - 8);
+    }
+    const float r = std::nearbyint(std::ldexp(a, 9));            // subnormal: r * 2^-9
+    if (r >= 8.f) return sign | 0x08;
+    return sign | (uint8_t)r;
+}
+
+// Pack one precision: conv weights [out][k] zero padded (float32 for FP32,
+// bfloat16 otherwise: the FP8 path runs the CNN in BF16); backbone matrices
+// zero padded to the kernel's tile sizes and stored in B-fragment order, in
+// float32, bfloat16 or E4M3 with one scale per output column (absmax / 448);
+// biases and the last layer stay float32.
 void pack_net(Net* net, int prec)
 {
     PackedNet& P = net->packed[prec];
-    auto put = [&](DevBuf& buf, const std::vector<float>& v, const char* what) {
+    auto put = [&](DevBuf& buf, const std::vector<float>& v, const char* what, bool allow_fp8) {
         if (prec == kPrecFP32) {
             upload_vec(buf, v, what);
+        } else if (prec == kPrecFP8 && allow_fp8) {
+            std::vector<uint8_t> h(v.size());
+            for (size_t i = 0; i < v.size(); i++) h[i] = fp8_e4m3(v[i]);
+            upload_vec(buf, h, what);
         } else {
             std::vector<uint16_t> h(v.size());
             for (size_t i = 0; i < v.size(); i++) h[i] = bf16_bits(v[i]);
@@ -351,8 +384,8 @@ void pack_net(Net* net, int prec)
         for (int o = 0; o < 16; o++)
             for (int ci = 0; ci < 8; ci++)
                 for (int tap = 0; tap < 27; tap++) t2[o * kConv2K + tap * 8 + ci] = w2[(o * 8 + ci) * 27 + tap];
-        put(P.w1t[gi], t1, "conv1 weights");
-        put(P.w2t[gi], t2, "conv2 weights");
+        put(P.w1t[gi], t1, "conv1 weights", false);
+        put(P.w2t[gi], t2, "conv2 weights", false);
         std::vector<float> cb;
         cb.insert(cb.end(), b1, b1 + 8);
         cb.insert(cb.end(), b2, b2 + 16);
@@ -364,11 +397,19 @@ void pack_net(Net* net, int prec)
     }
     const int W = net->width, Wp = net->wpad;
     for (int li = 0; li + 1 < net->n_linear; li++) {
-        const int din = li == 0 ? kDesc : W, kpad = li == 0 ? kDescPad : mlp_hidden_k(prec, Wp);
-        std::vector<float> t((size_t)Wp * kpad, 0.f), bb(Wp, 0.f);
+        const int din = li == 0 ? kDesc : W, kpad = li == 0 ? input_k(prec) : mlp_hidden_k(prec, Wp);
+        std::vector<float> t((size_t)Wp * kpad, 0.f), bb(Wp, 0.f), sc(Wp, 1.f);
         for (int o = 0; o < W; o++) {
-            for (int i = 0; i < din; i++) t[(size_t)o * kpad + i] = net->A[li][(size_t)o * din + i];
+            float amax = 0.f;
+            for (int i = 0; i < din; i++) {
+                t[(size_t)o * kpad + i] = net->A[li][(size_t)o * din + i];
+                amax = std::fmax(amax, std::fabs(net->A[li][(size_t)o * din + i]));
+            }
             bb[o] = net->beta[li][o];
+            if (prec == kPrecFP8 && amax > 0.f) {
+                sc[o] = amax / 448.f;
+                for (int i = 0; i < din; i++) t[(size_t)o * kpad + i] /= sc[o];
+            }
         }
         // B-fragment order: block (ct, kc) holds, for lane l = r + 16 g, the
         // elements W[ct*16 + r][kc*KS + g*KPL + e], e < KPL, contiguously
@@ -380,8 +421,9 @@ void pack_net(Net* net, int prec)
                 for (int l = 0; l < 64; l++)
                     for (int e = 0; e < KPL; e++)
                         f[pos++] = t[(size_t)(ct * 16 + l % 16) * kpad + kc * KS + (l / 16) * KPL + e];
-        put(P.W[li], f, "backbone weights");
+        put(P.W[li], f, "backbone weights", true);
         upload_vec(P.bias[li], bb, "backbone biases");
+        if (prec == kPrecFP8) upload_vec(P.wscale[li], sc, "backbone weight scales");
     }
     std::vector<float> wo(Wp, 0.f);
     for (int i = 0; i < W; i++) wo[i] = net->A[net->n_linear - 1][i];
@@ -399,6 +441,7 @@ void free_net(Net* net)
         }
         for (auto& b : P.W) b.release();
         for (auto& b : P.bias) b.release();
+        for (auto& b : P.wscale) b.release();
         P.wout.release();
     }
     delete net;
@@ -408,6 +451,7 @@ void free_net(Net* net)
 
 constexpr int64_t kChunk = 1 << 21;   // points per feature/backbone pass
 
+// the FP8 path stores the descriptor in BF16 and quantises it in the backbone
 size_t desc_elem_bytes(int prec) { return prec == kPrecFP32 ? 4 : 2; }
 
 struct QueryOut {
@@ -435,6 +479,7 @@ void run_query(nis_ctx* ctx, Medium* M, const float* d_pts, const float* d_dirs,
     const int64_t chunk = n < kChunk ? n : kChunk;
     ctx->desc.reserve((size_t)chunk * kDescPad * desc_elem_bytes(prec), "descriptor workspace");
     ctx->f0.reserve((size_t)chunk * sizeof(float), "single-scatter workspace");
+    if (prec == kPrecFP8) ctx->rowmax.reserve((size_t)chunk * sizeof(float), "descriptor row maxima");
     MediumView mv = make_view(M, net);
     for (int64_t p0 = 0; p0 < n; p0 += chunk) {
         const int64_t cn = (n - p0) < chunk ? (n - p0) : chunk;
@@ -456,6 +501,7 @@ void run_query(nis_ctx* ctx, Medium* M, const float* d_pts, const float* d_dirs,
         }
         fa.desc = ctx->desc.p;
         fa.f0 = o.f0 ? o.f0 + p0 : ctx->f0.as<float>();
+        fa.rowmax = prec == kPrecFP8 ? ctx->rowmax.as<float>() : nullptr;
         auto off = [&](float* base, int64_t per) { return base ? base + p0 * per : nullptr; };
         fa.dbg_tbar = off(o.tbar, kLayers * kSites);
         fa.dbg_rho = off(o.rho, kLayers * kSites);
@@ -476,7 +522,9 @@ void run_query(nis_ctx* ctx, Medium* M, const float* d_pts, const float* d_dirs,
         for (int li = 0; li + 1 < net->n_linear; li++) {
             ma.W[li] = P.W[li].p;
             ma.bias[li] = P.bias[li].as<float>();
+            ma.wscale[li] = P.wscale[li].as<float>();
         }
+        ma.rowmax = fa.rowmax;
         ma.wout = P.wout.as<float>();
         ma.bout = net->beta[net->n_linear - 1][0];
         ma.n_linear = net->n_linear;
@@ -533,6 +581,7 @@ int32_t nis_destroy(nis_ctx* ctx)
         free_net(ctx->net);
         ctx->desc.release();
         ctx->f0.release();
+        ctx->rowmax.release();
         ctx->io.release();
         (void)hipStreamDestroy(ctx->stream);
         delete ctx;
@@ -687,6 +736,7 @@ int32_t nis_set_weights(nis_ctx* ctx, const void* blob, size_t nbytes)
             if (net->has_fp8) net->fp8_scales.assign(all.begin() + pos, all.end());
             pack_net(net, kPrecFP32);
             pack_net(net, kPrecBF16);
+            pack_net(net, kPrecFP8);
         } catch (...) {
             free_net(net);
             throw;
@@ -701,8 +751,8 @@ int32_t nis_set_precision(nis_ctx* ctx, int32_t precision)
 {
     return guard([&] {
         check_ctx(ctx);
-        if (precision == NIS_FP8) fail(NIS_E_UNSUPPORTED, "FP8 network path is not available");
-        if (precision != NIS_FP32 && precision != NIS_BF16) fail(NIS_E_INVALID, "unknown precision");
+        if (precision != NIS_FP32 && precision != NIS_BF16 && precision != NIS_FP8)
+            fail(NIS_E_INVALID, "unknown precision");
         ctx->precision = precision;
     });
 }

@@ -94,9 +94,18 @@ def test_descriptor_and_network_output_fp32(ctx):
     s.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 1e-2)])
+FP8_TARGET_MISS = pytest.mark.xfail(
+    strict=True, reason="E4M3 keeps 3 mantissa bits: each quantised He-init layer adds about 5% relative "
+                        "error, so the all-FP8 backbone reaches rel-L2 0.06-0.07, above the 3e-2 target")
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 1e-2),
+                                      pytest.param("fp8", 3e-2, marks=FP8_TARGET_MISS),
+                                      ("fp8", 0.1)])
 def test_query_small_workload(ctx, prec, tol):
-    """The 32^3 / 64x64 / 6x128 workload end to end."""
+    """The 32^3 / 64x64 / 6x128 workload end to end.  FP32 and BF16 meet their
+    targets (1e-4, 1e-2).  FP8 is checked against its target (3e-2, recorded as
+    not met) and against the bound it achieves (0.1), which guards regressions."""
     w = configs.SMALL
     d = w.density()
     pts, dirs, _ = w.points(d)
@@ -117,7 +126,7 @@ def test_query_small_workload(ctx, prec, tol):
     s.close()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
 @pytest.mark.parametrize("width", [16, 24, 100, 200, 256])
 def test_backbone_widths(ctx, width, prec):
     """Every padded backbone width, including widths whose padding is not a
@@ -137,10 +146,15 @@ def test_backbone_widths(ctx, width, prec):
     print("width %d %s: rel-L2(L) %.3g max|dy| %.3g" % (
         width, prec, rel_l2(L, ref["L"]), np.abs(y.cpu().numpy() - ref["y"]).max()), flush=True)
     assert np.all(np.isfinite(L))
+    dy = np.abs(y.cpu().numpy() - ref["y"]).max()
     if prec == "fp32":
         assert rel_l2(L, ref["L"]) <= 1e-4
+    elif prec == "bf16":
+        assert dy <= 0.04
     else:
-        assert np.abs(y.cpu().numpy() - ref["y"]).max() <= 0.04
+        # E4M3 unit roundoff is 2^-4 (6.25%); three quantised layers of
+        # order-one activations, twice the worst case seen (0.38)
+        assert dy <= 0.75
     s.close()
 
 
@@ -174,18 +188,21 @@ def test_selector_weights_reach_every_descriptor_part(ctx, entry):
     s.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
 @pytest.mark.parametrize("count", [1, 31, 33, 127, 129, 1000])
-def test_ragged_batches_and_batch_invariance(ctx, count):
+def test_ragged_batches_and_batch_invariance(ctx, count, prec):
     d, pts, dirs = small_points()
     s = Scene(ctx, d, configs.LIGHT_DIR)
     params = weights.he_init(128, 6, seed=1)
     ctx.set_weights(params)
+    ctx.set_precision(prec)
     full = ctx.query(s.mid, pts, dirs)
     idx = np.random.default_rng(count).choice(len(pts), count, replace=False)
     part = ctx.query(s.mid, pts[idx], dirs[idx])
     np.testing.assert_array_equal(part, full[idx])          # points are independent
     again = ctx.query(s.mid, pts, dirs)
     np.testing.assert_array_equal(again, full)              # deterministic
+    ctx.set_precision("fp32")
     s.close()
 
 
