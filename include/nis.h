@@ -26,8 +26,15 @@
  *
  * Memory.  The context owns every device allocation it makes.  Host arrays
  * passed in are copied before the call returns (the caller may free them);
- * device arrays passed to nis_query_device are borrowed until the work queued
- * on the given stream has completed.
+ * device arrays passed to the asynchronous calls are borrowed until the work
+ * queued on the given stream has completed.
+ *
+ * Streams.  Asynchronous calls take a `hip_stream` (a hipStream_t; NULL is
+ * HIP's null stream).  The work of one context is ordered across streams: the
+ * work a call queues starts after the work of the context's earlier calls,
+ * whatever streams those used (an event recorded at the end of each call, and
+ * waited for when the next call uses another stream).  Synchronous calls
+ * return after their own work completes.
  */
 #ifndef NIS_H
 #define NIS_H
@@ -92,8 +99,8 @@ int32_t nis_load_medium(nis_ctx *ctx, const float *density, int32_t n, float sig
 
 /*
  * nis_rebuild_pyramid -- recomputes levels 1.. of the pyramid from the
- * resident level 0 on `hip_stream` (NULL = the context stream), without any
- * host transfer, and marks the transmittance fields stale.  Asynchronous.
+ * resident level 0 on `hip_stream`, without any host transfer, and marks the
+ * transmittance fields stale.  Asynchronous.
  */
 int32_t nis_rebuild_pyramid(nis_ctx *ctx, int32_t medium, void *hip_stream);
 
@@ -109,7 +116,7 @@ int32_t nis_unload_medium(nis_ctx *ctx, int32_t medium);
  * light, normalised inside; a zero or non-finite vector is NIS_E_INVALID) with
  * intensity `radiance`.  Marks the graded transmittance fields (eq. 1) stale;
  * they are recomputed by the sweep at the next query, or now with NIS_EAGER
- * (then asynchronous on the context stream).
+ * (then queued on the context's own stream, ordered before later calls).
  */
 int32_t nis_set_light(nis_ctx *ctx, int32_t medium, const float dir[3], float radiance,
                       int32_t flags);
@@ -152,13 +159,133 @@ int32_t nis_query(nis_ctx *ctx, int32_t medium, const float *points, const float
 
 /*
  * nis_query_device -- as nis_query on device arrays, queued on `hip_stream`
- * (a hipStream_t; NULL = the context stream) and returning before the work
- * completes.  Inputs are not validated element-wise.  Scratch memory is owned
- * by the context; overlapping queries on one context must use one stream.
+ * and returning before the work completes.  Inputs are not validated
+ * element-wise.  Scratch memory is owned by the context and reused by its
+ * next call (which the ordering above makes safe).
  */
 int32_t nis_query_device(nis_ctx *ctx, int32_t medium, const float *d_points,
                          const float *d_view_dirs, int64_t n, float *d_radiance_out,
                          void *hip_stream);
+
+/* ---- frames --------------------------------------------------------------- */
+
+/*
+ * A camera.  vfov_deg in (0,180): pinhole at `eye` looking at `target` with
+ * `up` fixing the roll; the vertical field of view is vfov_deg and the
+ * horizontal one follows from width / height.  Pixel (col, row), row 0 at the
+ * top, is index row * width + col; its ray passes through the pixel centre.
+ * vfov_deg == 0: orthographic rays along -z through the pixel centres of the
+ * unit square at height ortho_z (x = (col + 0.5) / width, y = (row + 0.5) /
+ * height).  At most 2^28 pixels.
+ */
+typedef struct nis_camera {
+    double eye[3];
+    double target[3];
+    double up[3];
+    double vfov_deg;
+    double ortho_z;
+    int32_t width;
+    int32_t height;
+} nis_camera;
+
+/*
+ * nis_frame_points -- the shading points of a frame: for each pixel's ray,
+ * the first real collision inside the unit cube found by delta tracking on the
+ * finest density level read as piecewise constant per voxel (majorant
+ * sigma_t * max density; free flights -log(1-u)/majorant; acceptance with
+ * probability sigma_t * rho / majorant; u from the SplitMix64 hash
+ * mix(mix(mix(seed) ^ pixel) ^ draw), top 53 bits, draw 2i for the i-th flight
+ * and 2i+1 for its acceptance; at most 100000 flights per ray).  Writes the
+ * collisions compacted in pixel order: d_points and d_dirs float32 [P][3]
+ * (ray direction, unit), d_pixel int32 [P], and P to d_count (one int32).  All
+ * four are device arrays sized for width*height entries, borrowed until the
+ * work queued on `hip_stream` completes.  Asynchronous.
+ * Errors: NIS_E_INVALID (NULL output, bad camera), NIS_E_STATE.
+ */
+int32_t nis_frame_points(nis_ctx *ctx, int32_t medium, const nis_camera *camera, uint64_t seed,
+                         float *d_points, float *d_dirs, int32_t *d_pixel, int32_t *d_count,
+                         void *hip_stream);
+
+/*
+ * nis_render -- one frame (eq. 19 at every collision): the points of
+ * nis_frame_points queried at the context's precision, and
+ * d_image[row * width + col] = albedo * L at a collision, 0 where the ray
+ * leaves the medium.  d_image is a device float32 array of width*height
+ * entries.  Queued on `hip_stream` with no host synchronisation: the query
+ * reads the collision count from device memory.  Errors as nis_query_device.
+ */
+int32_t nis_render(nis_ctx *ctx, int32_t medium, const nis_camera *camera, uint64_t seed,
+                   float *d_image, void *hip_stream);
+
+/* ---- frame server -------------------------------------------------------------
+ *
+ * A scheduler thread owned by the context takes frame requests from any
+ * number of host threads and keeps up to max_inflight of them on the device at
+ * once, each on its own stream with its own light fields and workspace,
+ * admitting the oldest queued request as soon as a stream is free and the
+ * device memory it needs fits the budget (first come, first served).  A
+ * frame's image does not depend on what else is in flight.  The server calls
+ * are thread-safe.  While a server runs, nis_set_weights, nis_unload_medium and
+ * nis_rebuild_pyramid return NIS_E_STATE; other calls stay valid.
+ */
+
+#define NIS_QUEUED 1    /* nis_frame_result.status: waiting for admission */
+#define NIS_RUNNING 2   /* on the device */
+
+typedef struct nis_server_cfg {
+    uint64_t hbm_budget_bytes;  /* device memory the server may hold: per-stream light
+                                   fields and workspaces plus every unreleased image */
+    int32_t precision;          /* NIS_FP32, NIS_BF16 or NIS_FP8 */
+    int32_t max_inflight;       /* frames on the device at once, 1..16 */
+} nis_server_cfg;
+
+typedef struct nis_frame_req {
+    int32_t medium;
+    nis_camera camera;
+    float light_dir[3];         /* towards the light, normalised inside */
+    float radiance;             /* light intensity I */
+    float g;                    /* HG asymmetry of this frame, in (-1,1) */
+    uint64_t seed;              /* delta-tracking seed */
+} nis_frame_req;
+
+typedef struct nis_frame_result {
+    int32_t status;             /* NIS_QUEUED, NIS_RUNNING, NIS_OK (done) or a negative error */
+    int32_t width, height;
+    int64_t n_points;           /* collisions shaded (valid when done) */
+    const float *d_image;       /* device [height][width] float32, valid until nis_release */
+    double t_submit, t_start, t_done;   /* seconds since nis_server_start (host steady clock):
+                                           submitted, admitted, completion observed */
+} nis_frame_result;
+
+/* Device memory the server holds while it runs the frame `req` at `precision`:
+ * the query workspace, the per-pixel frame buffers, the light's path-density
+ * fields and site tables, and the image.  Needs no server. */
+int32_t nis_frame_memory(nis_ctx *ctx, const nis_frame_req *req, int32_t precision,
+                         uint64_t *bytes);
+
+/* Starts the server.  NIS_E_STATE if one runs or no weights are set;
+ * NIS_E_INVALID for a bad configuration. */
+int32_t nis_server_start(nis_ctx *ctx, const nis_server_cfg *cfg);
+
+/* Queues a frame and writes its id.  The medium's sigma_t and albedo are read
+ * now.  NIS_E_NOMEM if the frame alone needs more than the whole budget;
+ * NIS_E_INVALID / NIS_E_STATE for bad requests or no server. */
+int32_t nis_submit_frame(nis_ctx *ctx, const nis_frame_req *req, uint64_t *id);
+
+/* Current state of a frame; never blocks.  NIS_E_INVALID for an unknown id. */
+int32_t nis_poll(nis_ctx *ctx, uint64_t id, nis_frame_result *out);
+
+/* As nis_poll, but blocks until the frame is done or failed. */
+int32_t nis_wait(nis_ctx *ctx, uint64_t id, nis_frame_result *out);
+
+/* Returns a finished frame's image memory to the server.  NIS_E_STATE while
+ * the frame is queued or running. */
+int32_t nis_release(nis_ctx *ctx, uint64_t id);
+
+/* Waits for the frames on the device, drops queued ones, frees every server
+ * allocation (unreleased images included) and stops the thread.  NIS_E_STATE if
+ * no server runs. */
+int32_t nis_server_stop(nis_ctx *ctx);
 
 /* Thread-local message of the last failing call ("" if none). */
 const char *nis_last_error(void);

@@ -25,6 +25,8 @@ COMMON = ["--offload-arch=" + ARCH, "-std=c++17", "-fPIC", "-Wall", "-Wno-unused
           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 SOURCES = {
     "nis_api.cpp": ["-O2", "-ffp-contract=off", "-x", "hip"],
+    "server.cpp": ["-O2", "-ffp-contract=off", "-x", "hip"],
+    "k_frame.hip": ["-O3"],
     "k_volume.hip": ["-O3"],
     "k_features.hip": ["-O3"],
     "k_mlp.hip": ["-O3"],
@@ -54,7 +56,7 @@ def build(verbose=False):
                 print(out, file=sys.stderr)
             objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)

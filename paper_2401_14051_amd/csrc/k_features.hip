@@ -173,13 +173,17 @@ k_features(FeatArgs A)
     const int wave = tid / 64, lane = tid % 64;
     const int lr = lane % 16, lg = lane / 16;
     const int64_t tile0 = (int64_t)blockIdx.x * kTP;
+    // the point count may live in device memory (frames whose hit count the
+    // device computed); blocks past it leave before any barrier
+    const int64_t npts = A.count ? min(max((int64_t)*A.count - A.count_off, (int64_t)0), A.npts) : A.npts;
+    if (tile0 >= npts) return;
 
     // ---- per point: position, phase features, transmittance to the light ----
     {
         const int pt = tid / 16, sub = tid % 16;
         const int64_t p = tile0 + pt;
-        const bool live = p < A.npts;
-        const int64_t pc = live ? p : A.npts - 1;
+        const bool live = p < npts;
+        const int64_t pc = live ? p : npts - 1;
         double x[3], w[3];
         for (int d = 0; d < 3; d++) {
             x[d] = A.pts[3 * pc + d];
@@ -400,7 +404,7 @@ k_features(FeatArgs A)
                 rmx = fmaxf(rmx, rv);
                 ts += T;
                 tmx = fmaxf(tmx, T);
-                if (DBG && p < A.npts) {
+                if (DBG && p < npts) {
                     A.dbg_tbar[(p * kLayers + k) * kSites + r * 5 + i] = T;
                     A.dbg_rho[(p * kLayers + k) * kSites + r * 5 + i] = rv;
                 }
@@ -528,7 +532,7 @@ k_features(FeatArgs A)
             }
             q[5] = M::cvt(o < kStats ? pstat[pt][o] : 0.f);
             lmax = fmaxf(lmax, fabsf((float)q[5]));
-            if (pp < A.npts) {
+            if (pp < npts) {
                 E* d = desc + pp * kDescPad + k * kPerLayer;
 #pragma unroll
                 for (int z = 0; z < 5; z++) d[o * 5 + z] = q[z];
@@ -545,9 +549,9 @@ k_features(FeatArgs A)
     for (int e = tid; e < kTP * (kDescPad - kDesc + 1); e += 256) {
         const int pt = e / (kDescPad - kDesc + 1), f = kDesc - 1 + e % (kDescPad - kDesc + 1);
         const int64_t pp = tile0 + pt;
-        if (pp < A.npts) desc[pp * kDescPad + f] = M::cvt(f == kDesc - 1 ? mv.albedo : 0.f);
+        if (pp < npts) desc[pp * kDescPad + f] = M::cvt(f == kDesc - 1 ? mv.albedo : 0.f);
     }
-    if (A.rowmax && tid % 16 == 0 && tile0 + tid / 16 < A.npts)
+    if (A.rowmax && tid % 16 == 0 && tile0 + tid / 16 < npts)
         A.rowmax[tile0 + tid / 16] = fmaxf(row_absmax, fabsf((float)M::cvt(mv.albedo)));
 }
 

@@ -1,0 +1,188 @@
+// k_frame.hip -- frame driver: camera rays, first-collision delta tracking,
+// compaction of the hits into a point list, and the image write.
+//
+// These kernels produce the shading points a frame queries (they are support
+// for the hot path, not part of the method).  One ray per pixel: pinhole rays
+// through pixel centres (row 0 at the top) or orthographic rays along -z
+// through the pixel centres of the unit square.  Delta tracking (Woodcock)
+// runs on the piecewise-constant voxel density of the finest level with
+// majorant sigma_t * max(rho): free flights -log(1-u)/majorant, a tentative
+// collision accepted with probability mu/majorant.  Uniform numbers are a
+// counter-based hash of (seed, pixel, draw) with the SplitMix64 mixer of
+// Steele, Lea and Flood (2014): mix(x) = finalise(x + 0x9E3779B97F4A7C15)
+// with xor-shift-multiply rounds (30, 0xBF58476D1CE4E5B9; 27,
+// 0x94D049BB133111EB; 31), h = mix(mix(mix(seed) ^ pixel) ^ draw),
+// u = (h >> 11) * 2^-53; draw 2i is the i-th flight, 2i+1 its acceptance.
+// Geometry runs in double precision.
+#include <hipcub/hipcub.hpp>
+
+#include "launch_args.h"
+
+namespace nis {
+
+__device__ __forceinline__ uint64_t sm_mix(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double uniform01(uint64_t seed, uint64_t stream, uint64_t draw)
+{
+    const uint64_t h = sm_mix(sm_mix(sm_mix(seed) ^ stream) ^ draw);
+    return (double)(h >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// slab interval of the ray against [0,1]^3; an axis whose products are NaN
+// (origin on a face with a zero direction) does not constrain the ray
+__device__ __forceinline__ void box_interval(const double o[3], const double d[3], double& t_in, double& t_out)
+{
+#pragma clang fp contract(off)
+    double tmin = -INFINITY, tmax = INFINITY;
+    bool any_min = false, any_max = false;
+    for (int a = 0; a < 3; a++) {
+        const double inv = 1.0 / d[a];
+        const double t0 = (0.0 - o[a]) * inv, t1 = (1.0 - o[a]) * inv;
+        if (isnan(t0) || isnan(t1)) continue;
+        const double lo = t0 < t1 ? t0 : t1, hi = t0 < t1 ? t1 : t0;
+        tmin = any_min ? fmax(tmin, lo) : lo;
+        tmax = any_max ? fmin(tmax, hi) : hi;
+        any_min = any_max = true;
+    }
+    t_in = fmax(tmin, 0.0);
+    t_out = tmax;
+}
+
+__device__ __forceinline__ void camera_ray(const CamArgs& C, int px, int py, double o[3], double d[3])
+{
+#pragma clang fp contract(off)
+    if (C.ortho) {
+        o[0] = (px + 0.5) / C.width;
+        o[1] = (py + 0.5) / C.height;
+        o[2] = C.oz;
+        d[0] = 0.0;
+        d[1] = 0.0;
+        d[2] = -1.0;
+        return;
+    }
+    const double col = (px + 0.5) / C.width * 2.0 - 1.0;
+    const double row = 1.0 - (py + 0.5) / C.height * 2.0;
+    const double sc = col * C.aspect * C.tan_half, sr = row * C.tan_half;
+    for (int a = 0; a < 3; a++) {
+        o[a] = C.eye[a];
+        d[a] = (C.f[a] + sc * C.r[a]) + sr * C.u[a];
+    }
+    const double nrm = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+    for (int a = 0; a < 3; a++) d[a] /= nrm;
+}
+
+__global__ void __launch_bounds__(256)
+k_raygen(CamArgs C, const float* __restrict__ rho, int n, double sigma_t, double majorant, uint64_t seed,
+         int* __restrict__ flag, float* __restrict__ pts, float* __restrict__ dirs)
+{
+#pragma clang fp contract(off)
+    const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= (int64_t)C.width * C.height) return;
+    const int px = (int)(pix % C.width), py = (int)(pix / C.width);
+    double o[3], d[3];
+    camera_ray(C, px, py, o, d);
+    double t_in, t_out;
+    box_interval(o, d, t_in, t_out);
+    int hit = 0;
+    double t = t_in;
+    if (t_in < t_out && majorant > 0.0) {
+        for (int step = 0; step < kMaxTrackingSteps; step++) {
+            const double uf = uniform01(seed, (uint64_t)pix, 2 * (uint64_t)step);
+            const double ua = uniform01(seed, (uint64_t)pix, 2 * (uint64_t)step + 1);
+            t = t - log1p(-uf) / majorant;
+            if (!(t < t_out)) break;
+            int idx[3];
+            for (int a = 0; a < 3; a++) {
+                const double x = o[a] + t * d[a];
+                const double fl = floor(x * n);
+                idx[a] = fl < 0.0 ? 0 : (fl > n - 1 ? n - 1 : (int)fl);
+            }
+            const double r = rho[((int64_t)idx[2] * n + idx[1]) * n + idx[0]];
+            if (ua * majorant < sigma_t * r) {
+                hit = 1;
+                break;
+            }
+        }
+    }
+    flag[pix] = hit;
+    for (int a = 0; a < 3; a++) {
+        pts[3 * pix + a] = hit ? (float)(o[a] + t * d[a]) : 0.f;
+        dirs[3 * pix + a] = (float)d[a];
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_compact(const int* __restrict__ flag, const int* __restrict__ offset, const float* __restrict__ pts,
+          const float* __restrict__ dirs, int64_t npix, float* __restrict__ cpts, float* __restrict__ cdirs,
+          int* __restrict__ cpix)
+{
+    const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= npix || !flag[pix]) return;
+    const int64_t o = offset[pix];
+    for (int a = 0; a < 3; a++) {
+        cpts[3 * o + a] = pts[3 * pix + a];
+        cdirs[3 * o + a] = dirs[3 * pix + a];
+    }
+    cpix[o] = (int)pix;
+}
+
+__global__ void k_count(const int* __restrict__ flag, const int* __restrict__ offset, int64_t npix,
+                        int* __restrict__ count)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count = npix > 0 ? offset[npix - 1] + flag[npix - 1] : 0;
+}
+
+__global__ void __launch_bounds__(256) k_fill(float* __restrict__ p, int64_t n, float v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void __launch_bounds__(256)
+k_scatter_image(const int* __restrict__ cpix, const float* __restrict__ L, const int* __restrict__ count,
+                float scale, float* __restrict__ image)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < *count) image[cpix[i]] = scale * L[i];
+}
+
+hipError_t frame_scan_bytes(int64_t npix, size_t* bytes)
+{
+    *bytes = 0;
+    return hipcub::DeviceScan::ExclusiveSum(nullptr, *bytes, (const int*)nullptr, (int*)nullptr, (int)npix);
+}
+
+hipError_t launch_raygen(const CamArgs& C, const float* rho0, int n, double sigma_t, double majorant,
+                         uint64_t seed, const FrameBuffers& fb, hipStream_t s)
+{
+    const int64_t npix = (int64_t)C.width * C.height;
+    const int blocks = (int)((npix + 255) / 256);
+    hipLaunchKernelGGL(k_raygen, dim3(blocks), dim3(256), 0, s, C, rho0, n, sigma_t, majorant, seed, fb.flag,
+                       fb.pts, fb.dirs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    size_t bytes = fb.scan_bytes;
+    e = hipcub::DeviceScan::ExclusiveSum(fb.scan_tmp, bytes, fb.flag, fb.offset, (int)npix, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(256), 0, s, fb.flag, fb.offset, fb.pts, fb.dirs, npix,
+                       fb.cpts, fb.cdirs, fb.cpix);
+    hipLaunchKernelGGL(k_count, dim3(1), dim3(64), 0, s, fb.flag, fb.offset, npix, fb.count);
+    return hipGetLastError();
+}
+
+hipError_t launch_image(const FrameBuffers& fb, int64_t npix, const float* L, float scale, float* image,
+                        hipStream_t s)
+{
+    const int blocks = (int)((npix + 255) / 256);
+    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, image, npix, 0.f);
+    hipLaunchKernelGGL(k_scatter_image, dim3(blocks), dim3(256), 0, s, fb.cpix, L, fb.count, scale, image);
+    return hipGetLastError();
+}
+
+}  // namespace nis

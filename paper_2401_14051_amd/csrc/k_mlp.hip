@@ -40,6 +40,8 @@ k_mlp(MlpArgs A)
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int lr = lane % 16, lg = lane / 16;
     const int64_t row0 = ((int64_t)blockIdx.x * kMlpWaves + wave) * ROWS;
+    const int64_t npts = A.count ? min(max((int64_t)*A.count - A.count_off, (int64_t)0), A.npts) : A.npts;
+    if ((int64_t)blockIdx.x * kMlpWaves * ROWS >= npts) return;
     E(*h)[HS] = hbuf[wave];
     const E* x = reinterpret_cast<const E*>(A.x);
 
@@ -61,7 +63,7 @@ k_mlp(MlpArgs A)
 #pragma unroll
             for (int rt = 0; rt < RT; rt++) {
                 int64_t r = row0 + rt * 16 + lr;
-                r = r < A.npts ? r : A.npts - 1;
+                r = r < npts ? r : npts - 1;
                 xr[rt] = x + r * kDescPad + lg * M::KPL;
             }
             for (int kc = 0; kc < KC; kc++) {
@@ -106,7 +108,7 @@ k_mlp(MlpArgs A)
         const int64_t row = row0 + rr;
         float y = A.bout;
         for (int k = 0; k < W; k++) y += (float)h[rr][k] * A.wout[k];
-        if (row < A.npts) {
+        if (row < npts) {
             if (A.y_out) A.y_out[row] = y;
             if (A.out) A.out[row] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
         }
@@ -138,6 +140,8 @@ k_mlp_fp8(MlpArgs A)
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int lr = lane % 16, lg = lane / 16;
     const int64_t row0 = ((int64_t)blockIdx.x * kMlpWaves + wave) * ROWS;
+    const int64_t npts = A.count ? min(max((int64_t)*A.count - A.count_off, (int64_t)0), A.npts) : A.npts;
+    if ((int64_t)blockIdx.x * kMlpWaves * ROWS >= npts) return;
     uint8_t(*h)[HS] = hbuf[wave];
     float* rs = rsc[wave];
     const __bf16* x = reinterpret_cast<const __bf16*>(A.x);
@@ -151,7 +155,7 @@ k_mlp_fp8(MlpArgs A)
 #pragma unroll
     for (int rt = 0; rt < RT; rt++) {
         int64_t r = row0 + rt * 16 + lr;
-        r = r < A.npts ? r : A.npts - 1;
+        r = r < npts ? r : npts - 1;
         xr[rt] = x + r * kDescPad + lg * M::KPL;
         const float m = A.rowmax[r];
         qs[rt] = m > 0.f ? kTarget / m : 1.f;
@@ -236,7 +240,7 @@ k_mlp_fp8(MlpArgs A)
         float y = 0.f;
         for (int k = 0; k < W; k++) y += __builtin_amdgcn_cvt_f32_fp8((int)h[rr][k], 0) * A.wout[k];
         y = A.bout + y * rs[rr];
-        if (row < A.npts) {
+        if (row < npts) {
             if (A.y_out) A.y_out[row] = y;
             if (A.out) A.out[row] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
         }

@@ -25,6 +25,8 @@ struct FeatArgs {
     float* dbg_stats;            // optional [npts][12][8]
     float* dbg_tp;               // optional [npts]
     float* rowmax;               // optional [npts]: max |entry| of each stored descriptor row
+    const int* count;            // optional device point count: the kernel serves
+    int64_t count_off;           // min(npts, *count - count_off) points
 };
 
 struct MlpArgs {
@@ -42,6 +44,34 @@ struct MlpArgs {
     float* y_out;                    // [npts] network output (may be NULL)
     float albedo_gamma;              // albedo^gamma
     float radiance;
+    const int* count;                // optional device point count, as in FeatArgs
+    int64_t count_off;
+};
+
+constexpr int kMaxTrackingSteps = 100000;   // free flights per camera ray before it is dropped
+
+// Camera of a frame: orthographic rays along -z through the pixel centres of
+// the unit square at height oz, or pinhole rays from eye along the
+// orthonormal frame (f forward, r right, u up); double precision.
+struct CamArgs {
+    int ortho;
+    int width, height;
+    double oz, aspect, tan_half;
+    double eye[3], f[3], r[3], u[3];
+};
+
+// Device buffers of one frame (npix = width * height entries each, except count).
+struct FrameBuffers {
+    int* flag;          // 1 where the ray collides inside the medium
+    int* offset;        // exclusive prefix sum of flag
+    float* pts;         // [npix][3] collision points (0 on a miss)
+    float* dirs;        // [npix][3] ray directions
+    float* cpts;        // [npix][3] compacted points, pixel order
+    float* cdirs;       // [npix][3] compacted directions
+    int* cpix;          // [npix] pixel of each compacted point
+    int* count;         // [1] number of collisions
+    void* scan_tmp;
+    size_t scan_bytes;
 };
 
 hipError_t launch_pyramid(const float* rho, const Level* lev, int levels, hipStream_t s);
@@ -51,6 +81,11 @@ hipError_t launch_features(int prec, const FeatArgs& a, hipStream_t s);
 hipError_t launch_desc_to_f32(int prec, const void* src, float* dst, int64_t n, hipStream_t s);
 hipError_t launch_mlp(int prec, const MlpArgs& a, hipStream_t s);
 int mlp_padded_width(int width);
+hipError_t frame_scan_bytes(int64_t npix, size_t* bytes);
+hipError_t launch_raygen(const CamArgs& C, const float* rho0, int n, double sigma_t, double majorant,
+                         uint64_t seed, const FrameBuffers& fb, hipStream_t s);
+hipError_t launch_image(const FrameBuffers& fb, int64_t npix, const float* L, float scale, float* image,
+                        hipStream_t s);
 int mlp_hidden_k(int prec, int wpad);
 int mlp_k_step(int prec);       // K per MFMA instruction
 int mlp_k_per_lane(int prec);   // K elements a lane holds in one B fragment

@@ -2,36 +2,22 @@
 //
 // Owns the device memory of every medium (density pyramid, path-density
 // fields, per-light site tables), the packed network weights for each
-// precision, and the per-context workspace, and queues the kernels on HIP
+// precision, and the per-stream workspaces, and queues the kernels on HIP
 // streams.  Double-precision set-up values (light frame, lattice offsets,
-// per-layer coefficients) are computed here term by term; this file is built
-// with -ffp-contract=off so that each product and sum is rounded once.
-#include <hip/hip_runtime.h>
-
+// per-layer coefficients, camera frames) are computed here term by term; this
+// file is built with -ffp-contract=off so that each product and sum is rounded
+// once.
 #include <cmath>
-#include <cstdint>
 #include <cstdio>
-#include <cstring>
-#include <map>
-#include <new>
-#include <string>
-#include <vector>
 
-#include "../../include/nis.h"
-#include "launch_args.h"
+#include "runtime.h"
 
-using namespace nis;
-
-namespace {
+namespace nis {
 
 thread_local std::string g_err;
+thread_local Profiler* g_prof = nullptr;
 
-struct Error {
-    int32_t code;
-    std::string msg;
-};
-
-[[noreturn]] void fail(int32_t code, const std::string& msg) { throw Error{code, msg}; }
+void fail(int32_t code, const std::string& msg) { throw Error{code, msg}; }
 
 void hip_check(hipError_t e, const char* what)
 {
@@ -40,42 +26,49 @@ void hip_check(hipError_t e, const char* what)
     fail(NIS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-template <class F> int32_t guard(F&& f)
+void DevBuf::reserve(size_t nbytes, const char* what)
 {
-    try {
-        f();
-        g_err.clear();
-        return NIS_OK;
-    } catch (const Error& e) {
-        g_err = e.msg;
-        return e.code;
-    } catch (const std::bad_alloc&) {
-        g_err = "host allocation failed";
-        return NIS_E_NOMEM;
-    } catch (...) {
-        g_err = "internal error";
-        return NIS_E_INTERNAL;
-    }
+    if (nbytes <= bytes) return;
+    release();
+    hip_check(hipMalloc(&p, nbytes), what);
+    bytes = nbytes;
 }
 
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    void reserve(size_t nbytes, const char* what)
-    {
-        if (nbytes <= bytes) return;
-        release();
-        hip_check(hipMalloc(&p, nbytes), what);
-        bytes = nbytes;
+void DevBuf::release()
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+hipEvent_t Profiler::get()
+{
+    if (pool.empty()) {
+        hipEvent_t e;
+        hip_check(hipEventCreate(&e), "hipEventCreate");
+        return e;
     }
-    void release()
-    {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+}
+
+void Profiler::clear()
+{
+    for (auto& r : recs) {
+        pool.push_back(r.a);
+        pool.push_back(r.b);
     }
-    template <class T> T* as() const { return reinterpret_cast<T*>(p); }
-};
+    recs.clear();
+}
+
+Profiler::~Profiler()
+{
+    clear();
+    for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+namespace {
 
 uint16_t bf16_bits(float f)
 {
@@ -86,101 +79,18 @@ uint16_t bf16_bits(float f)
     return (uint16_t)(u >> 16);
 }
 
-struct Medium {
-    int n = 0, levels = 0;
-    float sigma_t = 0, albedo = 0, g = 0;
-    Level lev[kMaxLevels] = {};
-    DevBuf rho, D, tab;
-    int64_t rho_floats = 0;
-    bool has_light = false, stale = true, tab_stale = true;
-    double l[3] = {0, 0, 0};
-    float radiance = 1.f;
-    int a = 0, b = 1, c = 2, sigma = 1;
-    double sb = 0, sc = 0, la = 1;
-    double qoff[3][9] = {};
-};
-
-struct PackedNet {
-    DevBuf w1t[2], w2t[2], cb[2];
-    DevBuf W[16], bias[16], wscale[16], wout;
-};
-
-struct Net {
-    int width = 0, n_linear = 0, wpad = 0;
-    float lam = 0.6f, gamma = 4.f;
-    bool has_fp8 = false;
-    std::vector<float> groups[2];      // 3844 floats each, blob order
-    std::vector<std::vector<float>> A, beta;
-    std::vector<float> fp8_scales;
-    PackedNet packed[3];               // fp32, bf16, fp8
-};
-
 constexpr int kGroupFloats = 216 + 8 + 3456 + 16 + 64 + 4 + 64 + 16;
-
-// Per-kernel timing with HIP events on the stream each kernel runs on.
-struct Profiler {
-    bool on = false;
-    struct Rec {
-        const char* name;
-        hipEvent_t a, b;
-    };
-    std::vector<Rec> recs;
-    std::vector<hipEvent_t> pool;
-    hipEvent_t get()
-    {
-        if (pool.empty()) {
-            hipEvent_t e;
-            hip_check(hipEventCreate(&e), "hipEventCreate");
-            return e;
-        }
-        hipEvent_t e = pool.back();
-        pool.pop_back();
-        return e;
-    }
-    void clear()
-    {
-        for (auto& r : recs) {
-            pool.push_back(r.a);
-            pool.push_back(r.b);
-        }
-        recs.clear();
-    }
-    ~Profiler()
-    {
-        clear();
-        for (auto e : pool) (void)hipEventDestroy(e);
-    }
-};
-
-thread_local Profiler* g_prof = nullptr;   // profiler of the context this thread is calling into
-
-}  // namespace
-
-struct nis_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    std::map<int32_t, Medium*> media;
-    int32_t next_id = 1;
-    Net* net = nullptr;
-    int precision = kPrecFP32;
-    DevBuf desc, f0, rowmax, io;
-    Profiler prof;
-};
-
-namespace {
-
-Medium* get_medium(nis_ctx* ctx, int32_t id)
-{
-    auto it = ctx->media.find(id);
-    if (it == ctx->media.end()) fail(NIS_E_STATE, "unknown medium handle");
-    return it->second;
-}
 
 void check_ctx(nis_ctx* ctx)
 {
     if (!ctx) fail(NIS_E_INVALID, "context is NULL");
     g_prof = &ctx->prof;
     hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+}
+
+void no_server(nis_ctx* ctx, const char* what)
+{
+    if (ctx->server) fail(NIS_E_STATE, std::string(what) + " is not allowed while the frame server runs");
 }
 
 bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
@@ -199,78 +109,36 @@ void ray_range(double s, int nm, int* lo, int* hi)
     *hi = (int)std::ceil((double)(nm - 1) + (a > 0.0 ? a : 0.0)) + 1;
 }
 
-double hg(double g, double mu)
-{
-    double den = 1.0 + g * g - 2.0 * g * mu;
-    return (1.0 - g * g) / (4.0 * M_PI * den * std::sqrt(den));
-}
-
-// Light frame, ray ranges and site tables (host, double precision).
-void setup_light(Medium* M)
-{
-    const double* l = M->l;
-    int a = 0;
-    for (int i = 1; i < 3; i++)
-        if (std::fabs(l[i]) > std::fabs(l[a])) a = i;
-    M->a = a;
-    M->b = a == 0 ? 1 : 0;
-    M->c = a == 2 ? 1 : 2;
-    M->sigma = l[a] > 0.0 ? 1 : -1;
-    M->la = std::fabs(l[a]);
-    M->sb = l[M->b] / M->la;
-    M->sc = l[M->c] / M->la;
-    for (int d = 0; d < 3; d++)
-        for (int qi = 0; qi < 9; qi++) M->qoff[d][qi] = (qi - 4) * l[d] / M->la;
-    int64_t off = 0;
-    for (int m = 0; m < M->levels; m++) {
-        Level& lv = M->lev[m];
-        int uhi, vhi;
-        ray_range(M->sb, lv.n, &lv.ulo, &uhi);
-        ray_range(M->sc, lv.n, &lv.vlo, &vhi);
-        lv.nu = uhi - lv.ulo + 1;
-        lv.nv = vhi - lv.vlo + 1;
-        lv.d_off = off;
-        lv.ds = (float)((1.0 / lv.n) / M->la);
-        if ((int64_t)lv.nu * lv.nv * lv.n >= ((int64_t)1 << 31))
-            fail(NIS_E_UNSUPPORTED, "path-density field of one level exceeds 2^31 entries for this light");
-        off += (int64_t)lv.nu * lv.nv * lv.n;
-    }
-    M->D.reserve((size_t)off * sizeof(float), "path-density fields");
-    M->tab_stale = true;
-    M->stale = true;
-}
-
-MediumView make_view(const Medium* M, const Net* net)
+MediumView make_view(const Medium* M, const LightState* ls, const Params& P, const Net* net)
 {
     MediumView v;
     std::memset(&v, 0, sizeof(v));
     v.rho = M->rho.as<float>();
-    v.D = M->D.as<float>();
-    for (int m = 0; m < M->levels; m++) v.lev[m] = M->lev[m];
+    v.D = ls->D.as<float>();
+    for (int m = 0; m < M->levels; m++) v.lev[m] = ls->lev[m];
     v.levels = M->levels;
     v.n0 = M->n;
-    v.a = M->a;
-    v.b = M->b;
-    v.c = M->c;
-    v.sigma = M->sigma;
-    v.sb = M->sb;
-    v.sc = M->sc;
-    for (int d = 0; d < 3; d++) v.l[d] = M->l[d];
-    v.la = M->la;
-    std::memcpy(v.qoff, M->qoff, sizeof(v.qoff));
-    v.sigma_t = M->sigma_t;
-    v.albedo = M->albedo;
-    v.g = M->g;
-    v.radiance = M->radiance;
+    v.a = ls->a;
+    v.b = ls->b;
+    v.c = ls->c;
+    v.sigma = ls->sigma;
+    v.sb = ls->sb;
+    v.sc = ls->sc;
+    for (int d = 0; d < 3; d++) v.l[d] = ls->l[d];
+    v.la = ls->la;
+    std::memcpy(v.qoff, ls->qoff, sizeof(v.qoff));
+    v.sigma_t = P.sigma_t;
+    v.albedo = P.albedo;
+    v.g = P.g;
+    v.radiance = P.radiance;
     v.lam = net ? net->lam : 0.6f;
     v.gamma = net ? net->gamma : 4.f;
-    double g = M->g;
+    double g = P.g;
     v.hg_a = 1.0 + g * g;
     v.hg_b = 2.0 * g;
     v.hg_k = (1.0 - g * g) / (4.0 * M_PI);
     return v;
 }
-
 
 template <class F> void timed(const char* name, hipStream_t s, F&& launch)
 {
@@ -285,22 +153,26 @@ template <class F> void timed(const char* name, hipStream_t s, F&& launch)
     g_prof->recs.push_back({name, a, b});
 }
 
-void refresh_tables(Medium* M, hipStream_t s)
+void refresh_tables(const Medium* M, LightState* ls, float g, hipStream_t s)
 {
-    if (!M->tab_stale) return;
-    M->tab.reserve(sizeof(SiteTables), "site tables");
-    MediumView mv = make_view(M, nullptr);
-    timed("site_tables", s, [&] { return launch_site_tables(mv, M->tab.as<SiteTables>(), s); });
-    M->tab_stale = false;
+    if (ls->tab_valid && ls->tab_g == g) return;
+    ls->tab.reserve(sizeof(SiteTables), "site tables");
+    Params P = medium_params(M);
+    P.g = g;
+    MediumView mv = make_view(M, ls, P, nullptr);
+    timed("site_tables", s, [&] { return launch_site_tables(mv, ls->tab.as<SiteTables>(), s); });
+    ls->tab_valid = true;
+    ls->tab_g = g;
 }
 
-void ensure_sweep(Medium* M, hipStream_t s)
+void ensure_sweep(const Medium* M, LightState* ls, hipStream_t s)
 {
-    if (!M->has_light) fail(NIS_E_STATE, "no light set for this medium");
-    if (!M->stale) return;
-    MediumView mv = make_view(M, nullptr);
+    if (!ls->valid) fail(NIS_E_STATE, "no light set for this medium");
+    if (!ls->stale && ls->swept_version == M->version) return;
+    MediumView mv = make_view(M, ls, medium_params(M), nullptr);
     timed("sweep", s, [&] { return launch_sweep(mv, s); });
-    M->stale = false;
+    ls->stale = false;
+    ls->swept_version = M->version;
 }
 
 // ---- weights --------------------------------------------------------------
@@ -447,61 +319,134 @@ void free_net(Net* net)
     delete net;
 }
 
-// ---- query ----------------------------------------------------------------
-
-constexpr int64_t kChunk = 1 << 21;   // points per feature/backbone pass
+void free_medium(Medium* M)
+{
+    M->rho.release();
+    M->light.release();
+    delete M;
+}
 
 // the FP8 path stores the descriptor in BF16 and quantises it in the backbone
 size_t desc_elem_bytes(int prec) { return prec == kPrecFP32 ? 4 : 2; }
 
-struct QueryOut {
-    float* radiance = nullptr;
-    float* y = nullptr;
-    float* tbar = nullptr;
-    float* rho = nullptr;
-    float* phi = nullptr;
-    float* stats = nullptr;
-    float* tp = nullptr;
-    float* f0 = nullptr;
-    void* desc = nullptr;     // raw descriptor copy (precision's element type), [n][kDescPad]
-    bool run_mlp = true;
-};
+// bytes of one FrameWork buffer set for npix pixels, scan storage excluded
+size_t frame_fixed_bytes(int64_t npix) { return (size_t)npix * (4 + 4 + 12 + 12 + 12 + 12 + 4 + 4) + 256; }
 
-void run_query(nis_ctx* ctx, Medium* M, const float* d_pts, const float* d_dirs, int64_t n,
-               const QueryOut& o, hipStream_t s)
+}  // namespace
+
+StreamUse::StreamUse(nis_ctx* c, hipStream_t stream) : ctx(c), s(stream)
 {
-    Net* net = ctx->net;
+    if (ctx->ordered && ctx->order_stream != s)
+        hip_check(hipStreamWaitEvent(s, ctx->order, 0), "hipStreamWaitEvent");
+}
+
+StreamUse::~StreamUse()
+{
+    if (hipEventRecord(ctx->order, s) == hipSuccess) {
+        ctx->order_stream = s;
+        ctx->ordered = true;
+    }
+}
+
+// ---- media and lights --------------------------------------------------------
+
+Medium* get_medium(nis_ctx* ctx, int32_t id)
+{
+    auto it = ctx->media.find(id);
+    if (it == ctx->media.end()) fail(NIS_E_STATE, "unknown medium handle");
+    return it->second;
+}
+
+Params medium_params(const Medium* M) { return Params{M->sigma_t, M->albedo, M->g, M->radiance}; }
+
+void light_layout(const Medium* M, const double l[3], LightState* ls)
+{
+    for (int d = 0; d < 3; d++) ls->l[d] = l[d];
+    int a = 0;
+    for (int i = 1; i < 3; i++)
+        if (std::fabs(l[i]) > std::fabs(l[a])) a = i;
+    ls->a = a;
+    ls->b = a == 0 ? 1 : 0;
+    ls->c = a == 2 ? 1 : 2;
+    ls->sigma = l[a] > 0.0 ? 1 : -1;
+    ls->la = std::fabs(l[a]);
+    ls->sb = l[ls->b] / ls->la;
+    ls->sc = l[ls->c] / ls->la;
+    for (int d = 0; d < 3; d++)
+        for (int qi = 0; qi < 9; qi++) ls->qoff[d][qi] = (qi - 4) * l[d] / ls->la;
+    int64_t off = 0;
+    for (int m = 0; m < M->levels; m++) {
+        Level& lv = ls->lev[m];
+        lv = M->lev[m];
+        int uhi, vhi;
+        ray_range(ls->sb, lv.n, &lv.ulo, &uhi);
+        ray_range(ls->sc, lv.n, &lv.vlo, &vhi);
+        lv.nu = uhi - lv.ulo + 1;
+        lv.nv = vhi - lv.vlo + 1;
+        lv.d_off = off;
+        lv.ds = (float)((1.0 / lv.n) / ls->la);
+        if ((int64_t)lv.nu * lv.nv * lv.n >= ((int64_t)1 << 31))
+            fail(NIS_E_UNSUPPORTED, "path-density field of one level exceeds 2^31 entries for this light");
+        off += (int64_t)lv.nu * lv.nv * lv.n;
+    }
+    ls->d_floats = off;
+}
+
+void set_light_state(const Medium* M, const double l[3], LightState* ls)
+{
+    light_layout(M, l, ls);
+    ls->D.reserve((size_t)ls->d_floats * sizeof(float), "path-density fields");
+    ls->valid = true;
+    ls->stale = true;
+    ls->tab_valid = false;
+}
+
+const char* precision_name(int prec) { return prec == kPrecFP32 ? "fp32" : prec == kPrecBF16 ? "bf16" : "fp8"; }
+
+// ---- query ----------------------------------------------------------------
+
+size_t workspace_bytes(int prec, int64_t npts)
+{
+    const int64_t chunk = npts < kChunk ? npts : kChunk;
+    return (size_t)chunk * kDescPad * desc_elem_bytes(prec) + (size_t)chunk * 4 * (prec == kPrecFP8 ? 2 : 1);
+}
+
+void run_query(Workspace& ws, const Net* net, int prec, const Medium* M, LightState* ls, const Params& Pm,
+               const float* d_pts, const float* d_dirs, int64_t n, const int* d_count, const QueryOut& o,
+               hipStream_t s)
+{
     if (!net) fail(NIS_E_STATE, "no weights set");
-    ensure_sweep(M, s);
-    refresh_tables(M, s);
-    const int prec = ctx->precision;
+    ensure_sweep(M, ls, s);
+    refresh_tables(M, ls, Pm.g, s);
     const PackedNet& P = net->packed[prec];
     const int64_t chunk = n < kChunk ? n : kChunk;
-    ctx->desc.reserve((size_t)chunk * kDescPad * desc_elem_bytes(prec), "descriptor workspace");
-    ctx->f0.reserve((size_t)chunk * sizeof(float), "single-scatter workspace");
-    if (prec == kPrecFP8) ctx->rowmax.reserve((size_t)chunk * sizeof(float), "descriptor row maxima");
-    MediumView mv = make_view(M, net);
+    ws.desc.reserve((size_t)chunk * kDescPad * desc_elem_bytes(prec), "descriptor workspace");
+    ws.f0.reserve((size_t)chunk * sizeof(float), "single-scatter workspace");
+    if (prec == kPrecFP8) ws.rowmax.reserve((size_t)chunk * sizeof(float), "descriptor row maxima");
+    MediumView mv = make_view(M, ls, Pm, net);
     for (int64_t p0 = 0; p0 < n; p0 += chunk) {
         const int64_t cn = (n - p0) < chunk ? (n - p0) : chunk;
         FeatArgs fa;
         std::memset(&fa, 0, sizeof(fa));
         fa.mv = mv;
-        fa.tab = M->tab.as<SiteTables>();
+        fa.tab = ls->tab.as<SiteTables>();
         fa.pts = d_pts + 3 * p0;
         fa.dirs = d_dirs + 3 * p0;
         fa.npts = cn;
+        fa.count = d_count;
+        fa.count_off = p0;
         for (int k = 0; k < kLayers; k++) {
             int m = k < M->levels - 1 ? k : M->levels - 1;
-            fa.coef[k] = (float)(std::pow((double)net->lam, m + 1) * (double)M->sigma_t);
+            fa.coef[k] = (float)(std::pow((double)net->lam, m + 1) * (double)Pm.sigma_t);
         }
         for (int gi = 0; gi < 2; gi++) {
             fa.w1t[gi] = P.w1t[gi].p;
             fa.w2t[gi] = P.w2t[gi].p;
             fa.cb[gi] = P.cb[gi].as<float>();
         }
-        fa.desc = ctx->desc.p;
-        fa.f0 = o.f0 ? o.f0 + p0 : ctx->f0.as<float>();
-        fa.rowmax = prec == kPrecFP8 ? ctx->rowmax.as<float>() : nullptr;
+        fa.desc = ws.desc.p;
+        fa.f0 = o.f0 ? o.f0 + p0 : ws.f0.as<float>();
+        fa.rowmax = prec == kPrecFP8 ? ws.rowmax.as<float>() : nullptr;
         auto off = [&](float* base, int64_t per) { return base ? base + p0 * per : nullptr; };
         fa.dbg_tbar = off(o.tbar, kLayers * kSites);
         fa.dbg_rho = off(o.rho, kLayers * kSites);
@@ -511,14 +456,16 @@ void run_query(nis_ctx* ctx, Medium* M, const float* d_pts, const float* d_dirs,
         timed("features", s, [&] { return launch_features(prec, fa, s); });
         if (o.desc) {
             size_t eb = desc_elem_bytes(prec) * kDescPad;
-            hip_check(hipMemcpyAsync((char*)o.desc + p0 * eb, ctx->desc.p, cn * eb,
-                                     hipMemcpyDeviceToDevice, s), "descriptor copy");
+            hip_check(hipMemcpyAsync((char*)o.desc + p0 * eb, ws.desc.p, cn * eb, hipMemcpyDeviceToDevice, s),
+                      "descriptor copy");
         }
         if (!o.run_mlp) continue;
         MlpArgs ma;
         std::memset(&ma, 0, sizeof(ma));
-        ma.x = ctx->desc.p;
+        ma.x = ws.desc.p;
         ma.npts = cn;
+        ma.count = d_count;
+        ma.count_off = p0;
         for (int li = 0; li + 1 < net->n_linear; li++) {
             ma.W[li] = P.W[li].p;
             ma.bias[li] = P.bias[li].as<float>();
@@ -532,13 +479,141 @@ void run_query(nis_ctx* ctx, Medium* M, const float* d_pts, const float* d_dirs,
         ma.f0 = fa.f0;
         ma.out = o.radiance ? o.radiance + p0 : nullptr;
         ma.y_out = o.y ? o.y + p0 : nullptr;
-        ma.albedo_gamma = (float)std::pow((double)M->albedo, (double)net->gamma);
-        ma.radiance = M->radiance;
+        ma.albedo_gamma = (float)std::pow((double)Pm.albedo, (double)net->gamma);
+        ma.radiance = Pm.radiance;
         timed("backbone", s, [&] { return launch_mlp(prec, ma, s); });
     }
 }
 
-}  // namespace
+// ---- frames -----------------------------------------------------------------
+
+size_t frame_work_bytes(int64_t npix)
+{
+    size_t scan = 0;
+    hip_check(frame_scan_bytes(npix, &scan), "scan storage size");
+    return frame_fixed_bytes(npix) + scan;
+}
+
+void FrameWork::reserve(int64_t n)
+{
+    if (n <= npix) return;
+    const size_t N = (size_t)n;
+    flag.reserve(N * 4, "frame flags");
+    offset.reserve(N * 4, "frame offsets");
+    pts.reserve(N * 12, "frame points");
+    dirs.reserve(N * 12, "frame directions");
+    cpts.reserve(N * 12, "frame points");
+    cdirs.reserve(N * 12, "frame directions");
+    cpix.reserve(N * 4, "frame pixels");
+    L.reserve(N * 4, "frame radiance");
+    count.reserve(256, "frame count");
+    size_t sb = 0;
+    hip_check(frame_scan_bytes(n, &sb), "scan storage size");
+    scan.reserve(sb ? sb : 1, "scan storage");
+    npix = n;
+}
+
+FrameBuffers FrameWork::view() const
+{
+    FrameBuffers fb;
+    fb.flag = flag.as<int>();
+    fb.offset = offset.as<int>();
+    fb.pts = pts.as<float>();
+    fb.dirs = dirs.as<float>();
+    fb.cpts = cpts.as<float>();
+    fb.cdirs = cdirs.as<float>();
+    fb.cpix = cpix.as<int>();
+    fb.count = count.as<int>();
+    fb.scan_tmp = scan.p;
+    fb.scan_bytes = scan.bytes;
+    return fb;
+}
+
+size_t FrameWork::bytes() const
+{
+    return flag.bytes + offset.bytes + pts.bytes + dirs.bytes + cpts.bytes + cdirs.bytes + cpix.bytes + L.bytes +
+           count.bytes + scan.bytes;
+}
+
+void FrameWork::release()
+{
+    for (DevBuf* b : {&flag, &offset, &pts, &dirs, &cpts, &cdirs, &cpix, &count, &scan, &L}) b->release();
+    npix = 0;
+}
+
+CamArgs camera_args(const nis_camera* cam)
+{
+    if (!cam) fail(NIS_E_INVALID, "camera is NULL");
+    if (cam->width < 1 || cam->height < 1 || (int64_t)cam->width * cam->height > ((int64_t)1 << 28))
+        fail(NIS_E_INVALID, "image size must be positive with at most 2^28 pixels");
+    CamArgs C;
+    std::memset(&C, 0, sizeof(C));
+    C.width = cam->width;
+    C.height = cam->height;
+    if (cam->vfov_deg == 0.0) {
+        if (!std::isfinite(cam->ortho_z)) fail(NIS_E_INVALID, "ortho_z must be finite");
+        C.ortho = 1;
+        C.oz = cam->ortho_z;
+        return C;
+    }
+    if (!(cam->vfov_deg > 0.0 && cam->vfov_deg < 180.0)) fail(NIS_E_INVALID, "vfov_deg must be 0 or in (0,180)");
+    double f[3], up[3];
+    for (int d = 0; d < 3; d++) {
+        if (!std::isfinite(cam->eye[d]) || !std::isfinite(cam->target[d]) || !std::isfinite(cam->up[d]))
+            fail(NIS_E_INVALID, "camera vectors must be finite");
+        C.eye[d] = cam->eye[d];
+        f[d] = cam->target[d] - cam->eye[d];
+        up[d] = cam->up[d];
+    }
+    const double fn = std::sqrt((f[0] * f[0] + f[1] * f[1]) + f[2] * f[2]);
+    if (!(fn > 0.0)) fail(NIS_E_INVALID, "eye and target coincide");
+    for (int d = 0; d < 3; d++) C.f[d] = f[d] / fn;
+    double r[3] = {C.f[1] * up[2] - C.f[2] * up[1], C.f[2] * up[0] - C.f[0] * up[2], C.f[0] * up[1] - C.f[1] * up[0]};
+    const double rn = std::sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+    if (!(rn > 0.0)) fail(NIS_E_INVALID, "up is parallel to the view direction");
+    for (int d = 0; d < 3; d++) C.r[d] = r[d] / rn;
+    C.u[0] = C.r[1] * C.f[2] - C.r[2] * C.f[1];
+    C.u[1] = C.r[2] * C.f[0] - C.r[0] * C.f[2];
+    C.u[2] = C.r[0] * C.f[1] - C.r[1] * C.f[0];
+    C.aspect = (double)cam->width / (double)cam->height;
+    C.tan_half = std::tan(cam->vfov_deg * (M_PI / 180.0) * 0.5);
+    return C;
+}
+
+void frame_points(FrameWork& fw, const Medium* M, const Params& P, const CamArgs& C, uint64_t seed, float* d_pts,
+                  float* d_dirs, int* d_pix, int* d_count, hipStream_t s)
+{
+    const int64_t npix = (int64_t)C.width * C.height;
+    fw.reserve(npix);
+    FrameBuffers fb = fw.view();
+    if (d_pts) {
+        fb.cpts = d_pts;
+        fb.cdirs = d_dirs;
+        fb.cpix = d_pix;
+        fb.count = d_count;
+    }
+    const double sigma_t = P.sigma_t, majorant = sigma_t * (double)M->rmax;
+    timed("raygen", s,
+          [&] { return launch_raygen(C, M->rho.as<float>(), M->n, sigma_t, majorant, seed, fb, s); });
+}
+
+void render_frame(Workspace& ws, FrameWork& fw, const Net* net, int prec, const Medium* M, LightState* ls,
+                  const Params& P, const CamArgs& C, uint64_t seed, float* d_image, hipStream_t s)
+{
+    if (!net) fail(NIS_E_STATE, "no weights set");
+    if (!ls->valid) fail(NIS_E_STATE, "no light set for this medium");
+    const int64_t npix = (int64_t)C.width * C.height;
+    frame_points(fw, M, P, C, seed, nullptr, nullptr, nullptr, nullptr, s);
+    FrameBuffers fb = fw.view();
+    QueryOut o;
+    o.radiance = fw.L.as<float>();
+    run_query(ws, net, prec, M, ls, P, fb.cpts, fb.cdirs, npix, fb.count, o, s);
+    timed("image", s, [&] { return launch_image(fb, npix, fw.L.as<float>(), P.albedo, d_image, s); });
+}
+
+}  // namespace nis
+
+using namespace nis;
 
 // ---- C ABI ------------------------------------------------------------------
 
@@ -558,7 +633,9 @@ int32_t nis_create(int32_t hip_device, nis_ctx** out)
         nis_ctx* ctx = new nis_ctx();
         ctx->device = hip_device;
         hipError_t e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->order, hipEventDisableTiming);
         if (e != hipSuccess) {
+            if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
             delete ctx;
             hip_check(e, "hipStreamCreate");
         }
@@ -571,40 +648,41 @@ int32_t nis_destroy(nis_ctx* ctx)
     if (!ctx) return NIS_OK;
     return guard([&] {
         (void)hipSetDevice(ctx->device);
-        (void)hipStreamSynchronize(ctx->stream);
-        for (auto& kv : ctx->media) {
-            kv.second->rho.release();
-            kv.second->D.release();
-            kv.second->tab.release();
-            delete kv.second;
-        }
+        server_shutdown(ctx);
+        (void)hipDeviceSynchronize();
+        for (auto& kv : ctx->media) free_medium(kv.second);
         free_net(ctx->net);
-        ctx->desc.release();
-        ctx->f0.release();
-        ctx->rowmax.release();
+        ctx->ws.release();
+        ctx->fw.release();
         ctx->io.release();
+        (void)hipEventDestroy(ctx->order);
         (void)hipStreamDestroy(ctx->stream);
         delete ctx;
     });
 }
 
-int32_t nis_load_medium(nis_ctx* ctx, const float* density, int32_t n, float sigma_t, float albedo,
-                        float g, int32_t* medium_out)
+int32_t nis_load_medium(nis_ctx* ctx, const float* density, int32_t n, float sigma_t, float albedo, float g,
+                        int32_t* medium_out)
 {
     return guard([&] {
         check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
         if (!density || !medium_out) fail(NIS_E_INVALID, "density or medium_out is NULL");
         if (n < 1 || n > 1024 || (n & (n - 1)) != 0) fail(NIS_E_INVALID, "n must be a power of two in [1,1024]");
         validate_params(sigma_t, albedo, g);
         const int64_t n3 = (int64_t)n * n * n;
-        for (int64_t i = 0; i < n3; i++)
+        float rmax = 0.f;
+        for (int64_t i = 0; i < n3; i++) {
             if (!(std::isfinite(density[i]) && density[i] >= 0.f)) fail(NIS_E_INVALID, "density must be finite and >= 0");
+            rmax = density[i] > rmax ? density[i] : rmax;
+        }
         Medium* M = new Medium();
         try {
             M->n = n;
             M->sigma_t = sigma_t;
             M->albedo = albedo;
             M->g = g;
+            M->rmax = rmax;
             int L = 1;
             while ((1 << (L - 1)) < n) L++;
             M->levels = L;
@@ -622,8 +700,7 @@ int32_t nis_load_medium(nis_ctx* ctx, const float* density, int32_t n, float sig
             hip_check(launch_pyramid(M->rho.as<float>(), M->lev, L, ctx->stream), "pyramid launch");
             hip_check(hipStreamSynchronize(ctx->stream), "pyramid");
         } catch (...) {
-            M->rho.release();
-            delete M;
+            free_medium(M);
             throw;
         }
         int32_t id = ctx->next_id++;
@@ -636,10 +713,13 @@ int32_t nis_rebuild_pyramid(nis_ctx* ctx, int32_t medium, void* hip_stream)
 {
     return guard([&] {
         check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        no_server(ctx, "rebuilding a pyramid");
         Medium* M = get_medium(ctx, medium);
-        hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+        StreamUse su(ctx, (hipStream_t)hip_stream);
+        hipStream_t s = su.s;
         timed("pyramid", s, [&] { return launch_pyramid(M->rho.as<float>(), M->lev, M->levels, s); });
-        M->stale = true;
+        M->version++;
     });
 }
 
@@ -647,9 +727,9 @@ int32_t nis_set_medium_params(nis_ctx* ctx, int32_t medium, float sigma_t, float
 {
     return guard([&] {
         check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
         Medium* M = get_medium(ctx, medium);
         validate_params(sigma_t, albedo, g);
-        if (g != M->g) M->tab_stale = true;
         M->sigma_t = sigma_t;
         M->albedo = albedo;
         M->g = g;
@@ -660,13 +740,12 @@ int32_t nis_unload_medium(nis_ctx* ctx, int32_t medium)
 {
     return guard([&] {
         check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        no_server(ctx, "unloading a medium");
         Medium* M = get_medium(ctx, medium);
-        hip_check(hipStreamSynchronize(ctx->stream), "unload");
-        M->rho.release();
-        M->D.release();
-        M->tab.release();
+        hip_check(hipDeviceSynchronize(), "unload");   // work on any stream may still read it
         ctx->media.erase(medium);
-        delete M;
+        free_medium(M);
     });
 }
 
@@ -674,16 +753,19 @@ int32_t nis_set_light(nis_ctx* ctx, int32_t medium, const float dir[3], float ra
 {
     return guard([&] {
         check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
         Medium* M = get_medium(ctx, medium);
         if (!dir || !finite3(dir) || !std::isfinite(radiance)) fail(NIS_E_INVALID, "light must be finite");
         double l[3] = {dir[0], dir[1], dir[2]};
         double nrm = std::sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]);
         if (!(nrm > 0.0)) fail(NIS_E_INVALID, "light direction is zero");
-        for (int d = 0; d < 3; d++) M->l[d] = l[d] / nrm;
+        for (int d = 0; d < 3; d++) l[d] /= nrm;
+        set_light_state(M, l, &M->light);
         M->radiance = radiance;
-        M->has_light = true;
-        setup_light(M);
-        if (flags & NIS_EAGER) ensure_sweep(M, ctx->stream);
+        if (flags & NIS_EAGER) {
+            StreamUse su(ctx, ctx->stream);
+            ensure_sweep(M, &M->light, su.s);
+        }
     });
 }
 
@@ -691,6 +773,8 @@ int32_t nis_set_weights(nis_ctx* ctx, const void* blob, size_t nbytes)
 {
     return guard([&] {
         check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        no_server(ctx, "replacing the weights");
         if (!blob || nbytes < sizeof(BlobHeader)) fail(NIS_E_INVALID, "weight blob too short");
         BlobHeader h;
         std::memcpy(&h, blob, sizeof(h));
@@ -741,7 +825,7 @@ int32_t nis_set_weights(nis_ctx* ctx, const void* blob, size_t nbytes)
             free_net(net);
             throw;
         }
-        hip_check(hipStreamSynchronize(ctx->stream), "weights");
+        hip_check(hipDeviceSynchronize(), "weights");   // queries on any stream may read the old ones
         free_net(ctx->net);
         ctx->net = net;
     });
@@ -751,6 +835,7 @@ int32_t nis_set_precision(nis_ctx* ctx, int32_t precision)
 {
     return guard([&] {
         check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
         if (precision != NIS_FP32 && precision != NIS_BF16 && precision != NIS_FP8)
             fail(NIS_E_INVALID, "unknown precision");
         ctx->precision = precision;
@@ -762,12 +847,15 @@ int32_t nis_query_device(nis_ctx* ctx, int32_t medium, const float* d_points, co
 {
     return guard([&] {
         check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
         if (!d_points || !d_dirs || !d_out || n <= 0) fail(NIS_E_INVALID, "bad query arguments");
         Medium* M = get_medium(ctx, medium);
-        hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+        StreamUse su(ctx, (hipStream_t)hip_stream);
+        hipStream_t s = su.s;
         QueryOut o;
         o.radiance = d_out;
-        run_query(ctx, M, d_points, d_dirs, n, o, s);
+        run_query(ctx->ws, ctx->net, ctx->precision, M, &M->light, medium_params(M), d_points, d_dirs, n, nullptr,
+                  o, s);
     });
 }
 
@@ -776,6 +864,7 @@ int32_t nis_query(nis_ctx* ctx, int32_t medium, const float* points, const float
 {
     return guard([&] {
         check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
         if (!points || !dirs || !radiance_out || n <= 0) fail(NIS_E_INVALID, "bad query arguments");
         for (int64_t i = 0; i < n; i++) {
             if (!finite3(points + 3 * i) || !finite3(dirs + 3 * i)) fail(NIS_E_INVALID, "non-finite query input");
@@ -784,19 +873,55 @@ int32_t nis_query(nis_ctx* ctx, int32_t medium, const float* points, const float
         }
         Medium* M = get_medium(ctx, medium);
         if (!ctx->net) fail(NIS_E_STATE, "no weights set");
-        if (!M->has_light) fail(NIS_E_STATE, "no light set for this medium");
+        if (!M->light.valid) fail(NIS_E_STATE, "no light set for this medium");
         const size_t bytes = (size_t)n * 7 * sizeof(float);
+        StreamUse su(ctx, ctx->stream);
         ctx->io.reserve(bytes, "query staging");
         float* d_pts = ctx->io.as<float>();
         float* d_dirs = d_pts + 3 * n;
         float* d_out = d_dirs + 3 * n;
-        hip_check(hipMemcpyAsync(d_pts, points, (size_t)n * 3 * sizeof(float), hipMemcpyHostToDevice, ctx->stream), "upload");
-        hip_check(hipMemcpyAsync(d_dirs, dirs, (size_t)n * 3 * sizeof(float), hipMemcpyHostToDevice, ctx->stream), "upload");
+        hip_check(hipMemcpyAsync(d_pts, points, (size_t)n * 3 * sizeof(float), hipMemcpyHostToDevice, ctx->stream),
+                  "upload");
+        hip_check(hipMemcpyAsync(d_dirs, dirs, (size_t)n * 3 * sizeof(float), hipMemcpyHostToDevice, ctx->stream),
+                  "upload");
         QueryOut o;
         o.radiance = d_out;
-        run_query(ctx, M, d_pts, d_dirs, n, o, ctx->stream);
-        hip_check(hipMemcpyAsync(radiance_out, d_out, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, ctx->stream), "download");
+        run_query(ctx->ws, ctx->net, ctx->precision, M, &M->light, medium_params(M), d_pts, d_dirs, n, nullptr, o,
+                  ctx->stream);
+        hip_check(hipMemcpyAsync(radiance_out, d_out, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, ctx->stream),
+                  "download");
         hip_check(hipStreamSynchronize(ctx->stream), "query");
+    });
+}
+
+int32_t nis_frame_points(nis_ctx* ctx, int32_t medium, const nis_camera* camera, uint64_t seed, float* d_points,
+                         float* d_dirs, int32_t* d_pixel, int32_t* d_count, void* hip_stream)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (!d_points || !d_dirs || !d_pixel || !d_count) fail(NIS_E_INVALID, "output arrays must not be NULL");
+        Medium* M = get_medium(ctx, medium);
+        CamArgs C = camera_args(camera);
+        StreamUse su(ctx, (hipStream_t)hip_stream);
+        hipStream_t s = su.s;
+        frame_points(ctx->fw, M, medium_params(M), C, seed, d_points, d_dirs, d_pixel, d_count, s);
+    });
+}
+
+int32_t nis_render(nis_ctx* ctx, int32_t medium, const nis_camera* camera, uint64_t seed, float* d_image,
+                   void* hip_stream)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (!d_image) fail(NIS_E_INVALID, "image is NULL");
+        Medium* M = get_medium(ctx, medium);
+        CamArgs C = camera_args(camera);
+        StreamUse su(ctx, (hipStream_t)hip_stream);
+        hipStream_t s = su.s;
+        render_frame(ctx->ws, ctx->fw, ctx->net, ctx->precision, M, &M->light, medium_params(M), C, seed, d_image,
+                     s);
     });
 }
 
@@ -804,6 +929,7 @@ int32_t nis_profile(nis_ctx* ctx, int32_t enable)
 {
     return guard([&] {
         check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
         hip_check(hipDeviceSynchronize(), "sync");
         ctx->prof.clear();
         ctx->prof.on = enable != 0;
@@ -814,6 +940,7 @@ int32_t nis_profile_report(nis_ctx* ctx, char* buf, size_t capacity)
 {
     return guard([&] {
         check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
         if (!buf || capacity == 0) fail(NIS_E_INVALID, "buffer is NULL");
         std::map<std::string, std::pair<int64_t, double>> agg;
         for (auto& r : ctx->prof.recs) {
@@ -840,6 +967,7 @@ int32_t nis_medium_info(nis_ctx* ctx, int32_t medium, int32_t* levels, int64_t* 
 {
     return guard([&] {
         check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
         Medium* M = get_medium(ctx, medium);
         if (levels) *levels = M->levels;
         if (pyramid_floats) *pyramid_floats = M->rho_floats;
@@ -850,9 +978,10 @@ int32_t nis_debug_pyramid(nis_ctx* ctx, int32_t medium, float* out, int64_t capa
 {
     return guard([&] {
         check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
         Medium* M = get_medium(ctx, medium);
         if (!out || capacity < M->rho_floats) fail(NIS_E_INVALID, "output too small");
-        hip_check(hipStreamSynchronize(ctx->stream), "sync");
+        hip_check(hipDeviceSynchronize(), "sync");
         hip_check(hipMemcpy(out, M->rho.p, (size_t)M->rho_floats * sizeof(float), hipMemcpyDeviceToHost), "download");
     });
 }
@@ -862,11 +991,13 @@ int32_t nis_debug_path_density(nis_ctx* ctx, int32_t medium, int32_t level, floa
 {
     return guard([&] {
         check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
         Medium* M = get_medium(ctx, medium);
         if (!dims) fail(NIS_E_INVALID, "dims is NULL");
         if (level < 0 || level >= M->levels) fail(NIS_E_INVALID, "no such level");
-        ensure_sweep(M, ctx->stream);
-        const Level& lv = M->lev[level];
+        hip_check(hipDeviceSynchronize(), "sync");   // the debug calls see all earlier work
+        ensure_sweep(M, &M->light, ctx->stream);
+        const Level& lv = M->light.lev[level];
         dims[0] = lv.ulo;
         dims[1] = lv.ulo + lv.nu - 1;
         dims[2] = lv.vlo;
@@ -876,7 +1007,8 @@ int32_t nis_debug_path_density(nis_ctx* ctx, int32_t medium, int32_t level, floa
         int64_t count = (int64_t)lv.nu * lv.nv * lv.n;
         if (capacity < count) fail(NIS_E_INVALID, "output too small");
         hip_check(hipStreamSynchronize(ctx->stream), "sync");
-        hip_check(hipMemcpy(out, M->D.as<float>() + lv.d_off, (size_t)count * sizeof(float), hipMemcpyDeviceToHost),
+        hip_check(hipMemcpy(out, M->light.D.as<float>() + lv.d_off, (size_t)count * sizeof(float),
+                            hipMemcpyDeviceToHost),
                   "download");
     });
 }
@@ -886,8 +1018,10 @@ int32_t nis_debug_features(nis_ctx* ctx, int32_t medium, const float* d_points, 
 {
     return guard([&] {
         check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
         if (!d_points || !d_dirs || n <= 0) fail(NIS_E_INVALID, "bad arguments");
         Medium* M = get_medium(ctx, medium);
+        hip_check(hipDeviceSynchronize(), "sync");
         QueryOut o;
         o.tbar = d_tbar;
         o.rho = d_rho;
@@ -896,7 +1030,8 @@ int32_t nis_debug_features(nis_ctx* ctx, int32_t medium, const float* d_points, 
         o.tp = d_tp;
         o.f0 = d_f0;
         o.run_mlp = false;
-        run_query(ctx, M, d_points, d_dirs, n, o, ctx->stream);
+        run_query(ctx->ws, ctx->net, ctx->precision, M, &M->light, medium_params(M), d_points, d_dirs, n, nullptr, o,
+                  ctx->stream);
         hip_check(hipStreamSynchronize(ctx->stream), "features");
     });
 }
@@ -906,8 +1041,10 @@ int32_t nis_debug_network(nis_ctx* ctx, int32_t medium, const float* d_points, c
 {
     return guard([&] {
         check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
         if (!d_points || !d_dirs || n <= 0) fail(NIS_E_INVALID, "bad arguments");
         Medium* M = get_medium(ctx, medium);
+        hip_check(hipDeviceSynchronize(), "sync");
         const int prec = ctx->precision;
         DevBuf raw;
         QueryOut o;
@@ -917,7 +1054,8 @@ int32_t nis_debug_network(nis_ctx* ctx, int32_t medium, const float* d_points, c
             o.desc = raw.p;
         }
         try {
-            run_query(ctx, M, d_points, d_dirs, n, o, ctx->stream);
+            run_query(ctx->ws, ctx->net, prec, M, &M->light, medium_params(M), d_points, d_dirs, n, nullptr, o,
+                      ctx->stream);
             if (d_desc) hip_check(launch_desc_to_f32(prec, raw.p, d_desc, n, ctx->stream), "descriptor convert");
             hip_check(hipStreamSynchronize(ctx->stream), "network");
         } catch (...) {

@@ -30,12 +30,40 @@ NIS_E_UNSUPPORTED = -5
 NIS_E_INTERNAL = -6
 NIS_FP32, NIS_BF16, NIS_FP8 = 0, 1, 2
 NIS_EAGER = 1
+NIS_QUEUED, NIS_RUNNING = 1, 2
 LAYERS, SITES, STATS, DESCRIPTOR = 12, 225, 8, 1057
+PRECISIONS = {"fp32": NIS_FP32, "bf16": NIS_BF16, "fp8": NIS_FP8}
 
 _fp = ctypes.POINTER(ctypes.c_float)
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
+
+class nis_camera(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_double * 3), ("target", ctypes.c_double * 3),
+                ("up", ctypes.c_double * 3), ("vfov_deg", ctypes.c_double),
+                ("ortho_z", ctypes.c_double), ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class nis_server_cfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("precision", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32)]
+
+
+class nis_frame_req(ctypes.Structure):
+    _fields_ = [("medium", ctypes.c_int32), ("camera", nis_camera),
+                ("light_dir", ctypes.c_float * 3), ("radiance", ctypes.c_float),
+                ("g", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+class nis_frame_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("n_points", ctypes.c_int64), ("d_image", ctypes.c_void_p),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+_u64 = ctypes.c_uint64
 
 _SIGNATURES = {
     "nis_create": [_i32, ctypes.POINTER(_vp)],
@@ -55,6 +83,15 @@ _SIGNATURES = {
     "nis_debug_path_density": [_vp, _i32, _i32, _vp, _i64, ctypes.POINTER(_i32)],
     "nis_debug_features": [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp],
     "nis_debug_network": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
+    "nis_frame_points": [_vp, _i32, ctypes.POINTER(nis_camera), _u64, _vp, _vp, _vp, _vp, _vp],
+    "nis_render": [_vp, _i32, ctypes.POINTER(nis_camera), _u64, _vp, _vp],
+    "nis_server_start": [_vp, ctypes.POINTER(nis_server_cfg)],
+    "nis_submit_frame": [_vp, ctypes.POINTER(nis_frame_req), ctypes.POINTER(_u64)],
+    "nis_poll": [_vp, _u64, ctypes.POINTER(nis_frame_result)],
+    "nis_wait": [_vp, _u64, ctypes.POINTER(nis_frame_result)],
+    "nis_release": [_vp, _u64],
+    "nis_frame_memory": [_vp, ctypes.POINTER(nis_frame_req), _i32, ctypes.POINTER(_u64)],
+    "nis_server_stop": [_vp],
     "nis_profile": [_vp, _i32],
     "nis_profile_report": [_vp, _vp, ctypes.c_size_t],
 }
@@ -141,6 +178,30 @@ def pack_weights(params, fp8_scales=None):
 # ---------------------------------------------------------------------------
 # convenience wrapper
 
+def camera(width, height, vfov_deg=45.0, eye=(0.5, 0.5, 2.0), target=(0.5, 0.5, 0.5),
+           up=(0.0, 1.0, 0.0), ortho_z=1.0):
+    """An ``nis_camera``; vfov_deg=0 gives the orthographic camera."""
+    c = nis_camera()
+    c.eye[:] = [float(v) for v in eye]
+    c.target[:] = [float(v) for v in target]
+    c.up[:] = [float(v) for v in up]
+    c.vfov_deg = float(vfov_deg)
+    c.ortho_z = float(ortho_z)
+    c.width, c.height = int(width), int(height)
+    return c
+
+
+def _memcpy_d2d(dst, src, nbytes):
+    """Device-to-device copy through the HIP runtime the library links
+    (dlsym on the library's handle also searches its dependencies)."""
+    fn = _lib.hipMemcpy
+    fn.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.c_int]
+    fn.restype = ctypes.c_int
+    rc = fn(_vp(dst), _vp(src), nbytes, 3)     # hipMemcpyDeviceToDevice
+    if rc != 0:
+        raise NisError(NIS_E_DEVICE, "hipMemcpy failed with HIP error %d" % rc)
+
+
 def _ptr(a):
     return ctypes.c_void_p(a.ctypes.data) if isinstance(a, np.ndarray) else ctypes.c_void_p(a)
 
@@ -195,7 +256,7 @@ class Context:
 
     def set_precision(self, precision):
         if isinstance(precision, str):
-            precision = {"fp32": NIS_FP32, "bf16": NIS_BF16, "fp8": NIS_FP8}[precision]
+            precision = PRECISIONS[precision]
         _check(_lib.nis_set_precision(self.h, precision))
 
     def query(self, medium, points, dirs):
@@ -214,6 +275,91 @@ class Context:
             stream = torch.cuda.current_stream(points.device).cuda_stream
         _check(_lib.nis_query_device(self.h, medium, _dptr(points), _dptr(dirs), points.shape[0],
                                      _dptr(out), _vp(stream)))
+
+    def frame_points(self, medium, cam, seed, stream=None):
+        """Collisions of a frame as torch device tensors (points [P,3], dirs [P,3],
+        pixel [P]); synchronises ``stream`` to read P."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        npix = cam.width * cam.height
+        pts = torch.empty(npix, 3, dtype=torch.float32, device=dev)
+        dirs = torch.empty(npix, 3, dtype=torch.float32, device=dev)
+        pix = torch.empty(npix, dtype=torch.int32, device=dev)
+        cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev).cuda_stream
+        _check(_lib.nis_frame_points(self.h, medium, ctypes.byref(cam), seed, _dptr(pts),
+                                     _dptr(dirs), _dptr(pix), _dptr(cnt), _vp(stream)))
+        n = int(cnt.item())
+        return pts[:n], dirs[:n], pix[:n]
+
+    def render(self, medium, cam, seed, out=None, stream=None):
+        """A frame image (torch float32 [height, width]) queued on ``stream``."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        if out is None:
+            out = torch.empty(cam.height, cam.width, dtype=torch.float32, device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev).cuda_stream
+        _check(_lib.nis_render(self.h, medium, ctypes.byref(cam), seed, _dptr(out), _vp(stream)))
+        return out
+
+    # -- frame server --
+
+    def server_start(self, budget_bytes, precision="bf16", max_inflight=4):
+        cfg = nis_server_cfg(int(budget_bytes), PRECISIONS.get(precision, precision), int(max_inflight))
+        _check(_lib.nis_server_start(self.h, ctypes.byref(cfg)))
+
+    @staticmethod
+    def frame_request(medium, cam, light_dir, radiance=1.0, g=0.85, seed=0):
+        req = nis_frame_req()
+        req.medium = medium
+        req.camera = cam
+        req.light_dir[:] = [float(v) for v in light_dir]
+        req.radiance = float(radiance)
+        req.g = float(g)
+        req.seed = int(seed)
+        return req
+
+    def frame_memory(self, medium, cam, light_dir, precision="bf16"):
+        req = self.frame_request(medium, cam, light_dir)
+        b = _u64()
+        _check(_lib.nis_frame_memory(self.h, ctypes.byref(req), PRECISIONS.get(precision, precision),
+                                     ctypes.byref(b)))
+        return b.value
+
+    def submit(self, medium, cam, light_dir, radiance=1.0, g=0.85, seed=0):
+        req = self.frame_request(medium, cam, light_dir, radiance, g, seed)
+        fid = _u64()
+        _check(_lib.nis_submit_frame(self.h, ctypes.byref(req), ctypes.byref(fid)))
+        return fid.value
+
+    def poll(self, fid):
+        r = nis_frame_result()
+        _check(_lib.nis_poll(self.h, fid, ctypes.byref(r)))
+        return r
+
+    def wait(self, fid):
+        r = nis_frame_result()
+        _check(_lib.nis_wait(self.h, fid, ctypes.byref(r)))
+        return r
+
+    def frame_image(self, result):
+        """Copy of a finished frame's image as a torch tensor."""
+        import torch
+        n = result.width * result.height
+        out = torch.empty(result.height, result.width, dtype=torch.float32,
+                          device=torch.device("cuda", self.device))
+        if n:
+            torch.cuda.synchronize(out.device)
+            _memcpy_d2d(out.data_ptr(), result.d_image, n * 4)
+        return out
+
+    def release(self, fid):
+        _check(_lib.nis_release(self.h, fid))
+
+    def server_stop(self):
+        _check(_lib.nis_server_stop(self.h))
 
     def profile(self, enable=True):
         _check(_lib.nis_profile(self.h, 1 if enable else 0))

@@ -67,3 +67,29 @@ def test_weight_blob_layout():
     assert body[-1] == p["beta"][-1][0]
     scaled = nis.pack_weights(p, fp8_scales=np.ones(6))
     assert len(scaled) == len(blob) + 6 * 4
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's sizes
+    and field offsets."""
+    import subprocess
+    from paper_2401_14051_amd import nis
+    structs = {"nis_camera": nis.nis_camera, "nis_server_cfg": nis.nis_server_cfg,
+               "nis_frame_req": nis.nis_frame_req, "nis_frame_result": nis.nis_frame_result}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "nis.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (name, name))
+        for field, _ in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (name, field, name, field))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                  check=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert int(got[name + "." + field]) == getattr(cls, field).offset, (name, field)
