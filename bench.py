@@ -1,22 +1,27 @@
 """Throughput benchmark of the in-scattering hot path on one GPU.
 
-A step is one pass of the whole path over one 1080p frame of the 256^3 fBm
-cloud (about 1.2M shading points, backbone 10 x 200): rebuild the density
-pyramid from the resident grid, apply the light (the transmittance sweep runs
-again), then gather, CNN + attention, backbone and decode for every point.
-Inputs are resident in device memory before the timed region starts.
+A step is one whole frame: rebuild the density pyramid of the 256^3 fBm cloud
+from the resident grid, apply the light (the transmittance sweep runs again),
+trace the 1920x1080 camera rays to their first delta-tracking collision and
+compact them (about 1.2M shading points), then gather, CNN + attention,
+backbone and decode for every point, and write the image.  Nothing crosses
+PCIe inside the timed region; the collision count stays on the device.
 
-Prints one JSON line: shading points/s (whole job), ms per step, 1080p frames/s,
-per-kernel times from HIP events recorded by the library on the stream its
-kernels run on, the roofline of the dominant kernel, the radiance error against
-the FP64 oracle on a seeded sample, and the oracle's own throughput on the host
-cores.
+Prints one JSON line: shading points/s (whole job), ms per frame, frames/s,
+per-kernel times from HIP events the library records on the stream its
+kernels run on, the roofline of the dominant kernel, the radiance error of
+each precision against the FP64 oracle on a seeded sample of the frame, the
+oracle's own throughput on the host cores, and a serving run (Poisson frame
+requests over media of 64^3..512^3 and three resolutions) with p50/p99 frame
+latency.
 """
 
 import argparse
 import json
 import os
+import queue
 import sys
+import threading
 import time
 
 import numpy as np
@@ -48,10 +53,19 @@ def parse():
                     help="run one plain device copy of this size (for scaling HBM counters)")
     ap.add_argument("--compare-fp32", action="store_true", default=True)
     ap.add_argument("--no-compare-fp32", dest="compare_fp32", action="store_false")
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="length of the Poisson request trace of the serving run (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-inflight", type=int, default=8)
+    ap.add_argument("--serve-budget-gb", type=int, default=200)
     return ap.parse_args()
 
 
-def kernel_work(wl, levels, level_geom, npts, width, n_linear, prec):
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_work(wl, levels, level_geom, npix, npts, width, n_linear, prec):
     """Algorithmic bytes / FLOPs per launch of each kernel."""
     esize = {"fp32": 4, "bf16": 2, "fp8": 2}[prec]     # the FP8 path stores the descriptor in BF16
     n0 = wl.n
@@ -63,9 +77,12 @@ def kernel_work(wl, levels, level_geom, npts, width, n_linear, prec):
         "pyramid": {"bytes": 4 * sum(vox[:-1]) + 4 * sum(vox[1:])},
         "sweep": {"bytes": 4 * sum(vox) + 4 * samples},
         "site_tables": {"bytes": 225 * 16},
+        # rays: flag, point and direction per pixel; scan; compacted copies
+        "raygen": {"bytes": npix * (4 + 12 + 12) + npix * 8 + npts * (12 + 12 + 4)},
         "features": {"bytes": npts * (24 + 4 + 1088 * esize), "flops": npts * conv_flop,
                      "valu_flops": npts * GATHER_FLOP_PER_POINT},
         "backbone": {"bytes": npts * (1088 * esize + 8), "flops": npts * mlp_flop},
+        "image": {"bytes": npix * 4 + npts * 12},
     }
 
 
@@ -83,6 +100,89 @@ def measured_traffic(kernel, prec, workload):
     return rec["traffic_bytes_per_launch"]
 
 
+def frame_camera(nis, wl):
+    if wl.cam == "ortho":
+        return nis.camera(wl.res[0], wl.res[0], vfov_deg=0.0, ortho_z=1.0)
+    return nis.camera(wl.res[0], wl.res[1], 45.0, eye=wl.eye)
+
+
+def serving(ctx, nis, args):
+    """Poisson frame requests through the frame server: media of 64^3..512^3
+    (pyramids resident), resolutions 256^2 / 720p / 1080p, a random light and
+    g per request, BF16 network.  Returns the offered and achieved rates and
+    the latency percentiles (submission to observed completion)."""
+    from workloads import configs, medium
+    t0 = time.time()
+    mids = {n: ctx.load_medium(medium.fbm_cloud(n, seed=0), 8.0, 0.99, 0.85) for n in (64, 128, 256, 512)}
+    log("serving: media loaded (%.1fs)" % (time.time() - t0))
+    cams = {res: nis.camera(res[0], res[1], 45.0, eye=configs.FRAME_EYE)
+            for res in ((256, 256), (1280, 720), (1920, 1080))}
+
+    def run(trace):
+        q = queue.Queue()
+        recs = []
+
+        def submit():
+            base = time.perf_counter()
+            for r in trace:
+                dt = r["t"] - (time.perf_counter() - base)
+                if dt > 0:
+                    time.sleep(dt)
+                q.put((ctx.submit(mids[r["n"]], cams[r["res"]], r["light"], 1.0, r["g"], r["seed"]), r))
+            q.put(None)
+
+        def collect():
+            while True:
+                item = q.get()
+                if item is None:
+                    return
+                fid, r = item
+                res = ctx.wait(fid)
+                recs.append((res.status, res.t_submit, res.t_start, res.t_done, res.n_points))
+                ctx.release(fid)
+
+        ts, tc = threading.Thread(target=submit), threading.Thread(target=collect)
+        ts.start()
+        tc.start()
+        ts.join()
+        tc.join()
+        ok = [x for x in recs if x[0] == 0]
+        lat = np.array([x[3] - x[1] for x in ok]) * 1e3
+        span = max(x[3] for x in ok) - min(x[1] for x in ok)
+        return {"requests": len(trace), "completed": len(ok), "failed": len(recs) - len(ok),
+                "offered_rps": len(trace) / max(trace[-1]["t"], 1e-9),
+                "frames_per_s": len(ok) / span, "points_per_s": sum(x[4] for x in ok) / span,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_queue_ms": float(np.mean([(x[2] - x[1]) * 1e3 for x in ok]))}
+
+    ctx.server_start(args.serve_budget_gb << 30, "bf16", args.serve_inflight)
+    try:
+        # warm every slot with a 1080p frame of the largest medium (allocations)
+        warm = [dict(t=0.0, n=512, res=(1920, 1080), light=(0.3, 0.9, 0.3), g=0.85, seed=i)
+                for i in range(args.serve_inflight)]
+        run(warm)
+        trace = configs.serving_trace(args.serve_seconds, rate=args.serve_rate, seed=7)
+        log("serving: %d requests over %.1fs at %.0f req/s" % (len(trace), args.serve_seconds, args.serve_rate))
+        offered = run(trace)
+        log("serving: offered %s" % json.dumps(offered))
+        # the same mix at 70% of the rate the device sustained, for latency
+        # percentiles that are not dominated by a growing queue
+        rate = 0.7 * offered["frames_per_s"]
+        trace2 = configs.serving_trace(max(args.serve_seconds, 300.0 / rate), rate=rate, seed=8)
+        sustained = run(trace2)
+        log("serving: sustained %s" % json.dumps(sustained))
+    finally:
+        ctx.server_stop()
+    for m in mids.values():
+        ctx.unload_medium(m)
+    return {"config": "Poisson arrivals; media 64^3/128^3/256^3/512^3 fBm (resident); 256^2/720p/1080p "
+                      "pinhole; random light and g in [0.3,0.95]; bf16; %d frames in flight; budget %d GB"
+                      % (args.serve_inflight, args.serve_budget_gb),
+            "latency": "submission to observed completion, host steady clock",
+            "at_%g_rps" % args.serve_rate: offered,
+            "at_70pct_capacity": dict(sustained, rate_rps=rate)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -91,30 +191,31 @@ def main():
         sys.exit(2)
     import torch
     from paper_2401_14051_amd import nis
-    from workloads import configs
+    from workloads import camera, configs
 
     wl = configs.BY_NAME[args.workload]
     t0 = time.time()
     density = wl.density()
-    pts, dirs, _ = wl.points(density)
+    o, d = wl.rays()
+    pts, dirs, pix = camera.delta_track(density, wl.sigma_t, o, d, seed=wl.point_seed)
     params = wl.params()
-    print("[bench] workload %s: %d^3 medium, %d points (%.1fs)" % (wl.name, wl.n, len(pts), time.time() - t0),
-          file=sys.stderr, flush=True)
+    npix = o.shape[0]
+    log("workload %s: %d^3 medium, %d pixels, %d points (%.1fs)" % (wl.name, wl.n, npix, len(pts),
+                                                                   time.time() - t0))
 
     ctx = nis.Context(0)
     mid = ctx.load_medium(density, wl.sigma_t, wl.albedo, wl.g)
     ctx.set_light(mid, wl.light, wl.radiance)
     ctx.set_weights(params)
+    cam = frame_camera(nis, wl)
     stream = torch.cuda.Stream()
-    dp = torch.from_numpy(pts).cuda()
-    dd = torch.from_numpy(dirs).cuda()
-    out = torch.empty(len(pts), dtype=torch.float32, device="cuda")
+    img = torch.empty(npix, dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
 
     def step():
         ctx.rebuild_pyramid(mid, stream.cuda_stream)
         ctx.set_light(mid, wl.light, wl.radiance)
-        ctx.query_device(mid, dp, dd, out, stream.cuda_stream)
+        ctx.render(mid, cam, wl.point_seed, out=img, stream=stream.cuda_stream)
 
     def run(prec, steps, warmup):
         ctx.set_precision(prec)
@@ -146,9 +247,7 @@ def main():
         ctx.profile(False)
         res[prec] = {"ms": ms, "wall_s": wall, "kernels": {k: v[1] / v[0] for k, v in rep.items()},
                      "launches": {k: v[0] for k, v in rep.items()}}
-        print("[bench] %s: %.3f ms/step, kernels %s" % (prec, ms, {k: round(v, 4) for k, v in
-                                                                 res[prec]["kernels"].items()}),
-              file=sys.stderr, flush=True)
+        log("%s: %.3f ms/frame, kernels %s" % (prec, ms, {k: round(v, 4) for k, v in res[prec]["kernels"].items()}))
 
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * (1 << 20) // 4
@@ -159,7 +258,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # parity on a seeded sample, against the FP64 oracle
+    # parity of the rendered frame on a seeded sample of its hit pixels,
+    # against the FP64 oracle at the generator's collision points
     from oracle import oracle
     f32 = lambda x: float(np.float32(x))
     om = oracle.Medium(density)
@@ -170,14 +270,18 @@ def main():
     op["lam"] = f32(params["lam"])
     rng = np.random.default_rng(123)
     sidx = np.sort(rng.choice(len(pts), min(args.parity_sample, len(pts)), replace=False))
-    ref = om.query(op, pts[sidx], dirs[sidx], f32(wl.sigma_t), f32(wl.albedo), f32(wl.g), f32(wl.radiance))
+    ref = f32(wl.albedo) * om.query(op, pts[sidx], dirs[sidx], f32(wl.sigma_t), f32(wl.albedo), f32(wl.g),
+                                    f32(wl.radiance))["L"]
     errs = {}
     for prec in precs:
         ctx.set_precision(prec)
         step()
         torch.cuda.synchronize()
-        got = out.cpu().numpy()[sidx].astype(np.float64)
-        errs[prec] = float(np.linalg.norm(got - ref["L"]) / np.linalg.norm(ref["L"]))
+        got = img.cpu().numpy()[pix[sidx]].astype(np.float64)
+        errs[prec] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    miss = np.ones(npix, bool)
+    miss[pix] = False
+    misses_zero = bool(np.all(img.cpu().numpy()[miss] == 0.0))
 
     # oracle throughput on the host cores (bounded sample)
     cpu = None
@@ -190,7 +294,7 @@ def main():
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         cpu = {"value": len(pts) / frame_s, "unit": "shading points/s", "cores": cores, "kind": "oracle",
                "sample": "FP64 oracle: full-resolution sweep (%.2fs, 1 thread) plus a seeded %d-point subset "
-                         "of the frame (%.2fs on %d threads), scaled to the frame's %d points"
+                         "of the frame's collisions (%.2fs on %d threads), scaled to the frame's %d points"
                          % (t_sweep, len(cidx), tq, cores, len(pts))}
 
     prec = args.precision
@@ -200,7 +304,7 @@ def main():
     for m in range(levels):
         D, (ulo, uhi, vlo, vhi) = ctx.path_density(mid, m)
         geom.append((uhi - ulo + 1, vhi - vlo + 1, D.shape[0]))
-    work = kernel_work(wl, levels, geom, len(pts), params["width"], params["n_linear"], prec)
+    work = kernel_work(wl, levels, geom, npix, len(pts), params["width"], params["n_linear"], prec)
     kernels = {}
     for k, t_ms in res[prec]["kernels"].items():
         w = work.get(k, {})
@@ -230,6 +334,11 @@ def main():
                 "frac": dk["hbm_frac"], "traffic": None}
     roof["traffic"] = measured_traffic(dom, prec, args.workload)
 
+    serve = None
+    if args.serve_seconds > 0:
+        ctx.set_weights(configs.FRAME.params())
+        serve = serving(ctx, nis, args)
+
     line = {
         "metric": "shading points/sec (1080p frame of a 256^3 fBm cloud, light change every frame)",
         "value": len(pts) / (ms * 1e-3),
@@ -242,18 +351,20 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": prec,
-        "data": "synthetic (seeded fBm cloud, delta-tracked 1080p camera points, He-init weights)",
+        "data": "synthetic (seeded fBm cloud, delta-tracked camera rays on the GPU, He-init weights)",
         "config": {"workload": "%s: %d^3 fBm cloud, %dx%d camera, %d shading points, backbone %dx%d, %s"
-                               % (wl.name, wl.n, wl.res[0], wl.res[1], len(pts), params["n_linear"],
-                                  params["width"], prec),
-                   "points": len(pts)},
+                               % (wl.name, wl.n, wl.res[0], wl.res[1] if wl.cam != "ortho" else wl.res[0],
+                                  len(pts), params["n_linear"], params["width"], prec),
+                   "points": len(pts), "pixels": npix},
         "fps": 1000.0 / ms,
         "rel_l2_vs_fp64_oracle": {p: errs[p] for p in precs},
+        "misses_are_zero": misses_zero,
         "per_precision": {p: {"ms_per_step": res[p]["ms"], "points_per_s": len(pts) / (res[p]["ms"] * 1e-3),
                               "fps": 1000.0 / res[p]["ms"], "kernels_ms": res[p]["kernels"]} for p in precs},
         "kernels": kernels,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serve,
     }
     print(json.dumps(line))
     ctx.close()
