@@ -23,58 +23,70 @@
 // p + 2^k h_0 (q l/|l_a| + i e_b + j e_c), evaluated term by term without
 // contraction, because that decision is discontinuous in the position.
 //
-// Work split.  A workgroup holds kTP points.  Per layer, every thread of the
-// workgroup evaluates rows of 5 sites (one slab q, one lateral j, i = -2..2):
-// a row needs 4 rows of 6 path densities and 4 rows of 6 densities, which it
-// reads contiguously and interpolates separably (along the slice or the light
-// axis first, then the lateral axes).  Rows whose indices all lie inside the
-// field take a path without clamping; the others clamp every index.  Levels
-// with at most 8^3 voxels are copied whole into LDS first and read from there.
+// Work split.  A workgroup is one wave and holds kTP = 4 points; the 16 lanes
+// of a point share its work, so no stage waits for another wave.  Per layer a
+// lane evaluates up to three rows of 5 sites (one slab q, one lateral j,
+// i = -2..2): a row needs 4 rows of 6 path densities and 4 rows of 6
+// densities, read contiguously and interpolated with the shared bilinear
+// weights across rows, then linearly along the row.  Rows whose indices all
+// lie inside the field take a path without clamping; the others clamp every
+// index.  Each lane keeps its own running sums and maxima, reduced over the
+// point's 16 lanes by shuffles.
+//
+// Lattice layout for conv1.  Each 5-site row of the transmittance lattice is
+// stored as three 4-wide windows starting at i = 0, 1, 2 (the last padded with
+// a zero), so the 3 taps of a kernel row -- plus a fourth tap with zero weight
+// -- are one aligned 4-element read for every output position.  conv1's K
+// index is tap-row * 4 + dx over 9 tap-rows (K = 36, padded to the MFMA step).
 #include "launch_args.h"
 #include "mfma.h"
 
 namespace nis {
 
-constexpr int kTP = 16;                   // points per workgroup
+constexpr int kTP = 4;                    // points per workgroup (one wave)
+constexpr int kXcds = 8;                  // accelerator complex dies of the MI355X
+constexpr int kCbFloats = 8 + 16 + 64 + 4 + 64 + 16;   // b1 b2 s1 c1 s2 c2
 constexpr int kRows = 45;                 // site rows per point and layer
-constexpr int kLatStride = 232;           // 225 sites + padding
+constexpr int kLatRow = 12;               // three 4-wide windows of a 5-site row
+constexpr int kLatStride = kRows * kLatRow + 4;
 constexpr int kY1Pos = 64;                // 63 conv1 positions + 1
-constexpr int kSmallLevel = 4096;         // floats of a level staged whole in LDS
 constexpr int kBufferFlags = 0x00020000;  // buffer resource word 3 for gfx9-family raw loads
+constexpr int kBrickJ = 10, kBrickV = 6, kBrickU = 6;   // path-density brick of one point-layer
 
-struct PointLayer {           // per point and layer
-    int iu, iv, ij, ia0;      // sheared base indices (path density) and light-axis base (density)
-    float wu, wv, wj, wa;     // their interpolation weights
+struct PointLayer {           // per point and layer (path-density lookups)
+    int iu, iv, ij, pad;      // sheared base indices
+    float w00, w10, w01, w11; // bilinear weights over (J, V): (J0,V0) (J0+1,V0) (J0,V0+1) (J0+1,V0+1)
+    float wu, wv, wj, pad1;
 };
 
-struct SlabParams {           // per point, layer and slab q
-    int ib0, ic0, mask, pad;  // density lateral bases; in-cube bits (0-4 i, 5-9 j, 10 slab)
-    float wb, wc, pad1, pad2;
+struct SlabParams {           // per point, layer and slab q (density lookups)
+    int ia, cbase, bbase, mask;   // a base of the slab, first c and b of its brick; in-cube bits
+    float wa, wc, wb, pad;        // (0-4 i, 5-9 j, 10 slab) and the weights along a, c, b
 };
 
-// Shared memory of one workgroup.  The whole-level copy is only live during
-// the gather and the conv1 output only afterwards; the per-row statistics only
-// until conv2 writes its output.
+// Shared memory of one wave.  The lattice is dead once conv1 has read it, so
+// the attention stage reuses its space.  The brick area holds the
+// path-density bricks, then the density bricks, then conv1's output, which in
+// turn stages the descriptor rows once conv2 has read it.
 template <class E> struct FeatShared {
-    E lat[kTP][kLatStride];
     union {
-        float small_lvl[kSmallLevel];
-        E y1[kTP][kY1Pos][8];                // conv1 output, channels fastest
-    } __attribute__((aligned(16))) u1;
-    union {
-        float part[kTP * kRows][4];
+        E lat[kTP][kLatStride];
         struct {
             float H[kTP][16][5];
             float zc[kTP][16];
             float hid[kTP][4];
-            float gate[kTP][16];
         } se;
-    } u2;
+    } __attribute__((aligned(16))) u0;
+    union {
+        float brick[kTP][kBrickJ * kBrickV * kBrickU];
+        E y1[kTP][kY1Pos][8];                  // conv1 output, channels fastest
+    } __attribute__((aligned(16))) u1;
     float pstat[kTP][kStats];
     float pfix[kTP][3];
     double px[kTP][3];
     PointLayer pl[kTP];
     SlabParams sp[kTP][9];
+    float cb[kCbFloats];                       // the group's conv biases and attention weights
 };
 
 __device__ __forceinline__ double site_coord(double x, double scale, double qo, int i)
@@ -98,6 +110,15 @@ __device__ __forceinline__ double hg64(const MediumView& mv, double mu)
 __device__ __forceinline__ float lerpf(float a, float b, float w) { return a + w * (b - a); }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+
+// The value unchanged, but opaque to the optimiser: per-lane index arithmetic
+// derived from it inside the layer loop is recomputed each layer instead of
+// being hoisted out of the loop and kept live (and spilled) across it.
+__device__ __forceinline__ int opaque(int v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
 
 // light-sheared continuous coordinates of x at level m
 __device__ __forceinline__ void sheared(const MediumView& mv, int nm, const double x[3], double& Uf,
@@ -127,60 +148,87 @@ __device__ __forceinline__ float sample_D(const float* __restrict__ D, const Lev
     return lerpf(lerpf(a00, a01, wv), lerpf(a10, a11, wv), wj);
 }
 
-// Separable interpolation of one row of 5 sites from 4 rows of 6 samples:
-// first between rows (r00,r10) and (r01,r11) with weight w1, then between the
-// two results with w2, then along the row with w3.
+// One row of 5 sites from 4 rows of 6 samples: bilinear across the rows with
+// the shared weights, then linear along the row.
 __device__ __forceinline__ void row5(const float* r00, const float* r10, const float* r01, const float* r11,
-                                     float w1, float w2, float w3, float out[5])
+                                     float w00, float w10, float w01, float w11, float wr, float out[5])
 {
     float b[6];
 #pragma unroll
-    for (int u = 0; u < 6; u++) b[u] = lerpf(lerpf(r00[u], r10[u], w1), lerpf(r01[u], r11[u], w1), w2);
+    for (int u = 0; u < 6; u++) b[u] = w00 * r00[u] + w10 * r10[u] + w01 * r01[u] + w11 * r11[u];
 #pragma unroll
-    for (int i = 0; i < 5; i++) out[i] = lerpf(b[i], b[i + 1], w3);
+    for (int i = 0; i < 5; i++) out[i] = lerpf(b[i], b[i + 1], wr);
 }
 
-template <class T>
-__device__ __forceinline__ void load6(const T* p, float v[6])
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b)
 {
-#pragma unroll
-    for (int u = 0; u < 6; u++) v[u] = p[u];
+    bf16x2 v = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, v);
 }
+
+// The three 4-wide windows of a lattice row of 5 values.
+template <class E> __device__ __forceinline__ void store_windows(E* row, const float t[5]);
+
+template <> __device__ __forceinline__ void store_windows<float>(float* row, const float t[5])
+{
+    *reinterpret_cast<float4*>(row + 0) = make_float4(t[0], t[1], t[2], t[3]);
+    *reinterpret_cast<float4*>(row + 4) = make_float4(t[1], t[2], t[3], t[4]);
+    *reinterpret_cast<float4*>(row + 8) = make_float4(t[2], t[3], t[4], 0.f);
+}
+
+template <> __device__ __forceinline__ void store_windows<__bf16>(__bf16* row, const float t[5])
+{
+    const uint32_t p01 = pack_bf16(t[0], t[1]), p12 = pack_bf16(t[1], t[2]), p23 = pack_bf16(t[2], t[3]);
+    const uint32_t p34 = pack_bf16(t[3], t[4]), p40 = pack_bf16(t[4], 0.f);
+    *reinterpret_cast<uint2*>(row + 0) = make_uint2(p01, p23);
+    *reinterpret_cast<uint2*>(row + 4) = make_uint2(p12, p34);
+    *reinterpret_cast<uint2*>(row + 8) = make_uint2(p23, p40);
+}
+
+// element offset in a point's lattice of tap-row tr = dz * 3 + dy
+__device__ __forceinline__ int taprow_off(int tr) { return ((tr / 3) * 5 + tr % 3) * kLatRow; }
 
 template <int PREC, bool DBG>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64, 4)
 k_features(FeatArgs A)
 {
     typedef Mfma<PREC> M;
     typedef typename M::elem E;
     __shared__ FeatShared<E> sh;
-    E(*lat)[kLatStride] = sh.lat;
+    E(*lat)[kLatStride] = sh.u0.lat;
     E(*y1)[kY1Pos][8] = sh.u1.y1;
-    float* small_lvl = sh.u1.small_lvl;
-    float(*part)[4] = sh.u2.part;
-    float(*H)[16][5] = sh.u2.se.H;
-    float(*zc)[16] = sh.u2.se.zc;
-    float(*hid)[4] = sh.u2.se.hid;
-    float(*gate)[16] = sh.u2.se.gate;
+    float(*brick)[kBrickJ * kBrickV * kBrickU] = sh.u1.brick;
+    SlabParams(*sp)[9] = sh.sp;
+    float* cbl = sh.cb;
+    float(*H)[16][5] = sh.u0.se.H;
+    float(*zc)[16] = sh.u0.se.zc;
+    float(*hid)[4] = sh.u0.se.hid;
     float(*pstat)[kStats] = sh.pstat;
     float(*pfix)[3] = sh.pfix;
     double(*px)[3] = sh.px;
     PointLayer* pl = sh.pl;
-    SlabParams(*sp)[9] = sh.sp;
 
     const MediumView& mv = A.mv;
-    const int tid = threadIdx.x;
-    const int wave = tid / 64, lane = tid % 64;
-    const int lr = lane % 16, lg = lane / 16;
-    const int64_t tile0 = (int64_t)blockIdx.x * kTP;
-    // the point count may live in device memory (frames whose hit count the
-    // device computed); blocks past it leave before any barrier
+    const int lane = threadIdx.x;
+    const int lr = lane % 16, lg = lane / 16;   // point lg of the tile, lane lr of the point
+    // Workgroups are dealt to the 8 XCDs in turn (workgroup i runs on XCD i mod
+    // 8), each with its own L2; give every XCD one contiguous run of tiles so
+    // that neighbouring points share an L2.  The grid is a multiple of 8.
     const int64_t npts = A.count ? min(max((int64_t)*A.count - A.count_off, (int64_t)0), A.npts) : A.npts;
+    const int64_t per_xcd = ((npts + kTP - 1) / kTP + kXcds - 1) / kXcds;   // of the live tiles
+    const int64_t slot = blockIdx.x / kXcds;
+    if (slot >= per_xcd) return;
+    const int64_t tile0 = ((int64_t)(blockIdx.x % kXcds) * per_xcd + slot) * kTP;
+    // (the point count may live in device memory: frames whose hit count the
+    // device computed; workgroups past it leave at once)
     if (tile0 >= npts) return;
 
     // ---- per point: position, phase features, transmittance to the light ----
     {
-        const int pt = tid / 16, sub = tid % 16;
+        const int pt = lg, sub = lr;
         const int64_t p = tile0 + pt;
         const bool live = p < npts;
         const int64_t pc = live ? p : npts - 1;
@@ -229,18 +277,12 @@ k_features(FeatArgs A)
         }
     }
 
-    // conv1 B-fragment lattice offsets of this lane's taps (fixed for all tiles)
-    int tapoff[M::KPL * (kConv1K / M::KS)];
-#pragma unroll
-    for (int kc = 0; kc < kConv1K / M::KS; kc++)
-#pragma unroll
-        for (int e = 0; e < M::KPL; e++) {
-            const int kk = kc * M::KS + lg * M::KPL + e;
-            tapoff[kc * M::KPL + e] = kk < 27 ? (kk / 9) * 25 + ((kk / 3) % 3) * 5 + (kk % 3) : -1;
-        }
     E* desc = reinterpret_cast<E*>(A.desc);
 
-    float row_absmax = 0.f;   // thread (point, o): max |stored entry| of its point so far
+    // conv1 A fragments of the current weight group (reloaded when it changes)
+    constexpr int KC1 = 72 / M::KS + (72 % M::KS != 0);
+    typename M::frag aw[KC1];
+    float row_absmax = 0.f;   // lane (point, o): max |stored entry| of its point so far
     for (int k = 0; k < kLayers; k++) {
         const int m = k < mv.levels - 1 ? k : mv.levels - 1;
         const Level lv = mv.lev[m];
@@ -253,221 +295,337 @@ k_features(FeatArgs A)
         const int sta = st[mv.a], stb = st[mv.b], stc = st[mv.c];
         const int plane = lv.nu * lv.nv;
         const int dsize = plane * nm, rsize = nm * nm * nm;
-        const bool small = dsize + rsize <= kSmallLevel;
-        __syncthreads();   // previous layer's users of the shared tables are done
+        const __amdgpu_buffer_rsrc_t rD =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(mv.D + lv.d_off), 0, dsize * 4, kBufferFlags);
+        const __amdgpu_buffer_rsrc_t rR =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(mv.rho + lv.rho_off), 0, rsize * 4, kBufferFlags);
+        auto ldD = [&](int o) { return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rD, o * 4, 0, 0)); };
+        auto ldR = [&](int o) { return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rR, o * 4, 0, 0)); };
+        __syncthreads();   // the previous layer's readers of the shared tables are done
+        const int ln = opaque(lane), lrl = ln & 15;
+        if (k == 0 || k == kDiffuse) {
+            const E* w1 = reinterpret_cast<const E*>(A.w1t[grp]);
+#pragma unroll
+            for (int kc = 0; kc < KC1; kc++) aw[kc] = M::load(w1 + lr * kConv1K + kc * M::KS + lg * M::KPL);
+            for (int e = ln; e < kCbFloats; e += 64) cbl[e] = A.cb[grp][e];
+        }
 
-        // ---- per point-layer and per slab set-up --------------------------------
-        if (tid < kTP * 9) {
-            const int pt = tid / 9, qi = tid % 9;
-            const double x[3] = {px[pt][0], px[pt][1], px[pt][2]};
+        // ---- set-up: sheared path-density bases (one lane per point) and the
+        // density bases, in-cube bits and weights of each slab (one lane per slab)
+        if (ln < kTP * 9) {
+            const int spt = ln / 9, qi = ln % 9;
+            const double x[3] = {px[spt][0], px[spt][1], px[spt][2]};
             int mask = 0;
-            double sa = site_coord_a(x[mv.a], scale, mv.qoff[mv.a][qi]);
+            const double sa = site_coord_a(x[mv.a], scale, mv.qoff[mv.a][qi]);
             if (sa >= 0.0 && sa <= 1.0) mask |= 1 << 10;
             for (int i = -2; i <= 2; i++) {
-                double sb = site_coord(x[mv.b], scale, mv.qoff[mv.b][qi], i);
-                double sc = site_coord(x[mv.c], scale, mv.qoff[mv.c][qi], i);
+                const double sb = site_coord(x[mv.b], scale, mv.qoff[mv.b][qi], i);
+                const double sc = site_coord(x[mv.c], scale, mv.qoff[mv.c][qi], i);
                 if (sb >= 0.0 && sb <= 1.0) mask |= 1 << (i + 2);
                 if (sc >= 0.0 && sc <= 1.0) mask |= 1 << (i + 7);
             }
-            double gb = x[mv.b] * nm - 0.5 + c * mv.qoff[mv.b][qi];
-            double gc = x[mv.c] * nm - 0.5 + c * mv.qoff[mv.c][qi];
-            double fb = floor(gb), fc = floor(gc);
+            const double gb = x[mv.b] * nm - 0.5 + c * mv.qoff[mv.b][qi];
+            const double gc = x[mv.c] * nm - 0.5 + c * mv.qoff[mv.c][qi];
+            const double ga = x[mv.a] * nm - 0.5;
+            const double fb = floor(gb), fc = floor(gc), fa = floor(ga);
             SlabParams s;
-            s.ib0 = (int)fb;
-            s.ic0 = (int)fc;
+            s.ia = (int)fa + (qi - 4) * mv.sigma;
+            s.cbase = (int)fc - 2;
+            s.bbase = (int)fb - 2;
             s.mask = mask;
-            s.pad = 0;
-            s.wb = (float)(gb - fb);
+            s.wa = (float)(ga - fa);
             s.wc = (float)(gc - fc);
-            s.pad1 = s.pad2 = 0.f;
-            sp[pt][qi] = s;
-        } else if (tid < kTP * 10) {
-            const int pt = tid - kTP * 9;
-            const double x[3] = {px[pt][0], px[pt][1], px[pt][2]};
+            s.wb = (float)(gb - fb);
+            s.pad = 0.f;
+            sp[spt][qi] = s;
+        } else if (ln < kTP * 10) {
+            const int q4 = ln - kTP * 9;
+            const double x[3] = {px[q4][0], px[q4][1], px[q4][2]};
             double Uf, Vf, Jf;
             sheared(mv, nm, x, Uf, Vf, Jf);
             const double fu = floor(Uf), fv = floor(Vf), fj = floor(Jf);
-            const double ga = x[mv.a] * nm - 0.5;
-            const double fa = floor(ga);
             PointLayer q;
             q.iu = (int)fu;
             q.iv = (int)fv;
             q.ij = (int)fj;
-            q.ia0 = (int)fa;
+            q.pad = 0;
             q.wu = (float)(Uf - fu);
             q.wv = (float)(Vf - fv);
             q.wj = (float)(Jf - fj);
-            q.wa = (float)(ga - fa);
-            pl[pt] = q;
+            q.w00 = (1.f - q.wj) * (1.f - q.wv);
+            q.w10 = q.wj * (1.f - q.wv);
+            q.w01 = (1.f - q.wj) * q.wv;
+            q.w11 = q.wj * q.wv;
+            q.pad1 = 0.f;
+            pl[q4] = q;
         }
-        if (small) {
-            const float* srcD = mv.D + lv.d_off;
-            const float* srcR = mv.rho + lv.rho_off;
-            for (int e = tid; e < dsize; e += 256) small_lvl[e] = srcD[e];
-            for (int e = tid; e < rsize; e += 256) small_lvl[dsize + e] = srcR[e];
+        __syncthreads();
+        const int pt = ln >> 4;
+        const PointLayer P = pl[pt];
+
+        // ---- path-density bricks: for each point the rows J = ij-4..ij+5,
+        // V = iv-2..iv+3 of 6 samples U = iu-2..iu+3 (index-clamped), shared by
+        // the point's 45 site rows.  One lane per row (16 + 8 byte loads); the
+        // loads of all its rows are issued before the first store.  The
+        // single-voxel level (c > 1) is one 3 x 3 slice, copied whole.
+        if (c == 1) {
+            constexpr int kDRows = kTP * kBrickJ * kBrickV, kDIt = (kDRows + 63) / 64;
+#pragma unroll
+            for (int it0 = 0; it0 < kDIt; it0 += 2) {
+                float dv[2][6];
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const int rr = ln + 64 * (it0 + h);
+                    if (rr < kDRows) {
+                        const int bp = rr / (kBrickJ * kBrickV), loc = rr % (kBrickJ * kBrickV);
+                        const PointLayer Q = pl[bp];
+                        const int J = Q.ij - 4 + loc / kBrickV, V = Q.iv - 2 + loc % kBrickV - lv.vlo;
+                        const int U0 = Q.iu - 2 - lv.ulo;
+                        if (J >= 0 && J < nm && V >= 0 && V < lv.nv && U0 >= 0 && U0 + 5 < lv.nu) {
+                            const int o = (J * lv.nv + V) * lv.nu + U0;
+#pragma unroll
+                            for (int u = 0; u < 6; u++) dv[h][u] = ldD(o + u);
+                        } else {
+                            const int jo = clampi(J, 0, nm - 1) * plane + clampi(V, 0, lv.nv - 1) * lv.nu;
+#pragma unroll
+                            for (int u = 0; u < 6; u++) dv[h][u] = ldD(jo + clampi(U0 + u, 0, lv.nu - 1));
+                        }
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const int rr = ln + 64 * (it0 + h);
+                    if (rr < kDRows) {
+                        float2* dst = reinterpret_cast<float2*>(&brick[0][0] + rr * kBrickU);
+                        dst[0] = make_float2(dv[h][0], dv[h][1]);
+                        dst[1] = make_float2(dv[h][2], dv[h][3]);
+                        dst[2] = make_float2(dv[h][4], dv[h][5]);
+                    }
+                }
+            }
+        } else {
+            for (int e = ln; e < dsize; e += 64) brick[0][e] = ldD(e);
         }
         __syncthreads();
 
-        // ---- gather: rows of 5 sites ---------------------------------------------
-        // One instantiation per source: LDS for whole small levels, raw buffer
-        // loads (32-bit offsets, immediate offsets along a row) for the others.
-        auto gather = [&](auto ldD, auto ldR) __attribute__((always_inline)) {
-        for (int R = tid; R < kTP * kRows; R += 256) {
-            const int pt = R / kRows, r = R % kRows;
+        // ---- transmittance lattice: up to three rows of 5 sites per lane --------
+        float ts = 0.f, tmx = -INFINITY;
+        for (int r = lrl; r < kRows; r += 16) {
             const int qi = r / 5, jj = r % 5;
             const int q = qi - 4, j = jj - 2;
-            const PointLayer P = pl[pt];
-            const SlabParams S = sp[pt][qi];
-            float Dv[5], Rv[5];
-            // path density rows: J = ij - c q (+1), V = iv + c j (+1), U = iu + c i (+1)
+            float Dv[5];
             if (c == 1) {
-                const int J0 = P.ij - q, V0 = P.iv + j - lv.vlo, U0 = P.iu - 2 - lv.ulo;
-                const bool inside = J0 >= 0 && J0 + 1 < nm && V0 >= 0 && V0 + 1 < lv.nv && U0 >= 0 && U0 + 5 < lv.nu;
-                float a0[6], a1[6], b0[6], b1[6];
-                if (inside) {
-                    const int o = (J0 * lv.nv + V0) * lv.nu + U0;
+                // rows (J0, V0), (J0, V0+1), (J0+1, V0), (J0+1, V0+1) of the brick,
+                // J0 = ij - q -> bj = 4 - q, V0 = iv + j -> bv = j + 2
+                const float* b0 = &brick[pt][((4 - q) * kBrickV + jj) * kBrickU];
+                float d00[6], d01[6], d10[6], d11[6];
 #pragma unroll
-                    for (int u = 0; u < 6; u++) {
-                        a0[u] = ldD(o + u);
-                        b0[u] = ldD(o + lv.nu + u);
-                        a1[u] = ldD(o + plane + u);
-                        b1[u] = ldD(o + plane + lv.nu + u);
-                    }
-                } else {
-                    const int j0 = clampi(J0, 0, nm - 1) * plane, j1 = clampi(J0 + 1, 0, nm - 1) * plane;
-                    const int v0 = clampi(V0, 0, lv.nv - 1) * lv.nu, v1 = clampi(V0 + 1, 0, lv.nv - 1) * lv.nu;
-#pragma unroll
-                    for (int u = 0; u < 6; u++) {
-                        const int uc = clampi(U0 + u, 0, lv.nu - 1);
-                        a0[u] = ldD(j0 + v0 + uc);
-                        b0[u] = ldD(j0 + v1 + uc);
-                        a1[u] = ldD(j1 + v0 + uc);
-                        b1[u] = ldD(j1 + v1 + uc);
-                    }
+                for (int h = 0; h < 3; h++) {
+                    const float2 e00 = reinterpret_cast<const float2*>(b0)[h];
+                    const float2 e01 = reinterpret_cast<const float2*>(b0 + kBrickU)[h];
+                    const float2 e10 = reinterpret_cast<const float2*>(b0 + kBrickV * kBrickU)[h];
+                    const float2 e11 = reinterpret_cast<const float2*>(b0 + kBrickV * kBrickU + kBrickU)[h];
+                    d00[2 * h] = e00.x, d00[2 * h + 1] = e00.y;
+                    d01[2 * h] = e01.x, d01[2 * h + 1] = e01.y;
+                    d10[2 * h] = e10.x, d10[2 * h + 1] = e10.y;
+                    d11[2 * h] = e11.x, d11[2 * h + 1] = e11.y;
                 }
-                row5(a0, a1, b0, b1, P.wj, P.wv, P.wu, Dv);
+                row5(d00, d10, d01, d11, P.w00, P.w10, P.w01, P.w11, P.wu, Dv);
             } else {
                 // c > 1 only on the single-voxel level (one slice): sites are c apart
+                const float* sl = &brick[0][0];   // the whole slice, staged above
                 const int v0 = clampi(P.iv + c * j - lv.vlo, 0, lv.nv - 1) * lv.nu;
                 const int v1 = clampi(P.iv + c * j + 1 - lv.vlo, 0, lv.nv - 1) * lv.nu;
 #pragma unroll
                 for (int i = 0; i < 5; i++) {
                     const int u0 = clampi(P.iu + c * (i - 2) - lv.ulo, 0, lv.nu - 1);
                     const int u1 = clampi(P.iu + c * (i - 2) + 1 - lv.ulo, 0, lv.nu - 1);
-                    const float d0 = lerpf(ldD(v0 + u0), ldD(v0 + u1), P.wu);
-                    const float d1 = lerpf(ldD(v1 + u0), ldD(v1 + u1), P.wu);
-                    const float dd = lerpf(d0, d1, P.wv);
+                    const float e0 = lerpf(sl[v0 + u0], sl[v0 + u1], P.wu);
+                    const float e1 = lerpf(sl[v1 + u0], sl[v1 + u1], P.wu);
+                    const float dd = lerpf(e0, e1, P.wv);
                     Dv[i] = lerpf(dd, dd, P.wj);
                 }
             }
-            // density rows: a = ia0 + c q sigma (+1), c-axis ic0(q) + c j (+1), b-axis ib0(q) + c i (+1)
+            float T[5];
+#pragma unroll
+            for (int i = 0; i < 5; i++) T[i] = __expf(-coef * Dv[i]);
+            store_windows<E>(lat[pt] + r * kLatRow, T);
+            const int64_t p = tile0 + pt;
+#pragma unroll
+            for (int i = 0; i < 5; i++) {
+                ts += T[i];
+                tmx = fmaxf(tmx, T[i]);
+                if (DBG && p < npts) A.dbg_tbar[(p * kLayers + k) * kSites + r * 5 + i] = T[i];
+            }
+        }
+        __syncthreads();   // the path-density bricks are dead
+
+        // ---- density bricks: for each point and slab the rows c = cbase..+5 of
+        // 6 samples b = bbase..+5, interpolated between a = ia and ia+1 while
+        // loading (the a weight is shared by the slab's 25 sites).  One lane
+        // per row pair; loads are issued two row pairs at a time.
+        if (nm > 1) {
+            constexpr int kRRows = kTP * 9 * kBrickV, kRIt = (kRRows + 63) / 64;
+#pragma unroll
+            for (int it0 = 0; it0 < kRIt; it0 += 2) {
+                float r0v[2][6], r1v[2][6], wav[2];
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const int rr = ln + 64 * (it0 + h);
+                    wav[h] = 0.f;
+                    if (rr < kRRows) {
+                        const int bp = rr / (9 * kBrickV), loc = rr % (9 * kBrickV);
+                        const SlabParams S = sp[bp][loc / kBrickV];
+                        const int C = S.cbase + loc % kBrickV, B0 = S.bbase;
+                        wav[h] = S.wa;
+                        if (S.ia >= 0 && S.ia + 1 < nm && C >= 0 && C < nm && B0 >= 0 && B0 + 5 < nm && stb == 1) {
+                            const int o = S.ia * sta + C * stc + B0;
+#pragma unroll
+                            for (int u = 0; u < 6; u++) {
+                                r0v[h][u] = ldR(o + u);
+                                r1v[h][u] = ldR(o + sta + u);
+                            }
+                        } else {
+                            const int a0 = clampi(S.ia, 0, nm - 1) * sta + clampi(C, 0, nm - 1) * stc;
+                            const int a1 = clampi(S.ia + 1, 0, nm - 1) * sta + clampi(C, 0, nm - 1) * stc;
+#pragma unroll
+                            for (int u = 0; u < 6; u++) {
+                                const int bo = clampi(B0 + u, 0, nm - 1) * stb;
+                                r0v[h][u] = ldR(a0 + bo);
+                                r1v[h][u] = ldR(a1 + bo);
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const int rr = ln + 64 * (it0 + h);
+                    if (rr < kRRows) {
+                        const int bp = rr / (9 * kBrickV), loc = rr % (9 * kBrickV);
+                        float2* dst = reinterpret_cast<float2*>(&brick[bp][loc * kBrickU]);
+#pragma unroll
+                        for (int e = 0; e < 3; e++)
+                            dst[e] = make_float2(lerpf(r0v[h][2 * e], r1v[h][2 * e], wav[h]),
+                                                 lerpf(r0v[h][2 * e + 1], r1v[h][2 * e + 1], wav[h]));
+                    }
+                }
+            }
+            __syncthreads();
+        }
+
+        // ---- density statistics over the site rows, one to three per lane -------
+        float rs = 0.f, rmx = -INFINITY;
+        for (int r = lrl; r < kRows; r += 16) {
+            const int qi = r / 5, jj = r % 5;
+            const SlabParams S = sp[pt][qi];
+            float Rv[5];
             if (nm == 1) {
                 const float r0 = ldR(0);
 #pragma unroll
                 for (int i = 0; i < 5; i++) Rv[i] = r0;
             } else {
-                const int A0 = P.ia0 + q * mv.sigma, C0 = S.ic0 + j, B0 = S.ib0 - 2;
-                const bool inside = A0 >= 0 && A0 + 1 < nm && C0 >= 0 && C0 + 1 < nm && B0 >= 0 && B0 + 5 < nm &&
-                                    stb == 1;
-                float a0[6], a1[6], b0[6], b1[6];
-                if (inside) {
-                    const int o = A0 * sta + C0 * stc + B0;
+                // plane rows c = c0 + j and c + 1 of the slab's a-interpolated brick
+                const float* b0 = &brick[pt][(qi * kBrickV + jj) * kBrickU];
+                float e0[6], e1[6], bb[6];
 #pragma unroll
-                    for (int u = 0; u < 6; u++) {
-                        a0[u] = ldR(o + u);
-                        a1[u] = ldR(o + sta + u);
-                        b0[u] = ldR(o + stc + u);
-                        b1[u] = ldR(o + sta + stc + u);
-                    }
-                } else {
-                    const int x0 = clampi(A0, 0, nm - 1) * sta, x1 = clampi(A0 + 1, 0, nm - 1) * sta;
-                    const int z0 = clampi(C0, 0, nm - 1) * stc, z1 = clampi(C0 + 1, 0, nm - 1) * stc;
-#pragma unroll
-                    for (int u = 0; u < 6; u++) {
-                        const int bc = clampi(B0 + u, 0, nm - 1) * stb;
-                        a0[u] = ldR(x0 + z0 + bc);
-                        a1[u] = ldR(x1 + z0 + bc);
-                        b0[u] = ldR(x0 + z1 + bc);
-                        b1[u] = ldR(x1 + z1 + bc);
-                    }
+                for (int h = 0; h < 3; h++) {
+                    const float2 f0 = reinterpret_cast<const float2*>(b0)[h];
+                    const float2 f1 = reinterpret_cast<const float2*>(b0 + kBrickU)[h];
+                    e0[2 * h] = f0.x, e0[2 * h + 1] = f0.y;
+                    e1[2 * h] = f1.x, e1[2 * h + 1] = f1.y;
                 }
-                row5(a0, a1, b0, b1, P.wa, S.wc, S.wb, Rv);
+#pragma unroll
+                for (int u = 0; u < 6; u++) bb[u] = lerpf(e0[u], e1[u], S.wc);
+#pragma unroll
+                for (int i = 0; i < 5; i++) Rv[i] = lerpf(bb[i], bb[i + 1], S.wb);
             }
-            float rs = 0.f, rmx = -INFINITY, ts = 0.f, tmx = -INFINITY;
+            // in-cube bits of the row's sites: the slab, the lateral j, then each i
+            const int m5 = ((S.mask >> 10) & (S.mask >> (jj + 5)) & 1) ? (S.mask & 31) : 0;
             const int64_t p = tile0 + pt;
 #pragma unroll
             for (int i = 0; i < 5; i++) {
-                const float T = __expf(-coef * Dv[i]);
-                const float rv = ((S.mask >> 10) & (S.mask >> i) & (S.mask >> (jj + 5)) & 1) ? Rv[i] : 0.f;
-                lat[pt][r * 5 + i] = M::cvt(T);
+                const float rv = (m5 >> i) & 1 ? Rv[i] : 0.f;
                 rs += rv;
                 rmx = fmaxf(rmx, rv);
-                ts += T;
-                tmx = fmaxf(tmx, T);
-                if (DBG && p < npts) {
-                    A.dbg_tbar[(p * kLayers + k) * kSites + r * 5 + i] = T;
-                    A.dbg_rho[(p * kLayers + k) * kSites + r * 5 + i] = rv;
-                }
+                if (DBG && p < npts) A.dbg_rho[(p * kLayers + k) * kSites + r * 5 + i] = rv;
             }
-            part[R][0] = rs;
-            part[R][1] = rmx;
-            part[R][2] = ts;
-            part[R][3] = tmx;
         }
-        };
-        if (small) {
-            const float* sD = small_lvl;
-            const float* sR = small_lvl + dsize;
-            gather([&](int o) { return sD[o]; }, [&](int o) { return sR[o]; });
-        } else {
-            const __amdgpu_buffer_rsrc_t rD =
-                __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(mv.D + lv.d_off), 0, dsize * 4, kBufferFlags);
-            const __amdgpu_buffer_rsrc_t rR =
-                __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(mv.rho + lv.rho_off), 0, rsize * 4, kBufferFlags);
-            gather([&](int o) { return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rD, o * 4, 0, 0)); },
-                   [&](int o) { return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rR, o * 4, 0, 0)); });
-        }
-        __syncthreads();
 
-        // ---- per-point statistics (eq. 24) ----------------------------------------
-        if (tid < kTP * 4) {
-            const int pt = tid / 4, s = tid % 4;
-            float v = s & 1 ? -INFINITY : 0.f;
-            for (int r = 0; r < kRows; r++) v = s & 1 ? fmaxf(v, part[pt * kRows + r][s]) : v + part[pt * kRows + r][s];
-            const int slot = s == 0 ? 0 : s == 1 ? 3 : s == 2 ? 2 : 5;
-            pstat[pt][slot] = s & 1 ? v : v / kSites;
-        } else if (tid < kTP * 5) {
-            const int pt = tid - kTP * 4;
+        // ---- per-point statistics (eq. 24) over the point's 16 lanes ------------
+        for (int o = 1; o < 16; o <<= 1) {
+            rs += __shfl_xor(rs, o);
+            ts += __shfl_xor(ts, o);
+            rmx = fmaxf(rmx, __shfl_xor(rmx, o));
+            tmx = fmaxf(tmx, __shfl_xor(tmx, o));
+        }
+        if (lr == 0) {
+            pstat[pt][0] = rs / kSites;
+            pstat[pt][2] = ts / kSites;
+            pstat[pt][3] = rmx;
+            pstat[pt][5] = tmx;
+        } else if (lr == 1) {
             pstat[pt][1] = pfix[pt][0];
             pstat[pt][4] = pfix[pt][1];
             pstat[pt][6] = mv.g;
             pstat[pt][7] = pfix[pt][2];
         }
+        __syncthreads();
 
-        // ---- conv1: out^T [8 ch x 16 positions] = W1 [8 x 27] . im2col [27 x 16]
+        // ---- conv1, two points per MFMA tile: out^T [16 x 16 positions] =
+        // [W1 on K 0..35 | W1 on K 36..71] . [im2col of point tp0 ; of tp0 + 1]
+        // (rows 0-7: tp0's 8 channels, rows 8-15: tp0 + 1's)
         {
-            const E* w1 = reinterpret_cast<const E*>(A.w1t[grp]);
-            const float* b1 = A.cb[grp];
-            typename M::frag aw[kConv1K / M::KS];
+            float bias[4];
 #pragma unroll
-            for (int kc = 0; kc < kConv1K / M::KS; kc++)
-                aw[kc] = M::load(w1 + lr * kConv1K + kc * M::KS + lg * M::KPL);
-            for (int tile = wave; tile < kTP * 4; tile += 4) {
-                const int pt = tile >> 2, pos = (tile & 3) * 16 + lr;
-                const int base = pos < 63 ? (pos / 9) * 25 + ((pos / 3) % 3) * 5 + pos % 3 : 0;
-                const E* L = lat[pt] + base;
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            for (int e = 0; e < 4; e++) bias[e] = cbl[(lg & 1) * 4 + e];
+            // BF16: lane group lg reads the 4-slot groups g = kc*8 + 2lg + h of K
+            // step kc; group g < 9 is tap-row g of tp0, 9 <= g < 18 tap-row g - 9
+            // of tp0 + 1, the rest is zero
+            int goff[3][2];
 #pragma unroll
-                for (int kc = 0; kc < kConv1K / M::KS; kc++) {
-                    auto get = [&](int kk) -> E {
-                        const int o = tapoff[kk - lg * M::KPL - kc * M::KS + kc * M::KPL];
-                        return o >= 0 ? L[o] : M::zero();
-                    };
-                    acc = M::mma(aw[kc], M::gather(get, kc * M::KS + lg * M::KPL), acc);
+            for (int kc = 0; kc < 3; kc++)
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const int g = kc * 8 + 2 * (ln >> 4) + h;
+                    goff[kc][h] = g < 18 ? (g >= 9 ? kLatStride : 0) + taprow_off(g % 9) : -1;
                 }
-                if (lg < 2 && pos < 63) {
+#pragma unroll 2
+            for (int tile = 0; tile < kTP * 2; tile++) {
+                const int tp0 = (tile >> 2) * 2, pos = (tile & 3) * 16 + lrl;
+                const int pc = pos < 63 ? pos : 62;
+                const int zp = pc / 9, yp = (pc / 3) % 3, xp = pc % 3;
+                const E* base = lat[tp0] + (zp * 5 + yp) * kLatRow + xp * 4;
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                if constexpr (PREC == kPrecFP32) {
+                    // K step kc is the 4-slot group kc: tap-row kc % 9 of point tp0 + kc / 9
 #pragma unroll
-                    for (int e = 0; e < 4; e++) y1[pt][pos][lg * 4 + e] = M::cvt(fmaxf(acc[e] + b1[lg * 4 + e], 0.f));
+                    for (int kc = 0; kc < KC1; kc++)
+                        acc = M::mma(aw[kc], base[(kc >= 9 ? kLatStride : 0) + taprow_off(kc % 9) + lg], acc);
+                } else {
+                    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+                    for (int kc = 0; kc < KC1; kc++) {
+                        u32x4 bv = {0u, 0u, 0u, 0u};
+#pragma unroll
+                        for (int h = 0; h < 2; h++)
+                            if (goff[kc][h] >= 0) {
+                                const uint2 r = *reinterpret_cast<const uint2*>(base + goff[kc][h]);
+                                bv[2 * h] = r.x;
+                                bv[2 * h + 1] = r.y;
+                            }
+                        acc = M::mma(aw[kc], __builtin_bit_cast(bf16x8, bv), acc);
+                    }
+                }
+                if (pos < 63) {
+                    float v[4];
+#pragma unroll
+                    for (int e = 0; e < 4; e++) v[e] = fmaxf(acc[e] + bias[e], 0.f);
+                    E* dst = &y1[tp0 + (lg >> 1)][pos][(lg & 1) * 4];
+                    if constexpr (PREC == kPrecFP32) {
+                        *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+                    } else {
+                        *reinterpret_cast<uint2*>(dst) = make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
+                    }
                 }
             }
         }
@@ -476,40 +634,43 @@ k_features(FeatArgs A)
         // ---- conv2: [rows = (point, z)] x [K = 27 taps x 8 channels] x [16 channels]
         {
             const E* w2 = reinterpret_cast<const E*>(A.w2t[grp]);
-            const float* b2 = A.cb[grp] + 8;
-            for (int tile = wave; tile < kTP * 5 / 16; tile += 4) {
-                const int row = tile * 16 + lr;
-                const int pt = row / 5, z = row % 5;
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            const float* b2 = cbl + 8;
+            constexpr int KC2 = kConv2K / M::KS;
+            // BF16: the layer's 7 weight fragments stay in registers for both tiles
+            typename M::frag bw[M::KPL == 8 ? KC2 : 1];
+            if constexpr (M::KPL == 8) {
 #pragma unroll
-                for (int kc = 0; kc < kConv2K / M::KS; kc++) {
+                for (int kc = 0; kc < KC2; kc++) bw[kc] = M::load(w2 + lr * kConv2K + kc * M::KS + lg * M::KPL);
+            }
+            for (int tile = 0; tile < 2; tile++) {
+                const int row = tile * 16 + lrl;
+                const int rc = row < kTP * 5 ? row : kTP * 5 - 1;
+                const int tp = rc / 5, z = rc % 5;
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+                for (int kc = 0; kc < KC2; kc++) {
                     const int k0 = kc * M::KS + lg * M::KPL;     // K index = tap * 8 + channel
-                    typename M::frag a;
+                    const int tap = k0 >> 3 < 27 ? k0 >> 3 : 0;
                     if constexpr (M::KPL == 8) {
-                        const int tap = k0 >> 3 < 27 ? k0 >> 3 : 0;
-                        const int pos = z * 9 + tap;
-                        a = M::load(&y1[pt][pos][0]);
+                        acc = M::mma(M::load(&y1[tp][z * 9 + tap][0]), bw[kc], acc);
                     } else {
-                        const int tap = k0 >> 3 < 27 ? k0 >> 3 : 0;
-                        a = y1[pt][z * 9 + tap][k0 & 7];
+                        acc = M::mma(y1[tp][z * 9 + tap][k0 & 7], M::load(w2 + lr * kConv2K + k0), acc);
                     }
-                    typename M::frag b = M::load(w2 + lr * kConv2K + k0);
-                    acc = M::mma(a, b, acc);
                 }
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
-                    int row2 = tile * 16 + lg * 4 + e;
-                    H[row2 / 5][lr][row2 % 5] = fmaxf(acc[e] + b2[lr], 0.f);
+                    const int row2 = tile * 16 + lg * 4 + e;
+                    if (row2 < kTP * 5) H[row2 / 5][lr][row2 % 5] = fmaxf(acc[e] + b2[lr], 0.f);
                 }
             }
         }
         __syncthreads();
 
-        // ---- squeeze-excitation gate
+        // ---- squeeze-excitation gate and the layer's descriptor entries ---------
         {
-            const float* cb = A.cb[grp];
+            const float* cb = cbl;
             const float *s1 = cb + 24, *c1 = cb + 88, *s2 = cb + 92, *c2 = cb + 156;
-            const int pt = tid / 16, o = tid % 16;
+            const int o = lr;
             zc[pt][o] = (H[pt][o][0] + H[pt][o][1] + H[pt][o][2] + H[pt][o][3] + H[pt][o][4]) / 5.f;
             __syncthreads();
             if (o < 4) {
@@ -520,39 +681,46 @@ k_features(FeatArgs A)
             __syncthreads();
             float s = c2[o];
             for (int h = 0; h < 4; h++) s += s2[o * 4 + h] * hid[pt][h];
-            gate[pt][o] = 1.f / (1.f + expf(-s));
-            // descriptor entries of layer k: 5 features of channel o, and stat o
-            const int64_t pp = tile0 + pt;
+            const float gate = 1.f / (1.f + expf(-s));
+            // stage the 88 entries of the layer in the (now free) conv1 output
+            E* stage = &y1[pt][0][0];
             float lmax = 0.f;
-            E q[6];
 #pragma unroll
             for (int z = 0; z < 5; z++) {
-                q[z] = M::cvt(gate[pt][o] * H[pt][o][z]);
-                lmax = fmaxf(lmax, fabsf((float)q[z]));
+                const E qz = M::cvt(gate * H[pt][o][z]);
+                stage[o * 5 + z] = qz;
+                lmax = fmaxf(lmax, fabsf((float)qz));
             }
-            q[5] = M::cvt(o < kStats ? pstat[pt][o] : 0.f);
-            lmax = fmaxf(lmax, fabsf((float)q[5]));
-            if (pp < npts) {
-                E* d = desc + pp * kDescPad + k * kPerLayer;
-#pragma unroll
-                for (int z = 0; z < 5; z++) d[o * 5 + z] = q[z];
-                if (o < kStats) d[kFeat + o] = q[5];
-                if (DBG && o < kStats) A.dbg_stats[(pp * kLayers + k) * kStats + o] = pstat[pt][o];
+            if (o < kStats) {
+                const E qs = M::cvt(pstat[pt][o]);
+                stage[kFeat + o] = qs;
+                lmax = fmaxf(lmax, fabsf((float)qs));
             }
-            // running maximum |entry| of the point's stored descriptor (the 16
-            // threads of a point are 16 consecutive lanes of one wave)
-            for (int s = 1; s < 16; s <<= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, s));
+            if (DBG && o < kStats && tile0 + pt < npts)
+                A.dbg_stats[((tile0 + pt) * kLayers + k) * kStats + o] = pstat[pt][o];
+            // running maximum |entry| of the point's stored descriptor
+            for (int sft = 1; sft < 16; sft <<= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, sft));
             row_absmax = fmaxf(row_absmax, lmax);
+            __syncthreads();
+            // 16-byte stores of the staged rows (88 entries per point)
+            constexpr int kVec = 16 / sizeof(E), kChunks = kPerLayer / kVec;
+            for (int e = lane; e < kTP * kChunks; e += 64) {
+                const int tq = e / kChunks, ch = e % kChunks;
+                const int64_t pp = tile0 + tq;
+                if (pp < npts)
+                    *reinterpret_cast<uint4*>(desc + pp * kDescPad + k * kPerLayer + ch * kVec) =
+                        *reinterpret_cast<const uint4*>(&y1[tq][0][0] + ch * kVec);
+            }
         }
     }
     // albedo entry and zero padding
-    for (int e = tid; e < kTP * (kDescPad - kDesc + 1); e += 256) {
-        const int pt = e / (kDescPad - kDesc + 1), f = kDesc - 1 + e % (kDescPad - kDesc + 1);
-        const int64_t pp = tile0 + pt;
+    for (int e = lane; e < kTP * (kDescPad - kDesc + 1); e += 64) {
+        const int tq = e / (kDescPad - kDesc + 1), f = kDesc - 1 + e % (kDescPad - kDesc + 1);
+        const int64_t pp = tile0 + tq;
         if (pp < npts) desc[pp * kDescPad + f] = M::cvt(f == kDesc - 1 ? mv.albedo : 0.f);
     }
-    if (A.rowmax && tid % 16 == 0 && tile0 + tid / 16 < npts)
-        A.rowmax[tile0 + tid / 16] = fmaxf(row_absmax, fabsf((float)M::cvt(mv.albedo)));
+    if (A.rowmax && lr == 0 && tile0 + lg < npts)
+        A.rowmax[tile0 + lg] = fmaxf(row_absmax, fabsf((float)M::cvt(mv.albedo)));
 }
 
 // Widen a descriptor of the given precision to float32 [n][1057].
@@ -579,17 +747,18 @@ hipError_t launch_desc_to_f32(int prec, const void* src, float* dst, int64_t n, 
 hipError_t launch_features(int prec, const FeatArgs& a, hipStream_t s)
 {
     if (a.npts <= 0) return hipSuccess;
-    const int blocks = (int)((a.npts + kTP - 1) / kTP);
+    const int64_t blocks = ((a.npts + kTP - 1) / kTP + kXcds - 1) / kXcds * kXcds;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     const bool dbg = a.dbg_tbar || a.dbg_rho || a.dbg_phi || a.dbg_stats || a.dbg_tp;
     if (dbg && !(a.dbg_tbar && a.dbg_rho && a.dbg_phi && a.dbg_stats && a.dbg_tp))
         return hipErrorInvalidValue;   // the debug variant writes every stage output
     // the FP8 path runs the CNN and stores the descriptor in BF16
     if (prec == kPrecBF16 || prec == kPrecFP8) {
-        if (dbg) hipLaunchKernelGGL((k_features<kPrecBF16, true>), dim3(blocks), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_features<kPrecBF16, false>), dim3(blocks), dim3(256), 0, s, a);
+        if (dbg) hipLaunchKernelGGL((k_features<kPrecBF16, true>), dim3((int)blocks), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_features<kPrecBF16, false>), dim3((int)blocks), dim3(64), 0, s, a);
     } else {
-        if (dbg) hipLaunchKernelGGL((k_features<kPrecFP32, true>), dim3(blocks), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_features<kPrecFP32, false>), dim3(blocks), dim3(256), 0, s, a);
+        if (dbg) hipLaunchKernelGGL((k_features<kPrecFP32, true>), dim3((int)blocks), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_features<kPrecFP32, false>), dim3((int)blocks), dim3(64), 0, s, a);
     }
     return hipGetLastError();
 }

@@ -250,7 +250,15 @@ void pack_net(Net* net, int prec)
         const float *s1 = b2 + 16, *c1 = s1 + 64, *s2 = c1 + 4, *c2 = s2 + 64;
         std::vector<float> t1(16 * kConv1K, 0.f), t2(16 * kConv2K, 0.f);
         for (int o = 0; o < 8; o++)
-            for (int k = 0; k < 27; k++) t1[o * kConv1K + k] = w1[o * 27 + k];
+            // K index = tap-row (dz * 3 + dy) * 4 + dx; the fourth slot of each
+            // tap-row is zero.  Rows 8-15 repeat rows 0-7 shifted to K 36..71, so
+            // one MFMA tile convolves two points (the kernel puts the second
+            // point's im2col on K 36..71); K >= 72 is zero.
+            for (int tr = 0; tr < 9; tr++)
+                for (int dx = 0; dx < 3; dx++) {
+                    t1[o * kConv1K + tr * 4 + dx] = w1[o * 27 + tr * 3 + dx];
+                    t1[(o + 8) * kConv1K + 36 + tr * 4 + dx] = w1[o * 27 + tr * 3 + dx];
+                }
         // conv2 K order is tap-major (k = tap * 8 + input channel), matching the
         // channels-fastest layout of the conv1 output the kernel reads
         for (int o = 0; o < 16; o++)

@@ -17,7 +17,7 @@ constexpr int kDesc = kLayers * kPerLayer + 1;   // 1057
 constexpr int kDescPad = 1088;    // row stride of the descriptor (multiple of 64)
 constexpr int kMaxLevels = 11;    // 1024^3 .. 1^3
 constexpr int kMaxWidth = 256;    // backbone width limit
-constexpr int kConv1K = 32;       // 27 taps padded
+constexpr int kConv1K = 96;       // two points x 9 tap-rows x 4 (3 taps + a zero), padded to the MFMA step
 constexpr int kConv2K = 224;      // 8 channels x 27 taps padded
 constexpr int kPrecFP32 = 0, kPrecBF16 = 1, kPrecFP8 = 2;
 
