@@ -87,6 +87,7 @@ template <class E> struct FeatShared {
     PointLayer pl[kTP];
     SlabParams sp[kTP][9];
     float cb[kCbFloats];                       // the group's conv biases and attention weights
+    uint16_t smask[kTP][kLayers][9];           // in-cube bits of every slab of every layer
 };
 
 __device__ __forceinline__ double site_coord(double x, double scale, double qo, int i)
@@ -203,6 +204,7 @@ k_features(FeatArgs A)
     float(*brick)[kBrickJ * kBrickV * kBrickU] = sh.u1.brick;
     SlabParams(*sp)[9] = sh.sp;
     float* cbl = sh.cb;
+    uint16_t(*smask)[kLayers][9] = sh.smask;
     float(*H)[16][5] = sh.u0.se.H;
     float(*zc)[16] = sh.u0.se.zc;
     float(*hid)[4] = sh.u0.se.hid;
@@ -257,6 +259,23 @@ k_features(FeatArgs A)
         for (int o = 1; o < 16; o <<= 1) {
             phs += __shfl_xor(phs, o);
             phm = fmaxf(phm, __shfl_xor(phm, o));
+        }
+        // in-cube bits of the sites of every slab of every layer (bits 0-4: i
+        // along b, 5-9: j along c, 10: the slab along a), decided on the
+        // double-precision site positions
+        for (int e = sub; e < kLayers * 9; e += 16) {
+            const int kk = e / 9, qi = e % 9;
+            const double scale = ldexp(1.0 / mv.n0, kk);
+            int mask = 0;
+            const double sa = site_coord_a(x[mv.a], scale, mv.qoff[mv.a][qi]);
+            if (sa >= 0.0 && sa <= 1.0) mask |= 1 << 10;
+            for (int i = -2; i <= 2; i++) {
+                const double sb = site_coord(x[mv.b], scale, mv.qoff[mv.b][qi], i);
+                const double sc = site_coord(x[mv.c], scale, mv.qoff[mv.c][qi], i);
+                if (sb >= 0.0 && sb <= 1.0) mask |= 1 << (i + 2);
+                if (sc >= 0.0 && sc <= 1.0) mask |= 1 << (i + 7);
+            }
+            smask[pt][kk][qi] = (uint16_t)mask;
         }
         if (sub == 0) {
             pfix[pt][0] = phs / kSites;
@@ -315,15 +334,7 @@ k_features(FeatArgs A)
         if (ln < kTP * 9) {
             const int spt = ln / 9, qi = ln % 9;
             const double x[3] = {px[spt][0], px[spt][1], px[spt][2]};
-            int mask = 0;
-            const double sa = site_coord_a(x[mv.a], scale, mv.qoff[mv.a][qi]);
-            if (sa >= 0.0 && sa <= 1.0) mask |= 1 << 10;
-            for (int i = -2; i <= 2; i++) {
-                const double sb = site_coord(x[mv.b], scale, mv.qoff[mv.b][qi], i);
-                const double sc = site_coord(x[mv.c], scale, mv.qoff[mv.c][qi], i);
-                if (sb >= 0.0 && sb <= 1.0) mask |= 1 << (i + 2);
-                if (sc >= 0.0 && sc <= 1.0) mask |= 1 << (i + 7);
-            }
+            const int mask = smask[spt][k][qi];
             const double gb = x[mv.b] * nm - 0.5 + c * mv.qoff[mv.b][qi];
             const double gc = x[mv.c] * nm - 0.5 + c * mv.qoff[mv.c][qi];
             const double ga = x[mv.a] * nm - 0.5;
@@ -571,6 +582,16 @@ k_features(FeatArgs A)
         }
         __syncthreads();
 
+        // conv2's weight fragments (BF16: all 7 stay in registers for both of
+        // its tiles) are requested now, so that their latency overlaps conv1
+        constexpr int KC2 = kConv2K / M::KS;
+        typename M::frag bw[M::KPL == 8 ? KC2 : 1];
+        const E* w2 = reinterpret_cast<const E*>(A.w2t[grp]);
+        if constexpr (M::KPL == 8) {
+#pragma unroll
+            for (int kc = 0; kc < KC2; kc++) bw[kc] = M::load(w2 + lr * kConv2K + kc * M::KS + lg * M::KPL);
+        }
+
         // ---- conv1, two points per MFMA tile: out^T [16 x 16 positions] =
         // [W1 on K 0..35 | W1 on K 36..71] . [im2col of point tp0 ; of tp0 + 1]
         // (rows 0-7: tp0's 8 channels, rows 8-15: tp0 + 1's)
@@ -603,6 +624,9 @@ k_features(FeatArgs A)
                         acc = M::mma(aw[kc], base[(kc >= 9 ? kLatStride : 0) + taprow_off(kc % 9) + lg], acc);
                 } else {
                     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+                    // independent accumulators per K step, so the three MFMAs
+                    // issue back to back
+                    f32x4 part[KC1];
 #pragma unroll
                     for (int kc = 0; kc < KC1; kc++) {
                         u32x4 bv = {0u, 0u, 0u, 0u};
@@ -613,8 +637,10 @@ k_features(FeatArgs A)
                                 bv[2 * h] = r.x;
                                 bv[2 * h + 1] = r.y;
                             }
-                        acc = M::mma(aw[kc], __builtin_bit_cast(bf16x8, bv), acc);
+                        part[kc] = M::mma(aw[kc], __builtin_bit_cast(bf16x8, bv), acc);
                     }
+#pragma unroll
+                    for (int kc = 0; kc < KC1; kc++) acc += part[kc];
                 }
                 if (pos < 63) {
                     float v[4];
@@ -633,15 +659,8 @@ k_features(FeatArgs A)
 
         // ---- conv2: [rows = (point, z)] x [K = 27 taps x 8 channels] x [16 channels]
         {
-            const E* w2 = reinterpret_cast<const E*>(A.w2t[grp]);
             const float* b2 = cbl + 8;
-            constexpr int KC2 = kConv2K / M::KS;
-            // BF16: the layer's 7 weight fragments stay in registers for both tiles
-            typename M::frag bw[M::KPL == 8 ? KC2 : 1];
-            if constexpr (M::KPL == 8) {
 #pragma unroll
-                for (int kc = 0; kc < KC2; kc++) bw[kc] = M::load(w2 + lr * kConv2K + kc * M::KS + lg * M::KPL);
-            }
             for (int tile = 0; tile < 2; tile++) {
                 const int row = tile * 16 + lrl;
                 const int rc = row < kTP * 5 ? row : kTP * 5 - 1;
