@@ -193,7 +193,7 @@ template <> __device__ __forceinline__ void store_windows<__bf16>(__bf16* row, c
 __device__ __forceinline__ int taprow_off(int tr) { return ((tr / 3) * 5 + tr % 3) * kLatRow; }
 
 template <int PREC, bool DBG>
-__global__ void __launch_bounds__(64, 4)
+__global__ void __launch_bounds__(64, 3)
 k_features(FeatArgs A)
 {
     typedef Mfma<PREC> M;
@@ -307,11 +307,8 @@ k_features(FeatArgs A)
         const Level lv = mv.lev[m];
         const int nm = lv.n;
         const int c = 1 << (k - m);
-        const double scale = ldexp(1.0 / mv.n0, k);
         const float coef = A.coef[k];
         const int grp = k < kDiffuse ? 0 : 1;
-        const int st[3] = {1, nm, nm * nm};
-        const int sta = st[mv.a], stb = st[mv.b], stc = st[mv.c];
         const int plane = lv.nu * lv.nv;
         const int dsize = plane * nm, rsize = nm * nm * nm;
         const __amdgpu_buffer_rsrc_t rD =
@@ -380,37 +377,49 @@ k_features(FeatArgs A)
         // loads of all its rows are issued before the first store.  The
         // single-voxel level (c > 1) is one 3 x 3 slice, copied whole.
         if (c == 1) {
-            constexpr int kDRows = kTP * kBrickJ * kBrickV, kDIt = (kDRows + 63) / 64;
+            // two V rows at a time from the path-density pairs: a pair row is 6
+            // pairs, 48 contiguous bytes
+            const __amdgpu_buffer_rsrc_t rQ = __builtin_amdgcn_make_buffer_rsrc(
+                mv.dpairs + lv.q_off, 0, (lv.nv + 1) * lv.nu * nm * 8, kBufferFlags);
+            auto ldQ = [&](int o) { return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rQ, o * 4, 0, 0)); };
+            constexpr int kDPairs = kTP * kBrickJ * (kBrickV / 2), kDIt = (kDPairs + 63) / 64;
+            float dv[kDIt][12];
 #pragma unroll
-            for (int it0 = 0; it0 < kDIt; it0 += 2) {
-                float dv[2][6];
+            for (int it = 0; it < kDIt; it++) {
+                const int rr = ln + 64 * it;
+                if (rr < kDPairs) {
+                    const int bp = rr / (kBrickJ * 3), loc = rr % (kBrickJ * 3);
+                    const PointLayer Q = pl[bp];
+                    const int J = Q.ij - 4 + loc / 3;
+                    const int Vp = clampi(Q.iv - 1 + 2 * (loc % 3) - lv.vlo, 0, lv.nv);
+                    const int U0 = Q.iu - 2 - lv.ulo;
+                    if (J >= 0 && J < nm && U0 >= 0 && U0 + 5 < lv.nu) {
+                        const int o = ((J * (lv.nv + 1) + Vp) * lv.nu + U0) * 2;
 #pragma unroll
-                for (int h = 0; h < 2; h++) {
-                    const int rr = ln + 64 * (it0 + h);
-                    if (rr < kDRows) {
-                        const int bp = rr / (kBrickJ * kBrickV), loc = rr % (kBrickJ * kBrickV);
-                        const PointLayer Q = pl[bp];
-                        const int J = Q.ij - 4 + loc / kBrickV, V = Q.iv - 2 + loc % kBrickV - lv.vlo;
-                        const int U0 = Q.iu - 2 - lv.ulo;
-                        if (J >= 0 && J < nm && V >= 0 && V < lv.nv && U0 >= 0 && U0 + 5 < lv.nu) {
-                            const int o = (J * lv.nv + V) * lv.nu + U0;
+                        for (int e = 0; e < 12; e++) dv[it][e] = ldQ(o + e);
+                    } else {
+                        const int ro = (clampi(J, 0, nm - 1) * (lv.nv + 1) + Vp) * lv.nu;
 #pragma unroll
-                            for (int u = 0; u < 6; u++) dv[h][u] = ldD(o + u);
-                        } else {
-                            const int jo = clampi(J, 0, nm - 1) * plane + clampi(V, 0, lv.nv - 1) * lv.nu;
-#pragma unroll
-                            for (int u = 0; u < 6; u++) dv[h][u] = ldD(jo + clampi(U0 + u, 0, lv.nu - 1));
+                        for (int u = 0; u < 6; u++) {
+                            const int o = (ro + clampi(U0 + u, 0, lv.nu - 1)) * 2;
+                            dv[it][2 * u] = ldQ(o);
+                            dv[it][2 * u + 1] = ldQ(o + 1);
                         }
                     }
                 }
+            }
 #pragma unroll
-                for (int h = 0; h < 2; h++) {
-                    const int rr = ln + 64 * (it0 + h);
-                    if (rr < kDRows) {
-                        float2* dst = reinterpret_cast<float2*>(&brick[0][0] + rr * kBrickU);
-                        dst[0] = make_float2(dv[h][0], dv[h][1]);
-                        dst[1] = make_float2(dv[h][2], dv[h][3]);
-                        dst[2] = make_float2(dv[h][4], dv[h][5]);
+            for (int it = 0; it < kDIt; it++) {
+                const int rr = ln + 64 * it;
+                if (rr < kDPairs) {
+                    // the pair row holds brick rows bv = 2 (loc % 3) and bv + 1,
+                    // which are adjacent in the brick
+                    const int bp = rr / (kBrickJ * 3), loc = rr % (kBrickJ * 3);
+                    float2* dst = reinterpret_cast<float2*>(&brick[bp][(loc / 3 * kBrickV + 2 * (loc % 3)) * kBrickU]);
+#pragma unroll
+                    for (int e = 0; e < 3; e++) {
+                        dst[e] = make_float2(dv[it][4 * e], dv[it][4 * e + 2]);
+                        dst[3 + e] = make_float2(dv[it][4 * e + 1], dv[it][4 * e + 3]);
                     }
                 }
             }
@@ -473,13 +482,18 @@ k_features(FeatArgs A)
 
         // ---- density bricks: for each point and slab the rows c = cbase..+5 of
         // 6 samples b = bbase..+5, interpolated between a = ia and ia+1 while
-        // loading (the a weight is shared by the slab's 25 sites).  One lane
-        // per row pair; loads are issued two row pairs at a time.
+        // loading (the a weight is shared by the slab's 25 sites).  The two
+        // a-planes come side by side from the light-axis pairs: a row is 6
+        // pairs, 48 contiguous bytes.  One lane per row; loads are issued two
+        // rows at a time.
         if (nm > 1) {
+            const __amdgpu_buffer_rsrc_t rP = __builtin_amdgcn_make_buffer_rsrc(
+                mv.pairs + lv.p_off, 0, (nm + 1) * nm * nm * 8, kBufferFlags);
+            auto ldP = [&](int o) { return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rP, o * 4, 0, 0)); };
             constexpr int kRRows = kTP * 9 * kBrickV, kRIt = (kRRows + 63) / 64;
 #pragma unroll
             for (int it0 = 0; it0 < kRIt; it0 += 2) {
-                float r0v[2][6], r1v[2][6], wav[2];
+                float pr[2][12], wav[2];
 #pragma unroll
                 for (int h = 0; h < 2; h++) {
                     const int rr = ln + 64 * (it0 + h);
@@ -487,23 +501,19 @@ k_features(FeatArgs A)
                     if (rr < kRRows) {
                         const int bp = rr / (9 * kBrickV), loc = rr % (9 * kBrickV);
                         const SlabParams S = sp[bp][loc / kBrickV];
-                        const int C = S.cbase + loc % kBrickV, B0 = S.bbase;
+                        const int Ap = clampi(S.ia + 1, 0, nm), C = S.cbase + loc % kBrickV, B0 = S.bbase;
                         wav[h] = S.wa;
-                        if (S.ia >= 0 && S.ia + 1 < nm && C >= 0 && C < nm && B0 >= 0 && B0 + 5 < nm && stb == 1) {
-                            const int o = S.ia * sta + C * stc + B0;
+                        if (C >= 0 && C < nm && B0 >= 0 && B0 + 5 < nm) {
+                            const int o = ((Ap * nm + C) * nm + B0) * 2;
 #pragma unroll
-                            for (int u = 0; u < 6; u++) {
-                                r0v[h][u] = ldR(o + u);
-                                r1v[h][u] = ldR(o + sta + u);
-                            }
+                            for (int e = 0; e < 12; e++) pr[h][e] = ldP(o + e);
                         } else {
-                            const int a0 = clampi(S.ia, 0, nm - 1) * sta + clampi(C, 0, nm - 1) * stc;
-                            const int a1 = clampi(S.ia + 1, 0, nm - 1) * sta + clampi(C, 0, nm - 1) * stc;
+                            const int ro = (Ap * nm + clampi(C, 0, nm - 1)) * nm;
 #pragma unroll
                             for (int u = 0; u < 6; u++) {
-                                const int bo = clampi(B0 + u, 0, nm - 1) * stb;
-                                r0v[h][u] = ldR(a0 + bo);
-                                r1v[h][u] = ldR(a1 + bo);
+                                const int o = (ro + clampi(B0 + u, 0, nm - 1)) * 2;
+                                pr[h][2 * u] = ldP(o);
+                                pr[h][2 * u + 1] = ldP(o + 1);
                             }
                         }
                     }
@@ -516,8 +526,8 @@ k_features(FeatArgs A)
                         float2* dst = reinterpret_cast<float2*>(&brick[bp][loc * kBrickU]);
 #pragma unroll
                         for (int e = 0; e < 3; e++)
-                            dst[e] = make_float2(lerpf(r0v[h][2 * e], r1v[h][2 * e], wav[h]),
-                                                 lerpf(r0v[h][2 * e + 1], r1v[h][2 * e + 1], wav[h]));
+                            dst[e] = make_float2(lerpf(pr[h][4 * e], pr[h][4 * e + 1], wav[h]),
+                                                 lerpf(pr[h][4 * e + 2], pr[h][4 * e + 3], wav[h]));
                     }
                 }
             }

@@ -119,6 +119,63 @@ __global__ void k_site_tables(MediumView mv, SiteTables* tab)
     tab->hg_dl[t] = (float)(mv.hg_k / (den * sqrt(den)));
 }
 
+// Light-axis density pairs (a layout of the pyramid for the gather): for each
+// level, entry (A', c, b), A' = 0..n, holds the densities at a = A'-1 and
+// a = A' along the light's dominant axis, each index clamped into [0, n-1],
+// stored with b fastest; so the two a-planes of a density row sit side by
+// side and a row of 6 pairs is 48 contiguous bytes whatever the light.
+__global__ void __launch_bounds__(256)
+k_pairs(const float* __restrict__ rho, float2* __restrict__ out, int n, int a, int b, int c)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)(n + 1) * n * n) return;
+    const int bb = (int)(i % n), cc = (int)((i / n) % n), ap = (int)(i / ((int64_t)n * n));
+    const int a0 = ap - 1 < 0 ? 0 : ap - 1, a1 = ap > n - 1 ? n - 1 : ap;
+    int p0[3], p1[3];
+    p0[a] = a0, p1[a] = a1;
+    p0[b] = p1[b] = bb;
+    p0[c] = p1[c] = cc;
+    out[i] = make_float2(rho[((int64_t)p0[2] * n + p0[1]) * n + p0[0]], rho[((int64_t)p1[2] * n + p1[1]) * n + p1[0]]);
+}
+
+hipError_t launch_pairs(const MediumView& mv, hipStream_t s)
+{
+    for (int m = 0; m < mv.levels; m++) {
+        const Level& lv = mv.lev[m];
+        const int64_t total = (int64_t)(lv.n + 1) * lv.n * lv.n;
+        const int blocks = (int)((total + 255) / 256);
+        hipLaunchKernelGGL(k_pairs, dim3(blocks), dim3(256), 0, s, mv.rho + lv.rho_off, mv.pairs + lv.p_off, lv.n,
+                           mv.a, mv.b, mv.c);
+    }
+    return hipGetLastError();
+}
+
+// Path-density pairs along V (a layout of D for the gather): entry (J, V', U),
+// V' = 0..nv, holds D at V = V'-1 and V = V', each index clamped into
+// [0, nv-1], so two neighbouring V rows of a brick are one contiguous run.
+__global__ void __launch_bounds__(256)
+k_dpairs(const float* __restrict__ D, float2* __restrict__ out, int n, int nv, int nu)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * (nv + 1) * nu) return;
+    const int u = (int)(i % nu), vp = (int)((i / nu) % (nv + 1)), j = (int)(i / ((int64_t)nu * (nv + 1)));
+    const int v0 = vp - 1 < 0 ? 0 : vp - 1, v1 = vp > nv - 1 ? nv - 1 : vp;
+    const float* row = D + (int64_t)j * nv * nu + u;
+    out[i] = make_float2(row[(int64_t)v0 * nu], row[(int64_t)v1 * nu]);
+}
+
+hipError_t launch_dpairs(const MediumView& mv, hipStream_t s)
+{
+    for (int m = 0; m < mv.levels; m++) {
+        const Level& lv = mv.lev[m];
+        const int64_t total = (int64_t)lv.n * (lv.nv + 1) * lv.nu;
+        const int blocks = (int)((total + 255) / 256);
+        hipLaunchKernelGGL(k_dpairs, dim3(blocks), dim3(256), 0, s, mv.D + lv.d_off, mv.dpairs + lv.q_off, lv.n, lv.nv,
+                           lv.nu);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_site_tables(const MediumView& mv, SiteTables* tab, hipStream_t s)
 {
     hipLaunchKernelGGL(k_site_tables, dim3(1), dim3(256), 0, s, mv, tab);

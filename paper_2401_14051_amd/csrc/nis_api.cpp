@@ -115,6 +115,8 @@ MediumView make_view(const Medium* M, const LightState* ls, const Params& P, con
     std::memset(&v, 0, sizeof(v));
     v.rho = M->rho.as<float>();
     v.D = ls->D.as<float>();
+    v.pairs = ls->P.as<float2>();
+    v.dpairs = ls->DP.as<float2>();
     for (int m = 0; m < M->levels; m++) v.lev[m] = ls->lev[m];
     v.levels = M->levels;
     v.n0 = M->n;
@@ -171,6 +173,8 @@ void ensure_sweep(const Medium* M, LightState* ls, hipStream_t s)
     if (!ls->stale && ls->swept_version == M->version) return;
     MediumView mv = make_view(M, ls, medium_params(M), nullptr);
     timed("sweep", s, [&] { return launch_sweep(mv, s); });
+    timed("pairs", s, [&] { return launch_pairs(mv, s); });
+    timed("dpairs", s, [&] { return launch_dpairs(mv, s); });
     ls->stale = false;
     ls->swept_version = M->version;
 }
@@ -382,7 +386,7 @@ void light_layout(const Medium* M, const double l[3], LightState* ls)
     ls->sc = l[ls->c] / ls->la;
     for (int d = 0; d < 3; d++)
         for (int qi = 0; qi < 9; qi++) ls->qoff[d][qi] = (qi - 4) * l[d] / ls->la;
-    int64_t off = 0;
+    int64_t off = 0, poff = 0, qoff = 0;
     for (int m = 0; m < M->levels; m++) {
         Level& lv = ls->lev[m];
         lv = M->lev[m];
@@ -392,18 +396,29 @@ void light_layout(const Medium* M, const double l[3], LightState* ls)
         lv.nu = uhi - lv.ulo + 1;
         lv.nv = vhi - lv.vlo + 1;
         lv.d_off = off;
+        lv.p_off = poff;
+        lv.q_off = qoff;
         lv.ds = (float)((1.0 / lv.n) / ls->la);
-        if ((int64_t)lv.nu * lv.nv * lv.n >= ((int64_t)1 << 31))
-            fail(NIS_E_UNSUPPORTED, "path-density field of one level exceeds 2^31 entries for this light");
-        off += (int64_t)lv.nu * lv.nv * lv.n;
+        // the gather addresses each level's fields with 32-bit byte offsets
+        const int64_t dn = (int64_t)lv.nu * lv.nv * lv.n, pn = (int64_t)(lv.n + 1) * lv.n * lv.n;
+        const int64_t qn = (int64_t)lv.nu * (lv.nv + 1) * lv.n;
+        if (qn * 8 >= ((int64_t)1 << 32) || pn * 8 >= ((int64_t)1 << 32) || (int64_t)lv.n * lv.n * lv.n * 4 >= ((int64_t)1 << 32))
+            fail(NIS_E_UNSUPPORTED, "a level's fields exceed 4 GiB for this light (media up to 512^3 are served)");
+        off += dn;
+        poff += pn;
+        qoff += qn;
     }
     ls->d_floats = off;
+    ls->pair_count = poff;
+    ls->dpair_count = qoff;
 }
 
 void set_light_state(const Medium* M, const double l[3], LightState* ls)
 {
     light_layout(M, l, ls);
     ls->D.reserve((size_t)ls->d_floats * sizeof(float), "path-density fields");
+    ls->P.reserve((size_t)ls->pair_count * sizeof(float2), "light-axis density pairs");
+    ls->DP.reserve((size_t)ls->dpair_count * sizeof(float2), "path-density pairs");
     ls->valid = true;
     ls->stale = true;
     ls->tab_valid = false;

@@ -70,15 +70,19 @@ struct LightState {
     double qoff[3][9] = {};
     Level lev[kMaxLevels] = {};             // medium's n and rho_off plus this light's ray ranges
     int64_t d_floats = 0;
-    DevBuf D, tab;
-    bool stale = true;                      // D must be recomputed
-    uint64_t swept_version = 0;             // pyramid version D was computed from
+    int64_t pair_count = 0;                 // light-axis density pairs of all levels
+    int64_t dpair_count = 0;                // path-density pairs of all levels
+    DevBuf D, P, DP, tab;
+    bool stale = true;                      // D, P and DP must be recomputed
+    uint64_t swept_version = 0;             // pyramid version they were computed from
     bool tab_valid = false;
     float tab_g = 0.f;                      // g the site tables were computed for
-    size_t bytes() const { return D.bytes + tab.bytes; }
+    size_t bytes() const { return D.bytes + P.bytes + DP.bytes + tab.bytes; }
     void release()
     {
         D.release();
+        P.release();
+        DP.release();
         tab.release();
         tab_valid = false;
         stale = true;
