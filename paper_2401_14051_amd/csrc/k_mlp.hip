@@ -247,6 +247,162 @@ k_mlp_fp8(MlpArgs A)
     }
 }
 
+// BF16 backbone with the weights as the MFMA A operand and the activations as
+// B.  A layer's output tile D[channel][point] leaves each lane holding 4
+// consecutive channels of one point, which after bias and ReLU are exactly the
+// lane's B fragment of the next layer once that layer's K index is permuted
+// to match: K slot s = kc*32 + g*8 + e (lane group g) is channel
+// (2 kc + e/4) * 16 + g * 4 + e % 4 (the weights are packed in that order).
+// So activations stay in registers from layer to layer.  A workgroup of 4
+// waves covers 256 points (4 tiles of 16 per wave); for every K step the
+// group stages the step's NT weight fragments (NT KiB) in LDS once, double
+// buffered, and all four waves read them there.  P point tiles of 16 per
+// wave (fewer for wide layers, whose accumulators and inputs must fit in the
+// register file).
+template <int NT, int P>
+__global__ void __launch_bounds__(256)
+k_mlp_bf16(MlpArgs A)
+{
+    typedef Mfma<kPrecBF16> M;
+    constexpr int KCH = hidden_k(kPrecBF16, NT * 16) / 32;
+    constexpr int KC0 = kDescPad / 32;
+    constexpr int BLK = NT * 64 * 8;           // bf16 elements of one K step's fragments
+    constexpr int CH = BLK / 8;                // their 16-byte chunks
+    constexpr int SJ = (CH + 255) / 256;
+    __shared__ __attribute__((aligned(16))) __bf16 abuf[2][BLK];
+
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, lr = lane % 16, lg = lane / 16;
+    const int64_t npts = A.count ? min(max((int64_t)*A.count - A.count_off, (int64_t)0), A.npts) : A.npts;
+    const int64_t wg0 = (int64_t)blockIdx.x * (4 * 16 * P);
+    if (wg0 >= npts) return;
+    const int64_t row0 = wg0 + wave * 16 * P;
+    const __bf16* x = reinterpret_cast<const __bf16*>(A.x);
+
+    // staging of one K step: chunk tid + 256 j, clamped to the last chunk (a
+    // clamped thread stores a copy of that chunk's own value)
+    struct Stage {
+        uint4 v[SJ];
+    };
+    auto stage_load = [&](const __bf16* src) __attribute__((always_inline)) {
+        Stage t;
+#pragma unroll
+        for (int j = 0; j < SJ; j++) t.v[j] = reinterpret_cast<const uint4*>(src)[min(tid + 256 * j, CH - 1)];
+        return t;
+    };
+    auto stage_store = [&](int b, Stage t) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < SJ; j++) reinterpret_cast<uint4*>(abuf[b])[min(tid + 256 * j, CH - 1)] = t.v[j];
+    };
+
+    f32x4 acc[NT][P];
+    bf16x8 hin[KCH][P];
+    for (int li = 0; li + 1 < A.n_linear; li++) {
+        const __bf16* Wl = reinterpret_cast<const __bf16*>(A.W[li]);
+        const int KC = li == 0 ? KC0 : KCH;
+#pragma unroll
+        for (int ct = 0; ct < NT; ct++)
+#pragma unroll
+            for (int p = 0; p < P; p++) acc[ct][p] = f32x4{0.f, 0.f, 0.f, 0.f};
+        stage_store(0, stage_load(Wl));
+        __syncthreads();
+        // K step kc from buffer kc & 1 while the next step's fragments are
+        // fetched (past the last step: the last again, into the idle buffer)
+        auto step = [&](int kc, const bf16x8* bx) __attribute__((always_inline)) {
+            const int b = kc & 1;
+            const Stage nxt = stage_load(Wl + (int64_t)min(kc + 1, KC - 1) * BLK);
+#pragma unroll
+            for (int ct = 0; ct < NT; ct++) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(&abuf[b][(ct * 64 + lane) * 8]);
+#pragma unroll
+                for (int p = 0; p < P; p++) acc[ct][p] = M::mma(a, bx[p], acc[ct][p]);
+            }
+            stage_store(b ^ 1, nxt);
+            __syncthreads();
+        };
+        if (li == 0) {
+            const __bf16* xr[P];
+#pragma unroll
+            for (int p = 0; p < P; p++) {
+                int64_t r = row0 + p * 16 + lr;
+                r = r < npts ? r : npts - 1;
+                xr[p] = x + r * kDescPad + lg * 8;
+            }
+            // descriptor fragments one K step ahead
+            bf16x8 bx[P], bn[P];
+#pragma unroll
+            for (int p = 0; p < P; p++) bx[p] = *reinterpret_cast<const bf16x8*>(xr[p]);
+            for (int kc = 0; kc < KC0; kc++) {
+#pragma unroll
+                for (int p = 0; p < P; p++)
+                    bn[p] = *reinterpret_cast<const bf16x8*>(xr[p] + min(kc + 1, KC0 - 1) * 32);
+                step(kc, bx);
+#pragma unroll
+                for (int p = 0; p < P; p++) bx[p] = bn[p];
+            }
+        } else {
+#pragma unroll
+            for (int kc = 0; kc < KCH; kc++) step(kc, hin[kc]);
+        }
+        // bias + ReLU into the next layer's B fragments (channels >= 16 NT are zero)
+        const float* bias = A.bias[li];
+#pragma unroll
+        for (int kc = 0; kc < KCH; kc++)
+#pragma unroll
+            for (int p = 0; p < P; p++) {
+                bf16x8 f;
+#pragma unroll
+                for (int e = 0; e < 8; e++) {
+                    const int ct = 2 * kc + e / 4;
+                    float v = 0.f;
+                    if (ct < NT) v = fmaxf(acc[ct][p][e % 4] + bias[ct * 16 + lg * 4 + e % 4], 0.f);
+                    f[e] = (__bf16)v;
+                }
+                hin[kc][p] = f;
+            }
+    }
+    // last layer (a dot product over the channels, spread over the lane groups) + decode
+#pragma unroll
+    for (int p = 0; p < P; p++) {
+        float s = 0.f;
+#pragma unroll
+        for (int kc = 0; kc < KCH; kc++)
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int ct = 2 * kc + e / 4;
+                if (ct < NT) s += (float)hin[kc][p][e] * A.wout[ct * 16 + lg * 4 + e % 4];
+            }
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        const int64_t row = row0 + p * 16 + lr;
+        if (lg == 0 && row < npts) {
+            const float y = A.bout + s;
+            if (A.y_out) A.y_out[row] = y;
+            if (A.out) A.out[row] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
+        }
+    }
+}
+
+template <int NT, int P>
+static void launch_bf16_nt(const MlpArgs& a, hipStream_t s)
+{
+    const int per = 4 * 16 * P;
+    hipLaunchKernelGGL((k_mlp_bf16<NT, P>), dim3((int)((a.npts + per - 1) / per)), dim3(256), 0, s, a);
+}
+
+static hipError_t launch_mlp_bf16(const MlpArgs& a, hipStream_t s)
+{
+    switch (a.wpad / 16) {
+    case 1: launch_bf16_nt<1, 4>(a, s); break;
+    case 2: launch_bf16_nt<2, 4>(a, s); break;
+    case 4: launch_bf16_nt<4, 4>(a, s); break;
+    case 8: launch_bf16_nt<8, 4>(a, s); break;
+    case 13: launch_bf16_nt<13, 3>(a, s); break;
+    case 16: launch_bf16_nt<16, 2>(a, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <int NT>
 static void launch_fp8_nt(const MlpArgs& a, dim3 g, dim3 b, hipStream_t s)
 {
@@ -315,7 +471,7 @@ hipError_t launch_mlp(int prec, const MlpArgs& a, hipStream_t s)
 {
     if (a.npts <= 0) return hipSuccess;
     if (prec == kPrecFP8) return launch_mlp_fp8(a, s);
-    if (prec == kPrecBF16) return launch_mlp_prec<kPrecBF16>(a, s);
+    if (prec == kPrecBF16) return launch_mlp_bf16(a, s);
     return launch_mlp_prec<kPrecFP32>(a, s);
 }
 

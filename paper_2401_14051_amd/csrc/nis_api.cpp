@@ -295,16 +295,33 @@ void pack_net(Net* net, int prec)
                 for (int i = 0; i < din; i++) t[(size_t)o * kpad + i] /= sc[o];
             }
         }
-        // B-fragment order: block (ct, kc) holds, for lane l = r + 16 g, the
-        // elements W[ct*16 + r][kc*KS + g*KPL + e], e < KPL, contiguously
         const int KS = mlp_k_step(prec), KPL = mlp_k_per_lane(prec), KC = kpad / KS;
         std::vector<float> f(t.size());
         size_t pos = 0;
-        for (int ct = 0; ct < Wp / 16; ct++)
+        if (prec == kPrecBF16) {
+            // A-fragment order of the BF16 kernel (weights as the A operand):
+            // K step kc holds, for output tile ct and lane l = r + 16 g, the
+            // elements W[ct*16 + r][col(kc*32 + g*8 + e)], e < 8, where col is
+            // the slot itself for the first layer and, for hidden layers, the
+            // previous layer's channel (2 kc + e/4) * 16 + g * 4 + e % 4 held in
+            // that register of the lane's output tile
             for (int kc = 0; kc < KC; kc++)
-                for (int l = 0; l < 64; l++)
-                    for (int e = 0; e < KPL; e++)
-                        f[pos++] = t[(size_t)(ct * 16 + l % 16) * kpad + kc * KS + (l / 16) * KPL + e];
+                for (int ct = 0; ct < Wp / 16; ct++)
+                    for (int l = 0; l < 64; l++)
+                        for (int e = 0; e < 8; e++) {
+                            const int g = l / 16;
+                            const int col = li == 0 ? kc * 32 + g * 8 + e : (2 * kc + e / 4) * 16 + g * 4 + e % 4;
+                            f[pos++] = col < kpad ? t[(size_t)(ct * 16 + l % 16) * kpad + col] : 0.f;
+                        }
+        } else {
+            // B-fragment order: block (ct, kc) holds, for lane l = r + 16 g, the
+            // elements W[ct*16 + r][kc*KS + g*KPL + e], e < KPL, contiguously
+            for (int ct = 0; ct < Wp / 16; ct++)
+                for (int kc = 0; kc < KC; kc++)
+                    for (int l = 0; l < 64; l++)
+                        for (int e = 0; e < KPL; e++)
+                            f[pos++] = t[(size_t)(ct * 16 + l % 16) * kpad + kc * KS + (l / 16) * KPL + e];
+        }
         put(P.W[li], f, "backbone weights", true);
         upload_vec(P.bias[li], bb, "backbone biases");
         if (prec == kPrecFP8) upload_vec(P.wscale[li], sc, "backbone weight scales");
