@@ -247,133 +247,303 @@ k_mlp_fp8(MlpArgs A)
     }
 }
 
-// BF16 backbone with the weights as the MFMA A operand and the activations as
-// B.  A layer's output tile D[channel][point] leaves each lane holding 4
-// consecutive channels of one point, which after bias and ReLU are exactly the
-// lane's B fragment of the next layer once that layer's K index is permuted
-// to match: K slot s = kc*32 + g*8 + e (lane group g) is channel
-// (2 kc + e/4) * 16 + g * 4 + e % 4 (the weights are packed in that order).
-// So activations stay in registers from layer to layer.  A workgroup of 4
-// waves covers 256 points (4 tiles of 16 per wave); for every K step the
-// group stages the step's NT weight fragments (NT KiB) in LDS once, double
-// buffered, and all four waves read them there.  P point tiles of 16 per
-// wave (fewer for wide layers, whose accumulators and inputs must fit in the
-// register file).
-template <int NT, int P>
+// BF16 backbone on 32x32x16 MFMA tiles, the weights as the A operand and the
+// activations as B.  A layer's output tile D[channel][point] leaves lane
+// l = p + 32 g holding, for point p, the 16 channels 8 (r/4) + 4 g + r%4 of
+// the tile (r < 16).  Split into two halves of 8 registers these are exactly
+// the lane's B fragments of two K steps of the next layer once that layer's K
+// index is permuted to match (the weights are packed in that order), so the
+// activations stay in registers from layer to layer.  For the first layer the
+// descriptor columns are permuted instead, so that a lane's elements of four
+// consecutive K steps are one 64-byte run of its descriptor row.
+//
+// A workgroup of 4 waves covers 4 * 32 * PT points.  The weights stream
+// through LDS in stages of kStage K steps (NO KiB per step), copied from
+// global memory straight into LDS and double buffered, so one barrier covers
+// kStage steps.  The first layer's descriptor fragments take the same route
+// into per-wave LDS regions, two stages ahead (three buffers), which keeps
+// the HBM latency of the descriptor stream off the MFMA pipeline.
+constexpr int kStage = 4;
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ f32x16 mfma32(bf16x8 a, bf16x8 b, f32x16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// waits until at most N of this wave's loads are outstanding
+template <int N> __device__ __forceinline__ void wait_vm()
+{
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+template <int V> using IC = std::integral_constant<int, V>;
+
+// f(IC<I>), f(IC<I+1>), ..., f(IC<N-1>)
+template <int I, int N, class F> __device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (I < N) {
+        f(IC<I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// Scheduling pattern of one K step: its first NO MFMAs each followed by one
+// of the LDS reads of the next step's A fragments, then the XB B-fragment
+// reads, then the remaining MFMAs, which cover the latency of the last reads.
+template <int NO, int PT, int XB> __device__ __forceinline__ void interleave()
+{
+#pragma unroll
+    for (int i = 0; i < NO; i++) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);    // LDS read
+    }
+    if constexpr (XB > 0) __builtin_amdgcn_sched_group_barrier(0x100, XB, 0);
+    if constexpr (PT > 1) __builtin_amdgcn_sched_group_barrier(0x008, NO * (PT - 1), 0);
+}
+
+// Every LDS buffer is a variable of its own and each access names its buffer
+// at compile time: the compiler can then tell that the copies in flight into
+// one buffer do not alias the reads of another, and does not wait for them.
+template <int NO, int KH, int PT>
 __global__ void __launch_bounds__(256)
 k_mlp_bf16(MlpArgs A)
 {
-    typedef Mfma<kPrecBF16> M;
-    constexpr int KCH = hidden_k(kPrecBF16, NT * 16) / 32;
-    constexpr int KC0 = kDescPad / 32;
-    constexpr int BLK = NT * 64 * 8;           // bf16 elements of one K step's fragments
-    constexpr int CH = BLK / 8;                // their 16-byte chunks
-    constexpr int SJ = (CH + 255) / 256;
-    __shared__ __attribute__((aligned(16))) __bf16 abuf[2][BLK];
+    constexpr int KC0 = kDescPad / 16;          // K steps of the first layer
+    constexpr int NQ0 = KC0 / kStage;           // its stages
+    static_assert(KC0 % kStage == 0, "first-layer stages must tile the descriptor");
+    constexpr int FRB = NO * 1024;              // bytes of one K step's weight fragments
+    constexpr int STB = kStage * FRB;           // bytes of one weight stage
+    constexpr int DTB = kStage * 1024;          // one wave's descriptor fragments of one point tile and stage
+    constexpr int ND = PT * kStage;             // descriptor copies per wave and stage
+    static_assert(PT <= 2, "descriptor buffers exist for two point tiles");
+    // The weight buffers are the largest variables, which places them first,
+    // where every read's offset fits the instruction's immediate field.
+    __shared__ __attribute__((aligned(16))) uint8_t wb0[STB];
+    __shared__ __attribute__((aligned(16))) uint8_t wb1[STB];
+    __shared__ __attribute__((aligned(16))) uint8_t db00[4][DTB];
+    __shared__ __attribute__((aligned(16))) uint8_t db01[4][DTB];
+    __shared__ __attribute__((aligned(16))) uint8_t db10[4][DTB];
+    __shared__ __attribute__((aligned(16))) uint8_t db11[4][DTB];
+    __shared__ __attribute__((aligned(16))) uint8_t db20[4][DTB];
+    __shared__ __attribute__((aligned(16))) uint8_t db21[4][DTB];
 
-    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, lr = lane % 16, lg = lane / 16;
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, lp = lane % 32, lg = lane / 32;
     const int64_t npts = A.count ? min(max((int64_t)*A.count - A.count_off, (int64_t)0), A.npts) : A.npts;
-    const int64_t wg0 = (int64_t)blockIdx.x * (4 * 16 * P);
+    const int64_t wg0 = (int64_t)blockIdx.x * (4 * 32 * PT);
     if (wg0 >= npts) return;
-    const int64_t row0 = wg0 + wave * 16 * P;
-    const __bf16* x = reinterpret_cast<const __bf16*>(A.x);
+    const int64_t row0 = wg0 + wave * 32 * PT;
 
-    // staging of one K step: chunk tid + 256 j, clamped to the last chunk (a
-    // clamped thread stores a copy of that chunk's own value)
-    struct Stage {
-        uint4 v[SJ];
+    auto wbuf = [&](auto bc) __attribute__((always_inline)) -> uint8_t* {
+        if constexpr (decltype(bc)::value == 0) return wb0;
+        else return wb1;
     };
-    auto stage_load = [&](const __bf16* src) __attribute__((always_inline)) {
-        Stage t;
-#pragma unroll
-        for (int j = 0; j < SJ; j++) t.v[j] = reinterpret_cast<const uint4*>(src)[min(tid + 256 * j, CH - 1)];
-        return t;
-    };
-    auto stage_store = [&](int b, Stage t) __attribute__((always_inline)) {
-#pragma unroll
-        for (int j = 0; j < SJ; j++) reinterpret_cast<uint4*>(abuf[b])[min(tid + 256 * j, CH - 1)] = t.v[j];
+    // descriptor buffer d (of three) of point tile p, this wave's part
+    auto dbuf = [&](auto dc, auto pc) __attribute__((always_inline)) -> uint8_t* {
+        constexpr int d = decltype(dc)::value, p = decltype(pc)::value;
+        if constexpr (d == 0) return p == 0 ? db00[wave] : db01[wave];
+        else if constexpr (d == 1) return p == 0 ? db10[wave] : db11[wave];
+        else return p == 0 ? db20[wave] : db21[wave];
     };
 
-    f32x4 acc[NT][P];
-    bf16x8 hin[KCH][P];
-    for (int li = 0; li + 1 < A.n_linear; li++) {
-        const __bf16* Wl = reinterpret_cast<const __bf16*>(A.W[li]);
-        const int KC = li == 0 ? KC0 : KCH;
+    // Copies nsteps K steps of weight fragments starting at src into dst:
+    // 1 KiB chunks, chunk c by wave c % 4, 16 bytes per lane.
+    auto issue_w = [&](const uint8_t* src, int nsteps, uint8_t* dst) __attribute__((always_inline)) {
+        const int nch = nsteps * NO;
+        for (int c = wave; c < nch; c += 4)
+            __builtin_amdgcn_global_load_lds(src + c * 1024 + lane * 16, dst + c * 1024, 16, 0, 0);
+    };
+    // A first-layer stage of a point tile is the 128-byte slice 128 q.. of
+    // each of its 32 descriptor rows (K steps 4q..4q+3 of both lane groups).
+    // In LDS row r's slice holds its 16-byte segment s at slot s ^ ((r/2)%8):
+    // each copy instruction then fills 8 whole rows (8 cache lines), and the
+    // 16 lanes of a B-fragment read phase (16 rows, one segment) fall on
+    // distinct banks.  Lane v of copy i of tile p fetches row 8i + v/8, slot
+    // v%8; rows past the live count repeat the last live row.
+    const uint8_t* dsrc[PT][4];
 #pragma unroll
-        for (int ct = 0; ct < NT; ct++)
+    for (int p = 0; p < PT; p++)
 #pragma unroll
-            for (int p = 0; p < P; p++) acc[ct][p] = f32x4{0.f, 0.f, 0.f, 0.f};
-        stage_store(0, stage_load(Wl));
-        __syncthreads();
-        // K step kc from buffer kc & 1 while the next step's fragments are
-        // fetched (past the last step: the last again, into the idle buffer)
-        auto step = [&](int kc, const bf16x8* bx) __attribute__((always_inline)) {
-            const int b = kc & 1;
-            const Stage nxt = stage_load(Wl + (int64_t)min(kc + 1, KC - 1) * BLK);
-#pragma unroll
-            for (int ct = 0; ct < NT; ct++) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8*>(&abuf[b][(ct * 64 + lane) * 8]);
-#pragma unroll
-                for (int p = 0; p < P; p++) acc[ct][p] = M::mma(a, bx[p], acc[ct][p]);
-            }
-            stage_store(b ^ 1, nxt);
-            __syncthreads();
-        };
-        if (li == 0) {
-            const __bf16* xr[P];
-#pragma unroll
-            for (int p = 0; p < P; p++) {
-                int64_t r = row0 + p * 16 + lr;
-                r = r < npts ? r : npts - 1;
-                xr[p] = x + r * kDescPad + lg * 8;
-            }
-            // descriptor fragments one K step ahead
-            bf16x8 bx[P], bn[P];
-#pragma unroll
-            for (int p = 0; p < P; p++) bx[p] = *reinterpret_cast<const bf16x8*>(xr[p]);
-            for (int kc = 0; kc < KC0; kc++) {
-#pragma unroll
-                for (int p = 0; p < P; p++)
-                    bn[p] = *reinterpret_cast<const bf16x8*>(xr[p] + min(kc + 1, KC0 - 1) * 32);
-                step(kc, bx);
-#pragma unroll
-                for (int p = 0; p < P; p++) bx[p] = bn[p];
-            }
-        } else {
-#pragma unroll
-            for (int kc = 0; kc < KCH; kc++) step(kc, hin[kc]);
+        for (int i = 0; i < 4; i++) {
+            const int r = 8 * i + lane / 8, sl = lane % 8, seg = sl ^ ((r >> 1) & 7);
+            int64_t row = row0 + p * 32 + r;
+            row = row < npts ? row : npts - 1;
+            dsrc[p][i] = reinterpret_cast<const uint8_t*>(A.x) + row * (kDescPad * 2) + seg * 16;
         }
-        // bias + ReLU into the next layer's B fragments (channels >= 16 NT are zero)
-        const float* bias = A.bias[li];
+    // byte offset of this lane's B fragment of step j within a tile's slice
+    int roff[kStage];
 #pragma unroll
-        for (int kc = 0; kc < KCH; kc++)
+    for (int j = 0; j < kStage; j++) roff[j] = lp * 128 + (((lg * 4 + j) ^ ((lp >> 1) & 7)) << 4);
+    auto issue_d = [&](int q, auto dc) __attribute__((always_inline)) {
+        static_for<0, PT>([&](auto pc) __attribute__((always_inline)) {
+            uint8_t* dst = dbuf(dc, pc);
 #pragma unroll
-            for (int p = 0; p < P; p++) {
+            for (int i = 0; i < 4; i++)
+                __builtin_amdgcn_global_load_lds(dsrc[decltype(pc)::value][i] + q * 128, dst + i * 1024, 16, 0, 0);
+        });
+    };
+
+    f32x16 acc[NO][PT];
+    // A fragments of K step j of a weight buffer
+    auto load_a = [&](const uint8_t* wsrc, int j, bf16x8* a) __attribute__((always_inline)) {
+#pragma unroll
+        for (int ct = 0; ct < NO; ct++) a[ct] = *reinterpret_cast<const bf16x8*>(wsrc + j * FRB + ct * 1024 + lane * 16);
+    };
+    auto mma = [&](const bf16x8* a, const bf16x8* bx) __attribute__((always_inline)) {
+#pragma unroll
+        for (int ct = 0; ct < NO; ct++)
+#pragma unroll
+            for (int p = 0; p < PT; p++) acc[ct][p] = mfma32(a[ct], bx[p], acc[ct][p]);
+    };
+    // accumulators start at the layer's bias (register r of tile ct holds
+    // channel ct*32 + (r/4)*8 + 4 g + r%4; the bias is padded to whole tiles)
+    auto init_acc = [&](const float* bias) __attribute__((always_inline)) {
+#pragma unroll
+        for (int ct = 0; ct < NO; ct++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const float4 bv = *reinterpret_cast<const float4*>(bias + ct * 32 + j * 8 + lg * 4);
+#pragma unroll
+                for (int p = 0; p < PT; p++) {
+                    acc[ct][p][j * 4 + 0] = bv.x;
+                    acc[ct][p][j * 4 + 1] = bv.y;
+                    acc[ct][p][j * 4 + 2] = bv.z;
+                    acc[ct][p][j * 4 + 3] = bv.w;
+                }
+            }
+    };
+    init_acc(A.bias[0]);
+
+    const int nhid = A.n_linear - 2;   // hidden layers after the first
+    const uint8_t* W0 = reinterpret_cast<const uint8_t*>(A.W[0]);
+    const uint8_t* W1 = nhid > 0 ? reinterpret_cast<const uint8_t*>(A.W[1]) : W0;
+
+    // ---- first layer.  Stage q multiplies from weight buffer q % 2 and
+    // descriptor buffer q % 3 while the weights of stage q + 1 and the
+    // descriptors of stage q + 2 are copied (past the last stage the copies
+    // repeat the last descriptor stage into an idle buffer, which keeps the
+    // count of loads in flight the same at every stage end).
+    auto stage0 = [&](auto bc, auto dc, int q) __attribute__((always_inline)) {
+        constexpr int B = decltype(bc)::value, D = decltype(dc)::value;
+        uint8_t* wcur = wbuf(IC<B>{});
+        if (q + 1 < NQ0) issue_w(W0 + (int64_t)(q + 1) * STB, kStage, wbuf(IC<1 - B>{}));
+        else if (nhid > 0) issue_w(W1, min(kStage, KH), wbuf(IC<1 - B>{}));
+        issue_d(min(q + 2, NQ0 - 1), IC<(D + 2) % 3>{});
+        const uint8_t* dcur[PT];
+        static_for<0, PT>([&](auto pc) __attribute__((always_inline)) { dcur[decltype(pc)::value] = dbuf(IC<D>{}, pc); });
+        // the operands of step j + 1 are read before the MFMAs of step j
+        bf16x8 a[2][NO], bx[2][PT];
+        auto load_b = [&](int j, bf16x8* b) __attribute__((always_inline)) {
+#pragma unroll
+            for (int p = 0; p < PT; p++) b[p] = *reinterpret_cast<const bf16x8*>(dcur[p] + roff[j]);
+        };
+        load_a(wcur, 0, a[0]);
+        load_b(0, bx[0]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < kStage; j++) {
+            mma(a[j % 2], bx[j % 2]);
+            if (j + 1 < kStage) {
+                load_a(wcur, j + 1, a[(j + 1) % 2]);
+                load_b(j + 1, bx[(j + 1) % 2]);
+                interleave<NO, PT, PT>();
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        wait_vm<ND>();
+        __syncthreads();
+    };
+    issue_d(0, IC<0>{});
+    issue_w(W0, kStage, wbuf(IC<0>{}));
+    issue_d(1, IC<1>{});
+    wait_vm<ND>();
+    __syncthreads();
+    for (int q = 0; q < NQ0; q += 6) {
+        stage0(IC<0>{}, IC<0>{}, q);
+        if (q + 1 < NQ0) stage0(IC<1>{}, IC<1>{}, q + 1);
+        if (q + 2 < NQ0) stage0(IC<0>{}, IC<2>{}, q + 2);
+        if (q + 3 < NQ0) stage0(IC<1>{}, IC<0>{}, q + 3);
+        if (q + 4 < NQ0) stage0(IC<0>{}, IC<1>{}, q + 4);
+        if (q + 5 < NQ0) stage0(IC<1>{}, IC<2>{}, q + 5);
+    }
+    wait_vm<0>();
+
+    // ---- ReLU of a finished layer into the next layer's B fragments
+    bf16x8 hin[KH][PT];
+    auto epilogue = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int kc = 0; kc < KH; kc++)
+#pragma unroll
+            for (int p = 0; p < PT; p++) {
                 bf16x8 f;
 #pragma unroll
-                for (int e = 0; e < 8; e++) {
-                    const int ct = 2 * kc + e / 4;
-                    float v = 0.f;
-                    if (ct < NT) v = fmaxf(acc[ct][p][e % 4] + bias[ct * 16 + lg * 4 + e % 4], 0.f);
-                    f[e] = (__bf16)v;
-                }
+                for (int e = 0; e < 8; e++) f[e] = (__bf16)fmaxf(acc[kc / 2][p][(kc % 2) * 8 + e], 0.f);
                 hin[kc][p] = f;
             }
-    }
-    // last layer (a dot product over the channels, spread over the lane groups) + decode
+    };
+    epilogue();
+
+    // ---- hidden layers: B fragments from registers; a layer whose stages
+    // start at weight buffer B0 copies the next layer's first stage during
+    // its own last stage
+    constexpr int NQH = (KH + kStage - 1) / kStage;
+    auto hidden = [&](auto b0c, int li) __attribute__((always_inline)) {
+        constexpr int B0 = decltype(b0c)::value;
+        const uint8_t* Wl = reinterpret_cast<const uint8_t*>(A.W[li]);
+        init_acc(A.bias[li]);
+        static_for<0, NQH>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = decltype(qc)::value, B = (B0 + q) % 2, k0 = q * kStage;
+            constexpr int ns = KH - k0 < kStage ? KH - k0 : kStage;
+            if constexpr (q + 1 < NQH) {
+                constexpr int nn = KH - k0 - kStage < kStage ? KH - k0 - kStage : kStage;
+                issue_w(Wl + (int64_t)(k0 + kStage) * FRB, nn, wbuf(IC<1 - B>{}));
+            } else if (li < nhid) {
+                issue_w(reinterpret_cast<const uint8_t*>(A.W[li + 1]), KH < kStage ? KH : kStage, wbuf(IC<1 - B>{}));
+            }
+            const uint8_t* wcur = wbuf(IC<B>{});
+            bf16x8 a[2][NO];
+            load_a(wcur, 0, a[0]);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int p = 0; p < P; p++) {
+            for (int j = 0; j < ns; j++) {
+                mma(a[j % 2], hin[k0 + j]);
+                if (j + 1 < ns) {
+                    load_a(wcur, j + 1, a[(j + 1) % 2]);
+                    interleave<NO, PT, 0>();
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            wait_vm<0>();
+            __syncthreads();
+        });
+        epilogue();
+    };
+    constexpr int HB = NQ0 % 2;   // weight buffer of the first hidden stage
+    if constexpr (NQH % 2 == 0) {
+        for (int li = 1; li <= nhid; li++) hidden(IC<HB>{}, li);
+    } else {
+        for (int li = 1; li <= nhid; li += 2) {
+            hidden(IC<HB>{}, li);
+            if (li + 1 <= nhid) hidden(IC<1 - HB>{}, li + 1);
+        }
+    }
+
+    // ---- last layer (a dot product over the lane's channels, then across the
+    // two lane groups) + decode
+#pragma unroll
+    for (int p = 0; p < PT; p++) {
         float s = 0.f;
 #pragma unroll
-        for (int kc = 0; kc < KCH; kc++)
+        for (int kc = 0; kc < KH; kc++)
 #pragma unroll
-            for (int e = 0; e < 8; e++) {
-                const int ct = 2 * kc + e / 4;
-                if (ct < NT) s += (float)hin[kc][p][e] * A.wout[ct * 16 + lg * 4 + e % 4];
+            for (int hf = 0; hf < 2; hf++) {
+                const float4 w = *reinterpret_cast<const float4*>(A.wout + (kc / 2) * 32 + (2 * (kc % 2) + hf) * 8 + lg * 4);
+                s += (float)hin[kc][p][hf * 4 + 0] * w.x + (float)hin[kc][p][hf * 4 + 1] * w.y +
+                     (float)hin[kc][p][hf * 4 + 2] * w.z + (float)hin[kc][p][hf * 4 + 3] * w.w;
             }
-        s += __shfl_xor(s, 16);
         s += __shfl_xor(s, 32);
-        const int64_t row = row0 + p * 16 + lr;
+        const int64_t row = row0 + p * 32 + lp;
         if (lg == 0 && row < npts) {
             const float y = A.bout + s;
             if (A.y_out) A.y_out[row] = y;
@@ -382,22 +552,22 @@ k_mlp_bf16(MlpArgs A)
     }
 }
 
-template <int NT, int P>
+template <int NO, int KH, int PT>
 static void launch_bf16_nt(const MlpArgs& a, hipStream_t s)
 {
-    const int per = 4 * 16 * P;
-    hipLaunchKernelGGL((k_mlp_bf16<NT, P>), dim3((int)((a.npts + per - 1) / per)), dim3(256), 0, s, a);
+    const int per = 4 * 32 * PT;
+    hipLaunchKernelGGL((k_mlp_bf16<NO, KH, PT>), dim3((int)((a.npts + per - 1) / per)), dim3(256), 0, s, a);
 }
 
 static hipError_t launch_mlp_bf16(const MlpArgs& a, hipStream_t s)
 {
-    switch (a.wpad / 16) {
-    case 1: launch_bf16_nt<1, 4>(a, s); break;
-    case 2: launch_bf16_nt<2, 4>(a, s); break;
-    case 4: launch_bf16_nt<4, 4>(a, s); break;
-    case 8: launch_bf16_nt<8, 4>(a, s); break;
-    case 13: launch_bf16_nt<13, 3>(a, s); break;
-    case 16: launch_bf16_nt<16, 2>(a, s); break;
+    switch (a.wpad) {
+    case 16: launch_bf16_nt<1, 1, 2>(a, s); break;
+    case 32: launch_bf16_nt<1, 2, 2>(a, s); break;
+    case 64: launch_bf16_nt<2, 4, 2>(a, s); break;
+    case 128: launch_bf16_nt<4, 8, 2>(a, s); break;
+    case 208: launch_bf16_nt<7, 13, 2>(a, s); break;
+    case 256: launch_bf16_nt<8, 16, 1>(a, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -280,9 +280,10 @@ void pack_net(Net* net, int prec)
         upload_vec(P.cb[gi], cb, "attention weights");
     }
     const int W = net->width, Wp = net->wpad;
+    const int Wb = (Wp + 31) / 32 * 32;   // biases and output weights padded to whole 32-channel tiles
     for (int li = 0; li + 1 < net->n_linear; li++) {
         const int din = li == 0 ? kDesc : W, kpad = li == 0 ? input_k(prec) : mlp_hidden_k(prec, Wp);
-        std::vector<float> t((size_t)Wp * kpad, 0.f), bb(Wp, 0.f), sc(Wp, 1.f);
+        std::vector<float> t((size_t)Wp * kpad, 0.f), bb(Wb, 0.f), sc(Wp, 1.f);
         for (int o = 0; o < W; o++) {
             float amax = 0.f;
             for (int i = 0; i < din; i++) {
@@ -299,19 +300,24 @@ void pack_net(Net* net, int prec)
         std::vector<float> f(t.size());
         size_t pos = 0;
         if (prec == kPrecBF16) {
-            // A-fragment order of the BF16 kernel (weights as the A operand):
-            // K step kc holds, for output tile ct and lane l = r + 16 g, the
-            // elements W[ct*16 + r][col(kc*32 + g*8 + e)], e < 8, where col is
-            // the slot itself for the first layer and, for hidden layers, the
-            // previous layer's channel (2 kc + e/4) * 16 + g * 4 + e % 4 held in
-            // that register of the lane's output tile
-            for (int kc = 0; kc < KC; kc++)
-                for (int ct = 0; ct < Wp / 16; ct++)
+            // A-fragment order of the BF16 kernel (32x32x16 tiles, weights as
+            // the A operand): K step kc holds, for output tile ct (32 channels)
+            // and lane l = r + 32 g, the elements W[ct*32 + r][col(kc, g, e)],
+            // e < 8.  First layer: col = (kc/4)*64 + g*32 + (kc%4)*8 + e, so a
+            // lane's descriptor elements of four consecutive K steps are one
+            // contiguous run.  Hidden layers: col is the previous layer's
+            // channel that the lane holds in register (kc%2)*8 + e of its
+            // output tile kc/2, i.e. (kc/2)*32 + (2 (kc%2) + e/4)*8 + g*4 + e%4.
+            const int NO = (Wp + 31) / 32, KCb = li == 0 ? kDescPad / 16 : Wp / 16;
+            f.assign((size_t)KCb * NO * 512, 0.f);
+            for (int kc = 0; kc < KCb; kc++)
+                for (int ct = 0; ct < NO; ct++)
                     for (int l = 0; l < 64; l++)
                         for (int e = 0; e < 8; e++) {
-                            const int g = l / 16;
-                            const int col = li == 0 ? kc * 32 + g * 8 + e : (2 * kc + e / 4) * 16 + g * 4 + e % 4;
-                            f[pos++] = col < kpad ? t[(size_t)(ct * 16 + l % 16) * kpad + col] : 0.f;
+                            const int g = l / 32, row = ct * 32 + l % 32;
+                            const int col = li == 0 ? (kc / 4) * 64 + g * 32 + (kc % 4) * 8 + e
+                                                    : (kc / 2) * 32 + (2 * (kc % 2) + e / 4) * 8 + g * 4 + e % 4;
+                            f[pos++] = row < Wp && col < kpad ? t[(size_t)row * kpad + col] : 0.f;
                         }
         } else {
             // B-fragment order: block (ct, kc) holds, for lane l = r + 16 g, the
@@ -326,7 +332,7 @@ void pack_net(Net* net, int prec)
         upload_vec(P.bias[li], bb, "backbone biases");
         if (prec == kPrecFP8) upload_vec(P.wscale[li], sc, "backbone weight scales");
     }
-    std::vector<float> wo(Wp, 0.f);
+    std::vector<float> wo(Wb, 0.f);
     for (int i = 0; i < W; i++) wo[i] = net->A[net->n_linear - 1][i];
     upload_vec(P.wout, wo, "output weights");
 }

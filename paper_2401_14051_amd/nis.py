@@ -220,7 +220,8 @@ class Context:
         self.device = device
 
     def close(self):
-        if getattr(self, "h", None):
+        # at interpreter exit the module's globals may already be cleared
+        if getattr(self, "h", None) and _lib is not None:
             _lib.nis_destroy(self.h)
             self.h = None
 
