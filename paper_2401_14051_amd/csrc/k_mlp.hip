@@ -266,6 +266,15 @@ k_mlp_fp8(MlpArgs A)
 constexpr int kStage = 4;
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef short i16x8 __attribute__((ext_vector_type(8)));
+
+// bfloat16 pair {lo, hi} rounded to nearest even, packed low half first
+__device__ __forceinline__ uint32_t cvt_pk_bf16(float lo, float hi)
+{
+    uint32_t r;
+    asm("v_cvt_pk_bf16_f32 %0, %1, %2" : "=v"(r) : "v"(lo), "v"(hi));
+    return r;
+}
 
 __device__ __forceinline__ f32x16 mfma32(bf16x8 a, bf16x8 b, f32x16 c)
 {
@@ -396,24 +405,33 @@ k_mlp_bf16(MlpArgs A)
 #pragma unroll
             for (int p = 0; p < PT; p++) acc[ct][p] = mfma32(a[ct], bx[p], acc[ct][p]);
     };
+    // first K step of a layer whose bias is in acc[.][0] only: the other
+    // point tiles take it as their C operand before tile 0 overwrites it
+    auto mma_first = [&](const bf16x8* a, const bf16x8* bx) __attribute__((always_inline)) {
+#pragma unroll
+        for (int ct = 0; ct < NO; ct++)
+#pragma unroll
+            for (int p = PT - 1; p >= 0; p--) acc[ct][p] = mfma32(a[ct], bx[p], acc[ct][0]);
+    };
     // accumulators start at the layer's bias (register r of tile ct holds
     // channel ct*32 + (r/4)*8 + 4 g + r%4; the bias is padded to whole tiles)
-    auto init_acc = [&](const float* bias) __attribute__((always_inline)) {
+    auto init_acc = [&](const float* bias, int np) __attribute__((always_inline)) {
 #pragma unroll
         for (int ct = 0; ct < NO; ct++)
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const float4 bv = *reinterpret_cast<const float4*>(bias + ct * 32 + j * 8 + lg * 4);
 #pragma unroll
-                for (int p = 0; p < PT; p++) {
-                    acc[ct][p][j * 4 + 0] = bv.x;
-                    acc[ct][p][j * 4 + 1] = bv.y;
-                    acc[ct][p][j * 4 + 2] = bv.z;
-                    acc[ct][p][j * 4 + 3] = bv.w;
-                }
+                for (int p = 0; p < PT; p++)
+                    if (p < np) {
+                        acc[ct][p][j * 4 + 0] = bv.x;
+                        acc[ct][p][j * 4 + 1] = bv.y;
+                        acc[ct][p][j * 4 + 2] = bv.z;
+                        acc[ct][p][j * 4 + 3] = bv.w;
+                    }
             }
     };
-    init_acc(A.bias[0]);
+    init_acc(A.bias[0], PT);
 
     const int nhid = A.n_linear - 2;   // hidden layers after the first
     const uint8_t* W0 = reinterpret_cast<const uint8_t*>(A.W[0]);
@@ -469,17 +487,21 @@ k_mlp_bf16(MlpArgs A)
     }
     wait_vm<0>();
 
-    // ---- ReLU of a finished layer into the next layer's B fragments
+    // ---- ReLU of a finished layer into the next layer's B fragments.  The
+    // ReLU is applied after rounding, as a signed 16-bit max on the bfloat16
+    // bit patterns (rounding keeps the sign, so both orders agree).
     bf16x8 hin[KH][PT];
     auto epilogue = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int kc = 0; kc < KH; kc++)
 #pragma unroll
             for (int p = 0; p < PT; p++) {
-                bf16x8 f;
-#pragma unroll
-                for (int e = 0; e < 8; e++) f[e] = (__bf16)fmaxf(acc[kc / 2][p][(kc % 2) * 8 + e], 0.f);
-                hin[kc][p] = f;
+                const f32x16& c = acc[kc / 2][p];
+                const int o = (kc % 2) * 8;
+                const uint4 f = {cvt_pk_bf16(c[o + 0], c[o + 1]), cvt_pk_bf16(c[o + 2], c[o + 3]),
+                                 cvt_pk_bf16(c[o + 4], c[o + 5]), cvt_pk_bf16(c[o + 6], c[o + 7])};
+                const i16x8 v = __builtin_elementwise_max(__builtin_bit_cast(i16x8, f), i16x8{});
+                hin[kc][p] = __builtin_bit_cast(bf16x8, v);
             }
     };
     epilogue();
@@ -491,7 +513,7 @@ k_mlp_bf16(MlpArgs A)
     auto hidden = [&](auto b0c, int li) __attribute__((always_inline)) {
         constexpr int B0 = decltype(b0c)::value;
         const uint8_t* Wl = reinterpret_cast<const uint8_t*>(A.W[li]);
-        init_acc(A.bias[li]);
+        init_acc(A.bias[li], 1);
         static_for<0, NQH>([&](auto qc) __attribute__((always_inline)) {
             constexpr int q = decltype(qc)::value, B = (B0 + q) % 2, k0 = q * kStage;
             constexpr int ns = KH - k0 < kStage ? KH - k0 : kStage;
@@ -507,7 +529,8 @@ k_mlp_bf16(MlpArgs A)
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int j = 0; j < ns; j++) {
-                mma(a[j % 2], hin[k0 + j]);
+                if (q == 0 && j == 0) mma_first(a[j % 2], hin[k0 + j]);
+                else mma(a[j % 2], hin[k0 + j]);
                 if (j + 1 < ns) {
                     load_a(wcur, j + 1, a[(j + 1) % 2]);
                     interleave<NO, PT, 0>();
