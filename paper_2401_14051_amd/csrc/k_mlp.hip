@@ -281,6 +281,19 @@ __device__ __forceinline__ f32x16 mfma32(bf16x8 a, bf16x8 b, f32x16 c)
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
+// buffer resource over bytes bytes at base (reads past the end return zero)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, int64_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// 16 bytes per lane from buffer r at voff + soff into LDS at lds + 16 * lane
+// (lds is wave-uniform)
+__device__ __forceinline__ void copy_lds16(__amdgpu_buffer_rsrc_t r, void* lds, int voff, int soff)
+{
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds, 16, voff, soff, 0, 0);
+}
+
 // waits until at most N of this wave's loads are outstanding
 template <int N> __device__ __forceinline__ void wait_vm()
 {
@@ -296,20 +309,6 @@ template <int I, int N, class F> __device__ __forceinline__ void static_for(F&& 
         f(IC<I>{});
         static_for<I + 1, N>(f);
     }
-}
-
-// Scheduling pattern of one K step: its first NO MFMAs each followed by one
-// of the LDS reads of the next step's A fragments, then the XB B-fragment
-// reads, then the remaining MFMAs, which cover the latency of the last reads.
-template <int NO, int PT, int XB> __device__ __forceinline__ void interleave()
-{
-#pragma unroll
-    for (int i = 0; i < NO; i++) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // MFMA
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);    // LDS read
-    }
-    if constexpr (XB > 0) __builtin_amdgcn_sched_group_barrier(0x100, XB, 0);
-    if constexpr (PT > 1) __builtin_amdgcn_sched_group_barrier(0x008, NO * (PT - 1), 0);
 }
 
 // Every LDS buffer is a variable of its own and each access names its buffer
@@ -338,7 +337,8 @@ k_mlp_bf16(MlpArgs A)
     __shared__ __attribute__((aligned(16))) uint8_t db20[4][DTB];
     __shared__ __attribute__((aligned(16))) uint8_t db21[4][DTB];
 
-    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, lp = lane % 32, lg = lane / 32;
+    const int tid = threadIdx.x, lane = tid % 64, lp = lane % 32, lg = lane / 32;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
     const int64_t npts = A.count ? min(max((int64_t)*A.count - A.count_off, (int64_t)0), A.npts) : A.npts;
     const int64_t wg0 = (int64_t)blockIdx.x * (4 * 32 * PT);
     if (wg0 >= npts) return;
@@ -356,12 +356,18 @@ k_mlp_bf16(MlpArgs A)
         else return p == 0 ? db20[wave] : db21[wave];
     };
 
-    // Copies nsteps K steps of weight fragments starting at src into dst:
-    // 1 KiB chunks, chunk c by wave c % 4, 16 bytes per lane.
-    auto issue_w = [&](const uint8_t* src, int nsteps, uint8_t* dst) __attribute__((always_inline)) {
-        const int nch = nsteps * NO;
-        for (int c = wave; c < nch; c += 4)
-            __builtin_amdgcn_global_load_lds(src + c * 1024 + lane * 16, dst + c * 1024, 16, 0, 0);
+    // The copies into LDS are buffer loads: the hardware checks each against
+    // its buffer's size, and the compiler counts them as vector-memory loads
+    // only, so they do not force waits on the LDS reads issued around them.
+    // Copies of weight stages: nch chunks of 1 KiB from byte offset off of a
+    // layer's weights, chunk c by wave c % 4; copy u of this wave is chunk
+    // wave + 4u (at most NWC per stage).  A chunk index past the stage
+    // repeats its last chunk (chunk 0 of an empty stage), so every wave
+    // issues the same number of copies.
+    constexpr int NWC = (kStage * NO + 3) / 4;
+    auto copy_w = [&](__amdgpu_buffer_rsrc_t r, int off, int nch, uint8_t* dst, int u) __attribute__((always_inline)) {
+        const int c = min(wave + 4 * u, max(nch, 1) - 1);
+        copy_lds16(r, dst + c * 1024, lane * 16, off + c * 1024);
     };
     // A first-layer stage of a point tile is the 128-byte slice 128 q.. of
     // each of its 32 descriptor rows (K steps 4q..4q+3 of both lane groups).
@@ -369,8 +375,11 @@ k_mlp_bf16(MlpArgs A)
     // each copy instruction then fills 8 whole rows (8 cache lines), and the
     // 16 lanes of a B-fragment read phase (16 rows, one segment) fall on
     // distinct banks.  Lane v of copy i of tile p fetches row 8i + v/8, slot
-    // v%8; rows past the live count repeat the last live row.
-    const uint8_t* dsrc[PT][4];
+    // v%8; rows past the live count repeat the last live row.  Offsets are
+    // taken from the workgroup's first row, so the base is wave-uniform.
+    const __amdgpu_buffer_rsrc_t xr = rsrc(reinterpret_cast<const uint8_t*>(A.x) + wg0 * (kDescPad * 2),
+                                           min(npts - wg0, (int64_t)(4 * 32 * PT)) * (kDescPad * 2));
+    uint32_t doff[PT][4];
 #pragma unroll
     for (int p = 0; p < PT; p++)
 #pragma unroll
@@ -378,40 +387,24 @@ k_mlp_bf16(MlpArgs A)
             const int r = 8 * i + lane / 8, sl = lane % 8, seg = sl ^ ((r >> 1) & 7);
             int64_t row = row0 + p * 32 + r;
             row = row < npts ? row : npts - 1;
-            dsrc[p][i] = reinterpret_cast<const uint8_t*>(A.x) + row * (kDescPad * 2) + seg * 16;
+            doff[p][i] = (uint32_t)((row - wg0) * (kDescPad * 2) + seg * 16);
         }
+    // copy k (of ND) of this wave's descriptor stage q into buffer d: tile k/4,
+    // rows 8 (k%4)..
+    auto copy_d = [&](int q, auto dc, int k) __attribute__((always_inline)) {
+        const int p = k / 4, i = k % 4;
+        uint8_t* dst = p == 0 ? dbuf(dc, IC<0>{}) : dbuf(dc, IC<PT - 1>{});
+        copy_lds16(xr, dst + i * 1024, doff[p][i], q * 128);
+    };
     // byte offset of this lane's B fragment of step j within a tile's slice
     int roff[kStage];
 #pragma unroll
     for (int j = 0; j < kStage; j++) roff[j] = lp * 128 + (((lg * 4 + j) ^ ((lp >> 1) & 7)) << 4);
-    auto issue_d = [&](int q, auto dc) __attribute__((always_inline)) {
-        static_for<0, PT>([&](auto pc) __attribute__((always_inline)) {
-            uint8_t* dst = dbuf(dc, pc);
-#pragma unroll
-            for (int i = 0; i < 4; i++)
-                __builtin_amdgcn_global_load_lds(dsrc[decltype(pc)::value][i] + q * 128, dst + i * 1024, 16, 0, 0);
-        });
-    };
 
     f32x16 acc[NO][PT];
-    // A fragments of K step j of a weight buffer
-    auto load_a = [&](const uint8_t* wsrc, int j, bf16x8* a) __attribute__((always_inline)) {
-#pragma unroll
-        for (int ct = 0; ct < NO; ct++) a[ct] = *reinterpret_cast<const bf16x8*>(wsrc + j * FRB + ct * 1024 + lane * 16);
-    };
-    auto mma = [&](const bf16x8* a, const bf16x8* bx) __attribute__((always_inline)) {
-#pragma unroll
-        for (int ct = 0; ct < NO; ct++)
-#pragma unroll
-            for (int p = 0; p < PT; p++) acc[ct][p] = mfma32(a[ct], bx[p], acc[ct][p]);
-    };
-    // first K step of a layer whose bias is in acc[.][0] only: the other
-    // point tiles take it as their C operand before tile 0 overwrites it
-    auto mma_first = [&](const bf16x8* a, const bf16x8* bx) __attribute__((always_inline)) {
-#pragma unroll
-        for (int ct = 0; ct < NO; ct++)
-#pragma unroll
-            for (int p = PT - 1; p >= 0; p--) acc[ct][p] = mfma32(a[ct], bx[p], acc[ct][0]);
+    // A fragment of output tile ct at K step j of a weight buffer
+    auto read_a = [&](const uint8_t* wsrc, int j, int ct) __attribute__((always_inline)) {
+        return *reinterpret_cast<const bf16x8*>(wsrc + j * FRB + ct * 1024 + lane * 16);
     };
     // accumulators start at the layer's bias (register r of tile ct holds
     // channel ct*32 + (r/4)*8 + 4 g + r%4; the bias is padded to whole tiles)
@@ -434,8 +427,15 @@ k_mlp_bf16(MlpArgs A)
     init_acc(A.bias[0], PT);
 
     const int nhid = A.n_linear - 2;   // hidden layers after the first
-    const uint8_t* W0 = reinterpret_cast<const uint8_t*>(A.W[0]);
-    const uint8_t* W1 = nhid > 0 ? reinterpret_cast<const uint8_t*>(A.W[1]) : W0;
+    const __amdgpu_buffer_rsrc_t W0 = rsrc(A.W[0], KC0 * FRB);
+    const __amdgpu_buffer_rsrc_t W1 = nhid > 0 ? rsrc(A.W[1], KH * FRB) : W0;
+
+    // A K step is issued as NO units in a fixed order: the PT MFMAs of
+    // output tile ct and one of the stage's copies (copy u = j*NO + ct while
+    // any are left), so that copies trickle out between MFMAs instead of
+    // stalling the wave in a burst; the first unit also reads all of the next
+    // step's fragments, which leaves the rest of the step to cover their
+    // latency.
 
     // ---- first layer.  Stage q multiplies from weight buffer q % 2 and
     // descriptor buffer q % 3 while the weights of stage q + 1 and the
@@ -444,37 +444,59 @@ k_mlp_bf16(MlpArgs A)
     // count of loads in flight the same at every stage end).
     auto stage0 = [&](auto bc, auto dc, int q) __attribute__((always_inline)) {
         constexpr int B = decltype(bc)::value, D = decltype(dc)::value;
-        uint8_t* wcur = wbuf(IC<B>{});
-        if (q + 1 < NQ0) issue_w(W0 + (int64_t)(q + 1) * STB, kStage, wbuf(IC<1 - B>{}));
-        else if (nhid > 0) issue_w(W1, min(kStage, KH), wbuf(IC<1 - B>{}));
-        issue_d(min(q + 2, NQ0 - 1), IC<(D + 2) % 3>{});
+        const IC<(D + 2) % 3> dn{};   // descriptor buffer being filled
+        const bool last = q + 1 == NQ0;
+        const uint8_t* wcur = wbuf(IC<B>{});
+        uint8_t* wnx = wbuf(IC<1 - B>{});
+        const __amdgpu_buffer_rsrc_t wsrc = last ? W1 : W0;
+        const int woff = last ? 0 : (q + 1) * STB;
+        const int wnch = !last ? kStage * NO : nhid > 0 ? min(kStage, KH) * NO : 0;
+        const int qd = min(q + 2, NQ0 - 1);
         const uint8_t* dcur[PT];
         static_for<0, PT>([&](auto pc) __attribute__((always_inline)) { dcur[decltype(pc)::value] = dbuf(IC<D>{}, pc); });
-        // the operands of step j + 1 are read before the MFMAs of step j
         bf16x8 a[2][NO], bx[2][PT];
-        auto load_b = [&](int j, bf16x8* b) __attribute__((always_inline)) {
 #pragma unroll
-            for (int p = 0; p < PT; p++) b[p] = *reinterpret_cast<const bf16x8*>(dcur[p] + roff[j]);
-        };
-        load_a(wcur, 0, a[0]);
-        load_b(0, bx[0]);
+        for (int ct = 0; ct < NO; ct++) a[0][ct] = read_a(wcur, 0, ct);
+#pragma unroll
+        for (int p = 0; p < PT; p++) bx[0][p] = *reinterpret_cast<const bf16x8*>(dcur[p] + roff[0]);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int j = 0; j < kStage; j++) {
-            mma(a[j % 2], bx[j % 2]);
-            if (j + 1 < kStage) {
-                load_a(wcur, j + 1, a[(j + 1) % 2]);
-                load_b(j + 1, bx[(j + 1) % 2]);
-                interleave<NO, PT, PT>();
+        for (int j = 0; j < kStage; j++)
+#pragma unroll
+            for (int ct = 0; ct < NO; ct++) {
+                const int u = j * NO + ct;
+#pragma unroll
+                for (int p = 0; p < PT; p++) acc[ct][p] = mfma32(a[j % 2][ct], bx[j % 2][p], acc[ct][p]);
+                __builtin_amdgcn_sched_barrier(0);
+                if (j + 1 < kStage && ct == 0) {
+#pragma unroll
+                    for (int c2 = 0; c2 < NO; c2++) a[(j + 1) % 2][c2] = read_a(wcur, j + 1, c2);
+#pragma unroll
+                    for (int p = 0; p < PT; p++)
+                        bx[(j + 1) % 2][p] = *reinterpret_cast<const bf16x8*>(dcur[p] + roff[j + 1]);
+                }
+                if (u < NWC) copy_w(wsrc, woff, wnch, wnx, u);
+                else if (u - NWC < ND) copy_d(qd, dn, u - NWC);
+                __builtin_amdgcn_sched_barrier(0);
             }
-            __builtin_amdgcn_sched_barrier(0);
+        // copies that found no unit (small widths)
+#pragma unroll
+        for (int u = kStage * NO; u < NWC + ND; u++) {
+            if (u < NWC) copy_w(wsrc, woff, wnch, wnx, u);
+            else copy_d(qd, dn, u - NWC);
         }
-        wait_vm<ND>();
-        __syncthreads();
+        // the last stage's copies are waited for after the epilogue
+        if (!last) {
+            wait_vm<ND>();
+            __syncthreads();
+        }
     };
-    issue_d(0, IC<0>{});
-    issue_w(W0, kStage, wbuf(IC<0>{}));
-    issue_d(1, IC<1>{});
+#pragma unroll
+    for (int u = 0; u < NWC; u++) copy_w(W0, 0, kStage * NO, wbuf(IC<0>{}), u);
+#pragma unroll
+    for (int k = 0; k < ND; k++) copy_d(0, IC<0>{}, k);
+#pragma unroll
+    for (int k = 0; k < ND; k++) copy_d(1, IC<1>{}, k);
     wait_vm<ND>();
     __syncthreads();
     for (int q = 0; q < NQ0; q += 6) {
@@ -485,7 +507,6 @@ k_mlp_bf16(MlpArgs A)
         if (q + 4 < NQ0) stage0(IC<0>{}, IC<1>{}, q + 4);
         if (q + 5 < NQ0) stage0(IC<1>{}, IC<2>{}, q + 5);
     }
-    wait_vm<0>();
 
     // ---- ReLU of a finished layer into the next layer's B fragments.  The
     // ReLU is applied after rounding, as a signed 16-bit max on the bfloat16
@@ -505,42 +526,66 @@ k_mlp_bf16(MlpArgs A)
             }
     };
     epilogue();
+    wait_vm<0>();
+    __syncthreads();
 
     // ---- hidden layers: B fragments from registers; a layer whose stages
     // start at weight buffer B0 copies the next layer's first stage during
-    // its own last stage
+    // its own last stage, and waits for it after its epilogue.  The bias is
+    // loaded into the accumulators of point tile 0 only: in the layer's first
+    // K step the other tiles take it as their C operand before tile 0
+    // overwrites it.
     constexpr int NQH = (KH + kStage - 1) / kStage;
     auto hidden = [&](auto b0c, int li) __attribute__((always_inline)) {
         constexpr int B0 = decltype(b0c)::value;
-        const uint8_t* Wl = reinterpret_cast<const uint8_t*>(A.W[li]);
+        const __amdgpu_buffer_rsrc_t Wl = rsrc(A.W[li], KH * FRB);
+        const __amdgpu_buffer_rsrc_t Wn = li < nhid ? rsrc(A.W[li + 1], KH * FRB) : Wl;
         init_acc(A.bias[li], 1);
         static_for<0, NQH>([&](auto qc) __attribute__((always_inline)) {
             constexpr int q = decltype(qc)::value, B = (B0 + q) % 2, k0 = q * kStage;
             constexpr int ns = KH - k0 < kStage ? KH - k0 : kStage;
-            if constexpr (q + 1 < NQH) {
-                constexpr int nn = KH - k0 - kStage < kStage ? KH - k0 - kStage : kStage;
-                issue_w(Wl + (int64_t)(k0 + kStage) * FRB, nn, wbuf(IC<1 - B>{}));
-            } else if (li < nhid) {
-                issue_w(reinterpret_cast<const uint8_t*>(A.W[li + 1]), KH < kStage ? KH : kStage, wbuf(IC<1 - B>{}));
-            }
+            // copies of this layer's next stage, or of the next layer's first
+            constexpr bool inner = q + 1 < NQH;
+            constexpr int nn = !inner ? 0 : KH - k0 - kStage < kStage ? KH - k0 - kStage : kStage;
+            const __amdgpu_buffer_rsrc_t wsrc = inner ? Wl : Wn;
+            const int woff = inner ? (k0 + kStage) * FRB : 0;
+            const int wnch = inner ? nn * NO : li < nhid ? (KH < kStage ? KH : kStage) * NO : 0;
             const uint8_t* wcur = wbuf(IC<B>{});
+            uint8_t* wnx = wbuf(IC<1 - B>{});
             bf16x8 a[2][NO];
-            load_a(wcur, 0, a[0]);
+#pragma unroll
+            for (int ct = 0; ct < NO; ct++) a[0][ct] = read_a(wcur, 0, ct);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int j = 0; j < ns; j++) {
-                if (q == 0 && j == 0) mma_first(a[j % 2], hin[k0 + j]);
-                else mma(a[j % 2], hin[k0 + j]);
-                if (j + 1 < ns) {
-                    load_a(wcur, j + 1, a[(j + 1) % 2]);
-                    interleave<NO, PT, 0>();
+            for (int j = 0; j < ns; j++)
+#pragma unroll
+                for (int ct = 0; ct < NO; ct++) {
+                    const int u = j * NO + ct;
+                    if (q == 0 && j == 0) {
+#pragma unroll
+                        for (int p = PT - 1; p >= 0; p--) acc[ct][p] = mfma32(a[0][ct], hin[k0][p], acc[ct][0]);
+                    } else {
+#pragma unroll
+                        for (int p = 0; p < PT; p++) acc[ct][p] = mfma32(a[j % 2][ct], hin[k0 + j][p], acc[ct][p]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (j + 1 < ns && ct == 0) {
+#pragma unroll
+                        for (int c2 = 0; c2 < NO; c2++) a[(j + 1) % 2][c2] = read_a(wcur, j + 1, c2);
+                    }
+                    if (u < NWC) copy_w(wsrc, woff, wnch, wnx, u);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = ns * NO; u < NWC; u++) copy_w(wsrc, woff, wnch, wnx, u);
+            if constexpr (q + 1 < NQH) {
+                wait_vm<0>();
+                __syncthreads();
             }
-            wait_vm<0>();
-            __syncthreads();
         });
         epilogue();
+        wait_vm<0>();
+        __syncthreads();
     };
     constexpr int HB = NQ0 % 2;   // weight buffer of the first hidden stage
     if constexpr (NQH % 2 == 0) {
