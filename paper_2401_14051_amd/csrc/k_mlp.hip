@@ -294,6 +294,9 @@ __device__ __forceinline__ void copy_lds16(__amdgpu_buffer_rsrc_t r, void* lds, 
     __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds, 16, voff, soff, 0, 0);
 }
 
+// an empty use of x that the compiler must keep: x stays allocated up to here
+__device__ __forceinline__ void keep_alive(const f32x16& x) { asm volatile("" ::"v"(x)); }
+
 // waits until at most N of this wave's loads are outstanding
 template <int N> __device__ __forceinline__ void wait_vm()
 {
@@ -314,8 +317,8 @@ template <int I, int N, class F> __device__ __forceinline__ void static_for(F&& 
 // Every LDS buffer is a variable of its own and each access names its buffer
 // at compile time: the compiler can then tell that the copies in flight into
 // one buffer do not alias the reads of another, and does not wait for them.
-template <int NO, int KH, int PT>
-__global__ void __launch_bounds__(256)
+template <int NO, int KH, int PT, int NW>
+__global__ void __launch_bounds__(64 * NW)
 k_mlp_bf16(MlpArgs A)
 {
     constexpr int KC0 = kDescPad / 16;          // K steps of the first layer
@@ -330,17 +333,17 @@ k_mlp_bf16(MlpArgs A)
     // where every read's offset fits the instruction's immediate field.
     __shared__ __attribute__((aligned(16))) uint8_t wb0[STB];
     __shared__ __attribute__((aligned(16))) uint8_t wb1[STB];
-    __shared__ __attribute__((aligned(16))) uint8_t db00[4][DTB];
-    __shared__ __attribute__((aligned(16))) uint8_t db01[4][DTB];
-    __shared__ __attribute__((aligned(16))) uint8_t db10[4][DTB];
-    __shared__ __attribute__((aligned(16))) uint8_t db11[4][DTB];
-    __shared__ __attribute__((aligned(16))) uint8_t db20[4][DTB];
-    __shared__ __attribute__((aligned(16))) uint8_t db21[4][DTB];
+    __shared__ __attribute__((aligned(16))) uint8_t db00[NW][DTB];
+    __shared__ __attribute__((aligned(16))) uint8_t db01[PT > 1 ? NW : 1][DTB];
+    __shared__ __attribute__((aligned(16))) uint8_t db10[NW][DTB];
+    __shared__ __attribute__((aligned(16))) uint8_t db11[PT > 1 ? NW : 1][DTB];
+    __shared__ __attribute__((aligned(16))) uint8_t db20[NW][DTB];
+    __shared__ __attribute__((aligned(16))) uint8_t db21[PT > 1 ? NW : 1][DTB];
 
     const int tid = threadIdx.x, lane = tid % 64, lp = lane % 32, lg = lane / 32;
     const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
     const int64_t npts = A.count ? min(max((int64_t)*A.count - A.count_off, (int64_t)0), A.npts) : A.npts;
-    const int64_t wg0 = (int64_t)blockIdx.x * (4 * 32 * PT);
+    const int64_t wg0 = (int64_t)blockIdx.x * (NW * 32 * PT);
     if (wg0 >= npts) return;
     const int64_t row0 = wg0 + wave * 32 * PT;
 
@@ -351,22 +354,28 @@ k_mlp_bf16(MlpArgs A)
     // descriptor buffer d (of three) of point tile p, this wave's part
     auto dbuf = [&](auto dc, auto pc) __attribute__((always_inline)) -> uint8_t* {
         constexpr int d = decltype(dc)::value, p = decltype(pc)::value;
-        if constexpr (d == 0) return p == 0 ? db00[wave] : db01[wave];
-        else if constexpr (d == 1) return p == 0 ? db10[wave] : db11[wave];
-        else return p == 0 ? db20[wave] : db21[wave];
+        if constexpr (p == 0) {
+            if constexpr (d == 0) return db00[wave];
+            else if constexpr (d == 1) return db10[wave];
+            else return db20[wave];
+        } else {
+            if constexpr (d == 0) return db01[wave];
+            else if constexpr (d == 1) return db11[wave];
+            else return db21[wave];
+        }
     };
 
     // The copies into LDS are buffer loads: the hardware checks each against
     // its buffer's size, and the compiler counts them as vector-memory loads
     // only, so they do not force waits on the LDS reads issued around them.
     // Copies of weight stages: nch chunks of 1 KiB from byte offset off of a
-    // layer's weights, chunk c by wave c % 4; copy u of this wave is chunk
-    // wave + 4u (at most NWC per stage).  A chunk index past the stage
+    // layer's weights, chunk c by wave c % NW; copy u of this wave is chunk
+    // wave + NW u (at most NWC per stage).  A chunk index past the stage
     // repeats its last chunk (chunk 0 of an empty stage), so every wave
     // issues the same number of copies.
-    constexpr int NWC = (kStage * NO + 3) / 4;
+    constexpr int NWC = (kStage * NO + NW - 1) / NW;
     auto copy_w = [&](__amdgpu_buffer_rsrc_t r, int off, int nch, uint8_t* dst, int u) __attribute__((always_inline)) {
-        const int c = min(wave + 4 * u, max(nch, 1) - 1);
+        const int c = min(wave + NW * u, max(nch, 1) - 1);
         copy_lds16(r, dst + c * 1024, lane * 16, off + c * 1024);
     };
     // A first-layer stage of a point tile is the 128-byte slice 128 q.. of
@@ -378,7 +387,7 @@ k_mlp_bf16(MlpArgs A)
     // v%8; rows past the live count repeat the last live row.  Offsets are
     // taken from the workgroup's first row, so the base is wave-uniform.
     const __amdgpu_buffer_rsrc_t xr = rsrc(reinterpret_cast<const uint8_t*>(A.x) + wg0 * (kDescPad * 2),
-                                           min(npts - wg0, (int64_t)(4 * 32 * PT)) * (kDescPad * 2));
+                                           min(npts - wg0, (int64_t)(NW * 32 * PT)) * (kDescPad * 2));
     uint32_t doff[PT][4];
 #pragma unroll
     for (int p = 0; p < PT; p++)
@@ -524,6 +533,18 @@ k_mlp_bf16(MlpArgs A)
                 const i16x8 v = __builtin_elementwise_max(__builtin_bit_cast(i16x8, f), i16x8{});
                 hin[kc][p] = __builtin_bit_cast(bf16x8, v);
             }
+        // With an odd number of K steps the second half of the last tile's
+        // accumulator is never read.  When the accumulators live in VGPRs (one
+        // point tile per wave), keep it allocated until the epilogue's end:
+        // otherwise its registers can be handed to the conversions above while
+        // the MFMA that writes them is still in flight, and its late write
+        // overwrites their results.  (With two tiles the accumulators are in
+        // AGPRs, which the conversions never write.)
+        if constexpr (KH % 2 == 1 && PT == 1) {
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int p = 0; p < PT; p++) keep_alive(acc[NO - 1][p]);
+        }
     };
     epilogue();
     wait_vm<0>();
@@ -620,22 +641,22 @@ k_mlp_bf16(MlpArgs A)
     }
 }
 
-template <int NO, int KH, int PT>
+template <int NO, int KH, int PT, int NW>
 static void launch_bf16_nt(const MlpArgs& a, hipStream_t s)
 {
-    const int per = 4 * 32 * PT;
-    hipLaunchKernelGGL((k_mlp_bf16<NO, KH, PT>), dim3((int)((a.npts + per - 1) / per)), dim3(256), 0, s, a);
+    const int per = NW * 32 * PT;
+    hipLaunchKernelGGL((k_mlp_bf16<NO, KH, PT, NW>), dim3((int)((a.npts + per - 1) / per)), dim3(64 * NW), 0, s, a);
 }
 
 static hipError_t launch_mlp_bf16(const MlpArgs& a, hipStream_t s)
 {
     switch (a.wpad) {
-    case 16: launch_bf16_nt<1, 1, 2>(a, s); break;
-    case 32: launch_bf16_nt<1, 2, 2>(a, s); break;
-    case 64: launch_bf16_nt<2, 4, 2>(a, s); break;
-    case 128: launch_bf16_nt<4, 8, 2>(a, s); break;
-    case 208: launch_bf16_nt<7, 13, 2>(a, s); break;
-    case 256: launch_bf16_nt<8, 16, 1>(a, s); break;
+    case 16: launch_bf16_nt<1, 1, 2, 4>(a, s); break;
+    case 32: launch_bf16_nt<1, 2, 2, 4>(a, s); break;
+    case 64: launch_bf16_nt<2, 4, 2, 4>(a, s); break;
+    case 128: launch_bf16_nt<4, 8, 2, 4>(a, s); break;
+    case 208: launch_bf16_nt<7, 13, 2, 4>(a, s); break;
+    case 256: launch_bf16_nt<8, 16, 1, 4>(a, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
