@@ -24,15 +24,16 @@
 // contraction, because that decision is discontinuous in the position.
 //
 // Work split.  A workgroup is one wave and holds kTP = 4 points; the 16 lanes
-// of a point share its work, so no stage waits for another wave.  Per layer a
-// lane evaluates up to three rows of 5 sites (one slab q, one lateral j,
-// i = -2..2): a row needs 4 rows of 6 path densities and 4 rows of 6
-// densities, read contiguously and interpolated with the shared bilinear
-// weights across rows, then linearly along the row.  Rows whose indices all
-// lie inside the field take a path without clamping; the others clamp every
-// index.  Each lane keeps its own running sums and maxima, reduced over the
-// point's 16 lanes by shuffles.
-//
+// of a point share its work, so no stage waits for another wave.  Per layer
+// the samples a point's sites need are first staged in LDS as small bricks:
+// the path densities around the point (index-clamped) from the per-light
+// path-density pairs, and for each slab the densities already interpolated
+// along the light axis from the light-axis density pairs, both as 48-byte
+// runs with one lane per brick row.  A lane then evaluates up to three rows of
+// 5 sites (one slab q, one lateral j, i = -2..2) from the bricks with the
+// shared weights.  Each lane keeps its own running sums and maxima, reduced
+// over the point's 16 lanes by shuffles.
+
 // Lattice layout for conv1.  Each 5-site row of the transmittance lattice is
 // stored as three 4-wide windows starting at i = 0, 1, 2 (the last padded with
 // a zero), so the 3 taps of a kernel row -- plus a fourth tap with zero weight
@@ -88,6 +89,7 @@ template <class E> struct FeatShared {
     SlabParams sp[kTP][9];
     float cb[kCbFloats];                       // the group's conv biases and attention weights
     uint16_t smask[kTP][kLayers][9];           // in-cube bits of every slab of every layer
+    uint16_t posoff[kY1Pos];                   // conv1: lattice offset of output position p (the 64th = the 63rd)
 };
 
 __device__ __forceinline__ double site_coord(double x, double scale, double qo, int i)
@@ -168,6 +170,16 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b)
 {
     bf16x2 v = {(__bf16)a, (__bf16)b};
     return __builtin_bit_cast(uint32_t, v);
+}
+
+// bfloat16 pair {lo, hi} rounded to nearest even, packed low half first: one
+// v_cvt_pk_bf16_f32, written as a vector conversion so that the compiler sees
+// it (and keeps the wait states an MFMA result needs before it is read)
+__device__ __forceinline__ uint32_t cvt_pk_bf16(float lo, float hi)
+{
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{lo, hi}, bf16x2v));
 }
 
 // The three 4-wide windows of a lattice row of 5 values.
@@ -297,6 +309,11 @@ k_features(FeatArgs A)
     }
 
     E* desc = reinterpret_cast<E*>(A.desc);
+
+    {
+        const int pc = lane < 63 ? lane : 62;
+        sh.posoff[lane] = (uint16_t)(((pc / 9) * 5 + (pc / 3) % 3) * kLatRow + (pc % 3) * 4);
+    }
 
     // conv1 A fragments of the current weight group (reloaded when it changes)
     constexpr int KC1 = 72 / M::KS + (72 % M::KS != 0);
@@ -604,64 +621,57 @@ k_features(FeatArgs A)
 
         // ---- conv1, two points per MFMA tile: out^T [16 x 16 positions] =
         // [W1 on K 0..35 | W1 on K 36..71] . [im2col of point tp0 ; of tp0 + 1]
-        // (rows 0-7: tp0's 8 channels, rows 8-15: tp0 + 1's)
+        // (rows 0-7: tp0's 8 channels, rows 8-15: tp0 + 1's), the bias as the
+        // C operand of the first K step
         {
-            float bias[4];
+            f32x4 bias;
 #pragma unroll
             for (int e = 0; e < 4; e++) bias[e] = cbl[(lg & 1) * 4 + e];
             // BF16: lane group lg reads the 4-slot groups g = kc*8 + 2lg + h of K
             // step kc; group g < 9 is tap-row g of tp0, 9 <= g < 18 tap-row g - 9
-            // of tp0 + 1, the rest is zero
+            // of tp0 + 1.  Groups g >= 18 meet zero weights: they read any lattice
+            // entry (all finite), which keeps every read unconditional.
             int goff[3][2];
 #pragma unroll
             for (int kc = 0; kc < 3; kc++)
 #pragma unroll
                 for (int h = 0; h < 2; h++) {
                     const int g = kc * 8 + 2 * (ln >> 4) + h;
-                    goff[kc][h] = g < 18 ? (g >= 9 ? kLatStride : 0) + taprow_off(g % 9) : -1;
+                    goff[kc][h] = g < 18 ? (g >= 9 ? kLatStride : 0) + taprow_off(g % 9) : 0;
                 }
-#pragma unroll 2
-            for (int tile = 0; tile < kTP * 2; tile++) {
-                const int tp0 = (tile >> 2) * 2, pos = (tile & 3) * 16 + lrl;
-                const int pc = pos < 63 ? pos : 62;
-                const int zp = pc / 9, yp = (pc / 3) % 3, xp = pc % 3;
-                const E* base = lat[tp0] + (zp * 5 + yp) * kLatRow + xp * 4;
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+            for (int tp0 = 0; tp0 < kTP; tp0 += 2)
+#pragma unroll
+            for (int t4 = 0; t4 < 4; t4++) {
+                const int pos = t4 * 16 + lrl;
+                const E* base = lat[tp0] + sh.posoff[pos];
+                f32x4 acc = bias;
                 if constexpr (PREC == kPrecFP32) {
                     // K step kc is the 4-slot group kc: tap-row kc % 9 of point tp0 + kc / 9
 #pragma unroll
                     for (int kc = 0; kc < KC1; kc++)
                         acc = M::mma(aw[kc], base[(kc >= 9 ? kLatStride : 0) + taprow_off(kc % 9) + lg], acc);
-                } else {
-                    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-                    // independent accumulators per K step, so the three MFMAs
-                    // issue back to back
-                    f32x4 part[KC1];
-#pragma unroll
-                    for (int kc = 0; kc < KC1; kc++) {
-                        u32x4 bv = {0u, 0u, 0u, 0u};
-#pragma unroll
-                        for (int h = 0; h < 2; h++)
-                            if (goff[kc][h] >= 0) {
-                                const uint2 r = *reinterpret_cast<const uint2*>(base + goff[kc][h]);
-                                bv[2 * h] = r.x;
-                                bv[2 * h + 1] = r.y;
-                            }
-                        part[kc] = M::mma(aw[kc], __builtin_bit_cast(bf16x8, bv), acc);
-                    }
-#pragma unroll
-                    for (int kc = 0; kc < KC1; kc++) acc += part[kc];
-                }
-                if (pos < 63) {
                     float v[4];
 #pragma unroll
-                    for (int e = 0; e < 4; e++) v[e] = fmaxf(acc[e] + bias[e], 0.f);
-                    E* dst = &y1[tp0 + (lg >> 1)][pos][(lg & 1) * 4];
-                    if constexpr (PREC == kPrecFP32) {
-                        *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
-                    } else {
-                        *reinterpret_cast<uint2*>(dst) = make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
+                    for (int e = 0; e < 4; e++) v[e] = fmaxf(acc[e], 0.f);
+                    if (pos < 63)
+                        *reinterpret_cast<float4*>(&y1[tp0 + (lg >> 1)][pos][(lg & 1) * 4]) =
+                            make_float4(v[0], v[1], v[2], v[3]);
+                } else {
+                    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+                    for (int kc = 0; kc < KC1; kc++) {
+                        const uint2 r0 = *reinterpret_cast<const uint2*>(base + goff[kc][0]);
+                        const uint2 r1 = *reinterpret_cast<const uint2*>(base + goff[kc][1]);
+                        const u32x4 bv = {r0.x, r0.y, r1.x, r1.y};
+                        acc = M::mma(aw[kc], __builtin_bit_cast(bf16x8, bv), acc);
                     }
+                    // ReLU after rounding, as a signed 16-bit max on the bfloat16
+                    // patterns (rounding keeps the sign); position 63 is padding
+                    typedef short i16x4 __attribute__((ext_vector_type(4)));
+                    const uint2 pk = make_uint2(cvt_pk_bf16(acc[0], acc[1]), cvt_pk_bf16(acc[2], acc[3]));
+                    const i16x4 rl = __builtin_elementwise_max(__builtin_bit_cast(i16x4, pk), i16x4{});
+                    *reinterpret_cast<uint2*>(&y1[tp0 + (lg >> 1)][pos][(lg & 1) * 4]) = __builtin_bit_cast(uint2, rl);
                 }
             }
         }

@@ -268,12 +268,14 @@ constexpr int kStage = 4;
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef short i16x8 __attribute__((ext_vector_type(8)));
 
-// bfloat16 pair {lo, hi} rounded to nearest even, packed low half first
+// bfloat16 pair {lo, hi} rounded to nearest even, packed low half first: one
+// v_cvt_pk_bf16_f32, written as a vector conversion so that the compiler sees
+// it (and keeps the wait states an MFMA result needs before it is read)
 __device__ __forceinline__ uint32_t cvt_pk_bf16(float lo, float hi)
 {
-    uint32_t r;
-    asm("v_cvt_pk_bf16_f32 %0, %1, %2" : "=v"(r) : "v"(lo), "v"(hi));
-    return r;
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{lo, hi}, bf16x2v));
 }
 
 __device__ __forceinline__ f32x16 mfma32(bf16x8 a, bf16x8 b, f32x16 c)
