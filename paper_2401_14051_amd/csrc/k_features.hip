@@ -90,6 +90,7 @@ template <class E> struct FeatShared {
     float cb[kCbFloats];                       // the group's conv biases and attention weights
     uint16_t smask[kTP][kLayers][9];           // in-cube bits of every slab of every layer
     uint16_t posoff[kY1Pos];                   // conv1: lattice offset of output position p (the 64th = the 63rd)
+    double qo[3][9];                           // the light's lattice offsets, per axis and slab
 };
 
 __device__ __forceinline__ double site_coord(double x, double scale, double qo, int i)
@@ -240,6 +241,16 @@ k_features(FeatArgs A)
     // device computed; workgroups past it leave at once)
     if (tile0 >= npts) return;
 
+    // tables read by every lane: the lattice offsets (a dynamic index into
+    // the kernel arguments would be a vector load from them at every use) and
+    // conv1's position offsets
+    if (lane < 27) sh.qo[lane / 9][lane % 9] = mv.qoff[lane / 9][lane % 9];
+    {
+        const int pc = lane < 63 ? lane : 62;
+        sh.posoff[lane] = (uint16_t)(((pc / 9) * 5 + (pc / 3) % 3) * kLatRow + (pc % 3) * 4);
+    }
+    __syncthreads();
+
     // ---- per point: position, phase features, transmittance to the light ----
     {
         const int pt = lg, sub = lr;
@@ -279,11 +290,11 @@ k_features(FeatArgs A)
             const int kk = e / 9, qi = e % 9;
             const double scale = ldexp(1.0 / mv.n0, kk);
             int mask = 0;
-            const double sa = site_coord_a(x[mv.a], scale, mv.qoff[mv.a][qi]);
+            const double sa = site_coord_a(x[mv.a], scale, sh.qo[mv.a][qi]);
             if (sa >= 0.0 && sa <= 1.0) mask |= 1 << 10;
             for (int i = -2; i <= 2; i++) {
-                const double sb = site_coord(x[mv.b], scale, mv.qoff[mv.b][qi], i);
-                const double sc = site_coord(x[mv.c], scale, mv.qoff[mv.c][qi], i);
+                const double sb = site_coord(x[mv.b], scale, sh.qo[mv.b][qi], i);
+                const double sc = site_coord(x[mv.c], scale, sh.qo[mv.c][qi], i);
                 if (sb >= 0.0 && sb <= 1.0) mask |= 1 << (i + 2);
                 if (sc >= 0.0 && sc <= 1.0) mask |= 1 << (i + 7);
             }
@@ -310,10 +321,6 @@ k_features(FeatArgs A)
 
     E* desc = reinterpret_cast<E*>(A.desc);
 
-    {
-        const int pc = lane < 63 ? lane : 62;
-        sh.posoff[lane] = (uint16_t)(((pc / 9) * 5 + (pc / 3) % 3) * kLatRow + (pc % 3) * 4);
-    }
 
     // conv1 A fragments of the current weight group (reloaded when it changes)
     constexpr int KC1 = 72 / M::KS + (72 % M::KS != 0);
@@ -349,8 +356,8 @@ k_features(FeatArgs A)
             const int spt = ln / 9, qi = ln % 9;
             const double x[3] = {px[spt][0], px[spt][1], px[spt][2]};
             const int mask = smask[spt][k][qi];
-            const double gb = x[mv.b] * nm - 0.5 + c * mv.qoff[mv.b][qi];
-            const double gc = x[mv.c] * nm - 0.5 + c * mv.qoff[mv.c][qi];
+            const double gb = x[mv.b] * nm - 0.5 + c * sh.qo[mv.b][qi];
+            const double gc = x[mv.c] * nm - 0.5 + c * sh.qo[mv.c][qi];
             const double ga = x[mv.a] * nm - 0.5;
             const double fb = floor(gb), fc = floor(gc), fa = floor(ga);
             SlabParams s;
