@@ -414,15 +414,17 @@ k_features(FeatArgs A)
                 if (rr < kDPairs) {
                     const int bp = rr / (kBrickJ * 3), loc = rr % (kBrickJ * 3);
                     const PointLayer Q = pl[bp];
-                    const int J = Q.ij - 4 + loc / 3;
+                    // J and V are clamped per row; only a row that crosses a U
+                    // edge is read sample by sample
+                    const int J = clampi(Q.ij - 4 + loc / 3, 0, nm - 1);
                     const int Vp = clampi(Q.iv - 1 + 2 * (loc % 3) - lv.vlo, 0, lv.nv);
                     const int U0 = Q.iu - 2 - lv.ulo;
-                    if (J >= 0 && J < nm && U0 >= 0 && U0 + 5 < lv.nu) {
+                    if (U0 >= 0 && U0 + 5 < lv.nu) {
                         const int o = ((J * (lv.nv + 1) + Vp) * lv.nu + U0) * 2;
 #pragma unroll
                         for (int e = 0; e < 12; e++) dv[it][e] = ldQ(o + e);
                     } else {
-                        const int ro = (clampi(J, 0, nm - 1) * (lv.nv + 1) + Vp) * lv.nu;
+                        const int ro = (J * (lv.nv + 1) + Vp) * lv.nu;
 #pragma unroll
                         for (int u = 0; u < 6; u++) {
                             const int o = (ro + clampi(U0 + u, 0, lv.nu - 1)) * 2;
@@ -525,14 +527,17 @@ k_features(FeatArgs A)
                     if (rr < kRRows) {
                         const int bp = rr / (9 * kBrickV), loc = rr % (9 * kBrickV);
                         const SlabParams S = sp[bp][loc / kBrickV];
-                        const int Ap = clampi(S.ia + 1, 0, nm), C = S.cbase + loc % kBrickV, B0 = S.bbase;
+                        // a and c are clamped per row; only a row that crosses a
+                        // b edge is read sample by sample
+                        const int Ap = clampi(S.ia + 1, 0, nm), C = clampi(S.cbase + loc % kBrickV, 0, nm - 1);
+                        const int B0 = S.bbase;
                         wav[h] = S.wa;
-                        if (C >= 0 && C < nm && B0 >= 0 && B0 + 5 < nm) {
+                        if (B0 >= 0 && B0 + 5 < nm) {
                             const int o = ((Ap * nm + C) * nm + B0) * 2;
 #pragma unroll
                             for (int e = 0; e < 12; e++) pr[h][e] = ldP(o + e);
                         } else {
-                            const int ro = (Ap * nm + clampi(C, 0, nm - 1)) * nm;
+                            const int ro = (Ap * nm + C) * nm;
 #pragma unroll
                             for (int u = 0; u < 6; u++) {
                                 const int o = (ro + clampi(B0 + u, 0, nm - 1)) * 2;
