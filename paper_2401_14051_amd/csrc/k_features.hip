@@ -265,16 +265,21 @@ k_features(FeatArgs A)
         const double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
         for (int d = 0; d < 3; d++) w[d] /= wn;
         const double wl = w[0] * mv.l[0] + w[1] * mv.l[1] + w[2] * mv.l[2];
+        // Phase features in FP32 through a denominator without cancellation:
+        // for unit vectors 1 + g^2 - 2g w.d = (1-|g|)^2 + |g| |w - sign(g) d|^2,
+        // every term non-negative, so a few roundings in relative terms;
+        // den^(-3/2) as rsq^3.  The centre site's table entry is (l, 1).
+        const float ga = fabsf(mv.g), gs = mv.g < 0.f ? -1.f : 1.f;
+        const float ca = (float)((1.0 - (double)ga) * (1.0 - (double)ga)), ck = (float)mv.hg_k;
+        const float wf[3] = {(float)w[0], (float)w[1], (float)w[2]};
         float phs = 0.f, phm = -INFINITY;
         for (int t = sub; t < kSites; t += 16) {
-            double P;
-            if (t == kSites / 2) {
-                P = hg64(mv, wl);
-            } else {
-                const double* dt = A.tab->dir[t];
-                P = hg64(mv, w[0] * dt[0] + w[1] * dt[1] + w[2] * dt[2]) * (double)A.tab->hg_dl[t];
-            }
-            float ph = log1pf((float)P);
+            const float4 e = A.tab->site[t];
+            const float dx = wf[0] - gs * e.x, dy = wf[1] - gs * e.y, dz = wf[2] - gs * e.z;
+            const float den = ca + ga * (dx * dx + dy * dy + dz * dz);
+            const float r = __builtin_amdgcn_rsqf(den);
+            const float P = ck * e.w * (r * r * r);
+            float ph = log1pf(P);
             phs += ph;
             phm = fmaxf(phm, ph);
             if (DBG && live) A.dbg_phi[p * kSites + t] = ph;

@@ -97,7 +97,8 @@ k_sweep(MediumView mv, SweepArgs sa)
 
 // Per-light lattice tables: unit offset directions d_t = o_t / |o_t| and the
 // incident-side phase HG(d_t . l) of the phase feature (eq. 8) for the
-// current g; the centre site (o = 0) has no direction.
+// current g.  The centre site (o = 0) has no direction; its phase feature is
+// HG(w . l), so it stores (l, 1).
 __global__ void k_site_tables(MediumView mv, SiteTables* tab)
 {
     const int t = threadIdx.x;
@@ -109,14 +110,13 @@ __global__ void k_site_tables(MediumView mv, SiteTables* tab)
     o[mv.c] += j;
     const double on = sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
     if (on == 0.0) {
-        for (int d = 0; d < 3; d++) tab->dir[t][d] = 0.0;
-        tab->hg_dl[t] = 0.f;
+        tab->site[t] = make_float4((float)mv.l[0], (float)mv.l[1], (float)mv.l[2], 1.f);
         return;
     }
     const double dl = (o[0] * mv.l[0] + o[1] * mv.l[1] + o[2] * mv.l[2]) / on;
     const double den = mv.hg_a - mv.hg_b * dl;
-    for (int d = 0; d < 3; d++) tab->dir[t][d] = o[d] / on;
-    tab->hg_dl[t] = (float)(mv.hg_k / (den * sqrt(den)));
+    tab->site[t] = make_float4((float)(o[0] / on), (float)(o[1] / on), (float)(o[2] / on),
+                               (float)(mv.hg_k / (den * sqrt(den))));
 }
 
 // Light-axis density pairs (a layout of the pyramid for the gather): for each

@@ -57,8 +57,9 @@ struct MediumView {
 
 // Per-light constant tables for the gather (one copy per medium).
 struct SiteTables {
-    double dir[kSites][3];     // unit lattice offset directions d_t (centre: 0)
-    float hg_dl[kSites];       // HG(d_t . l) for the current g (centre: unused)
+    // (d_t, HG(d_t . l)) per site: the unit lattice offset direction and the
+    // incident-side phase for the current g; the centre site holds (l, 1)
+    float4 site[kSites];
 };
 
 }  // namespace nis

@@ -60,7 +60,8 @@ def test_sweep_matches_oracle(ctx, light, n):
 
 
 @pytest.mark.parametrize("light,g", [((0.3, 0.9, 0.3), 0.85), ((-0.7, 0.2, 0.4), 0.5),
-                                     ((0.1, -0.3, -0.95), 0.95), ((1.0, 0.2, -0.3), 0.0)])
+                                     ((0.1, -0.3, -0.95), 0.95), ((1.0, 0.2, -0.3), 0.0),
+                                     ((0.2, 0.3, -0.9), -0.9)])
 def test_features_match_oracle(ctx, light, g):
     print("features light=%s g=%s" % (light, g), flush=True)
     d, pts, dirs = small_points()
