@@ -460,12 +460,26 @@ k_features(FeatArgs A)
         __syncthreads();
 
         // ---- transmittance lattice: up to three rows of 5 sites per lane --------
+        // (one loop per case, so that the single-voxel level's set-up is not
+        // paid on the other levels; exp(-coef D) as exp2 of one product)
         float ts = 0.f, tmx = -INFINITY;
-        for (int r = lrl; r < kRows; r += 16) {
-            const int qi = r / 5, jj = r % 5;
-            const int q = qi - 4, j = jj - 2;
-            float Dv[5];
-            if (c == 1) {
+        const float nl2c = -coef * 1.44269504088896341f;
+        auto emit = [&](int r, const float* Dv) __attribute__((always_inline)) {
+            float T[5];
+#pragma unroll
+            for (int i = 0; i < 5; i++) T[i] = __builtin_amdgcn_exp2f(nl2c * Dv[i]);
+            store_windows<E>(lat[pt] + r * kLatRow, T);
+            const int64_t p = tile0 + pt;
+#pragma unroll
+            for (int i = 0; i < 5; i++) {
+                ts += T[i];
+                tmx = fmaxf(tmx, T[i]);
+                if (DBG && p < npts) A.dbg_tbar[(p * kLayers + k) * kSites + r * 5 + i] = T[i];
+            }
+        };
+        if (c == 1) {
+            for (int r = lrl; r < kRows; r += 16) {
+                const int qi = r / 5, jj = r % 5, q = qi - 4;
                 // rows (J0, V0), (J0, V0+1), (J0+1, V0), (J0+1, V0+1) of the brick,
                 // J0 = ij - q -> bj = 4 - q, V0 = iv + j -> bv = j + 2
                 const float* b0 = &brick[pt][((4 - q) * kBrickV + jj) * kBrickU];
@@ -481,12 +495,18 @@ k_features(FeatArgs A)
                     d10[2 * h] = e10.x, d10[2 * h + 1] = e10.y;
                     d11[2 * h] = e11.x, d11[2 * h + 1] = e11.y;
                 }
+                float Dv[5];
                 row5(d00, d10, d01, d11, P.w00, P.w10, P.w01, P.w11, P.wu, Dv);
-            } else {
-                // c > 1 only on the single-voxel level (one slice): sites are c apart
-                const float* sl = &brick[0][0];   // the whole slice, staged above
+                emit(r, Dv);
+            }
+        } else {
+            // c > 1 only on the single-voxel level (one slice): sites are c apart
+            const float* sl = &brick[0][0];   // the whole slice, staged above
+            for (int r = lrl; r < kRows; r += 16) {
+                const int j = r % 5 - 2;
                 const int v0 = clampi(P.iv + c * j - lv.vlo, 0, lv.nv - 1) * lv.nu;
                 const int v1 = clampi(P.iv + c * j + 1 - lv.vlo, 0, lv.nv - 1) * lv.nu;
+                float Dv[5];
 #pragma unroll
                 for (int i = 0; i < 5; i++) {
                     const int u0 = clampi(P.iu + c * (i - 2) - lv.ulo, 0, lv.nu - 1);
@@ -496,17 +516,7 @@ k_features(FeatArgs A)
                     const float dd = lerpf(e0, e1, P.wv);
                     Dv[i] = lerpf(dd, dd, P.wj);
                 }
-            }
-            float T[5];
-#pragma unroll
-            for (int i = 0; i < 5; i++) T[i] = __expf(-coef * Dv[i]);
-            store_windows<E>(lat[pt] + r * kLatRow, T);
-            const int64_t p = tile0 + pt;
-#pragma unroll
-            for (int i = 0; i < 5; i++) {
-                ts += T[i];
-                tmx = fmaxf(tmx, T[i]);
-                if (DBG && p < npts) A.dbg_tbar[(p * kLayers + k) * kSites + r * 5 + i] = T[i];
+                emit(r, Dv);
             }
         }
         __syncthreads();   // the path-density bricks are dead
@@ -569,19 +579,32 @@ k_features(FeatArgs A)
         }
 
         // ---- density statistics over the site rows, one to three per lane -------
+        // (one loop per case: the single-voxel level reads its voxel once)
         float rs = 0.f, rmx = -INFINITY;
-        for (int r = lrl; r < kRows; r += 16) {
-            const int qi = r / 5, jj = r % 5;
-            const SlabParams S = sp[pt][qi];
-            float Rv[5];
-            if (nm == 1) {
-                const float r0 = ldR(0);
+        auto accum = [&](int r, int mask, const float* Rv) __attribute__((always_inline)) {
+            // in-cube bits of the row's sites: the slab, the lateral j, then each i
+            const int jj = r % 5;
+            const int m5 = ((mask >> 10) & (mask >> (jj + 5)) & 1) ? (mask & 31) : 0;
+            const int64_t p = tile0 + pt;
 #pragma unroll
-                for (int i = 0; i < 5; i++) Rv[i] = r0;
-            } else {
+            for (int i = 0; i < 5; i++) {
+                const float rv = (m5 >> i) & 1 ? Rv[i] : 0.f;
+                rs += rv;
+                rmx = fmaxf(rmx, rv);
+                if (DBG && p < npts) A.dbg_rho[(p * kLayers + k) * kSites + r * 5 + i] = rv;
+            }
+        };
+        if (nm == 1) {
+            const float r0 = ldR(0);
+            const float Rv[5] = {r0, r0, r0, r0, r0};
+            for (int r = lrl; r < kRows; r += 16) accum(r, sp[pt][r / 5].mask, Rv);
+        } else {
+            for (int r = lrl; r < kRows; r += 16) {
+                const int qi = r / 5, jj = r % 5;
+                const SlabParams S = sp[pt][qi];
                 // plane rows c = c0 + j and c + 1 of the slab's a-interpolated brick
                 const float* b0 = &brick[pt][(qi * kBrickV + jj) * kBrickU];
-                float e0[6], e1[6], bb[6];
+                float e0[6], e1[6], bb[6], Rv[5];
 #pragma unroll
                 for (int h = 0; h < 3; h++) {
                     const float2 f0 = reinterpret_cast<const float2*>(b0)[h];
@@ -593,16 +616,7 @@ k_features(FeatArgs A)
                 for (int u = 0; u < 6; u++) bb[u] = lerpf(e0[u], e1[u], S.wc);
 #pragma unroll
                 for (int i = 0; i < 5; i++) Rv[i] = lerpf(bb[i], bb[i + 1], S.wb);
-            }
-            // in-cube bits of the row's sites: the slab, the lateral j, then each i
-            const int m5 = ((S.mask >> 10) & (S.mask >> (jj + 5)) & 1) ? (S.mask & 31) : 0;
-            const int64_t p = tile0 + pt;
-#pragma unroll
-            for (int i = 0; i < 5; i++) {
-                const float rv = (m5 >> i) & 1 ? Rv[i] : 0.f;
-                rs += rv;
-                rmx = fmaxf(rmx, rv);
-                if (DBG && p < npts) A.dbg_rho[(p * kLayers + k) * kSites + r * 5 + i] = rv;
+                accum(r, S.mask, Rv);
             }
         }
 
