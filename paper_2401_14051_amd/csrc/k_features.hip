@@ -308,7 +308,7 @@ k_features(FeatArgs A)
             smask[pt][kk][qi] = (uint16_t)mask;
         }
         if (sub == 0) {
-            pfix[pt][0] = phs / kSites;
+            pfix[pt][0] = phs * (1.f / kSites);
             pfix[pt][1] = phm;
             pfix[pt][2] = (float)acos(fmin(1.0, fmax(-1.0, wl)));
             for (int d = 0; d < 3; d++) px[pt][d] = x[d];
@@ -630,8 +630,8 @@ k_features(FeatArgs A)
             tmx = fmaxf(tmx, __shfl_xor(tmx, o));
         }
         if (lr == 0) {
-            pstat[pt][0] = rs / kSites;
-            pstat[pt][2] = ts / kSites;
+            pstat[pt][0] = rs * (1.f / kSites);
+            pstat[pt][2] = ts * (1.f / kSites);
             pstat[pt][3] = rmx;
             pstat[pt][5] = tmx;
         } else if (lr == 1) {
@@ -743,7 +743,7 @@ k_features(FeatArgs A)
             const float* cb = cbl;
             const float *s1 = cb + 24, *c1 = cb + 88, *s2 = cb + 92, *c2 = cb + 156;
             const int o = lr;
-            zc[pt][o] = (H[pt][o][0] + H[pt][o][1] + H[pt][o][2] + H[pt][o][3] + H[pt][o][4]) / 5.f;
+            zc[pt][o] = (H[pt][o][0] + H[pt][o][1] + H[pt][o][2] + H[pt][o][3] + H[pt][o][4]) * 0.2f;
             __syncthreads();
             if (o < 4) {
                 float s = c1[o];
@@ -753,7 +753,8 @@ k_features(FeatArgs A)
             __syncthreads();
             float s = c2[o];
             for (int h = 0; h < 4; h++) s += s2[o * 4 + h] * hid[pt][h];
-            const float gate = 1.f / (1.f + expf(-s));
+            // sigmoid with the hardware exponential and reciprocal (each about 1 ulp)
+            const float gate = __builtin_amdgcn_rcpf(1.f + __expf(-s));
             // stage the 88 entries of the layer in the (now free) conv1 output
             E* stage = &y1[pt][0][0];
             float lmax = 0.f;
