@@ -74,8 +74,6 @@ template <class E> struct FeatShared {
         E lat[kTP][kLatStride];
         struct {
             float H[kTP][16][5];
-            float zc[kTP][16];
-            float hid[kTP][4];
         } se;
     } __attribute__((aligned(16))) u0;
     union {
@@ -219,8 +217,6 @@ k_features(FeatArgs A)
     float* cbl = sh.cb;
     uint16_t(*smask)[kLayers][9] = sh.smask;
     float(*H)[16][5] = sh.u0.se.H;
-    float(*zc)[16] = sh.u0.se.zc;
-    float(*hid)[4] = sh.u0.se.hid;
     float(*pstat)[kStats] = sh.pstat;
     float(*pfix)[3] = sh.pfix;
     double(*px)[3] = sh.px;
@@ -740,40 +736,48 @@ k_features(FeatArgs A)
 
         // ---- squeeze-excitation gate and the layer's descriptor entries ---------
         {
-            const float* cb = cbl;
-            const float *s1 = cb + 24, *c1 = cb + 88, *s2 = cb + 92, *c2 = cb + 156;
-            const int o = lr;
-            zc[pt][o] = (H[pt][o][0] + H[pt][o][1] + H[pt][o][2] + H[pt][o][3] + H[pt][o][4]) * 0.2f;
-            __syncthreads();
-            if (o < 4) {
-                float s = c1[o];
-                for (int i = 0; i < 16; i++) s += s1[o * 16 + i] * zc[pt][i];
-                hid[pt][o] = fmaxf(s, 0.f);
-            }
-            __syncthreads();
+            const float *s1 = cbl + 24, *c1 = cbl + 88, *s2 = cbl + 92, *c2 = cbl + 156;
+            const int o = lr, pbase = lane & ~15;
+            float hv[5];
+#pragma unroll
+            for (int z = 0; z < 5; z++) hv[z] = H[pt][o][z];
+            const float zo = (hv[0] + hv[1] + hv[2] + hv[3] + hv[4]) * 0.2f;   // squeeze of channel o
+            // hidden unit h = o % 4 over the inputs 4 (o/4) .. +3, summed over the
+            // point's four lanes with the same h: every lane then holds unit o % 4
+            const int h = o & 3, i0 = o & ~3;
+            float part = 0.f;
+#pragma unroll
+            for (int d = 0; d < 4; d++) part += s1[h * 16 + i0 + d] * __shfl(zo, pbase | (i0 + d));
+            part += __shfl_xor(part, 4);
+            part += __shfl_xor(part, 8);
+            const float hid_h = fmaxf(part + c1[h], 0.f);
             float s = c2[o];
-            for (int h = 0; h < 4; h++) s += s2[o * 4 + h] * hid[pt][h];
+#pragma unroll
+            for (int hh = 0; hh < 4; hh++) s += s2[o * 4 + hh] * __shfl(hid_h, pbase | hh);
             // sigmoid with the hardware exponential and reciprocal (each about 1 ulp)
             const float gate = __builtin_amdgcn_rcpf(1.f + __expf(-s));
             // stage the 88 entries of the layer in the (now free) conv1 output
             E* stage = &y1[pt][0][0];
+            const bool want_max = A.rowmax != nullptr;   // the FP8 backbone's row scales
             float lmax = 0.f;
 #pragma unroll
             for (int z = 0; z < 5; z++) {
-                const E qz = M::cvt(gate * H[pt][o][z]);
+                const E qz = M::cvt(gate * hv[z]);
                 stage[o * 5 + z] = qz;
-                lmax = fmaxf(lmax, fabsf((float)qz));
+                if (want_max) lmax = fmaxf(lmax, fabsf((float)qz));
             }
             if (o < kStats) {
                 const E qs = M::cvt(pstat[pt][o]);
                 stage[kFeat + o] = qs;
-                lmax = fmaxf(lmax, fabsf((float)qs));
+                if (want_max) lmax = fmaxf(lmax, fabsf((float)qs));
             }
             if (DBG && o < kStats && tile0 + pt < npts)
                 A.dbg_stats[((tile0 + pt) * kLayers + k) * kStats + o] = pstat[pt][o];
             // running maximum |entry| of the point's stored descriptor
-            for (int sft = 1; sft < 16; sft <<= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, sft));
-            row_absmax = fmaxf(row_absmax, lmax);
+            if (want_max) {
+                for (int sft = 1; sft < 16; sft <<= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, sft));
+                row_absmax = fmaxf(row_absmax, lmax);
+            }
             __syncthreads();
             // 16-byte stores of the staged rows (88 entries per point)
             constexpr int kVec = 16 / sizeof(E), kChunks = kPerLayer / kVec;
