@@ -70,12 +70,13 @@ def kernel_work(wl, levels, level_geom, npix, npts, width, n_linear, prec):
     esize = {"fp32": 4, "bf16": 2, "fp8": 2}[prec]     # the FP8 path stores the descriptor in BF16
     n0 = wl.n
     vox = [(n0 >> m) ** 3 for m in range(levels)]
-    samples = sum(nu * nv * n for (nu, nv, n) in level_geom)
+    pairs_v = sum(nu * (nv + 1) * n for (nu, nv, n) in level_geom)
     conv_flop = 2 * 12 * (504 * 27 + 80 * 216)                       # per point
     mlp_flop = 2 * (1057 * width + (n_linear - 2) * width * width + width)
     return {
         "pyramid": {"bytes": 4 * sum(vox[:-1]) + 4 * sum(vox[1:])},
-        "sweep": {"bytes": 4 * sum(vox) + 4 * samples},
+        # reads the pyramid, writes the path density as its pairs along V
+        "sweep": {"bytes": 4 * sum(vox) + 8 * pairs_v},
         "site_tables": {"bytes": 225 * 16},
         # rays: flag, point and direction per pixel; scan; compacted copies
         "raygen": {"bytes": npix * (4 + 12 + 12) + npix * 8 + npts * (12 + 12 + 4)},

@@ -319,6 +319,15 @@ int32_t nis_debug_path_density(nis_ctx *ctx, int32_t medium, int32_t level, floa
                                int64_t capacity, int32_t dims[5]);
 
 /*
+ * Runs the sweep if stale and copies level `level`'s path-density pairs to
+ * host: [J][V' = 0..n_V][U] float pairs (D(V'-1), D(V')) with V' - 1 and V'
+ * clamped into the level's ray range, the layout the gather reads (the same
+ * values as D, rearranged; eq. 1).  capacity counts floats and must be at
+ * least 2 n_J (n_V + 1) n_U, with the dims of nis_debug_path_density.
+ */
+int32_t nis_debug_path_pairs(nis_ctx *ctx, int32_t medium, int32_t level, float *out, int64_t capacity);
+
+/*
  * Gather stage on device arrays (synchronous): tbar/rho [n][12][225],
  * phi [n][225], stats [n][12][8], tp [n] (transmittance to the light),
  * f0 [n] (single-scatter term HG(w.l) T(p)).  Any output may be NULL.

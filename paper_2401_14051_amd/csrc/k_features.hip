@@ -133,20 +133,23 @@ __device__ __forceinline__ void sheared(const MediumView& mv, int nm, const doub
     Vf = g[mv.c] + Jf * mv.sc;
 }
 
-// index-clamped trilinear lookup in a path-density field D[J][V][U]
-__device__ __forceinline__ float sample_D(const float* __restrict__ D, const Level& lv, int U, int V,
+// Index-clamped trilinear lookup in a path-density field, read from its
+// pairs along V: pair V' = V + 1 (clamped into 0..n_V) holds D at the clamped
+// rows V and V + 1, the two rows the lookup interpolates between.
+__device__ __forceinline__ float sample_D(const float2* __restrict__ Q, const Level& lv, int U, int V,
                                           int J, float wu, float wv, float wj)
 {
-    int u0 = clampi(U - lv.ulo, 0, lv.nu - 1), u1 = clampi(U + 1 - lv.ulo, 0, lv.nu - 1);
-    int v0 = clampi(V - lv.vlo, 0, lv.nv - 1), v1 = clampi(V + 1 - lv.vlo, 0, lv.nv - 1);
-    int j0 = clampi(J, 0, lv.n - 1), j1 = clampi(J + 1, 0, lv.n - 1);
-    const int64_t plane = (int64_t)lv.nu * lv.nv;
-    const float* d0 = D + j0 * plane;
-    const float* d1 = D + j1 * plane;
-    float a00 = lerpf(d0[v0 * lv.nu + u0], d0[v0 * lv.nu + u1], wu);
-    float a01 = lerpf(d0[v1 * lv.nu + u0], d0[v1 * lv.nu + u1], wu);
-    float a10 = lerpf(d1[v0 * lv.nu + u0], d1[v0 * lv.nu + u1], wu);
-    float a11 = lerpf(d1[v1 * lv.nu + u0], d1[v1 * lv.nu + u1], wu);
+    const int u0 = clampi(U - lv.ulo, 0, lv.nu - 1), u1 = clampi(U + 1 - lv.ulo, 0, lv.nu - 1);
+    const int vp = clampi(V + 1 - lv.vlo, 0, lv.nv);
+    const int j0 = clampi(J, 0, lv.n - 1), j1 = clampi(J + 1, 0, lv.n - 1);
+    const int64_t qplane = (int64_t)lv.nu * (lv.nv + 1);
+    const float2* q0 = Q + j0 * qplane + (int64_t)vp * lv.nu;
+    const float2* q1 = Q + j1 * qplane + (int64_t)vp * lv.nu;
+    const float2 p00 = q0[u0], p10 = q0[u1], p01 = q1[u0], p11 = q1[u1];
+    float a00 = lerpf(p00.x, p10.x, wu);
+    float a01 = lerpf(p00.y, p10.y, wu);
+    float a10 = lerpf(p01.x, p11.x, wu);
+    float a11 = lerpf(p01.y, p11.y, wu);
     return lerpf(lerpf(a00, a01, wv), lerpf(a10, a11, wv), wj);
 }
 
@@ -314,7 +317,7 @@ k_features(FeatArgs A)
             double Uf, Vf, Jf;
             sheared(mv, l0.n, x, Uf, Vf, Jf);
             double fu = floor(Uf), fv = floor(Vf), fj = floor(Jf);
-            float D0 = sample_D(mv.D + l0.d_off, l0, (int)fu, (int)fv, (int)fj, (float)(Uf - fu),
+            float D0 = sample_D(mv.dpairs + l0.q_off, l0, (int)fu, (int)fv, (int)fj, (float)(Uf - fu),
                                 (float)(Vf - fv), (float)(Jf - fj));
             float T = expf(-mv.sigma_t * D0);
             A.f0[p] = (float)(hg64(mv, wl) * (double)T);
@@ -336,13 +339,17 @@ k_features(FeatArgs A)
         const int c = 1 << (k - m);
         const float coef = A.coef[k];
         const int grp = k < kDiffuse ? 0 : 1;
-        const int plane = lv.nu * lv.nv;
-        const int dsize = plane * nm, rsize = nm * nm * nm;
-        const __amdgpu_buffer_rsrc_t rD =
-            __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(mv.D + lv.d_off), 0, dsize * 4, kBufferFlags);
+        const int rsize = nm * nm * nm;
         const __amdgpu_buffer_rsrc_t rR =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(mv.rho + lv.rho_off), 0, rsize * 4, kBufferFlags);
-        auto ldD = [&](int o) { return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rD, o * 4, 0, 0)); };
+        // the path-density pairs of the level: below 2^32 bytes (the light's
+        // layout refuses larger fields), so sizes and offsets are unsigned
+        const uint32_t qrow = (uint32_t)lv.nu * (lv.nv + 1);
+        const __amdgpu_buffer_rsrc_t rQ =
+            __builtin_amdgcn_make_buffer_rsrc(mv.dpairs + lv.q_off, 0, (int)(qrow * nm * 8), kBufferFlags);
+        auto ldQ = [&](uint32_t o) {
+            return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rQ, (int)(o * 4), 0, 0));
+        };
         auto ldR = [&](int o) { return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rR, o * 4, 0, 0)); };
         __syncthreads();   // the previous layer's readers of the shared tables are done
         const int ln = opaque(lane), lrl = ln & 15;
@@ -406,9 +413,6 @@ k_features(FeatArgs A)
         if (c == 1) {
             // two V rows at a time from the path-density pairs: a pair row is 6
             // pairs, 48 contiguous bytes
-            const __amdgpu_buffer_rsrc_t rQ = __builtin_amdgcn_make_buffer_rsrc(
-                mv.dpairs + lv.q_off, 0, (lv.nv + 1) * lv.nu * nm * 8, kBufferFlags);
-            auto ldQ = [&](int o) { return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rQ, o * 4, 0, 0)); };
             constexpr int kDPairs = kTP * kBrickJ * (kBrickV / 2), kDIt = (kDPairs + 63) / 64;
             float dv[kDIt][12];
 #pragma unroll
@@ -423,14 +427,14 @@ k_features(FeatArgs A)
                     const int Vp = clampi(Q.iv - 1 + 2 * (loc % 3) - lv.vlo, 0, lv.nv);
                     const int U0 = Q.iu - 2 - lv.ulo;
                     if (U0 >= 0 && U0 + 5 < lv.nu) {
-                        const int o = ((J * (lv.nv + 1) + Vp) * lv.nu + U0) * 2;
+                        const uint32_t o = ((uint32_t)J * qrow + (uint32_t)Vp * lv.nu + U0) * 2;
 #pragma unroll
                         for (int e = 0; e < 12; e++) dv[it][e] = ldQ(o + e);
                     } else {
-                        const int ro = (J * (lv.nv + 1) + Vp) * lv.nu;
+                        const uint32_t ro = (uint32_t)J * qrow + (uint32_t)Vp * lv.nu;
 #pragma unroll
                         for (int u = 0; u < 6; u++) {
-                            const int o = (ro + clampi(U0 + u, 0, lv.nu - 1)) * 2;
+                            const uint32_t o = (ro + clampi(U0 + u, 0, lv.nu - 1)) * 2;
                             dv[it][2 * u] = ldQ(o);
                             dv[it][2 * u + 1] = ldQ(o + 1);
                         }
@@ -453,7 +457,10 @@ k_features(FeatArgs A)
                 }
             }
         } else {
-            for (int e = ln; e < dsize; e += 64) brick[0][e] = ldD(e);
+            // the 1^3 level's field is 1 slice of 3 x 3 rays; D(U, V) is the
+            // second member of pair V' = V
+            const int u = ln & 7, v = ln >> 3;
+            if (u < lv.nu && v < lv.nv) brick[0][v * lv.nu + u] = ldQ(((uint32_t)v * lv.nu + u) * 2 + 1);
         }
         __syncthreads();
 

@@ -5,93 +5,236 @@
 //
 // Sweep (eq. 1 with the extinction of eq. 15): for every level m and every
 // light-sheared ray (U,V) the kernel walks the n_m slices J from the
-// light-facing face and writes the path density
+// light-facing face and computes the path density
 //     D_m(U,V,J) = ds_m * ( sum_{J'<J} r(J') + r(J)/2 ),
 // where r(J) is the bilinear density on slice J at lateral index coordinates
 // (U - J sb, V - J sc), or 0 outside [-1/2, n_m - 1/2].  The graded
 // transmittance exp(-lambda^(m+1) sigma_t D) is applied at lookup time, so
-// the field does not depend on sigma_t.  The running sum is compensated
-// (Neumaier) float32.  One lane per ray, lanes along U: for a light dominated
-// by y or z the lateral axis b is x, so neighbouring lanes read neighbouring
-// voxels and write neighbouring D entries.
+// the field does not depend on sigma_t.  Running sums are compensated
+// (Neumaier) float32 within a segment of slices and double across segments.
+// D is stored only in the layout the gather reads, the pairs
+// (D(V'-1), D(V')) along V, V' = 0..n_V with both rows clamped into the ray
+// range: the pairs hold every value of D.  Lanes run along U: for a light dominated by y or z the lateral
+// axis b is x, so neighbouring lanes read neighbouring voxels and write
+// neighbouring entries.
 #include "launch_args.h"
 
 namespace nis {
 
+// One thread per two neighbouring coarse voxels along x (nc >= 2; the 1^3
+// level takes one thread): four 16-byte rows of the fine level in, one
+// 8-byte pair out.  Edges are powers of two, so the index splits by shifts.
 __global__ void __launch_bounds__(256)
-k_mip(const float* __restrict__ fine, float* __restrict__ coarse, int nc)
+k_mip(const float* __restrict__ fine, float* __restrict__ coarse, int nc, int lg)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t total = (int64_t)nc * nc * nc;
-    if (i >= total) return;
-    int x = (int)(i % nc);
-    int y = (int)((i / nc) % nc);
-    int z = (int)(i / ((int64_t)nc * nc));
-    int64_t nf = 2 * (int64_t)nc;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nf = 2 * nc;
+    if (nc == 1) {
+        if (i > 0) return;
+        const float* f = fine;
+        coarse[0] = (((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) * 0.125f;
+        return;
+    }
+    if (i >= (nc * nc * nc) >> 1) return;
+    const int x = (i & ((nc >> 1) - 1)) * 2, y = (i >> (lg - 1)) & (nc - 1), z = i >> (2 * lg - 1);
     const float* f = fine + ((2 * z) * nf + 2 * y) * nf + 2 * x;
-    float2 a = *reinterpret_cast<const float2*>(f);
-    float2 b = *reinterpret_cast<const float2*>(f + nf);
-    float2 c = *reinterpret_cast<const float2*>(f + nf * nf);
-    float2 d = *reinterpret_cast<const float2*>(f + nf * nf + nf);
-    float s = ((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y));
-    coarse[i] = s * 0.125f;
+    const float4 a = *reinterpret_cast<const float4*>(f);
+    const float4 b = *reinterpret_cast<const float4*>(f + nf);
+    const float4 c = *reinterpret_cast<const float4*>(f + nf * nf);
+    const float4 d = *reinterpret_cast<const float4*>(f + nf * nf + nf);
+    const float s0 = ((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y));
+    const float s1 = ((a.z + a.w) + (b.z + b.w)) + ((c.z + c.w) + (d.z + d.w));
+    *reinterpret_cast<float2*>(coarse + (z * nc + y) * nc + x) = make_float2(s0 * 0.125f, s1 * 0.125f);
 }
 
-// (U - J s) evaluated as a product then a difference, each rounded once: the
-// in-range test below must be decided exactly as the definition states it.
-__device__ __forceinline__ double lateral(int U, int J, double s)
-{
-#pragma clang fp contract(off)
-    return (double)U - (double)J * s;
-}
+// Work split of the sweep.  A workgroup owns a tile of 64 rays along U (one
+// per lane) by kSwRays rays along V, and its kSwWaves waves cut the slices
+// into consecutive segments of up to kSwSeg slices each (a chunk of kSwWaves
+// segments; finer levels take several chunks in turn).  Every wave keeps its
+// segment's samples in registers, sums them, and after one barrier starts its
+// running sums from the earlier segments' totals.  Each lane also samples the
+// ray just below its tile (V0 - 1), so that it can write the path-density
+// pairs (D(V'-1), D(V')) of its own rays whole; and since ray V+1 at slice J
+// samples the density rows one above those of ray V, the rays of a lane share
+// their row loads.
+constexpr int kSwRays = 4;
+constexpr int kSwSeg = 4;
+constexpr int kSwWaves = 8;
 
 struct SweepArgs {
-    int64_t ray_off[kMaxLevels + 1];   // prefix sums of rays per level
+    int blk_off[kMaxLevels + 1];   // prefix sums of workgroups per level
 };
 
-__global__ void __launch_bounds__(256)
+__device__ __forceinline__ void neumaier(float& sum, float& comp, float r)
+{
+    const float t = sum + r;
+    comp += fabsf(sum) >= fabsf(r) ? (sum - t) + r : (r - t) + sum;
+    sum = t;
+}
+
+constexpr int kBufFlags = 0x00020000;   // buffer resource word 3 for gfx9-family raw accesses
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__global__ void __launch_bounds__(64 * kSwWaves)
 k_sweep(MediumView mv, SweepArgs sa)
 {
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= sa.ray_off[mv.levels]) return;
+    constexpr int R = kSwRays, K = kSwRays + 1;   // rays written, rays sampled
+    __shared__ double tot[kSwWaves][K][64];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int bid = blockIdx.x;
     int m = 0;
-    while (m + 1 < mv.levels && gid >= sa.ray_off[m + 1]) m++;
+    while (m + 1 < mv.levels && bid >= sa.blk_off[m + 1]) m++;
     const Level lv = mv.lev[m];
-    int64_t local = gid - sa.ray_off[m];
-    int iu = (int)(local % lv.nu), iv = (int)(local / lv.nu);
-    int U = lv.ulo + iu, V = lv.vlo + iv;
-    const int n = lv.n;
-    const float* rho = mv.rho + lv.rho_off;
-    float* D = mv.D + lv.d_off + (int64_t)iv * lv.nu + iu;
-    const int64_t plane = (int64_t)lv.nu * lv.nv;
-    int64_t st[3] = {1, n, (int64_t)n * n};
-    const int64_t sta = st[mv.a], stb = st[mv.b], stc = st[mv.c];
+    const int local = bid - sa.blk_off[m];
+    const int tiles_u = (lv.nu + 63) >> 6;
+    const int iu = (local % tiles_u) * 64 + lane;
+    const int V0 = (local / tiles_u) * R;          // first ray written (local index)
+    const int n = lv.n, nu = lv.nu, nv = lv.nv;
+    const int seg = n >= kSwWaves * kSwSeg ? kSwSeg : (n >= kSwWaves ? n / kSwWaves : 1);
+    const int chunk = kSwWaves * seg;
+    auto stride = [n](int axis) { return axis == 0 ? 1 : axis == 1 ? n : n * n; };
+    const int sta = stride(mv.a) * 4, stb = stride(mv.b) * 4, stc = stride(mv.c) * 4;   // bytes
     const double hi = n - 0.5;
-    float sum = 0.f, comp = 0.f;
-#pragma unroll 4
-    for (int J = 0; J < n; J++) {
-        int ia = mv.sigma > 0 ? n - 1 - J : J;
-        double u = lateral(U, J, mv.sb);
-        double v = lateral(V, J, mv.sc);
-        float r = 0.f;
-        if (u >= -0.5 && u <= hi && v >= -0.5 && v <= hi) {
-            double fu = floor(u), fv = floor(v);
-            int u0 = (int)fu, v0 = (int)fv;
-            float wu = (float)(u - fu), wv = (float)(v - fv);
-            int u1 = min(u0 + 1, n - 1), v1 = min(v0 + 1, n - 1);
-            u0 = max(u0, 0);
-            v0 = max(v0, 0);
-            const float* s = rho + ia * sta;
-            float r00 = s[u0 * stb + v0 * stc], r10 = s[u1 * stb + v0 * stc];
-            float r01 = s[u0 * stb + v1 * stc], r11 = s[u1 * stb + v1 * stc];
-            float r0 = r00 + wu * (r10 - r00);
-            float r1 = r01 + wu * (r11 - r01);
-            r = r0 + wv * (r1 - r0);
+    const double dU = (double)(lv.ulo + iu), dV = (double)(lv.vlo + V0 - 1);   // sampled ray k is V = dV + k
+    const bool lane_out = iu < nu;
+    // byte sizes and offsets within a level stay below 2^32 (the light's
+    // layout refuses larger fields); unsigned, so that they wrap as the
+    // hardware's 32-bit buffer offsets do rather than overflow
+    const uint32_t qplane = (uint32_t)nu * (nv + 1) * 8;
+    const __amdgpu_buffer_rsrc_t rR = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(mv.rho + lv.rho_off), 0, (int)((uint32_t)n * n * n * 4), kBufFlags);
+    const __amdgpu_buffer_rsrc_t rQ =
+        __builtin_amdgcn_make_buffer_rsrc(mv.dpairs + lv.q_off, 0, (int)(n * qplane), kBufFlags);
+    auto ld = [&](int off) { return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rR, off, 0, 0)); };
+
+    // The K samples of slice J.  (U - J s) is a product then a difference,
+    // each rounded once (no contraction): the in-range test must be decided
+    // exactly as the definition states it.
+    auto sample = [&](int J, float (&r)[K]) {
+#pragma clang fp contract(off)
+        const int sl = (mv.sigma > 0 ? n - 1 - J : J) * sta;
+        const double pb = (double)J * mv.sb, pc = (double)J * mv.sc;
+        const double u = dU - pb;
+        const bool uin = u >= -0.5 && u <= hi;
+        const double fu = floor(u);
+        const float wu = (float)(u - fu);
+        const int u0 = (int)fu;
+        const int ou0 = sl + min(max(u0, 0), n - 1) * stb, ou1 = sl + min(max(u0 + 1, 0), n - 1) * stb;
+        double v[K];
+        int f[K];
+        bool in[K], any = false;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            v[k] = (dV + k) - pc;
+            f[k] = (int)floor(v[k]);
+            in[k] = uin && v[k] >= -0.5 && v[k] <= hi;
+            any |= in[k];
         }
-        D[J * plane] = lv.ds * ((sum + comp) + 0.5f * r);
-        float t = sum + r;
-        comp += fabsf(sum) >= fabsf(r) ? (sum - t) + r : (r - t) + sum;
-        sum = t;
+        float a[K + 1], b[K + 1];
+#pragma unroll
+        for (int q = 0; q <= K; q++) a[q] = b[q] = 0.f;
+        if (any) {
+#pragma unroll
+            for (int q = 0; q <= K; q++) {
+                const int oy = min(max(f[0] + q, 0), n - 1) * stc;
+                a[q] = ld(ou0 + oy);
+                b[q] = ld(ou1 + oy);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            float r00 = a[k], r10 = b[k], r01 = a[k + 1], r11 = b[k + 1];
+            if (in[k] && f[k] != f[0] + k) {
+                // the rows of ray k are not those of ray 0 shifted by k (a
+                // rounding of U - J s at another magnitude): load its own
+                const int oy0 = min(max(f[k], 0), n - 1) * stc, oy1 = min(max(f[k] + 1, 0), n - 1) * stc;
+                r00 = ld(ou0 + oy0);
+                r10 = ld(ou1 + oy0);
+                r01 = ld(ou0 + oy1);
+                r11 = ld(ou1 + oy1);
+            }
+            const float wv = (float)(v[k] - (double)f[k]);
+            const float r0 = r00 + wu * (r10 - r00);
+            const float r1 = r01 + wu * (r11 - r01);
+            r[k] = in[k] ? r0 + wv * (r1 - r0) : 0.f;
+        }
+    };
+
+    double carry[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) carry[k] = 0.0;
+    for (int J0 = 0; J0 < n; J0 += chunk) {
+        const int Js = J0 + w * seg;
+        const int cnt = min(seg, n - Js);   // slices of this wave's segment (may be <= 0)
+        float rs[kSwSeg][K];
+        float sm[K], cp[K];
+#pragma unroll
+        for (int k = 0; k < K; k++) sm[k] = cp[k] = 0.f;
+#pragma unroll
+        for (int j = 0; j < kSwSeg; j++) {
+            if (j < cnt) {
+                sample(Js + j, rs[j]);
+#pragma unroll
+                for (int k = 0; k < K; k++) neumaier(sm[k], cp[k], rs[j][k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; k++) tot[w][k][lane] = (double)sm[k] + (double)cp[k];
+        __syncthreads();
+        // this segment starts from the earlier chunks and the earlier segments
+        double P[K];
+#pragma unroll
+        for (int k = 0; k < K; k++) P[k] = carry[k];
+#pragma unroll 1
+        for (int q = 0; q < w; q++) {
+#pragma unroll
+            for (int k = 0; k < K; k++) P[k] += tot[q][k][lane];
+        }
+        if (J0 + chunk < n) {
+#pragma unroll
+            for (int k = 0; k < K; k++) carry[k] = P[k];
+#pragma unroll 1
+            for (int q = w; q < kSwWaves; q++) {
+#pragma unroll
+                for (int k = 0; k < K; k++) carry[k] += tot[q][k][lane];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            sm[k] = (float)P[k];
+            cp[k] = (float)(P[k] - (double)sm[k]);
+        }
+        const uint32_t o0 = ((uint32_t)V0 * nu + iu) * 8;   // pair of the first written ray at J = 0
+#pragma unroll
+        for (int j = 0; j < kSwSeg; j++) {
+            if (j < cnt) {
+                const int J = Js + j;
+                float d[K];
+#pragma unroll
+                for (int k = 0; k < K; k++) {
+                    d[k] = lv.ds * ((sm[k] + cp[k]) + 0.5f * rs[j][k]);
+                    neumaier(sm[k], cp[k], rs[j][k]);
+                }
+                if (lane_out) {
+#pragma unroll
+                    for (int k = 1; k < K; k++) {
+                        const int iv = V0 + k - 1;
+                        if (iv < nv) {
+                            const float dm = iv == 0 ? d[k] : d[k - 1];
+                            const uint32_t oq = J * qplane + o0 + (uint32_t)(k - 1) * nu * 8;
+                            __builtin_amdgcn_raw_buffer_store_b64(u32x2{__float_as_uint(dm), __float_as_uint(d[k])},
+                                                                  rQ, (int)oq, 0, 0);
+                            if (iv == nv - 1)
+                                __builtin_amdgcn_raw_buffer_store_b64(
+                                    u32x2{__float_as_uint(d[k]), __float_as_uint(d[k])}, rQ,
+                                    (int)(oq + (uint32_t)nu * 8), 0, 0);
+                        }
+                    }
+                }
+            }
+        }
+        if (J0 + chunk < n) __syncthreads();   // tot is rewritten by the next chunk
     }
 }
 
@@ -124,54 +267,52 @@ __global__ void k_site_tables(MediumView mv, SiteTables* tab)
 // a = A' along the light's dominant axis, each index clamped into [0, n-1],
 // stored with b fastest; so the two a-planes of a density row sit side by
 // side and a row of 6 pairs is 48 contiguous bytes whatever the light.
+// One thread per four neighbouring entries along b (n >= 4; smaller levels
+// one entry per thread): 16-byte loads of the two a-planes when b is x, two
+// 16-byte stores.
+template <int E>
 __global__ void __launch_bounds__(256)
-k_pairs(const float* __restrict__ rho, float2* __restrict__ out, int n, int a, int b, int c)
+k_pairs(const float* __restrict__ rho, float2* __restrict__ out, int n, int lg, int a, int b, int c)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)(n + 1) * n * n) return;
-    const int bb = (int)(i % n), cc = (int)((i / n) % n), ap = (int)(i / ((int64_t)n * n));
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ((n + 1) << (2 * lg)) / E) return;
+    const int lq = lg - (E == 4 ? 2 : 0);
+    const int bb = (t & ((n / E) - 1)) * E, cc = (t >> lq) & (n - 1), ap = t >> (lq + lg);
     const int a0 = ap - 1 < 0 ? 0 : ap - 1, a1 = ap > n - 1 ? n - 1 : ap;
-    int p0[3], p1[3];
-    p0[a] = a0, p1[a] = a1;
-    p0[b] = p1[b] = bb;
-    p0[c] = p1[c] = cc;
-    out[i] = make_float2(rho[((int64_t)p0[2] * n + p0[1]) * n + p0[0]], rho[((int64_t)p1[2] * n + p1[1]) * n + p1[0]]);
+    auto stride = [n](int axis) { return axis == 0 ? 1 : axis == 1 ? n : n * n; };
+    const int sa = stride(a), sb = stride(b), sc = stride(c);
+    const float* r0 = rho + a0 * sa + cc * sc + bb * sb;
+    const float* r1 = rho + a1 * sa + cc * sc + bb * sb;
+    float v0[E], v1[E];
+    if (E == 4 && b == 0) {
+        const float4 p = *reinterpret_cast<const float4*>(r0), q = *reinterpret_cast<const float4*>(r1);
+        v0[0] = p.x, v0[1] = p.y, v0[2] = p.z, v0[3] = p.w;
+        v1[0] = q.x, v1[1] = q.y, v1[2] = q.z, v1[3] = q.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; e++) v0[e] = r0[e * sb], v1[e] = r1[e * sb];
+    }
+    float2* o = out + ((ap << lg) + cc) * n + bb;
+    if (E == 4) {
+        reinterpret_cast<float4*>(o)[0] = make_float4(v0[0], v1[0], v0[1], v1[1]);
+        reinterpret_cast<float4*>(o)[1] = make_float4(v0[2], v1[2], v0[3], v1[3]);
+    } else {
+        o[0] = make_float2(v0[0], v1[0]);
+    }
 }
 
 hipError_t launch_pairs(const MediumView& mv, hipStream_t s)
 {
     for (int m = 0; m < mv.levels; m++) {
         const Level& lv = mv.lev[m];
-        const int64_t total = (int64_t)(lv.n + 1) * lv.n * lv.n;
-        const int blocks = (int)((total + 255) / 256);
-        hipLaunchKernelGGL(k_pairs, dim3(blocks), dim3(256), 0, s, mv.rho + lv.rho_off, mv.pairs + lv.p_off, lv.n,
-                           mv.a, mv.b, mv.c);
-    }
-    return hipGetLastError();
-}
-
-// Path-density pairs along V (a layout of D for the gather): entry (J, V', U),
-// V' = 0..nv, holds D at V = V'-1 and V = V', each index clamped into
-// [0, nv-1], so two neighbouring V rows of a brick are one contiguous run.
-__global__ void __launch_bounds__(256)
-k_dpairs(const float* __restrict__ D, float2* __restrict__ out, int n, int nv, int nu)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)n * (nv + 1) * nu) return;
-    const int u = (int)(i % nu), vp = (int)((i / nu) % (nv + 1)), j = (int)(i / ((int64_t)nu * (nv + 1)));
-    const int v0 = vp - 1 < 0 ? 0 : vp - 1, v1 = vp > nv - 1 ? nv - 1 : vp;
-    const float* row = D + (int64_t)j * nv * nu + u;
-    out[i] = make_float2(row[(int64_t)v0 * nu], row[(int64_t)v1 * nu]);
-}
-
-hipError_t launch_dpairs(const MediumView& mv, hipStream_t s)
-{
-    for (int m = 0; m < mv.levels; m++) {
-        const Level& lv = mv.lev[m];
-        const int64_t total = (int64_t)lv.n * (lv.nv + 1) * lv.nu;
-        const int blocks = (int)((total + 255) / 256);
-        hipLaunchKernelGGL(k_dpairs, dim3(blocks), dim3(256), 0, s, mv.D + lv.d_off, mv.dpairs + lv.q_off, lv.n, lv.nv,
-                           lv.nu);
+        const int lg = __builtin_ctz(lv.n);
+        const int total = (lv.n + 1) << (2 * lg);
+        if (lv.n >= 4)
+            hipLaunchKernelGGL(k_pairs<4>, dim3((total / 4 + 255) / 256), dim3(256), 0, s, mv.rho + lv.rho_off,
+                               mv.pairs + lv.p_off, lv.n, lg, mv.a, mv.b, mv.c);
+        else
+            hipLaunchKernelGGL(k_pairs<1>, dim3((total + 255) / 256), dim3(256), 0, s, mv.rho + lv.rho_off,
+                               mv.pairs + lv.p_off, lv.n, lg, mv.a, mv.b, mv.c);
     }
     return hipGetLastError();
 }
@@ -185,11 +326,10 @@ hipError_t launch_site_tables(const MediumView& mv, SiteTables* tab, hipStream_t
 hipError_t launch_pyramid(const float* rho, const Level* lev, int levels, hipStream_t s)
 {
     for (int m = 0; m + 1 < levels; m++) {
-        int nc = lev[m + 1].n;
-        int64_t total = (int64_t)nc * nc * nc;
-        int blocks = (int)((total + 255) / 256);
-        hipLaunchKernelGGL(k_mip, dim3(blocks), dim3(256), 0, s, rho + lev[m].rho_off,
-                           const_cast<float*>(rho) + lev[m + 1].rho_off, nc);
+        const int nc = lev[m + 1].n, lg = __builtin_ctz(nc);
+        const int threads = nc == 1 ? 1 : (nc * nc * nc) / 2;
+        hipLaunchKernelGGL(k_mip, dim3((threads + 255) / 256), dim3(256), 0, s, rho + lev[m].rho_off,
+                           const_cast<float*>(rho) + lev[m + 1].rho_off, nc, lg);
     }
     return hipGetLastError();
 }
@@ -197,12 +337,13 @@ hipError_t launch_pyramid(const float* rho, const Level* lev, int levels, hipStr
 hipError_t launch_sweep(const MediumView& mv, hipStream_t s)
 {
     SweepArgs sa;
-    sa.ray_off[0] = 0;
-    for (int m = 0; m < kMaxLevels; m++)
-        sa.ray_off[m + 1] = sa.ray_off[m] + (m < mv.levels ? (int64_t)mv.lev[m].nu * mv.lev[m].nv : 0);
-    int64_t total = sa.ray_off[mv.levels];
-    int blocks = (int)((total + 255) / 256);
-    hipLaunchKernelGGL(k_sweep, dim3(blocks), dim3(256), 0, s, mv, sa);
+    sa.blk_off[0] = 0;
+    for (int m = 0; m < kMaxLevels; m++) {
+        const Level& lv = mv.lev[m];
+        const int blocks = m < mv.levels ? ((lv.nu + 63) / 64) * ((lv.nv + kSwRays - 1) / kSwRays) : 0;
+        sa.blk_off[m + 1] = sa.blk_off[m] + blocks;
+    }
+    hipLaunchKernelGGL(k_sweep, dim3(sa.blk_off[mv.levels]), dim3(64 * kSwWaves), 0, s, mv, sa);
     return hipGetLastError();
 }
 

@@ -77,7 +77,6 @@ struct FrameBuffers {
 hipError_t launch_pyramid(const float* rho, const Level* lev, int levels, hipStream_t s);
 hipError_t launch_sweep(const MediumView& mv, hipStream_t s);
 hipError_t launch_pairs(const MediumView& mv, hipStream_t s);
-hipError_t launch_dpairs(const MediumView& mv, hipStream_t s);
 hipError_t launch_site_tables(const MediumView& mv, SiteTables* tab, hipStream_t s);
 hipError_t launch_features(int prec, const FeatArgs& a, hipStream_t s);
 hipError_t launch_desc_to_f32(int prec, const void* src, float* dst, int64_t n, hipStream_t s);

@@ -114,7 +114,6 @@ MediumView make_view(const Medium* M, const LightState* ls, const Params& P, con
     MediumView v;
     std::memset(&v, 0, sizeof(v));
     v.rho = M->rho.as<float>();
-    v.D = ls->D.as<float>();
     v.pairs = ls->P.as<float2>();
     v.dpairs = ls->DP.as<float2>();
     for (int m = 0; m < M->levels; m++) v.lev[m] = ls->lev[m];
@@ -174,7 +173,6 @@ void ensure_sweep(const Medium* M, LightState* ls, hipStream_t s)
     MediumView mv = make_view(M, ls, medium_params(M), nullptr);
     timed("sweep", s, [&] { return launch_sweep(mv, s); });
     timed("pairs", s, [&] { return launch_pairs(mv, s); });
-    timed("dpairs", s, [&] { return launch_dpairs(mv, s); });
     ls->stale = false;
     ls->swept_version = M->version;
 }
@@ -409,7 +407,7 @@ void light_layout(const Medium* M, const double l[3], LightState* ls)
     ls->sc = l[ls->c] / ls->la;
     for (int d = 0; d < 3; d++)
         for (int qi = 0; qi < 9; qi++) ls->qoff[d][qi] = (qi - 4) * l[d] / ls->la;
-    int64_t off = 0, poff = 0, qoff = 0;
+    int64_t poff = 0, qoff = 0;
     for (int m = 0; m < M->levels; m++) {
         Level& lv = ls->lev[m];
         lv = M->lev[m];
@@ -418,20 +416,17 @@ void light_layout(const Medium* M, const double l[3], LightState* ls)
         ray_range(ls->sc, lv.n, &lv.vlo, &vhi);
         lv.nu = uhi - lv.ulo + 1;
         lv.nv = vhi - lv.vlo + 1;
-        lv.d_off = off;
         lv.p_off = poff;
         lv.q_off = qoff;
         lv.ds = (float)((1.0 / lv.n) / ls->la);
         // the gather addresses each level's fields with 32-bit byte offsets
-        const int64_t dn = (int64_t)lv.nu * lv.nv * lv.n, pn = (int64_t)(lv.n + 1) * lv.n * lv.n;
+        const int64_t pn = (int64_t)(lv.n + 1) * lv.n * lv.n;
         const int64_t qn = (int64_t)lv.nu * (lv.nv + 1) * lv.n;
         if (qn * 8 >= ((int64_t)1 << 32) || pn * 8 >= ((int64_t)1 << 32) || (int64_t)lv.n * lv.n * lv.n * 4 >= ((int64_t)1 << 32))
             fail(NIS_E_UNSUPPORTED, "a level's fields exceed 4 GiB for this light (media up to 512^3 are served)");
-        off += dn;
         poff += pn;
         qoff += qn;
     }
-    ls->d_floats = off;
     ls->pair_count = poff;
     ls->dpair_count = qoff;
 }
@@ -439,7 +434,6 @@ void light_layout(const Medium* M, const double l[3], LightState* ls)
 void set_light_state(const Medium* M, const double l[3], LightState* ls)
 {
     light_layout(M, l, ls);
-    ls->D.reserve((size_t)ls->d_floats * sizeof(float), "path-density fields");
     ls->P.reserve((size_t)ls->pair_count * sizeof(float2), "light-axis density pairs");
     ls->DP.reserve((size_t)ls->dpair_count * sizeof(float2), "path-density pairs");
     ls->valid = true;
@@ -1050,10 +1044,37 @@ int32_t nis_debug_path_density(nis_ctx* ctx, int32_t medium, int32_t level, floa
         dims[3] = lv.vlo + lv.nv - 1;
         dims[4] = lv.n;
         if (!out) return;
-        int64_t count = (int64_t)lv.nu * lv.nv * lv.n;
+        const int64_t count = (int64_t)lv.nu * lv.nv * lv.n;
+        if (capacity < count) fail(NIS_E_INVALID, "output too small");
+        // D is stored only inside its pairs along V: D(V) is the second
+        // member of pair V' = V
+        std::vector<float2> q((size_t)lv.nu * (lv.nv + 1) * lv.n);
+        hip_check(hipStreamSynchronize(ctx->stream), "sync");
+        hip_check(hipMemcpy(q.data(), M->light.DP.as<float2>() + lv.q_off, q.size() * sizeof(float2),
+                            hipMemcpyDeviceToHost),
+                  "download");
+        for (int64_t j = 0; j < lv.n; j++)
+            for (int64_t v = 0; v < lv.nv; v++)
+                for (int64_t u = 0; u < lv.nu; u++)
+                    out[(j * lv.nv + v) * lv.nu + u] = q[(size_t)((j * (lv.nv + 1) + v) * lv.nu + u)].y;
+    });
+}
+
+int32_t nis_debug_path_pairs(nis_ctx* ctx, int32_t medium, int32_t level, float* out, int64_t capacity)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        Medium* M = get_medium(ctx, medium);
+        if (!out) fail(NIS_E_INVALID, "out is NULL");
+        if (level < 0 || level >= M->levels) fail(NIS_E_INVALID, "no such level");
+        hip_check(hipDeviceSynchronize(), "sync");
+        ensure_sweep(M, &M->light, ctx->stream);
+        const Level& lv = M->light.lev[level];
+        const int64_t count = 2 * (int64_t)lv.nu * (lv.nv + 1) * lv.n;
         if (capacity < count) fail(NIS_E_INVALID, "output too small");
         hip_check(hipStreamSynchronize(ctx->stream), "sync");
-        hip_check(hipMemcpy(out, M->light.D.as<float>() + lv.d_off, (size_t)count * sizeof(float),
+        hip_check(hipMemcpy(out, M->light.DP.as<float2>() + lv.q_off, (size_t)count * sizeof(float),
                             hipMemcpyDeviceToHost),
                   "download");
     });

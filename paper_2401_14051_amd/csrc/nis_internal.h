@@ -27,7 +27,6 @@ struct Level {
     int ulo, vlo;       // first ray indices along the lateral axes b, c
     int nu, nv;         // ray counts
     int64_t rho_off;    // offset of the level in the density pyramid
-    int64_t d_off;      // offset of the level's D[J][V][U] field
     int64_t p_off;      // offset (in pairs) of the level's light-axis density pairs
     int64_t q_off;      // offset (in pairs) of the level's path-density pairs
     float ds;           // slice step along the ray, h_m / |l_a|
@@ -38,7 +37,6 @@ struct MediumView {
     const float* rho;   // density pyramid
     float2* pairs;      // per level [A' = 0..n][c][b]: (rho(a = A'-1), rho(a = A')), index-clamped
     float2* dpairs;     // per level [J][V' = 0..nv][U]: (D(V'-1), D(V')), index-clamped
-    float* D;           // path density fields
     Level lev[kMaxLevels];
     int levels;
     int n0;             // finest edge

@@ -81,6 +81,7 @@ _SIGNATURES = {
     "nis_medium_info": [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i64)],
     "nis_debug_pyramid": [_vp, _i32, _vp, _i64],
     "nis_debug_path_density": [_vp, _i32, _i32, _vp, _i64, ctypes.POINTER(_i32)],
+    "nis_debug_path_pairs": [_vp, _i32, _i32, _vp, _i64],
     "nis_debug_features": [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp],
     "nis_debug_network": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
     "nis_frame_points": [_vp, _i32, ctypes.POINTER(nis_camera), _u64, _vp, _vp, _vp, _vp, _vp],
@@ -399,6 +400,15 @@ class Context:
         out = np.empty(nu * nv * nj, np.float32)
         _check(_lib.nis_debug_path_density(self.h, medium, level, _ptr(out), out.size, dims))
         return out.reshape(nj, nv, nu), (dims[0], dims[1], dims[2], dims[3])
+
+    def path_pairs(self, medium, level):
+        """Path-density pairs of one level as [J][V' = 0..n_V][U][2]."""
+        dims = (_i32 * 5)()
+        _check(_lib.nis_debug_path_density(self.h, medium, level, None, 0, dims))
+        nu, nv, nj = dims[1] - dims[0] + 1, dims[3] - dims[2] + 1, dims[4]
+        out = np.empty(2 * nu * (nv + 1) * nj, np.float32)
+        _check(_lib.nis_debug_path_pairs(self.h, medium, level, _ptr(out), out.size))
+        return out.reshape(nj, nv + 1, nu, 2)
 
     def features(self, medium, points, dirs):
         """Gather-stage outputs for torch device tensors (returns torch tensors)."""

@@ -43,9 +43,17 @@ def test_pyramid_matches_oracle(ctx, n):
     ctx.unload_medium(mid)
 
 
-@pytest.mark.parametrize("light", LIGHTS)
-@pytest.mark.parametrize("n", [8, 32])
-def test_sweep_matches_oracle(ctx, light, n):
+# (n, light): every test light at two sizes; lights whose shear times a slice
+# index lands a hair above an integer, so that the rows of neighbouring rays
+# are not one apart at every magnitude (the sweep's row-sharing exception);
+# and the frame's size, whose slices take two chunks of the sweep's segments.
+SWEEP_CASES = ([(n, light) for n in (8, 32) for light in LIGHTS]
+               + [(32, (-0.9583333134651184, 1.0, 0.375)), (32, (-0.9375, 1.0, 0.4375)),
+                  (128, (0.3, 0.9, 0.3)), (256, (0.3, 0.9, 0.3)), (256, (1.0, 0.2, -0.3))])
+
+
+@pytest.mark.parametrize("n,light", SWEEP_CASES)
+def test_sweep_matches_oracle(ctx, n, light):
     print("sweep n=%d light=%s" % (n, light), flush=True)
     rho = medium.fbm_cloud(n, seed=3)
     s = Scene(ctx, rho, light)
@@ -56,6 +64,12 @@ def test_sweep_matches_oracle(ctx, light, n):
         assert got.shape == ref.shape
         scale = max(ref.max(), 1e-30)
         np.testing.assert_allclose(got, ref, rtol=0, atol=2e-6 * scale)
+        # the gather's pairs along V hold the same values, index-clamped
+        pairs = ctx.path_pairs(s.mid, m)
+        nv = got.shape[1]
+        vp = np.arange(nv + 1)
+        np.testing.assert_array_equal(pairs[..., 0], got[:, np.clip(vp - 1, 0, nv - 1), :])
+        np.testing.assert_array_equal(pairs[..., 1], got[:, np.clip(vp, 0, nv - 1), :])
     s.close()
 
 
