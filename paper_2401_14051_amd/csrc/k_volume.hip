@@ -56,7 +56,9 @@ k_mip(const float* __restrict__ fine, float* __restrict__ coarse, int nc, int lg
 // ray just below its tile (V0 - 1), so that it can write the path-density
 // pairs (D(V'-1), D(V')) of its own rays whole; and since ray V+1 at slice J
 // samples the density rows one above those of ray V, the rays of a lane share
-// their row loads.
+// their row loads.  The pairs leave as non-temporal stores: they are read
+// back only by the gather, and cached dirty lines of them would otherwise be
+// written back during the passes that follow.
 constexpr int kSwRays = 4;
 constexpr int kSwSeg = 4;
 constexpr int kSwWaves = 8;
@@ -73,6 +75,7 @@ __device__ __forceinline__ void neumaier(float& sum, float& comp, float r)
 }
 
 constexpr int kBufFlags = 0x00020000;   // buffer resource word 3 for gfx9-family raw accesses
+constexpr int kStream = 2;               // cache policy of a buffer access: non-temporal
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 __global__ void __launch_bounds__(64 * kSwWaves)
@@ -107,6 +110,10 @@ k_sweep(MediumView mv, SweepArgs sa)
     const __amdgpu_buffer_rsrc_t rQ =
         __builtin_amdgcn_make_buffer_rsrc(mv.dpairs + lv.q_off, 0, (int)(n * qplane), kBufFlags);
     auto ld = [&](int off) { return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rR, off, 0, 0)); };
+    // When the lateral axis b is x, the two samples u0, u0+1 of a density row
+    // are adjacent floats: one 8-byte load from clamp(u0, 0, n-2) then holds
+    // both clamped samples, and u0 alone picks which member each one is.
+    const bool wide = stb == 4 && n >= 2;
 
     // The K samples of slice J.  (U - J s) is a product then a difference,
     // each rounded once (no contraction): the in-range test must be decided
@@ -120,7 +127,10 @@ k_sweep(MediumView mv, SweepArgs sa)
         const double fu = floor(u);
         const float wu = (float)(u - fu);
         const int u0 = (int)fu;
-        const int ou0 = sl + min(max(u0, 0), n - 1) * stb, ou1 = sl + min(max(u0 + 1, 0), n - 1) * stb;
+        const int cu0 = min(max(u0, 0), n - 1), cu1 = min(max(u0 + 1, 0), n - 1);
+        const int ou0 = sl + cu0 * stb, ou1 = sl + cu1 * stb;
+        const int cb = min(max(u0, 0), n - 2), ob = sl + cb * 4;
+        const bool hiA = cu0 != cb, hiB = cu1 != cb;
         double v[K];
         int f[K];
         bool in[K], any = false;
@@ -134,7 +144,15 @@ k_sweep(MediumView mv, SweepArgs sa)
         float a[K + 1], b[K + 1];
 #pragma unroll
         for (int q = 0; q <= K; q++) a[q] = b[q] = 0.f;
-        if (any) {
+        if (any && wide) {
+#pragma unroll
+            for (int q = 0; q <= K; q++) {
+                const int oy = min(max(f[0] + q, 0), n - 1) * stc;
+                const u32x2 p = __builtin_amdgcn_raw_buffer_load_b64(rR, ob + oy, 0, 0);
+                a[q] = __uint_as_float(hiA ? p.y : p.x);
+                b[q] = __uint_as_float(hiB ? p.y : p.x);
+            }
+        } else if (any) {
 #pragma unroll
             for (int q = 0; q <= K; q++) {
                 const int oy = min(max(f[0] + q, 0), n - 1) * stc;
@@ -224,11 +242,11 @@ k_sweep(MediumView mv, SweepArgs sa)
                             const float dm = iv == 0 ? d[k] : d[k - 1];
                             const uint32_t oq = J * qplane + o0 + (uint32_t)(k - 1) * nu * 8;
                             __builtin_amdgcn_raw_buffer_store_b64(u32x2{__float_as_uint(dm), __float_as_uint(d[k])},
-                                                                  rQ, (int)oq, 0, 0);
+                                                                  rQ, (int)oq, 0, kStream);
                             if (iv == nv - 1)
                                 __builtin_amdgcn_raw_buffer_store_b64(
                                     u32x2{__float_as_uint(d[k]), __float_as_uint(d[k])}, rQ,
-                                    (int)(oq + (uint32_t)nu * 8), 0, 0);
+                                    (int)(oq + (uint32_t)nu * 8), 0, kStream);
                         }
                     }
                 }
@@ -292,10 +310,13 @@ k_pairs(const float* __restrict__ rho, float2* __restrict__ out, int n, int lg, 
 #pragma unroll
         for (int e = 0; e < E; e++) v0[e] = r0[e * sb], v1[e] = r1[e * sb];
     }
+    // non-temporal stores: the pairs are read back only by the gather, long
+    // after this pass, so they should not displace cached lines on the way
     float2* o = out + ((ap << lg) + cc) * n + bb;
     if (E == 4) {
-        reinterpret_cast<float4*>(o)[0] = make_float4(v0[0], v1[0], v0[1], v1[1]);
-        reinterpret_cast<float4*>(o)[1] = make_float4(v0[2], v1[2], v0[3], v1[3]);
+        typedef float f32x4 __attribute__((ext_vector_type(4)));
+        __builtin_nontemporal_store(f32x4{v0[0], v1[0], v0[1], v1[1]}, reinterpret_cast<f32x4*>(o));
+        __builtin_nontemporal_store(f32x4{v0[2], v1[2], v0[3], v1[3]}, reinterpret_cast<f32x4*>(o) + 1);
     } else {
         o[0] = make_float2(v0[0], v1[0]);
     }
