@@ -321,9 +321,10 @@ int32_t nis_debug_path_density(nis_ctx *ctx, int32_t medium, int32_t level, floa
 /*
  * Runs the sweep if stale and copies level `level`'s path-density pairs to
  * host: [J][V' = 0..n_V][U] float pairs (D(V'-1), D(V')) with V' - 1 and V'
- * clamped into the level's ray range, the layout the gather reads (the same
- * values as D, rearranged; eq. 1).  capacity counts floats and must be at
- * least 2 n_J (n_V + 1) n_U, with the dims of nis_debug_path_density.
+ * clamped into the level's ray range: the layout the gather reads, without
+ * its padding rays along U (the same values as D, rearranged; eq. 1).
+ * capacity counts floats and must be at least 2 n_J (n_V + 1) n_U, with the
+ * dims of nis_debug_path_density.
  */
 int32_t nis_debug_path_pairs(nis_ctx *ctx, int32_t medium, int32_t level, float *out, int64_t capacity);
 

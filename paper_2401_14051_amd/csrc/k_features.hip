@@ -422,7 +422,8 @@ k_features(FeatArgs A)
                     const int bp = rr / (kBrickJ * 3), loc = rr % (kBrickJ * 3);
                     const PointLayer Q = pl[bp];
                     // J and V are clamped per row; only a row that crosses a U
-                    // edge is read sample by sample
+                    // edge of the padded field (none does for a point inside
+                    // the cube) is read sample by sample
                     const int J = clampi(Q.ij - 4 + loc / 3, 0, nm - 1);
                     const int Vp = clampi(Q.iv - 1 + 2 * (loc % 3) - lv.vlo, 0, lv.nv);
                     const int U0 = Q.iu - 2 - lv.ulo;
@@ -533,8 +534,9 @@ k_features(FeatArgs A)
         // pairs, 48 contiguous bytes.  One lane per row; loads are issued two
         // rows at a time.
         if (nm > 1) {
+            const int nb = nm + 2 * kPairPad;   // stored row length of the pairs
             const __amdgpu_buffer_rsrc_t rP = __builtin_amdgcn_make_buffer_rsrc(
-                mv.pairs + lv.p_off, 0, (nm + 1) * nm * nm * 8, kBufferFlags);
+                mv.pairs + lv.p_off, 0, (nm + 1) * nm * nb * 8, kBufferFlags);
             auto ldP = [&](int o) { return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rP, o * 4, 0, 0)); };
             constexpr int kRRows = kTP * 9 * kBrickV, kRIt = (kRRows + 63) / 64;
 #pragma unroll
@@ -547,17 +549,18 @@ k_features(FeatArgs A)
                     if (rr < kRRows) {
                         const int bp = rr / (9 * kBrickV), loc = rr % (9 * kBrickV);
                         const SlabParams S = sp[bp][loc / kBrickV];
-                        // a and c are clamped per row; only a row that crosses a
-                        // b edge is read sample by sample
+                        // a and c are clamped per row; a row within the padded
+                        // b range (every row of an in-cube point) is one run,
+                        // others are read sample by sample
                         const int Ap = clampi(S.ia + 1, 0, nm), C = clampi(S.cbase + loc % kBrickV, 0, nm - 1);
                         const int B0 = S.bbase;
                         wav[h] = S.wa;
-                        if (B0 >= 0 && B0 + 5 < nm) {
-                            const int o = ((Ap * nm + C) * nm + B0) * 2;
+                        if (B0 >= -kPairPad && B0 + 5 < nm + kPairPad) {
+                            const int o = ((Ap * nm + C) * nb + kPairPad + B0) * 2;
 #pragma unroll
                             for (int e = 0; e < 12; e++) pr[h][e] = ldP(o + e);
                         } else {
-                            const int ro = (Ap * nm + C) * nm;
+                            const int ro = (Ap * nm + C) * nb + kPairPad;
 #pragma unroll
                             for (int u = 0; u < 6; u++) {
                                 const int o = (ro + clampi(B0 + u, 0, nm - 1)) * 2;

@@ -281,10 +281,11 @@ __global__ void k_site_tables(MediumView mv, SiteTables* tab)
 }
 
 // Light-axis density pairs (a layout of the pyramid for the gather): for each
-// level, entry (A', c, b), A' = 0..n, holds the densities at a = A'-1 and
-// a = A' along the light's dominant axis, each index clamped into [0, n-1],
-// stored with b fastest; so the two a-planes of a density row sit side by
-// side and a row of 6 pairs is 48 contiguous bytes whatever the light.
+// level, entry (A', c, b), A' = 0..n, b = -kPairPad..n-1+kPairPad, holds the
+// densities at a = A'-1 and a = A' along the light's dominant axis, each
+// index (b too) clamped into [0, n-1], stored with b fastest; so the two
+// a-planes of a density row sit side by side and a row of 6 pairs is 48
+// contiguous bytes whatever the light.
 // One thread per four neighbouring entries along b (n >= 4; smaller levels
 // one entry per thread): 16-byte loads of the two a-planes when b is x, two
 // 16-byte stores.
@@ -312,7 +313,14 @@ k_pairs(const float* __restrict__ rho, float2* __restrict__ out, int n, int lg, 
     }
     // non-temporal stores: the pairs are read back only by the gather, long
     // after this pass, so they should not displace cached lines on the way
-    float2* o = out + ((ap << lg) + cc) * n + bb;
+    const int nb = n + 2 * kPairPad;
+    float2* row = out + ((ap << lg) + cc) * nb;
+    float2* o = row + kPairPad + bb;
+    // the padding entries of the row repeat its end samples
+    if (bb == 0)
+        for (int e = 0; e < kPairPad; e++) row[e] = make_float2(v0[0], v1[0]);
+    if (bb + E == n)
+        for (int e = 0; e < kPairPad; e++) row[kPairPad + n + e] = make_float2(v0[E - 1], v1[E - 1]);
     if (E == 4) {
         typedef float f32x4 __attribute__((ext_vector_type(4)));
         __builtin_nontemporal_store(f32x4{v0[0], v1[0], v0[1], v1[1]}, reinterpret_cast<f32x4*>(o));

@@ -414,13 +414,15 @@ void light_layout(const Medium* M, const double l[3], LightState* ls)
         int uhi, vhi;
         ray_range(ls->sb, lv.n, &lv.ulo, &uhi);
         ray_range(ls->sc, lv.n, &lv.vlo, &vhi);
+        lv.ulo -= kRayPad;
+        uhi += kRayPad;
         lv.nu = uhi - lv.ulo + 1;
         lv.nv = vhi - lv.vlo + 1;
         lv.p_off = poff;
         lv.q_off = qoff;
         lv.ds = (float)((1.0 / lv.n) / ls->la);
         // the gather addresses each level's fields with 32-bit byte offsets
-        const int64_t pn = (int64_t)(lv.n + 1) * lv.n * lv.n;
+        const int64_t pn = (int64_t)(lv.n + 1) * lv.n * (lv.n + 2 * kPairPad);
         const int64_t qn = (int64_t)lv.nu * (lv.nv + 1) * lv.n;
         if (qn * 8 >= ((int64_t)1 << 32) || pn * 8 >= ((int64_t)1 << 32) || (int64_t)lv.n * lv.n * lv.n * 4 >= ((int64_t)1 << 32))
             fail(NIS_E_UNSUPPORTED, "a level's fields exceed 4 GiB for this light (media up to 512^3 are served)");
@@ -1038,13 +1040,15 @@ int32_t nis_debug_path_density(nis_ctx* ctx, int32_t medium, int32_t level, floa
         hip_check(hipDeviceSynchronize(), "sync");   // the debug calls see all earlier work
         ensure_sweep(M, &M->light, ctx->stream);
         const Level& lv = M->light.lev[level];
-        dims[0] = lv.ulo;
-        dims[1] = lv.ulo + lv.nu - 1;
+        // the rays of the definition, without the layout's padding
+        const int nu = lv.nu - 2 * kRayPad;
+        dims[0] = lv.ulo + kRayPad;
+        dims[1] = lv.ulo + kRayPad + nu - 1;
         dims[2] = lv.vlo;
         dims[3] = lv.vlo + lv.nv - 1;
         dims[4] = lv.n;
         if (!out) return;
-        const int64_t count = (int64_t)lv.nu * lv.nv * lv.n;
+        const int64_t count = (int64_t)nu * lv.nv * lv.n;
         if (capacity < count) fail(NIS_E_INVALID, "output too small");
         // D is stored only inside its pairs along V: D(V) is the second
         // member of pair V' = V
@@ -1055,8 +1059,8 @@ int32_t nis_debug_path_density(nis_ctx* ctx, int32_t medium, int32_t level, floa
                   "download");
         for (int64_t j = 0; j < lv.n; j++)
             for (int64_t v = 0; v < lv.nv; v++)
-                for (int64_t u = 0; u < lv.nu; u++)
-                    out[(j * lv.nv + v) * lv.nu + u] = q[(size_t)((j * (lv.nv + 1) + v) * lv.nu + u)].y;
+                for (int64_t u = 0; u < nu; u++)
+                    out[(j * lv.nv + v) * nu + u] = q[(size_t)((j * (lv.nv + 1) + v) * lv.nu + kRayPad + u)].y;
     });
 }
 
@@ -1071,12 +1075,17 @@ int32_t nis_debug_path_pairs(nis_ctx* ctx, int32_t medium, int32_t level, float*
         hip_check(hipDeviceSynchronize(), "sync");
         ensure_sweep(M, &M->light, ctx->stream);
         const Level& lv = M->light.lev[level];
-        const int64_t count = 2 * (int64_t)lv.nu * (lv.nv + 1) * lv.n;
+        const int nu = lv.nu - 2 * kRayPad;
+        const int64_t count = 2 * (int64_t)nu * (lv.nv + 1) * lv.n;
         if (capacity < count) fail(NIS_E_INVALID, "output too small");
+        std::vector<float2> q((size_t)lv.nu * (lv.nv + 1) * lv.n);
         hip_check(hipStreamSynchronize(ctx->stream), "sync");
-        hip_check(hipMemcpy(out, M->light.DP.as<float2>() + lv.q_off, (size_t)count * sizeof(float),
+        hip_check(hipMemcpy(q.data(), M->light.DP.as<float2>() + lv.q_off, q.size() * sizeof(float2),
                             hipMemcpyDeviceToHost),
                   "download");
+        // the rays of the definition, without the layout's padding
+        for (int64_t r = 0; r < (int64_t)(lv.nv + 1) * lv.n; r++)
+            std::memcpy(out + 2 * r * nu, q.data() + r * lv.nu + kRayPad, (size_t)nu * sizeof(float2));
     });
 }
 

@@ -21,11 +21,20 @@ constexpr int kConv1K = 96;       // two points x 9 tap-rows x 4 (3 taps + a zer
 constexpr int kConv2K = 224;      // 8 channels x 27 taps padded
 constexpr int kPrecFP32 = 0, kPrecBF16 = 1, kPrecFP8 = 2;
 
+// Padding of the gather's layouts, so that the bricks of every point inside
+// the unit cube lie within the stored rows and load as whole runs: the
+// path-density fields hold kRayPad extra rays (all zero: they miss the cube)
+// on each side along U, and the light-axis density pairs kPairPad extra
+// entries (index-clamped copies) on each side along b, where the outermost
+// slab of an in-cube point's lattice reaches 4 voxels out and its brick 2 more.
+constexpr int kRayPad = 2;
+constexpr int kPairPad = 8;
+
 // Geometry of one pyramid level and its light-sheared path-density field.
 struct Level {
     int n;              // edge n_m
-    int ulo, vlo;       // first ray indices along the lateral axes b, c
-    int nu, nv;         // ray counts
+    int ulo, vlo;       // first ray indices along the lateral axes b, c (ulo includes kRayPad)
+    int nu, nv;         // ray counts (nu includes 2 kRayPad)
     int64_t rho_off;    // offset of the level in the density pyramid
     int64_t p_off;      // offset (in pairs) of the level's light-axis density pairs
     int64_t q_off;      // offset (in pairs) of the level's path-density pairs
@@ -35,7 +44,7 @@ struct Level {
 // Everything a kernel needs to know about a medium under a light.
 struct MediumView {
     const float* rho;   // density pyramid
-    float2* pairs;      // per level [A' = 0..n][c][b]: (rho(a = A'-1), rho(a = A')), index-clamped
+    float2* pairs;      // per level [A' = 0..n][c][b + kPairPad < n + 2 kPairPad]: (rho(a = A'-1), rho(a = A')), index-clamped
     float2* dpairs;     // per level [J][V' = 0..nv][U]: (D(V'-1), D(V')), index-clamped
     Level lev[kMaxLevels];
     int levels;
