@@ -47,6 +47,27 @@ k_mip(const float* __restrict__ fine, float* __restrict__ coarse, int nc, int lg
     *reinterpret_cast<float2*>(coarse + (z * nc + y) * nc + x) = make_float2(s0 * 0.125f, s1 * 0.125f);
 }
 
+// Copy of a level with y fastest, [x][z][y], for lights dominated by x: their
+// lateral axes are y and z, and the sweep's and the light-axis pairs' lanes
+// run along b = y.  32 x 32 tiles of one z-plane through LDS, so that both
+// the reads (along x) and the writes (along y) are whole rows.
+__global__ void __launch_bounds__(256)
+k_transpose_x(const float* __restrict__ in, float* __restrict__ out, int n)
+{
+    __shared__ float t[32][33];
+    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32, z = blockIdx.z;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int j = ty; j < 32; j += 8) {
+        const int x = x0 + tx, y = y0 + j;
+        if (x < n && y < n) t[j][tx] = in[((int64_t)z * n + y) * n + x];
+    }
+    __syncthreads();
+    for (int j = ty; j < 32; j += 8) {
+        const int x = x0 + j, y = y0 + tx;
+        if (x < n && y < n) out[((int64_t)x * n + z) * n + y] = t[tx][j];
+    }
+}
+
 // Work split of the sweep.  A workgroup owns a tile of 64 rays along U (one
 // per lane) by kSwRays rays along V, and its kSwWaves waves cut the slices
 // into consecutive segments of up to kSwSeg slices each (a chunk of kSwWaves
@@ -96,7 +117,7 @@ k_sweep(MediumView mv, SweepArgs sa)
     const int n = lv.n, nu = lv.nu, nv = lv.nv;
     const int seg = n >= kSwWaves * kSwSeg ? kSwSeg : (n >= kSwWaves ? n / kSwWaves : 1);
     const int chunk = kSwWaves * seg;
-    auto stride = [n](int axis) { return axis == 0 ? 1 : axis == 1 ? n : n * n; };
+    auto stride = [&](int axis) { return mv.se[axis] == 0 ? 1 : mv.se[axis] == 1 ? n : n * n; };
     const int sta = stride(mv.a) * 4, stb = stride(mv.b) * 4, stc = stride(mv.c) * 4;   // bytes
     const double hi = n - 0.5;
     const double dU = (double)(lv.ulo + iu), dV = (double)(lv.vlo + V0 - 1);   // sampled ray k is V = dV + k
@@ -106,7 +127,7 @@ k_sweep(MediumView mv, SweepArgs sa)
     // hardware's 32-bit buffer offsets do rather than overflow
     const uint32_t qplane = (uint32_t)nu * (nv + 1) * 8;
     const __amdgpu_buffer_rsrc_t rR = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float*>(mv.rho + lv.rho_off), 0, (int)((uint32_t)n * n * n * 4), kBufFlags);
+        const_cast<float*>(mv.rho_s + lv.rho_off), 0, (int)((uint32_t)n * n * n * 4), kBufFlags);
     const __amdgpu_buffer_rsrc_t rQ =
         __builtin_amdgcn_make_buffer_rsrc(mv.dpairs + lv.q_off, 0, (int)(n * qplane), kBufFlags);
     auto ld = [&](int off) { return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rR, off, 0, 0)); };
@@ -291,19 +312,17 @@ __global__ void k_site_tables(MediumView mv, SiteTables* tab)
 // 16-byte stores.
 template <int E>
 __global__ void __launch_bounds__(256)
-k_pairs(const float* __restrict__ rho, float2* __restrict__ out, int n, int lg, int a, int b, int c)
+k_pairs(const float* __restrict__ rho, float2* __restrict__ out, int n, int lg, int sa, int sb, int sc)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ((n + 1) << (2 * lg)) / E) return;
     const int lq = lg - (E == 4 ? 2 : 0);
     const int bb = (t & ((n / E) - 1)) * E, cc = (t >> lq) & (n - 1), ap = t >> (lq + lg);
     const int a0 = ap - 1 < 0 ? 0 : ap - 1, a1 = ap > n - 1 ? n - 1 : ap;
-    auto stride = [n](int axis) { return axis == 0 ? 1 : axis == 1 ? n : n * n; };
-    const int sa = stride(a), sb = stride(b), sc = stride(c);
     const float* r0 = rho + a0 * sa + cc * sc + bb * sb;
     const float* r1 = rho + a1 * sa + cc * sc + bb * sb;
     float v0[E], v1[E];
-    if (E == 4 && b == 0) {
+    if (E == 4 && sb == 1) {
         const float4 p = *reinterpret_cast<const float4*>(r0), q = *reinterpret_cast<const float4*>(r1);
         v0[0] = p.x, v0[1] = p.y, v0[2] = p.z, v0[3] = p.w;
         v1[0] = q.x, v1[1] = q.y, v1[2] = q.z, v1[3] = q.w;
@@ -336,12 +355,14 @@ hipError_t launch_pairs(const MediumView& mv, hipStream_t s)
         const Level& lv = mv.lev[m];
         const int lg = __builtin_ctz(lv.n);
         const int total = (lv.n + 1) << (2 * lg);
+        auto stride = [&](int axis) { return 1 << (lg * mv.se[axis]); };
+        const int sa = stride(mv.a), sb = stride(mv.b), sc = stride(mv.c);
         if (lv.n >= 4)
-            hipLaunchKernelGGL(k_pairs<4>, dim3((total / 4 + 255) / 256), dim3(256), 0, s, mv.rho + lv.rho_off,
-                               mv.pairs + lv.p_off, lv.n, lg, mv.a, mv.b, mv.c);
+            hipLaunchKernelGGL(k_pairs<4>, dim3((total / 4 + 255) / 256), dim3(256), 0, s, mv.rho_s + lv.rho_off,
+                               mv.pairs + lv.p_off, lv.n, lg, sa, sb, sc);
         else
-            hipLaunchKernelGGL(k_pairs<1>, dim3((total + 255) / 256), dim3(256), 0, s, mv.rho + lv.rho_off,
-                               mv.pairs + lv.p_off, lv.n, lg, mv.a, mv.b, mv.c);
+            hipLaunchKernelGGL(k_pairs<1>, dim3((total + 255) / 256), dim3(256), 0, s, mv.rho_s + lv.rho_off,
+                               mv.pairs + lv.p_off, lv.n, lg, sa, sb, sc);
     }
     return hipGetLastError();
 }
@@ -359,6 +380,17 @@ hipError_t launch_pyramid(const float* rho, const Level* lev, int levels, hipStr
         const int threads = nc == 1 ? 1 : (nc * nc * nc) / 2;
         hipLaunchKernelGGL(k_mip, dim3((threads + 255) / 256), dim3(256), 0, s, rho + lev[m].rho_off,
                            const_cast<float*>(rho) + lev[m + 1].rho_off, nc, lg);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(const MediumView& mv, hipStream_t s)
+{
+    for (int m = 0; m < mv.levels; m++) {
+        const Level& lv = mv.lev[m];
+        const int t = (lv.n + 31) / 32;
+        hipLaunchKernelGGL(k_transpose_x, dim3(t, t, lv.n), dim3(256), 0, s, mv.rho + lv.rho_off,
+                           const_cast<float*>(mv.rho_s) + lv.rho_off, lv.n);
     }
     return hipGetLastError();
 }

@@ -75,6 +75,7 @@ struct FrameBuffers {
 };
 
 hipError_t launch_pyramid(const float* rho, const Level* lev, int levels, hipStream_t s);
+hipError_t launch_transpose(const MediumView& mv, hipStream_t s);
 hipError_t launch_sweep(const MediumView& mv, hipStream_t s);
 hipError_t launch_pairs(const MediumView& mv, hipStream_t s);
 hipError_t launch_site_tables(const MediumView& mv, SiteTables* tab, hipStream_t s);

@@ -114,6 +114,14 @@ MediumView make_view(const Medium* M, const LightState* ls, const Params& P, con
     MediumView v;
     std::memset(&v, 0, sizeof(v));
     v.rho = M->rho.as<float>();
+    if (ls->a == 0) {
+        // x-dominant light: the transposed copy, [x][z][y] per level
+        v.rho_s = ls->RT.as<float>();
+        v.se[0] = 2, v.se[1] = 0, v.se[2] = 1;
+    } else {
+        v.rho_s = v.rho;
+        v.se[0] = 0, v.se[1] = 1, v.se[2] = 2;
+    }
     v.pairs = ls->P.as<float2>();
     v.dpairs = ls->DP.as<float2>();
     for (int m = 0; m < M->levels; m++) v.lev[m] = ls->lev[m];
@@ -171,6 +179,7 @@ void ensure_sweep(const Medium* M, LightState* ls, hipStream_t s)
     if (!ls->valid) fail(NIS_E_STATE, "no light set for this medium");
     if (!ls->stale && ls->swept_version == M->version) return;
     MediumView mv = make_view(M, ls, medium_params(M), nullptr);
+    if (ls->a == 0) timed("transpose", s, [&] { return launch_transpose(mv, s); });
     timed("sweep", s, [&] { return launch_sweep(mv, s); });
     timed("pairs", s, [&] { return launch_pairs(mv, s); });
     ls->stale = false;
@@ -430,12 +439,17 @@ void light_layout(const Medium* M, const double l[3], LightState* ls)
         qoff += qn;
     }
     ls->pair_count = poff;
+    ls->rt_floats = a == 0 ? M->rho_floats : 0;
     ls->dpair_count = qoff;
 }
 
 void set_light_state(const Medium* M, const double l[3], LightState* ls)
 {
     light_layout(M, l, ls);
+    if (ls->rt_floats > 0)
+        ls->RT.reserve((size_t)ls->rt_floats * sizeof(float), "transposed pyramid");
+    else
+        ls->RT.release();
     ls->P.reserve((size_t)ls->pair_count * sizeof(float2), "light-axis density pairs");
     ls->DP.reserve((size_t)ls->dpair_count * sizeof(float2), "path-density pairs");
     ls->valid = true;

@@ -62,7 +62,9 @@ struct DevBuf {
 // Everything that depends on the light direction: the light frame (dominant
 // axis, shears, lattice offsets), each level's sheared-ray ranges, the path
 // density fields (stored only as pairs along V), the light-axis density pairs
-// and the per-site direction/phase tables.
+// and the per-site direction/phase tables; for a light dominated by x also a
+// copy of the pyramid with y fastest, so that the sweep's lanes (along the
+// lateral axis b = y) read neighbouring floats.
 struct LightState {
     bool valid = false;
     double l[3] = {0, 0, 0};                // unit vector towards the light
@@ -70,16 +72,18 @@ struct LightState {
     double sb = 0, sc = 0, la = 1;
     double qoff[3][9] = {};
     Level lev[kMaxLevels] = {};             // medium's n and rho_off plus this light's ray ranges
+    int64_t rt_floats = 0;                  // transposed pyramid (x-dominant lights only)
     int64_t pair_count = 0;                 // light-axis density pairs of all levels
     int64_t dpair_count = 0;                // path-density pairs of all levels
-    DevBuf P, DP, tab;
+    DevBuf RT, P, DP, tab;
     bool stale = true;                      // D, P and DP must be recomputed
     uint64_t swept_version = 0;             // pyramid version they were computed from
     bool tab_valid = false;
     float tab_g = 0.f;                      // g the site tables were computed for
-    size_t bytes() const { return P.bytes + DP.bytes + tab.bytes; }
+    size_t bytes() const { return RT.bytes + P.bytes + DP.bytes + tab.bytes; }
     void release()
     {
+        RT.release();
         P.release();
         DP.release();
         tab.release();

@@ -97,7 +97,8 @@ void slot_need(int prec, const Medium* M, const Request& r, size_t* ws, size_t* 
     *fw = frame_work_bytes(npix);
     LightState tmp;
     light_layout(M, r.l, &tmp);
-    *ls = (size_t)(tmp.pair_count + tmp.dpair_count) * sizeof(float2) + sizeof(SiteTables);
+    *ls = (size_t)tmp.rt_floats * sizeof(float) + (size_t)(tmp.pair_count + tmp.dpair_count) * sizeof(float2) +
+          sizeof(SiteTables);
 }
 
 size_t grow(size_t need, size_t have) { return need > have ? need - have : 0; }
