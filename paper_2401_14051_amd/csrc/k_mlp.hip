@@ -115,138 +115,6 @@ k_mlp(MlpArgs A)
     }
 }
 
-// FP8 backbone.  Every GEMM is E4M3 x E4M3 -> FP32 on MFMA with two scales:
-// one per output column of the weights (absmax / 448, fixed at set_weights)
-// and one per row of the activations (absmax / 448 of that point's layer
-// input, computed here), so a point's result never depends on the others in
-// its batch.  The descriptor arrives in BF16 with its row maxima and is
-// quantised while it is loaded; hidden activations are stored in LDS as E4M3.
-template <int NT>
-__global__ void __launch_bounds__(256)
-k_mlp_fp8(MlpArgs A)
-{
-    typedef Mfma<kPrecFP8> M;
-    constexpr int ROWS = 64, RT = 4;
-    constexpr int W = NT * 16;
-    constexpr int KH = hidden_k(kPrecFP8, W);
-    constexpr int K0 = input_k(kPrecFP8);
-    constexpr int HS = KH + 16;                  // bytes per activation row
-    constexpr int FRAG = 64 * M::KPL;
-    // scaling to 447.5 keeps every rounded code finite (the conversion does not saturate)
-    constexpr float kTarget = 447.5f;
-    __shared__ __attribute__((aligned(16))) uint8_t hbuf[kMlpWaves][ROWS][HS];
-    __shared__ float rsc[kMlpWaves][ROWS];      // dequantisation scale of each row's activations
-
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int lr = lane % 16, lg = lane / 16;
-    const int64_t row0 = ((int64_t)blockIdx.x * kMlpWaves + wave) * ROWS;
-    const int64_t npts = A.count ? min(max((int64_t)*A.count - A.count_off, (int64_t)0), A.npts) : A.npts;
-    if ((int64_t)blockIdx.x * kMlpWaves * ROWS >= npts) return;
-    uint8_t(*h)[HS] = hbuf[wave];
-    float* rs = rsc[wave];
-    const __bf16* x = reinterpret_cast<const __bf16*>(A.x);
-
-    if constexpr (KH > W) {
-        for (int e = lane; e < ROWS * (KH - W); e += 64) h[e / (KH - W)][W + e % (KH - W)] = 0;
-    }
-    // row scales of the descriptor
-    float qs[RT];
-    const __bf16* xr[RT];
-#pragma unroll
-    for (int rt = 0; rt < RT; rt++) {
-        int64_t r = row0 + rt * 16 + lr;
-        r = r < npts ? r : npts - 1;
-        xr[rt] = x + r * kDescPad + lg * M::KPL;
-        const float m = A.rowmax[r];
-        qs[rt] = m > 0.f ? kTarget / m : 1.f;
-        if (lg == 0) rs[rt * 16 + lr] = m > 0.f ? m / kTarget : 1.f;
-    }
-    __syncthreads();
-
-    f32x4 acc[RT][NT];
-    for (int li = 0; li + 1 < A.n_linear; li++) {
-        const uint8_t* Wf = reinterpret_cast<const uint8_t*>(A.W[li]) + lane * M::KPL;
-        const int K = li == 0 ? K0 : KH;
-        const int KC = K / M::KS;
-#pragma unroll
-        for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-            for (int ct = 0; ct < NT; ct++) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int kc = 0; kc < KC; kc++) {
-            typename M::frag a[RT];
-            if (li == 0) {
-                const bool valid = kc * M::KS + lg * M::KPL < kDescPad;
-#pragma unroll
-                for (int rt = 0; rt < RT; rt++) {
-                    if (valid) {
-                        const bf16x8* src = reinterpret_cast<const bf16x8*>(xr[rt] + kc * M::KS);
-#pragma unroll
-                        for (int v = 0; v < 4; v++) {
-                            const bf16x8 u = src[v];
-                            a[rt][2 * v] = pack_fp8x4_inrange((float)u[0] * qs[rt], (float)u[1] * qs[rt],
-                                                              (float)u[2] * qs[rt], (float)u[3] * qs[rt]);
-                            a[rt][2 * v + 1] = pack_fp8x4_inrange((float)u[4] * qs[rt], (float)u[5] * qs[rt],
-                                                                  (float)u[6] * qs[rt], (float)u[7] * qs[rt]);
-                        }
-                    } else {
-#pragma unroll
-                        for (int v = 0; v < 8; v++) a[rt][v] = 0;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int rt = 0; rt < RT; rt++) a[rt] = M::load(&h[rt * 16 + lr][kc * M::KS + lg * M::KPL]);
-            }
-#pragma unroll
-            for (int ct = 0; ct < NT; ct++) {
-                typename M::frag b = M::load(Wf + (ct * KC + kc) * FRAG);
-#pragma unroll
-                for (int rt = 0; rt < RT; rt++) acc[rt][ct] = M::mma(a[rt], b, acc[rt][ct]);
-            }
-        }
-        __syncthreads();   // every lane's reads of h and rs precede their overwrite
-        const float* bias = A.bias[li];
-        const float* wsc = A.wscale[li];
-#pragma unroll
-        for (int rt = 0; rt < RT; rt++) {
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const int row = rt * 16 + lg * 4 + e;
-                const float din = rs[row];
-                float m = 0.f;
-#pragma unroll
-                for (int ct = 0; ct < NT; ct++) {
-                    const int col = ct * 16 + lr;
-                    const float v = fmaxf(acc[rt][ct][e] * din * wsc[col] + bias[col], 0.f);
-                    acc[rt][ct][e] = v;
-                    m = fmaxf(m, v);
-                }
-                for (int o = 1; o < 16; o <<= 1) m = fmaxf(m, __shfl_xor(m, o));
-                const float q = m > 0.f ? kTarget / m : 1.f;
-#pragma unroll
-                for (int ct = 0; ct < NT; ct++) {
-                    const int w = __builtin_amdgcn_cvt_pk_fp8_f32(acc[rt][ct][e] * q, 0.f, 0, false);
-                    h[row][ct * 16 + lr] = (uint8_t)(w & 0xff);
-                }
-                // the row's 16 lanes read rs[row] above, in this wave, before this write
-                if (lr == 0) rs[row] = m > 0.f ? m / kTarget : 1.f;
-            }
-        }
-        __syncthreads();
-    }
-    // last layer + decode, one row per lane
-    for (int rr = lane; rr < ROWS; rr += 64) {
-        const int64_t row = row0 + rr;
-        float y = 0.f;
-        for (int k = 0; k < W; k++) y += __builtin_amdgcn_cvt_f32_fp8((int)h[rr][k], 0) * A.wout[k];
-        y = A.bout + y * rs[rr];
-        if (row < npts) {
-            if (A.y_out) A.y_out[row] = y;
-            if (A.out) A.out[row] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
-        }
-    }
-}
-
 // BF16 backbone on 32x32x16 MFMA tiles, the weights as the A operand and the
 // activations as B.  A layer's output tile D[channel][point] leaves lane
 // l = p + 32 g holding, for point p, the 16 channels 8 (r/4) + 4 g + r%4 of
@@ -637,6 +505,186 @@ k_mlp_bf16(MlpArgs A)
         const int64_t row = row0 + p * 32 + lp;
         if (lg == 0 && row < npts) {
             const float y = A.bout + s;
+            if (A.y_out) A.y_out[row] = y;
+            if (A.out) A.out[row] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
+        }
+    }
+}
+
+// FP8 backbone.  Every GEMM is E4M3 x E4M3 -> FP32 on MFMA with two scales:
+// one per output column of the weights (absmax / 448, fixed at set_weights)
+// and one per row of the activations (absmax / 448 of that point's layer
+// input, computed here), so a point's result never depends on the others in
+// its batch.  The descriptor arrives in BF16 with its row maxima and is
+// quantised while it is loaded; hidden activations are stored in LDS as E4M3.
+// A K step's weight fragments (NT x 2 KiB) are copied once per workgroup
+// from global memory straight into LDS, double buffered, and read there by
+// all four waves; each buffer is an LDS variable of its own and is named at
+// compile time, so reads of one do not wait for the copies into the other.
+template <int NT>
+__global__ void __launch_bounds__(256)
+k_mlp_fp8(MlpArgs A)
+{
+    typedef Mfma<kPrecFP8> M;
+    constexpr int ROWS = 64, RT = 4;
+    constexpr int W = NT * 16;
+    constexpr int KH = hidden_k(kPrecFP8, W);
+    constexpr int K0 = input_k(kPrecFP8);
+    constexpr int HS = KH + 16;                  // bytes per activation row
+    constexpr int FRAG = 64 * M::KPL;
+    // scaling to 447.5 keeps every rounded code finite (the conversion does not saturate)
+    constexpr float kTarget = 447.5f;
+    __shared__ __attribute__((aligned(16))) uint8_t wq0[NT * FRAG];
+    __shared__ __attribute__((aligned(16))) uint8_t wq1[NT * FRAG];
+    __shared__ __attribute__((aligned(16))) uint8_t hbuf[kMlpWaves][ROWS][HS];
+    __shared__ float rsc[kMlpWaves][ROWS];      // dequantisation scale of each row's activations
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
+    const int lr = lane % 16, lg = lane / 16;
+    const int64_t row0 = ((int64_t)blockIdx.x * kMlpWaves + wave) * ROWS;
+    const int64_t npts = A.count ? min(max((int64_t)*A.count - A.count_off, (int64_t)0), A.npts) : A.npts;
+    if ((int64_t)blockIdx.x * kMlpWaves * ROWS >= npts) return;
+    uint8_t(*h)[HS] = hbuf[wave];
+    float* rs = rsc[wave];
+    const __bf16* x = reinterpret_cast<const __bf16*>(A.x);
+
+    if constexpr (KH > W) {
+        for (int e = lane; e < ROWS * (KH - W); e += 64) h[e / (KH - W)][W + e % (KH - W)] = 0;
+    }
+    // row scales of the descriptor
+    float qs[RT];
+    const __bf16* xr[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++) {
+        int64_t r = row0 + rt * 16 + lr;
+        r = r < npts ? r : npts - 1;
+        xr[rt] = x + r * kDescPad + lg * M::KPL;
+        const float m = A.rowmax[r];
+        qs[rt] = m > 0.f ? kTarget / m : 1.f;
+        if (lg == 0) rs[rt * 16 + lr] = m > 0.f ? m / kTarget : 1.f;
+    }
+    __syncthreads();
+
+    // the NT fragments of K step kc of layer li into dst: 2 NT chunks of 1 KiB,
+    // dealt to the waves in turn
+    auto copy_w = [&](uint8_t* dst, int li, int KC, int kc) __attribute__((always_inline)) {
+        const __amdgpu_buffer_rsrc_t r = rsrc(A.W[li], (int64_t)NT * KC * FRAG);
+        for (int c = wave; c < 2 * NT; c += kMlpWaves)
+            copy_lds16(r, dst + c * 1024, lane * 16, ((c >> 1) * KC + kc) * FRAG + (c & 1) * 1024);
+    };
+
+    f32x4 acc[RT][NT];
+    for (int li = 0; li + 1 < A.n_linear; li++) {
+        const int K = li == 0 ? K0 : KH;
+        const int KC = K / M::KS;
+#pragma unroll
+        for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+            for (int ct = 0; ct < NT; ct++) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // the first layer's descriptor slices of step kc, loaded one step ahead
+        bf16x8 u[RT][4];
+        auto load_u = [&](int kc) __attribute__((always_inline)) {
+            const bool valid = kc * M::KS + lg * M::KPL < kDescPad;
+#pragma unroll
+            for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+                for (int v = 0; v < 4; v++)
+                    u[rt][v] = valid ? reinterpret_cast<const bf16x8*>(xr[rt] + kc * M::KS)[v] : bf16x8{};
+        };
+        if (li == 0) load_u(0);
+        copy_w(wq0, li, KC, 0);
+        // one K step from buffer bc; issues the next step's copy into the other
+        auto step = [&](auto bc, int kc) __attribute__((always_inline)) {
+            uint8_t* cur = decltype(bc)::value == 0 ? wq0 : wq1;
+            uint8_t* nxt = decltype(bc)::value == 0 ? wq1 : wq0;
+            wait_vm<0>();
+            __syncthreads();   // step kc's fragments are in; every wave is done with nxt
+            typename M::frag a[RT];
+            if (li == 0) {
+#pragma unroll
+                for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+                    for (int v = 0; v < 4; v++) {
+                        a[rt][2 * v] = pack_fp8x4_inrange((float)u[rt][v][0] * qs[rt], (float)u[rt][v][1] * qs[rt],
+                                                          (float)u[rt][v][2] * qs[rt], (float)u[rt][v][3] * qs[rt]);
+                        a[rt][2 * v + 1] = pack_fp8x4_inrange((float)u[rt][v][4] * qs[rt], (float)u[rt][v][5] * qs[rt],
+                                                              (float)u[rt][v][6] * qs[rt], (float)u[rt][v][7] * qs[rt]);
+                    }
+                // the next step's descriptor slices and weight fragments stay in
+                // flight while this step's MFMAs run
+                if (kc + 1 < KC) {
+                    load_u(kc + 1);
+                    copy_w(nxt, li, KC, kc + 1);
+                }
+            } else {
+                if (kc + 1 < KC) copy_w(nxt, li, KC, kc + 1);
+#pragma unroll
+                for (int rt = 0; rt < RT; rt++) a[rt] = M::load(&h[rt * 16 + lr][kc * M::KS + lg * M::KPL]);
+            }
+#pragma unroll
+            for (int ct = 0; ct < NT; ct++) {
+                typename M::frag b = M::load(cur + ct * FRAG + lane * M::KPL);
+#pragma unroll
+                for (int rt = 0; rt < RT; rt++) acc[rt][ct] = M::mma(a[rt], b, acc[rt][ct]);
+            }
+        };
+        for (int kc = 0; kc < KC; kc += 2) {
+            step(IC<0>{}, kc);
+            if (kc + 1 < KC) step(IC<1>{}, kc + 1);
+        }
+        __syncthreads();   // every lane's reads of h and rs precede their overwrite
+        const float* __restrict__ bias = A.bias[li];
+        const float* __restrict__ wsc = A.wscale[li];
+        // dequantise, bias, ReLU: column by column, so that each column's scale
+        // and bias are loaded once; the rows' maxima accumulate meanwhile
+        float din[RT][4], m[RT][4];
+#pragma unroll
+        for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                din[rt][e] = rs[rt * 16 + lg * 4 + e];
+                m[rt][e] = 0.f;
+            }
+#pragma unroll
+        for (int ct = 0; ct < NT; ct++) {
+            const int col = ct * 16 + lr;
+            const float ws = wsc[col], bs = bias[col];
+#pragma unroll
+            for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const float v = fmaxf(acc[rt][ct][e] * din[rt][e] * ws + bs, 0.f);
+                    acc[rt][ct][e] = v;
+                    m[rt][e] = fmaxf(m[rt][e], v);
+                }
+        }
+        // requantise each row to its own maximum
+#pragma unroll
+        for (int rt = 0; rt < RT; rt++) {
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int row = rt * 16 + lg * 4 + e;
+                float mx = m[rt][e];
+                for (int o = 1; o < 16; o <<= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+                const float q = mx > 0.f ? kTarget / mx : 1.f;
+#pragma unroll
+                for (int ct = 0; ct < NT; ct++) {
+                    const int w = __builtin_amdgcn_cvt_pk_fp8_f32(acc[rt][ct][e] * q, 0.f, 0, false);
+                    h[row][ct * 16 + lr] = (uint8_t)(w & 0xff);
+                }
+                // the row's 16 lanes read rs[row] above, in this wave, before this write
+                if (lr == 0) rs[row] = mx > 0.f ? mx / kTarget : 1.f;
+            }
+        }
+        __syncthreads();
+    }
+    // last layer + decode, one row per lane
+    for (int rr = lane; rr < ROWS; rr += 64) {
+        const int64_t row = row0 + rr;
+        float y = 0.f;
+        for (int k = 0; k < W; k++) y += __builtin_amdgcn_cvt_f32_fp8((int)h[rr][k], 0) * A.wout[k];
+        y = A.bout + y * rs[rr];
+        if (row < npts) {
             if (A.y_out) A.y_out[row] = y;
             if (A.out) A.out[row] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
         }
