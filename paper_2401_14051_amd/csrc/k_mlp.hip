@@ -164,6 +164,13 @@ __device__ __forceinline__ void copy_lds16(__amdgpu_buffer_rsrc_t r, void* lds, 
     __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds, 16, voff, soff, 0, 0);
 }
 
+// as copy_lds16 with the non-temporal cache policy, for data read exactly
+// once (the descriptor stream), so that it does not displace the weights
+__device__ __forceinline__ void copy_lds16_stream(__amdgpu_buffer_rsrc_t r, void* lds, int voff, int soff)
+{
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds, 16, voff, soff, 0, 2);
+}
+
 // an empty use of x that the compiler must keep: x stays allocated up to here
 __device__ __forceinline__ void keep_alive(const f32x16& x) { asm volatile("" ::"v"(x)); }
 
@@ -273,7 +280,7 @@ k_mlp_bf16(MlpArgs A)
     auto copy_d = [&](int q, auto dc, int k) __attribute__((always_inline)) {
         const int p = k / 4, i = k % 4;
         uint8_t* dst = p == 0 ? dbuf(dc, IC<0>{}) : dbuf(dc, IC<PT - 1>{});
-        copy_lds16(xr, dst + i * 1024, doff[p][i], q * 128);
+        copy_lds16_stream(xr, dst + i * 1024, doff[p][i], q * 128);
     };
     // byte offset of this lane's B fragment of step j within a tile's slice
     int roff[kStage];
