@@ -223,23 +223,24 @@ def main():
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         w0 = time.perf_counter()
-        e0.record(stream)
-        for _ in range(steps):
+        ev[0].record(stream)
+        for i in range(steps):
             step()
-        e1.record(stream)
+            ev[i + 1].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
-        ms = e0.elapsed_time(e1) / steps
-        return ms, wall
+        ms = ev[0].elapsed_time(ev[steps]) / steps
+        per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+        return ms, wall, per
 
     res = {}
     precs = [args.precision] + ([p for p in ("bf16", "fp8", "fp32") if p != args.precision]
                                 if args.compare_fp32 else [])
+    per_frame = {}
     for prec in precs:
-        ms, wall = run(prec, args.steps, args.warmup)
+        ms, wall, per_frame[prec] = run(prec, args.steps, args.warmup)
         ctx.profile(True)
         for _ in range(max(3, min(args.steps, 10))):
             step()
@@ -249,6 +250,34 @@ def main():
         res[prec] = {"ms": ms, "wall_s": wall, "kernels": {k: v[1] / v[0] for k, v in rep.items()},
                      "launches": {k: v[0] for k, v in rep.items()}}
         log("%s: %.3f ms/frame, kernels %s" % (prec, ms, {k: round(v, 4) for k, v in res[prec]["kernels"].items()}))
+
+    # the headline precision's fps three ways: the light changed every frame
+    # (the steps above), a static light (rays and query only), and the query of
+    # the frame's collision points alone (no camera rays)
+    ctx.set_precision(args.precision)
+    tp = torch.from_numpy(np.ascontiguousarray(pts, np.float32)).cuda()
+    td = torch.from_numpy(np.ascontiguousarray(dirs, np.float32)).cuda()
+    tl = torch.empty(len(pts), dtype=torch.float32, device="cuda")
+    nmode = max(3, min(args.steps, 10))
+
+    def timed_mode(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(nmode):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / nmode
+
+    ms_static = timed_mode(lambda: ctx.render(mid, cam, wl.point_seed, out=img, stream=stream.cuda_stream))
+    ms_query = timed_mode(lambda: ctx.query_device(mid, tp, td, tl, stream=stream.cuda_stream))
+    fps_modes = {"light_change_full_frame": 1000.0 / res[args.precision]["ms"],
+                 "static_light_full_frame": 1000.0 / ms_static,
+                 "static_light_query_only": 1000.0 / ms_query}
+    log("fps: light change %.1f, static light %.1f, query only %.1f" % tuple(fps_modes.values()))
 
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * (1 << 20) // 4
@@ -271,15 +300,21 @@ def main():
     op["lam"] = f32(params["lam"])
     rng = np.random.default_rng(123)
     sidx = np.sort(rng.choice(len(pts), min(args.parity_sample, len(pts)), replace=False))
-    ref = f32(wl.albedo) * om.query(op, pts[sidx], dirs[sidx], f32(wl.sigma_t), f32(wl.albedo), f32(wl.g),
-                                    f32(wl.radiance))["L"]
-    errs = {}
+    oref = om.query(op, pts[sidx], dirs[sidx], f32(wl.sigma_t), f32(wl.albedo), f32(wl.g), f32(wl.radiance))
+    ref = f32(wl.albedo) * oref["L"]
+    errs, errs_f = {}, {}
+    sp = torch.from_numpy(np.ascontiguousarray(pts[sidx], np.float32)).cuda()
+    sd = torch.from_numpy(np.ascontiguousarray(dirs[sidx], np.float32)).cuda()
     for prec in precs:
         ctx.set_precision(prec)
         step()
         torch.cuda.synchronize()
         got = img.cpu().numpy()[pix[sidx]].astype(np.float64)
         errs[prec] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        # the network's part alone, F = albedo^gamma expm1(y)
+        _, y = ctx.network(mid, sp, sd, want_desc=False)
+        fh = f32(wl.albedo) ** params["gamma"] * np.expm1(y.cpu().numpy().astype(np.float64))
+        errs_f[prec] = float(np.linalg.norm(fh - oref["F"]) / np.linalg.norm(oref["F"]))
     miss = np.ones(npix, bool)
     miss[pix] = False
     misses_zero = bool(np.all(img.cpu().numpy()[miss] == 0.0))
@@ -359,6 +394,10 @@ def main():
                    "points": len(pts), "pixels": npix},
         "fps": 1000.0 / ms,
         "rel_l2_vs_fp64_oracle": {p: errs[p] for p in precs},
+        "rel_l2_F_vs_fp64_oracle": {p: errs_f[p] for p in precs},
+        "frame_ms": {p: {"median": float(np.median(per_frame[p])), "p99": float(np.percentile(per_frame[p], 99))}
+                     for p in precs},
+        "fps_modes": fps_modes,
         "misses_are_zero": misses_zero,
         "per_precision": {p: {"ms_per_step": res[p]["ms"], "points_per_s": len(pts) / (res[p]["ms"] * 1e-3),
                               "fps": 1000.0 / res[p]["ms"], "kernels_ms": res[p]["kernels"]} for p in precs},
