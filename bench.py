@@ -274,6 +274,21 @@ def main():
 
     ms_static = timed_mode(lambda: ctx.render(mid, cam, wl.point_seed, out=img, stream=stream.cuda_stream))
     ms_query = timed_mode(lambda: ctx.query_device(mid, tp, td, tl, stream=stream.cuda_stream))
+    # the paper's own use: the network evaluated at 4129 template centres
+    # sampled uniformly in the medium, with and without a light change
+    cp, cd = camera.random_points(4129, seed=17, lo=0.0, hi=1.0)
+    tcp = torch.from_numpy(np.ascontiguousarray(cp, np.float32)).cuda()
+    tcd = torch.from_numpy(np.ascontiguousarray(cd, np.float32)).cuda()
+    tcl = torch.empty(len(cp), dtype=torch.float32, device="cuda")
+    ms_tpl = timed_mode(lambda: ctx.query_device(mid, tcp, tcd, tcl, stream=stream.cuda_stream))
+
+    def tpl_light():
+        ctx.set_light(mid, wl.light, wl.radiance)
+        ctx.query_device(mid, tcp, tcd, tcl, stream=stream.cuda_stream)
+
+    ms_tpl_light = timed_mode(tpl_light)
+    template_batch = {"points": len(cp), "ms_static_light": ms_tpl, "ms_light_change": ms_tpl_light}
+    log("4129 template centres: %.3f ms (static light), %.3f ms (light change)" % (ms_tpl, ms_tpl_light))
     fps_modes = {"light_change_full_frame": 1000.0 / res[args.precision]["ms"],
                  "static_light_full_frame": 1000.0 / ms_static,
                  "static_light_query_only": 1000.0 / ms_query}
@@ -398,6 +413,7 @@ def main():
         "frame_ms": {p: {"median": float(np.median(per_frame[p])), "p99": float(np.percentile(per_frame[p], 99))}
                      for p in precs},
         "fps_modes": fps_modes,
+        "template_batch": template_batch,
         "misses_are_zero": misses_zero,
         "per_precision": {p: {"ms_per_step": res[p]["ms"], "points_per_s": len(pts) / (res[p]["ms"] * 1e-3),
                               "fps": 1000.0 / res[p]["ms"], "kernels_ms": res[p]["kernels"]} for p in precs},
