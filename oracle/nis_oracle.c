@@ -63,6 +63,16 @@ double om_hg(double g, double mu)
     return (1.0 - g * g) / (4.0 * OM_PI * den * sqrt(den));
 }
 
+/* Multi-lobe HG phase (Sec. III.A, eq. 6): a linear combination of HG lobes
+ * with weights lw[i] (summing to one) and asymmetries lg[i].  One lobe of
+ * weight 1 is the HG phase of eq. 5. */
+double om_mhg(int nl, const double *lw, const double *lg, double mu)
+{
+    double v = 0.0;
+    for (int i = 0; i < nl; i++) v += lw[i] * om_hg(lg[i], mu);
+    return v;
+}
+
 static int clampi(int i, int lo, int hi) { return i < lo ? lo : (i > hi ? hi : i); }
 
 /* ------------------------------------------------------------------ */
@@ -281,20 +291,24 @@ static void site_offset(const om_medium *M, int t, double o[3])
     o[M->c] += j;
 }
 
-/* Per-point features of every layer (Sec. III.B.2-4, eq. 1, 8, 15, 24):
+/* Per-point features of every layer (Sec. III.B.2-4, eq. 1, 8, 15, 24) for
+ * a phase of nl HG lobes (eq. 6; f below; one lobe is plain HG):
  *   tbar[p][k][t] graded transmittance exp(-lam^(m+1) sigma_t D_m(site)),
  *   rho [p][k][t] density at the site,
- *   phi [p][t]    log1p of the phase feature HG(w.d_t) HG(d_t.l), d_t = o/|o|
- *                 (HG(w.l) at the centre site),
+ *   phi [p][t]    log1p of the phase feature f(w.d_t) f(d_t.l), d_t = o/|o|
+ *                 (f(w.l) at the centre site),
  *   stats[p][k][8] = mean rho, mean phi, mean tbar, max rho, max phi,
- *                 max tbar, g, alpha = acos(w.l),
- *   tp[p] = exp(-sigma_t D_0(p)) (eq. 15), f0[p] = HG(w.l) tp[p] (eq. 19).
+ *                 max tbar, g, alpha = acos(w.l), where g is the phase's
+ *                 mean cosine, sum_i lw[i] lg[i],
+ *   tp[p] = exp(-sigma_t D_0(p)) (eq. 15), f0[p] = f(w.l) tp[p] (eq. 19).
  * Any output pointer may be NULL.                                           */
-void om_features(const om_medium *M, double sigma_t, double g, double lam,
-                 const float *pts, const float *dirs, int64_t np,
+void om_features(const om_medium *M, double sigma_t, int nl, const double *lw, const double *lg,
+                 double lam, const float *pts, const float *dirs, int64_t np,
                  double *tbar, double *rho, double *phi, double *stats,
                  double *tp, double *f0)
 {
+    double g = 0.0;
+    for (int i = 0; i < nl; i++) g += lw[i] * lg[i];
     int L = M->levels;
     double h0 = 1.0 / M->n;
 #pragma omp parallel for schedule(dynamic, 16)
@@ -313,11 +327,11 @@ void om_features(const om_medium *M, double sigma_t, double g, double lam,
             double on = sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
             double P;
             if (on == 0.0) {
-                P = om_hg(g, wl);
+                P = om_mhg(nl, lw, lg, wl);
             } else {
                 double wd = (w[0] * o[0] + w[1] * o[1] + w[2] * o[2]) / on;
                 double dl = (o[0] * M->l[0] + o[1] * M->l[1] + o[2] * M->l[2]) / on;
-                P = om_hg(g, wd) * om_hg(g, dl);
+                P = om_mhg(nl, lw, lg, wd) * om_mhg(nl, lw, lg, dl);
             }
             ph[t] = log1p(P);
             phmean += ph[t];
@@ -350,7 +364,7 @@ void om_features(const om_medium *M, double sigma_t, double g, double lam,
         }
         double T0 = exp(-sigma_t * om_sample_D(M, 0, x));
         if (tp) tp[p] = T0;
-        if (f0) f0[p] = om_hg(g, wl) * T0;
+        if (f0) f0[p] = om_mhg(nl, lw, lg, wl) * T0;
     }
 }
 
@@ -458,11 +472,13 @@ double om_mlp(const double *params, int width, int n_linear, const double *desc)
     return y;
 }
 
-/* Whole query: radiance L = I (HG(w.l) T(p) + F), with the network output
- * decoded from the log space of the loss (Sec. III.C.3, eq. 21, gamma = 4):
- * F = albedo^gamma * expm1(y).  F0 = HG(w.l) T(p) I is the single-scatter
- * term of the scattering-order series (eq. 19).  y_out/fhat_out may be NULL. */
-void om_query(const om_medium *M, double sigma_t, double albedo, double g, double lam,
+/* Whole query: radiance L = I (f(w.l) T(p) + F) for a phase f of nl HG
+ * lobes, with the network output decoded from the log space of the loss
+ * (Sec. III.C.3, eq. 21, gamma = 4): F = albedo^gamma * expm1(y).
+ * F0 = f(w.l) T(p) I is the single-scatter term of the scattering-order
+ * series (eq. 19).  y_out/fhat_out may be NULL. */
+void om_query(const om_medium *M, double sigma_t, double albedo, int nl, const double *lw,
+              const double *lg, double lam,
               double gamma, double radiance, const double *params, int width, int n_linear,
               const float *pts, const float *dirs, int64_t np,
               double *L_out, double *y_out, double *fhat_out, double *desc_out)
@@ -473,7 +489,7 @@ void om_query(const om_medium *M, double sigma_t, double albedo, double g, doubl
         double st[OM_LAYERS * OM_STATS];
         double f0;
         double *desc = desc_out ? desc_out + p * OM_DESC : (double *)malloc(sizeof(double) * OM_DESC);
-        om_features(M, sigma_t, g, lam, pts + 3 * p, dirs + 3 * p, 1, tb, NULL, NULL, st, NULL, &f0);
+        om_features(M, sigma_t, nl, lw, lg, lam, pts + 3 * p, dirs + 3 * p, 1, tb, NULL, NULL, st, NULL, &f0);
         om_descriptor(params, tb, st, albedo, desc);
         double y = om_mlp(params, width, n_linear, desc);
         double F = pow(albedo, gamma) * expm1(y);

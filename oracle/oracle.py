@@ -61,13 +61,15 @@ def lib():
         L.om_sample_D.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
         L.om_hg.restype = ctypes.c_double
         L.om_hg.argtypes = [ctypes.c_double, ctypes.c_double]
-        L.om_features.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+        L.om_mhg.restype = ctypes.c_double
+        L.om_mhg.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double]
+        L.om_features.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, _dp, _dp, ctypes.c_double,
                                   _fp, _fp, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _dp]
         L.om_cnn_se.argtypes = [_dp, _dp, _dp]
         L.om_descriptor.argtypes = [_dp, _dp, _dp, ctypes.c_double, _dp]
         L.om_mlp.restype = ctypes.c_double
         L.om_mlp.argtypes = [_dp, ctypes.c_int, ctypes.c_int, _dp]
-        L.om_query.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+        L.om_query.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp, _dp,
                                ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, ctypes.c_int,
                                ctypes.c_int, _fp, _fp, ctypes.c_int64, _dp, _dp, _dp, _dp]
         _lib = L
@@ -89,6 +91,22 @@ def _ptr(a, t):
 def hg(g, mu):
     """Henyey-Greenstein phase value (eq. 5)."""
     return lib().om_hg(float(g), float(mu))
+
+
+def lobes(phase):
+    """(weights, asymmetries) as float64 arrays of a phase given either as one
+    asymmetry g (plain HG, eq. 5) or as a sequence of (weight, g) lobes (eq. 6)."""
+    if np.ndim(phase) == 0:
+        return np.array([1.0]), np.array([float(phase)])
+    lw = np.array([float(w) for w, _ in phase])
+    lg = np.array([float(g) for _, g in phase])
+    return lw, lg
+
+
+def mhg(phase, mu):
+    """Multi-lobe HG phase value (eq. 6) of a phase as accepted by lobes()."""
+    lw, lg = lobes(phase)
+    return lib().om_mhg(len(lw), _ptr(lw, _dp), _ptr(lg, _dp), float(mu))
 
 
 def flatten_params(params):
@@ -187,24 +205,29 @@ class Medium:
         return lib().om_sample_D(self.h, m, _ptr(_f64(x), _dp))
 
     def features(self, sigma_t, g, lam, pts, dirs):
+        """Per-point features; g is one asymmetry or a sequence of (weight, g) lobes."""
         pts, dirs = _f32(pts), _f32(dirs)
         P = pts.shape[0]
         out = {"tbar": np.zeros((P, LAYERS, SITES)), "rho": np.zeros((P, LAYERS, SITES)),
                "phi": np.zeros((P, SITES)), "stats": np.zeros((P, LAYERS, STATS)),
                "tp": np.zeros(P), "f0": np.zeros(P)}
-        lib().om_features(self.h, float(sigma_t), float(g), float(lam), _ptr(pts, _fp),
+        lw, lg = lobes(g)
+        lib().om_features(self.h, float(sigma_t), len(lw), _ptr(lw, _dp), _ptr(lg, _dp), float(lam), _ptr(pts, _fp),
                           _ptr(dirs, _fp), P, *[_ptr(out[k], _dp) for k in
                                                 ("tbar", "rho", "phi", "stats", "tp", "f0")])
         return out
 
     def query(self, params, pts, dirs, sigma_t, albedo, g, radiance=1.0, want_desc=False):
-        """Radiance, network output y and decoded F for each point."""
+        """Radiance, network output y and decoded F for each point; g is one
+        asymmetry or a sequence of (weight, g) lobes."""
         pts, dirs = _f32(pts), _f32(dirs)
         P = pts.shape[0]
         flat = flatten_params(params)
         L, y, F = np.zeros(P), np.zeros(P), np.zeros(P)
         desc = np.zeros((P, DESC)) if want_desc else None
-        lib().om_query(self.h, float(sigma_t), float(albedo), float(g), float(params["lam"]),
+        lw, lg = lobes(g)
+        lib().om_query(self.h, float(sigma_t), float(albedo), len(lw), _ptr(lw, _dp), _ptr(lg, _dp),
+                       float(params["lam"]),
                        float(params["gamma"]), float(radiance), _ptr(flat, _dp),
                        int(params["width"]), int(params["n_linear"]), _ptr(pts, _fp),
                        _ptr(dirs, _fp), P, _ptr(L, _dp), _ptr(y, _dp), _ptr(F, _dp),

@@ -329,6 +329,60 @@ def test_phase_features_closed_forms():
     assert f["stats"][0, 0, 7] == pytest.approx(math.acos(wl), rel=1e-12)
 
 
+# --------------------------------------------------------------------------
+# Multi-lobe HG phase, Sec. III.A eq. (6): weights summing to one
+
+MHG_PHASES = ([(0.7, 0.8), (0.3, -0.4)], [(0.5, 0.95), (0.3, 0.2), (0.2, -0.7)], [(1.0, 0.6)])
+
+
+@pytest.mark.parametrize("phase", MHG_PHASES)
+def test_mhg_normalises_and_mean_cosine_is_weighted(phase):
+    val, _ = scipy.integrate.quad(lambda mu: oracle.mhg(phase, mu), -1.0, 1.0, limit=400,
+                                  epsabs=1e-13, epsrel=1e-13)
+    assert 2 * math.pi * val == pytest.approx(1.0, abs=1e-9)
+    mc, _ = scipy.integrate.quad(lambda mu: mu * oracle.mhg(phase, mu), -1.0, 1.0, limit=400,
+                                 epsabs=1e-13, epsrel=1e-13)
+    assert 2 * math.pi * mc == pytest.approx(sum(w * g for w, g in phase), abs=1e-9)
+
+
+def test_mhg_reduces_to_hg():
+    for mu in (-1.0, -0.3, 0.0, 0.4, 1.0):
+        # one lobe of weight 1 is plain HG, bit for bit; equal lobes add up to it
+        assert oracle.mhg([(1.0, 0.7)], mu) == oracle.hg(0.7, mu)
+        assert oracle.mhg([(0.25, 0.7), (0.75, 0.7)], mu) == pytest.approx(oracle.hg(0.7, mu), rel=1e-15)
+        # forward and backward values of a two-lobe mixture, each lobe in closed form
+        fw = 0.6 * (1 + 0.9) / (4 * math.pi * (1 - 0.9) ** 2) + 0.4 * (1 - 0.5) / (4 * math.pi * (1 + 0.5) ** 2)
+        assert oracle.mhg([(0.6, 0.9), (0.4, -0.5)], 1.0) == pytest.approx(fw, rel=1e-13)
+
+
+def test_mhg_phase_features_and_single_scatter():
+    """With a two-lobe phase f, the centre site carries f(w.l), a site toward
+    the light f(w.l) f(1), the squeeze vector the mean cosine, and the
+    single-scatter term f(w.l) T(p); one lobe of weight 1 gives the HG
+    features bit for bit."""
+    phase = [(0.7, 0.8), (0.3, -0.4)]
+    f = lambda mu: sum(w * (1 - g * g) / (4 * math.pi * (1 + g * g - 2 * g * mu) ** 1.5) for w, g in phase)
+    M = oracle.Medium(medium.fbm_cloud(16, seed=2))
+    l = np.array([0.2, 0.3, 0.9])
+    l /= np.linalg.norm(l)
+    M.set_light(l.astype(np.float32))
+    lf = M.light_frame()["l"]
+    w = np.array([0.6, -0.48, 0.64], np.float32)
+    wf = w.astype(np.float64) / np.linalg.norm(w.astype(np.float64))
+    x = np.array([[0.45, 0.5, 0.55]], np.float32)
+    r = M.features(8.0, phase, 0.6, x, w[None])
+    wl = float(wf @ lf)
+    site = lambda q, j, i: ((q + 4) * 5 + (j + 2)) * 5 + (i + 2)
+    assert math.expm1(r["phi"][0, site(0, 0, 0)]) == pytest.approx(f(wl), rel=1e-12)
+    assert math.expm1(r["phi"][0, site(2, 0, 0)]) == pytest.approx(f(wl) * f(1.0), rel=1e-12)
+    assert r["stats"][0, 3, 6] == pytest.approx(0.7 * 0.8 - 0.3 * 0.4, rel=1e-15)
+    assert r["f0"][0] == pytest.approx(f(wl) * r["tp"][0], rel=1e-12)
+    one = M.features(8.0, [(1.0, 0.8)], 0.6, x, w[None])
+    plain = M.features(8.0, 0.8, 0.6, x, w[None])
+    for k in one:
+        np.testing.assert_array_equal(one[k], plain[k])
+
+
 def test_isotropic_phase_features():
     M = oracle.Medium(medium.constant(8, 0.3))
     M.set_light((0.3, 0.9, 0.3))
