@@ -104,9 +104,21 @@ int32_t nis_load_medium(nis_ctx *ctx, const float *density, int32_t n, float sig
  */
 int32_t nis_rebuild_pyramid(nis_ctx *ctx, int32_t medium, void *hip_stream);
 
-/* Changes sigma_t, albedo and g of a loaded medium.  The stored path density
- * is independent of sigma_t, so no sweep is needed.  Errors as above. */
+/* Changes sigma_t, albedo and g of a loaded medium (its phase becomes the
+ * single HG lobe g).  The stored path density is independent of sigma_t, so
+ * no sweep is needed.  Errors as above. */
 int32_t nis_set_medium_params(nis_ctx *ctx, int32_t medium, float sigma_t, float albedo, float g);
+
+/*
+ * nis_set_phase_lobes -- gives a loaded medium a multi-lobe phase (Sec. III.A,
+ * eq. 6): the weighted sum of n Henyey-Greenstein lobes, weights[i] >= 0
+ * summing to 1 (within 1e-5) and g[i] in (-1,1), 1 <= n <= 4; both arrays are
+ * copied.  The phase enters the phase features (eq. 8), the single-scatter
+ * term and, as its mean cosine sum(weights[i] g[i]), the squeeze vector
+ * (eq. 24).  One lobe of weight 1 equals nis_set_medium_params' g.  Frame
+ * server requests keep their own single g.  NIS_E_INVALID on a bad argument.
+ */
+int32_t nis_set_phase_lobes(nis_ctx *ctx, int32_t medium, int32_t n, const float *weights, const float *g);
 
 /* Frees a medium's pyramid and transmittance fields. */
 int32_t nis_unload_medium(nis_ctx *ctx, int32_t medium);
@@ -148,7 +160,8 @@ int32_t nis_set_precision(nis_ctx *ctx, int32_t precision);
 
 /*
  * nis_query -- in-scattered radiance at shading points (Sec. III.C.2 output
- * layer; eq. 19, eq. 21):  L = I * (HG(w.l) T(p) + albedo^gamma expm1(y)).
+ * layer; eq. 19, eq. 21):  L = I * (f(w.l) T(p) + albedo^gamma expm1(y)), f the
+ * medium's phase (HG, or the HG lobes of nis_set_phase_lobes).
  * `points`: host float32 [n][3] in unit-cube coordinates (may lie outside);
  * `view_dirs`: host float32 [n][3], normalised inside; `radiance_out`: host
  * float32 [n].  Synchronous.  Errors: NIS_E_INVALID (n <= 0, NULL, non-finite
@@ -331,7 +344,7 @@ int32_t nis_debug_path_pairs(nis_ctx *ctx, int32_t medium, int32_t level, float 
 /*
  * Gather stage on device arrays (synchronous): tbar/rho [n][12][225],
  * phi [n][225], stats [n][12][8], tp [n] (transmittance to the light),
- * f0 [n] (single-scatter term HG(w.l) T(p)).  Any output may be NULL.
+ * f0 [n] (single-scatter term f(w.l) T(p)).  Any output may be NULL.
  */
 int32_t nis_debug_features(nis_ctx *ctx, int32_t medium, const float *d_points,
                            const float *d_view_dirs, int64_t n, float *d_tbar, float *d_rho,

@@ -103,10 +103,15 @@ __device__ __forceinline__ double site_coord_a(double x, double scale, double qo
     return x + scale * qo;
 }
 
+// the medium's phase (its HG lobes summed with their weights, eq. 6) in FP64
 __device__ __forceinline__ double hg64(const MediumView& mv, double mu)
 {
-    double den = mv.hg_a - mv.hg_b * mu;
-    return mv.hg_k / (den * sqrt(den));
+    double v = 0.0;
+    for (int i = 0; i < mv.nl; i++) {
+        const double den = mv.hg_a[i] - mv.hg_b[i] * mu;
+        v += mv.hg_k[i] / (den * sqrt(den));
+    }
+    return v;
 }
 
 __device__ __forceinline__ float lerpf(float a, float b, float w) { return a + w * (b - a); }
@@ -267,17 +272,27 @@ k_features(FeatArgs A)
         // Phase features in FP32 through a denominator without cancellation:
         // for unit vectors 1 + g^2 - 2g w.d = (1-|g|)^2 + |g| |w - sign(g) d|^2,
         // every term non-negative, so a few roundings in relative terms;
-        // den^(-3/2) as rsq^3.  The centre site's table entry is (l, 1).
-        const float ga = fabsf(mv.g), gs = mv.g < 0.f ? -1.f : 1.f;
-        const float ca = (float)((1.0 - (double)ga) * (1.0 - (double)ga)), ck = (float)mv.hg_k;
+        // den^(-3/2) as rsq^3, summed over the phase's lobes (eq. 6).  The
+        // centre site's table entry is (l, 1).
         const float wf[3] = {(float)w[0], (float)w[1], (float)w[2]};
+        // one lobe's term of the phase at w . d for a site table entry e
+        auto lobe = [&](int i, const float4& e) __attribute__((always_inline)) {
+            const float gs = mv.ph_s[i];
+            const float dx = wf[0] - gs * e.x, dy = wf[1] - gs * e.y, dz = wf[2] - gs * e.z;
+            const float den = mv.ph_c[i] + mv.ph_a[i] * (dx * dx + dy * dy + dz * dz);
+            const float r = __builtin_amdgcn_rsqf(den);
+            return mv.ph_k[i] * e.w * (r * r * r);
+        };
+        const bool one_lobe = mv.nl == 1;
         float phs = 0.f, phm = -INFINITY;
         for (int t = sub; t < kSites; t += 16) {
             const float4 e = A.tab->site[t];
-            const float dx = wf[0] - gs * e.x, dy = wf[1] - gs * e.y, dz = wf[2] - gs * e.z;
-            const float den = ca + ga * (dx * dx + dy * dy + dz * dz);
-            const float r = __builtin_amdgcn_rsqf(den);
-            const float P = ck * e.w * (r * r * r);
+            float P = lobe(0, e);
+            if (!one_lobe) {
+#pragma unroll
+                for (int i = 1; i < kMaxLobes; i++)
+                    if (i < mv.nl) P += lobe(i, e);
+            }
             // log(1 + P) with the hardware logarithm: P >= 0, so 1 + P rounds
             // to within 6e-8 and the absolute error stays near 1e-7
             float ph = __logf(1.f + P);

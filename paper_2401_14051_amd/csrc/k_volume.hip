@@ -278,9 +278,9 @@ k_sweep(MediumView mv, SweepArgs sa)
 }
 
 // Per-light lattice tables: unit offset directions d_t = o_t / |o_t| and the
-// incident-side phase HG(d_t . l) of the phase feature (eq. 8) for the
-// current g.  The centre site (o = 0) has no direction; its phase feature is
-// HG(w . l), so it stores (l, 1).
+// incident-side phase f(d_t . l) of the phase feature (eq. 8) for the
+// medium's phase f (its HG lobes, eq. 6).  The centre site (o = 0) has no
+// direction; its phase feature is f(w . l), so it stores (l, 1).
 __global__ void k_site_tables(MediumView mv, SiteTables* tab)
 {
     const int t = threadIdx.x;
@@ -296,9 +296,12 @@ __global__ void k_site_tables(MediumView mv, SiteTables* tab)
         return;
     }
     const double dl = (o[0] * mv.l[0] + o[1] * mv.l[1] + o[2] * mv.l[2]) / on;
-    const double den = mv.hg_a - mv.hg_b * dl;
-    tab->site[t] = make_float4((float)(o[0] / on), (float)(o[1] / on), (float)(o[2] / on),
-                               (float)(mv.hg_k / (den * sqrt(den))));
+    double ph = 0.0;   // the medium's phase at d_t . l: its lobes summed with their weights (eq. 6)
+    for (int k = 0; k < mv.nl; k++) {
+        const double den = mv.hg_a[k] - mv.hg_b[k] * dl;
+        ph += mv.hg_k[k] / (den * sqrt(den));
+    }
+    tab->site[t] = make_float4((float)(o[0] / on), (float)(o[1] / on), (float)(o[2] / on), (float)ph);
 }
 
 // Light-axis density pairs (a layout of the pyramid for the gather): for each

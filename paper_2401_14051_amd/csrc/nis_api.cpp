@@ -138,14 +138,24 @@ MediumView make_view(const Medium* M, const LightState* ls, const Params& P, con
     std::memcpy(v.qoff, ls->qoff, sizeof(v.qoff));
     v.sigma_t = P.sigma_t;
     v.albedo = P.albedo;
-    v.g = P.g;
     v.radiance = P.radiance;
     v.lam = net ? net->lam : 0.6f;
     v.gamma = net ? net->gamma : 4.f;
-    double g = P.g;
-    v.hg_a = 1.0 + g * g;
-    v.hg_b = 2.0 * g;
-    v.hg_k = (1.0 - g * g) / (4.0 * M_PI);
+    v.nl = P.phase.n;
+    double mc = 0.0;
+    for (int i = 0; i < P.phase.n; i++) {
+        const double g = P.phase.g[i], w = P.phase.w[i];
+        mc += w * g;
+        v.hg_a[i] = 1.0 + g * g;
+        v.hg_b[i] = 2.0 * g;
+        v.hg_k[i] = w * ((1.0 - g * g) / (4.0 * M_PI));
+        const double ga = std::fabs(g);
+        v.ph_a[i] = (float)ga;
+        v.ph_s[i] = g < 0.0 ? -1.f : 1.f;
+        v.ph_c[i] = (float)((1.0 - ga) * (1.0 - ga));
+        v.ph_k[i] = (float)v.hg_k[i];
+    }
+    v.g = (float)mc;
     return v;
 }
 
@@ -162,16 +172,16 @@ template <class F> void timed(const char* name, hipStream_t s, F&& launch)
     g_prof->recs.push_back({name, a, b});
 }
 
-void refresh_tables(const Medium* M, LightState* ls, float g, hipStream_t s)
+void refresh_tables(const Medium* M, LightState* ls, const Phase& ph, hipStream_t s)
 {
-    if (ls->tab_valid && ls->tab_g == g) return;
+    if (ls->tab_valid && same_phase(ls->tab_phase, ph)) return;
     ls->tab.reserve(sizeof(SiteTables), "site tables");
     Params P = medium_params(M);
-    P.g = g;
+    P.phase = ph;
     MediumView mv = make_view(M, ls, P, nullptr);
     timed("site_tables", s, [&] { return launch_site_tables(mv, ls->tab.as<SiteTables>(), s); });
     ls->tab_valid = true;
-    ls->tab_g = g;
+    ls->tab_phase = ph;
 }
 
 void ensure_sweep(const Medium* M, LightState* ls, hipStream_t s)
@@ -399,7 +409,7 @@ Medium* get_medium(nis_ctx* ctx, int32_t id)
     return it->second;
 }
 
-Params medium_params(const Medium* M) { return Params{M->sigma_t, M->albedo, M->g, M->radiance}; }
+Params medium_params(const Medium* M) { return Params{M->sigma_t, M->albedo, M->phase, M->radiance}; }
 
 void light_layout(const Medium* M, const double l[3], LightState* ls)
 {
@@ -473,7 +483,7 @@ void run_query(Workspace& ws, const Net* net, int prec, const Medium* M, LightSt
 {
     if (!net) fail(NIS_E_STATE, "no weights set");
     ensure_sweep(M, ls, s);
-    refresh_tables(M, ls, Pm.g, s);
+    refresh_tables(M, ls, Pm.phase, s);
     const PackedNet& P = net->packed[prec];
     const int64_t chunk = n < kChunk ? n : kChunk;
     ws.desc.reserve((size_t)chunk * kDescPad * desc_elem_bytes(prec), "descriptor workspace");
@@ -737,7 +747,7 @@ int32_t nis_load_medium(nis_ctx* ctx, const float* density, int32_t n, float sig
             M->n = n;
             M->sigma_t = sigma_t;
             M->albedo = albedo;
-            M->g = g;
+            M->phase = single_lobe(g);
             M->rmax = rmax;
             int L = 1;
             while ((1 << (L - 1)) < n) L++;
@@ -788,7 +798,30 @@ int32_t nis_set_medium_params(nis_ctx* ctx, int32_t medium, float sigma_t, float
         validate_params(sigma_t, albedo, g);
         M->sigma_t = sigma_t;
         M->albedo = albedo;
-        M->g = g;
+        M->phase = single_lobe(g);
+    });
+}
+
+int32_t nis_set_phase_lobes(nis_ctx* ctx, int32_t medium, int32_t n, const float* weights, const float* g)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        Medium* M = get_medium(ctx, medium);
+        if (!weights || !g) fail(NIS_E_INVALID, "weights or g is NULL");
+        if (n < 1 || n > kMaxLobes) fail(NIS_E_INVALID, "the phase takes 1 to 4 lobes");
+        Phase ph = {};
+        ph.n = n;
+        double sum = 0.0;
+        for (int i = 0; i < n; i++) {
+            if (!(std::isfinite(weights[i]) && weights[i] >= 0.f)) fail(NIS_E_INVALID, "lobe weights must be >= 0");
+            if (!(std::isfinite(g[i]) && g[i] > -1.f && g[i] < 1.f)) fail(NIS_E_INVALID, "lobe g must be in (-1,1)");
+            ph.w[i] = weights[i];
+            ph.g[i] = g[i];
+            sum += weights[i];
+        }
+        if (std::fabs(sum - 1.0) > 1e-5) fail(NIS_E_INVALID, "lobe weights must sum to 1");
+        M->phase = ph;
     });
 }
 

@@ -30,6 +30,14 @@ constexpr int kPrecFP32 = 0, kPrecBF16 = 1, kPrecFP8 = 2;
 constexpr int kRayPad = 2;
 constexpr int kPairPad = 8;
 
+// Phase function of a medium: n HG lobes with weights w summing to one and
+// asymmetries g (Sec. III.A, eq. 6); one lobe of weight 1 is plain HG (eq. 5).
+constexpr int kMaxLobes = 4;
+struct Phase {
+    int n;
+    float w[kMaxLobes], g[kMaxLobes];
+};
+
 // Geometry of one pyramid level and its light-sheared path-density field.
 struct Level {
     int n;              // edge n_m
@@ -58,16 +66,18 @@ struct MediumView {
     double l[3];        // unit light direction (towards the light)
     double la;          // |l_a|
     double qoff[3][9];  // (q * l_d) / |l_a| for q = -4..4, the lattice's along-light offsets
-    float sigma_t, albedo, g, radiance;
+    float sigma_t, albedo, g, radiance;   // g: the phase's mean cosine, sum of w_i g_i
     float lam;          // graded-field coefficient base (eq. 1)
     float gamma;        // decode exponent (eq. 21)
-    double hg_a, hg_b, hg_k;   // HG constants: 1+g^2, 2g, (1-g^2)/(4 pi)
+    int nl;                    // phase lobes; per lobe i:
+    double hg_a[kMaxLobes], hg_b[kMaxLobes], hg_k[kMaxLobes];   // 1+g^2, 2g, w (1-g^2)/(4 pi)
+    float ph_a[kMaxLobes], ph_s[kMaxLobes], ph_c[kMaxLobes], ph_k[kMaxLobes];   // |g|, sign g, (1-|g|)^2, float(hg_k)
 };
 
 // Per-light constant tables for the gather (one copy per medium).
 struct SiteTables {
-    // (d_t, HG(d_t . l)) per site: the unit lattice offset direction and the
-    // incident-side phase for the current g; the centre site holds (l, 1)
+    // (d_t, f(d_t . l)) per site: the unit lattice offset direction and the
+    // incident-side value of the medium's phase f; the centre site holds (l, 1)
     float4 site[kSites];
 };
 

@@ -79,7 +79,7 @@ struct LightState {
     bool stale = true;                      // D, P and DP must be recomputed
     uint64_t swept_version = 0;             // pyramid version they were computed from
     bool tab_valid = false;
-    float tab_g = 0.f;                      // g the site tables were computed for
+    Phase tab_phase = {};                   // phase the site tables were computed for
     size_t bytes() const { return RT.bytes + P.bytes + DP.bytes + tab.bytes; }
     void release()
     {
@@ -94,7 +94,8 @@ struct LightState {
 
 struct Medium {
     int n = 0, levels = 0;
-    float sigma_t = 0, albedo = 0, g = 0;
+    float sigma_t = 0, albedo = 0;
+    Phase phase = {1, {1.f}, {0.f}};
     float rmax = 0;                         // largest density of level 0
     Level lev[kMaxLevels] = {};             // n and rho_off of every level
     DevBuf rho;
@@ -106,8 +107,19 @@ struct Medium {
 
 // Medium parameters a computation runs with.
 struct Params {
-    float sigma_t, albedo, g, radiance;
+    float sigma_t, albedo;
+    Phase phase;
+    float radiance;
 };
+
+inline Phase single_lobe(float g) { return Phase{1, {1.f}, {g}}; }
+inline bool same_phase(const Phase& a, const Phase& b)
+{
+    if (a.n != b.n) return false;
+    for (int i = 0; i < a.n; i++)
+        if (a.w[i] != b.w[i] || a.g[i] != b.g[i]) return false;
+    return true;
+}
 
 // Fills the light frame and level ranges of `ls` for direction l (unit);
 // reserves nothing.  Fails with NIS_E_UNSUPPORTED if a level's field would

@@ -74,6 +74,7 @@ _SIGNATURES = {
     "nis_set_medium_params": [_vp, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float],
     "nis_unload_medium": [_vp, _i32],
     "nis_set_light": [_vp, _i32, _vp, ctypes.c_float, _i32],
+    "nis_set_phase_lobes": [_vp, _i32, _i32, _vp, _vp],
     "nis_set_weights": [_vp, _vp, ctypes.c_size_t],
     "nis_set_precision": [_vp, _i32],
     "nis_query": [_vp, _i32, _vp, _vp, _i64, _vp],
@@ -245,6 +246,12 @@ class Context:
 
     def unload_medium(self, medium):
         _check(_lib.nis_unload_medium(self.h, medium))
+
+    def set_phase_lobes(self, medium, lobes):
+        """Multi-lobe HG phase (eq. 6) from a sequence of (weight, g) pairs."""
+        w = np.ascontiguousarray([float(a) for a, _ in lobes], np.float32)
+        g = np.ascontiguousarray([float(b) for _, b in lobes], np.float32)
+        _check(_lib.nis_set_phase_lobes(self.h, medium, len(w), _ptr(w), _ptr(g)))
 
     def set_light(self, medium, direction, radiance=1.0, eager=False):
         d = np.ascontiguousarray(direction, dtype=np.float32)

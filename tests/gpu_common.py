@@ -27,13 +27,18 @@ def rel_l2(a, b):
 
 
 class Scene:
-    """A medium loaded both on the GPU and in the oracle, under one light."""
+    """A medium loaded both on the GPU and in the oracle, under one light.  g
+    is one HG asymmetry or a sequence of (weight, g) lobes."""
 
     def __init__(self, ctx, density, light, sigma_t=8.0, albedo=0.99, g=0.85, radiance=1.0):
         self.ctx = ctx
         self.density = np.ascontiguousarray(density, np.float32)
         self.sigma_t, self.albedo, self.g, self.radiance = sigma_t, albedo, g, radiance
-        self.mid = ctx.load_medium(self.density, sigma_t, albedo, g)
+        if np.ndim(g) == 0:
+            self.mid = ctx.load_medium(self.density, sigma_t, albedo, g)
+        else:
+            self.mid = ctx.load_medium(self.density, sigma_t, albedo, g[0][1])
+            ctx.set_phase_lobes(self.mid, g)
         self.ctx.set_light(self.mid, light, radiance)
         self.om = oracle.Medium(self.density)
         self.om.set_light(np.asarray(light, np.float32))
@@ -41,12 +46,18 @@ class Scene:
     def close(self):
         self.ctx.unload_medium(self.mid)
 
+    def phase(self):
+        """The phase as the library holds it (float32 values)."""
+        if np.ndim(self.g) == 0:
+            return f32(self.g)
+        return [(f32(w), f32(g)) for w, g in self.g]
+
     def oracle_query(self, params, pts, dirs, want_desc=False):
         return self.om.query(oracle_params(params), pts, dirs, f32(self.sigma_t), f32(self.albedo),
-                             f32(self.g), f32(self.radiance), want_desc=want_desc)
+                             self.phase(), f32(self.radiance), want_desc=want_desc)
 
     def oracle_features(self, params, pts, dirs):
-        return self.om.features(f32(self.sigma_t), f32(self.g), f32(params["lam"]), pts, dirs)
+        return self.om.features(f32(self.sigma_t), self.phase(), f32(params["lam"]), pts, dirs)
 
 
 def small_points(extra_random=300, seed=5):

@@ -75,7 +75,10 @@ def test_sweep_matches_oracle(ctx, n, light):
 
 @pytest.mark.parametrize("light,g", [((0.3, 0.9, 0.3), 0.85), ((-0.7, 0.2, 0.4), 0.5),
                                      ((0.1, -0.3, -0.95), 0.95), ((1.0, 0.2, -0.3), 0.0),
-                                     ((0.2, 0.3, -0.9), -0.9)])
+                                     ((0.2, 0.3, -0.9), -0.9),
+                                     # multi-lobe phases (eq. 6): two and three HG lobes
+                                     ((0.3, 0.9, 0.3), [(0.7, 0.8), (0.3, -0.4)]),
+                                     ((-0.7, 0.2, 0.4), [(0.5, 0.95), (0.3, 0.2), (0.2, -0.7)])])
 def test_features_match_oracle(ctx, light, g):
     print("features light=%s g=%s" % (light, g), flush=True)
     d, pts, dirs = small_points()
@@ -173,6 +176,27 @@ def test_backbone_widths(ctx, width, prec):
     s.close()
 
 
+def test_multi_lobe_phase_query_and_single_lobe_identity(ctx):
+    """FP32 radiance with a two-lobe phase meets the FP32 bound against the
+    oracle; one lobe of weight 1 gives the plain-HG features bit for bit."""
+    d, pts, dirs = small_points(extra_random=100)
+    phase = [(0.6, 0.9), (0.4, -0.3)]
+    s = Scene(ctx, d, (0.2, -0.5, 0.8), g=phase)
+    params = weights.he_init(128, 6, seed=1, bias_scale=0.05)
+    ctx.set_weights(params)
+    ctx.set_precision("fp32")
+    ref = s.oracle_query(params, pts, dirs)
+    L = ctx.query(s.mid, pts, dirs)
+    assert rel_l2(L, ref["L"]) <= 1e-4
+    ctx.set_phase_lobes(s.mid, [(1.0, 0.7)])
+    one = ctx.features(s.mid, dev(pts), dev(dirs))
+    ctx.set_medium_params(s.mid, 8.0, 0.99, 0.7)
+    plain = ctx.features(s.mid, dev(pts), dev(dirs))
+    for k in one:
+        np.testing.assert_array_equal(one[k].cpu().numpy(), plain[k].cpu().numpy())
+    s.close()
+
+
 def test_zero_weights_reduce_to_single_scatter(ctx):
     d, pts, dirs = small_points()
     s = Scene(ctx, d, (0.2, -0.5, 0.8), radiance=2.5)
@@ -251,6 +275,11 @@ def test_invalid_arguments_are_rejected(ctx):
     with pytest.raises(nis.NisError) as e:
         ctx.set_light(mid, (0.0, 0.0, 0.0))
     assert e.value.code == nis.NIS_E_INVALID
+    for lobes in ([], [(0.2, 0.1)] * 5, [(0.5, 0.3), (0.4, 0.2)], [(1.0, 1.0)], [(1.5, 0.2), (-0.5, 0.1)],
+                  [(0.5, np.nan), (0.5, 0.1)]):
+        with pytest.raises(nis.NisError) as e:
+            ctx.set_phase_lobes(mid, lobes)
+        assert e.value.code == nis.NIS_E_INVALID
     pts, dirs = camera.random_points(10, seed=1)
     with pytest.raises(nis.NisError) as e:
         ctx.query(mid, pts, dirs)
