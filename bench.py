@@ -343,10 +343,17 @@ def main():
         tq = time.perf_counter() - tq
         frame_s = t_sweep + tq * len(pts) / len(cidx)
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        model = "unknown CPU"
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+        except (OSError, StopIteration):
+            pass
         cpu = {"value": len(pts) / frame_s, "unit": "shading points/s", "cores": cores, "kind": "oracle",
-               "sample": "FP64 oracle: full-resolution sweep (%.2fs, 1 thread) plus a seeded %d-point subset "
-                         "of the frame's collisions (%.2fs on %d threads), scaled to the frame's %d points"
-                         % (t_sweep, len(cidx), tq, cores, len(pts))}
+               "sample": "FP64 oracle on %s (%d logical CPUs visible): full-resolution sweep (%.2fs, 1 thread) "
+                         "plus a seeded %d-point subset of the frame's collisions (%.2fs on %d threads), scaled to "
+                         "the frame's %d points" % (model, os.cpu_count() or 0, t_sweep, len(cidx), tq, cores,
+                                                    len(pts))}
 
     prec = args.precision
     ms = res[prec]["ms"]
