@@ -63,9 +63,79 @@ double om_hg(double g, double mu)
     return (1.0 - g * g) / (4.0 * OM_PI * den * sqrt(den));
 }
 
+/* Complete elliptic integral of the second kind,
+ * E(m) = int_0^(pi/2) sqrt(1 - m sin^2 t) dt, 0 <= m < 1, by the
+ * arithmetic-geometric mean: a0 = 1, b0 = sqrt(1-m), c0 = sqrt(m),
+ * K = pi / (2 a_N), E = K (1 - sum_n 2^(n-1) c_n^2). */
+static double om_ellip_e(double m)
+{
+    double a = 1.0, b = sqrt(1.0 - m), c = sqrt(m), sum = 0.5 * c * c, pw = 0.5;
+    for (int it = 0; it < 40 && fabs(c) > 1e-17; it++) {
+        double an = 0.5 * (a + b);
+        c = 0.5 * (a - b);
+        b = sqrt(a * b);
+        a = an;
+        pw *= 2.0;
+        sum += pw * c * c;
+    }
+    return (OM_PI / (2.0 * a)) * (1.0 - sum);
+}
+
+/* 64-point Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_64). */
+static double om_gl_x[64], om_gl_w[64];
+static int om_gl_ready = 0;
+static void om_gl_init(void)
+{
+    if (om_gl_ready) return;
+    const int n = 64;
+    for (int i = 0; i < n; i++) {
+        double x = cos(OM_PI * (i + 0.75) / (n + 0.5)), dp = 0.0;
+        for (int it = 0; it < 100; it++) {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= n; k++) {
+                double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (x * p1 - p0) / (x * x - 1.0);
+            double dx = p1 / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        om_gl_x[i] = x;
+        om_gl_w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+    om_gl_ready = 1;
+}
+
+/* Volume phase of one HG lobe (Sec. III.A, eq. 9): the mean of HG(g, w.phi)
+ * over the directions phi of a cone of half-angle beta around a unit
+ * direction d, given mu0 = w.d.  With phi at polar angle theta from d and
+ * azimuth psi, w.phi = mu0 cos theta + sqrt(1 - mu0^2) sin theta cos psi, so
+ * 1 + g^2 - 2 g w.phi = A - B cos psi; the azimuthal integral of
+ * (A - B cos psi)^(-3/2) over [0, 2 pi) is 4 E(2B/(A+B)) / ((A-B) sqrt(A+B))
+ * (B taken >= 0, cos psi being symmetric), and cos theta in [cos beta, 1] is
+ * integrated by 64-point Gauss-Legendre.  The cone's solid angle is
+ * 2 pi (1 - cos beta).  om_gl_init() must have run. */
+double om_hg_cone(double g, double mu0, double beta)
+{
+    double cb = cos(beta), s0 = sqrt(fmax(0.0, 1.0 - mu0 * mu0));
+    double half = 0.5 * (1.0 - cb), mid = 0.5 * (1.0 + cb), acc = 0.0;
+    for (int i = 0; i < 64; i++) {
+        double t = mid + half * om_gl_x[i];
+        double A = 1.0 + g * g - 2.0 * g * mu0 * t;
+        double B = fabs(2.0 * g * s0 * sqrt(fmax(0.0, 1.0 - t * t)));
+        double az = 4.0 * om_ellip_e(2.0 * B / (A + B)) / ((A - B) * sqrt(A + B));
+        acc += om_gl_w[i] * half * az;
+    }
+    return (1.0 - g * g) / (4.0 * OM_PI) * acc / (2.0 * OM_PI * (1.0 - cb));
+}
+
 /* Multi-lobe HG phase (Sec. III.A, eq. 6): a linear combination of HG lobes
  * with weights lw[i] (summing to one) and asymmetries lg[i].  One lobe of
  * weight 1 is the HG phase of eq. 5. */
+void om_volume_init(void) { om_gl_init(); }
+
 double om_mhg(int nl, const double *lw, const double *lg, double mu)
 {
     double v = 0.0;
@@ -301,14 +371,18 @@ static void site_offset(const om_medium *M, int t, double o[3])
  *                 max tbar, g, alpha = acos(w.l), where g is the phase's
  *                 mean cosine, sum_i lw[i] lg[i],
  *   tp[p] = exp(-sigma_t D_0(p)) (eq. 15), f0[p] = f(w.l) tp[p] (eq. 19).
+ * With volume != 0 both factors of the phase feature are volume phases
+ * (eq. 9): means of f over the cone under which the site, a ball of half the
+ * lattice spacing, is seen from p (om_hg_cone); the centre site keeps f(w.l).
  * Any output pointer may be NULL.                                           */
 void om_features(const om_medium *M, double sigma_t, int nl, const double *lw, const double *lg,
-                 double lam, const float *pts, const float *dirs, int64_t np,
+                 int volume, double lam, const float *pts, const float *dirs, int64_t np,
                  double *tbar, double *rho, double *phi, double *stats,
                  double *tp, double *f0)
 {
     double g = 0.0;
     for (int i = 0; i < nl; i++) g += lw[i] * lg[i];
+    om_gl_init();
     int L = M->levels;
     double h0 = 1.0 / M->n;
 #pragma omp parallel for schedule(dynamic, 16)
@@ -331,7 +405,18 @@ void om_features(const om_medium *M, double sigma_t, int nl, const double *lw, c
             } else {
                 double wd = (w[0] * o[0] + w[1] * o[1] + w[2] * o[2]) / on;
                 double dl = (o[0] * M->l[0] + o[1] * M->l[1] + o[2] * M->l[2]) / on;
-                P = om_mhg(nl, lw, lg, wd) * om_mhg(nl, lw, lg, dl);
+                if (volume) {
+                    /* eq. 9: the site seen from p as a ball of half the lattice
+                     * spacing, i.e. a cone of half-angle asin(1 / (2 |o|)) */
+                    double beta = asin(0.5 / on), fw = 0.0, fl = 0.0;
+                    for (int i = 0; i < nl; i++) {
+                        fw += lw[i] * om_hg_cone(lg[i], wd, beta);
+                        fl += lw[i] * om_hg_cone(lg[i], dl, beta);
+                    }
+                    P = fw * fl;
+                } else {
+                    P = om_mhg(nl, lw, lg, wd) * om_mhg(nl, lw, lg, dl);
+                }
             }
             ph[t] = log1p(P);
             phmean += ph[t];
@@ -478,18 +563,19 @@ double om_mlp(const double *params, int width, int n_linear, const double *desc)
  * F0 = f(w.l) T(p) I is the single-scatter term of the scattering-order
  * series (eq. 19).  y_out/fhat_out may be NULL. */
 void om_query(const om_medium *M, double sigma_t, double albedo, int nl, const double *lw,
-              const double *lg, double lam,
+              const double *lg, int volume, double lam,
               double gamma, double radiance, const double *params, int width, int n_linear,
               const float *pts, const float *dirs, int64_t np,
               double *L_out, double *y_out, double *fhat_out, double *desc_out)
 {
+    om_gl_init();
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t p = 0; p < np; p++) {
         double *tb = (double *)malloc(sizeof(double) * OM_LAYERS * OM_SITES);
         double st[OM_LAYERS * OM_STATS];
         double f0;
         double *desc = desc_out ? desc_out + p * OM_DESC : (double *)malloc(sizeof(double) * OM_DESC);
-        om_features(M, sigma_t, nl, lw, lg, lam, pts + 3 * p, dirs + 3 * p, 1, tb, NULL, NULL, st, NULL, &f0);
+        om_features(M, sigma_t, nl, lw, lg, volume, lam, pts + 3 * p, dirs + 3 * p, 1, tb, NULL, NULL, st, NULL, &f0);
         om_descriptor(params, tb, st, albedo, desc);
         double y = om_mlp(params, width, n_linear, desc);
         double F = pow(albedo, gamma) * expm1(y);

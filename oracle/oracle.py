@@ -63,14 +63,18 @@ def lib():
         L.om_hg.argtypes = [ctypes.c_double, ctypes.c_double]
         L.om_mhg.restype = ctypes.c_double
         L.om_mhg.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double]
-        L.om_features.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, _dp, _dp, ctypes.c_double,
+        L.om_hg_cone.restype = ctypes.c_double
+        L.om_hg_cone.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.om_volume_init.argtypes = []
+        L.om_features.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, _dp, _dp, ctypes.c_int,
+                                  ctypes.c_double,
                                   _fp, _fp, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _dp]
         L.om_cnn_se.argtypes = [_dp, _dp, _dp]
         L.om_descriptor.argtypes = [_dp, _dp, _dp, ctypes.c_double, _dp]
         L.om_mlp.restype = ctypes.c_double
         L.om_mlp.argtypes = [_dp, ctypes.c_int, ctypes.c_int, _dp]
         L.om_query.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp, _dp,
-                               ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, ctypes.c_int,
+                               ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, ctypes.c_int,
                                ctypes.c_int, _fp, _fp, ctypes.c_int64, _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
@@ -101,6 +105,13 @@ def lobes(phase):
     lw = np.array([float(w) for w, _ in phase])
     lg = np.array([float(g) for _, g in phase])
     return lw, lg
+
+
+def hg_cone(g, mu0, beta):
+    """Volume phase of one HG lobe (eq. 9): its mean over a cone of half-angle
+    beta around a direction d, for mu0 = w . d."""
+    lib().om_volume_init()
+    return lib().om_hg_cone(float(g), float(mu0), float(beta))
 
 
 def mhg(phase, mu):
@@ -204,20 +215,22 @@ class Medium:
     def sample_D(self, m, x):
         return lib().om_sample_D(self.h, m, _ptr(_f64(x), _dp))
 
-    def features(self, sigma_t, g, lam, pts, dirs):
-        """Per-point features; g is one asymmetry or a sequence of (weight, g) lobes."""
+    def features(self, sigma_t, g, lam, pts, dirs, volume=False):
+        """Per-point features; g is one asymmetry or a sequence of (weight, g)
+        lobes; volume selects the volume phase of eq. 9 for the phase features."""
         pts, dirs = _f32(pts), _f32(dirs)
         P = pts.shape[0]
         out = {"tbar": np.zeros((P, LAYERS, SITES)), "rho": np.zeros((P, LAYERS, SITES)),
                "phi": np.zeros((P, SITES)), "stats": np.zeros((P, LAYERS, STATS)),
                "tp": np.zeros(P), "f0": np.zeros(P)}
         lw, lg = lobes(g)
-        lib().om_features(self.h, float(sigma_t), len(lw), _ptr(lw, _dp), _ptr(lg, _dp), float(lam), _ptr(pts, _fp),
+        lib().om_features(self.h, float(sigma_t), len(lw), _ptr(lw, _dp), _ptr(lg, _dp), int(bool(volume)),
+                          float(lam), _ptr(pts, _fp),
                           _ptr(dirs, _fp), P, *[_ptr(out[k], _dp) for k in
                                                 ("tbar", "rho", "phi", "stats", "tp", "f0")])
         return out
 
-    def query(self, params, pts, dirs, sigma_t, albedo, g, radiance=1.0, want_desc=False):
+    def query(self, params, pts, dirs, sigma_t, albedo, g, radiance=1.0, want_desc=False, volume=False):
         """Radiance, network output y and decoded F for each point; g is one
         asymmetry or a sequence of (weight, g) lobes."""
         pts, dirs = _f32(pts), _f32(dirs)
@@ -227,7 +240,7 @@ class Medium:
         desc = np.zeros((P, DESC)) if want_desc else None
         lw, lg = lobes(g)
         lib().om_query(self.h, float(sigma_t), float(albedo), len(lw), _ptr(lw, _dp), _ptr(lg, _dp),
-                       float(params["lam"]),
+                       int(bool(volume)), float(params["lam"]),
                        float(params["gamma"]), float(radiance), _ptr(flat, _dp),
                        int(params["width"]), int(params["n_linear"]), _ptr(pts, _fp),
                        _ptr(dirs, _fp), P, _ptr(L, _dp), _ptr(y, _dp), _ptr(F, _dp),

@@ -383,6 +383,75 @@ def test_mhg_phase_features_and_single_scatter():
         np.testing.assert_array_equal(one[k], plain[k])
 
 
+# --------------------------------------------------------------------------
+# Volume phase, Sec. III.A eq. (9): the phase averaged over the cone under
+# which a template site is seen from the point
+
+
+def _cone_mean_brute(phase, mu0, beta):
+    """Mean of a phase over a cone of half-angle beta around d, w.d = mu0, by
+    two-dimensional adaptive quadrature over the cone's polar and azimuthal
+    angles (the definition, integrated numerically)."""
+    lobes = [(1.0, phase)] if np.ndim(phase) == 0 else phase
+    f = lambda mu: sum(w * (1 - g * g) / (4 * math.pi * (1 + g * g - 2 * g * mu) ** 1.5) for w, g in lobes)
+    s0 = math.sqrt(1 - mu0 * mu0)
+    val, _ = scipy.integrate.dblquad(
+        lambda psi, th: f(mu0 * math.cos(th) + s0 * math.sin(th) * math.cos(psi)) * math.sin(th),
+        0.0, beta, 0.0, 2 * math.pi, epsabs=1e-14, epsrel=1e-12)
+    return val / (2 * math.pi * (1 - math.cos(beta)))
+
+
+@pytest.mark.parametrize("g,mu0,beta", [(0.9, 0.7, 0.3), (0.95, 0.99, 0.07), (0.95, -0.4, 0.5),
+                                        (-0.6, 0.2, 0.25), (0.5, 1.0, 0.1), (0.8, -1.0, 0.2)])
+def test_volume_phase_matches_brute_force_cone_quadrature(g, mu0, beta):
+    assert oracle.hg_cone(g, mu0, beta) == pytest.approx(_cone_mean_brute(g, mu0, beta), rel=1e-10)
+
+
+def test_volume_phase_limits():
+    for g in (0.0, 0.6, -0.85):
+        # the whole sphere: the normalisation 1/(4 pi) (the 64-point rule over the
+        # whole of cos theta leaves ~2e-11 at g = -0.85; the lattice's cones are
+        # at most 30 degrees wide); g = 0: isotropic for any cone
+        assert oracle.hg_cone(g, 0.3, math.pi) == pytest.approx(1 / (4 * math.pi), rel=1e-9)
+    assert oracle.hg_cone(0.0, -0.7, 0.4) == pytest.approx(1 / (4 * math.pi), rel=1e-14)
+    # a vanishing cone: the point phase
+    for g, mu0 in ((0.9, 0.5), (0.95, 0.999), (-0.5, -0.8)):
+        assert oracle.hg_cone(g, mu0, 1e-5) == pytest.approx(oracle.hg(g, mu0), rel=1e-8)
+
+
+def test_volume_phase_features():
+    """With the volume phase a site's feature is the product of the two cone
+    means (site seen as a ball of half the lattice spacing: half-angle
+    asin(1 / (2 |o|))); the centre site keeps the point phase."""
+    phase = [(0.7, 0.8), (0.3, -0.4)]
+    M = oracle.Medium(medium.constant(8, 0.3))
+    l = np.array([0.2, 0.3, 0.9])
+    l /= np.linalg.norm(l)
+    M.set_light(l.astype(np.float32))
+    fr = M.light_frame()
+    lf = fr["l"]
+    w = np.array([0.6, -0.48, 0.64], np.float32)
+    wf = w.astype(np.float64) / np.linalg.norm(w.astype(np.float64))
+    x = np.array([[0.45, 0.5, 0.55]], np.float32)
+    vol = M.features(8.0, phase, 0.6, x, w[None], volume=True)
+    pnt = M.features(8.0, phase, 0.6, x, w[None])
+    site = lambda q, j, i: ((q + 4) * 5 + (j + 2)) * 5 + (i + 2)
+    assert vol["phi"][0, site(0, 0, 0)] == pnt["phi"][0, site(0, 0, 0)]
+    # a lateral site: o = e_b (b = x for a = z), |o| = 1
+    d = np.array([1.0, 0.0, 0.0])
+    beta = math.asin(0.5)
+    expect = _cone_mean_brute(phase, float(wf @ d), beta) * _cone_mean_brute(phase, float(d @ lf), beta)
+    assert math.expm1(vol["phi"][0, site(0, 0, 1)]) == pytest.approx(expect, rel=1e-9)
+    # a site toward the light, q = 2: o = 2 l / |l_a|, |o| = 2 / |l_a|
+    on = 2 / abs(lf[2])
+    beta = math.asin(0.5 / on)
+    expect = _cone_mean_brute(phase, float(wf @ lf), beta) * _cone_mean_brute(phase, 1.0, beta)
+    assert math.expm1(vol["phi"][0, site(2, 0, 0)]) == pytest.approx(expect, rel=1e-9)
+    # everything but the phase features is unchanged
+    for k in ("tbar", "rho", "tp", "f0"):
+        np.testing.assert_array_equal(vol[k], pnt[k])
+
+
 def test_isotropic_phase_features():
     M = oracle.Medium(medium.constant(8, 0.3))
     M.set_light((0.3, 0.9, 0.3))
