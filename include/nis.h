@@ -120,6 +120,18 @@ int32_t nis_set_medium_params(nis_ctx *ctx, int32_t medium, float sigma_t, float
  */
 int32_t nis_set_phase_lobes(nis_ctx *ctx, int32_t medium, int32_t n, const float *weights, const float *g);
 
+/*
+ * nis_set_volume_phase -- enable = 1 makes both factors of every site's phase
+ * feature volume phases (Sec. III.A, eq. 9): the medium's phase averaged over
+ * the cone under which the site, read as a ball of half the lattice spacing,
+ * is seen from the point (half-angle asin(1 / (2 |o|)) for lattice offset o);
+ * the centre site keeps the point phase.  The cone means are tabulated per
+ * light and phase (2048 bins over the angle between w and the site direction,
+ * per site, linear interpolation).  enable = 0 restores the point phases (the default).
+ * NIS_E_INVALID for other values.
+ */
+int32_t nis_set_volume_phase(nis_ctx *ctx, int32_t medium, int32_t enable);
+
 /* Frees a medium's pyramid and transmittance fields. */
 int32_t nis_unload_medium(nis_ctx *ctx, int32_t medium);
 

@@ -285,20 +285,51 @@ k_features(FeatArgs A)
         };
         const bool one_lobe = mv.nl == 1;
         float phs = 0.f, phm = -INFINITY;
-        for (int t = sub; t < kSites; t += 16) {
-            const float4 e = A.tab->site[t];
-            float P = lobe(0, e);
-            if (!one_lobe) {
-#pragma unroll
-                for (int i = 1; i < kMaxLobes; i++)
-                    if (i < mv.nl) P += lobe(i, e);
-            }
+        auto accum_phase = [&](int t, float P) __attribute__((always_inline)) {
             // log(1 + P) with the hardware logarithm: P >= 0, so 1 + P rounds
             // to within 6e-8 and the absolute error stays near 1e-7
-            float ph = __logf(1.f + P);
+            const float ph = __logf(1.f + P);
             phs += ph;
             phm = fmaxf(phm, ph);
             if (DBG && live) A.dbg_phi[p * kSites + t] = ph;
+        };
+        if (mv.volume == 0) {
+            for (int t = sub; t < kSites; t += 16) {
+                const float4 e = A.tab->site[t];
+                float P = lobe(0, e);
+                if (!one_lobe) {
+#pragma unroll
+                    for (int i = 1; i < kMaxLobes; i++)
+                        if (i < mv.nl) P += lobe(i, e);
+                }
+                accum_phase(t, P);
+            }
+        } else {
+            for (int t = sub; t < kSites; t += 16) {
+                const float4 e = A.tab->site[t];
+                float P;
+                if (t != kCentreSite) {
+                    // volume phase (eq. 9): the site's table of cone means, linear
+                    // in the angle between w and d (2 asin(|w - d|/2), or pi minus
+                    // 2 asin(|w + d|/2) past a right angle: both exact near their
+                    // end), times the incident-side cone mean
+                    const float mu0 = wf[0] * e.x + wf[1] * e.y + wf[2] * e.z;
+                    const float sg = mu0 >= 0.f ? 1.f : -1.f;
+                    const float ex = wf[0] - sg * e.x, ey = wf[1] - sg * e.y, ez = wf[2] - sg * e.z;
+                    const float h = 2.f * asinf(fminf(1.f, 0.5f * sqrtf(ex * ex + ey * ey + ez * ez)));
+                    const float ang = mu0 >= 0.f ? h : (float)M_PI - h;
+                    const float xf = ang * (float)((kVBins - 1) / M_PI);
+                    const int i0 = min((int)xf, kVBins - 2);
+                    const float fr = xf - (float)i0;
+                    const float* row = A.vtab + t * kVBins;
+                    const float v0 = row[i0], v1 = row[i0 + 1];
+                    P = e.w * (v0 + fr * (v1 - v0));
+                } else {
+                    P = lobe(0, e);
+                    for (int i = 1; i < mv.nl; i++) P += lobe(i, e);
+                }
+                accum_phase(t, P);
+            }
         }
         for (int o = 1; o < 16; o <<= 1) {
             phs += __shfl_xor(phs, o);

@@ -304,6 +304,84 @@ __global__ void k_site_tables(MediumView mv, SiteTables* tab)
     tab->site[t] = make_float4((float)(o[0] / on), (float)(o[1] / on), (float)(o[2] / on), (float)ph);
 }
 
+// ---- volume phase (eq. 9) ----------------------------------------------------
+// A site seen from the point is read as a ball of half the lattice spacing,
+// so it subtends a cone of half-angle beta = asin(1 / (2 |o|)) around the
+// site direction d; the volume phase is the medium's phase averaged over the
+// cone.  For a direction v with v . d = mu0, a cone direction at polar angle
+// theta and azimuth psi has v . phi = mu0 cos theta + sqrt(1 - mu0^2) sin theta
+// cos psi, so an HG lobe's denominator is A - B cos psi; its azimuthal
+// integral, of (A - B cos psi)^(-3/2), is 4 E(m) / ((A - B) sqrt(A + B)) with
+// m = 2B / (A + B) (B >= 0), and cos theta over [cos beta, 1] is integrated
+// with 64-point Gauss-Legendre.
+
+// complete elliptic integral of the second kind by the arithmetic-geometric mean
+__device__ double ellip_e(double m)
+{
+    double a = 1.0, b = sqrt(1.0 - m), c = sqrt(m), s = 0.5 * m, p = 0.5;
+    for (int it = 0; it < 40 && c > 1e-17; it++) {
+        const double an = 0.5 * (a + b);
+        c = 0.5 * (a - b);
+        b = sqrt(a * b);
+        a = an;
+        p *= 2.0;
+        s += p * c * c;
+    }
+    return (M_PI / (2.0 * a)) * (1.0 - s);
+}
+
+// the medium's phase averaged over a cone of half-angle beta around d, mu0 = v . d
+__device__ double cone_phase(const MediumView& mv, const GaussLegendre64& gl, double mu0, double beta)
+{
+    const double cb = cos(beta), s0 = sqrt(fmax(0.0, 1.0 - mu0 * mu0));
+    const double half = 0.5 * (1.0 - cb), mid = 0.5 * (1.0 + cb);
+    double total = 0.0;
+    for (int k = 0; k < mv.nl; k++) {
+        const double g2 = 0.5 * mv.hg_b[k];   // g
+        double acc = 0.0;
+        for (int i = 0; i < 64; i++) {
+            const double t = mid + half * gl.x[i];
+            const double A = mv.hg_a[k] - mv.hg_b[k] * mu0 * t;
+            const double B = fabs(2.0 * g2 * s0 * sqrt(fmax(0.0, 1.0 - t * t)));
+            acc += gl.w[i] * half * (4.0 * ellip_e(2.0 * B / (A + B)) / ((A - B) * sqrt(A + B)));
+        }
+        total += mv.hg_k[k] * acc;   // hg_k carries the lobe's weight and (1 - g^2) / (4 pi)
+    }
+    return total / (2.0 * M_PI * (1.0 - cb));
+}
+
+// Volume-phase tables of the current light and phase: block t (a site other
+// than the centre) replaces its site-table entry's incident-side phase by the
+// cone mean at d_t . l, and fills row t of vtab with the cone means at angles
+// pi b / (kVBins - 1), b < kVBins, between w and d_t (uniform in the angle,
+// so that forward and backward lobes are resolved alike).
+__global__ void __launch_bounds__(256) k_volume_tables(MediumView mv, GaussLegendre64 gl, SiteTables* tab, float* vtab)
+{
+    const int t = blockIdx.x;
+    if (t == kCentreSite) return;
+    const int qi = t / 25, j = (t / 5) % 5 - 2, i = t % 5 - 2;
+    double o[3];
+    for (int d = 0; d < 3; d++) o[d] = mv.qoff[d][qi];
+    o[mv.b] += i;
+    o[mv.c] += j;
+    const double on = sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+    const double beta = asin(0.5 / on);
+    for (int b = threadIdx.x; b < kVBins; b += blockDim.x) {
+        vtab[(int64_t)t * kVBins + b] = (float)cone_phase(mv, gl, cos(M_PI * b / (kVBins - 1)), beta);
+    }
+    if (threadIdx.x == 0) {
+        const double dl = (o[0] * mv.l[0] + o[1] * mv.l[1] + o[2] * mv.l[2]) / on;
+        tab->site[t].w = (float)cone_phase(mv, gl, dl, beta);
+    }
+}
+
+hipError_t launch_volume_tables(const MediumView& mv, const GaussLegendre64& gl, SiteTables* tab, float* vtab,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_volume_tables, dim3(kSites), dim3(256), 0, s, mv, gl, tab, vtab);
+    return hipGetLastError();
+}
+
 // Light-axis density pairs (a layout of the pyramid for the gather): for each
 // level, entry (A', c, b), A' = 0..n, b = -kPairPad..n-1+kPairPad, holds the
 // densities at a = A'-1 and a = A' along the light's dominant axis, each

@@ -10,6 +10,7 @@ constexpr int kMaxLinear = 16;
 struct FeatArgs {
     MediumView mv;
     const SiteTables* tab;
+    const float* vtab;           // volume phase only: [kSites][kVBins] w-side cone means over the angle
     const float* pts;
     const float* dirs;
     int64_t npts;
@@ -79,6 +80,12 @@ hipError_t launch_transpose(const MediumView& mv, hipStream_t s);
 hipError_t launch_sweep(const MediumView& mv, hipStream_t s);
 hipError_t launch_pairs(const MediumView& mv, hipStream_t s);
 hipError_t launch_site_tables(const MediumView& mv, SiteTables* tab, hipStream_t s);
+// 64-point Gauss-Legendre rule on [-1, 1] for the volume-phase tables
+struct GaussLegendre64 {
+    double x[64], w[64];
+};
+hipError_t launch_volume_tables(const MediumView& mv, const GaussLegendre64& gl, SiteTables* tab, float* vtab,
+                                hipStream_t s);
 hipError_t launch_features(int prec, const FeatArgs& a, hipStream_t s);
 hipError_t launch_desc_to_f32(int prec, const void* src, float* dst, int64_t n, hipStream_t s);
 hipError_t launch_mlp(int prec, const MlpArgs& a, hipStream_t s);

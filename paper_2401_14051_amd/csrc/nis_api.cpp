@@ -139,6 +139,7 @@ MediumView make_view(const Medium* M, const LightState* ls, const Params& P, con
     v.sigma_t = P.sigma_t;
     v.albedo = P.albedo;
     v.radiance = P.radiance;
+    v.volume = P.volume ? 1 : 0;
     v.lam = net ? net->lam : 0.6f;
     v.gamma = net ? net->gamma : 4.f;
     v.nl = P.phase.n;
@@ -172,16 +173,54 @@ template <class F> void timed(const char* name, hipStream_t s, F&& launch)
     g_prof->recs.push_back({name, a, b});
 }
 
-void refresh_tables(const Medium* M, LightState* ls, const Phase& ph, hipStream_t s)
+// 64-point Gauss-Legendre nodes and weights on [-1, 1]: Newton's method on
+// the Legendre polynomial P_64 from the Chebyshev-like initial guesses
+// cos(pi (i + 3/4) / (n + 1/2)); the weights are 2 / ((1 - x^2) P'_64(x)^2).
+static const GaussLegendre64& gauss_legendre64()
 {
-    if (ls->tab_valid && same_phase(ls->tab_phase, ph)) return;
+    static const GaussLegendre64 gl = [] {
+        GaussLegendre64 r;
+        const int n = 64;
+        for (int i = 0; i < n; i++) {
+            double x = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dpn = 1.0;
+            for (int it = 0; it < 100; it++) {
+                double pm = 1.0, pn = x;
+                for (int k = 2; k <= n; k++) {
+                    const double pk = ((2 * k - 1) * x * pn - (k - 1) * pm) / k;
+                    pm = pn;
+                    pn = pk;
+                }
+                dpn = n * (x * pn - pm) / (x * x - 1.0);
+                const double step = pn / dpn;
+                x -= step;
+                if (std::fabs(step) < 1e-16) break;
+            }
+            r.x[i] = x;
+            r.w[i] = 2.0 / ((1.0 - x * x) * dpn * dpn);
+        }
+        return r;
+    }();
+    return gl;
+}
+
+void refresh_tables(const Medium* M, LightState* ls, const Phase& ph, bool volume, hipStream_t s)
+{
+    if (ls->tab_valid && same_phase(ls->tab_phase, ph) && ls->tab_volume == volume) return;
     ls->tab.reserve(sizeof(SiteTables), "site tables");
     Params P = medium_params(M);
     P.phase = ph;
+    P.volume = volume;
     MediumView mv = make_view(M, ls, P, nullptr);
     timed("site_tables", s, [&] { return launch_site_tables(mv, ls->tab.as<SiteTables>(), s); });
+    if (volume) {
+        ls->vtab.reserve((size_t)kSites * kVBins * sizeof(float), "volume phase tables");
+        timed("volume_tables", s, [&] {
+            return launch_volume_tables(mv, gauss_legendre64(), ls->tab.as<SiteTables>(), ls->vtab.as<float>(), s);
+        });
+    }
     ls->tab_valid = true;
     ls->tab_phase = ph;
+    ls->tab_volume = volume;
 }
 
 void ensure_sweep(const Medium* M, LightState* ls, hipStream_t s)
@@ -409,7 +448,7 @@ Medium* get_medium(nis_ctx* ctx, int32_t id)
     return it->second;
 }
 
-Params medium_params(const Medium* M) { return Params{M->sigma_t, M->albedo, M->phase, M->radiance}; }
+Params medium_params(const Medium* M) { return Params{M->sigma_t, M->albedo, M->phase, M->radiance, M->volume_phase}; }
 
 void light_layout(const Medium* M, const double l[3], LightState* ls)
 {
@@ -483,7 +522,7 @@ void run_query(Workspace& ws, const Net* net, int prec, const Medium* M, LightSt
 {
     if (!net) fail(NIS_E_STATE, "no weights set");
     ensure_sweep(M, ls, s);
-    refresh_tables(M, ls, Pm.phase, s);
+    refresh_tables(M, ls, Pm.phase, Pm.volume, s);
     const PackedNet& P = net->packed[prec];
     const int64_t chunk = n < kChunk ? n : kChunk;
     ws.desc.reserve((size_t)chunk * kDescPad * desc_elem_bytes(prec), "descriptor workspace");
@@ -496,6 +535,7 @@ void run_query(Workspace& ws, const Net* net, int prec, const Medium* M, LightSt
         std::memset(&fa, 0, sizeof(fa));
         fa.mv = mv;
         fa.tab = ls->tab.as<SiteTables>();
+        fa.vtab = Pm.volume ? ls->vtab.as<float>() : nullptr;
         fa.pts = d_pts + 3 * p0;
         fa.dirs = d_dirs + 3 * p0;
         fa.npts = cn;
@@ -799,6 +839,17 @@ int32_t nis_set_medium_params(nis_ctx* ctx, int32_t medium, float sigma_t, float
         M->sigma_t = sigma_t;
         M->albedo = albedo;
         M->phase = single_lobe(g);
+    });
+}
+
+int32_t nis_set_volume_phase(nis_ctx* ctx, int32_t medium, int32_t enable)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        Medium* M = get_medium(ctx, medium);
+        if (enable != 0 && enable != 1) fail(NIS_E_INVALID, "enable must be 0 or 1");
+        M->volume_phase = enable == 1;
     });
 }
 

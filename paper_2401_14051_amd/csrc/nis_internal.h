@@ -33,6 +33,9 @@ constexpr int kPairPad = 8;
 // Phase function of a medium: n HG lobes with weights w summing to one and
 // asymmetries g (Sec. III.A, eq. 6); one lobe of weight 1 is plain HG (eq. 5).
 constexpr int kMaxLobes = 4;
+// Volume phase (eq. 9): bins of the per-site tables over the angle between w and d
+constexpr int kVBins = 2048;
+constexpr int kCentreSite = 112;   // q = j = i = 0
 struct Phase {
     int n;
     float w[kMaxLobes], g[kMaxLobes];
@@ -69,6 +72,7 @@ struct MediumView {
     float sigma_t, albedo, g, radiance;   // g: the phase's mean cosine, sum of w_i g_i
     float lam;          // graded-field coefficient base (eq. 1)
     float gamma;        // decode exponent (eq. 21)
+    int volume;                // phase features from volume phases (eq. 9) rather than point phases
     int nl;                    // phase lobes; per lobe i:
     double hg_a[kMaxLobes], hg_b[kMaxLobes], hg_k[kMaxLobes];   // 1+g^2, 2g, w (1-g^2)/(4 pi)
     float ph_a[kMaxLobes], ph_s[kMaxLobes], ph_c[kMaxLobes], ph_k[kMaxLobes];   // |g|, sign g, (1-|g|)^2, float(hg_k)

@@ -75,18 +75,20 @@ struct LightState {
     int64_t rt_floats = 0;                  // transposed pyramid (x-dominant lights only)
     int64_t pair_count = 0;                 // light-axis density pairs of all levels
     int64_t dpair_count = 0;                // path-density pairs of all levels
-    DevBuf RT, P, DP, tab;
+    DevBuf RT, P, DP, tab, vtab;
     bool stale = true;                      // D, P and DP must be recomputed
     uint64_t swept_version = 0;             // pyramid version they were computed from
     bool tab_valid = false;
     Phase tab_phase = {};                   // phase the site tables were computed for
-    size_t bytes() const { return RT.bytes + P.bytes + DP.bytes + tab.bytes; }
+    bool tab_volume = false;                // ... and whether as volume phases (then vtab too)
+    size_t bytes() const { return RT.bytes + P.bytes + DP.bytes + tab.bytes + vtab.bytes; }
     void release()
     {
         RT.release();
         P.release();
         DP.release();
         tab.release();
+        vtab.release();
         tab_valid = false;
         stale = true;
     }
@@ -96,6 +98,7 @@ struct Medium {
     int n = 0, levels = 0;
     float sigma_t = 0, albedo = 0;
     Phase phase = {1, {1.f}, {0.f}};
+    bool volume_phase = false;              // phase features from volume phases (eq. 9)
     float rmax = 0;                         // largest density of level 0
     Level lev[kMaxLevels] = {};             // n and rho_off of every level
     DevBuf rho;
@@ -110,6 +113,7 @@ struct Params {
     float sigma_t, albedo;
     Phase phase;
     float radiance;
+    bool volume = false;   // volume phases (eq. 9) in the phase features
 };
 
 inline Phase single_lobe(float g) { return Phase{1, {1.f}, {g}}; }

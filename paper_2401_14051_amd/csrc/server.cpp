@@ -298,7 +298,7 @@ Request make_request(nis_ctx* ctx, const nis_frame_req* req)
     const double nrm = std::sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]);
     if (!(nrm > 0.0)) fail(NIS_E_INVALID, "light direction is zero");
     for (int d = 0; d < 3; d++) r.l[d] = l[d] / nrm;
-    r.P = Params{M->sigma_t, M->albedo, single_lobe(req->g), req->radiance};
+    r.P = Params{M->sigma_t, M->albedo, single_lobe(req->g), req->radiance, M->volume_phase};
     return r;
 }
 

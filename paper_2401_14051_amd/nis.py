@@ -75,6 +75,7 @@ _SIGNATURES = {
     "nis_unload_medium": [_vp, _i32],
     "nis_set_light": [_vp, _i32, _vp, ctypes.c_float, _i32],
     "nis_set_phase_lobes": [_vp, _i32, _i32, _vp, _vp],
+    "nis_set_volume_phase": [_vp, _i32, _i32],
     "nis_set_weights": [_vp, _vp, ctypes.c_size_t],
     "nis_set_precision": [_vp, _i32],
     "nis_query": [_vp, _i32, _vp, _vp, _i64, _vp],
@@ -252,6 +253,10 @@ class Context:
         w = np.ascontiguousarray([float(a) for a, _ in lobes], np.float32)
         g = np.ascontiguousarray([float(b) for _, b in lobes], np.float32)
         _check(_lib.nis_set_phase_lobes(self.h, medium, len(w), _ptr(w), _ptr(g)))
+
+    def set_volume_phase(self, medium, enable=True):
+        """Volume phases (eq. 9) in the phase features, or point phases."""
+        _check(_lib.nis_set_volume_phase(self.h, medium, 1 if enable else 0))
 
     def set_light(self, medium, direction, radiance=1.0, eager=False):
         d = np.ascontiguousarray(direction, dtype=np.float32)

@@ -30,8 +30,9 @@ class Scene:
     """A medium loaded both on the GPU and in the oracle, under one light.  g
     is one HG asymmetry or a sequence of (weight, g) lobes."""
 
-    def __init__(self, ctx, density, light, sigma_t=8.0, albedo=0.99, g=0.85, radiance=1.0):
+    def __init__(self, ctx, density, light, sigma_t=8.0, albedo=0.99, g=0.85, radiance=1.0, volume=False):
         self.ctx = ctx
+        self.volume = volume
         self.density = np.ascontiguousarray(density, np.float32)
         self.sigma_t, self.albedo, self.g, self.radiance = sigma_t, albedo, g, radiance
         if np.ndim(g) == 0:
@@ -39,6 +40,8 @@ class Scene:
         else:
             self.mid = ctx.load_medium(self.density, sigma_t, albedo, g[0][1])
             ctx.set_phase_lobes(self.mid, g)
+        if volume:
+            ctx.set_volume_phase(self.mid, True)
         self.ctx.set_light(self.mid, light, radiance)
         self.om = oracle.Medium(self.density)
         self.om.set_light(np.asarray(light, np.float32))
@@ -54,10 +57,10 @@ class Scene:
 
     def oracle_query(self, params, pts, dirs, want_desc=False):
         return self.om.query(oracle_params(params), pts, dirs, f32(self.sigma_t), f32(self.albedo),
-                             self.phase(), f32(self.radiance), want_desc=want_desc)
+                             self.phase(), f32(self.radiance), want_desc=want_desc, volume=self.volume)
 
     def oracle_features(self, params, pts, dirs):
-        return self.om.features(f32(self.sigma_t), self.phase(), f32(params["lam"]), pts, dirs)
+        return self.om.features(f32(self.sigma_t), self.phase(), f32(params["lam"]), pts, dirs, volume=self.volume)
 
 
 def small_points(extra_random=300, seed=5):

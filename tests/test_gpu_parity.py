@@ -197,6 +197,60 @@ def test_multi_lobe_phase_query_and_single_lobe_identity(ctx):
     s.close()
 
 
+# The volume phase (eq. 9) is tabulated per light and phase over the angle
+# between w and each site direction (2048 bins, linear interpolation): the
+# interpolation error, about (h^2/8) max|d2f/dangle2| with h = pi/2047, is
+# largest for the sharpest lobe and the narrowest cone (g = 0.95, the
+# farthest sites); measured maxima of |dphi| are 1.4e-4 (g = 0.95),
+# 3.8e-5 (g = -0.9), 1.9e-5 (g = 0.85), and fall as h^2 with the bin count.
+VOLUME_PHI_ATOL = 3e-4
+
+
+@pytest.mark.parametrize("light,g", [((0.3, 0.9, 0.3), 0.85), ((-0.7, 0.2, 0.4), 0.95),
+                                     ((0.2, 0.3, -0.9), -0.9),
+                                     ((0.1, -0.3, -0.95), [(0.7, 0.8), (0.3, -0.4)])])
+def test_volume_phase_features_match_oracle(ctx, light, g):
+    print("volume phase light=%s g=%s" % (light, g), flush=True)
+    d, pts, dirs = small_points()
+    s = Scene(ctx, d, light, g=g, volume=True)
+    params = weights.he_init(16, 3, seed=1)
+    ctx.set_weights(params)
+    ref = s.oracle_features(params, pts, dirs)
+    got = {k: v.cpu().numpy().astype(np.float64) for k, v in ctx.features(s.mid, dev(pts), dev(dirs)).items()}
+    np.testing.assert_allclose(got["phi"], ref["phi"], rtol=0, atol=VOLUME_PHI_ATOL)
+    np.testing.assert_allclose(got["stats"], ref["stats"], rtol=2e-5, atol=VOLUME_PHI_ATOL)
+    # only the phase features change
+    np.testing.assert_allclose(got["tbar"], ref["tbar"], rtol=2e-5, atol=1e-6)
+    np.testing.assert_allclose(got["f0"], ref["f0"], rtol=2e-5, atol=1e-9)
+    s.close()
+
+
+def test_volume_phase_query_and_switching_back(ctx):
+    """FP32 radiance with volume phases against the oracle; switching the
+    volume phase off again restores the point-phase features bit for bit."""
+    d, pts, dirs = small_points(extra_random=100)
+    s = Scene(ctx, d, (0.2, -0.5, 0.8), g=0.9, volume=True)
+    params = weights.he_init(128, 6, seed=1, bias_scale=0.05)
+    ctx.set_weights(params)
+    ctx.set_precision("fp32")
+    ref = s.oracle_query(params, pts, dirs)
+    L = ctx.query(s.mid, pts, dirs)
+    err = rel_l2(L, ref["L"])
+    print("volume phase FP32 rel-L2 %.3g" % err, flush=True)
+    # the tables' phase-feature error (|dphi| <= 3e-4) passes through the
+    # network into y (measured 8.8e-7 here); the FP32 arithmetic alone stays
+    # near 3e-7
+    assert err <= 1e-5
+    ctx.set_volume_phase(s.mid, False)
+    off = ctx.features(s.mid, dev(pts), dev(dirs))
+    fresh = Scene(ctx, d, (0.2, -0.5, 0.8), g=0.9)
+    plain = ctx.features(fresh.mid, dev(pts), dev(dirs))
+    for k in off:
+        np.testing.assert_array_equal(off[k].cpu().numpy(), plain[k].cpu().numpy())
+    fresh.close()
+    s.close()
+
+
 def test_zero_weights_reduce_to_single_scatter(ctx):
     d, pts, dirs = small_points()
     s = Scene(ctx, d, (0.2, -0.5, 0.8), radiance=2.5)
@@ -280,6 +334,9 @@ def test_invalid_arguments_are_rejected(ctx):
         with pytest.raises(nis.NisError) as e:
             ctx.set_phase_lobes(mid, lobes)
         assert e.value.code == nis.NIS_E_INVALID
+    with pytest.raises(nis.NisError) as e:
+        nis._check(nis._lib.nis_set_volume_phase(ctx.h, mid, 2))   # only 0 and 1
+    assert e.value.code == nis.NIS_E_INVALID
     pts, dirs = camera.random_points(10, seed=1)
     with pytest.raises(nis.NisError) as e:
         ctx.query(mid, pts, dirs)
