@@ -132,6 +132,19 @@ int32_t nis_set_phase_lobes(nis_ctx *ctx, int32_t medium, int32_t n, const float
  */
 int32_t nis_set_volume_phase(nis_ctx *ctx, int32_t medium, int32_t enable);
 
+/*
+ * nis_set_albedo_rgb -- a coloured albedo (Sec. III.C.2: one albedo per red,
+ * green and blue channel, each in [0,1]; eq. 21 decodes channel c with
+ * albedo_c^gamma).  albedo_rgb: host float32[3], copied.  The network runs once
+ * per channel on the shared features with that channel's albedo as its input
+ * entry; nis_query_rgb, nis_query_rgb_device and nis_render_rgb return the
+ * three channels.  While the channels differ, the one-channel calls and the
+ * frame server fail with NIS_E_STATE; three equal values make the medium grey
+ * again, as does nis_set_medium_params.  NIS_E_INVALID for NULL or values out
+ * of range.
+ */
+int32_t nis_set_albedo_rgb(nis_ctx *ctx, int32_t medium, const float *albedo_rgb);
+
 /* Frees a medium's pyramid and transmittance fields. */
 int32_t nis_unload_medium(nis_ctx *ctx, int32_t medium);
 
@@ -177,10 +190,26 @@ int32_t nis_set_precision(nis_ctx *ctx, int32_t precision);
  * `points`: host float32 [n][3] in unit-cube coordinates (may lie outside);
  * `view_dirs`: host float32 [n][3], normalised inside; `radiance_out`: host
  * float32 [n].  Synchronous.  Errors: NIS_E_INVALID (n <= 0, NULL, non-finite
- * input, zero direction), NIS_E_STATE (unknown medium, no light, no weights).
+ * input, zero direction), NIS_E_STATE (unknown medium, no light, no weights, a
+ * coloured albedo).
  */
 int32_t nis_query(nis_ctx *ctx, int32_t medium, const float *points, const float *view_dirs,
                   int64_t n, float *radiance_out);
+
+/*
+ * nis_query_rgb -- as nis_query with one radiance per colour channel:
+ * radiance_out is host float32 [n][3], channel c computed with albedo_c
+ * (nis_set_albedo_rgb; a grey medium gives three copies of nis_query's
+ * result).  The features are computed once and the backbone runs three times.
+ */
+int32_t nis_query_rgb(nis_ctx *ctx, int32_t medium, const float *points, const float *view_dirs,
+                      int64_t n, float *radiance_out);
+
+/* nis_query_rgb_device -- nis_query_rgb on device arrays (d_radiance_out
+ * float32 [n][3]), queued on `hip_stream` as nis_query_device. */
+int32_t nis_query_rgb_device(nis_ctx *ctx, int32_t medium, const float *d_points,
+                             const float *d_view_dirs, int64_t n, float *d_radiance_out,
+                             void *hip_stream);
 
 /*
  * nis_query_device -- as nis_query on device arrays, queued on `hip_stream`
@@ -241,6 +270,15 @@ int32_t nis_frame_points(nis_ctx *ctx, int32_t medium, const nis_camera *camera,
  */
 int32_t nis_render(nis_ctx *ctx, int32_t medium, const nis_camera *camera, uint64_t seed,
                    float *d_image, void *hip_stream);
+
+/*
+ * nis_render_rgb -- nis_render with a coloured albedo: d_image is a device
+ * float32 array [width*height][3], d_image[3 * pixel + c] = albedo_c * L_c at a
+ * collision and 0 elsewhere, L_c the radiance of nis_query_rgb.  The frame
+ * points are the same as nis_render's (they do not depend on the albedo).
+ */
+int32_t nis_render_rgb(nis_ctx *ctx, int32_t medium, const nis_camera *camera, uint64_t seed,
+                       float *d_image, void *hip_stream);
 
 /* ---- frame server -------------------------------------------------------------
  *

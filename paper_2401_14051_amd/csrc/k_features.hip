@@ -852,8 +852,37 @@ k_features(FeatArgs A)
         const int64_t pp = tile0 + tq;
         if (pp < npts) desc[pp * kDescPad + f] = M::cvt(f == kDesc - 1 ? mv.albedo : 0.f);
     }
-    if (A.rowmax && lr == 0 && tile0 + lg < npts)
-        A.rowmax[tile0 + lg] = fmaxf(row_absmax, fabsf((float)M::cvt(mv.albedo)));
+    // the largest |entry| of the features alone: the FP8 backbone adds the
+    // albedo entry, which a colour query rewrites per channel
+    if (A.rowmax && lr == 0 && tile0 + lg < npts) A.rowmax[tile0 + lg] = row_absmax;
+}
+
+// Rewrites the albedo entry of n descriptor rows: the channels of a coloured
+// albedo share every other entry.
+// Rows beyond a device count (count[0] - count_off, when count is given) are
+// left alone, as the backbone does not read them.
+template <int PREC>
+__global__ void k_albedo_entry(void* desc, int64_t n, const int* count, int64_t count_off, float eta)
+{
+    typedef typename Mfma<PREC>::elem E;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nv = count ? (int64_t)*count - count_off : n;
+    if (i < n && i < nv) reinterpret_cast<E*>(desc)[i * kDescPad + kDesc - 1] = Mfma<PREC>::cvt(eta);
+}
+
+hipError_t launch_albedo_entry(int prec, void* desc, int64_t n, const int* count, int64_t count_off, float eta,
+                               hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (prec == kPrecBF16 || prec == kPrecFP8)
+        hipLaunchKernelGGL(k_albedo_entry<kPrecBF16>, dim3((int)blocks), dim3(256), 0, s, desc, n, count, count_off,
+                           eta);
+    else
+        hipLaunchKernelGGL(k_albedo_entry<kPrecFP32>, dim3((int)blocks), dim3(256), 0, s, desc, n, count, count_off,
+                           eta);
+    return hipGetLastError();
 }
 
 // Widen a descriptor of the given precision to float32 [n][1057].

@@ -152,6 +152,19 @@ k_scatter_image(const int* __restrict__ cpix, const float* __restrict__ L, const
     if (i < *count) image[cpix[i]] = scale * L[i];
 }
 
+__global__ void __launch_bounds__(256)
+k_scatter_image_rgb(const int* __restrict__ cpix, const float* __restrict__ L, const int* __restrict__ count,
+                    float s0, float s1, float s2, float* __restrict__ image)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < *count) {
+        const int64_t o = (int64_t)cpix[i] * 3;
+        image[o] = s0 * L[3 * i];
+        image[o + 1] = s1 * L[3 * i + 1];
+        image[o + 2] = s2 * L[3 * i + 2];
+    }
+}
+
 hipError_t frame_scan_bytes(int64_t npix, size_t* bytes)
 {
     *bytes = 0;
@@ -182,6 +195,16 @@ hipError_t launch_image(const FrameBuffers& fb, int64_t npix, const float* L, fl
     const int blocks = (int)((npix + 255) / 256);
     hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, image, npix, 0.f);
     hipLaunchKernelGGL(k_scatter_image, dim3(blocks), dim3(256), 0, s, fb.cpix, L, fb.count, scale, image);
+    return hipGetLastError();
+}
+
+hipError_t launch_image_rgb(const FrameBuffers& fb, int64_t npix, const float* L, const float scale[3],
+                            float* image, hipStream_t s)
+{
+    const int64_t nf = 3 * npix;
+    hipLaunchKernelGGL(k_fill, dim3((int)((nf + 255) / 256)), dim3(256), 0, s, image, nf, 0.f);
+    hipLaunchKernelGGL(k_scatter_image_rgb, dim3((int)((npix + 255) / 256)), dim3(256), 0, s, fb.cpix, L, fb.count,
+                       scale[0], scale[1], scale[2], image);
     return hipGetLastError();
 }
 

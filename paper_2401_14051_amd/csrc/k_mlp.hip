@@ -110,7 +110,7 @@ k_mlp(MlpArgs A)
         for (int k = 0; k < W; k++) y += (float)h[rr][k] * A.wout[k];
         if (row < npts) {
             if (A.y_out) A.y_out[row] = y;
-            if (A.out) A.out[row] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
+            if (A.out) A.out[row * A.out_stride] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
         }
     }
 }
@@ -513,7 +513,7 @@ k_mlp_bf16(MlpArgs A)
         if (lg == 0 && row < npts) {
             const float y = A.bout + s;
             if (A.y_out) A.y_out[row] = y;
-            if (A.out) A.out[row] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
+            if (A.out) A.out[row * A.out_stride] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
         }
     }
 }
@@ -566,7 +566,7 @@ k_mlp_fp8(MlpArgs A)
         int64_t r = row0 + rt * 16 + lr;
         r = r < npts ? r : npts - 1;
         xr[rt] = x + r * kDescPad + lg * M::KPL;
-        const float m = A.rowmax[r];
+        const float m = fmaxf(A.rowmax[r], A.eta_max);
         qs[rt] = m > 0.f ? kTarget / m : 1.f;
         if (lg == 0) rs[rt * 16 + lr] = m > 0.f ? m / kTarget : 1.f;
     }
@@ -693,7 +693,7 @@ k_mlp_fp8(MlpArgs A)
         y = A.bout + y * rs[rr];
         if (row < npts) {
             if (A.y_out) A.y_out[row] = y;
-            if (A.out) A.out[row] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
+            if (A.out) A.out[row * A.out_stride] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
         }
     }
 }

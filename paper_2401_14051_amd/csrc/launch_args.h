@@ -25,7 +25,7 @@ struct FeatArgs {
     float* dbg_phi;              // optional [npts][225]
     float* dbg_stats;            // optional [npts][12][8]
     float* dbg_tp;               // optional [npts]
-    float* rowmax;               // optional [npts]: max |entry| of each stored descriptor row
+    float* rowmax;               // optional [npts]: max |entry| of each stored descriptor row but its albedo entry
     const int* count;            // optional device point count: the kernel serves
     int64_t count_off;           // min(npts, *count - count_off) points
 };
@@ -36,12 +36,14 @@ struct MlpArgs {
     const void* W[kMaxLinear];       // layer i: [wpad][kin_pad] (kin_pad = kDescPad for i = 0)
     const float* bias[kMaxLinear];   // [wpad], zero padded
     const float* wscale[kMaxLinear]; // FP8 only: per-output-column weight scale [wpad]
-    const float* rowmax;             // FP8 only: max |x| of each descriptor row [npts]
+    const float* rowmax;             // FP8 only: max |x| of each descriptor row but its albedo entry [npts]
+    float eta_max;                   // FP8 only: |albedo entry| as stored (BF16)
     const float* wout;               // [wpad] last-layer weights (float32)
     float bout;
     int n_linear, wpad;
     const float* f0;                 // [npts]
-    float* out;                      // [npts] radiance (may be NULL)
+    float* out;                      // radiance of row r at out[r * out_stride] (may be NULL)
+    int64_t out_stride;              // 1, or 3 for one channel of an RGB result
     float* y_out;                    // [npts] network output (may be NULL)
     float albedo_gamma;              // albedo^gamma
     float radiance;
@@ -89,12 +91,17 @@ hipError_t launch_volume_tables(const MediumView& mv, const GaussLegendre64& gl,
 hipError_t launch_features(int prec, const FeatArgs& a, hipStream_t s);
 hipError_t launch_desc_to_f32(int prec, const void* src, float* dst, int64_t n, hipStream_t s);
 hipError_t launch_mlp(int prec, const MlpArgs& a, hipStream_t s);
+hipError_t launch_albedo_entry(int prec, void* desc, int64_t n, const int* count, int64_t count_off, float eta,
+                               hipStream_t s);
 int mlp_padded_width(int width);
 hipError_t frame_scan_bytes(int64_t npix, size_t* bytes);
 hipError_t launch_raygen(const CamArgs& C, const float* rho0, int n, double sigma_t, double majorant,
                          uint64_t seed, const FrameBuffers& fb, hipStream_t s);
 hipError_t launch_image(const FrameBuffers& fb, int64_t npix, const float* L, float scale, float* image,
                         hipStream_t s);
+// RGB image [npix][3] from RGB radiance [count][3], channel c scaled by scale[c].
+hipError_t launch_image_rgb(const FrameBuffers& fb, int64_t npix, const float* L, const float scale[3],
+                            float* image, hipStream_t s);
 int mlp_hidden_k(int prec, int wpad);
 int mlp_k_step(int prec);       // K per MFMA instruction
 int mlp_k_per_lane(int prec);   // K elements a lane holds in one B fragment

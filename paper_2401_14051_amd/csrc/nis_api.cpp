@@ -450,6 +450,23 @@ Medium* get_medium(nis_ctx* ctx, int32_t id)
 
 Params medium_params(const Medium* M) { return Params{M->sigma_t, M->albedo, M->phase, M->radiance, M->volume_phase}; }
 
+// Parameters of a one-channel result: the albedo must be grey.
+Params grey_params(const Medium* M)
+{
+    if (!grey_albedo(M)) fail(NIS_E_STATE, "the medium has a coloured albedo: use the RGB calls");
+    return medium_params(M);
+}
+
+// Parameters of an RGB result; channel 0's albedo goes into the features.
+Params rgb_params(const Medium* M)
+{
+    Params P = medium_params(M);
+    P.channels = 3;
+    for (int c = 0; c < 3; c++) P.rgb[c] = M->albedo_rgb[c];
+    P.albedo = P.rgb[0];
+    return P;
+}
+
 void light_layout(const Medium* M, const double l[3], LightState* ls)
 {
     for (int d = 0; d < 3; d++) ls->l[d] = l[d];
@@ -516,11 +533,24 @@ size_t workspace_bytes(int prec, int64_t npts)
     return (size_t)chunk * kDescPad * desc_elem_bytes(prec) + (size_t)chunk * 4 * (prec == kPrecFP8 ? 2 : 1);
 }
 
+// |x| rounded to nearest even BF16, as a BF16 descriptor stores it.
+float bf16_abs(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u &= 0x7fffffffu;
+    u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+    float r;
+    std::memcpy(&r, &u, 4);
+    return r;
+}
+
 void run_query(Workspace& ws, const Net* net, int prec, const Medium* M, LightState* ls, const Params& Pm,
                const float* d_pts, const float* d_dirs, int64_t n, const int* d_count, const QueryOut& o,
                hipStream_t s)
 {
     if (!net) fail(NIS_E_STATE, "no weights set");
+    if (Pm.channels != 1 && (Pm.channels != 3 || o.y || o.desc)) fail(NIS_E_INVALID, "bad channel count");
     ensure_sweep(M, ls, s);
     refresh_tables(M, ls, Pm.phase, Pm.volume, s);
     const PackedNet& P = net->packed[prec];
@@ -583,11 +613,21 @@ void run_query(Workspace& ws, const Net* net, int prec, const Medium* M, LightSt
         ma.n_linear = net->n_linear;
         ma.wpad = net->wpad;
         ma.f0 = fa.f0;
-        ma.out = o.radiance ? o.radiance + p0 : nullptr;
-        ma.y_out = o.y ? o.y + p0 : nullptr;
-        ma.albedo_gamma = (float)std::pow((double)Pm.albedo, (double)net->gamma);
         ma.radiance = Pm.radiance;
-        timed("backbone", s, [&] { return launch_mlp(prec, ma, s); });
+        ma.out_stride = Pm.channels;
+        // colour channels share the features; each rewrites the albedo entry
+        // (the features stored channel 0's) and runs the backbone
+        for (int c = 0; c < Pm.channels; c++) {
+            const float eta = Pm.channels == 3 ? Pm.rgb[c] : Pm.albedo;
+            if (c > 0)
+                timed("albedo_entry", s,
+                      [&] { return launch_albedo_entry(prec, ws.desc.p, cn, d_count, p0, eta, s); });
+            ma.out = o.radiance ? o.radiance + p0 * Pm.channels + c : nullptr;
+            ma.y_out = o.y && c == 0 ? o.y + p0 : nullptr;
+            ma.albedo_gamma = (float)std::pow((double)eta, (double)net->gamma);
+            ma.eta_max = bf16_abs(eta);
+            timed("backbone", s, [&] { return launch_mlp(prec, ma, s); });
+        }
     }
 }
 
@@ -638,12 +678,12 @@ FrameBuffers FrameWork::view() const
 size_t FrameWork::bytes() const
 {
     return flag.bytes + offset.bytes + pts.bytes + dirs.bytes + cpts.bytes + cdirs.bytes + cpix.bytes + L.bytes +
-           count.bytes + scan.bytes;
+           count.bytes + scan.bytes + L3.bytes;
 }
 
 void FrameWork::release()
 {
-    for (DevBuf* b : {&flag, &offset, &pts, &dirs, &cpts, &cdirs, &cpix, &count, &scan, &L}) b->release();
+    for (DevBuf* b : {&flag, &offset, &pts, &dirs, &cpts, &cdirs, &cpix, &count, &scan, &L, &L3}) b->release();
     npix = 0;
 }
 
@@ -713,8 +753,49 @@ void render_frame(Workspace& ws, FrameWork& fw, const Net* net, int prec, const 
     FrameBuffers fb = fw.view();
     QueryOut o;
     o.radiance = fw.L.as<float>();
+    if (P.channels == 3) {
+        fw.L3.reserve((size_t)fw.npix * 3 * sizeof(float), "frame radiance");
+        o.radiance = fw.L3.as<float>();
+    }
     run_query(ws, net, prec, M, ls, P, fb.cpts, fb.cdirs, npix, fb.count, o, s);
-    timed("image", s, [&] { return launch_image(fb, npix, fw.L.as<float>(), P.albedo, d_image, s); });
+    if (P.channels == 3)
+        timed("image", s, [&] { return launch_image_rgb(fb, npix, fw.L3.as<float>(), P.rgb, d_image, s); });
+    else
+        timed("image", s, [&] { return launch_image(fb, npix, fw.L.as<float>(), P.albedo, d_image, s); });
+}
+
+// Synchronous query of host arrays: channels = 1 (grey) or 3 (RGB, [n][3] out).
+void query_host(nis_ctx* ctx, int32_t medium, const float* points, const float* dirs, int64_t n, float* out,
+                int channels)
+{
+    check_ctx(ctx);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!points || !dirs || !out || n <= 0) fail(NIS_E_INVALID, "bad query arguments");
+    for (int64_t i = 0; i < n; i++) {
+        if (!finite3(points + 3 * i) || !finite3(dirs + 3 * i)) fail(NIS_E_INVALID, "non-finite query input");
+        const float* d = dirs + 3 * i;
+        if (d[0] == 0.f && d[1] == 0.f && d[2] == 0.f) fail(NIS_E_INVALID, "zero view direction");
+    }
+    Medium* M = get_medium(ctx, medium);
+    const Params P = channels == 3 ? rgb_params(M) : grey_params(M);
+    if (!ctx->net) fail(NIS_E_STATE, "no weights set");
+    if (!M->light.valid) fail(NIS_E_STATE, "no light set for this medium");
+    const size_t bytes = (size_t)n * (6 + channels) * sizeof(float);
+    StreamUse su(ctx, ctx->stream);
+    ctx->io.reserve(bytes, "query staging");
+    float* d_pts = ctx->io.as<float>();
+    float* d_dirs = d_pts + 3 * n;
+    float* d_out = d_dirs + 3 * n;
+    hip_check(hipMemcpyAsync(d_pts, points, (size_t)n * 3 * sizeof(float), hipMemcpyHostToDevice, ctx->stream),
+              "upload");
+    hip_check(hipMemcpyAsync(d_dirs, dirs, (size_t)n * 3 * sizeof(float), hipMemcpyHostToDevice, ctx->stream),
+              "upload");
+    QueryOut o;
+    o.radiance = d_out;
+    run_query(ctx->ws, ctx->net, ctx->precision, M, &M->light, P, d_pts, d_dirs, n, nullptr, o, ctx->stream);
+    hip_check(hipMemcpyAsync(out, d_out, (size_t)n * channels * sizeof(float), hipMemcpyDeviceToHost, ctx->stream),
+              "download");
+    hip_check(hipStreamSynchronize(ctx->stream), "query");
 }
 
 }  // namespace nis
@@ -787,6 +868,7 @@ int32_t nis_load_medium(nis_ctx* ctx, const float* density, int32_t n, float sig
             M->n = n;
             M->sigma_t = sigma_t;
             M->albedo = albedo;
+            for (int c = 0; c < 3; c++) M->albedo_rgb[c] = albedo;
             M->phase = single_lobe(g);
             M->rmax = rmax;
             int L = 1;
@@ -838,7 +920,23 @@ int32_t nis_set_medium_params(nis_ctx* ctx, int32_t medium, float sigma_t, float
         validate_params(sigma_t, albedo, g);
         M->sigma_t = sigma_t;
         M->albedo = albedo;
+        for (int c = 0; c < 3; c++) M->albedo_rgb[c] = albedo;
         M->phase = single_lobe(g);
+    });
+}
+
+int32_t nis_set_albedo_rgb(nis_ctx* ctx, int32_t medium, const float* albedo_rgb)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        Medium* M = get_medium(ctx, medium);
+        if (!albedo_rgb) fail(NIS_E_INVALID, "albedo_rgb is NULL");
+        for (int c = 0; c < 3; c++)
+            if (!(std::isfinite(albedo_rgb[c]) && albedo_rgb[c] >= 0.f && albedo_rgb[c] <= 1.f))
+                fail(NIS_E_INVALID, "albedo must be in [0,1]");
+        for (int c = 0; c < 3; c++) M->albedo_rgb[c] = albedo_rgb[c];
+        if (grey_albedo(M)) M->albedo = albedo_rgb[0];
     });
 }
 
@@ -994,7 +1092,7 @@ int32_t nis_query_device(nis_ctx* ctx, int32_t medium, const float* d_points, co
         hipStream_t s = su.s;
         QueryOut o;
         o.radiance = d_out;
-        run_query(ctx->ws, ctx->net, ctx->precision, M, &M->light, medium_params(M), d_points, d_dirs, n, nullptr,
+        run_query(ctx->ws, ctx->net, ctx->precision, M, &M->light, grey_params(M), d_points, d_dirs, n, nullptr,
                   o, s);
     });
 }
@@ -1002,35 +1100,28 @@ int32_t nis_query_device(nis_ctx* ctx, int32_t medium, const float* d_points, co
 int32_t nis_query(nis_ctx* ctx, int32_t medium, const float* points, const float* dirs, int64_t n,
                   float* radiance_out)
 {
+    return guard([&] { query_host(ctx, medium, points, dirs, n, radiance_out, 1); });
+}
+
+int32_t nis_query_rgb(nis_ctx* ctx, int32_t medium, const float* points, const float* dirs, int64_t n,
+                      float* radiance_out)
+{
+    return guard([&] { query_host(ctx, medium, points, dirs, n, radiance_out, 3); });
+}
+
+int32_t nis_query_rgb_device(nis_ctx* ctx, int32_t medium, const float* d_points, const float* d_dirs, int64_t n,
+                             float* d_out, void* hip_stream)
+{
     return guard([&] {
         check_ctx(ctx);
         std::lock_guard<std::mutex> lk(ctx->mu);
-        if (!points || !dirs || !radiance_out || n <= 0) fail(NIS_E_INVALID, "bad query arguments");
-        for (int64_t i = 0; i < n; i++) {
-            if (!finite3(points + 3 * i) || !finite3(dirs + 3 * i)) fail(NIS_E_INVALID, "non-finite query input");
-            const float* d = dirs + 3 * i;
-            if (d[0] == 0.f && d[1] == 0.f && d[2] == 0.f) fail(NIS_E_INVALID, "zero view direction");
-        }
+        if (!d_points || !d_dirs || !d_out || n <= 0) fail(NIS_E_INVALID, "bad query arguments");
         Medium* M = get_medium(ctx, medium);
-        if (!ctx->net) fail(NIS_E_STATE, "no weights set");
-        if (!M->light.valid) fail(NIS_E_STATE, "no light set for this medium");
-        const size_t bytes = (size_t)n * 7 * sizeof(float);
-        StreamUse su(ctx, ctx->stream);
-        ctx->io.reserve(bytes, "query staging");
-        float* d_pts = ctx->io.as<float>();
-        float* d_dirs = d_pts + 3 * n;
-        float* d_out = d_dirs + 3 * n;
-        hip_check(hipMemcpyAsync(d_pts, points, (size_t)n * 3 * sizeof(float), hipMemcpyHostToDevice, ctx->stream),
-                  "upload");
-        hip_check(hipMemcpyAsync(d_dirs, dirs, (size_t)n * 3 * sizeof(float), hipMemcpyHostToDevice, ctx->stream),
-                  "upload");
+        StreamUse su(ctx, (hipStream_t)hip_stream);
         QueryOut o;
         o.radiance = d_out;
-        run_query(ctx->ws, ctx->net, ctx->precision, M, &M->light, medium_params(M), d_pts, d_dirs, n, nullptr, o,
-                  ctx->stream);
-        hip_check(hipMemcpyAsync(radiance_out, d_out, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, ctx->stream),
-                  "download");
-        hip_check(hipStreamSynchronize(ctx->stream), "query");
+        run_query(ctx->ws, ctx->net, ctx->precision, M, &M->light, rgb_params(M), d_points, d_dirs, n, nullptr, o,
+                  su.s);
     });
 }
 
@@ -1060,8 +1151,23 @@ int32_t nis_render(nis_ctx* ctx, int32_t medium, const nis_camera* camera, uint6
         CamArgs C = camera_args(camera);
         StreamUse su(ctx, (hipStream_t)hip_stream);
         hipStream_t s = su.s;
-        render_frame(ctx->ws, ctx->fw, ctx->net, ctx->precision, M, &M->light, medium_params(M), C, seed, d_image,
+        render_frame(ctx->ws, ctx->fw, ctx->net, ctx->precision, M, &M->light, grey_params(M), C, seed, d_image,
                      s);
+    });
+}
+
+int32_t nis_render_rgb(nis_ctx* ctx, int32_t medium, const nis_camera* camera, uint64_t seed, float* d_image,
+                       void* hip_stream)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (!d_image) fail(NIS_E_INVALID, "image is NULL");
+        Medium* M = get_medium(ctx, medium);
+        CamArgs C = camera_args(camera);
+        StreamUse su(ctx, (hipStream_t)hip_stream);
+        render_frame(ctx->ws, ctx->fw, ctx->net, ctx->precision, M, &M->light, rgb_params(M), C, seed, d_image,
+                     su.s);
     });
 }
 
@@ -1204,7 +1310,7 @@ int32_t nis_debug_features(nis_ctx* ctx, int32_t medium, const float* d_points, 
         o.tp = d_tp;
         o.f0 = d_f0;
         o.run_mlp = false;
-        run_query(ctx->ws, ctx->net, ctx->precision, M, &M->light, medium_params(M), d_points, d_dirs, n, nullptr, o,
+        run_query(ctx->ws, ctx->net, ctx->precision, M, &M->light, grey_params(M), d_points, d_dirs, n, nullptr, o,
                   ctx->stream);
         hip_check(hipStreamSynchronize(ctx->stream), "features");
     });
@@ -1228,7 +1334,7 @@ int32_t nis_debug_network(nis_ctx* ctx, int32_t medium, const float* d_points, c
             o.desc = raw.p;
         }
         try {
-            run_query(ctx->ws, ctx->net, prec, M, &M->light, medium_params(M), d_points, d_dirs, n, nullptr, o,
+            run_query(ctx->ws, ctx->net, prec, M, &M->light, grey_params(M), d_points, d_dirs, n, nullptr, o,
                       ctx->stream);
             if (d_desc) hip_check(launch_desc_to_f32(prec, raw.p, d_desc, n, ctx->stream), "descriptor convert");
             hip_check(hipStreamSynchronize(ctx->stream), "network");

@@ -97,6 +97,7 @@ struct LightState {
 struct Medium {
     int n = 0, levels = 0;
     float sigma_t = 0, albedo = 0;
+    float albedo_rgb[3] = {0, 0, 0};        // per colour channel; all three equal albedo for a grey medium
     Phase phase = {1, {1.f}, {0.f}};
     bool volume_phase = false;              // phase features from volume phases (eq. 9)
     float rmax = 0;                         // largest density of level 0
@@ -114,7 +115,14 @@ struct Params {
     Phase phase;
     float radiance;
     bool volume = false;   // volume phases (eq. 9) in the phase features
+    int channels = 1;      // 3: one radiance per colour channel, albedo rgb[c]
+    float rgb[3] = {0, 0, 0};
 };
+
+inline bool grey_albedo(const Medium* M)
+{
+    return M->albedo_rgb[0] == M->albedo_rgb[1] && M->albedo_rgb[1] == M->albedo_rgb[2];
+}
 
 inline Phase single_lobe(float g) { return Phase{1, {1.f}, {g}}; }
 inline bool same_phase(const Phase& a, const Phase& b)
@@ -185,6 +193,7 @@ struct Workspace {
 // Per-pixel buffers of one frame on one stream.
 struct FrameWork {
     DevBuf flag, offset, pts, dirs, cpts, cdirs, cpix, count, scan, L;
+    DevBuf L3;   // RGB radiance of the collisions, reserved by the first RGB frame
     int64_t npix = 0;
     void reserve(int64_t npix);
     FrameBuffers view() const;

@@ -287,6 +287,7 @@ Request make_request(nis_ctx* ctx, const nis_frame_req* req)
 {
     if (!req) fail(NIS_E_INVALID, "req is NULL");
     Medium* M = get_medium(ctx, req->medium);
+    if (!grey_albedo(M)) fail(NIS_E_STATE, "the frame server renders grey media only");
     Request r;
     r.req = *req;
     r.C = camera_args(&req->camera);

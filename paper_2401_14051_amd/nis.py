@@ -76,10 +76,13 @@ _SIGNATURES = {
     "nis_set_light": [_vp, _i32, _vp, ctypes.c_float, _i32],
     "nis_set_phase_lobes": [_vp, _i32, _i32, _vp, _vp],
     "nis_set_volume_phase": [_vp, _i32, _i32],
+    "nis_set_albedo_rgb": [_vp, _i32, _vp],
     "nis_set_weights": [_vp, _vp, ctypes.c_size_t],
     "nis_set_precision": [_vp, _i32],
     "nis_query": [_vp, _i32, _vp, _vp, _i64, _vp],
     "nis_query_device": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
+    "nis_query_rgb": [_vp, _i32, _vp, _vp, _i64, _vp],
+    "nis_query_rgb_device": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
     "nis_medium_info": [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i64)],
     "nis_debug_pyramid": [_vp, _i32, _vp, _i64],
     "nis_debug_path_density": [_vp, _i32, _i32, _vp, _i64, ctypes.POINTER(_i32)],
@@ -88,6 +91,7 @@ _SIGNATURES = {
     "nis_debug_network": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
     "nis_frame_points": [_vp, _i32, ctypes.POINTER(nis_camera), _u64, _vp, _vp, _vp, _vp, _vp],
     "nis_render": [_vp, _i32, ctypes.POINTER(nis_camera), _u64, _vp, _vp],
+    "nis_render_rgb": [_vp, _i32, ctypes.POINTER(nis_camera), _u64, _vp, _vp],
     "nis_server_start": [_vp, ctypes.POINTER(nis_server_cfg)],
     "nis_submit_frame": [_vp, ctypes.POINTER(nis_frame_req), ctypes.POINTER(_u64)],
     "nis_poll": [_vp, _u64, ctypes.POINTER(nis_frame_result)],
@@ -258,6 +262,11 @@ class Context:
         """Volume phases (eq. 9) in the phase features, or point phases."""
         _check(_lib.nis_set_volume_phase(self.h, medium, 1 if enable else 0))
 
+    def set_albedo_rgb(self, medium, albedo_rgb):
+        """One albedo per colour channel (red, green, blue), each in [0,1]."""
+        a = np.ascontiguousarray(albedo_rgb, dtype=np.float32).reshape(3)
+        _check(_lib.nis_set_albedo_rgb(self.h, medium, _ptr(a)))
+
     def set_light(self, medium, direction, radiance=1.0, eager=False):
         d = np.ascontiguousarray(direction, dtype=np.float32)
         _check(_lib.nis_set_light(self.h, medium, _ptr(d), radiance, NIS_EAGER if eager else 0))
@@ -290,6 +299,22 @@ class Context:
         _check(_lib.nis_query_device(self.h, medium, _dptr(points), _dptr(dirs), points.shape[0],
                                      _dptr(out), _vp(stream)))
 
+    def query_rgb(self, medium, points, dirs):
+        """As query, one radiance per colour channel: host [n, 3]."""
+        p = np.ascontiguousarray(points, dtype=np.float32)
+        d = np.ascontiguousarray(dirs, dtype=np.float32)
+        out = np.empty((p.shape[0], 3), np.float32)
+        _check(_lib.nis_query_rgb(self.h, medium, _ptr(p), _ptr(d), p.shape[0], _ptr(out)))
+        return out
+
+    def query_rgb_device(self, medium, points, dirs, out, stream=None):
+        """As query_device with ``out`` a device tensor [n, 3]."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(points.device).cuda_stream
+        _check(_lib.nis_query_rgb_device(self.h, medium, _dptr(points), _dptr(dirs), points.shape[0],
+                                         _dptr(out), _vp(stream)))
+
     def frame_points(self, medium, cam, seed, stream=None):
         """Collisions of a frame as torch device tensors (points [P,3], dirs [P,3],
         pixel [P]); synchronises ``stream`` to read P."""
@@ -316,6 +341,17 @@ class Context:
         if stream is None:
             stream = torch.cuda.current_stream(dev).cuda_stream
         _check(_lib.nis_render(self.h, medium, ctypes.byref(cam), seed, _dptr(out), _vp(stream)))
+        return out
+
+    def render_rgb(self, medium, cam, seed, out=None, stream=None):
+        """An RGB frame image (torch float32 [height, width, 3]) queued on ``stream``."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        if out is None:
+            out = torch.empty(cam.height, cam.width, 3, dtype=torch.float32, device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev).cuda_stream
+        _check(_lib.nis_render_rgb(self.h, medium, ctypes.byref(cam), seed, _dptr(out), _vp(stream)))
         return out
 
     # -- frame server --
