@@ -3,8 +3,9 @@
 Kernel timings:
     python -m paper_2401_14051_amd.rocprof_summary times DB [--title T --command C] > out.md
 
-HBM traffic of a kernel from two counter runs (FETCH_SIZE, then WRITE_SIZE),
-scaled by what the same counters read for a plain copy kernel of known size:
+HBM traffic of a kernel's largest launches from two counter runs (FETCH_SIZE,
+then WRITE_SIZE), scaled by what the same counters read for a plain copy
+kernel of known size:
     python -m paper_2401_14051_amd.rocprof_summary traffic --fetch DB1 --write DB2 \\
         --kernel k_features --copy-kernel elementwise --copy-bytes B > out.json
 
@@ -39,19 +40,23 @@ def source_hash(kernel):
 
 
 def kernel_times(db):
+    """Rows (name, workgroups, calls, avg, min, max, total duration in ns), one
+    per kernel and launch size, so that launches of one kernel over different
+    batch sizes are not averaged together."""
     con = sqlite3.connect(db)
-    rows = con.execute("select name, count(*), avg(duration), min(duration), max(duration), sum(duration) "
-                       "from kernels group by name order by sum(duration) desc").fetchall()
+    rows = con.execute("select name, (grid_x * grid_y * grid_z) / (workgroup_x * workgroup_y * workgroup_z), "
+                       "count(*), avg(duration), min(duration), max(duration), sum(duration) from kernels "
+                       "group by name, grid_x, grid_y, grid_z order by sum(duration) desc").fetchall()
     return rows
 
 
 def counters(db, counter):
-    """{kernel name: [value per dispatch]} of one counter."""
+    """{kernel name: {grid size in work-items: [value per dispatch]}} of one counter."""
     con = sqlite3.connect(db)
-    out = collections.defaultdict(list)
-    for name, val in con.execute("select kernel_name, value from counters_collection where counter_name = ? "
-                                 "order by dispatch_id", (counter,)):
-        out[name].append(val)
+    out = collections.defaultdict(lambda: collections.defaultdict(list))
+    for name, grid, val in con.execute("select kernel_name, grid_size, value from counters_collection "
+                                       "where counter_name = ? order by dispatch_id", (counter,)):
+        out[name][grid].append(val)
     return out
 
 
@@ -64,30 +69,36 @@ def pick(d, key):
 
 def cmd_times(a):
     rows = kernel_times(a.db)
-    total = sum(r[5] for r in rows)
+    total = sum(r[6] for r in rows)
     print("# %s\n" % (a.title or "Kernel times"))
     if a.command:
         print("Command:\n\n```\n%s\n```\n" % a.command)
-    print("| kernel | calls | avg (us) | min (us) | max (us) | total (us) | share |")
-    print("|---|---|---|---|---|---|---|")
-    for name, n, avg, mn, mx, tot in rows:
-        print("| `%s` | %d | %.1f | %.1f | %.1f | %.1f | %.1f%% |" % (name[:80], n, avg / 1e3, mn / 1e3, mx / 1e3,
-                                                                     tot / 1e3, 100.0 * tot / total))
+    print("One row per kernel and launch size (workgroups).\n")
+    print("| kernel | workgroups | calls | avg (us) | min (us) | max (us) | total (us) | share |")
+    print("|---|---|---|---|---|---|---|---|")
+    for name, wgs, n, avg, mn, mx, tot in rows:
+        print("| `%s` | %d | %d | %.1f | %.1f | %.1f | %.1f | %.1f%% |" % (name[:80], wgs, n, avg / 1e3, mn / 1e3,
+                                                                          mx / 1e3, tot / 1e3, 100.0 * tot / total))
 
 
 def cmd_traffic(a):
     fetch = counters(a.fetch, "FETCH_SIZE")
     write = counters(a.write, "WRITE_SIZE")
-    cf = pick(fetch, a.copy_kernel)
-    cw = pick(write, a.copy_kernel)
-    kf = pick(fetch, a.kernel)
-    kw = pick(write, a.kernel)
+    cf = [v for g in pick(fetch, a.copy_kernel).values() for v in g]
+    cw = [v for g in pick(write, a.copy_kernel).values() for v in g]
+    # the kernel's largest launches: those of a whole frame
+    kfg, kwg = pick(fetch, a.kernel), pick(write, a.kernel)
+    grid = max(kfg)
+    if grid not in kwg:
+        raise SystemExit("launch size %d missing from the WRITE_SIZE run" % grid)
+    kf, kw = kfg[grid], kwg[grid]
     # counters are in KiB per dispatch; the copy kernel moves copy_bytes each way
     f_scale = a.copy_bytes / (1024.0 * max(cf))
     w_scale = a.copy_bytes / (1024.0 * max(cw))
     fetch_b = 1024.0 * sum(kf) / len(kf) * f_scale
     write_b = 1024.0 * sum(kw) / len(kw) * w_scale
-    out = {"kernel": a.name, "source_hash": source_hash(a.name), "fetch_bytes_per_launch": fetch_b,
+    out = {"kernel": a.name, "source_hash": source_hash(a.name), "grid_work_items": grid,
+           "fetch_bytes_per_launch": fetch_b,
            "write_bytes_per_launch": write_b, "traffic_bytes_per_launch": fetch_b + write_b,
            "copy_calibration": {"kernel": a.copy_kernel, "bytes": a.copy_bytes,
                                 "fetch_kib": max(cf), "write_kib": max(cw),
