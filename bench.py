@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 VALU_FP32_TFLOPS = 78.6   # 256 CUs x 64 lanes x 2 FLOP x 2.4 GHz, without packed FP32
+G_SWEEP = (0.0, 0.5, 0.85, 0.95)   # HG asymmetries of the precision workload
 
 # Algorithmic FP32 vector work of the gather per shading point: 12 layers x 225
 # sites, each two trilinear interpolations (7 lerps of 2 FLOP), one exponent
@@ -334,6 +335,25 @@ def main():
     miss[pix] = False
     misses_zero = bool(np.all(img.cpu().numpy()[miss] == 0.0))
 
+    # radiance rel-L2 per precision over the HG asymmetries of the precision
+    # workload, at the same sampled collisions (device query, medium g changed
+    # in place; the light fields do not depend on g)
+    errs_g = {}
+    sl = torch.empty(len(sidx), dtype=torch.float32, device="cuda")
+    for g in G_SWEEP:
+        ctx.set_medium_params(mid, wl.sigma_t, wl.albedo, g)
+        rg = om.query(op, pts[sidx], dirs[sidx], f32(wl.sigma_t), f32(wl.albedo), f32(g), f32(wl.radiance))["L"]
+        errs_g[str(g)] = {}
+        for prec in precs:
+            ctx.set_precision(prec)
+            ctx.query_device(mid, sp, sd, sl)
+            torch.cuda.synchronize()
+            got = sl.cpu().numpy().astype(np.float64)
+            errs_g[str(g)][prec] = float(np.linalg.norm(got - rg) / np.linalg.norm(rg))
+        log("g = %s: rel-L2 %s" % (g, ", ".join("%s %.2e" % kv for kv in errs_g[str(g)].items())))
+    ctx.set_medium_params(mid, wl.sigma_t, wl.albedo, wl.g)
+    ctx.set_precision(args.precision)
+
     # oracle throughput on the host cores (bounded sample)
     cpu = None
     if args.cpu_sample > 0:
@@ -417,6 +437,7 @@ def main():
         "fps": 1000.0 / ms,
         "rel_l2_vs_fp64_oracle": {p: errs[p] for p in precs},
         "rel_l2_F_vs_fp64_oracle": {p: errs_f[p] for p in precs},
+        "rel_l2_vs_fp64_oracle_by_g": errs_g,
         "frame_ms": {p: {"median": float(np.median(per_frame[p])), "p99": float(np.percentile(per_frame[p], 99))}
                      for p in precs},
         "fps_modes": fps_modes,

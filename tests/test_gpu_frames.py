@@ -295,3 +295,42 @@ def test_server_state_errors(ctx):
     finally:
         ctx.server_stop()
     ctx.unload_medium(m)
+
+
+# ---- the large workload -----------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def large_scene(ctx):
+    """The large workload (512^3, 4K) loaded on both sides, and the generator's
+    collisions of 4096 seeded pixels of its frame."""
+    w = configs.LARGE
+    d = w.density()
+    s = Scene(ctx, d, w.light, w.sigma_t, w.albedo, w.g, w.radiance)
+    o, dirs = w.rays()
+    pick = np.sort(np.random.default_rng(13).choice(o.shape[0], 4096, replace=False))
+    rp, rd, rpix = camera.delta_track(d, w.sigma_t, o[pick], dirs[pick], seed=w.point_seed, pixels=pick)
+    yield s, pick, rp, rd, rpix
+    s.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 1e-2)])
+def test_render_4k_large_sampled(ctx, large_scene, prec, tol):
+    """The large workload's 4K frame of the 512^3 cloud, checked against the
+    oracle at the hits among 4096 sampled pixels; the sampled misses are
+    exactly zero."""
+    print("render 4K large %s" % prec, flush=True)
+    nis = nis_mod()
+    w = configs.LARGE
+    s, pick, rp, rd, rpix = large_scene
+    params = w.params()
+    ctx.set_weights(params)
+    ctx.set_precision(prec)
+    img = ctx.render(s.mid, nis.camera(3840, 2160, 45.0, eye=w.eye), w.point_seed).cpu().numpy().ravel()
+    ctx.set_precision("fp32")
+    miss = np.setdiff1d(pick, rpix)
+    assert np.all(img[miss] == 0.0)
+    assert rpix.size > 1000
+    L = s.oracle_query(params, rp, rd)["L"]
+    err = rel_l2(img[rpix], f32(w.albedo) * L)
+    print("render 4K large %s rel-L2 %.3e over %d hits" % (prec, err, rpix.size), flush=True)
+    assert err <= tol

@@ -144,6 +144,28 @@ def test_query_small_workload(ctx, prec, tol):
     s.close()
 
 
+@pytest.mark.parametrize("g", [0.0, 0.5, 0.95])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 1e-2), ("fp8", 0.1)])
+def test_query_small_workload_g_sweep(ctx, g, prec, tol):
+    """The small workload at the other HG asymmetries of the precision
+    workload (0.85 is the test above): FP32 and BF16 within their targets, FP8
+    within the bound it achieves."""
+    w = configs.SMALL
+    d = w.density()
+    pts, dirs, _ = w.points(d)
+    s = Scene(ctx, d, w.light, w.sigma_t, w.albedo, g, w.radiance)
+    params = w.params()
+    ctx.set_weights(params)
+    ctx.set_precision(prec)
+    ref = s.oracle_query(params, pts, dirs)
+    L = ctx.query(s.mid, pts, dirs)
+    ctx.set_precision("fp32")
+    err = rel_l2(L, ref["L"])
+    print("g=%s %s small: rel-L2(L) %.3g" % (g, prec, err), flush=True)
+    assert err <= tol
+    s.close()
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
 @pytest.mark.parametrize("width", [16, 24, 100, 200, 256])
 def test_backbone_widths(ctx, width, prec):

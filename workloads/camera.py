@@ -63,12 +63,15 @@ def _box_interval(o, d):
     return np.maximum(tmin, 0.0), tmax
 
 
-def delta_track(density, sigma_t, origins, dirs, seed=0, max_steps=100000):
+def delta_track(density, sigma_t, origins, dirs, seed=0, max_steps=100000, pixels=None):
     """First real collision of each ray by delta tracking.
 
     Returns (points float32 [P,3], dirs float32 [P,3], pixel int64 [P]) for
-    the rays that collide inside the box, in pixel order.
+    the rays that collide inside the box, in pixel order.  ``pixels`` (sorted
+    int64, one per ray) tracks a subset of a frame's rays: the random numbers
+    and the returned indices are those of these pixels.
     """
+    ids = np.arange(origins.shape[0], dtype=np.int64) if pixels is None else np.asarray(pixels, np.int64)
     n = density.shape[0]
     rmax = float(density.max())
     npx = origins.shape[0]
@@ -82,8 +85,8 @@ def delta_track(density, sigma_t, origins, dirs, seed=0, max_steps=100000):
     t = t_in[alive].copy()
     step = 0
     while alive.size and step < max_steps:
-        u_fly = rng.uniform(seed, alive, 2 * step)
-        u_acc = rng.uniform(seed, alive, 2 * step + 1)
+        u_fly = rng.uniform(seed, ids[alive], 2 * step)
+        u_acc = rng.uniform(seed, ids[alive], 2 * step + 1)
         t = t - np.log1p(-u_fly) / majorant
         inside = t < t_out[alive]
         x = origins[alive] + t[:, None] * dirs[alive]
@@ -94,9 +97,9 @@ def delta_track(density, sigma_t, origins, dirs, seed=0, max_steps=100000):
         keep = inside & ~accept
         alive, t = alive[keep], t[keep]
         step += 1
-    pix = np.nonzero(~np.isnan(hit_t))[0]
-    pts = origins[pix] + hit_t[pix, None] * dirs[pix]
-    return pts.astype(np.float32), dirs[pix].astype(np.float32), pix
+    hit = np.nonzero(~np.isnan(hit_t))[0]
+    pts = origins[hit] + hit_t[hit, None] * dirs[hit]
+    return pts.astype(np.float32), dirs[hit].astype(np.float32), ids[hit]
 
 
 def random_points(count, seed, lo=0.0, hi=1.0):
