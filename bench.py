@@ -67,7 +67,9 @@ def log(msg):
 
 
 def kernel_work(wl, levels, level_geom, npix, npts, width, n_linear, prec):
-    """Algorithmic bytes / FLOPs per launch of each kernel."""
+    """Algorithmic bytes / FLOPs of each kernel per frame (one launch per frame
+    for the frame workload; the large one runs the features and backbone in
+    passes of at most 2^21 points)."""
     esize = {"fp32": 4, "bf16": 2, "fp8": 2}[prec]     # the FP8 path stores the descriptor in BF16
     n0 = wl.n
     vox = [(n0 >> m) ** 3 for m in range(levels)]
@@ -243,13 +245,16 @@ def main():
     for prec in precs:
         ms, wall, per_frame[prec] = run(prec, args.steps, args.warmup)
         ctx.profile(True)
-        for _ in range(max(3, min(args.steps, 10))):
+        nprof = max(3, min(args.steps, 10))
+        for _ in range(nprof):
             step()
         torch.cuda.synchronize()
         rep = ctx.profile_report()
         ctx.profile(False)
-        res[prec] = {"ms": ms, "wall_s": wall, "kernels": {k: v[1] / v[0] for k, v in rep.items()},
-                     "launches": {k: v[0] for k, v in rep.items()}}
+        # time per frame of each kernel (a frame of more points than one pass
+        # holds launches the features and backbone kernels once per pass)
+        res[prec] = {"ms": ms, "wall_s": wall, "kernels": {k: v[1] / nprof for k, v in rep.items()},
+                     "launches_per_frame": {k: v[0] / nprof for k, v in rep.items()}}
         log("%s: %.3f ms/frame, kernels %s" % (prec, ms, {k: round(v, 4) for k, v in res[prec]["kernels"].items()}))
 
     # the headline precision's fps three ways: the light changed every frame

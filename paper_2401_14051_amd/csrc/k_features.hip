@@ -375,7 +375,7 @@ k_features(FeatArgs A)
 
 
     // conv1 A fragments of the current weight group (reloaded when it changes)
-    constexpr int KC1 = 72 / M::KS + (72 % M::KS != 0);
+    constexpr int KC1 = PREC == kPrecFP32 ? 18 : 3;
     typename M::frag aw[KC1];
     float row_absmax = 0.f;   // lane (point, o): max |stored entry| of its point so far
     for (int k = 0; k < kLayers; k++) {
@@ -705,24 +705,27 @@ k_features(FeatArgs A)
         }
 
         // ---- conv1, two points per MFMA tile: out^T [16 x 16 positions] =
-        // [W1 on K 0..35 | W1 on K 36..71] . [im2col of point tp0 ; of tp0 + 1]
-        // (rows 0-7: tp0's 8 channels, rows 8-15: tp0 + 1's), the bias as the
-        // C operand of the first K step
+        // W1 (tp0's rows 0-7 and tp0 + 1's rows 8-15, each zero on the other's
+        // K slots) . [im2col of tp0 and tp0 + 1 on their K slots], the bias as
+        // the C operand of the first K step
         {
             f32x4 bias;
 #pragma unroll
             for (int e = 0; e < 4; e++) bias[e] = cbl[(lg & 1) * 4 + e];
             // BF16: lane group lg reads the 4-slot groups g = kc*8 + 2lg + h of K
-            // step kc; group g < 9 is tap-row g of tp0, 9 <= g < 18 tap-row g - 9
-            // of tp0 + 1.  Groups g >= 18 meet zero weights: they read any lattice
-            // entry (all finite), which keeps every read unconditional.
-            int goff[3][2];
+            // step kc: g < 8 is tap-row g of tp0, 8 <= g < 16 tap-row g - 8 of
+            // tp0 + 1, g = 16 tap-row 8 of tp0 and g = 17 tap-row 8 of tp0 + 1,
+            // so that both points group their products alike.  Groups g >= 18
+            // meet zero weights: they read any lattice entry (all finite), which
+            // keeps every read unconditional.
+            int goff[KC1 < 3 ? KC1 : 3][2];
 #pragma unroll
-            for (int kc = 0; kc < 3; kc++)
+            for (int kc = 0; kc < (KC1 < 3 ? KC1 : 3); kc++)
 #pragma unroll
                 for (int h = 0; h < 2; h++) {
                     const int g = kc * 8 + 2 * (ln >> 4) + h;
-                    goff[kc][h] = g < 18 ? (g >= 9 ? kLatStride : 0) + taprow_off(g % 9) : 0;
+                    goff[kc][h] = g < 16 ? (g >= 8 ? kLatStride : 0) + taprow_off(g % 8)
+                                : g == 16 ? taprow_off(8) : g == 17 ? kLatStride + taprow_off(8) : 0;
                 }
 #pragma unroll 1
             for (int tp0 = 0; tp0 < kTP; tp0 += 2)

@@ -77,13 +77,27 @@ __device__ __forceinline__ void camera_ray(const CamArgs& C, int px, int py, dou
     for (int a = 0; a < 3; a++) d[a] /= nrm;
 }
 
+// Pixel of ray slot s.  In bands of B rows (the last band may be lower) the
+// slots walk each band column by column, so that consecutive collisions, and
+// the shading points that run side by side on a compute unit, form compact
+// patches of the image rather than strips of one row.
+__device__ __forceinline__ int64_t slot_pixel(int64_t s, int w, int h, int band)
+{
+    if (band <= 1) return s;
+    const int64_t full = (int64_t)band * w;
+    const int64_t b = s / full, r = s - b * full;
+    const int64_t hb = (int64_t)h - b * band < band ? (int64_t)h - b * band : band;
+    return (b * band + r % hb) * w + r / hb;
+}
+
 __global__ void __launch_bounds__(256)
 k_raygen(CamArgs C, const float* __restrict__ rho, int n, double sigma_t, double majorant, uint64_t seed,
          int* __restrict__ flag, float* __restrict__ pts, float* __restrict__ dirs)
 {
 #pragma clang fp contract(off)
-    const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= (int64_t)C.width * C.height) return;
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= (int64_t)C.width * C.height) return;
+    const int64_t pix = slot_pixel(slot, C.width, C.height, C.band);
     const int px = (int)(pix % C.width), py = (int)(pix / C.width);
     double o[3], d[3];
     camera_ray(C, px, py, o, d);
@@ -110,26 +124,26 @@ k_raygen(CamArgs C, const float* __restrict__ rho, int n, double sigma_t, double
             }
         }
     }
-    flag[pix] = hit;
+    flag[slot] = hit;
     for (int a = 0; a < 3; a++) {
-        pts[3 * pix + a] = hit ? (float)(o[a] + t * d[a]) : 0.f;
-        dirs[3 * pix + a] = (float)d[a];
+        pts[3 * slot + a] = hit ? (float)(o[a] + t * d[a]) : 0.f;
+        dirs[3 * slot + a] = (float)d[a];
     }
 }
 
 __global__ void __launch_bounds__(256)
 k_compact(const int* __restrict__ flag, const int* __restrict__ offset, const float* __restrict__ pts,
-          const float* __restrict__ dirs, int64_t npix, float* __restrict__ cpts, float* __restrict__ cdirs,
-          int* __restrict__ cpix)
+          const float* __restrict__ dirs, int w, int h, int band, float* __restrict__ cpts,
+          float* __restrict__ cdirs, int* __restrict__ cpix)
 {
-    const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= npix || !flag[pix]) return;
-    const int64_t o = offset[pix];
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= (int64_t)w * h || !flag[slot]) return;
+    const int64_t o = offset[slot];
     for (int a = 0; a < 3; a++) {
-        cpts[3 * o + a] = pts[3 * pix + a];
-        cdirs[3 * o + a] = dirs[3 * pix + a];
+        cpts[3 * o + a] = pts[3 * slot + a];
+        cdirs[3 * o + a] = dirs[3 * slot + a];
     }
-    cpix[o] = (int)pix;
+    cpix[o] = (int)slot_pixel(slot, w, h, band);
 }
 
 __global__ void k_count(const int* __restrict__ flag, const int* __restrict__ offset, int64_t npix,
@@ -183,8 +197,8 @@ hipError_t launch_raygen(const CamArgs& C, const float* rho0, int n, double sigm
     size_t bytes = fb.scan_bytes;
     e = hipcub::DeviceScan::ExclusiveSum(fb.scan_tmp, bytes, fb.flag, fb.offset, (int)npix, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(256), 0, s, fb.flag, fb.offset, fb.pts, fb.dirs, npix,
-                       fb.cpts, fb.cdirs, fb.cpix);
+    hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(256), 0, s, fb.flag, fb.offset, fb.pts, fb.dirs, C.width,
+                       C.height, C.band, fb.cpts, fb.cdirs, fb.cpix);
     hipLaunchKernelGGL(k_count, dim3(1), dim3(64), 0, s, fb.flag, fb.offset, npix, fb.count);
     return hipGetLastError();
 }

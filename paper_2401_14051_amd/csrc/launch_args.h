@@ -59,6 +59,7 @@ constexpr int kMaxTrackingSteps = 100000;   // free flights per camera ray befor
 struct CamArgs {
     int ortho;
     int width, height;
+    int band;   // order of the ray slots: 0 pixel order; B > 1 bands of B rows, each walked column by column
     double oz, aspect, tan_half;
     double eye[3], f[3], r[3], u[3];
 };

@@ -309,15 +309,26 @@ void pack_net(Net* net, int prec)
         const float *w1 = G, *b1 = w1 + 216, *w2 = b1 + 8, *b2 = w2 + 3456;
         const float *s1 = b2 + 16, *c1 = s1 + 64, *s2 = c1 + 4, *c2 = s2 + 64;
         std::vector<float> t1(16 * kConv1K, 0.f), t2(16 * kConv2K, 0.f);
+        // One MFMA tile convolves two points: rows 0-7 are the first point's
+        // channels, rows 8-15 the second's, each with zero weights on the other
+        // point's K slots.  A tap-row (dz * 3 + dy) takes 4 slots, dx and a zero.
+        // FP32 (K step 4): the first point's tap-row tr at K 4 tr, the second's
+        // at 36 + 4 tr.  BF16 (K step 32): tap-rows 0-7 of the first point fill
+        // step 0 and those of the second step 1; tap-row 8 takes slots 0-3 of
+        // step 2 (first point) and slots 4-7 (second).  Both points then sum
+        // their products with the same grouping, the other point's steps
+        // adding exact zeros, so that a point's result does not depend on its
+        // place in the batch (the tests compare frames rendered in two point
+        // orders bit for bit).
+        auto k1 = [&](int second, int tr) {
+            if (prec == kPrecFP32) return 36 * second + 4 * tr;
+            return tr < 8 ? 32 * second + 4 * tr : 64 + 4 * second;
+        };
         for (int o = 0; o < 8; o++)
-            // K index = tap-row (dz * 3 + dy) * 4 + dx; the fourth slot of each
-            // tap-row is zero.  Rows 8-15 repeat rows 0-7 shifted to K 36..71, so
-            // one MFMA tile convolves two points (the kernel puts the second
-            // point's im2col on K 36..71); K >= 72 is zero.
             for (int tr = 0; tr < 9; tr++)
                 for (int dx = 0; dx < 3; dx++) {
-                    t1[o * kConv1K + tr * 4 + dx] = w1[o * 27 + tr * 3 + dx];
-                    t1[(o + 8) * kConv1K + 36 + tr * 4 + dx] = w1[o * 27 + tr * 3 + dx];
+                    t1[o * kConv1K + k1(0, tr) + dx] = w1[o * 27 + tr * 3 + dx];
+                    t1[(o + 8) * kConv1K + k1(1, tr) + dx] = w1[o * 27 + tr * 3 + dx];
                 }
         // conv2 K order is tap-major (k = tap * 8 + input channel), matching the
         // channels-fastest layout of the conv1 output the kernel reads
@@ -749,7 +760,11 @@ void render_frame(Workspace& ws, FrameWork& fw, const Net* net, int prec, const 
     if (!net) fail(NIS_E_STATE, "no weights set");
     if (!ls->valid) fail(NIS_E_STATE, "no light set for this medium");
     const int64_t npix = (int64_t)C.width * C.height;
-    frame_points(fw, M, P, C, seed, nullptr, nullptr, nullptr, nullptr, s);
+    // collisions in bands of rows: the result of a point does not depend on
+    // its place in the batch, and compact patches share more of their bricks
+    CamArgs Cb = C;
+    Cb.band = kRenderBand;
+    frame_points(fw, M, P, Cb, seed, nullptr, nullptr, nullptr, nullptr, s);
     FrameBuffers fb = fw.view();
     QueryOut o;
     o.radiance = fw.L.as<float>();

@@ -177,6 +177,7 @@ extern thread_local Profiler* g_prof;   // profiler of the context this thread i
 // ---- workspaces ------------------------------------------------------------------
 
 constexpr int64_t kChunk = 1 << 21;   // points per feature/backbone pass
+constexpr int kRenderBand = 8;         // rows per band of a rendered frame's collision order
 
 // Descriptor, single-scatter and row-maximum scratch of one stream.
 struct Workspace {

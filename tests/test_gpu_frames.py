@@ -164,6 +164,33 @@ def test_render_1080p_sampled(ctx, frame_density, prec, tol):
     ctx.set_precision("fp32")
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_render_equals_query_of_frame_points(ctx, prec):
+    """A rendered frame walks its collisions in bands of rows, which changes
+    only their order: its image equals, bit for bit, the query of the
+    pixel-ordered collisions of nis_frame_points scattered to their pixels
+    (a camera whose last band of rows is partial)."""
+    print("render vs frame points %s" % prec, flush=True)
+    nis = nis_mod()
+    d = medium.fbm_cloud(32, seed=5)
+    mid = ctx.load_medium(d, 8.0, 0.9, 0.7)
+    ctx.set_light(mid, (0.3, 0.9, 0.3), 1.0)
+    ctx.set_weights(weights.he_init(64, 4, seed=3, bias_scale=0.05))
+    ctx.set_precision(prec)
+    cam = nis.camera(101, 43, 40.0, eye=(1.6, 0.7, 1.2))
+    img = ctx.render(mid, cam, 7).cpu().numpy().ravel()
+    pts, dirs, pix = ctx.frame_points(mid, cam, 7)
+    L = torch.empty(pts.shape[0], dtype=torch.float32, device="cuda")
+    ctx.query_device(mid, pts.contiguous(), dirs.contiguous(), L)
+    torch.cuda.synchronize()
+    ctx.set_precision("fp32")
+    ref = np.zeros(101 * 43, np.float32)
+    ref[pix.cpu().numpy()] = np.float32(0.9) * L.cpu().numpy()
+    assert pts.shape[0] > 500
+    np.testing.assert_array_equal(img, ref)
+    ctx.unload_medium(mid)
+
+
 # ---- frame server ---------------------------------------------------------------
 
 def _requests(m32, m64):
