@@ -138,10 +138,11 @@ int32_t nis_set_volume_phase(nis_ctx *ctx, int32_t medium, int32_t enable);
  * albedo_c^gamma).  albedo_rgb: host float32[3], copied.  The network runs once
  * per channel on the shared features with that channel's albedo as its input
  * entry; nis_query_rgb, nis_query_rgb_device and nis_render_rgb return the
- * three channels.  While the channels differ, the one-channel calls and the
- * frame server fail with NIS_E_STATE; three equal values make the medium grey
- * again, as does nis_set_medium_params.  NIS_E_INVALID for NULL or values out
- * of range.
+ * three channels, and the frame server renders the medium's frames in RGB
+ * (nis_frame_result.channels = 3; the albedo is read at submission).  While the
+ * channels differ, the one-channel calls fail with NIS_E_STATE; three equal
+ * values make the medium grey again, as does nis_set_medium_params.
+ * NIS_E_INVALID for NULL or values out of range.
  */
 int32_t nis_set_albedo_rgb(nis_ctx *ctx, int32_t medium, const float *albedo_rgb);
 
@@ -314,8 +315,9 @@ typedef struct nis_frame_req {
 typedef struct nis_frame_result {
     int32_t status;             /* NIS_QUEUED, NIS_RUNNING, NIS_OK (done) or a negative error */
     int32_t width, height;
+    int32_t channels;           /* 1, or 3 for a medium with a coloured albedo (nis_set_albedo_rgb) */
     int64_t n_points;           /* collisions shaded (valid when done) */
-    const float *d_image;       /* device [height][width] float32, valid until nis_release */
+    const float *d_image;       /* device [height][width][channels] float32, valid until nis_release */
     double t_submit, t_start, t_done;   /* seconds since nis_server_start (host steady clock):
                                            submitted, admitted, completion observed */
 } nis_frame_result;

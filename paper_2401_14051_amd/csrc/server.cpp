@@ -86,7 +86,10 @@ struct Server {
 
 namespace {
 
-size_t image_bytes(const CamArgs& C) { return (size_t)C.width * C.height * sizeof(float); }
+size_t image_bytes(const Request& r)
+{
+    return (size_t)r.C.width * r.C.height * r.P.channels * sizeof(float);
+}
 
 // Device memory a slot must hold to run the request (workspace, frame buffers
 // and light fields).
@@ -94,7 +97,7 @@ void slot_need(int prec, const Medium* M, const Request& r, size_t* ws, size_t* 
 {
     const int64_t npix = (int64_t)r.C.width * r.C.height;
     *ws = workspace_bytes(prec, npix);
-    *fw = frame_work_bytes(npix);
+    *fw = frame_work_bytes(npix) + (r.P.channels == 3 ? (size_t)npix * 3 * sizeof(float) : 0);
     LightState tmp;
     light_layout(M, r.l, &tmp);
     *ls = (size_t)tmp.rt_floats * sizeof(float) + (size_t)(tmp.pair_count + tmp.dpair_count) * sizeof(float2) +
@@ -160,7 +163,7 @@ void launch(nis_ctx* ctx, Server* S, int k, uint64_t id)
         set_light_state(M, r.l, &s.ls);
         s.medium = r.req.medium;
     }
-    const size_t ib = image_bytes(r.C);
+    const size_t ib = image_bytes(r);
     // the smallest spare image that fits, else a new one
     int best = -1;
     for (size_t i = 0; i < S->spare_images.size(); i++)
@@ -207,7 +210,7 @@ void admit(nis_ctx* ctx, Server* S)
             }
         }
         if (k < 0) return;
-        size_t ib = image_bytes(r.C), img_growth = ib;
+        size_t ib = image_bytes(r), img_growth = ib;
         for (const DevBuf& d : S->spare_images)
             if (d.bytes >= ib) img_growth = 0;
         size_t need = slot_growth(S, S->slots[k], M, r) + img_growth;
@@ -268,6 +271,7 @@ void fill_result(const Request& r, nis_frame_result* out)
     out->status = r.status;
     out->width = r.C.width;
     out->height = r.C.height;
+    out->channels = r.P.channels;
     out->n_points = r.n_points;
     out->d_image = r.status == NIS_OK ? r.image.as<float>() : nullptr;
     out->t_submit = r.t_submit;
@@ -287,7 +291,6 @@ Request make_request(nis_ctx* ctx, const nis_frame_req* req)
 {
     if (!req) fail(NIS_E_INVALID, "req is NULL");
     Medium* M = get_medium(ctx, req->medium);
-    if (!grey_albedo(M)) fail(NIS_E_STATE, "the frame server renders grey media only");
     Request r;
     r.req = *req;
     r.C = camera_args(&req->camera);
@@ -300,6 +303,12 @@ Request make_request(nis_ctx* ctx, const nis_frame_req* req)
     if (!(nrm > 0.0)) fail(NIS_E_INVALID, "light direction is zero");
     for (int d = 0; d < 3; d++) r.l[d] = l[d] / nrm;
     r.P = Params{M->sigma_t, M->albedo, single_lobe(req->g), req->radiance, M->volume_phase};
+    if (!grey_albedo(M)) {
+        // a coloured medium renders an RGB frame (one backbone pass per channel)
+        r.P.channels = 3;
+        for (int c = 0; c < 3; c++) r.P.rgb[c] = M->albedo_rgb[c];
+        r.P.albedo = r.P.rgb[0];
+    }
     return r;
 }
 
@@ -308,7 +317,7 @@ size_t frame_need(int prec, const Medium* M, const Request& r)
 {
     size_t ws, fw, ls;
     slot_need(prec, M, r, &ws, &fw, &ls);
-    return ws + fw + ls + image_bytes(r.C);
+    return ws + fw + ls + image_bytes(r);
 }
 
 void free_server(Server* S)

@@ -58,7 +58,7 @@ class nis_frame_req(ctypes.Structure):
 
 class nis_frame_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
-                ("n_points", ctypes.c_int64), ("d_image", ctypes.c_void_p),
+                ("channels", ctypes.c_int32), ("n_points", ctypes.c_int64), ("d_image", ctypes.c_void_p),
                 ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
                 ("t_done", ctypes.c_double)]
 
@@ -395,11 +395,12 @@ class Context:
         return r
 
     def frame_image(self, result):
-        """Copy of a finished frame's image as a torch tensor."""
+        """Copy of a finished frame's image as a torch tensor ([height, width],
+        or [height, width, 3] for a medium with a coloured albedo)."""
         import torch
-        n = result.width * result.height
-        out = torch.empty(result.height, result.width, dtype=torch.float32,
-                          device=torch.device("cuda", self.device))
+        n = result.width * result.height * result.channels
+        shape = (result.height, result.width) + ((3,) if result.channels == 3 else ())
+        out = torch.empty(*shape, dtype=torch.float32, device=torch.device("cuda", self.device))
         if n:
             torch.cuda.synchronize(out.device)
             _memcpy_d2d(out.data_ptr(), result.d_image, n * 4)

@@ -126,6 +126,8 @@ def test_rgb_render_small_workload(ctx):
 
 
 def test_rgb_invalid_arguments(ctx):
+    """Albedos out of range are refused; the one-channel calls refuse a
+    coloured medium."""
     print("rgb invalid arguments", flush=True)
     nis = nis_mod()
     d, pts, dirs = small_points(extra_random=10)
@@ -140,13 +142,47 @@ def test_rgb_invalid_arguments(ctx):
     with pytest.raises(nis.NisError) as e:
         ctx.render(s.mid, cam, 0)
     assert e.value.code == nis.NIS_E_STATE
-    ctx.server_start(1 << 30, "fp32")
-    try:
-        with pytest.raises(nis.NisError) as e:
-            ctx.submit(s.mid, cam, (0.2, -0.5, 0.8))
-        assert e.value.code == nis.NIS_E_STATE
-    finally:
-        ctx.server_stop()
-    # the RGB calls work on it, and the frame points do not depend on the albedo
+    # the RGB calls work on it
     assert ctx.query_rgb(s.mid, pts, dirs).shape == (pts.shape[0], 3)
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_server_renders_coloured_media_in_rgb(ctx, prec):
+    """Frames of a coloured medium through the frame server, in a mix with
+    grey frames: each equals the synchronous render (RGB or grey) bit for bit."""
+    print("server rgb %s" % prec, flush=True)
+    nis = nis_mod()
+    from workloads import medium
+    ctx.set_weights(weights.he_init(64, 4, seed=4, bias_scale=0.05))
+    ctx.set_precision(prec)
+    grey = ctx.load_medium(medium.fbm_cloud(32, seed=1), 8.0, 0.9, 0.8)
+    col = ctx.load_medium(medium.fbm_cloud(32, seed=2), 8.0, 0.9, 0.8)
+    ctx.set_albedo_rgb(col, RGB)
+    cams = [nis.camera(96, 40, 40.0, eye=(1.6, 0.7, 1.2)), nis.camera(64, 64, 35.0, eye=(0.4, 1.8, 0.9))]
+    reqs = [(col, cams[0], (0.3, 0.9, 0.3), 0.85, 1), (grey, cams[1], (-0.5, 0.4, 0.7), 0.6, 2),
+            (col, cams[1], (0.2, -0.6, 0.7), 0.3, 3), (grey, cams[0], (0.3, 0.9, 0.3), 0.9, 4)]
+    ctx.server_start(1 << 32, prec, max_inflight=3)
+    try:
+        fids = [ctx.submit(m, cam, l, g=g, seed=sd) for m, cam, l, g, sd in reqs]
+        imgs = []
+        for fid in fids:
+            r = ctx.wait(fid)
+            imgs.append((r.channels, ctx.frame_image(r).cpu().numpy()))
+            ctx.release(fid)
+    finally:
+        ctx.server_stop()
+    for (m, cam, l, g, sd), (ch, img) in zip(reqs, imgs):
+        ctx.set_light(m, l, 1.0)
+        ctx.set_medium_params(m, 8.0, 0.9, g)
+        if m == col:
+            ctx.set_albedo_rgb(m, RGB)
+            ref = ctx.render_rgb(m, cam, sd).cpu().numpy()
+            assert ch == 3 and img.shape == (cam.height, cam.width, 3)
+        else:
+            ref = ctx.render(m, cam, sd).cpu().numpy()
+            assert ch == 1 and img.shape == (cam.height, cam.width)
+        np.testing.assert_array_equal(img, ref)
+    ctx.unload_medium(grey)
+    ctx.unload_medium(col)
+    ctx.set_precision("fp32")
