@@ -9,6 +9,10 @@ kernel of known size:
     python -m paper_2401_14051_amd.rocprof_summary traffic --fetch DB1 --write DB2 \\
         --kernel k_features --copy-kernel elementwise --copy-bytes B > out.json
 
+Per-dispatch (and per-wave) averages of other counters of a kernel's largest
+launches:
+    python -m paper_2401_14051_amd.rocprof_summary counters DB1 DB2 --kernel k_features > out.md
+
 The traffic summary records a hash of the kernel's source files, so that the
 benchmark reports it only while the kernel is unchanged.
 """
@@ -108,6 +112,33 @@ def cmd_traffic(a):
     print()
 
 
+def cmd_counters(a):
+    """Per-dispatch averages of every counter in the given runs for the
+    kernel's largest launches, and per wave where SQ_WAVES was counted."""
+    vals = {}
+    for db in a.db:
+        con = sqlite3.connect(db)
+        names = [r[0] for r in con.execute("select distinct counter_name from counters_collection")]
+        for c in names:
+            per = collections.defaultdict(lambda: collections.defaultdict(list))
+            for name, grid, val in con.execute("select kernel_name, grid_size, value from counters_collection "
+                                               "where counter_name = ?", (c,)):
+                per[name][grid].append(val)
+            g = pick(per, a.kernel)
+            top = max(g)
+            vals[c] = (top, sum(g[top]) / len(g[top]), len(g[top]))
+    print("# %s\n" % (a.title or "Counters"))
+    for cmd in a.command:
+        print("```\n%s\n```\n" % cmd)
+    waves = vals.get("SQ_WAVES", (0, 0.0, 0))[1]
+    print("| counter | launch work-items | dispatches | per dispatch | per wave |")
+    print("|---|---|---|---|---|")
+    for c in sorted(vals):
+        grid, avg, n = vals[c]
+        pw = "%.1f" % (avg / waves) if waves else "-"
+        print("| %s | %d | %d | %.4g | %s |" % (c, grid, n, avg, pw))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -123,8 +154,13 @@ def main(argv=None):
     r.add_argument("--copy-kernel", required=True)
     r.add_argument("--copy-bytes", type=float, required=True)
     r.add_argument("--command", action="append", default=[])
+    c = sub.add_parser("counters")
+    c.add_argument("db", nargs="+")
+    c.add_argument("--kernel", required=True, help="substring of the measured kernel's name")
+    c.add_argument("--title")
+    c.add_argument("--command", action="append", default=[])
     a = ap.parse_args(argv)
-    {"times": cmd_times, "traffic": cmd_traffic}[a.cmd](a)
+    {"times": cmd_times, "traffic": cmd_traffic, "counters": cmd_counters}[a.cmd](a)
 
 
 if __name__ == "__main__":
