@@ -92,6 +92,30 @@ def test_rgb_channels_equal_grey_queries(ctx, prec):
     ctx.set_precision("fp32")
 
 
+def test_rgb_query_in_several_passes(ctx):
+    """A device query of more points than one pass holds (2^21): each channel
+    still equals the one-channel query at its albedo, bit for bit."""
+    print("rgb multi-pass", flush=True)
+    d, _, _ = small_points(extra_random=10)
+    s = Scene(ctx, d, (0.3, 0.9, 0.3))
+    ctx.set_weights(weights.he_init(64, 4, seed=6, bias_scale=0.05))
+    ctx.set_precision("bf16")
+    n = (1 << 21) + 1000
+    p, q = camera.random_points(n, seed=21, lo=-0.1, hi=1.1)
+    tp, tq = dev(p), dev(q)
+    ctx.set_albedo_rgb(s.mid, RGB)
+    out = torch.empty(n, 3, dtype=torch.float32, device="cuda")
+    ctx.query_rgb_device(s.mid, tp, tq, out)
+    one = torch.empty(n, dtype=torch.float32, device="cuda")
+    for c in range(3):
+        ctx.set_medium_params(s.mid, 8.0, RGB[c], 0.85)
+        ctx.query_device(s.mid, tp, tq, one)
+        torch.cuda.synchronize()
+        assert torch.equal(out[:, c], one), c
+    s.close()
+    ctx.set_precision("fp32")
+
+
 def test_rgb_render_small_workload(ctx):
     """FP32 RGB frame of the 64^2 orthographic workload against the oracle per
     channel; a grey medium's RGB frame is three copies of its grey frame."""
