@@ -48,6 +48,13 @@ def test_calls_fail_cleanly_without_a_device():
     assert nis.nis_last_error()
     assert nis.nis_destroy(None) == nis.NIS_OK
     assert nis.nis_create(0, None) == nis.NIS_E_INVALID
+    # calls on a NULL context are refused before anything touches a device
+    rgb = (ctypes.c_float * 3)(0.5, 0.5, 0.5)
+    assert nis.nis_set_albedo_rgb(None, 0, rgb) == nis.NIS_E_INVALID
+    assert nis.nis_query_rgb(None, 0, None, None, 1, None) == nis.NIS_E_INVALID
+    assert nis.nis_query_rgb_device(None, 0, None, None, 1, None, None) == nis.NIS_E_INVALID
+    assert nis.nis_render_rgb(None, 0, None, 0, None, None) == nis.NIS_E_INVALID
+    assert nis.nis_set_volume_phase(None, 0, 1) == nis.NIS_E_INVALID
 
 
 def test_weight_blob_layout():
