@@ -408,44 +408,49 @@ k_features(FeatArgs A)
 
         // ---- set-up: sheared path-density bases (one lane per point) and the
         // density bases, in-cube bits and weights of each slab (one lane per slab)
-        if (ln < kTP * 9) {
-            const int spt = ln / 9, qi = ln % 9;
+        if (ln < kTP * 10) {
+            // one path for both: three FP64 coordinates of the point, each an
+            // offset of g = x n_m - 1/2, then their floors and fractions
+            const bool slab = ln < kTP * 9;
+            const int spt = slab ? ln / 9 : ln - kTP * 9, qi = slab ? ln % 9 : 0;
             const double x[3] = {px[spt][0], px[spt][1], px[spt][2]};
-            const int mask = smask[spt][k][qi];
-            const double gb = x[mv.b] * nm - 0.5 + c * sh.qo[mv.b][qi];
-            const double gc = x[mv.c] * nm - 0.5 + c * sh.qo[mv.c][qi];
-            const double ga = x[mv.a] * nm - 0.5;
-            const double fb = floor(gb), fc = floor(gc), fa = floor(ga);
-            SlabParams s;
-            s.ia = (int)fa + (qi - 4) * mv.sigma;
-            s.cbase = (int)fc - 2;
-            s.bbase = (int)fb - 2;
-            s.mask = mask;
-            s.wa = (float)(ga - fa);
-            s.wc = (float)(gc - fc);
-            s.wb = (float)(gb - fb);
-            s.pad = 0.f;
-            sp[spt][qi] = s;
-        } else if (ln < kTP * 10) {
-            const int q4 = ln - kTP * 9;
-            const double x[3] = {px[q4][0], px[q4][1], px[q4][2]};
-            double Uf, Vf, Jf;
-            sheared(mv, nm, x, Uf, Vf, Jf);
-            const double fu = floor(Uf), fv = floor(Vf), fj = floor(Jf);
-            PointLayer q;
-            q.iu = (int)fu;
-            q.iv = (int)fv;
-            q.ij = (int)fj;
-            q.pad = 0;
-            q.wu = (float)(Uf - fu);
-            q.wv = (float)(Vf - fv);
-            q.wj = (float)(Jf - fj);
-            q.w00 = (1.f - q.wj) * (1.f - q.wv);
-            q.w10 = q.wj * (1.f - q.wv);
-            q.w01 = (1.f - q.wj) * q.wv;
-            q.w11 = q.wj * q.wv;
-            q.pad1 = 0.f;
-            pl[q4] = q;
+            const double ga = x[mv.a] * nm - 0.5, gb = x[mv.b] * nm - 0.5, gc = x[mv.c] * nm - 0.5;
+            // slab q: (a, b, c) = (g_a, g_b + c o_b(q), g_c + c o_c(q)); point:
+            // the sheared (J, U, V) with J = g_a (or n_m - 1 - g_a against the
+            // axis) and U = g_b + J s_b, V = g_c + J s_c
+            const double t0 = !slab && mv.sigma > 0 ? (nm - 1) - ga : ga;
+            const double t1 = gb + (slab ? c * sh.qo[mv.b][qi] : t0 * mv.sb);
+            const double t2 = gc + (slab ? c * sh.qo[mv.c][qi] : t0 * mv.sc);
+            const double f0 = floor(t0), f1 = floor(t1), f2 = floor(t2);
+            const int i0 = (int)f0, i1 = (int)f1, i2 = (int)f2;
+            const float w0 = (float)(t0 - f0), w1 = (float)(t1 - f1), w2 = (float)(t2 - f2);
+            if (slab) {
+                SlabParams sp1;
+                sp1.ia = i0 + (qi - 4) * mv.sigma;
+                sp1.cbase = i2 - 2;
+                sp1.bbase = i1 - 2;
+                sp1.mask = smask[spt][k][qi];
+                sp1.wa = w0;
+                sp1.wc = w2;
+                sp1.wb = w1;
+                sp1.pad = 0.f;
+                sp[spt][qi] = sp1;
+            } else {
+                PointLayer q;
+                q.iu = i1;
+                q.iv = i2;
+                q.ij = i0;
+                q.pad = 0;
+                q.wu = w1;
+                q.wv = w2;
+                q.wj = w0;
+                q.w00 = (1.f - w0) * (1.f - w2);
+                q.w10 = w0 * (1.f - w2);
+                q.w01 = (1.f - w0) * w2;
+                q.w11 = w0 * w2;
+                q.pad1 = 0.f;
+                pl[spt] = q;
+            }
         }
         __syncthreads();
         const int pt = ln >> 4;
