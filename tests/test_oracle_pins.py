@@ -222,6 +222,148 @@ def test_path_density_converges_to_ray_integral():
     assert slope > 1.8, (errs, slope)
 
 
+# Sheared lights at the edges of the box (eq. 1 integrated along rays parallel
+# to l).  Each pin is geometry worked out on the unit cube, by brute force over
+# rays, slices or points: none retypes the oracle's ray-range or lookup formulas.
+SHEARED_LIGHTS = [(0.3, 0.9, 0.3), (-0.7, 0.2, 0.4), (0.1, -0.3, -0.95), (0.5, 0.5, -0.45),
+                  (0.9, -0.85, 0.2), (-0.35, -0.6, 0.58)]
+
+
+def _frame_of(light):
+    # the library and the oracle receive the direction as float32
+    l = np.asarray(light, np.float32).astype(np.float64)
+    l = l / np.linalg.norm(l)
+    a = int(np.argmax(np.abs(l)))
+    b, c = [i for i in range(3) if i != a]
+    return l, a, b, c
+
+
+@pytest.mark.parametrize("light", SHEARED_LIGHTS)
+def test_stored_rays_cover_every_ray_that_meets_the_box(light):
+    # With a density that is positive everywhere, a sheared ray has a non-zero
+    # sample exactly when it crosses the box's lateral extent at some slice.
+    # Every such ray must be stored strictly inside the stored range (its
+    # first and last rays are margins that miss the box), the margin rays must
+    # be zero at every slice, and every stored ray that meets the box must
+    # carry a positive path density at the far end of the box.
+    rho = (medium.fbm_cloud(16, seed=3) * 0.5 + 0.25).astype(np.float32)
+    M = oracle.Medium(rho)
+    M.set_light(light)
+    fr = M.light_frame()
+    for m in range(M.levels):
+        nm = 16 >> m
+        D, (ulo, uhi, vlo, vhi) = M.path_density(m)
+        # brute force over a wide window of integer rays and every slice:
+        # lateral index coordinate of ray U at slice J is U - J s
+        def meets(r, s):
+            return any(-0.5 <= r - J * s <= nm - 0.5 for J in range(nm))
+        us = [U for U in range(-4 * nm - 4, 5 * nm + 5) if meets(U, fr["sb"])]
+        vs = [V for V in range(-4 * nm - 4, 5 * nm + 5) if meets(V, fr["sc"])]
+        assert ulo < min(us) and max(us) < uhi, (m, ulo, uhi, us[0], us[-1])
+        assert vlo < min(vs) and max(vs) < vhi, (m, vlo, vhi, vs[0], vs[-1])
+        assert np.all(D[:, :, 0] == 0) and np.all(D[:, :, -1] == 0)
+        assert np.all(D[:, 0, :] == 0) and np.all(D[:, -1, :] == 0)
+        for V in range(vlo, vhi + 1):
+            for U in range(ulo, uhi + 1):
+                hit = any(-0.5 <= U - J * fr["sb"] <= nm - 0.5 and -0.5 <= V - J * fr["sc"] <= nm - 0.5
+                          for J in range(nm))
+                assert (D[-1, V - vlo, U - ulo] > 0) == hit, (m, U, V)
+
+
+def _slice_planes(nm, sigma):
+    """World coordinates along the dominant axis of the voxel-centre planes of
+    a level, ordered from the light side."""
+    c = (np.arange(nm) + 0.5) / nm
+    return c[::-1] if sigma > 0 else c
+
+
+@pytest.mark.parametrize("light", SHEARED_LIGHTS)
+def test_path_density_is_zero_beside_the_box(light):
+    # A point whose line towards the light passes the box more than one voxel
+    # away (laterally, at every slice plane between the light-facing face and
+    # two slices beyond the point) sees no medium: the interpolated path
+    # density is exactly zero, at every level.
+    n, c = 16, 0.5
+    M = oracle.Medium(medium.constant(n, c))
+    M.set_light(light)
+    l, a, b, cc = _frame_of(light)
+    fr = M.light_frame()
+    rng = np.random.default_rng(5)
+    for m in range(M.levels):
+        nm = n >> m
+        h = 1.0 / nm
+        pts = rng.uniform(-0.5 - 3 * h, 1.5 + 3 * h, (1500, 3))
+        pts[:, a] = rng.uniform(0.0, 1.0, 1500)
+        planes = _slice_planes(nm, fr["sigma"])
+        checked = 0
+        for x in pts:
+            # planes from the light side up to two slices beyond the point
+            beyond = x[a] - 2 * h if fr["sigma"] > 0 else x[a] + 2 * h
+            use = planes[planes >= beyond] if fr["sigma"] > 0 else planes[planes <= beyond]
+            clear = True
+            for pa in use:
+                t = (pa - x[a]) / l[a]
+                yb, yc = x[b] + t * l[b], x[cc] + t * l[cc]
+                if not (yb < -h or yb > 1 + h or yc < -h or yc > 1 + h):
+                    clear = False
+                    break
+            if clear:
+                assert M.sample_D(m, x) == 0.0, (m, x)
+                checked += 1
+        assert checked > 50, (m, checked)
+
+
+@pytest.mark.parametrize("light", SHEARED_LIGHTS)
+def test_path_density_beyond_the_faces_of_a_slab(light):
+    # Homogeneous slab rho == c.  Beyond the light-facing face the lookup
+    # clamps to the first slice, whose trapezoid value is half a step:
+    # c h_m / (2 |l_a|).  Beyond the far face it clamps to the last slice:
+    # c h_m (n_m - 1/2) / |l_a|.  Both hold where the line through the point
+    # stays at least one voxel inside the box laterally on the slices involved.
+    n, c = 16, 0.5
+    M = oracle.Medium(medium.constant(n, c))
+    M.set_light(light)
+    l, a, b, cc = _frame_of(light)
+    fr = M.light_frame()
+    la = abs(l[a])
+    rng = np.random.default_rng(9)
+    far_total = 0
+    for m in range(M.levels):
+        nm = n >> m
+        h = 1.0 / nm
+        planes = _slice_planes(nm, fr["sigma"])
+        near = far = 0
+        for _ in range(600):
+            x = rng.uniform(0.0, 1.0, 3)
+            side = rng.integers(2)                    # 0: light side, 1: far side
+            out = rng.uniform(0.01, 0.6)
+            light_face = 1.0 if fr["sigma"] > 0 else 0.0
+            far_face = 1.0 - light_face
+            toward = 1.0 if fr["sigma"] > 0 else -1.0
+            x[a] = light_face + toward * out if side == 0 else far_face - toward * out
+            use = planes[:1] if side == 0 else planes
+            inside = True
+            for pa in use:
+                t = (pa - x[a]) / l[a]
+                yb, yc = x[b] + t * l[b], x[cc] + t * l[cc]
+                if not (h <= yb <= 1 - h and h <= yc <= 1 - h):
+                    inside = False
+                    break
+            if not inside:
+                continue
+            if side == 0:
+                assert M.sample_D(m, x) == pytest.approx(c * h / (2 * la), rel=1e-12)
+                near += 1
+            else:
+                assert M.sample_D(m, x) == pytest.approx(c * h * (nm - 0.5) / la, rel=1e-12)
+                far += 1
+        if nm >= 4:                                   # coarser levels have no interior
+            assert near > 20, (m, near)
+        far_total += far
+    if max(abs(fr["sb"]), abs(fr["sc"])) < 0.8:       # steeper shears leave no full column
+        assert far_total > 20, far_total
+
+
 # --------------------------------------------------------------------------
 # Template sampling, Sec. III.B.2-4 (light-aligned 12 x 5x5x9 lattice)
 
