@@ -47,17 +47,25 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--workload", default="frame", choices=["frame", "large", "small"])
-    ap.add_argument("--cpu-sample", type=int, default=131072,
-                    help="points of the frame the oracle is timed on (0 = skip)")
-    ap.add_argument("--parity-sample", type=int, default=2048)
+    ap.add_argument("--cpu-sample", type=int, default=32768,
+                    help="points of the frame the oracle is timed on, per run (0 = skip)")
+    ap.add_argument("--cpu-runs", type=int, default=3, help="oracle timing runs (the median is reported)")
+    ap.add_argument("--parity-sample", type=int, default=262144,
+                    help="seeded subset of the frame's collisions checked against the oracle at the workload's g")
+    ap.add_argument("--parity-sample-by-g", type=int, default=16384,
+                    help="seeded subset checked at each g of the precision workload")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size (for scaling HBM counters)")
     ap.add_argument("--compare-fp32", action="store_true", default=True)
     ap.add_argument("--no-compare-fp32", dest="compare_fp32", action="store_false")
-    ap.add_argument("--serve-seconds", type=float, default=2.0,
-                    help="length of the Poisson request trace of the serving run (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="measured length of the Poisson request trace of the serving run (0 = skip)")
+    ap.add_argument("--serve-warmup", type=float, default=5.0,
+                    help="seconds of the trace before the measured part (requests not recorded)")
+    ap.add_argument("--serve-sustained-seconds", type=float, default=30.0,
+                    help="length of the second trace, at 70%% of the rate the device sustained")
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--serve-inflight", type=int, default=8)
+    ap.add_argument("--serve-inflight", type=int, default=4)
     ap.add_argument("--serve-budget-gb", type=int, default=200)
     return ap.parse_args()
 
@@ -71,19 +79,29 @@ def kernel_work(wl, levels, level_geom, npix, npts, width, n_linear, prec):
     for the frame workload; the large one runs the features and backbone in
     passes of at most 2^21 points)."""
     esize = {"fp32": 4, "bf16": 2, "fp8": 2}[prec]     # the FP8 path stores the descriptor in BF16
+    # bytes per stored transmittance feature: the FP8 path runs the CNN on BF16
+    b_t = {"fp32": 4, "bf16": 2, "fp8": 2}[prec]
     n0 = wl.n
     vox = [(n0 >> m) ** 3 for m in range(levels)]
+    samples = sum(nu * nv * n for (nu, nv, n) in level_geom)          # rays x slices of every level
     pairs_v = sum(nu * (nv + 1) * n for (nu, nv, n) in level_geom)
-    conv_flop = 2 * 12 * (504 * 27 + 80 * 216)                       # per point
+    conv_flop = 2 * 12 * (504 * 27 + 80 * 216) + 2 * 12 * (64 + 64)  # per point: conv1, conv2, attention
     mlp_flop = 2 * (1057 * width + (n_linear - 2) * width * width + width)
+    # the transmittance fields as the method defines them: the density pyramid
+    # read and one FP32 path density per ray sample written
+    fields = 4 * sum(vox) + 4 * samples
     return {
         "pyramid": {"bytes": 4 * sum(vox[:-1]) + 4 * sum(vox[1:])},
-        # reads the pyramid, writes the path density as its pairs along V
-        "sweep": {"bytes": 4 * sum(vox) + 8 * pairs_v},
+        # reads the pyramid, writes the path density; this library writes it
+        # as its pairs along V (the gather's layout), counted as layout bytes
+        "sweep": {"bytes": fields, "layout_bytes": 4 * sum(vox) + 8 * pairs_v},
         "site_tables": {"bytes": 225 * 16},
         # rays: flag, point and direction per pixel; scan; compacted copies
         "raygen": {"bytes": npix * (4 + 12 + 12) + npix * 8 + npts * (12 + 12 + 4)},
-        "features": {"bytes": npts * (24 + 4 + 1088 * esize), "flops": npts * conv_flop,
+        # the gather of the method: per point its position and direction in,
+        # 12 x 225 graded transmittances (b_t bytes each) and 12 x 8 squeeze
+        # statistics and the two scalars out, plus the fields read once
+        "features": {"bytes": npts * (24 + 2700 * b_t + 208) + fields, "flops": npts * conv_flop,
                      "valu_flops": npts * GATHER_FLOP_PER_POINT},
         "backbone": {"bytes": npts * (1088 * esize + 8), "flops": npts * mlp_flop},
         "image": {"bytes": npix * 4 + npts * 12},
@@ -104,6 +122,67 @@ def measured_traffic(kernel, prec, workload):
     return rec["traffic_bytes_per_launch"]
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        return "unknown CPU"
+
+
+def cpu_baseline(args, om, op, wl, pts, dirs, rng):
+    """The FP64 oracle timed on the host cores (median of args.cpu_runs runs):
+    the full-resolution sweep, then the gather alone and the whole query on a
+    seeded subset of the frame's collisions, scaled to the frame; the small
+    workload (32^3, all points) also on one core."""
+    from oracle import oracle
+    from workloads import configs
+    f32 = lambda x: float(np.float32(x))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.set_threads(threads)
+    cidx = np.sort(rng.choice(len(pts), min(args.cpu_sample, len(pts)), replace=False))
+    cp, cd = pts[cidx], dirs[cidx]
+    t_sweep, t_gather, t_query = [], [], []
+    for _ in range(args.cpu_runs):
+        t = time.perf_counter()
+        om.set_light(np.asarray(wl.light, np.float32))
+        t_sweep.append(time.perf_counter() - t)
+        t = time.perf_counter()
+        om.features(f32(wl.sigma_t), f32(wl.g), op["lam"], cp, cd, outputs=("stats", "f0"))
+        t_gather.append(time.perf_counter() - t)
+        t = time.perf_counter()
+        om.query(op, cp, cd, f32(wl.sigma_t), f32(wl.albedo), f32(wl.g), f32(wl.radiance))
+        t_query.append(time.perf_counter() - t)
+    sw, ga, qu = (float(np.median(v)) for v in (t_sweep, t_gather, t_query))
+    frame_s = sw + qu * len(pts) / len(cidx)
+    # the small workload on one core, all of its points
+    sm = configs.SMALL
+    sd = sm.density()
+    sp, sdir, _ = sm.points(sd)
+    sop = dict(sm.params())
+    sop["lam"] = f32(sop["lam"])
+    oracle.set_threads(1)
+    t_small = []
+    for _ in range(args.cpu_runs):
+        t = time.perf_counter()
+        smm = oracle.Medium(sd)
+        smm.set_light(np.asarray(sm.light, np.float32))
+        smm.query(sop, sp, sdir, f32(sm.sigma_t), f32(sm.albedo), f32(sm.g), f32(sm.radiance))
+        t_small.append(time.perf_counter() - t)
+    oracle.set_threads(threads)
+    ts = float(np.median(t_small))
+    log("oracle: sweep %.2fs, gather %.2fs and query %.2fs for %d points on %d threads; small workload "
+        "%.2fs on 1 thread" % (sw, ga, qu, len(cidx), threads, ts))
+    return {"value": len(pts) / frame_s, "unit": "shading points/s", "cores": threads, "kind": "oracle",
+            "sample": "FP64 oracle (C, OpenMP) on %s, %d threads (%d logical CPUs visible), median of %d runs: "
+                      "full-resolution sweep plus a seeded %d-point subset of the frame's %d collisions, scaled to "
+                      "the frame" % (cpu_model(), threads, os.cpu_count() or 0, args.cpu_runs, len(cidx), len(pts)),
+            "per_stage_s": {"sweep_per_light": sw, "gather_per_point": ga / len(cidx),
+                            "network_per_point": (qu - ga) / len(cidx), "query_per_point": qu / len(cidx)},
+            "small_workload_1_core": {"points": len(sp), "seconds": ts, "points_per_s": len(sp) / ts,
+                                      "includes": "pyramid, sweep and query of the 32^3 workload"}}
+
+
 def frame_camera(nis, wl):
     if wl.cam == "ortho":
         return nis.camera(wl.res[0], wl.res[0], vfov_deg=0.0, ortho_z=1.0)
@@ -117,12 +196,16 @@ def serving(ctx, nis, args):
     the latency percentiles (submission to observed completion)."""
     from workloads import configs, medium
     t0 = time.time()
-    mids = {n: ctx.load_medium(medium.fbm_cloud(n, seed=0), 8.0, 0.99, 0.85) for n in (64, 128, 256, 512)}
+    # media seeds 101..104 for the four sizes
+    mids = {n: ctx.load_medium(medium.fbm_cloud(n, seed=101 + i), 8.0, 0.99, 0.85)
+            for i, n in enumerate((64, 128, 256, 512))}
     log("serving: media loaded (%.1fs)" % (time.time() - t0))
     cams = {res: nis.camera(res[0], res[1], 45.0, eye=configs.FRAME_EYE)
             for res in ((256, 256), (1280, 720), (1920, 1080))}
 
-    def run(trace):
+    def run(trace, t_from=0.0):
+        """Submits the trace in real time; requests arriving before t_from
+        (the warm-up) run but are not recorded."""
         q = queue.Queue()
         recs = []
 
@@ -142,7 +225,9 @@ def serving(ctx, nis, args):
                     return
                 fid, r = item
                 res = ctx.wait(fid)
-                recs.append((res.status, res.t_submit, res.t_start, res.t_done, res.n_points))
+                if r["t"] >= t_from:
+                    recs.append((res.status, res.t_submit, res.t_start, res.t_done, res.n_points, r["n"],
+                                 r["res"]))
                 ctx.release(fid)
 
         ts, tc = threading.Thread(target=submit), threading.Thread(target=collect)
@@ -153,11 +238,26 @@ def serving(ctx, nis, args):
         ok = [x for x in recs if x[0] == 0]
         lat = np.array([x[3] - x[1] for x in ok]) * 1e3
         span = max(x[3] for x in ok) - min(x[1] for x in ok)
-        return {"requests": len(trace), "completed": len(ok), "failed": len(recs) - len(ok),
-                "offered_rps": len(trace) / max(trace[-1]["t"], 1e-9),
-                "frames_per_s": len(ok) / span, "points_per_s": sum(x[4] for x in ok) / span,
-                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                "mean_queue_ms": float(np.mean([(x[2] - x[1]) * 1e3 for x in ok]))}
+        measured = [r for r in trace if r["t"] >= t_from]
+        out = {"requests": len(measured), "completed": len(ok), "failed": len(recs) - len(ok),
+               "offered_rps": len(measured) / max(trace[-1]["t"] - t_from, 1e-9),
+               "frames_per_s": len(ok) / span, "points_per_s": sum(x[4] for x in ok) / span,
+               "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+               "mean_queue_ms": float(np.mean([(x[2] - x[1]) * 1e3 for x in ok])),
+               "mean_service_ms": float(np.mean([(x[3] - x[2]) * 1e3 for x in ok]))}
+        # latency by request class (medium edge, resolution): queueing
+        # (submission to admission) and service (admission to completion)
+        by = {}
+        for key in sorted({(x[5], tuple(x[6])) for x in ok}):
+            sel = [x for x in ok if (x[5], tuple(x[6])) == key]
+            ql = np.array([x[2] - x[1] for x in sel]) * 1e3
+            sv = np.array([x[3] - x[2] for x in sel]) * 1e3
+            by["%d^3 %dx%d" % (key[0], key[1][0], key[1][1])] = {
+                "n": len(sel), "queue_p50_ms": float(np.percentile(ql, 50)),
+                "queue_p99_ms": float(np.percentile(ql, 99)), "service_p50_ms": float(np.percentile(sv, 50)),
+                "service_p99_ms": float(np.percentile(sv, 99))}
+        out["by_class"] = by
+        return out
 
     ctx.server_start(args.serve_budget_gb << 30, "bf16", args.serve_inflight)
     try:
@@ -165,23 +265,25 @@ def serving(ctx, nis, args):
         warm = [dict(t=0.0, n=512, res=(1920, 1080), light=(0.3, 0.9, 0.3), g=0.85, seed=i)
                 for i in range(args.serve_inflight)]
         run(warm)
-        trace = configs.serving_trace(args.serve_seconds, rate=args.serve_rate, seed=7)
-        log("serving: %d requests over %.1fs at %.0f req/s" % (len(trace), args.serve_seconds, args.serve_rate))
-        offered = run(trace)
+        trace = configs.serving_trace(args.serve_warmup + args.serve_seconds, rate=args.serve_rate, seed=7)
+        log("serving: %d requests over %.1fs (%.1fs warm-up) at %.0f req/s"
+            % (len(trace), args.serve_warmup + args.serve_seconds, args.serve_warmup, args.serve_rate))
+        offered = run(trace, args.serve_warmup)
         log("serving: offered %s" % json.dumps(offered))
         # the same mix at 70% of the rate the device sustained, for latency
         # percentiles that are not dominated by a growing queue
         rate = 0.7 * offered["frames_per_s"]
-        trace2 = configs.serving_trace(max(args.serve_seconds, 300.0 / rate), rate=rate, seed=8)
-        sustained = run(trace2)
+        trace2 = configs.serving_trace(args.serve_warmup + args.serve_sustained_seconds, rate=rate, seed=8)
+        sustained = run(trace2, args.serve_warmup)
         log("serving: sustained %s" % json.dumps(sustained))
     finally:
         ctx.server_stop()
     for m in mids.values():
         ctx.unload_medium(m)
-    return {"config": "Poisson arrivals; media 64^3/128^3/256^3/512^3 fBm (resident); 256^2/720p/1080p "
-                      "pinhole; random light and g in [0.3,0.95]; bf16; %d frames in flight; budget %d GB"
-                      % (args.serve_inflight, args.serve_budget_gb),
+    return {"config": "Poisson arrivals (trace seed 7; %gs measured after a %gs warm-up); media 64^3/128^3/256^3/"
+                      "512^3 fBm, seeds 101-104 (resident); 256^2/720p/1080p pinhole; random light and g in "
+                      "[0.3,0.95]; bf16; %d frames in flight; budget %d GB"
+                      % (args.serve_seconds, args.serve_warmup, args.serve_inflight, args.serve_budget_gb),
             "latency": "submission to observed completion, host steady clock",
             "at_%g_rps" % args.serve_rate: offered,
             "at_70pct_capacity": dict(sustained, rate_rps=rate)}
@@ -314,14 +416,14 @@ def main():
     from oracle import oracle
     f32 = lambda x: float(np.float32(x))
     om = oracle.Medium(density)
-    t_sw = time.perf_counter()
     om.set_light(np.asarray(wl.light, np.float32))
-    t_sweep = time.perf_counter() - t_sw
     op = dict(params)
     op["lam"] = f32(params["lam"])
     rng = np.random.default_rng(123)
     sidx = np.sort(rng.choice(len(pts), min(args.parity_sample, len(pts)), replace=False))
+    t_par = time.perf_counter()
     oref = om.query(op, pts[sidx], dirs[sidx], f32(wl.sigma_t), f32(wl.albedo), f32(wl.g), f32(wl.radiance))
+    log("oracle at %d sampled collisions: %.1fs" % (len(sidx), time.perf_counter() - t_par))
     ref = f32(wl.albedo) * oref["L"]
     errs, errs_f = {}, {}
     sp = torch.from_numpy(np.ascontiguousarray(pts[sidx], np.float32)).cuda()
@@ -341,17 +443,21 @@ def main():
     misses_zero = bool(np.all(img.cpu().numpy()[miss] == 0.0))
 
     # radiance rel-L2 per precision over the HG asymmetries of the precision
-    # workload, at the same sampled collisions (device query, medium g changed
-    # in place; the light fields do not depend on g)
+    # workload, at a smaller seeded subset of the same collisions (device
+    # query, medium g changed in place; the light fields do not depend on g)
     errs_g = {}
-    sl = torch.empty(len(sidx), dtype=torch.float32, device="cuda")
+    gidx = np.sort(rng.choice(len(sidx), min(args.parity_sample_by_g, len(sidx)), replace=False))
+    gp, gd = pts[sidx][gidx], dirs[sidx][gidx]
+    tgp = torch.from_numpy(np.ascontiguousarray(gp, np.float32)).cuda()
+    tgd = torch.from_numpy(np.ascontiguousarray(gd, np.float32)).cuda()
+    sl = torch.empty(len(gidx), dtype=torch.float32, device="cuda")
     for g in G_SWEEP:
         ctx.set_medium_params(mid, wl.sigma_t, wl.albedo, g)
-        rg = om.query(op, pts[sidx], dirs[sidx], f32(wl.sigma_t), f32(wl.albedo), f32(g), f32(wl.radiance))["L"]
+        rg = om.query(op, gp, gd, f32(wl.sigma_t), f32(wl.albedo), f32(g), f32(wl.radiance))["L"]
         errs_g[str(g)] = {}
         for prec in precs:
             ctx.set_precision(prec)
-            ctx.query_device(mid, sp, sd, sl)
+            ctx.query_device(mid, tgp, tgd, sl)
             torch.cuda.synchronize()
             got = sl.cpu().numpy().astype(np.float64)
             errs_g[str(g)][prec] = float(np.linalg.norm(got - rg) / np.linalg.norm(rg))
@@ -359,26 +465,10 @@ def main():
     ctx.set_medium_params(mid, wl.sigma_t, wl.albedo, wl.g)
     ctx.set_precision(args.precision)
 
-    # oracle throughput on the host cores (bounded sample)
+    # oracle throughput on the host cores (bounded sample, median of runs)
     cpu = None
     if args.cpu_sample > 0:
-        cidx = np.sort(rng.choice(len(pts), min(args.cpu_sample, len(pts)), replace=False))
-        tq = time.perf_counter()
-        om.query(op, pts[cidx], dirs[cidx], f32(wl.sigma_t), f32(wl.albedo), f32(wl.g), f32(wl.radiance))
-        tq = time.perf_counter() - tq
-        frame_s = t_sweep + tq * len(pts) / len(cidx)
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        model = "unknown CPU"
-        try:
-            with open("/proc/cpuinfo") as f:
-                model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
-        except (OSError, StopIteration):
-            pass
-        cpu = {"value": len(pts) / frame_s, "unit": "shading points/s", "cores": cores, "kind": "oracle",
-               "sample": "FP64 oracle on %s (%d logical CPUs visible): full-resolution sweep (%.2fs, 1 thread) "
-                         "plus a seeded %d-point subset of the frame's collisions (%.2fs on %d threads), scaled to "
-                         "the frame's %d points" % (model, os.cpu_count() or 0, t_sweep, len(cidx), tq, cores,
-                                                    len(pts))}
+        cpu = cpu_baseline(args, om, op, wl, pts, dirs, rng)
 
     prec = args.precision
     ms = res[prec]["ms"]
@@ -395,6 +485,8 @@ def main():
         if "bytes" in w:
             ent["GBps"] = w["bytes"] / (t_ms * 1e-3) / 1e9
             ent["hbm_frac"] = ent["GBps"] / HBM_PEAK_GBS
+        if "layout_bytes" in w:
+            ent["layout_GBps"] = w["layout_bytes"] / (t_ms * 1e-3) / 1e9
         if "flops" in w:
             ent["TFLOPs"] = w["flops"] / (t_ms * 1e-3) / 1e12
             ent["mfma_frac"] = ent["TFLOPs"] / MFMA_PEAK_TFLOPS[prec]
@@ -402,19 +494,27 @@ def main():
             ent["valu_TFLOPs"] = w["valu_flops"] / (t_ms * 1e-3) / 1e12
             ent["valu_frac"] = ent["valu_TFLOPs"] / VALU_FP32_TFLOPS
         kernels[k] = ent
+    # the whole network (conv + attention inside the gather kernel, backbone):
+    # its useful FLOPs over the two kernels' time
+    net_ms = res[prec]["kernels"].get("features", 0.0) + res[prec]["kernels"].get("backbone", 0.0)
+    net_flops = work["features"]["flops"] + work["backbone"]["flops"]
+    network = {"flops_per_point": net_flops / len(pts), "ms": net_ms,
+               "TFLOPs": net_flops / (net_ms * 1e-3) / 1e12,
+               "mfma_frac": net_flops / (net_ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS[prec]}
     dom = max(res[prec]["kernels"], key=lambda k: res[prec]["kernels"][k])
     dk = kernels[dom]
-    if dom == "features":
-        # the gather's interpolation arithmetic runs on the vector ALUs; the two
-        # small convolutions (conv_flop) run on MFMA and are reported beside it
-        roof = {"kernel": dom, "bound": "alu", "achieved": dk["valu_TFLOPs"], "peak": VALU_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": dk["valu_frac"], "traffic": None}
-    elif "flops" in work.get(dom, {}):
+    if "flops" in work.get(dom, {}) and "valu_flops" not in work.get(dom, {}):
         roof = {"kernel": dom, "bound": "mfma", "achieved": dk["TFLOPs"], "peak": MFMA_PEAK_TFLOPS[prec],
                 "unit": "TFLOP/s", "frac": dk["mfma_frac"], "traffic": None}
     else:
+        # the gather (and any other kernel) against HBM on its algorithmic
+        # bytes; for the gather also its vector-ALU and conv MFMA fractions
         roof = {"kernel": dom, "bound": "hbm", "achieved": dk["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": dk["hbm_frac"], "traffic": None}
+        if "valu_frac" in dk:
+            roof.update({"algorithmic_bytes": work[dom]["bytes"], "valu_achieved_TFLOPs": dk["valu_TFLOPs"],
+                         "valu_peak_TFLOPs": VALU_FP32_TFLOPS, "valu_frac": dk["valu_frac"],
+                         "conv_mfma_frac": dk["mfma_frac"]})
     roof["traffic"] = measured_traffic(dom, prec, args.workload)
 
     serve = None
@@ -451,6 +551,7 @@ def main():
         "per_precision": {p: {"ms_per_step": res[p]["ms"], "points_per_s": len(pts) / (res[p]["ms"] * 1e-3),
                               "fps": 1000.0 / res[p]["ms"], "kernels_ms": res[p]["kernels"]} for p in precs},
         "kernels": kernels,
+        "network": network,
         "roofline": roof,
         "cpu_baseline": cpu,
         "serving": serve,

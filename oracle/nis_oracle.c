@@ -31,6 +31,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OM_LAYERS 12          /* 8 diffuse + 4 highlight template layers */
 #define OM_DIFFUSE 8
@@ -144,6 +147,25 @@ double om_mhg(int nl, const double *lw, const double *lg, double mu)
 }
 
 static int clampi(int i, int lo, int hi) { return i < lo ? lo : (i > hi ? hi : i); }
+
+/* Threads of the OpenMP loops (for timing the oracle on a given core count). */
+void om_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int om_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------ */
 /* Density pyramid, Sec. III.B.1: the grid is down-sampled level by level to
@@ -269,6 +291,8 @@ int om_set_light(om_medium *M, const float dir[3])
         free(M->D[m]);
         M->D[m] = (double *)malloc((size_t)nu * nv * nm * sizeof(double));
         double ds = (1.0 / nm) / fabs(M->l[a]);
+        /* rays are independent: one thread per row of rays */
+#pragma omp parallel for schedule(dynamic, 1)
         for (int V = M->vlo[m]; V <= M->vhi[m]; V++)
             for (int U = M->ulo[m]; U <= M->uhi[m]; U++) {
                 double sum = 0.0;

@@ -66,6 +66,9 @@ def lib():
         L.om_hg_cone.restype = ctypes.c_double
         L.om_hg_cone.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.om_volume_init.argtypes = []
+        L.om_set_threads.argtypes = [ctypes.c_int]
+        L.om_get_threads.restype = ctypes.c_int
+        L.om_get_threads.argtypes = []
         L.om_features.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, _dp, _dp, ctypes.c_int,
                                   ctypes.c_double,
                                   _fp, _fp, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _dp]
@@ -78,6 +81,15 @@ def lib():
                                ctypes.c_int, _fp, _fp, ctypes.c_int64, _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops from now on."""
+    lib().om_set_threads(int(n))
+
+
+def get_threads():
+    return lib().om_get_threads()
 
 
 def _f32(a):
@@ -215,18 +227,20 @@ class Medium:
     def sample_D(self, m, x):
         return lib().om_sample_D(self.h, m, _ptr(_f64(x), _dp))
 
-    def features(self, sigma_t, g, lam, pts, dirs, volume=False):
+    def features(self, sigma_t, g, lam, pts, dirs, volume=False,
+                 outputs=("tbar", "rho", "phi", "stats", "tp", "f0")):
         """Per-point features; g is one asymmetry or a sequence of (weight, g)
-        lobes; volume selects the volume phase of eq. 9 for the phase features."""
+        lobes; volume selects the volume phase of eq. 9 for the phase features.
+        Only the named outputs are kept (the others are computed, not stored)."""
         pts, dirs = _f32(pts), _f32(dirs)
         P = pts.shape[0]
-        out = {"tbar": np.zeros((P, LAYERS, SITES)), "rho": np.zeros((P, LAYERS, SITES)),
-               "phi": np.zeros((P, SITES)), "stats": np.zeros((P, LAYERS, STATS)),
-               "tp": np.zeros(P), "f0": np.zeros(P)}
+        shapes = {"tbar": (P, LAYERS, SITES), "rho": (P, LAYERS, SITES), "phi": (P, SITES),
+                  "stats": (P, LAYERS, STATS), "tp": (P,), "f0": (P,)}
+        out = {k: np.zeros(shapes[k]) for k in outputs}
         lw, lg = lobes(g)
         lib().om_features(self.h, float(sigma_t), len(lw), _ptr(lw, _dp), _ptr(lg, _dp), int(bool(volume)),
                           float(lam), _ptr(pts, _fp),
-                          _ptr(dirs, _fp), P, *[_ptr(out[k], _dp) for k in
+                          _ptr(dirs, _fp), P, *[_ptr(out.get(k), _dp) for k in
                                                 ("tbar", "rho", "phi", "stats", "tp", "f0")])
         return out
 

@@ -137,6 +137,17 @@ def cmd_counters(a):
         grid, avg, n = vals[c]
         pw = "%.1f" % (avg / waves) if waves else "-"
         print("| %s | %d | %d | %.4g | %s |" % (c, grid, n, avg, pw))
+    if "SQ_VALU_MFMA_BUSY_CYCLES" in vals and "GRBM_GUI_ACTIVE" in vals:
+        # GRBM_GUI_ACTIVE sums the XCDs' clocks; the MFMA busy cycles sum the SIMDs
+        cyc = vals["GRBM_GUI_ACTIVE"][1] / a.xcds
+        busy = vals["SQ_VALU_MFMA_BUSY_CYCLES"][1]
+        print("\nDerived (%d XCDs, %d SIMDs):\n" % (a.xcds, a.simds))
+        print("* kernel cycles per XCD (GRBM_GUI_ACTIVE / %d): %.4g" % (a.xcds, cyc))
+        print("* MFMA busy fraction (SQ_VALU_MFMA_BUSY_CYCLES / (cycles x %d SIMDs)): %.3f"
+              % (a.simds, busy / (cyc * a.simds)))
+        for c in sorted(vals):
+            if c.startswith("SQ_INSTS_VALU_MFMA_MOPS_") and vals[c][1] > 0:
+                print("* %s x 512: %.4g MFMA FLOP per dispatch" % (c, vals[c][1] * 512))
 
 
 def main(argv=None):
@@ -159,6 +170,8 @@ def main(argv=None):
     c.add_argument("--kernel", required=True, help="substring of the measured kernel's name")
     c.add_argument("--title")
     c.add_argument("--command", action="append", default=[])
+    c.add_argument("--xcds", type=int, default=8)
+    c.add_argument("--simds", type=int, default=1024)
     a = ap.parse_args(argv)
     {"times": cmd_times, "traffic": cmd_traffic, "counters": cmd_counters}[a.cmd](a)
 
