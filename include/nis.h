@@ -222,6 +222,28 @@ int32_t nis_query_device(nis_ctx *ctx, int32_t medium, const float *d_points,
                          const float *d_view_dirs, int64_t n, float *d_radiance_out,
                          void *hip_stream);
 
+/*
+ * nis_query_device_noalloc -- nis_query_device for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same computation and the same result,
+ * bit for bit, but the call allocates nothing.  Its scratch (descriptor rows,
+ * single-scatter terms and row maxima of one pass) is a fixed array of
+ * device memory inside the library, about 36 MB, of which each GPU the library
+ * runs on holds its own copy until the process ends; no part of it has to
+ * start at zero.  Every call on one GPU shares that GPU's copy, which keeps
+ * the last call's contents: calls whose work overlaps on one GPU (other
+ * streams, other contexts, other host threads) race, and the caller must
+ * order them.  Limits: 1 <= n <= NIS_NOALLOC_MAX_POINTS points per call
+ * (NIS_E_INVALID beyond); the medium's light must have been set (its fields
+ * and tables are allocated by nis_set_light, and by nis_set_volume_phase for
+ * volume phases), else NIS_E_STATE.  Arguments, layouts, ownership, ordering
+ * and other errors as nis_query_device.
+ */
+#define NIS_NOALLOC_MAX_POINTS 8192
+int32_t nis_query_device_noalloc(nis_ctx *ctx, int32_t medium, const float *d_points,
+                                 const float *d_view_dirs, int64_t n, float *d_radiance_out,
+                                 void *hip_stream);
+
 /* ---- frames --------------------------------------------------------------- */
 
 /*

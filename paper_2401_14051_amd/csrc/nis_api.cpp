@@ -12,6 +12,17 @@
 
 #include "runtime.h"
 
+// Scratch of the allocation-free query (nis_query_device_noalloc): room for
+// the descriptor rows, single-scatter terms and row maxima of
+// NIS_NOALLOC_MAX_POINTS points at the widest precision (FP32 descriptor),
+// each part starting on a 256-byte boundary.  Every GPU the library runs on
+// holds its own copy until the process ends.  Host code never passes this
+// name to a kernel or a copy: it reaches the memory only through the device
+// address that scratch_setup() looks up per device.
+constexpr size_t kScratchBytes =
+    ((size_t)NIS_NOALLOC_MAX_POINTS * nis::kDescPad * 4 + 255) / 256 * 256 + 2 * (((size_t)NIS_NOALLOC_MAX_POINTS * 4 + 255) / 256 * 256);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace nis {
 
 thread_local std::string g_err;
@@ -203,9 +214,13 @@ static const GaussLegendre64& gauss_legendre64()
     return gl;
 }
 
-void refresh_tables(const Medium* M, LightState* ls, const Phase& ph, bool volume, hipStream_t s)
+void refresh_tables(const Medium* M, LightState* ls, const Phase& ph, bool volume, hipStream_t s,
+                    bool may_alloc = true)
 {
     if (ls->tab_valid && same_phase(ls->tab_phase, ph) && ls->tab_volume == volume) return;
+    if (!may_alloc && (ls->tab.bytes < sizeof(SiteTables) ||
+                       (volume && ls->vtab.bytes < (size_t)kSites * kVBins * sizeof(float))))
+        fail(NIS_E_STATE, "the light's site tables are not allocated: set the light (after enabling volume phases)");
     ls->tab.reserve(sizeof(SiteTables), "site tables");
     Params P = medium_params(M);
     P.phase = ph;
@@ -529,12 +544,65 @@ void set_light_state(const Medium* M, const double l[3], LightState* ls)
         ls->RT.release();
     ls->P.reserve((size_t)ls->pair_count * sizeof(float2), "light-axis density pairs");
     ls->DP.reserve((size_t)ls->dpair_count * sizeof(float2), "path-density pairs");
+    // the site tables too, so that a query under this light allocates nothing
+    ls->tab.reserve(sizeof(SiteTables), "site tables");
+    if (M->volume_phase) ls->vtab.reserve((size_t)kSites * kVBins * sizeof(float), "volume phase tables");
     ls->valid = true;
     ls->stale = true;
     ls->tab_valid = false;
 }
 
 const char* precision_name(int prec) { return prec == kPrecFP32 ? "fp32" : prec == kPrecBF16 ? "bf16" : "fp8"; }
+
+// ---- allocation-free scratch ------------------------------------------------
+
+namespace {
+
+struct ScratchSlot {
+    bool done = false;
+    hipError_t err = hipSuccess;
+    void* ptr = nullptr;   // device address of this device's copy of `scratch`
+};
+std::mutex g_scratch_mu;
+std::map<int, ScratchSlot> g_scratch;
+
+// Looks up the device address of `scratch` on `device`, which must be the
+// current device; once per device, the result (or the HIP error) kept.
+void scratch_setup(int device)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    ScratchSlot& sl = g_scratch[device];
+    if (sl.done) return;
+    void* ptr = nullptr;
+    sl.err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    sl.ptr = sl.err == hipSuccess ? ptr : nullptr;
+    sl.done = true;
+}
+
+// The scratch of `device` cut into the parts of one pass of n points.
+WsView scratch_view(int device, int prec, int64_t n)
+{
+    ScratchSlot sl;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        auto it = g_scratch.find(device);
+        if (it != g_scratch.end()) sl = it->second;
+    }
+    if (!sl.done) fail(NIS_E_INTERNAL, "scratch not set up for this device");
+    if (!sl.ptr) fail(NIS_E_DEVICE, std::string("scratch address: ") + hipGetErrorString(sl.err));
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t d = up((size_t)n * kDescPad * desc_elem_bytes(prec)), f = up((size_t)n * 4);
+    if (d + 2 * f > kScratchBytes) fail(NIS_E_INTERNAL, "scratch too small");
+    char* base = static_cast<char*>(sl.ptr);
+    WsView w;
+    w.desc = base;
+    w.f0 = reinterpret_cast<float*>(base + d);
+    w.rowmax = reinterpret_cast<float*>(base + d + f);
+    w.chunk = n;
+    return w;
+}
+
+}  // namespace
 
 // ---- query ----------------------------------------------------------------
 
@@ -561,14 +629,29 @@ void run_query(Workspace& ws, const Net* net, int prec, const Medium* M, LightSt
                hipStream_t s)
 {
     if (!net) fail(NIS_E_STATE, "no weights set");
-    if (Pm.channels != 1 && (Pm.channels != 3 || o.y || o.desc)) fail(NIS_E_INVALID, "bad channel count");
-    ensure_sweep(M, ls, s);
-    refresh_tables(M, ls, Pm.phase, Pm.volume, s);
-    const PackedNet& P = net->packed[prec];
     const int64_t chunk = n < kChunk ? n : kChunk;
     ws.desc.reserve((size_t)chunk * kDescPad * desc_elem_bytes(prec), "descriptor workspace");
     ws.f0.reserve((size_t)chunk * sizeof(float), "single-scatter workspace");
     if (prec == kPrecFP8) ws.rowmax.reserve((size_t)chunk * sizeof(float), "descriptor row maxima");
+    WsView w;
+    w.desc = ws.desc.p;
+    w.f0 = ws.f0.as<float>();
+    w.rowmax = prec == kPrecFP8 ? ws.rowmax.as<float>() : nullptr;
+    w.chunk = chunk;
+    run_query_in(w, net, prec, M, ls, Pm, d_pts, d_dirs, n, d_count, o, s, true);
+}
+
+void run_query_in(const WsView& ws, const Net* net, int prec, const Medium* M, LightState* ls, const Params& Pm,
+                  const float* d_pts, const float* d_dirs, int64_t n, const int* d_count, const QueryOut& o,
+                  hipStream_t s, bool may_alloc)
+{
+    if (!net) fail(NIS_E_STATE, "no weights set");
+    if (Pm.channels != 1 && (Pm.channels != 3 || o.y || o.desc)) fail(NIS_E_INVALID, "bad channel count");
+    if (ws.chunk <= 0 || !ws.desc || !ws.f0 || (prec == kPrecFP8 && !ws.rowmax)) fail(NIS_E_INTERNAL, "no scratch");
+    ensure_sweep(M, ls, s);
+    refresh_tables(M, ls, Pm.phase, Pm.volume, s, may_alloc);
+    const PackedNet& P = net->packed[prec];
+    const int64_t chunk = ws.chunk;
     MediumView mv = make_view(M, ls, Pm, net);
     for (int64_t p0 = 0; p0 < n; p0 += chunk) {
         const int64_t cn = (n - p0) < chunk ? (n - p0) : chunk;
@@ -591,9 +674,9 @@ void run_query(Workspace& ws, const Net* net, int prec, const Medium* M, LightSt
             fa.w2t[gi] = P.w2t[gi].p;
             fa.cb[gi] = P.cb[gi].as<float>();
         }
-        fa.desc = ws.desc.p;
-        fa.f0 = o.f0 ? o.f0 + p0 : ws.f0.as<float>();
-        fa.rowmax = prec == kPrecFP8 ? ws.rowmax.as<float>() : nullptr;
+        fa.desc = ws.desc;
+        fa.f0 = o.f0 ? o.f0 + p0 : ws.f0;
+        fa.rowmax = prec == kPrecFP8 ? ws.rowmax : nullptr;
         auto off = [&](float* base, int64_t per) { return base ? base + p0 * per : nullptr; };
         fa.dbg_tbar = off(o.tbar, kLayers * kSites);
         fa.dbg_rho = off(o.rho, kLayers * kSites);
@@ -603,13 +686,13 @@ void run_query(Workspace& ws, const Net* net, int prec, const Medium* M, LightSt
         timed("features", s, [&] { return launch_features(prec, fa, s); });
         if (o.desc) {
             size_t eb = desc_elem_bytes(prec) * kDescPad;
-            hip_check(hipMemcpyAsync((char*)o.desc + p0 * eb, ws.desc.p, cn * eb, hipMemcpyDeviceToDevice, s),
+            hip_check(hipMemcpyAsync((char*)o.desc + p0 * eb, ws.desc, cn * eb, hipMemcpyDeviceToDevice, s),
                       "descriptor copy");
         }
         if (!o.run_mlp) continue;
         MlpArgs ma;
         std::memset(&ma, 0, sizeof(ma));
-        ma.x = ws.desc.p;
+        ma.x = ws.desc;
         ma.npts = cn;
         ma.count = d_count;
         ma.count_off = p0;
@@ -632,7 +715,7 @@ void run_query(Workspace& ws, const Net* net, int prec, const Medium* M, LightSt
             const float eta = Pm.channels == 3 ? Pm.rgb[c] : Pm.albedo;
             if (c > 0)
                 timed("albedo_entry", s,
-                      [&] { return launch_albedo_entry(prec, ws.desc.p, cn, d_count, p0, eta, s); });
+                      [&] { return launch_albedo_entry(prec, ws.desc, cn, d_count, p0, eta, s); });
             ma.out = o.radiance ? o.radiance + p0 * Pm.channels + c : nullptr;
             ma.y_out = o.y && c == 0 ? o.y + p0 : nullptr;
             ma.albedo_gamma = (float)std::pow((double)eta, (double)net->gamma);
@@ -832,6 +915,7 @@ int32_t nis_create(int32_t hip_device, nis_ctx** out)
         hip_check(hipGetDeviceCount(&count), "hipGetDeviceCount");
         if (hip_device < 0 || hip_device >= count) fail(NIS_E_INVALID, "no such HIP device");
         hip_check(hipSetDevice(hip_device), "hipSetDevice");
+        scratch_setup(hip_device);
         nis_ctx* ctx = new nis_ctx();
         ctx->device = hip_device;
         hipError_t e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
@@ -962,6 +1046,8 @@ int32_t nis_set_volume_phase(nis_ctx* ctx, int32_t medium, int32_t enable)
         std::lock_guard<std::mutex> lk(ctx->mu);
         Medium* M = get_medium(ctx, medium);
         if (enable != 0 && enable != 1) fail(NIS_E_INVALID, "enable must be 0 or 1");
+        if (enable == 1 && M->light.valid)
+            M->light.vtab.reserve((size_t)kSites * kVBins * sizeof(float), "volume phase tables");
         M->volume_phase = enable == 1;
     });
 }
@@ -1109,6 +1195,27 @@ int32_t nis_query_device(nis_ctx* ctx, int32_t medium, const float* d_points, co
         o.radiance = d_out;
         run_query(ctx->ws, ctx->net, ctx->precision, M, &M->light, grey_params(M), d_points, d_dirs, n, nullptr,
                   o, s);
+    });
+}
+
+int32_t nis_query_device_noalloc(nis_ctx* ctx, int32_t medium, const float* d_points, const float* d_dirs,
+                                 int64_t n, float* d_out, void* hip_stream)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (!d_points || !d_dirs || !d_out || n <= 0) fail(NIS_E_INVALID, "bad query arguments");
+        if (n > NIS_NOALLOC_MAX_POINTS)
+            fail(NIS_E_INVALID, "the allocation-free query takes at most " + std::to_string(NIS_NOALLOC_MAX_POINTS) +
+                                    " points per call");
+        Medium* M = get_medium(ctx, medium);
+        const Params P = grey_params(M);
+        if (!M->light.valid) fail(NIS_E_STATE, "no light set for this medium");
+        const WsView w = scratch_view(ctx->device, ctx->precision, n);
+        StreamUse su(ctx, (hipStream_t)hip_stream);
+        QueryOut o;
+        o.radiance = d_out;
+        run_query_in(w, ctx->net, ctx->precision, M, &M->light, P, d_points, d_dirs, n, nullptr, o, su.s, false);
     });
 }
 

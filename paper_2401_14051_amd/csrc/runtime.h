@@ -218,11 +218,26 @@ struct QueryOut {
     bool run_mlp = true;
 };
 
+// Device addresses of the scratch one pass of the query uses: the descriptor
+// rows [chunk][kDescPad], the single-scatter terms [chunk] and (FP8) the
+// descriptor row maxima [chunk].
+struct WsView {
+    void* desc = nullptr;
+    float* f0 = nullptr;
+    float* rowmax = nullptr;
+    int64_t chunk = 0;   // points per pass
+};
+
 // Sweep if stale, refresh the site tables, then features and backbone over
 // n points (or min(n, *d_count) when d_count is given), in chunks.
 void run_query(Workspace& ws, const Net* net, int prec, const Medium* M, LightState* ls, const Params& P,
                const float* d_pts, const float* d_dirs, int64_t n, const int* d_count, const QueryOut& o,
                hipStream_t s);
+// The same on caller-provided scratch; allocates nothing (fails with
+// NIS_E_STATE where the light's tables would have to be allocated first).
+void run_query_in(const WsView& w, const Net* net, int prec, const Medium* M, LightState* ls, const Params& P,
+                  const float* d_pts, const float* d_dirs, int64_t n, const int* d_count, const QueryOut& o,
+                  hipStream_t s, bool may_alloc);
 
 // Validates a camera and converts it to kernel arguments.
 CamArgs camera_args(const nis_camera* cam);

@@ -30,6 +30,7 @@ NIS_E_UNSUPPORTED = -5
 NIS_E_INTERNAL = -6
 NIS_FP32, NIS_BF16, NIS_FP8 = 0, 1, 2
 NIS_EAGER = 1
+NOALLOC_MAX_POINTS = 8192   # NIS_NOALLOC_MAX_POINTS
 NIS_QUEUED, NIS_RUNNING = 1, 2
 LAYERS, SITES, STATS, DESCRIPTOR = 12, 225, 8, 1057
 PRECISIONS = {"fp32": NIS_FP32, "bf16": NIS_BF16, "fp8": NIS_FP8}
@@ -81,6 +82,7 @@ _SIGNATURES = {
     "nis_set_precision": [_vp, _i32],
     "nis_query": [_vp, _i32, _vp, _vp, _i64, _vp],
     "nis_query_device": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
+    "nis_query_device_noalloc": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
     "nis_query_rgb": [_vp, _i32, _vp, _vp, _i64, _vp],
     "nis_query_rgb_device": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
     "nis_medium_info": [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i64)],
@@ -298,6 +300,16 @@ class Context:
             stream = torch.cuda.current_stream(points.device).cuda_stream
         _check(_lib.nis_query_device(self.h, medium, _dptr(points), _dptr(dirs), points.shape[0],
                                      _dptr(out), _vp(stream)))
+
+    def query_device_noalloc(self, medium, points, dirs, out, stream=None):
+        """As query_device through the entry point that allocates nothing (its
+        scratch is the library's fixed per-GPU array; at most
+        NOALLOC_MAX_POINTS points)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(points.device).cuda_stream
+        _check(_lib.nis_query_device_noalloc(self.h, medium, _dptr(points), _dptr(dirs), points.shape[0],
+                                             _dptr(out), _vp(stream)))
 
     def query_rgb(self, medium, points, dirs):
         """As query, one radiance per colour channel: host [n, 3]."""

@@ -1,0 +1,88 @@
+"""The allocation-free query (nis_query_device_noalloc) against
+nis_query_device, through the C ABI: the same kernels on the library's fixed
+per-GPU scratch array instead of the context's workspace, so the radiance must
+be equal bit for bit.  Two calls in a row, the second with fewer points (the
+scratch keeps the first call's contents), at every precision, on a fresh
+context whose first query is the allocation-free one; FP32 also against the
+FP64 oracle (rel-L2 <= 1e-4); the point limit and the state errors."""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import Scene, camera, configs, f32, medium, rel_l2, weights
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+@pytest.fixture(scope="module")
+def nis_mod():
+    from paper_2401_14051_amd import nis
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return nis
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_noalloc_query_equals_query_device(nis_mod, prec):
+    print("noalloc prec=%s" % prec, flush=True)
+    ctx = nis_mod.Context(0)
+    try:
+        rho = medium.fbm_cloud(32, seed=0)
+        params = weights.he_init(128, 6, seed=1)
+        s = Scene(ctx, rho, (0.3, 0.9, 0.3))
+        ctx.set_weights(params)
+        ctx.set_precision(prec)
+        stream = torch.cuda.current_stream().cuda_stream
+        # the largest batch first, then a smaller one (ragged, not a tile multiple)
+        for n, seed in ((nis_mod.NOALLOC_MAX_POINTS, 3), (1237, 4)):
+            print("  n=%d" % n, flush=True)
+            pts, dirs = camera.random_points(n, seed=seed, lo=-0.2, hi=1.2)
+            tp, td = dev(pts), dev(dirs)
+            got = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
+            ctx.query_device_noalloc(s.mid, tp, td, got, stream)
+            ref = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
+            ctx.query_device(s.mid, tp, td, ref, stream)
+            torch.cuda.synchronize()
+            g, r = got.cpu().numpy(), ref.cpu().numpy()
+            assert np.all(np.isfinite(g))
+            np.testing.assert_array_equal(g, r)
+            if prec == "fp32" and n < 2000:
+                o = s.oracle_query(params, pts, dirs)["L"]
+                assert rel_l2(g, o) <= 1e-4
+        s.close()
+    finally:
+        ctx.close()
+
+
+def test_noalloc_query_limits_and_state(nis_mod):
+    ctx = nis_mod.Context(0)
+    try:
+        rho = medium.fbm_cloud(8, seed=1)
+        mid = ctx.load_medium(rho, 8.0, 0.99, 0.85)
+        ctx.set_weights(weights.he_init(32, 3, seed=1))
+        n = nis_mod.NOALLOC_MAX_POINTS + 1
+        pts, dirs = camera.random_points(n, seed=2, lo=0.0, hi=1.0)
+        tp, td = dev(pts), dev(dirs)
+        out = torch.empty(n, dtype=torch.float32, device="cuda")
+        # no light yet
+        with pytest.raises(nis_mod.NisError) as e:
+            ctx.query_device_noalloc(mid, tp[:10], td[:10], out[:10])
+        assert e.value.code == nis_mod.NIS_E_STATE
+        ctx.set_light(mid, (0.3, 0.9, 0.3), 1.0)
+        with pytest.raises(nis_mod.NisError) as e:
+            ctx.query_device_noalloc(mid, tp, td, out)
+        assert e.value.code == nis_mod.NIS_E_INVALID
+        assert "at most" in nis_mod.nis_last_error()
+        # volume phases switched on after the light: the call still allocates nothing
+        ctx.set_volume_phase(mid, True)
+        ctx.query_device_noalloc(mid, tp[:100], td[:100], out[:100])
+        ref = torch.empty(100, dtype=torch.float32, device="cuda")
+        ctx.query_device(mid, tp[:100], td[:100], ref)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out[:100].cpu().numpy(), ref.cpu().numpy())
+    finally:
+        ctx.close()
