@@ -60,9 +60,11 @@ typedef struct nis_ctx nis_ctx;
 /* network precisions (nis_set_precision) */
 #define NIS_FP32 0   /* every GEMM in float32 (MFMA f32), float32 descriptor */
 #define NIS_BF16 1   /* CNN and backbone GEMMs in bfloat16 x bfloat16 -> float32 */
-#define NIS_FP8 2    /* backbone GEMMs in FP8-E4M3 (OCP) x E4M3 -> float32, with one
-                        weight scale per output column and one activation scale per
-                        shading point and layer; CNN and descriptor in BF16 */
+#define NIS_FP8 2    /* backbone GEMMs in FP8-E4M3 (OCP) x E4M3 -> float32: one static
+                        activation scale per layer input (from the weight blob or
+                        nis_calibrate_fp8), one power-of-two weight scale per output
+                        channel (the MFMA's E8M0 block scale); descriptor stored as
+                        E4M3 codes; CNN in BF16 */
 
 /* nis_set_light flags */
 #define NIS_EAGER 1  /* run the transmittance sweep now rather than at the next query */
@@ -171,18 +173,35 @@ int32_t nis_set_light(nis_ctx *ctx, int32_t medium, const float dir[3], float ra
  *     w2[16][8][3][3][3], b2[16], s1[4][16], c1[4], s2[16][4], c2[16];
  *   then for i = 0..n_linear-1: A_i[out][in], beta_i[out] with in = 1057 for
  *     i = 0 and width otherwise, out = width except 1 for the last layer;
- *   then, if has_fp8_scales, float32 activation scales: conv1 input, conv2
- *     input, and one per backbone layer input (2 + n_linear values).
+ *   then, if has_fp8_scales, float32 activation scales (x = E4M3 code *
+ *     scale, each > 0): conv1 input, conv2 input, and one per backbone layer
+ *     input (2 + n_linear values).
  * Errors: NIS_E_INVALID on a malformed blob, NIS_E_NOMEM, NIS_E_DEVICE.
  */
 int32_t nis_set_weights(nis_ctx *ctx, const void *blob, size_t nbytes);
 
-/* NIS_FP32 (default), NIS_BF16 or NIS_FP8.  The FP8 path needs no calibration:
- * weight scales (column absmax / 448) are fixed at nis_set_weights and each
- * point's activation scale is its own row absmax, so results do not depend on
- * the batch.  The blob's optional fp8 scale block is accepted and unused.
- * Errors: NIS_E_INVALID for an unknown precision. */
+/* NIS_FP32 (default), NIS_BF16 or NIS_FP8.  FP8 needs the activation scales
+ * of the weight blob's fp8 block (x = code * scale, entries > 0) or of
+ * nis_calibrate_fp8; without them NIS_FP8 is NIS_E_UNSUPPORTED (here, and for
+ * queries if weights without scales replace them later).  The scales are
+ * static, so a point's result does not depend on its batch.  The blob's two
+ * CNN-input scales are kept and unused (the CNN runs in BF16).
+ * Errors: NIS_E_INVALID for an unknown precision, NIS_E_UNSUPPORTED. */
 int32_t nis_set_precision(nis_ctx *ctx, int32_t precision);
+
+/*
+ * nis_calibrate_fp8 -- the static activation scales of the FP8 backbone
+ * (per-layer absmax scaling of E4M3, Sec. III.C.2's network in FP8): runs the
+ * FP32 path over n representative points (device arrays as nis_query_device)
+ * of `medium` under its light, records the largest |input| of every backbone
+ * layer (the descriptor, then each hidden activation), and sets each layer
+ * input's scale to 2 max|x| / 448 (codes saturate at 448, so a factor of two
+ * above the calibration range is kept).  Replaces the blob's scales and
+ * repacks the FP8 weights.  Synchronous on `hip_stream`.
+ * Errors: NIS_E_INVALID, NIS_E_STATE (no weights, no light, server running).
+ */
+int32_t nis_calibrate_fp8(nis_ctx *ctx, int32_t medium, const float *d_points,
+                          const float *d_view_dirs, int64_t n, void *hip_stream);
 
 /*
  * nis_query -- in-scattered radiance at shading points (Sec. III.C.2 output
@@ -226,8 +245,8 @@ int32_t nis_query_device(nis_ctx *ctx, int32_t medium, const float *d_points,
  * nis_query_device_noalloc -- nis_query_device for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc): the same computation and the same result,
- * bit for bit, but the call allocates nothing.  Its scratch (descriptor rows,
- * single-scatter terms and row maxima of one pass) is a fixed array of
+ * bit for bit, but the call allocates nothing.  Its scratch (descriptor rows and
+ * single-scatter terms of one pass) is a fixed array of
  * device memory inside the library, about 36 MB, of which each GPU the library
  * runs on holds its own copy until the process ends; no part of it has to
  * start at zero.  Every call on one GPU shares that GPU's copy, which keeps

@@ -211,7 +211,16 @@ template <> __device__ __forceinline__ void store_windows<__bf16>(__bf16* row, c
 // element offset in a point's lattice of tap-row tr = dz * 3 + dy
 __device__ __forceinline__ int taprow_off(int tr) { return ((tr / 3) * 5 + tr % 3) * kLatRow; }
 
-template <int PREC, bool DBG>
+// E4M3 code of x (saturated at +-448), rounded to nearest even
+__device__ __forceinline__ uint8_t fp8_code(float x)
+{
+    x = __builtin_amdgcn_fmed3f(x, -448.f, 448.f);
+    return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false) & 0xff);
+}
+
+// F8: the descriptor is stored as E4M3 codes of the entries divided by the
+// backbone's first input scale (the CNN itself runs in BF16).
+template <int PREC, bool DBG, bool F8>
 __global__ void __launch_bounds__(64, 3)
 k_features(FeatArgs A)
 {
@@ -372,12 +381,12 @@ k_features(FeatArgs A)
     }
 
     E* desc = reinterpret_cast<E*>(A.desc);
+    uint8_t* desc8 = reinterpret_cast<uint8_t*>(A.desc);
 
 
     // conv1 A fragments of the current weight group (reloaded when it changes)
     constexpr int KC1 = PREC == kPrecFP32 ? 18 : 3;
     typename M::frag aw[KC1];
-    float row_absmax = 0.f;   // lane (point, o): max |stored entry| of its point so far
     for (int k = 0; k < kLayers; k++) {
         const int m = k < mv.levels - 1 ? k : mv.levels - 1;
         const Level lv = mv.lev[m];
@@ -821,61 +830,78 @@ k_features(FeatArgs A)
             // sigmoid with the hardware exponential and reciprocal (each about 1 ulp)
             const float gate = __builtin_amdgcn_rcpf(1.f + __expf(-s));
             // stage the 88 entries of the layer in the (now free) conv1 output
-            E* stage = &y1[pt][0][0];
-            const bool want_max = A.rowmax != nullptr;   // the FP8 backbone's row scales
-            float lmax = 0.f;
+            if constexpr (F8) {
+                uint8_t* stage = reinterpret_cast<uint8_t*>(&y1[pt][0][0]);
+                const float inv = A.desc_inv_scale;
 #pragma unroll
-            for (int z = 0; z < 5; z++) {
-                const E qz = M::cvt(gate * hv[z]);
-                stage[o * 5 + z] = qz;
-                if (want_max) lmax = fmaxf(lmax, fabsf((float)qz));
-            }
-            if (o < kStats) {
-                const E qs = M::cvt(pstat[pt][o]);
-                stage[kFeat + o] = qs;
-                if (want_max) lmax = fmaxf(lmax, fabsf((float)qs));
+                for (int z = 0; z < 5; z++) stage[o * 5 + z] = fp8_code(gate * hv[z] * inv);
+                if (o < kStats) stage[kFeat + o] = fp8_code(pstat[pt][o] * inv);
+            } else {
+                E* stage = &y1[pt][0][0];
+#pragma unroll
+                for (int z = 0; z < 5; z++) stage[o * 5 + z] = M::cvt(gate * hv[z]);
+                if (o < kStats) stage[kFeat + o] = M::cvt(pstat[pt][o]);
             }
             if (DBG && o < kStats && tile0 + pt < npts)
                 A.dbg_stats[((tile0 + pt) * kLayers + k) * kStats + o] = pstat[pt][o];
-            // running maximum |entry| of the point's stored descriptor
-            if (want_max) {
-                for (int sft = 1; sft < 16; sft <<= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, sft));
-                row_absmax = fmaxf(row_absmax, lmax);
-            }
             __syncthreads();
-            // 16-byte stores of the staged rows (88 entries per point)
-            constexpr int kVec = 16 / sizeof(E), kChunks = kPerLayer / kVec;
-            for (int e = lane; e < kTP * kChunks; e += 64) {
-                const int tq = e / kChunks, ch = e % kChunks;
-                const int64_t pp = tile0 + tq;
-                if (pp < npts)
-                    *reinterpret_cast<uint4*>(desc + pp * kDescPad + k * kPerLayer + ch * kVec) =
-                        *reinterpret_cast<const uint4*>(&y1[tq][0][0] + ch * kVec);
+            if constexpr (F8) {
+                // 8-byte stores of the staged codes (88 per point)
+                constexpr int kChunks = kPerLayer / 8;
+                for (int e = lane; e < kTP * kChunks; e += 64) {
+                    const int tq = e / kChunks, ch = e % kChunks;
+                    const int64_t pp = tile0 + tq;
+                    if (pp < npts)
+                        *reinterpret_cast<uint2*>(desc8 + pp * kDescF8 + k * kPerLayer + ch * 8) =
+                            *reinterpret_cast<const uint2*>(reinterpret_cast<const uint8_t*>(&y1[tq][0][0]) + ch * 8);
+                }
+            } else {
+                // 16-byte stores of the staged rows (88 entries per point)
+                constexpr int kVec = 16 / sizeof(E), kChunks = kPerLayer / kVec;
+                for (int e = lane; e < kTP * kChunks; e += 64) {
+                    const int tq = e / kChunks, ch = e % kChunks;
+                    const int64_t pp = tile0 + tq;
+                    if (pp < npts)
+                        *reinterpret_cast<uint4*>(desc + pp * kDescPad + k * kPerLayer + ch * kVec) =
+                            *reinterpret_cast<const uint4*>(&y1[tq][0][0] + ch * kVec);
+                }
             }
         }
     }
     // albedo entry and zero padding
-    for (int e = lane; e < kTP * (kDescPad - kDesc + 1); e += 64) {
-        const int tq = e / (kDescPad - kDesc + 1), f = kDesc - 1 + e % (kDescPad - kDesc + 1);
-        const int64_t pp = tile0 + tq;
-        if (pp < npts) desc[pp * kDescPad + f] = M::cvt(f == kDesc - 1 ? mv.albedo : 0.f);
+    if constexpr (F8) {
+        constexpr int kTail = kDescF8 - kDesc + 1;
+        for (int e = lane; e < kTP * kTail; e += 64) {
+            const int tq = e / kTail, f = kDesc - 1 + e % kTail;
+            const int64_t pp = tile0 + tq;
+            if (pp < npts) desc8[pp * kDescF8 + f] = f == kDesc - 1 ? fp8_code(mv.albedo * A.desc_inv_scale) : 0;
+        }
+    } else {
+        for (int e = lane; e < kTP * (kDescPad - kDesc + 1); e += 64) {
+            const int tq = e / (kDescPad - kDesc + 1), f = kDesc - 1 + e % (kDescPad - kDesc + 1);
+            const int64_t pp = tile0 + tq;
+            if (pp < npts) desc[pp * kDescPad + f] = M::cvt(f == kDesc - 1 ? mv.albedo : 0.f);
+        }
     }
-    // the largest |entry| of the features alone: the FP8 backbone adds the
-    // albedo entry, which a colour query rewrites per channel
-    if (A.rowmax && lr == 0 && tile0 + lg < npts) A.rowmax[tile0 + lg] = row_absmax;
 }
 
 // Rewrites the albedo entry of n descriptor rows: the channels of a coloured
-// albedo share every other entry.
+// albedo share every other entry.  eta is the entry's value as stored (for
+// the FP8 descriptor, already divided by its scale).
 // Rows beyond a device count (count[0] - count_off, when count is given) are
 // left alone, as the backbone does not read them.
 template <int PREC>
 __global__ void k_albedo_entry(void* desc, int64_t n, const int* count, int64_t count_off, float eta)
 {
-    typedef typename Mfma<PREC>::elem E;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nv = count ? (int64_t)*count - count_off : n;
-    if (i < n && i < nv) reinterpret_cast<E*>(desc)[i * kDescPad + kDesc - 1] = Mfma<PREC>::cvt(eta);
+    if (!(i < n && i < nv)) return;
+    if constexpr (PREC == kPrecFP8) {
+        reinterpret_cast<uint8_t*>(desc)[i * kDescF8 + kDesc - 1] = fp8_code(eta);
+    } else {
+        typedef typename Mfma<PREC>::elem E;
+        reinterpret_cast<E*>(desc)[i * kDescPad + kDesc - 1] = Mfma<PREC>::cvt(eta);
+    }
 }
 
 hipError_t launch_albedo_entry(int prec, void* desc, int64_t n, const int* count, int64_t count_off, float eta,
@@ -884,7 +910,10 @@ hipError_t launch_albedo_entry(int prec, void* desc, int64_t n, const int* count
     if (n <= 0) return hipSuccess;
     const int64_t blocks = (n + 255) / 256;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    if (prec == kPrecBF16 || prec == kPrecFP8)
+    if (prec == kPrecFP8)
+        hipLaunchKernelGGL(k_albedo_entry<kPrecFP8>, dim3((int)blocks), dim3(256), 0, s, desc, n, count, count_off,
+                           eta);
+    else if (prec == kPrecBF16)
         hipLaunchKernelGGL(k_albedo_entry<kPrecBF16>, dim3((int)blocks), dim3(256), 0, s, desc, n, count, count_off,
                            eta);
     else
@@ -893,24 +922,32 @@ hipError_t launch_albedo_entry(int prec, void* desc, int64_t n, const int* count
     return hipGetLastError();
 }
 
-// Widen a descriptor of the given precision to float32 [n][1057].
+// Widen a descriptor of the given precision to float32 [n][1057] (FP8: the
+// codes times the descriptor's scale).
 template <int PREC>
-__global__ void k_desc_to_f32(const void* src, float* dst, int64_t n)
+__global__ void k_desc_to_f32(const void* src, float* dst, int64_t n, float scale)
 {
-    typedef typename Mfma<PREC>::elem E;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n * kDesc) return;
     int64_t row = i / kDesc, col = i % kDesc;
-    dst[i] = (float)reinterpret_cast<const E*>(src)[row * kDescPad + col];
+    if constexpr (PREC == kPrecFP8) {
+        const int c = reinterpret_cast<const uint8_t*>(src)[row * kDescF8 + col];
+        dst[i] = __builtin_amdgcn_cvt_f32_fp8(c, 0) * scale;
+    } else {
+        typedef typename Mfma<PREC>::elem E;
+        dst[i] = (float)reinterpret_cast<const E*>(src)[row * kDescPad + col];
+    }
 }
 
-hipError_t launch_desc_to_f32(int prec, const void* src, float* dst, int64_t n, hipStream_t s)
+hipError_t launch_desc_to_f32(int prec, const void* src, float* dst, int64_t n, float scale, hipStream_t s)
 {
     int blocks = (int)((n * kDesc + 255) / 256);
-    if (prec == kPrecBF16 || prec == kPrecFP8)
-        hipLaunchKernelGGL(k_desc_to_f32<kPrecBF16>, dim3(blocks), dim3(256), 0, s, src, dst, n);
+    if (prec == kPrecFP8)
+        hipLaunchKernelGGL(k_desc_to_f32<kPrecFP8>, dim3(blocks), dim3(256), 0, s, src, dst, n, scale);
+    else if (prec == kPrecBF16)
+        hipLaunchKernelGGL(k_desc_to_f32<kPrecBF16>, dim3(blocks), dim3(256), 0, s, src, dst, n, scale);
     else
-        hipLaunchKernelGGL(k_desc_to_f32<kPrecFP32>, dim3(blocks), dim3(256), 0, s, src, dst, n);
+        hipLaunchKernelGGL(k_desc_to_f32<kPrecFP32>, dim3(blocks), dim3(256), 0, s, src, dst, n, scale);
     return hipGetLastError();
 }
 
@@ -922,13 +959,16 @@ hipError_t launch_features(int prec, const FeatArgs& a, hipStream_t s)
     const bool dbg = a.dbg_tbar || a.dbg_rho || a.dbg_phi || a.dbg_stats || a.dbg_tp;
     if (dbg && !(a.dbg_tbar && a.dbg_rho && a.dbg_phi && a.dbg_stats && a.dbg_tp))
         return hipErrorInvalidValue;   // the debug variant writes every stage output
-    // the FP8 path runs the CNN and stores the descriptor in BF16
-    if (prec == kPrecBF16 || prec == kPrecFP8) {
-        if (dbg) hipLaunchKernelGGL((k_features<kPrecBF16, true>), dim3((int)blocks), dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_features<kPrecBF16, false>), dim3((int)blocks), dim3(64), 0, s, a);
+    // the FP8 path runs the CNN in BF16 and stores the descriptor as E4M3 codes
+    if (prec == kPrecFP8) {
+        if (dbg) hipLaunchKernelGGL((k_features<kPrecBF16, true, true>), dim3((int)blocks), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_features<kPrecBF16, false, true>), dim3((int)blocks), dim3(64), 0, s, a);
+    } else if (prec == kPrecBF16) {
+        if (dbg) hipLaunchKernelGGL((k_features<kPrecBF16, true, false>), dim3((int)blocks), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_features<kPrecBF16, false, false>), dim3((int)blocks), dim3(64), 0, s, a);
     } else {
-        if (dbg) hipLaunchKernelGGL((k_features<kPrecFP32, true>), dim3((int)blocks), dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_features<kPrecFP32, false>), dim3((int)blocks), dim3(64), 0, s, a);
+        if (dbg) hipLaunchKernelGGL((k_features<kPrecFP32, true, false>), dim3((int)blocks), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_features<kPrecFP32, false, false>), dim3((int)blocks), dim3(64), 0, s, a);
     }
     return hipGetLastError();
 }

@@ -13,9 +13,10 @@
 // with xor-shift-multiply rounds (30, 0xBF58476D1CE4E5B9; 27,
 // 0x94D049BB133111EB; 31), h = mix(mix(mix(seed) ^ pixel) ^ draw),
 // u = (h >> 11) * 2^-53; draw 2i is the i-th flight, 2i+1 its acceptance.
-// Geometry runs in double precision.
-#include <hipcub/hipcub.hpp>
-
+// Geometry runs in double precision.  The hit flags are compacted through an
+// exclusive prefix sum: wavefront prefix sums within blocks of 1024 flags,
+// then one workgroup scans the block totals (and writes the hit count), and
+// the compaction adds each block's prefix.
 #include "launch_args.h"
 
 namespace nis {
@@ -131,25 +132,85 @@ k_raygen(CamArgs C, const float* __restrict__ rho, int n, double sigma_t, double
     }
 }
 
+constexpr int kScanBlock = 1024;   // flags per workgroup of the local scan (256 lanes x 4)
+
+// inclusive prefix sum of v over the 64 lanes of a wavefront
+__device__ __forceinline__ int wave_inclusive_scan(int v, int lane)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(v, o);
+        if (lane >= o) v += y;
+    }
+    return v;
+}
+
+// Exclusive prefix sum of the flags within each block of kScanBlock slots,
+// and each block's total in part[block].
 __global__ void __launch_bounds__(256)
-k_compact(const int* __restrict__ flag, const int* __restrict__ offset, const float* __restrict__ pts,
-          const float* __restrict__ dirs, int w, int h, int band, float* __restrict__ cpts,
-          float* __restrict__ cdirs, int* __restrict__ cpix)
+k_scan_local(const int* __restrict__ flag, int64_t n, int* __restrict__ offset, int* __restrict__ part)
+{
+    __shared__ int wsum[4];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + 4 * t;
+    int v[4];
+    if (base + 3 < n) {
+        const int4 f = *reinterpret_cast<const int4*>(flag + base);
+        v[0] = f.x, v[1] = f.y, v[2] = f.z, v[3] = f.w;
+    } else {
+        for (int e = 0; e < 4; e++) v[e] = base + e < n ? flag[base + e] : 0;
+    }
+    const int s = v[0] + v[1] + v[2] + v[3];
+    const int inc = wave_inclusive_scan(s, lane);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int wpre = 0;
+    for (int i = 0; i < w; i++) wpre += wsum[i];
+    int ex = wpre + inc - s;
+    for (int e = 0; e < 4; e++) {
+        if (base + e < n) offset[base + e] = ex;
+        ex += v[e];
+    }
+    if (t == 255) part[blockIdx.x] = wpre + inc;
+}
+
+// Exclusive prefix sum of the nb block totals in place (one workgroup, each
+// lane a contiguous run of them), and the total: the frame's hit count.
+__global__ void __launch_bounds__(1024) k_scan_parts(int* __restrict__ part, int nb, int* __restrict__ count)
+{
+    __shared__ int wsum[16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int per = (nb + 1023) / 1024;
+    const int b0 = min(t * per, nb), b1 = min(b0 + per, nb);
+    int s = 0;
+    for (int b = b0; b < b1; b++) s += part[b];
+    const int inc = wave_inclusive_scan(s, lane);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int wpre = 0;
+    for (int i = 0; i < w; i++) wpre += wsum[i];
+    int ex = wpre + inc - s;
+    for (int b = b0; b < b1; b++) {
+        const int v = part[b];
+        part[b] = ex;
+        ex += v;
+    }
+    if (t == 1023) *count = wpre + inc;
+}
+
+__global__ void __launch_bounds__(256)
+k_compact(const int* __restrict__ flag, const int* __restrict__ offset, const int* __restrict__ part,
+          const float* __restrict__ pts, const float* __restrict__ dirs, int w, int h, int band,
+          float* __restrict__ cpts, float* __restrict__ cdirs, int* __restrict__ cpix)
 {
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= (int64_t)w * h || !flag[slot]) return;
-    const int64_t o = offset[slot];
+    const int64_t o = (int64_t)offset[slot] + part[slot / kScanBlock];
     for (int a = 0; a < 3; a++) {
         cpts[3 * o + a] = pts[3 * slot + a];
         cdirs[3 * o + a] = dirs[3 * slot + a];
     }
     cpix[o] = (int)slot_pixel(slot, w, h, band);
-}
-
-__global__ void k_count(const int* __restrict__ flag, const int* __restrict__ offset, int64_t npix,
-                        int* __restrict__ count)
-{
-    if (blockIdx.x == 0 && threadIdx.x == 0) *count = npix > 0 ? offset[npix - 1] + flag[npix - 1] : 0;
 }
 
 __global__ void __launch_bounds__(256) k_fill(float* __restrict__ p, int64_t n, float v)
@@ -179,10 +240,11 @@ k_scatter_image_rgb(const int* __restrict__ cpix, const float* __restrict__ L, c
     }
 }
 
+// scan storage: one total per block of kScanBlock flags
 hipError_t frame_scan_bytes(int64_t npix, size_t* bytes)
 {
-    *bytes = 0;
-    return hipcub::DeviceScan::ExclusiveSum(nullptr, *bytes, (const int*)nullptr, (int*)nullptr, (int)npix);
+    *bytes = (size_t)((npix + kScanBlock - 1) / kScanBlock + 1) * sizeof(int);
+    return hipSuccess;
 }
 
 hipError_t launch_raygen(const CamArgs& C, const float* rho0, int n, double sigma_t, double majorant,
@@ -194,12 +256,15 @@ hipError_t launch_raygen(const CamArgs& C, const float* rho0, int n, double sigm
                        fb.pts, fb.dirs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    size_t bytes = fb.scan_bytes;
-    e = hipcub::DeviceScan::ExclusiveSum(fb.scan_tmp, bytes, fb.flag, fb.offset, (int)npix, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(256), 0, s, fb.flag, fb.offset, fb.pts, fb.dirs, C.width,
-                       C.height, C.band, fb.cpts, fb.cdirs, fb.cpix);
-    hipLaunchKernelGGL(k_count, dim3(1), dim3(64), 0, s, fb.flag, fb.offset, npix, fb.count);
+    const int64_t nb = (npix + kScanBlock - 1) / kScanBlock;
+    size_t need = 0;
+    frame_scan_bytes(npix, &need);
+    if (fb.scan_bytes < need || nb > 0x7fffffff) return hipErrorInvalidValue;
+    int* part = reinterpret_cast<int*>(fb.scan_tmp);
+    hipLaunchKernelGGL(k_scan_local, dim3((int)nb), dim3(256), 0, s, fb.flag, npix, fb.offset, part);
+    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(1024), 0, s, part, (int)nb, fb.count);
+    hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(256), 0, s, fb.flag, fb.offset, part, fb.pts, fb.dirs,
+                       C.width, C.height, C.band, fb.cpts, fb.cdirs, fb.cpix);
     return hipGetLastError();
 }
 

@@ -49,6 +49,13 @@ k_mlp(MlpArgs A)
     if constexpr (KH > W) {
         for (int e = lane; e < ROWS * (KH - W); e += 64) h[e / (KH - W)][W + e % (KH - W)] = M::zero();
     }
+    // calibration (FP32 only): the largest |input| of every layer, per lane,
+    // then per wave, into A.absmax with an atomic maximum on the float bits
+    const bool track = PREC == kPrecFP32 && A.absmax != nullptr;
+    auto publish = [&](float v, int li) __attribute__((always_inline)) {
+        for (int o = 1; o < 64; o <<= 1) v = fmaxf(v, __shfl_xor(v, o));
+        if (lane == 0) atomicMax(reinterpret_cast<unsigned int*>(A.absmax) + li, __float_as_uint(v));
+    };
     f32x4 acc[RT][NT];
     for (int li = 0; li + 1 < A.n_linear; li++) {
         const E* Wf = reinterpret_cast<const E*>(A.W[li]) + lane * M::KPL;
@@ -66,10 +73,17 @@ k_mlp(MlpArgs A)
                 r = r < npts ? r : npts - 1;
                 xr[rt] = x + r * kDescPad + lg * M::KPL;
             }
+            float imx = 0.f;
             for (int kc = 0; kc < KC; kc++) {
                 typename M::frag a[RT];
 #pragma unroll
                 for (int rt = 0; rt < RT; rt++) a[rt] = M::load(xr[rt] + kc * M::KS);
+                if constexpr (PREC == kPrecFP32) {
+                    if (track) {
+#pragma unroll
+                        for (int rt = 0; rt < RT; rt++) imx = fmaxf(imx, fabsf(a[rt]));
+                    }
+                }
 #pragma unroll
                 for (int ct = 0; ct < NT; ct++) {
                     typename M::frag b = M::load(Wf + (ct * KC + kc) * FRAG);
@@ -77,6 +91,7 @@ k_mlp(MlpArgs A)
                     for (int rt = 0; rt < RT; rt++) acc[rt][ct] = M::mma(a[rt], b, acc[rt][ct]);
                 }
             }
+            if (track) publish(imx, 0);
         } else {
             for (int kc = 0; kc < KC; kc++) {
                 typename M::frag a[RT];
@@ -92,15 +107,20 @@ k_mlp(MlpArgs A)
         }
         __syncthreads();   // every lane's reads of h precede the in-place overwrite
         const float* bias = A.bias[li];
+        float omx = 0.f;
 #pragma unroll
         for (int ct = 0; ct < NT; ct++) {
             const float bb = bias[ct * 16 + lr];
 #pragma unroll
             for (int rt = 0; rt < RT; rt++)
 #pragma unroll
-                for (int e = 0; e < 4; e++)
-                    h[rt * 16 + lg * 4 + e][ct * 16 + lr] = M::cvt(fmaxf(acc[rt][ct][e] + bb, 0.f));
+                for (int e = 0; e < 4; e++) {
+                    const float v = fmaxf(acc[rt][ct][e] + bb, 0.f);
+                    omx = fmaxf(omx, v);
+                    h[rt * 16 + lg * 4 + e][ct * 16 + lr] = M::cvt(v);
+                }
         }
+        if (track) publish(omx, li + 1);
         __syncthreads();
     }
     // last layer + decode, one row per lane
@@ -518,180 +538,367 @@ k_mlp_bf16(MlpArgs A)
     }
 }
 
-// FP8 backbone.  Every GEMM is E4M3 x E4M3 -> FP32 on MFMA with two scales:
-// one per output column of the weights (absmax / 448, fixed at set_weights)
-// and one per row of the activations (absmax / 448 of that point's layer
-// input, computed here), so a point's result never depends on the others in
-// its batch.  The descriptor arrives in BF16 with its row maxima and is
-// quantised while it is loaded; hidden activations are stored in LDS as E4M3.
-// A K step's weight fragments (NT x 2 KiB) are copied once per workgroup
-// from global memory straight into LDS, double buffered, and read there by
-// all four waves; each buffer is an LDS variable of its own and is named at
-// compile time, so reads of one do not wait for the copies into the other.
-template <int NT>
-__global__ void __launch_bounds__(256)
-k_mlp_fp8(MlpArgs A)
+// FP8 backbone on 32x32x64 E4M3 MFMA tiles with hardware block scales
+// (v_mfma_scale_f32_32x32x64_f8f6f4), the weights as the A operand and the
+// activations as B, in the layout of the BF16 kernel above.  Every layer
+// input x_l is stored as E4M3 codes q = x_l / s_l with one static scale s_l
+// per layer (calibrated on representative points, nis_calibrate_fp8).  The
+// host folds the scales into the packed network: layer l's weights become
+// W_l s_l / s_{l+1}, quantised per output channel with a power-of-two scale
+// that the MFMA applies (its E8M0 block scale; the activations' block scale
+// is 1), and its bias beta_l / s_{l+1}.  The accumulator then holds
+// z_l / s_{l+1}, and the next layer's codes are med3(acc, 0, 448) converted
+// to E4M3: ReLU and saturation in one instruction.  Nothing depends on the
+// other points of the batch.
+//
+// A K step is 64 inputs.  The output tile pair (2 kc, 2 kc + 1) leaves lane
+// l = p + 32 g holding 32 values of point p, which are exactly its B fragment
+// of the next layer's K step kc once that layer's K order is permuted to
+// match (slot e < 16: channel 32 (2 kc) + 8 (e/4) + 4 g + e%4 of tile 2 kc;
+// e >= 16: the same in tile 2 kc + 1, zero past the last tile).  For the
+// first layer, a stage of two K steps is the 128-byte slice of each
+// descriptor row, lane group g taking its bytes 64 g .. 64 g + 63 (32 per
+// step).  A lane's 32-byte A fragment of one tile and step is stored as two
+// 16-byte halves, the 64 lanes' first halves before their second halves, so
+// that each 16-byte LDS read is one contiguous 1 KiB row of the wave.
+constexpr int kStage8 = 2;   // K steps per weight stage (FP8)
+
+// The value unchanged, but opaque to the optimiser (it cannot be hoisted or
+// shared across the places that ask for it).
+__device__ __forceinline__ int opaque(int v)
 {
-    typedef Mfma<kPrecFP8> M;
-    constexpr int ROWS = 64, RT = 4;
-    constexpr int W = NT * 16;
-    constexpr int KH = hidden_k(kPrecFP8, W);
-    constexpr int K0 = input_k(kPrecFP8);
-    constexpr int HS = KH + 16;                  // bytes per activation row
-    constexpr int FRAG = 64 * M::KPL;
-    // scaling to 447.5 keeps every rounded code finite (the conversion does not saturate)
-    constexpr float kTarget = 447.5f;
-    __shared__ __attribute__((aligned(16))) uint8_t wq0[NT * FRAG];
-    __shared__ __attribute__((aligned(16))) uint8_t wq1[NT * FRAG];
-    __shared__ __attribute__((aligned(16))) uint8_t hbuf[kMlpWaves][ROWS][HS];
-    __shared__ float rsc[kMlpWaves][ROWS];      // dequantisation scale of each row's activations
+    asm volatile("" : "+v"(v));
+    return v;
+}
 
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
-    const int lr = lane % 16, lg = lane / 16;
-    const int64_t row0 = ((int64_t)blockIdx.x * kMlpWaves + wave) * ROWS;
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f32x16 mfma32_f8(const i32x8& a, const i32x8& b, f32x16 c, int ea)
+{
+    // formats: E4M3 for both operands; block scales: ea for A, 2^0 for B
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, ea, 0, 127);
+}
+
+// four floats -> four E4M3 codes (little-endian) after med3(x, lo, 448)
+__device__ __forceinline__ int fp8x4_clamped(float a, float b, float c, float d, float lo)
+{
+    a = __builtin_amdgcn_fmed3f(a, lo, 448.f);
+    b = __builtin_amdgcn_fmed3f(b, lo, 448.f);
+    c = __builtin_amdgcn_fmed3f(c, lo, 448.f);
+    d = __builtin_amdgcn_fmed3f(d, lo, 448.f);
+    const int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    return __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+}
+
+template <int NO, int KH, int PT, int NW>
+__global__ void __launch_bounds__(64 * NW)
+k_mlp_f8(MlpArgs A)
+{
+    constexpr int KC0 = kDescF8 / 64;           // K steps of the first layer
+    constexpr int NQ0 = KC0 / kStage8;          // its stages
+    static_assert(KC0 % kStage8 == 0, "first-layer stages must tile the descriptor");
+    constexpr int FRB = NO * 2048;              // bytes of one K step's weight fragments
+    constexpr int STB = kStage8 * FRB;          // bytes of one weight stage
+    constexpr int DTB = 4096;                   // one wave's descriptor slices of one point tile and stage
+    constexpr int ND = PT * 4;                  // descriptor copies (1 KiB) per wave and stage
+    static_assert(PT <= 2, "descriptor buffers exist for two point tiles");
+    __shared__ __attribute__((aligned(16))) uint8_t wb0[STB];
+    __shared__ __attribute__((aligned(16))) uint8_t wb1[STB];
+    __shared__ __attribute__((aligned(16))) uint8_t db00[NW][DTB];
+    __shared__ __attribute__((aligned(16))) uint8_t db01[PT > 1 ? NW : 1][DTB];
+    __shared__ __attribute__((aligned(16))) uint8_t db10[NW][DTB];
+    __shared__ __attribute__((aligned(16))) uint8_t db11[PT > 1 ? NW : 1][DTB];
+    __shared__ __attribute__((aligned(16))) uint8_t db20[NW][DTB];
+    __shared__ __attribute__((aligned(16))) uint8_t db21[PT > 1 ? NW : 1][DTB];
+
+    const int tid = threadIdx.x, lane = tid % 64, lp = lane % 32, lg = lane / 32;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
     const int64_t npts = A.count ? min(max((int64_t)*A.count - A.count_off, (int64_t)0), A.npts) : A.npts;
-    if ((int64_t)blockIdx.x * kMlpWaves * ROWS >= npts) return;
-    uint8_t(*h)[HS] = hbuf[wave];
-    float* rs = rsc[wave];
-    const __bf16* x = reinterpret_cast<const __bf16*>(A.x);
+    const int64_t wg0 = (int64_t)blockIdx.x * (NW * 32 * PT);
+    if (wg0 >= npts) return;
+    const int64_t row0 = wg0 + wave * 32 * PT;
 
-    if constexpr (KH > W) {
-        for (int e = lane; e < ROWS * (KH - W); e += 64) h[e / (KH - W)][W + e % (KH - W)] = 0;
-    }
-    // row scales of the descriptor
-    float qs[RT];
-    const __bf16* xr[RT];
-#pragma unroll
-    for (int rt = 0; rt < RT; rt++) {
-        int64_t r = row0 + rt * 16 + lr;
-        r = r < npts ? r : npts - 1;
-        xr[rt] = x + r * kDescPad + lg * M::KPL;
-        const float m = fmaxf(A.rowmax[r], A.eta_max);
-        qs[rt] = m > 0.f ? kTarget / m : 1.f;
-        if (lg == 0) rs[rt * 16 + lr] = m > 0.f ? m / kTarget : 1.f;
-    }
-    __syncthreads();
-
-    // the NT fragments of K step kc of layer li into dst: 2 NT chunks of 1 KiB,
-    // dealt to the waves in turn
-    auto copy_w = [&](uint8_t* dst, int li, int KC, int kc) __attribute__((always_inline)) {
-        const __amdgpu_buffer_rsrc_t r = rsrc(A.W[li], (int64_t)NT * KC * FRAG);
-        for (int c = wave; c < 2 * NT; c += kMlpWaves)
-            copy_lds16(r, dst + c * 1024, lane * 16, ((c >> 1) * KC + kc) * FRAG + (c & 1) * 1024);
+    auto wbuf = [&](auto bc) __attribute__((always_inline)) -> uint8_t* {
+        if constexpr (decltype(bc)::value == 0) return wb0;
+        else return wb1;
+    };
+    auto dbuf = [&](auto dc, auto pc) __attribute__((always_inline)) -> uint8_t* {
+        constexpr int d = decltype(dc)::value, p = decltype(pc)::value;
+        if constexpr (p == 0) {
+            if constexpr (d == 0) return db00[wave];
+            else if constexpr (d == 1) return db10[wave];
+            else return db20[wave];
+        } else {
+            if constexpr (d == 0) return db01[wave];
+            else if constexpr (d == 1) return db11[wave];
+            else return db21[wave];
+        }
     };
 
-    f32x4 acc[RT][NT];
-    for (int li = 0; li + 1 < A.n_linear; li++) {
-        const int K = li == 0 ? K0 : KH;
-        const int KC = K / M::KS;
+    // weight stages as in the BF16 kernel: chunks of 1 KiB, chunk c by wave c % NW
+    constexpr int NWC = (kStage8 * NO * 2 + NW - 1) / NW;
+    auto copy_w = [&](__amdgpu_buffer_rsrc_t r, int off, int nch, uint8_t* dst, int u) __attribute__((always_inline)) {
+        const int c = min(wave + NW * u, max(nch, 1) - 1);
+        copy_lds16(r, dst + c * 1024, lane * 16, off + c * 1024);
+    };
+    // descriptor slices: 128 bytes of each of 32 rows per tile and stage, row
+    // r's 16-byte segment s at slot s ^ ((r/2) % 8), as in the BF16 kernel
+    const __amdgpu_buffer_rsrc_t xr = rsrc(reinterpret_cast<const uint8_t*>(A.x) + wg0 * kDescF8,
+                                           min(npts - wg0, (int64_t)(NW * 32 * PT)) * kDescF8);
+    uint32_t doff[PT][4];
 #pragma unroll
-        for (int rt = 0; rt < RT; rt++)
+    for (int p = 0; p < PT; p++)
 #pragma unroll
-            for (int ct = 0; ct < NT; ct++) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-        // the first layer's descriptor slices of step kc, loaded one step ahead
-        bf16x8 u[RT][4];
-        auto load_u = [&](int kc) __attribute__((always_inline)) {
-            const bool valid = kc * M::KS + lg * M::KPL < kDescPad;
+        for (int i = 0; i < 4; i++) {
+            const int r = 8 * i + lane / 8, sl = lane % 8, seg = sl ^ ((r >> 1) & 7);
+            int64_t row = row0 + p * 32 + r;
+            row = row < npts ? row : npts - 1;
+            doff[p][i] = (uint32_t)((row - wg0) * kDescF8 + seg * 16);
+        }
+    auto copy_d = [&](int q, auto dc, int k) __attribute__((always_inline)) {
+        const int p = k / 4, i = k % 4;
+        uint8_t* dst = p == 0 ? dbuf(dc, IC<0>{}) : dbuf(dc, IC<PT - 1>{});
+        copy_lds16_stream(xr, dst + i * 1024, doff[p][i], q * 128);
+    };
+    // byte offsets of the two 16-byte halves of this lane's B fragment of step j
+    int roff[kStage8][2];
 #pragma unroll
-            for (int rt = 0; rt < RT; rt++)
+    for (int j = 0; j < kStage8; j++)
 #pragma unroll
-                for (int v = 0; v < 4; v++)
-                    u[rt][v] = valid ? reinterpret_cast<const bf16x8*>(xr[rt] + kc * M::KS)[v] : bf16x8{};
-        };
-        if (li == 0) load_u(0);
-        copy_w(wq0, li, KC, 0);
-        // one K step from buffer bc; issues the next step's copy into the other
-        auto step = [&](auto bc, int kc) __attribute__((always_inline)) {
-            uint8_t* cur = decltype(bc)::value == 0 ? wq0 : wq1;
-            uint8_t* nxt = decltype(bc)::value == 0 ? wq1 : wq0;
-            wait_vm<0>();
-            __syncthreads();   // step kc's fragments are in; every wave is done with nxt
-            typename M::frag a[RT];
-            if (li == 0) {
+        for (int h = 0; h < 2; h++) roff[j][h] = lp * 128 + (((lg * 4 + 2 * j + h) ^ ((lp >> 1) & 7)) << 4);
+
+    f32x16 acc[NO][PT];
+    // (the per-lane parts of the LDS addresses pass through opaque() once per
+    // stage, so that the compiler forms each stage's addresses anew instead of
+    // keeping every buffer's precomputed addresses live across the kernel)
+    auto read_a = [&](const uint8_t* wsrc, int j, int ct, int lo16) __attribute__((always_inline)) {
+        const uint8_t* base = wsrc + j * FRB + ct * 2048 + lo16;
+        const int4 lo = *reinterpret_cast<const int4*>(base), hi = *reinterpret_cast<const int4*>(base + 1024);
+        return i32x8{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    };
+    auto read_b = [&](const uint8_t* dsrc, int o0, int o1) __attribute__((always_inline)) {
+        const int4 lo = *reinterpret_cast<const int4*>(dsrc + o0);
+        const int4 hi = *reinterpret_cast<const int4*>(dsrc + o1);
+        return i32x8{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    };
+    auto init_acc = [&](const float* bias, int np) __attribute__((always_inline)) {
 #pragma unroll
-                for (int rt = 0; rt < RT; rt++)
+        for (int ct = 0; ct < NO; ct++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const float4 bv = *reinterpret_cast<const float4*>(bias + ct * 32 + j * 8 + lg * 4);
+#pragma unroll
+                for (int p = 0; p < PT; p++)
+                    if (p < np) {
+                        acc[ct][p][j * 4 + 0] = bv.x;
+                        acc[ct][p][j * 4 + 1] = bv.y;
+                        acc[ct][p][j * 4 + 2] = bv.z;
+                        acc[ct][p][j * 4 + 3] = bv.w;
+                    }
+            }
+    };
+    // the E8M0 weight scales of this lane's row (channel ct*32 + lp) of a layer
+    int ea[NO];
+    auto load_scales = [&](int li) __attribute__((always_inline)) {
+#pragma unroll
+        for (int ct = 0; ct < NO; ct++) ea[ct] = (int)A.wexp[li][ct * 32 + lp];
+    };
+    init_acc(A.bias[0], PT);
+    load_scales(0);
+
+    const int nhid = A.n_linear - 2;
+    const __amdgpu_buffer_rsrc_t W0 = rsrc(A.W[0], KC0 * FRB);
+    const __amdgpu_buffer_rsrc_t W1 = nhid > 0 ? rsrc(A.W[1], KH * FRB) : W0;
+
+    // ---- first layer: stage q from weight buffer q % 2 and descriptor buffer
+    // q % 3 while stage q + 1's weights and stage q + 2's descriptors load
+    auto stage0 = [&](auto bc, auto dc, int q) __attribute__((always_inline)) {
+        constexpr int B = decltype(bc)::value, D = decltype(dc)::value;
+        const IC<(D + 2) % 3> dn{};
+        const bool last = q + 1 == NQ0;
+        const uint8_t* wcur = wbuf(IC<B>{});
+        uint8_t* wnx = wbuf(IC<1 - B>{});
+        const __amdgpu_buffer_rsrc_t wsrc = last ? W1 : W0;
+        const int woff = last ? 0 : (q + 1) * STB;
+        const int wnch = !last ? kStage8 * NO * 2 : nhid > 0 ? min(kStage8, KH) * NO * 2 : 0;
+        const int qd = min(q + 2, NQ0 - 1);
+        const uint8_t* dcur[PT];
+        static_for<0, PT>([&](auto pc) __attribute__((always_inline)) { dcur[decltype(pc)::value] = dbuf(IC<D>{}, pc); });
+        // A fragments are read one unit ahead (one tile's worth in flight),
+        // B fragments one step ahead
+        const int la = opaque(lane * 16);
+        int ro[kStage8][2];
+#pragma unroll
+        for (int j = 0; j < kStage8; j++)
+#pragma unroll
+            for (int h = 0; h < 2; h++) ro[j][h] = opaque(roff[j][h]);
+        i32x8 a[2], bx[2][PT];
+        a[0] = read_a(wcur, 0, 0, la);
+#pragma unroll
+        for (int p = 0; p < PT; p++) bx[0][p] = read_b(dcur[p], ro[0][0], ro[0][1]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < kStage8; j++)
+#pragma unroll
+            for (int ct = 0; ct < NO; ct++) {
+                const int u = j * NO + ct;
+                // (each read's address passes through opaque() here, so that
+                // the read cannot be hoisted above this unit)
+                if (u + 1 < kStage8 * NO) a[(u + 1) % 2] = read_a(wcur, (u + 1) / NO, (u + 1) % NO, opaque(la));
+                if (j + 1 < kStage8 && ct == 0) {
+#pragma unroll
+                    for (int p = 0; p < PT; p++)
+                        bx[(j + 1) % 2][p] = read_b(dcur[p], opaque(ro[j + 1][0]), opaque(ro[j + 1][1]));
+                }
+#pragma unroll
+                for (int p = 0; p < PT; p++) acc[ct][p] = mfma32_f8(a[u % 2], bx[j % 2][p], acc[ct][p], ea[ct]);
+                __builtin_amdgcn_sched_barrier(0);
+                if (u < NWC) copy_w(wsrc, woff, wnch, wnx, u);
+                else if (u - NWC < ND) copy_d(qd, dn, u - NWC);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+        for (int u = kStage8 * NO; u < NWC + ND; u++) {
+            if (u < NWC) copy_w(wsrc, woff, wnch, wnx, u);
+            else copy_d(qd, dn, u - NWC);
+        }
+        // (unconditional: a branch here would let the compiler sink this
+        // stage's MFMAs past it into one block, with every fragment live)
+        wait_vm<ND>();
+        __syncthreads();
+    };
+#pragma unroll
+    for (int u = 0; u < NWC; u++) copy_w(W0, 0, kStage8 * NO * 2, wbuf(IC<0>{}), u);
+#pragma unroll
+    for (int k = 0; k < ND; k++) copy_d(0, IC<0>{}, k);
+#pragma unroll
+    for (int k = 0; k < ND; k++) copy_d(1, IC<1>{}, k);
+    wait_vm<ND>();
+    __syncthreads();
+    for (int q = 0; q < NQ0; q += 6) {
+        stage0(IC<0>{}, IC<0>{}, q);
+        if (q + 1 < NQ0) stage0(IC<1>{}, IC<1>{}, q + 1);
+        if (q + 2 < NQ0) stage0(IC<0>{}, IC<2>{}, q + 2);
+        if (q + 3 < NQ0) stage0(IC<1>{}, IC<0>{}, q + 3);
+        if (q + 4 < NQ0) stage0(IC<0>{}, IC<1>{}, q + 4);
+        if (q + 5 < NQ0) stage0(IC<1>{}, IC<2>{}, q + 5);
+    }
+
+    // ---- a finished layer's accumulators (z / s_next) into the next layer's
+    // B fragments: ReLU and saturation by med3, then E4M3
+    i32x8 hin[KH][PT];
+    auto epilogue = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int kc = 0; kc < KH; kc++)
+#pragma unroll
+            for (int p = 0; p < PT; p++) {
+                i32x8 f;
+#pragma unroll
+                for (int hf = 0; hf < 2; hf++) {
+                    const int t = 2 * kc + hf;
+                    if (t < NO) {
+                        const f32x16& c = acc[t < NO ? t : 0][p];
+#pragma unroll
+                        for (int v = 0; v < 4; v++)
+                            f[hf * 4 + v] = fp8x4_clamped(c[4 * v], c[4 * v + 1], c[4 * v + 2], c[4 * v + 3], 0.f);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < 4; v++) f[hf * 4 + v] = 0;
+                    }
+                }
+                hin[kc][p] = f;
+            }
+    };
+    epilogue();
+    wait_vm<0>();
+    __syncthreads();
+
+    // ---- hidden layers, B fragments from registers (as in the BF16 kernel)
+    constexpr int NQH = (KH + kStage8 - 1) / kStage8;
+    auto hidden = [&](auto b0c, int li) __attribute__((always_inline)) {
+        constexpr int B0 = decltype(b0c)::value;
+        const __amdgpu_buffer_rsrc_t Wl = rsrc(A.W[li], KH * FRB);
+        const __amdgpu_buffer_rsrc_t Wn = li < nhid ? rsrc(A.W[li + 1], KH * FRB) : Wl;
+        init_acc(A.bias[li], 1);
+        load_scales(li);
+        static_for<0, NQH>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = decltype(qc)::value, B = (B0 + q) % 2, k0 = q * kStage8;
+            constexpr int ns = KH - k0 < kStage8 ? KH - k0 : kStage8;
+            constexpr bool inner = q + 1 < NQH;
+            constexpr int nn = !inner ? 0 : KH - k0 - kStage8 < kStage8 ? KH - k0 - kStage8 : kStage8;
+            const __amdgpu_buffer_rsrc_t wsrc = inner ? Wl : Wn;
+            const int woff = inner ? (k0 + kStage8) * FRB : 0;
+            const int wnch = inner ? nn * NO * 2 : li < nhid ? (KH < kStage8 ? KH : kStage8) * NO * 2 : 0;
+            const uint8_t* wcur = wbuf(IC<B>{});
+            uint8_t* wnx = wbuf(IC<1 - B>{});
+            const int la = opaque(lane * 16);
+            i32x8 a[2];
+            a[0] = read_a(wcur, 0, 0, la);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < ns; j++)
+#pragma unroll
+                for (int ct = 0; ct < NO; ct++) {
+                    const int u = j * NO + ct;
+                    if (u + 1 < ns * NO) a[(u + 1) % 2] = read_a(wcur, (u + 1) / NO, (u + 1) % NO, opaque(la));
+                    if (q == 0 && j == 0) {
+#pragma unroll
+                        for (int p = PT - 1; p >= 0; p--)
+                            acc[ct][p] = mfma32_f8(a[u % 2], hin[k0][p], acc[ct][0], ea[ct]);
+                    } else {
+#pragma unroll
+                        for (int p = 0; p < PT; p++)
+                            acc[ct][p] = mfma32_f8(a[u % 2], hin[k0 + j][p], acc[ct][p], ea[ct]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (u < NWC) copy_w(wsrc, woff, wnch, wnx, u);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+#pragma unroll
+            for (int u = ns * NO; u < NWC; u++) copy_w(wsrc, woff, wnch, wnx, u);
+            if constexpr (q + 1 < NQH) {
+                wait_vm<0>();
+                __syncthreads();
+            }
+        });
+        epilogue();
+        wait_vm<0>();
+        __syncthreads();
+    };
+    constexpr int HB = NQ0 % 2;
+    if constexpr (NQH % 2 == 0) {
+        for (int li = 1; li <= nhid; li++) hidden(IC<HB>{}, li);
+    } else {
+        for (int li = 1; li <= nhid; li += 2) {
+            hidden(IC<HB>{}, li);
+            if (li + 1 <= nhid) hidden(IC<1 - HB>{}, li + 1);
+        }
+    }
+
+    // ---- last layer: the codes times the output weights (which carry the
+    // last input scale), over the lane's channels and across its two groups
+#pragma unroll
+    for (int p = 0; p < PT; p++) {
+        float s = 0.f;
+#pragma unroll
+        for (int kc = 0; kc < KH; kc++)
+#pragma unroll
+            for (int hf = 0; hf < 2; hf++) {
+                const int t = 2 * kc + hf;
+                if (t < NO) {
 #pragma unroll
                     for (int v = 0; v < 4; v++) {
-                        a[rt][2 * v] = pack_fp8x4_inrange((float)u[rt][v][0] * qs[rt], (float)u[rt][v][1] * qs[rt],
-                                                          (float)u[rt][v][2] * qs[rt], (float)u[rt][v][3] * qs[rt]);
-                        a[rt][2 * v + 1] = pack_fp8x4_inrange((float)u[rt][v][4] * qs[rt], (float)u[rt][v][5] * qs[rt],
-                                                              (float)u[rt][v][6] * qs[rt], (float)u[rt][v][7] * qs[rt]);
+                        const int w4 = hin[kc][p][hf * 4 + v];
+                        const float4 w = *reinterpret_cast<const float4*>(A.wout + t * 32 + v * 8 + lg * 4);
+                        s += __builtin_amdgcn_cvt_f32_fp8(w4, 0) * w.x + __builtin_amdgcn_cvt_f32_fp8(w4, 1) * w.y +
+                             __builtin_amdgcn_cvt_f32_fp8(w4, 2) * w.z + __builtin_amdgcn_cvt_f32_fp8(w4, 3) * w.w;
                     }
-                // the next step's descriptor slices and weight fragments stay in
-                // flight while this step's MFMAs run
-                if (kc + 1 < KC) {
-                    load_u(kc + 1);
-                    copy_w(nxt, li, KC, kc + 1);
                 }
-            } else {
-                if (kc + 1 < KC) copy_w(nxt, li, KC, kc + 1);
-#pragma unroll
-                for (int rt = 0; rt < RT; rt++) a[rt] = M::load(&h[rt * 16 + lr][kc * M::KS + lg * M::KPL]);
             }
-#pragma unroll
-            for (int ct = 0; ct < NT; ct++) {
-                typename M::frag b = M::load(cur + ct * FRAG + lane * M::KPL);
-#pragma unroll
-                for (int rt = 0; rt < RT; rt++) acc[rt][ct] = M::mma(a[rt], b, acc[rt][ct]);
-            }
-        };
-        for (int kc = 0; kc < KC; kc += 2) {
-            step(IC<0>{}, kc);
-            if (kc + 1 < KC) step(IC<1>{}, kc + 1);
-        }
-        __syncthreads();   // every lane's reads of h and rs precede their overwrite
-        const float* __restrict__ bias = A.bias[li];
-        const float* __restrict__ wsc = A.wscale[li];
-        // dequantise, bias, ReLU: column by column, so that each column's scale
-        // and bias are loaded once; the rows' maxima accumulate meanwhile
-        float din[RT][4], m[RT][4];
-#pragma unroll
-        for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                din[rt][e] = rs[rt * 16 + lg * 4 + e];
-                m[rt][e] = 0.f;
-            }
-#pragma unroll
-        for (int ct = 0; ct < NT; ct++) {
-            const int col = ct * 16 + lr;
-            const float ws = wsc[col], bs = bias[col];
-#pragma unroll
-            for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const float v = fmaxf(acc[rt][ct][e] * din[rt][e] * ws + bs, 0.f);
-                    acc[rt][ct][e] = v;
-                    m[rt][e] = fmaxf(m[rt][e], v);
-                }
-        }
-        // requantise each row to its own maximum
-#pragma unroll
-        for (int rt = 0; rt < RT; rt++) {
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const int row = rt * 16 + lg * 4 + e;
-                float mx = m[rt][e];
-                for (int o = 1; o < 16; o <<= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-                const float q = mx > 0.f ? kTarget / mx : 1.f;
-#pragma unroll
-                for (int ct = 0; ct < NT; ct++) {
-                    const int w = __builtin_amdgcn_cvt_pk_fp8_f32(acc[rt][ct][e] * q, 0.f, 0, false);
-                    h[row][ct * 16 + lr] = (uint8_t)(w & 0xff);
-                }
-                // the row's 16 lanes read rs[row] above, in this wave, before this write
-                if (lr == 0) rs[row] = mx > 0.f ? mx / kTarget : 1.f;
-            }
-        }
-        __syncthreads();
-    }
-    // last layer + decode, one row per lane
-    for (int rr = lane; rr < ROWS; rr += 64) {
-        const int64_t row = row0 + rr;
-        float y = 0.f;
-        for (int k = 0; k < W; k++) y += __builtin_amdgcn_cvt_f32_fp8((int)h[rr][k], 0) * A.wout[k];
-        y = A.bout + y * rs[rr];
-        if (row < npts) {
+        s += __shfl_xor(s, 32);
+        const int64_t row = row0 + p * 32 + lp;
+        if (lg == 0 && row < npts) {
+            const float y = A.bout + s;
             if (A.y_out) A.y_out[row] = y;
             if (A.out) A.out[row * A.out_stride] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
         }
@@ -719,24 +926,22 @@ static hipError_t launch_mlp_bf16(const MlpArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int NT>
-static void launch_fp8_nt(const MlpArgs& a, dim3 g, dim3 b, hipStream_t s)
+template <int NO, int KH, int PT, int NW>
+static void launch_f8_nt(const MlpArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_mlp_fp8<NT>), g, b, 0, s, a);
+    const int per = NW * 32 * PT;
+    hipLaunchKernelGGL((k_mlp_f8<NO, KH, PT, NW>), dim3((int)((a.npts + per - 1) / per)), dim3(64 * NW), 0, s, a);
 }
 
 static hipError_t launch_mlp_fp8(const MlpArgs& a, hipStream_t s)
 {
-    constexpr int per = kMlpWaves * 64;
-    int blocks = (int)((a.npts + per - 1) / per);
-    dim3 g(blocks), b(256);
-    switch (a.wpad / 16) {
-    case 1: launch_fp8_nt<1>(a, g, b, s); break;
-    case 2: launch_fp8_nt<2>(a, g, b, s); break;
-    case 4: launch_fp8_nt<4>(a, g, b, s); break;
-    case 8: launch_fp8_nt<8>(a, g, b, s); break;
-    case 13: launch_fp8_nt<13>(a, g, b, s); break;
-    case 16: launch_fp8_nt<16>(a, g, b, s); break;
+    switch (a.wpad) {
+    case 16: launch_f8_nt<1, 1, 2, 4>(a, s); break;
+    case 32: launch_f8_nt<1, 1, 2, 4>(a, s); break;
+    case 64: launch_f8_nt<2, 1, 2, 4>(a, s); break;
+    case 128: launch_f8_nt<4, 2, 2, 4>(a, s); break;
+    case 208: launch_f8_nt<7, 4, 2, 4>(a, s); break;
+    case 256: launch_f8_nt<8, 4, 1, 4>(a, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -763,15 +968,9 @@ static hipError_t launch_mlp_prec(const MlpArgs& a, hipStream_t s)
 // K of the hidden layers for a padded width: a multiple of the MFMA K step.
 int mlp_hidden_k(int prec, int wpad) { return hidden_k(prec, wpad); }
 
-// MFMA K step and elements per lane of a B fragment for a precision.
-int mlp_k_step(int prec)
-{
-    return prec == kPrecFP32 ? Mfma<kPrecFP32>::KS : prec == kPrecBF16 ? Mfma<kPrecBF16>::KS : Mfma<kPrecFP8>::KS;
-}
-int mlp_k_per_lane(int prec)
-{
-    return prec == kPrecFP32 ? Mfma<kPrecFP32>::KPL : prec == kPrecBF16 ? Mfma<kPrecBF16>::KPL : Mfma<kPrecFP8>::KPL;
-}
+// MFMA K step and elements per lane of a B fragment of the FP32 kernel.
+int mlp_k_step(int prec) { return prec == kPrecFP32 ? Mfma<kPrecFP32>::KS : Mfma<kPrecBF16>::KS; }
+int mlp_k_per_lane(int prec) { return prec == kPrecFP32 ? Mfma<kPrecFP32>::KPL : Mfma<kPrecBF16>::KPL; }
 
 // Padded width the kernel is instantiated for: the smallest of
 // 16, 32, 64, 128, 208, 256 that holds `width`.

@@ -18,27 +18,26 @@ struct FeatArgs {
     const void* w1t[2];          // conv1 weights [16 out][32 k], k = tap, zero padded
     const void* w2t[2];          // conv2 weights [16 out][224 k], k = c*27 + tap
     const float* cb[2];          // b1[8] b2[16] s1[64] c1[4] s2[64] c2[16]
-    void* desc;                  // [npts][kDescPad]
+    void* desc;                  // [npts][kDescPad] (FP8 output: [npts][kDescF8] E4M3 codes)
+    float desc_inv_scale;        // FP8 output only: 1 / the backbone's first input scale
     float* f0;                   // [npts] HG(w.l) T(p)
     float* dbg_tbar;             // optional [npts][12][225]
     float* dbg_rho;              // optional [npts][12][225]
     float* dbg_phi;              // optional [npts][225]
     float* dbg_stats;            // optional [npts][12][8]
     float* dbg_tp;               // optional [npts]
-    float* rowmax;               // optional [npts]: max |entry| of each stored descriptor row but its albedo entry
     const int* count;            // optional device point count: the kernel serves
     int64_t count_off;           // min(npts, *count - count_off) points
 };
 
 struct MlpArgs {
-    const void* x;                   // [npts][kDescPad] descriptor
+    const void* x;                   // [npts][kDescPad] descriptor ([npts][kDescF8] codes for FP8)
     int64_t npts;
-    const void* W[kMaxLinear];       // layer i: [wpad][kin_pad] (kin_pad = kDescPad for i = 0)
-    const float* bias[kMaxLinear];   // [wpad], zero padded
-    const float* wscale[kMaxLinear]; // FP8 only: per-output-column weight scale [wpad]
-    const float* rowmax;             // FP8 only: max |x| of each descriptor row but its albedo entry [npts]
-    float eta_max;                   // FP8 only: |albedo entry| as stored (BF16)
-    const float* wout;               // [wpad] last-layer weights (float32)
+    const void* W[kMaxLinear];       // layer i, in the kernel's fragment order
+    const float* bias[kMaxLinear];   // [wpad], zero padded (FP8: divided by the layer's output scale)
+    const uint32_t* wexp[kMaxLinear];// FP8 only: E8M0 weight scale of each output channel, [tiles * 32]
+    float* absmax;                   // FP32 only, optional: [n_linear] running max |input| of each layer
+    const float* wout;               // [wpad] last-layer weights (float32; FP8: times its input scale)
     float bout;
     int n_linear, wpad;
     const float* f0;                 // [npts]
@@ -90,8 +89,9 @@ struct GaussLegendre64 {
 hipError_t launch_volume_tables(const MediumView& mv, const GaussLegendre64& gl, SiteTables* tab, float* vtab,
                                 hipStream_t s);
 hipError_t launch_features(int prec, const FeatArgs& a, hipStream_t s);
-hipError_t launch_desc_to_f32(int prec, const void* src, float* dst, int64_t n, hipStream_t s);
+hipError_t launch_desc_to_f32(int prec, const void* src, float* dst, int64_t n, float scale, hipStream_t s);
 hipError_t launch_mlp(int prec, const MlpArgs& a, hipStream_t s);
+// eta: the albedo entry as stored (FP8: already divided by the descriptor's scale)
 hipError_t launch_albedo_entry(int prec, void* desc, int64_t n, const int* count, int64_t count_off, float eta,
                                hipStream_t s);
 int mlp_padded_width(int width);
@@ -111,13 +111,19 @@ int mlp_k_per_lane(int prec);   // K elements a lane holds in one B fragment
 // K step (4 for FP32, 32 for BF16); the extra weight columns are zero.
 __host__ __device__ constexpr int hidden_k(int prec, int wpad)
 {
-    return prec == kPrecFP32 ? wpad : prec == kPrecBF16 ? (wpad + 31) / 32 * 32 : (wpad + 127) / 128 * 128;
+    return prec == kPrecFP32 ? wpad : prec == kPrecBF16 ? (wpad + 31) / 32 * 32 : (wpad + 63) / 64 * 64;
 }
 
 // K of the backbone's first layer: the descriptor padded to the MFMA K step.
 __host__ __device__ constexpr int input_k(int prec)
 {
-    return prec == kPrecFP8 ? (kDescPad + 127) / 128 * 128 : kDescPad;
+    return prec == kPrecFP8 ? kDescF8 : kDescPad;
+}
+
+// Bytes of one stored descriptor row.
+__host__ __device__ constexpr int desc_row_bytes(int prec)
+{
+    return prec == kPrecFP32 ? kDescPad * 4 : prec == kPrecBF16 ? kDescPad * 2 : kDescF8;
 }
 
 }  // namespace nis

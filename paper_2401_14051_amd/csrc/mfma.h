@@ -1,4 +1,5 @@
-// mfma.h -- 16x16 MFMA fragments for gfx950 in float32 and bfloat16.
+// mfma.h -- 16x16 MFMA fragments for gfx950 in float32 and bfloat16 (the
+// CNN and the FP32 backbone).
 //
 // Lane layouts (wave64, lane l, g = l / 16, r = l % 16):
 //   A (16 x K):  row r, k = g*KPL + e for element e < KPL
@@ -59,44 +60,5 @@ template <> struct Mfma<1> {
     __device__ static __forceinline__ elem cvt(float x) { return (__bf16)x; }
     __device__ static __forceinline__ elem zero() { return (__bf16)0.f; }
 };
-
-// FP8 (OCP E4M3FN): v_mfma_scale_f32_16x16x128_f8f6f4 with unit block scales
-// (E8M0 exponent 127), K = 128, 32 one-byte elements per lane.  Elements are
-// raw fp8 codes; the caller applies its own per-row and per-column scales.
-typedef int i32x8 __attribute__((ext_vector_type(8)));
-template <> struct Mfma<2> {
-    static constexpr int KS = 128;
-    static constexpr int KPL = 32;
-    typedef uint8_t elem;
-    typedef i32x8 frag;
-    __device__ static __forceinline__ f32x4 mma(frag a, frag b, f32x4 c)
-    {
-        return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
-    }
-    __device__ static __forceinline__ frag load(const elem* p) { return *reinterpret_cast<const frag*>(p); }
-    __device__ static __forceinline__ elem zero() { return 0; }
-};
-
-// Largest finite OCP E4M3FN value; the hardware conversion does not saturate.
-constexpr float kFp8Max = 448.f;
-
-// Four floats (already scaled) -> four E4M3FN codes packed little-endian.
-__device__ __forceinline__ int pack_fp8x4(float a, float b, float c, float d)
-{
-    a = fminf(fmaxf(a, -kFp8Max), kFp8Max);
-    b = fminf(fmaxf(b, -kFp8Max), kFp8Max);
-    c = fminf(fmaxf(c, -kFp8Max), kFp8Max);
-    d = fminf(fmaxf(d, -kFp8Max), kFp8Max);
-    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
-    return __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
-}
-
-// As pack_fp8x4 for values already known to lie in [-448, 448] after rounding
-// to E4M3 (callers scale to at most 447.5 in magnitude).
-__device__ __forceinline__ int pack_fp8x4_inrange(float a, float b, float c, float d)
-{
-    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
-    return __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
-}
 
 }  // namespace nis

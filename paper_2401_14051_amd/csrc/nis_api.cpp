@@ -13,14 +13,14 @@
 #include "runtime.h"
 
 // Scratch of the allocation-free query (nis_query_device_noalloc): room for
-// the descriptor rows, single-scatter terms and row maxima of
-// NIS_NOALLOC_MAX_POINTS points at the widest precision (FP32 descriptor),
+// the descriptor rows and single-scatter terms of NIS_NOALLOC_MAX_POINTS
+// points at the widest precision (FP32 descriptor),
 // each part starting on a 256-byte boundary.  Every GPU the library runs on
 // holds its own copy until the process ends.  Host code never passes this
 // name to a kernel or a copy: it reaches the memory only through the device
 // address that scratch_setup() looks up per device.
 constexpr size_t kScratchBytes =
-    ((size_t)NIS_NOALLOC_MAX_POINTS * nis::kDescPad * 4 + 255) / 256 * 256 + 2 * (((size_t)NIS_NOALLOC_MAX_POINTS * 4 + 255) / 256 * 256);
+    ((size_t)NIS_NOALLOC_MAX_POINTS * nis::kDescPad * 4 + 255) / 256 * 256 + ((size_t)NIS_NOALLOC_MAX_POINTS * 4 + 255) / 256 * 256;
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace nis {
@@ -298,21 +298,77 @@ uint8_t fp8_e4m3(float f)
     return sign | (uint8_t)r;
 }
 
+// The FP8 backbone (k_mlp_f8): every layer's scales folded into its weights
+// and bias, weights as E4M3 codes with one power-of-two (E8M0) scale per
+// output channel, in the kernel's A-fragment order.  Layer l reads codes of
+// x_l / s_l and writes codes of ReLU(z_l) / s_{l+1}, so its weights are
+// W_l s_l / s_{l+1} and its bias beta_l / s_{l+1}; the output weights carry
+// s_{n-1}.  Needs the activation scales (net->has_fp8).
+void pack_fp8_backbone(Net* net, PackedNet& P)
+{
+    const int W = net->width, Wp = net->wpad, NO = (Wp + 31) / 32, Wb = NO * 32;
+    const float* sc = net->fp8_scales.data() + 2;   // input scale of each backbone layer
+    for (int li = 0; li + 1 < net->n_linear; li++) {
+        const int din = li == 0 ? kDesc : W;
+        const int KC = li == 0 ? kDescF8 / 64 : hidden_k(kPrecFP8, Wp) / 64;
+        const double f = (double)sc[li] / (double)sc[li + 1];
+        std::vector<int> ex(Wb, 0);
+        std::vector<uint32_t> eb(Wb, 127u);
+        std::vector<float> bb(Wb, 0.f);
+        for (int o = 0; o < W; o++) {
+            double amax = 0.0;
+            for (int i = 0; i < din; i++) amax = std::fmax(amax, std::fabs(net->A[li][(size_t)o * din + i] * f));
+            int e = amax > 0.0 ? (int)std::ceil(std::log2(amax / 448.0)) : 0;
+            e = e < -127 ? -127 : e > 127 ? 127 : e;
+            ex[o] = e;
+            eb[o] = (uint32_t)(e + 127);
+            bb[o] = (float)((double)net->beta[li][o] / (double)sc[li + 1]);
+        }
+        // step kc, tile ct, half h, lane l = r + 32 g, byte e16: weight row
+        // ct*32 + r, K slot e = 16 h + e16 of lane group g, whose input column
+        // is (first layer) the descriptor byte (kc/2)*128 + 64 g + 32 (kc%2) + e,
+        // (hidden layers) the previous layer's channel held in that slot
+        std::vector<uint8_t> frag((size_t)KC * NO * 2048, 0);
+        size_t pos = 0;
+        for (int kc = 0; kc < KC; kc++)
+            for (int ct = 0; ct < NO; ct++)
+                for (int h = 0; h < 2; h++)
+                    for (int l = 0; l < 64; l++)
+                        for (int e16 = 0; e16 < 16; e16++) {
+                            const int g = l / 32, row = ct * 32 + l % 32, e = 16 * h + e16;
+                            int col;
+                            if (li == 0) {
+                                col = (kc / 2) * 128 + 64 * g + 32 * (kc % 2) + e;
+                            } else {
+                                const int t = 2 * kc + e / 16, rr = e % 16;
+                                col = t < NO ? t * 32 + 8 * (rr / 4) + 4 * g + rr % 4 : din;
+                            }
+                            uint8_t code = 0;
+                            if (row < W && col < din)
+                                code = fp8_e4m3((float)std::ldexp(net->A[li][(size_t)row * din + col] * f, -ex[row]));
+                            frag[pos++] = code;
+                        }
+        upload_vec(P.W[li], frag, "backbone weights");
+        upload_vec(P.bias[li], bb, "backbone biases");
+        upload_vec(P.wexp[li], eb, "backbone weight scales");
+    }
+    std::vector<float> wo(Wb, 0.f);
+    const float slast = sc[net->n_linear - 1];
+    for (int i = 0; i < W; i++) wo[i] = (float)((double)net->A[net->n_linear - 1][i] * (double)slast);
+    upload_vec(P.wout, wo, "output weights");
+}
+
 // Pack one precision: conv weights [out][k] zero padded (float32 for FP32,
 // bfloat16 otherwise: the FP8 path runs the CNN in BF16); backbone matrices
-// zero padded to the kernel's tile sizes and stored in B-fragment order, in
-// float32, bfloat16 or E4M3 with one scale per output column (absmax / 448);
-// biases and the last layer stay float32.
+// zero padded to the kernel's tile sizes and stored in fragment order, in
+// float32 or bfloat16 (FP8: pack_fp8_backbone, once the activation scales
+// are known); biases and the last layer stay float32.
 void pack_net(Net* net, int prec)
 {
     PackedNet& P = net->packed[prec];
-    auto put = [&](DevBuf& buf, const std::vector<float>& v, const char* what, bool allow_fp8) {
+    auto put = [&](DevBuf& buf, const std::vector<float>& v, const char* what) {
         if (prec == kPrecFP32) {
             upload_vec(buf, v, what);
-        } else if (prec == kPrecFP8 && allow_fp8) {
-            std::vector<uint8_t> h(v.size());
-            for (size_t i = 0; i < v.size(); i++) h[i] = fp8_e4m3(v[i]);
-            upload_vec(buf, h, what);
         } else {
             std::vector<uint16_t> h(v.size());
             for (size_t i = 0; i < v.size(); i++) h[i] = bf16_bits(v[i]);
@@ -350,8 +406,8 @@ void pack_net(Net* net, int prec)
         for (int o = 0; o < 16; o++)
             for (int ci = 0; ci < 8; ci++)
                 for (int tap = 0; tap < 27; tap++) t2[o * kConv2K + tap * 8 + ci] = w2[(o * 8 + ci) * 27 + tap];
-        put(P.w1t[gi], t1, "conv1 weights", false);
-        put(P.w2t[gi], t2, "conv2 weights", false);
+        put(P.w1t[gi], t1, "conv1 weights");
+        put(P.w2t[gi], t2, "conv2 weights");
         std::vector<float> cb;
         cb.insert(cb.end(), b1, b1 + 8);
         cb.insert(cb.end(), b2, b2 + 16);
@@ -361,22 +417,18 @@ void pack_net(Net* net, int prec)
         cb.insert(cb.end(), c2, c2 + 16);
         upload_vec(P.cb[gi], cb, "attention weights");
     }
+    if (prec == kPrecFP8) {
+        if (net->has_fp8) pack_fp8_backbone(net, P);
+        return;
+    }
     const int W = net->width, Wp = net->wpad;
     const int Wb = (Wp + 31) / 32 * 32;   // biases and output weights padded to whole 32-channel tiles
     for (int li = 0; li + 1 < net->n_linear; li++) {
         const int din = li == 0 ? kDesc : W, kpad = li == 0 ? input_k(prec) : mlp_hidden_k(prec, Wp);
-        std::vector<float> t((size_t)Wp * kpad, 0.f), bb(Wb, 0.f), sc(Wp, 1.f);
+        std::vector<float> t((size_t)Wp * kpad, 0.f), bb(Wb, 0.f);
         for (int o = 0; o < W; o++) {
-            float amax = 0.f;
-            for (int i = 0; i < din; i++) {
-                t[(size_t)o * kpad + i] = net->A[li][(size_t)o * din + i];
-                amax = std::fmax(amax, std::fabs(net->A[li][(size_t)o * din + i]));
-            }
+            for (int i = 0; i < din; i++) t[(size_t)o * kpad + i] = net->A[li][(size_t)o * din + i];
             bb[o] = net->beta[li][o];
-            if (prec == kPrecFP8 && amax > 0.f) {
-                sc[o] = amax / 448.f;
-                for (int i = 0; i < din; i++) t[(size_t)o * kpad + i] /= sc[o];
-            }
         }
         const int KS = mlp_k_step(prec), KPL = mlp_k_per_lane(prec), KC = kpad / KS;
         std::vector<float> f(t.size());
@@ -410,9 +462,8 @@ void pack_net(Net* net, int prec)
                         for (int e = 0; e < KPL; e++)
                             f[pos++] = t[(size_t)(ct * 16 + l % 16) * kpad + kc * KS + (l / 16) * KPL + e];
         }
-        put(P.W[li], f, "backbone weights", true);
+        put(P.W[li], f, "backbone weights");
         upload_vec(P.bias[li], bb, "backbone biases");
-        if (prec == kPrecFP8) upload_vec(P.wscale[li], sc, "backbone weight scales");
     }
     std::vector<float> wo(Wb, 0.f);
     for (int i = 0; i < W; i++) wo[i] = net->A[net->n_linear - 1][i];
@@ -430,7 +481,7 @@ void free_net(Net* net)
         }
         for (auto& b : P.W) b.release();
         for (auto& b : P.bias) b.release();
-        for (auto& b : P.wscale) b.release();
+        for (auto& b : P.wexp) b.release();
         P.wout.release();
     }
     delete net;
@@ -442,9 +493,6 @@ void free_medium(Medium* M)
     M->light.release();
     delete M;
 }
-
-// the FP8 path stores the descriptor in BF16 and quantises it in the backbone
-size_t desc_elem_bytes(int prec) { return prec == kPrecFP32 ? 4 : 2; }
 
 // bytes of one FrameWork buffer set for npix pixels, scan storage excluded
 size_t frame_fixed_bytes(int64_t npix) { return (size_t)npix * (4 + 4 + 12 + 12 + 12 + 12 + 4 + 4) + 256; }
@@ -591,13 +639,12 @@ WsView scratch_view(int device, int prec, int64_t n)
     if (!sl.done) fail(NIS_E_INTERNAL, "scratch not set up for this device");
     if (!sl.ptr) fail(NIS_E_DEVICE, std::string("scratch address: ") + hipGetErrorString(sl.err));
     auto up = [](size_t b) { return (b + 255) / 256 * 256; };
-    const size_t d = up((size_t)n * kDescPad * desc_elem_bytes(prec)), f = up((size_t)n * 4);
-    if (d + 2 * f > kScratchBytes) fail(NIS_E_INTERNAL, "scratch too small");
+    const size_t d = up((size_t)n * desc_row_bytes(prec)), f = up((size_t)n * 4);
+    if (d + f > kScratchBytes) fail(NIS_E_INTERNAL, "scratch too small");
     char* base = static_cast<char*>(sl.ptr);
     WsView w;
     w.desc = base;
     w.f0 = reinterpret_cast<float*>(base + d);
-    w.rowmax = reinterpret_cast<float*>(base + d + f);
     w.chunk = n;
     return w;
 }
@@ -609,19 +656,7 @@ WsView scratch_view(int device, int prec, int64_t n)
 size_t workspace_bytes(int prec, int64_t npts)
 {
     const int64_t chunk = npts < kChunk ? npts : kChunk;
-    return (size_t)chunk * kDescPad * desc_elem_bytes(prec) + (size_t)chunk * 4 * (prec == kPrecFP8 ? 2 : 1);
-}
-
-// |x| rounded to nearest even BF16, as a BF16 descriptor stores it.
-float bf16_abs(float x)
-{
-    uint32_t u;
-    std::memcpy(&u, &x, 4);
-    u &= 0x7fffffffu;
-    u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
-    float r;
-    std::memcpy(&r, &u, 4);
-    return r;
+    return (size_t)chunk * desc_row_bytes(prec) + (size_t)chunk * 4;
 }
 
 void run_query(Workspace& ws, const Net* net, int prec, const Medium* M, LightState* ls, const Params& Pm,
@@ -630,13 +665,11 @@ void run_query(Workspace& ws, const Net* net, int prec, const Medium* M, LightSt
 {
     if (!net) fail(NIS_E_STATE, "no weights set");
     const int64_t chunk = n < kChunk ? n : kChunk;
-    ws.desc.reserve((size_t)chunk * kDescPad * desc_elem_bytes(prec), "descriptor workspace");
+    ws.desc.reserve((size_t)chunk * desc_row_bytes(prec), "descriptor workspace");
     ws.f0.reserve((size_t)chunk * sizeof(float), "single-scatter workspace");
-    if (prec == kPrecFP8) ws.rowmax.reserve((size_t)chunk * sizeof(float), "descriptor row maxima");
     WsView w;
     w.desc = ws.desc.p;
     w.f0 = ws.f0.as<float>();
-    w.rowmax = prec == kPrecFP8 ? ws.rowmax.as<float>() : nullptr;
     w.chunk = chunk;
     run_query_in(w, net, prec, M, ls, Pm, d_pts, d_dirs, n, d_count, o, s, true);
 }
@@ -647,7 +680,9 @@ void run_query_in(const WsView& ws, const Net* net, int prec, const Medium* M, L
 {
     if (!net) fail(NIS_E_STATE, "no weights set");
     if (Pm.channels != 1 && (Pm.channels != 3 || o.y || o.desc)) fail(NIS_E_INVALID, "bad channel count");
-    if (ws.chunk <= 0 || !ws.desc || !ws.f0 || (prec == kPrecFP8 && !ws.rowmax)) fail(NIS_E_INTERNAL, "no scratch");
+    if (ws.chunk <= 0 || !ws.desc || !ws.f0) fail(NIS_E_INTERNAL, "no scratch");
+    if (prec == kPrecFP8 && !net->has_fp8)
+        fail(NIS_E_UNSUPPORTED, "FP8 needs the activation scales: pass them in the weight blob or call nis_calibrate_fp8");
     ensure_sweep(M, ls, s);
     refresh_tables(M, ls, Pm.phase, Pm.volume, s, may_alloc);
     const PackedNet& P = net->packed[prec];
@@ -675,8 +710,8 @@ void run_query_in(const WsView& ws, const Net* net, int prec, const Medium* M, L
             fa.cb[gi] = P.cb[gi].as<float>();
         }
         fa.desc = ws.desc;
+        fa.desc_inv_scale = prec == kPrecFP8 ? 1.f / net->fp8_scales[2] : 1.f;
         fa.f0 = o.f0 ? o.f0 + p0 : ws.f0;
-        fa.rowmax = prec == kPrecFP8 ? ws.rowmax : nullptr;
         auto off = [&](float* base, int64_t per) { return base ? base + p0 * per : nullptr; };
         fa.dbg_tbar = off(o.tbar, kLayers * kSites);
         fa.dbg_rho = off(o.rho, kLayers * kSites);
@@ -685,7 +720,7 @@ void run_query_in(const WsView& ws, const Net* net, int prec, const Medium* M, L
         fa.dbg_tp = off(o.tp, 1);
         timed("features", s, [&] { return launch_features(prec, fa, s); });
         if (o.desc) {
-            size_t eb = desc_elem_bytes(prec) * kDescPad;
+            size_t eb = desc_row_bytes(prec);
             hip_check(hipMemcpyAsync((char*)o.desc + p0 * eb, ws.desc, cn * eb, hipMemcpyDeviceToDevice, s),
                       "descriptor copy");
         }
@@ -699,9 +734,9 @@ void run_query_in(const WsView& ws, const Net* net, int prec, const Medium* M, L
         for (int li = 0; li + 1 < net->n_linear; li++) {
             ma.W[li] = P.W[li].p;
             ma.bias[li] = P.bias[li].as<float>();
-            ma.wscale[li] = P.wscale[li].as<float>();
+            ma.wexp[li] = P.wexp[li].as<uint32_t>();
         }
-        ma.rowmax = fa.rowmax;
+        ma.absmax = o.absmax;
         ma.wout = P.wout.as<float>();
         ma.bout = net->beta[net->n_linear - 1][0];
         ma.n_linear = net->n_linear;
@@ -713,13 +748,14 @@ void run_query_in(const WsView& ws, const Net* net, int prec, const Medium* M, L
         // (the features stored channel 0's) and runs the backbone
         for (int c = 0; c < Pm.channels; c++) {
             const float eta = Pm.channels == 3 ? Pm.rgb[c] : Pm.albedo;
-            if (c > 0)
+            if (c > 0) {
+                const float stored = prec == kPrecFP8 ? eta * fa.desc_inv_scale : eta;
                 timed("albedo_entry", s,
-                      [&] { return launch_albedo_entry(prec, ws.desc, cn, d_count, p0, eta, s); });
+                      [&] { return launch_albedo_entry(prec, ws.desc, cn, d_count, p0, stored, s); });
+            }
             ma.out = o.radiance ? o.radiance + p0 * Pm.channels + c : nullptr;
             ma.y_out = o.y && c == 0 ? o.y + p0 : nullptr;
             ma.albedo_gamma = (float)std::pow((double)eta, (double)net->gamma);
-            ma.eta_max = bf16_abs(eta);
             timed("backbone", s, [&] { return launch_mlp(prec, ma, s); });
         }
     }
@@ -1156,7 +1192,11 @@ int32_t nis_set_weights(nis_ctx* ctx, const void* blob, size_t nbytes)
                 net->beta.emplace_back(all.begin() + pos, all.begin() + pos + dout[i]);
                 pos += dout[i];
             }
-            if (net->has_fp8) net->fp8_scales.assign(all.begin() + pos, all.end());
+            if (net->has_fp8) {
+                net->fp8_scales.assign(all.begin() + pos, all.end());
+                for (float v : net->fp8_scales)
+                    if (!(v > 0.f)) fail(NIS_E_INVALID, "FP8 activation scales must be > 0");
+            }
             pack_net(net, kPrecFP32);
             pack_net(net, kPrecBF16);
             pack_net(net, kPrecFP8);
@@ -1177,6 +1217,9 @@ int32_t nis_set_precision(nis_ctx* ctx, int32_t precision)
         std::lock_guard<std::mutex> lk(ctx->mu);
         if (precision != NIS_FP32 && precision != NIS_BF16 && precision != NIS_FP8)
             fail(NIS_E_INVALID, "unknown precision");
+        if (precision == NIS_FP8 && ctx->net && !ctx->net->has_fp8)
+            fail(NIS_E_UNSUPPORTED, "FP8 needs the activation scales: pass them in the weight blob or call "
+                                    "nis_calibrate_fp8");
         ctx->precision = precision;
     });
 }
@@ -1195,6 +1238,49 @@ int32_t nis_query_device(nis_ctx* ctx, int32_t medium, const float* d_points, co
         o.radiance = d_out;
         run_query(ctx->ws, ctx->net, ctx->precision, M, &M->light, grey_params(M), d_points, d_dirs, n, nullptr,
                   o, s);
+    });
+}
+
+int32_t nis_calibrate_fp8(nis_ctx* ctx, int32_t medium, const float* d_points, const float* d_dirs, int64_t n,
+                          void* hip_stream)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        no_server(ctx, "calibrating the FP8 scales");
+        if (!d_points || !d_dirs || n <= 0) fail(NIS_E_INVALID, "bad calibration arguments");
+        Medium* M = get_medium(ctx, medium);
+        if (!ctx->net) fail(NIS_E_STATE, "no weights set");
+        Net* net = ctx->net;
+        const Params P = grey_params(M);
+        DevBuf amax;
+        amax.reserve((size_t)net->n_linear * sizeof(float), "calibration maxima");
+        std::vector<float> h(net->n_linear, 0.f);
+        try {
+            StreamUse su(ctx, (hipStream_t)hip_stream);
+            hip_check(hipMemsetAsync(amax.p, 0, amax.bytes, su.s), "calibration maxima");
+            QueryOut o;
+            o.absmax = amax.as<float>();
+            run_query(ctx->ws, net, kPrecFP32, M, &M->light, P, d_points, d_dirs, n, nullptr, o, su.s);
+            hip_check(hipMemcpyAsync(h.data(), amax.p, h.size() * sizeof(float), hipMemcpyDeviceToHost, su.s),
+                      "calibration maxima");
+            hip_check(hipStreamSynchronize(su.s), "calibration");
+        } catch (...) {
+            amax.release();
+            throw;
+        }
+        amax.release();
+        // x = code * s with s = 2 max|x| / 448: a factor of two of headroom
+        // above the calibration points' range (codes saturate at 448)
+        std::vector<float> sc(2 + net->n_linear, 1.f);
+        for (int i = 0; i < net->n_linear; i++) {
+            if (!std::isfinite(h[i])) fail(NIS_E_INTERNAL, "non-finite calibration maximum");
+            sc[2 + i] = h[i] > 0.f ? 2.f * h[i] / 448.f : 1.f;
+        }
+        hip_check(hipDeviceSynchronize(), "calibration");   // FP8 queries on any stream may read the old weights
+        net->fp8_scales = sc;
+        net->has_fp8 = true;
+        pack_net(net, kPrecFP8);
     });
 }
 
@@ -1452,13 +1538,14 @@ int32_t nis_debug_network(nis_ctx* ctx, int32_t medium, const float* d_points, c
         QueryOut o;
         o.y = d_y;
         if (d_desc) {
-            raw.reserve((size_t)n * kDescPad * desc_elem_bytes(prec), "descriptor copy");
+            raw.reserve((size_t)n * desc_row_bytes(prec), "descriptor copy");
             o.desc = raw.p;
         }
         try {
             run_query(ctx->ws, ctx->net, prec, M, &M->light, grey_params(M), d_points, d_dirs, n, nullptr, o,
                       ctx->stream);
-            if (d_desc) hip_check(launch_desc_to_f32(prec, raw.p, d_desc, n, ctx->stream), "descriptor convert");
+            const float dscale = prec == kPrecFP8 ? ctx->net->fp8_scales[2] : 1.f;
+            if (d_desc) hip_check(launch_desc_to_f32(prec, raw.p, d_desc, n, dscale, ctx->stream), "descriptor convert");
             hip_check(hipStreamSynchronize(ctx->stream), "network");
         } catch (...) {
             (void)hipStreamSynchronize(ctx->stream);

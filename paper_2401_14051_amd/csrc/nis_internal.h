@@ -14,7 +14,8 @@ constexpr int kStats = 8;         // squeeze vector, eq. (24)
 constexpr int kFeat = 80;         // 16 channels x 5 positions after the CNN
 constexpr int kPerLayer = kFeat + kStats;
 constexpr int kDesc = kLayers * kPerLayer + 1;   // 1057
-constexpr int kDescPad = 1088;    // row stride of the descriptor (multiple of 64)
+constexpr int kDescPad = 1088;    // row stride of the descriptor in elements, FP32 and BF16 (multiple of 64)
+constexpr int kDescF8 = 1152;     // row stride of the FP8 descriptor in bytes (E4M3 codes; 18 K steps of 64)
 constexpr int kMaxLevels = 11;    // 1024^3 .. 1^3
 constexpr int kMaxWidth = 256;    // backbone width limit
 constexpr int kConv1K = 96;       // two points x 9 tap-rows x 4 (3 taps + a zero), padded to the MFMA step

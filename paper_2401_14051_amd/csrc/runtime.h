@@ -144,15 +144,18 @@ void set_light_state(const Medium* M, const double l[3], LightState* ls);
 
 struct PackedNet {
     DevBuf w1t[2], w2t[2], cb[2];
-    DevBuf W[kMaxLinear], bias[kMaxLinear], wscale[kMaxLinear], wout;
+    DevBuf W[kMaxLinear], bias[kMaxLinear], wexp[kMaxLinear], wout;
 };
 
 struct Net {
     int width = 0, n_linear = 0, wpad = 0;
     float lam = 0.6f, gamma = 4.f;
-    bool has_fp8 = false;
+    bool has_fp8 = false;              // activation scales known (blob or calibration); FP8 packed
     std::vector<float> groups[2];      // 3844 floats each, blob order
     std::vector<std::vector<float>> A, beta;
+    // dequantisation scales of the FP8 activations (x = code * scale): conv1
+    // input, conv2 input (unused: the CNN runs in BF16), then the input of
+    // each backbone layer
     std::vector<float> fp8_scales;
     PackedNet packed[3];               // fp32, bf16, fp8
 };
@@ -179,15 +182,14 @@ extern thread_local Profiler* g_prof;   // profiler of the context this thread i
 constexpr int64_t kChunk = 1 << 21;   // points per feature/backbone pass
 constexpr int kRenderBand = 8;         // rows per band of a rendered frame's collision order
 
-// Descriptor, single-scatter and row-maximum scratch of one stream.
+// Descriptor and single-scatter scratch of one stream.
 struct Workspace {
-    DevBuf desc, f0, rowmax;
-    size_t bytes() const { return desc.bytes + f0.bytes + rowmax.bytes; }
+    DevBuf desc, f0;
+    size_t bytes() const { return desc.bytes + f0.bytes; }
     void release()
     {
         desc.release();
         f0.release();
-        rowmax.release();
     }
 };
 
@@ -214,17 +216,16 @@ struct QueryOut {
     float* stats = nullptr;
     float* tp = nullptr;
     float* f0 = nullptr;
-    void* desc = nullptr;     // raw descriptor copy (precision's element type), [n][kDescPad]
+    void* desc = nullptr;     // raw descriptor copy (precision's row layout), [n][desc_row_bytes]
+    float* absmax = nullptr;  // FP32 backbone only: device [n_linear], running max |input| of each layer
     bool run_mlp = true;
 };
 
 // Device addresses of the scratch one pass of the query uses: the descriptor
-// rows [chunk][kDescPad], the single-scatter terms [chunk] and (FP8) the
-// descriptor row maxima [chunk].
+// rows [chunk][desc_row_bytes] and the single-scatter terms [chunk].
 struct WsView {
     void* desc = nullptr;
     float* f0 = nullptr;
-    float* rowmax = nullptr;
     int64_t chunk = 0;   // points per pass
 };
 

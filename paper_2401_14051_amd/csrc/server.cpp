@@ -371,6 +371,9 @@ int32_t nis_server_start(nis_ctx* ctx, const nis_server_cfg* cfg)
         if (!cfg) fail(NIS_E_INVALID, "cfg is NULL");
         if (cfg->precision != NIS_FP32 && cfg->precision != NIS_BF16 && cfg->precision != NIS_FP8)
             fail(NIS_E_INVALID, "unknown precision");
+        if (cfg->precision == NIS_FP8 && !ctx->net->has_fp8)
+            fail(NIS_E_UNSUPPORTED, "FP8 needs the activation scales: pass them in the weight blob or call "
+                                    "nis_calibrate_fp8");
         if (cfg->max_inflight < 1 || cfg->max_inflight > 16) fail(NIS_E_INVALID, "max_inflight must be in [1,16]");
         if (cfg->hbm_budget_bytes == 0) fail(NIS_E_INVALID, "budget is zero");
         Server* S = new Server();

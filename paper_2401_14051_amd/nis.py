@@ -83,6 +83,7 @@ _SIGNATURES = {
     "nis_query": [_vp, _i32, _vp, _vp, _i64, _vp],
     "nis_query_device": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
     "nis_query_device_noalloc": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
+    "nis_calibrate_fp8": [_vp, _i32, _vp, _vp, _i64, _vp],
     "nis_query_rgb": [_vp, _i32, _vp, _vp, _i64, _vp],
     "nis_query_rgb_device": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
     "nis_medium_info": [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i64)],
@@ -300,6 +301,14 @@ class Context:
             stream = torch.cuda.current_stream(points.device).cuda_stream
         _check(_lib.nis_query_device(self.h, medium, _dptr(points), _dptr(dirs), points.shape[0],
                                      _dptr(out), _vp(stream)))
+
+    def calibrate_fp8(self, medium, points, dirs, stream=None):
+        """Static FP8 activation scales from the FP32 path over these points
+        (torch device tensors [n, 3]); synchronous."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(points.device).cuda_stream
+        _check(_lib.nis_calibrate_fp8(self.h, medium, _dptr(points), _dptr(dirs), points.shape[0], _vp(stream)))
 
     def query_device_noalloc(self, medium, points, dirs, out, stream=None):
         """As query_device through the entry point that allocates nothing (its

@@ -73,5 +73,17 @@ def small_points(extra_random=300, seed=5):
     return d, np.concatenate([p, rp]), np.concatenate([dd, rd])
 
 
-__all__ = ["f32", "oracle_params", "rel_l2", "Scene", "small_points", "configs", "medium", "weights",
-           "camera", "oracle"]
+def set_precision(ctx, prec, mid=None, pts=None, dirs=None):
+    """ctx.set_precision(prec); for FP8 the static activation scales are
+    calibrated first, with the FP32 path over the given points of medium mid
+    (nis_calibrate_fp8)."""
+    if prec == "fp8":
+        import torch
+        tp = torch.from_numpy(np.ascontiguousarray(pts, np.float32)).cuda()
+        td = torch.from_numpy(np.ascontiguousarray(dirs, np.float32)).cuda()
+        ctx.calibrate_fp8(mid, tp, td)
+    ctx.set_precision(prec)
+
+
+__all__ = ["f32", "oracle_params", "rel_l2", "Scene", "small_points", "set_precision", "configs", "medium",
+           "weights", "camera", "oracle"]

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import Scene, camera, configs, f32, medium, rel_l2, weights
+from gpu_common import Scene, camera, configs, f32, medium, rel_l2, set_precision, weights
 
 pytestmark = pytest.mark.gpu
 
@@ -176,7 +176,8 @@ def test_render_equals_query_of_frame_points(ctx, prec):
     mid = ctx.load_medium(d, 8.0, 0.9, 0.7)
     ctx.set_light(mid, (0.3, 0.9, 0.3), 1.0)
     ctx.set_weights(weights.he_init(64, 4, seed=3, bias_scale=0.05))
-    ctx.set_precision(prec)
+    cp, cd = camera.random_points(2048, seed=9, lo=0.0, hi=1.0)
+    set_precision(ctx, prec, mid, cp, cd)
     cam = nis.camera(101, 43, 40.0, eye=(1.6, 0.7, 1.2))
     img = ctx.render(mid, cam, 7).cpu().numpy().ravel()
     pts, dirs, pix = ctx.frame_points(mid, cam, 7)

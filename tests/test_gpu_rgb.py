@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import Scene, camera, configs, f32, rel_l2, small_points, weights
+from gpu_common import Scene, camera, configs, f32, rel_l2, set_precision, small_points, weights
 
 pytestmark = pytest.mark.gpu
 
@@ -67,7 +67,7 @@ def test_rgb_channels_equal_grey_queries(ctx, prec):
     d, pts, dirs = small_points(extra_random=100)
     s = Scene(ctx, d, (-0.7, 0.2, 0.4), albedo=0.8)
     ctx.set_weights(weights.he_init(128, 6, seed=2, bias_scale=0.05))
-    ctx.set_precision(prec)
+    set_precision(ctx, prec, s.mid, pts, dirs)
     grey = ctx.query(s.mid, pts, dirs)
     L3 = ctx.query_rgb(s.mid, pts, dirs)
     for c in range(3):

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import Scene, camera, configs, f32, medium, rel_l2, weights
+from gpu_common import Scene, camera, medium, rel_l2, set_precision, weights
 
 pytestmark = pytest.mark.gpu
 
@@ -35,7 +35,8 @@ def test_noalloc_query_equals_query_device(nis_mod, prec):
         params = weights.he_init(128, 6, seed=1)
         s = Scene(ctx, rho, (0.3, 0.9, 0.3))
         ctx.set_weights(params)
-        ctx.set_precision(prec)
+        cp, cd = camera.random_points(2048, seed=7, lo=0.0, hi=1.0)
+        set_precision(ctx, prec, s.mid, cp, cd)
         stream = torch.cuda.current_stream().cuda_stream
         # the largest batch first, then a smaller one (ragged, not a tile multiple)
         for n, seed in ((nis_mod.NOALLOC_MAX_POINTS, 3), (1237, 4)):
