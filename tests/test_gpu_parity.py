@@ -98,6 +98,62 @@ def test_features_match_oracle(ctx, light, g):
     s.close()
 
 
+def frame_size_points(n, seed):
+    """Points for the frame-size checks: inside the cube, within two voxels
+    of a face (each face, corners included), and outside it."""
+    r = np.random.default_rng(seed)
+    inner = r.uniform(0.02, 0.98, (n // 2, 3))
+    near = r.uniform(0.0, 1.0, (n // 4, 3))
+    axis = r.integers(0, 3, n // 4)
+    side = r.integers(0, 2, n // 4)
+    near[np.arange(n // 4), axis] = np.where(side == 1, 1.0 - r.uniform(0, 2.0 / 256, n // 4),
+                                             r.uniform(0, 2.0 / 256, n // 4))
+    near[:4] = [[0.0, 0.0, 0.0], [1.0, 1.0, 1.0], [0.001, 0.999, 0.5], [0.999, 0.001, 0.001]]
+    outside = r.uniform(-0.05, 1.05, (n - n // 2 - n // 4, 3))
+    outside[:, 0] = np.where(r.random(len(outside)) < 0.5, r.uniform(-0.05, -0.001, len(outside)),
+                             r.uniform(1.001, 1.05, len(outside)))
+    pts = np.concatenate([inner, near, outside]).astype(np.float32)
+    dirs = r.standard_normal((n, 3))
+    dirs = (dirs / np.linalg.norm(dirs, axis=1, keepdims=True)).astype(np.float32)
+    return pts, dirs
+
+
+@pytest.fixture(scope="module")
+def frame_cloud():
+    return configs.FRAME.density()
+
+
+@pytest.mark.parametrize("light", [configs.LIGHT_DIR, (1.0, 0.2, -0.3)])
+def test_features_descriptor_and_y_at_frame_size(ctx, frame_cloud, light):
+    """The 256^3 frame medium (9 levels, the brick and slab paths a 32^3 grid
+    never takes at levels 0-4), with the frame light and an x-dominant light:
+    every site's density, graded transmittance and phase, the statistics, the
+    descriptor and y (FP32, the frame's 10 x 200 network) element by element
+    against the oracle, at 256 points inside the cube, within two voxels of
+    its faces and outside it."""
+    print("frame-size features light=%s" % (light,), flush=True)
+    w = configs.FRAME
+    pts, dirs = frame_size_points(256, seed=31)
+    s = Scene(ctx, frame_cloud, light, w.sigma_t, w.albedo, w.g, w.radiance)
+    params = w.params()
+    ctx.set_weights(params)
+    ctx.set_precision("fp32")
+    ref = s.oracle_features(params, pts, dirs)
+    got = {k: v.cpu().numpy().astype(np.float64) for k, v in ctx.features(s.mid, dev(pts), dev(dirs)).items()}
+    np.testing.assert_array_equal(got["rho"] == 0, ref["rho"] == 0)
+    np.testing.assert_allclose(got["rho"], ref["rho"], rtol=0, atol=2e-6)
+    np.testing.assert_allclose(got["tbar"], ref["tbar"], rtol=2e-5, atol=1e-6)
+    np.testing.assert_allclose(got["phi"], ref["phi"], rtol=2e-5, atol=2e-6)
+    np.testing.assert_allclose(got["stats"], ref["stats"], rtol=2e-5, atol=2e-6)
+    np.testing.assert_allclose(got["tp"], ref["tp"], rtol=2e-5, atol=1e-7)
+    np.testing.assert_allclose(got["f0"], ref["f0"], rtol=2e-5, atol=1e-9)
+    q = s.oracle_query(params, pts, dirs, want_desc=True)
+    desc, y = ctx.network(s.mid, dev(pts), dev(dirs))
+    np.testing.assert_allclose(desc.cpu().numpy().astype(np.float64), q["desc"], rtol=2e-5, atol=2e-6)
+    np.testing.assert_allclose(y.cpu().numpy(), q["y"], rtol=0, atol=2e-5 * np.abs(q["y"]).max())
+    s.close()
+
+
 def test_descriptor_and_network_output_fp32(ctx):
     d, pts, dirs = small_points(extra_random=100)
     s = Scene(ctx, d, configs.LIGHT_DIR)
