@@ -25,14 +25,14 @@
 //
 // Work split.  A workgroup is one wave and holds kTP = 4 points; the 16 lanes
 // of a point share its work, so no stage waits for another wave.  Per layer
-// the samples a point's sites need are first staged in LDS as small bricks:
-// the path densities around the point (index-clamped) from the per-light
-// path-density pairs, and for each slab the densities already interpolated
-// along the light axis from the light-axis density pairs, both as 48-byte
-// runs with one lane per brick row.  A lane then evaluates up to three rows of
-// 5 sites (one slab q, one lateral j, i = -2..2) from the bricks with the
-// shared weights.  Each lane keeps its own running sums and maxima, reduced
-// over the point's 16 lanes by shuffles.
+// the path densities around the point (index-clamped) are first staged in LDS
+// as a small brick from the per-light path-density pairs, as 48-byte runs
+// with one lane per brick row; a lane then evaluates up to three rows of 5
+// transmittance sites (one slab q, one lateral j, i = -2..2) from the brick
+// with the shared weights.  The densities need no staging: lane q < 9 of a
+// point loads its slab's 6 rows of light-axis density pairs (48-byte runs)
+// into registers and evaluates the slab's 25 sites.  Each lane keeps its own
+// running sums and maxima, reduced over the point's 16 lanes by shuffles.
 
 // Lattice layout for conv1.  Each 5-site row of the transmittance lattice is
 // stored as three 4-wide windows starting at i = 0, 1, 2 (the last padded with
@@ -67,8 +67,8 @@ struct SlabParams {           // per point, layer and slab q (density lookups)
 
 // Shared memory of one wave.  The lattice is dead once conv1 has read it, so
 // the attention stage reuses its space.  The brick area holds the
-// path-density bricks, then the density bricks, then conv1's output, which in
-// turn stages the descriptor rows once conv2 has read it.
+// path-density bricks, then conv1's output, which in turn stages the
+// descriptor rows once conv2 has read it.
 template <class E> struct FeatShared {
     union {
         E lat[kTP][kLatStride];
@@ -585,69 +585,13 @@ k_features(FeatArgs A)
                 emit(r, Dv);
             }
         }
-        __syncthreads();   // the path-density bricks are dead
-
-        // ---- density bricks: for each point and slab the rows c = cbase..+5 of
-        // 6 samples b = bbase..+5, interpolated between a = ia and ia+1 while
-        // loading (the a weight is shared by the slab's 25 sites).  The two
-        // a-planes come side by side from the light-axis pairs: a row is 6
-        // pairs, 48 contiguous bytes.  One lane per row; loads are issued two
-        // rows at a time.
-        if (nm > 1) {
-            const int nb = nm + 2 * kPairPad;   // stored row length of the pairs
-            const __amdgpu_buffer_rsrc_t rP = __builtin_amdgcn_make_buffer_rsrc(
-                mv.pairs + lv.p_off, 0, (nm + 1) * nm * nb * 8, kBufferFlags);
-            auto ldP = [&](int o) { return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rP, o * 4, 0, 0)); };
-            constexpr int kRRows = kTP * 9 * kBrickV, kRIt = (kRRows + 63) / 64;
-#pragma unroll
-            for (int it0 = 0; it0 < kRIt; it0 += 2) {
-                float pr[2][12], wav[2];
-#pragma unroll
-                for (int h = 0; h < 2; h++) {
-                    const int rr = ln + 64 * (it0 + h);
-                    wav[h] = 0.f;
-                    if (rr < kRRows) {
-                        const int bp = rr / (9 * kBrickV), loc = rr % (9 * kBrickV);
-                        const SlabParams S = sp[bp][loc / kBrickV];
-                        // a and c are clamped per row; a row within the padded
-                        // b range (every row of an in-cube point) is one run,
-                        // others are read sample by sample
-                        const int Ap = clampi(S.ia + 1, 0, nm), C = clampi(S.cbase + loc % kBrickV, 0, nm - 1);
-                        const int B0 = S.bbase;
-                        wav[h] = S.wa;
-                        if (B0 >= -kPairPad && B0 + 5 < nm + kPairPad) {
-                            const int o = ((Ap * nm + C) * nb + kPairPad + B0) * 2;
-#pragma unroll
-                            for (int e = 0; e < 12; e++) pr[h][e] = ldP(o + e);
-                        } else {
-                            const int ro = (Ap * nm + C) * nb + kPairPad;
-#pragma unroll
-                            for (int u = 0; u < 6; u++) {
-                                const int o = (ro + clampi(B0 + u, 0, nm - 1)) * 2;
-                                pr[h][2 * u] = ldP(o);
-                                pr[h][2 * u + 1] = ldP(o + 1);
-                            }
-                        }
-                    }
-                }
-#pragma unroll
-                for (int h = 0; h < 2; h++) {
-                    const int rr = ln + 64 * (it0 + h);
-                    if (rr < kRRows) {
-                        const int bp = rr / (9 * kBrickV), loc = rr % (9 * kBrickV);
-                        float2* dst = reinterpret_cast<float2*>(&brick[bp][loc * kBrickU]);
-#pragma unroll
-                        for (int e = 0; e < 3; e++)
-                            dst[e] = make_float2(lerpf(pr[h][4 * e], pr[h][4 * e + 1], wav[h]),
-                                                 lerpf(pr[h][4 * e + 2], pr[h][4 * e + 3], wav[h]));
-                    }
-                }
-            }
-            __syncthreads();
-        }
-
-        // ---- density statistics over the site rows, one to three per lane -------
-        // (one loop per case: the single-voxel level reads its voxel once)
+        // ---- densities and their statistics: lane q < 9 of each point's 16
+        // takes slab q.  It loads the slab's brick rows c = cbase..+5 of 6
+        // samples b = bbase..+5 straight into registers, both a-planes side by
+        // side from the light-axis pairs (a row is 6 pairs, 48 contiguous
+        // bytes), interpolates along a with the slab's shared weight, then
+        // evaluates the slab's 5 site rows (c, then b) and accumulates their
+        // statistics.  The single-voxel level reads its voxel once.
         float rs = 0.f, rmx = -INFINITY;
         auto accum = [&](int r, int mask, const float* Rv) __attribute__((always_inline)) {
             // in-cube bits of the row's sites: the slab, the lateral j, then each i
@@ -666,25 +610,48 @@ k_features(FeatArgs A)
             const float r0 = ldR(0);
             const float Rv[5] = {r0, r0, r0, r0, r0};
             for (int r = lrl; r < kRows; r += 16) accum(r, sp[pt][r / 5].mask, Rv);
-        } else {
-            for (int r = lrl; r < kRows; r += 16) {
-                const int qi = r / 5, jj = r % 5;
-                const SlabParams S = sp[pt][qi];
-                // plane rows c = c0 + j and c + 1 of the slab's a-interpolated brick
-                const float* b0 = &brick[pt][(qi * kBrickV + jj) * kBrickU];
-                float e0[6], e1[6], bb[6], Rv[5];
+        } else if (lrl < 9) {
+            const int qi = lrl;
+            const SlabParams S = sp[pt][qi];
+            const int nb = nm + 2 * kPairPad;   // stored row length of the pairs
+            const __amdgpu_buffer_rsrc_t rP = __builtin_amdgcn_make_buffer_rsrc(
+                mv.pairs + lv.p_off, 0, (nm + 1) * nm * nb * 8, kBufferFlags);
+            auto ldP = [&](int o) { return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rP, o * 4, 0, 0)); };
+            // a is clamped once, c per row; a row within the padded b range
+            // (every row of an in-cube point) is one run, others are read
+            // sample by sample
+            const int Ap = clampi(S.ia + 1, 0, nm), B0 = S.bbase;
+            const bool run = B0 >= -kPairPad && B0 + 5 < nm + kPairPad;
+            float pr[kBrickV][12];
 #pragma unroll
-                for (int h = 0; h < 3; h++) {
-                    const float2 f0 = reinterpret_cast<const float2*>(b0)[h];
-                    const float2 f1 = reinterpret_cast<const float2*>(b0 + kBrickU)[h];
-                    e0[2 * h] = f0.x, e0[2 * h + 1] = f0.y;
-                    e1[2 * h] = f1.x, e1[2 * h + 1] = f1.y;
+            for (int cc = 0; cc < kBrickV; cc++) {
+                const int C = clampi(S.cbase + cc, 0, nm - 1);
+                const int ro = (Ap * nm + C) * nb + kPairPad;
+                if (run) {
+#pragma unroll
+                    for (int e = 0; e < 12; e++) pr[cc][e] = ldP((ro + B0) * 2 + e);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 6; u++) {
+                        const int o = (ro + clampi(B0 + u, 0, nm - 1)) * 2;
+                        pr[cc][2 * u] = ldP(o);
+                        pr[cc][2 * u + 1] = ldP(o + 1);
+                    }
                 }
+            }
+            float R[kBrickV][6];
 #pragma unroll
-                for (int u = 0; u < 6; u++) bb[u] = lerpf(e0[u], e1[u], S.wc);
+            for (int cc = 0; cc < kBrickV; cc++)
+#pragma unroll
+                for (int u = 0; u < 6; u++) R[cc][u] = lerpf(pr[cc][2 * u], pr[cc][2 * u + 1], S.wa);
+#pragma unroll
+            for (int jj = 0; jj < 5; jj++) {
+                float bb[6], Rv[5];
+#pragma unroll
+                for (int u = 0; u < 6; u++) bb[u] = lerpf(R[jj][u], R[jj + 1][u], S.wc);
 #pragma unroll
                 for (int i = 0; i < 5; i++) Rv[i] = lerpf(bb[i], bb[i + 1], S.wb);
-                accum(r, S.mask, Rv);
+                accum(qi * 5 + jj, S.mask, Rv);
             }
         }
 
