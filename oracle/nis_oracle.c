@@ -610,3 +610,282 @@ void om_query(const om_medium *M, double sigma_t, double albedo, int nl, const d
         free(tb);
     }
 }
+
+/* ------------------------------------------------------------------ */
+/* The paper's own templates (Sec. III.B.2, eq. 2-4), in place of the
+ * lattices.  Readings (the paper gives counts, a uniformity measure and a
+ * radius rule, but no construction):
+ *  - diffuse sphere, 8 layers of 6, 8, 12, 16, 24, 32, 48, 48 points (the
+ *    per-layer counts as printed; they sum to 194, not the 182 the text
+ *    states); highlight cone, 4 layers of 32, 16, 16, 8 points;
+ *  - unit templates: layer 0 is the centre plus 5 points on the unit
+ *    sphere (of all arrangements in the closed unit ball, those farthest
+ *    from the centre and each other, the most even by eq. 3), layer i >= 1
+ *    fills the shell 1/2 <= |u| <= 1 (the sphere of the
+ *    previous layer, about half as large, is the inner surface); "evenly
+ *    distributed" is a spherical-Fibonacci direction (golden-angle
+ *    azimuth, stratified z) per point with an equal-volume radial stratum
+ *    taken from the additive sequence frac(1/2 + k c), c = 0.5698402909980532
+ *    (the plastic-number step, decorrelated from the golden angle);
+ *  - D(S_i) (eq. 3) is the mean over the layer's points of the distance to
+ *    the nearest other point of the unit template, and the layer's radius is
+ *    r_i = 2^(i-1) xi_i / (2^8 D(S_i)) with xi_i = 1 - 0.08 min(i, 5)
+ *    (eq. 4), in unit-cube lengths; so neighbouring points of layer i are
+ *    2^(i-1) xi_i voxels of a 256^3 grid apart;
+ *  - the highlight cone has its apex at the point, its axis along l, unit
+ *    length and unit base radius (the text's unit-size cone); it is scaled by
+ *    d_l, the distance from the point towards the light to where that ray
+ *    leaves the unit cube (the light's entry into the medium; 0 when the ray
+ *    misses it), and its 4 layers split the axis into equal quarters;
+ *    point k of layer h sits at the axial t that divides the layer's
+ *    frustum volume at the fraction (k+1/2)/n, at radius sqrt(w_k) t (w_k
+ *    as above) and golden-angle azimuth in the orthonormal
+ *    frame of l of Duff et al. (2017), "Building an orthonormal basis,
+ *    revisited";
+ *  - each layer samples the level whose voxel matches its point spacing:
+ *    m = the number of k >= 0 with spacing * N >= sqrt(2) 2^k (capped at
+ *    L-1), spacing = r_i D(S_i) for a diffuse layer and D(C_h) d_l for a
+ *    highlight layer;
+ *  - features per template point as for the lattice sites (density, graded
+ *    transmittance, point phase with d the unit direction from p to the
+ *    point, f(w.l) where the point is p itself), the squeeze vector of
+ *    eq. (24) per layer over its points;
+ *  - descriptor: per layer, its graded transmittances, densities, phase
+ *    features (template order) and squeeze vector; zeros up to the albedo
+ *    entry, which keeps index 1056 (the lattice descriptor's).            */
+#define OM_TPL_SITES 266
+static const int om_tpl_count[OM_LAYERS] = {6, 8, 12, 16, 24, 32, 48, 48, 32, 16, 16, 8};
+static const double OM_GOLDEN_ANGLE = 2.39996322972865332;   /* pi (3 - sqrt 5) */
+static const double OM_R2STEP = 0.5698402909980532;
+
+int om_tpl_count_of(int layer) { return om_tpl_count[layer]; }
+
+static int om_tpl_first(int layer)
+{
+    int f = 0;
+    for (int i = 0; i < layer; i++) f += om_tpl_count[i];
+    return f;
+}
+
+static double om_frac(double x) { return x - floor(x); }
+
+/* Unit template point k of a layer: diffuse layers in world axes, highlight
+ * layers as (t along l, x1, x2) in the frame of l.                          */
+void om_tpl_unit(int layer, int k, double u[3])
+{
+    int n = om_tpl_count[layer];
+    if (layer < OM_DIFFUSE) {
+        int kk = k, nn = n;
+        double rad;
+        if (layer == 0) {
+            if (k == 0) { u[0] = u[1] = u[2] = 0.0; return; }
+            kk = k - 1;
+            nn = n - 1;
+            rad = 1.0;
+        } else {
+            double w = om_frac(0.5 + kk * OM_R2STEP);
+            rad = cbrt(0.125 + w * 0.875);
+        }
+        double z = 1.0 - (2.0 * kk + 1.0) / nn;
+        double rxy = sqrt(1.0 - z * z);
+        double az = kk * OM_GOLDEN_ANGLE;
+        u[0] = rad * (rxy * cos(az));
+        u[1] = rad * (rxy * sin(az));
+        u[2] = rad * z;
+    } else {
+        int h = layer - OM_DIFFUSE;
+        double lo = h / 4.0, hi = (h + 1) / 4.0;
+        double t = cbrt(lo * lo * lo + ((k + 0.5) / n) * (hi * hi * hi - lo * lo * lo));
+        double w = om_frac(0.5 + k * OM_R2STEP);
+        double rad = sqrt(w) * t;
+        double az = k * OM_GOLDEN_ANGLE;
+        u[0] = t;
+        u[1] = rad * cos(az);
+        u[2] = rad * sin(az);
+    }
+}
+
+/* eq. (3): mean over the layer's unit points of the nearest-neighbour distance */
+double om_tpl_D(int layer)
+{
+    int n = om_tpl_count[layer];
+    double sum = 0.0;
+    for (int j = 0; j < n; j++) {
+        double a[3], best = INFINITY;
+        om_tpl_unit(layer, j, a);
+        for (int k = 0; k < n; k++) {
+            if (k == j) continue;
+            double b[3];
+            om_tpl_unit(layer, k, b);
+            double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+            double d = sqrt(dx * dx + dy * dy + dz * dz);
+            if (d < best) best = d;
+        }
+        sum += best;
+    }
+    return sum / n;
+}
+
+/* eq. (4): radius of diffuse layer i in unit-cube lengths */
+double om_tpl_radius(int layer)
+{
+    double xi = 1.0 - 0.08 * (layer < 5 ? layer : 5);
+    return ldexp(1.0, layer - 1) * xi / (256.0 * om_tpl_D(layer));
+}
+
+/* level whose voxel matches a spacing (unit-cube length) on an n^3 grid */
+static int om_tpl_level(double spacing, int n, int L)
+{
+    double x = spacing * n;
+    int m = 0;
+    while (m < L - 1 && x >= 1.4142135623730951 * ldexp(1.0, m)) m++;
+    return m;
+}
+
+/* distance from x towards the light to where that ray leaves the unit cube
+ * (0 when it misses the cube or leaves it behind x)                         */
+double om_tpl_light_extent(const double l[3], const double x[3])
+{
+    double t0 = -INFINITY, t1 = INFINITY;
+    for (int d = 0; d < 3; d++) {
+        if (l[d] == 0.0) {
+            if (x[d] < 0.0 || x[d] > 1.0) return 0.0;
+            continue;
+        }
+        double a = (0.0 - x[d]) / l[d], b = (1.0 - x[d]) / l[d];
+        double lo = a < b ? a : b, hi = a < b ? b : a;
+        if (lo > t0) t0 = lo;
+        if (hi < t1) t1 = hi;
+    }
+    if (t1 < t0 || t1 <= 0.0) return 0.0;
+    return t1;
+}
+
+/* orthonormal frame (e1, e2) of unit l, Duff et al. 2017 */
+static void om_onb(const double l[3], double e1[3], double e2[3])
+{
+    double s = l[2] >= 0.0 ? 1.0 : -1.0;
+    double a = -1.0 / (s + l[2]);
+    double b = l[0] * l[1] * a;
+    e1[0] = 1.0 + s * l[0] * l[0] * a;
+    e1[1] = s * b;
+    e1[2] = -s * l[0];
+    e2[0] = b;
+    e2[1] = s + l[1] * l[1] * a;
+    e2[2] = -l[1];
+}
+
+/* Features at the template points of every layer for np points:
+ *   tbar/rho/phi [p][266] in template order (layer by layer), stats
+ *   [p][12][8] as eq. (24), f0[p] = f(w.l) T(p); any output may be NULL.    */
+void om_tpl_features(const om_medium *M, double sigma_t, int nl, const double *lw, const double *lg,
+                     double lam, const float *pts, const float *dirs, int64_t np,
+                     double *tbar, double *rho, double *phi, double *stats, double *f0)
+{
+    double g = 0.0;
+    for (int i = 0; i < nl; i++) g += lw[i] * lg[i];
+    int L = M->levels;
+    double rad[OM_DIFFUSE], Dl[OM_LAYERS];
+    int mdiff[OM_DIFFUSE];
+    for (int i = 0; i < OM_LAYERS; i++) Dl[i] = om_tpl_D(i);
+    for (int i = 0; i < OM_DIFFUSE; i++) {
+        rad[i] = om_tpl_radius(i);
+        mdiff[i] = om_tpl_level(rad[i] * Dl[i], M->n, L);
+    }
+    double e1[3], e2[3];
+    om_onb(M->l, e1, e2);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < np; p++) {
+        double x[3], w[3];
+        for (int d = 0; d < 3; d++) { x[d] = pts[3 * p + d]; w[d] = dirs[3 * p + d]; }
+        double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        for (int d = 0; d < 3; d++) w[d] /= wn;
+        double wl = w[0] * M->l[0] + w[1] * M->l[1] + w[2] * M->l[2];
+        double alpha = acos(wl < -1.0 ? -1.0 : (wl > 1.0 ? 1.0 : wl));
+        double dlen = om_tpl_light_extent(M->l, x);
+        for (int k = 0; k < OM_LAYERS; k++) {
+            int n = om_tpl_count[k], f = om_tpl_first(k);
+            int m = k < OM_DIFFUSE ? mdiff[k] : om_tpl_level(Dl[k] * dlen, M->n, L);
+            double coef = pow(lam, m + 1) * sigma_t;
+            double rs = 0.0, rm = -INFINITY, ts = 0.0, tm = -INFINITY, ps = 0.0, pm = -INFINITY;
+            for (int j = 0; j < n; j++) {
+                double u[3], s[3];
+                om_tpl_unit(k, j, u);
+                if (k < OM_DIFFUSE) {
+                    for (int d = 0; d < 3; d++) s[d] = x[d] + rad[k] * u[d];
+                } else {
+                    for (int d = 0; d < 3; d++) {
+                        double o = u[0] * M->l[d] + u[1] * e1[d] + u[2] * e2[d];
+                        s[d] = x[d] + dlen * o;
+                    }
+                }
+                double r = om_sample_rho(M, m, s);
+                double T = exp(-coef * om_sample_D(M, m, s));
+                double v[3] = {s[0] - x[0], s[1] - x[1], s[2] - x[2]};
+                double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                double P;
+                if (vn == 0.0) {
+                    P = om_mhg(nl, lw, lg, wl);
+                } else {
+                    double wd = (w[0] * v[0] + w[1] * v[1] + w[2] * v[2]) / vn;
+                    double dl = (v[0] * M->l[0] + v[1] * M->l[1] + v[2] * M->l[2]) / vn;
+                    P = om_mhg(nl, lw, lg, wd) * om_mhg(nl, lw, lg, dl);
+                }
+                double ph = log1p(P);
+                if (rho) rho[p * OM_TPL_SITES + f + j] = r;
+                if (tbar) tbar[p * OM_TPL_SITES + f + j] = T;
+                if (phi) phi[p * OM_TPL_SITES + f + j] = ph;
+                rs += r; ts += T; ps += ph;
+                if (r > rm) rm = r;
+                if (T > tm) tm = T;
+                if (ph > pm) pm = ph;
+            }
+            if (stats) {
+                double *v = stats + (p * OM_LAYERS + k) * OM_STATS;
+                v[0] = rs / n; v[1] = ps / n; v[2] = ts / n;
+                v[3] = rm; v[4] = pm; v[5] = tm; v[6] = g; v[7] = alpha;
+            }
+        }
+        if (f0) f0[p] = om_mhg(nl, lw, lg, wl) * exp(-sigma_t * om_sample_D(M, 0, x));
+    }
+}
+
+/* Template descriptor: per layer its graded transmittances, densities and
+ * phase features in template order, then its squeeze vector (3 n_k + 8
+ * entries); zeros up to the albedo entry at index OM_DESC - 1.              */
+void om_tpl_descriptor(const double *tbar, const double *rho, const double *phi, const double *stats,
+                       double albedo, double *desc)
+{
+    for (int i = 0; i < OM_DESC; i++) desc[i] = 0.0;
+    int pos = 0;
+    for (int k = 0; k < OM_LAYERS; k++) {
+        int n = om_tpl_count[k], f = om_tpl_first(k);
+        for (int j = 0; j < n; j++) desc[pos++] = tbar[f + j];
+        for (int j = 0; j < n; j++) desc[pos++] = rho[f + j];
+        for (int j = 0; j < n; j++) desc[pos++] = phi[f + j];
+        for (int s = 0; s < OM_STATS; s++) desc[pos++] = stats[k * OM_STATS + s];
+    }
+    desc[OM_DESC - 1] = albedo;
+}
+
+/* Whole query with the paper's templates: as om_query (point phase) with the
+ * template descriptor in place of the lattice CNN's.                        */
+void om_tpl_query(const om_medium *M, double sigma_t, double albedo, int nl, const double *lw,
+                  const double *lg, double lam, double gamma, double radiance, const double *params, int width,
+                  int n_linear, const float *pts, const float *dirs, int64_t np,
+                  double *L_out, double *y_out, double *fhat_out, double *desc_out)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t p = 0; p < np; p++) {
+        double tb[OM_TPL_SITES], rh[OM_TPL_SITES], ph[OM_TPL_SITES], st[OM_LAYERS * OM_STATS], f0;
+        double *desc = desc_out ? desc_out + p * OM_DESC : (double *)malloc(sizeof(double) * OM_DESC);
+        om_tpl_features(M, sigma_t, nl, lw, lg, lam, pts + 3 * p, dirs + 3 * p, 1, tb, rh, ph, st, &f0);
+        om_tpl_descriptor(tb, rh, ph, st, albedo, desc);
+        double y = om_mlp(params, width, n_linear, desc);
+        double F = pow(albedo, gamma) * expm1(y);
+        L_out[p] = radiance * (f0 + F);
+        if (y_out) y_out[p] = y;
+        if (fhat_out) fhat_out[p] = F;
+        if (!desc_out) free(desc);
+    }
+}

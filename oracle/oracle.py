@@ -79,8 +79,59 @@ def lib():
         L.om_query.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp, _dp,
                                ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, ctypes.c_int,
                                ctypes.c_int, _fp, _fp, ctypes.c_int64, _dp, _dp, _dp, _dp]
+        L.om_tpl_count_of.restype = ctypes.c_int
+        L.om_tpl_count_of.argtypes = [ctypes.c_int]
+        L.om_tpl_unit.argtypes = [ctypes.c_int, ctypes.c_int, _dp]
+        L.om_tpl_D.restype = ctypes.c_double
+        L.om_tpl_D.argtypes = [ctypes.c_int]
+        L.om_tpl_radius.restype = ctypes.c_double
+        L.om_tpl_radius.argtypes = [ctypes.c_int]
+        L.om_tpl_light_extent.restype = ctypes.c_double
+        L.om_tpl_light_extent.argtypes = [_dp, _dp]
+        L.om_tpl_features.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, _dp, _dp, ctypes.c_double,
+                                      _fp, _fp, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp]
+        L.om_tpl_descriptor.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_double, _dp]
+        L.om_tpl_query.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp, _dp,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, ctypes.c_int,
+                                   ctypes.c_int, _fp, _fp, ctypes.c_int64, _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
+
+
+# ---- the paper's templates (Sec. III.B.2, eq. 2-4) ----
+TPL_SITES = 266
+
+
+def tpl_counts():
+    """Points per template layer: 8 diffuse sphere layers, 4 highlight cone layers."""
+    return [lib().om_tpl_count_of(k) for k in range(LAYERS)]
+
+
+def tpl_unit(layer):
+    """Unit template points of a layer as an [n, 3] array (diffuse: world axes;
+    highlight: (t along l, x1, x2) in the frame of l)."""
+    n = lib().om_tpl_count_of(layer)
+    out = np.zeros((n, 3))
+    u = np.zeros(3)
+    for k in range(n):
+        lib().om_tpl_unit(layer, k, _ptr(u, _dp))
+        out[k] = u
+    return out
+
+
+def tpl_D(layer):
+    """eq. (3): mean nearest-neighbour distance of the layer's unit points."""
+    return lib().om_tpl_D(layer)
+
+
+def tpl_radius(layer):
+    """eq. (4): radius of diffuse layer i in unit-cube lengths."""
+    return lib().om_tpl_radius(layer)
+
+
+def tpl_light_extent(l, x):
+    """Distance from x towards the light to where that ray leaves the unit cube."""
+    return lib().om_tpl_light_extent(_ptr(_f64(l), _dp), _ptr(_f64(x), _dp))
 
 
 def set_threads(n):
@@ -242,6 +293,36 @@ class Medium:
                           float(lam), _ptr(pts, _fp),
                           _ptr(dirs, _fp), P, *[_ptr(out.get(k), _dp) for k in
                                                 ("tbar", "rho", "phi", "stats", "tp", "f0")])
+        return out
+
+    def tpl_features(self, sigma_t, g, lam, pts, dirs):
+        """Features at the paper's template points: tbar/rho/phi [P][266],
+        stats [P][12][8], f0 [P] (point phase; g as in features())."""
+        pts, dirs = _f32(pts), _f32(dirs)
+        P = pts.shape[0]
+        out = {"tbar": np.zeros((P, TPL_SITES)), "rho": np.zeros((P, TPL_SITES)), "phi": np.zeros((P, TPL_SITES)),
+               "stats": np.zeros((P, LAYERS, STATS)), "f0": np.zeros(P)}
+        lw, lg = lobes(g)
+        lib().om_tpl_features(self.h, float(sigma_t), len(lw), _ptr(lw, _dp), _ptr(lg, _dp), float(lam),
+                              _ptr(pts, _fp), _ptr(dirs, _fp), P,
+                              *[_ptr(out[k], _dp) for k in ("tbar", "rho", "phi", "stats", "f0")])
+        return out
+
+    def tpl_query(self, params, pts, dirs, sigma_t, albedo, g, radiance=1.0, want_desc=False):
+        """As query() with the paper's templates and their descriptor."""
+        pts, dirs = _f32(pts), _f32(dirs)
+        P = pts.shape[0]
+        flat = flatten_params(params)
+        L, y, F = np.zeros(P), np.zeros(P), np.zeros(P)
+        desc = np.zeros((P, DESC)) if want_desc else None
+        lw, lg = lobes(g)
+        lib().om_tpl_query(self.h, float(sigma_t), float(albedo), len(lw), _ptr(lw, _dp), _ptr(lg, _dp),
+                           float(params["lam"]), float(params["gamma"]), float(radiance), _ptr(flat, _dp),
+                           int(params["width"]), int(params["n_linear"]), _ptr(pts, _fp), _ptr(dirs, _fp), P,
+                           _ptr(L, _dp), _ptr(y, _dp), _ptr(F, _dp), _ptr(desc, _dp))
+        out = {"L": L, "y": y, "F": F}
+        if want_desc:
+            out["desc"] = desc
         return out
 
     def query(self, params, pts, dirs, sigma_t, albedo, g, radiance=1.0, want_desc=False, volume=False):

@@ -754,3 +754,226 @@ def test_batch_order_invariance():
     perm = np.random.default_rng(3).permutation(len(pts))
     part = M.query(params, pts[perm], dirs[perm], 8.0, 0.99, 0.85)["L"]
     np.testing.assert_array_equal(full[perm], part)
+
+
+# ---- the paper's templates (Sec. III.B.2, eq. 2-4) ----------------------------
+
+def test_template_counts():
+    # the per-layer counts as printed: 6, 8, ..., 48 (sum 194, where the text
+    # says 182) and 32, 16, 16, 8 (sum 72)
+    c = oracle.tpl_counts()
+    assert c[:8] == [6, 8, 12, 16, 24, 32, 48, 48] and sum(c[:8]) == 194
+    assert c[8:] == [32, 16, 16, 8] and sum(c[8:]) == 72
+    assert oracle.TPL_SITES == 266
+
+
+def test_template_points_lie_in_their_regions():
+    # layer 0: the centre and 5 points on the unit sphere; layers 1-7: the shell
+    # 1/2 <= |u| <= 1; cone layer h: axial t in [h/4, (h+1)/4], radius <= t
+    u0 = oracle.tpl_unit(0)
+    assert np.all(u0[0] == 0.0) and np.all(np.linalg.norm(u0[1:], axis=1) > 0)
+    assert np.all(np.linalg.norm(u0, axis=1) <= 1.0 + 1e-15)
+    for k in range(1, 8):
+        r = np.linalg.norm(oracle.tpl_unit(k), axis=1)
+        assert np.all((r >= 0.5 - 1e-15) & (r <= 1.0 + 1e-15)), k
+        assert len(np.unique(np.round(oracle.tpl_unit(k), 12), axis=0)) == len(r)   # distinct points
+    for h in range(4):
+        u = oracle.tpl_unit(8 + h)
+        assert np.all((u[:, 0] >= h / 4) & (u[:, 0] <= (h + 1) / 4))
+        assert np.all(np.hypot(u[:, 1], u[:, 2]) <= u[:, 0] + 1e-15)
+
+
+def test_template_uniformity_measure_matches_nearest_neighbours():
+    # eq. (3): D(S_i) is the mean nearest-neighbour distance (scipy's k-d tree)
+    from scipy.spatial import cKDTree
+    for k in range(12):
+        u = oracle.tpl_unit(k)
+        d, _ = cKDTree(u).query(u, k=2)
+        assert oracle.tpl_D(k) == pytest.approx(d[:, 1].mean(), rel=1e-13), k
+
+
+def test_templates_are_more_even_than_random_sets():
+    # "evenly distributed": each layer's D(S_i) exceeds the 95th percentile
+    # of D over 200 seeded sets of as many points drawn uniformly in the same
+    # region (ball, shell, or the layer's frustum of the cone)
+    from scipy.spatial import cKDTree
+    r = np.random.default_rng(3)
+    for k in range(12):
+        n = oracle.tpl_counts()[k]
+        vals = []
+        for _ in range(200):
+            if k < 8:
+                v = r.standard_normal((n, 3))
+                v /= np.linalg.norm(v, axis=1, keepdims=True)
+                lo = 0.0 if k == 0 else 0.125
+                v *= np.cbrt(r.uniform(lo, 1.0, (n, 1)))
+            else:
+                lo, hi = (k - 8) / 4, (k - 7) / 4
+                t = np.cbrt(lo ** 3 + r.random(n) * (hi ** 3 - lo ** 3))
+                rad = np.sqrt(r.random(n)) * t
+                a = r.uniform(0, 2 * np.pi, n)
+                v = np.stack([t, rad * np.cos(a), rad * np.sin(a)], axis=1)
+            vals.append(cKDTree(v).query(v, k=2)[0][:, 1].mean())
+        assert oracle.tpl_D(k) > np.percentile(vals, 95), k
+
+
+def test_template_radii_follow_eq4():
+    # r_i = 2^(i-1) xi_i / (2^8 D(S_i)), xi_i = 1 - 0.08 min(i, 5): the
+    # layer's nearest-neighbour spacing is 2^(i-1) xi_i voxels of a 256^3 grid
+    for i in range(8):
+        xi = 1.0 - 0.08 * min(i, 5)
+        assert oracle.tpl_radius(i) * oracle.tpl_D(i) * 256 == pytest.approx(2.0 ** (i - 1) * xi, rel=1e-14)
+    r = [oracle.tpl_radius(i) for i in range(8)]
+    assert all(b > a for a, b in zip(r, r[1:]))
+
+
+def test_light_extent_closed_forms():
+    s3 = 1 / np.sqrt(3)
+    assert oracle.tpl_light_extent([0, 1, 0], [0.5, 0.5, 0.5]) == pytest.approx(0.5, rel=1e-15)
+    assert oracle.tpl_light_extent([s3, s3, s3], [0.5, 0.5, 0.5]) == pytest.approx(0.5 * np.sqrt(3), rel=1e-14)
+    assert oracle.tpl_light_extent([0, 0, -1], [0.2, 0.3, 0.9]) == pytest.approx(0.9, rel=1e-15)
+    assert oracle.tpl_light_extent([1, 0, 0], [0.5, 1.5, 0.5]) == 0.0            # misses the cube
+    assert oracle.tpl_light_extent([1, 0, 0], [0.5, 0.5, 0.5]) == pytest.approx(0.5)
+    assert oracle.tpl_light_extent([1, 0, 0], [-0.5, 0.5, 0.5]) == pytest.approx(1.5)   # enters, far exit
+    assert oracle.tpl_light_extent([-1, 0, 0], [-0.5, 0.5, 0.5]) == 0.0          # the cube is behind
+
+
+def _expected_tpl_levels(n, L):
+    # level whose voxel matches the layer's spacing: round(log2(spacing * n)),
+    # clamped to [0, L-1]
+    out = []
+    for i in range(8):
+        x = 2.0 ** (i - 1) * (1 - 0.08 * min(i, 5)) / 256 * n
+        out.append(int(min(max(np.floor(np.log2(x) + 0.5), 0), L - 1)))
+    return out
+
+
+@pytest.mark.parametrize("light", [(0.3, 0.9, 0.3), (0.2, -0.1, 0.8)])
+def test_template_features_homogeneous_medium(light):
+    # rho == c: the density is c at every template point inside the closed
+    # cube and 0 outside; the graded transmittance at a point whose ray to
+    # the light leaves through the light face is exp(-lam^(m+1) sigma_t c d),
+    # d its distance to that face, which also pins each layer's level m
+    c, n, sigma_t, lam = 0.5, 32, 8.0, 0.6
+    M = oracle.Medium(medium.constant(n, c))
+    M.set_light(light)
+    fr = M.light_frame()
+    l = fr["l"]
+    r = np.random.default_rng(1)
+    pts = r.uniform(0.3, 0.7, (6, 3)).astype(np.float32)
+    dirs = np.tile(np.array([[0, 0, -1]], np.float32), (6, 1))
+    f = M.tpl_features(sigma_t, 0.5, lam, pts, dirs)
+    counts = oracle.tpl_counts()
+    first = np.cumsum([0] + counts)
+    a = fr["a"]
+    face = 1.0 if l[a] > 0 else 0.0
+    levels = _expected_tpl_levels(n, M.levels)
+    checked = 0
+    for p in range(len(pts)):
+        x = pts[p].astype(np.float64)
+        dl = oracle.tpl_light_extent(l, x)
+        for k in range(12):
+            u = oracle.tpl_unit(k)
+            if k < 8:
+                s = x + oracle.tpl_radius(k) * u
+                m = levels[k]
+            else:
+                e1, e2 = _duff_onb(l)
+                s = x + dl * (u[:, :1] * l + u[:, 1:2] * e1 + u[:, 2:3] * e2)
+                sp = oracle.tpl_D(k) * dl * n
+                m = int(min(max(np.floor(np.log2(sp) + 0.5), 0), M.levels - 1)) if sp > 0 else 0
+            inside = np.all((s >= 0) & (s <= 1), axis=1)
+            got_r = f["rho"][p, first[k]:first[k + 1]]
+            np.testing.assert_array_equal(got_r[~inside], 0.0)
+            np.testing.assert_allclose(got_r[inside], c, rtol=1e-14)
+            got_t = f["tbar"][p, first[k]:first[k + 1]]
+            for j in range(counts[k]):
+                t = (face - s[j, a]) / l[a]
+                ex = s[j] + t * l
+                lat = ex[[fr["b"], fr["c"]]]
+                # (rays whose interpolation neighbours, a voxel of the level
+                # to either side, stay inside too: two voxels of margin)
+                mg = 2.0 / (n >> m)
+                if inside[j] and np.all((lat >= mg) & (lat <= 1 - mg)) and mg <= s[j, a] <= 1 - mg:
+                    assert got_t[j] == pytest.approx(math.exp(-lam ** (m + 1) * sigma_t * c * t), rel=1e-10)
+                    checked += 1
+    assert checked > 300
+
+
+def _duff_onb(l):
+    s = 1.0 if l[2] >= 0 else -1.0
+    a = -1.0 / (s + l[2])
+    b = l[0] * l[1] * a
+    return (np.array([1.0 + s * l[0] * l[0] * a, s * b, -s * l[0]]),
+            np.array([b, s + l[1] * l[1] * a, -l[1]]))
+
+
+def test_duff_frame_is_orthonormal():
+    for l in np.random.default_rng(2).standard_normal((50, 3)):
+        l = l / np.linalg.norm(l)
+        e1, e2 = _duff_onb(l)
+        B = np.stack([l, e1, e2])
+        np.testing.assert_allclose(B @ B.T, np.eye(3), atol=1e-14)
+
+
+def test_template_phase_and_statistics():
+    # the centre point (layer 0, point 0) carries f(w.l); at g = 0 every other
+    # point carries log1p(1/(4 pi)^2); the squeeze vector holds each layer's
+    # means and maxima, g and alpha
+    n = 16
+    M = oracle.Medium(medium.fbm_cloud(n, seed=2))
+    M.set_light((0.3, 0.9, 0.3))
+    l = M.light_frame()["l"]
+    pts, dirs = camera.random_points(20, seed=4, lo=0.1, hi=0.9)
+    for g in (0.0, 0.7):
+        f = M.tpl_features(8.0, g, 0.6, pts, dirs)
+        w = dirs.astype(np.float64)
+        w /= np.linalg.norm(w, axis=1, keepdims=True)
+        wl = w @ l
+        for p in range(len(pts)):
+            assert f["phi"][p, 0] == pytest.approx(math.log1p(oracle.hg(g, wl[p])), rel=1e-14)
+            if g == 0.0:
+                np.testing.assert_allclose(f["phi"][p, 1:], math.log1p(1 / (4 * np.pi) ** 2), rtol=1e-14)
+        first = np.cumsum([0] + oracle.tpl_counts())
+        for k in range(12):
+            sl = slice(first[k], first[k + 1])
+            v = f["stats"][:, k]
+            for col, key, red in ((0, "rho", np.mean), (1, "phi", np.mean), (2, "tbar", np.mean),
+                                  (3, "rho", np.max), (4, "phi", np.max), (5, "tbar", np.max)):
+                np.testing.assert_allclose(v[:, col], red(f[key][:, sl], axis=1), rtol=1e-13)
+            np.testing.assert_allclose(v[:, 6], g)
+            np.testing.assert_allclose(v[:, 7], np.arccos(np.clip(wl, -1, 1)), rtol=1e-13)
+
+
+def test_template_descriptor_layout_and_probes():
+    # per layer: tbar, rho, phi (template order), then the squeeze vector;
+    # zeros up to the albedo entry 1056.  Zero weights give the single-scatter
+    # term; a selector network returns any chosen entry.
+    n = 16
+    d = medium.fbm_cloud(n, seed=3)
+    M = oracle.Medium(d)
+    M.set_light((0.3, 0.9, 0.3))
+    pts, dirs = camera.random_points(12, seed=5, lo=0.05, hi=0.95)
+    params = weights.he_init(16, 3, seed=1)
+    f = M.tpl_features(8.0, 0.85, 0.6, pts, dirs)
+    q = M.tpl_query(params, pts, dirs, 8.0, 0.9, 0.85, 1.0, want_desc=True)
+    first = np.cumsum([0] + oracle.tpl_counts())
+    for p in range(len(pts)):
+        exp = []
+        for k in range(12):
+            sl = slice(first[k], first[k + 1])
+            exp += list(f["tbar"][p, sl]) + list(f["rho"][p, sl]) + list(f["phi"][p, sl]) + list(f["stats"][p, k])
+        assert len(exp) == 894
+        np.testing.assert_allclose(q["desc"][p, :894], exp, rtol=1e-15)
+        np.testing.assert_array_equal(q["desc"][p, 894:1056], 0.0)
+        assert q["desc"][p, 1056] == 0.9
+    z = weights.zeros_like(params)
+    qz = M.tpl_query(z, pts, dirs, 8.0, 0.9, 0.85, 2.0)
+    np.testing.assert_allclose(qz["L"], 2.0 * f["f0"], rtol=1e-14)
+    for entry in (0, 17, 893, 1056):
+        s = weights.zeros_like(params)
+        s["A"][0][0, entry] = 1.0
+        s["A"][1][0, 0] = 1.0
+        s["A"][2][0, 0] = 1.0
+        y = M.tpl_query(s, pts, dirs, 8.0, 0.9, 0.85, 1.0)["y"]
+        np.testing.assert_allclose(y, np.maximum(q["desc"][:, entry], 0.0), rtol=1e-14)
