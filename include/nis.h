@@ -180,6 +180,31 @@ int32_t nis_set_light(nis_ctx *ctx, int32_t medium, const float dir[3], float ra
  */
 int32_t nis_set_weights(nis_ctx *ctx, const void *blob, size_t nbytes);
 
+/* template kinds (nis_set_templates) */
+#define NIS_TEMPLATES_LATTICE 0  /* 12 light-aligned 5x5x9 lattices with the 3D-CNN (default) */
+#define NIS_TEMPLATES_PAPER 1    /* the paper's diffuse sphere and highlight cone (Sec. III.B.2) */
+
+/*
+ * nis_set_templates -- which sampling templates the context's queries and
+ * renders use.  NIS_TEMPLATES_PAPER: the paper's own templates (Sec. III.B.2,
+ * eq. 2-4): a diffuse sphere of 8 layers (6, 8, 12, 16, 24, 32, 48, 48
+ * points; layer 0 the centre and 5 points on its sphere, layer i >= 1 a
+ * shell from half its radius to its radius r_i = 2^(i-1) xi_i / (2^8 D(S_i)),
+ * xi_i = 1 - 0.08 min(i, 5), D the mean nearest-neighbour distance of the
+ * unit set, eq. 3) and a highlight cone of 4 layers (32, 16, 16, 8 points)
+ * with its apex at the point, its axis towards the light, scaled to the
+ * distance at which the light enters the medium, its layers the four equal
+ * quarters of that distance.  Each layer samples the pyramid level whose
+ * voxel matches its point spacing.  The network's input is then, per layer,
+ * the graded transmittances, densities and phase features at its points
+ * (template order) and the squeeze vector of eq. (24), zeros up to the
+ * albedo entry at index 1056 (the same weight blob layout; the first layer's
+ * columns 894..1055 meet zeros).  Volume phases are not available there
+ * (NIS_E_UNSUPPORTED at query time).  The frame server keeps the lattices.
+ * Errors: NIS_E_INVALID for an unknown kind.
+ */
+int32_t nis_set_templates(nis_ctx *ctx, int32_t kind);
+
 /* NIS_FP32 (default), NIS_BF16 or NIS_FP8.  FP8 needs the activation scales
  * of the weight blob's fp8 block (x = code * scale, entries > 0) or of
  * nis_calibrate_fp8; without them NIS_FP8 is NIS_E_UNSUPPORTED (here, and for
@@ -442,6 +467,16 @@ int32_t nis_debug_path_pairs(nis_ctx *ctx, int32_t medium, int32_t level, float 
 int32_t nis_debug_features(nis_ctx *ctx, int32_t medium, const float *d_points,
                            const float *d_view_dirs, int64_t n, float *d_tbar, float *d_rho,
                            float *d_phi, float *d_stats, float *d_tp, float *d_f0);
+
+/*
+ * Gather stage at the paper's templates (whatever nis_set_templates holds;
+ * synchronous): tbar/rho/phi [n][266] in template order (the 8 diffuse
+ * layers, then the 4 highlight layers), stats [n][12][8] (eq. 24), f0 [n]
+ * (may be NULL).  The other arrays are required.
+ */
+int32_t nis_debug_template_features(nis_ctx *ctx, int32_t medium, const float *d_points,
+                                    const float *d_view_dirs, int64_t n, float *d_tbar,
+                                    float *d_rho, float *d_phi, float *d_stats, float *d_f0);
 
 /*
  * Descriptor and network output on device arrays (synchronous), at the

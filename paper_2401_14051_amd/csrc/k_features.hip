@@ -852,6 +852,243 @@ k_features(FeatArgs A)
     }
 }
 
+// ---- the gather at the paper's own templates (Sec. III.B.2, eq. 2-4) -----
+//
+// Diffuse layer k < 8: point s = p + r_k u (u its unit template point, r_k its
+// radius by eq. 4), level m_k matched to the layer's point spacing.
+// Highlight layer h: point s = p + d_l o, o the unit cone point along l and
+// d_l the distance from p towards the light to where that ray leaves the
+// unit cube; the level is matched to the spacing D(C_h) d_l.  At each point:
+// the density (zero outside the closed cube), the graded transmittance
+// exp(-lambda^(m+1) sigma_t D_m) and the phase feature log1p(f(w.d) f(d.l))
+// (f(w.l) where the point is p itself); per layer the squeeze vector of
+// eq. (24).  The descriptor holds, per layer, its transmittances, densities
+// and phase features in template order and its squeeze vector, then zeros up
+// to the albedo entry (index 1056, as in the lattice descriptor).
+//
+// Work split: a workgroup of 4 waves, one point per wave, a lane per template
+// point (266 points, five rounds of 64 lanes); values are staged in LDS for
+// the per-layer statistics (a lane per layer) and the descriptor row.
+constexpr int kTplWaves = 4;
+
+__device__ __forceinline__ int tpl_layer_of(int t)
+{
+    int k = 0;
+#pragma unroll
+    for (int i = 1; i < kLayers; i++) k += t >= tpl_first(i) ? 1 : 0;
+    return k;
+}
+
+// the level whose voxel matches a point spacing (unit-cube length) on an n^3
+// grid: the number of m >= 0 with spacing * n >= sqrt(2) 2^m, below L
+__device__ __forceinline__ int tpl_level(double spacing, int n, int L)
+{
+#pragma clang fp contract(off)
+    const double x = spacing * n;
+    int m = 0;
+    while (m < L - 1 && x >= 1.4142135623730951 * ldexp(1.0, m)) m++;
+    return m;
+}
+
+// distance from x towards the light to where that ray leaves the unit cube
+// (0 when it misses the cube or the cube lies behind x)
+__device__ __forceinline__ double tpl_light_extent(const double l[3], const double x[3])
+{
+#pragma clang fp contract(off)
+    double t0 = -INFINITY, t1 = INFINITY;
+    for (int d = 0; d < 3; d++) {
+        if (l[d] == 0.0) {
+            if (x[d] < 0.0 || x[d] > 1.0) return 0.0;
+            continue;
+        }
+        const double a = (0.0 - x[d]) / l[d], b = (1.0 - x[d]) / l[d];
+        const double lo = a < b ? a : b, hi = a < b ? b : a;
+        if (lo > t0) t0 = lo;
+        if (hi < t1) t1 = hi;
+    }
+    if (t1 < t0 || t1 <= 0.0) return 0.0;
+    return t1;
+}
+
+__device__ __forceinline__ double tpl_coord(double x, double scale, double o)
+{
+#pragma clang fp contract(off)
+    return x + scale * o;
+}
+
+// density of level m at s: zero outside the closed unit cube, else index-clamped trilinear
+__device__ __forceinline__ float tpl_rho(const MediumView& mv, int m, const double s[3])
+{
+    if (s[0] < 0.0 || s[0] > 1.0 || s[1] < 0.0 || s[1] > 1.0 || s[2] < 0.0 || s[2] > 1.0) return 0.f;
+    const int nm = mv.lev[m].n;
+    const float* R = mv.rho + mv.lev[m].rho_off;
+    int i0[3], i1[3];
+    float w[3];
+    for (int d = 0; d < 3; d++) {
+        const double g = s[d] * nm - 0.5, f = floor(g);
+        i0[d] = clampi((int)f, 0, nm - 1);
+        i1[d] = clampi((int)f + 1, 0, nm - 1);
+        w[d] = (float)(g - f);
+    }
+    auto at = [&](int x, int y, int z) { return R[((int64_t)z * nm + y) * nm + x]; };
+    const float c00 = lerpf(at(i0[0], i0[1], i0[2]), at(i1[0], i0[1], i0[2]), w[0]);
+    const float c10 = lerpf(at(i0[0], i1[1], i0[2]), at(i1[0], i1[1], i0[2]), w[0]);
+    const float c01 = lerpf(at(i0[0], i0[1], i1[2]), at(i1[0], i0[1], i1[2]), w[0]);
+    const float c11 = lerpf(at(i0[0], i1[1], i1[2]), at(i1[0], i1[1], i1[2]), w[0]);
+    return lerpf(lerpf(c00, c10, w[1]), lerpf(c01, c11, w[1]), w[2]);
+}
+
+template <int PREC, bool DBG, bool F8>
+__global__ void __launch_bounds__(64 * kTplWaves)
+k_template_features(TplArgs A)
+{
+    typedef Mfma<PREC> M;
+    typedef typename M::elem E;
+    __shared__ float vals[kTplWaves][3][kTplSites];   // tbar, rho, phi of each template point
+    __shared__ float stv[kTplWaves][kLayers][kStats];
+    const MediumView& mv = A.mv;
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int64_t npts = A.count ? min(max((int64_t)*A.count - A.count_off, (int64_t)0), A.npts) : A.npts;
+    const int64_t p = (int64_t)blockIdx.x * kTplWaves + wave;
+    if ((int64_t)blockIdx.x * kTplWaves >= npts) return;
+    const bool live = p < npts;
+    const int64_t pc = live ? p : npts - 1;
+
+    double x[3], w[3];
+    for (int d = 0; d < 3; d++) {
+        x[d] = A.pts[3 * pc + d];
+        w[d] = A.dirs[3 * pc + d];
+    }
+    const double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    for (int d = 0; d < 3; d++) w[d] /= wn;
+    const double wl = w[0] * mv.l[0] + w[1] * mv.l[1] + w[2] * mv.l[2];
+    const float wf[3] = {(float)w[0], (float)w[1], (float)w[2]};
+    const double dlen = tpl_light_extent(mv.l, x);
+    int mh[kLayers - kDiffuse];
+    for (int h = 0; h < kLayers - kDiffuse; h++) mh[h] = tpl_level(A.dh[h] * dlen, mv.n0, mv.levels);
+    // one lobe's term of the phase at w . d for a site table entry (as in k_features)
+    auto lobe = [&](int i, const float4& e) __attribute__((always_inline)) {
+        const float gs = mv.ph_s[i];
+        const float dx = wf[0] - gs * e.x, dy = wf[1] - gs * e.y, dz = wf[2] - gs * e.z;
+        const float den = mv.ph_c[i] + mv.ph_a[i] * (dx * dx + dy * dy + dz * dz);
+        const float r = __builtin_amdgcn_rsqf(den);
+        return mv.ph_k[i] * e.w * (r * r * r);
+    };
+    const float4 centre = make_float4((float)mv.l[0], (float)mv.l[1], (float)mv.l[2], 1.f);
+
+    for (int t = lane; t < kTplSites; t += 64) {
+        const int k = tpl_layer_of(t);
+        double s[3];
+        int m;
+        if (k < kDiffuse) {
+            for (int d = 0; d < 3; d++) s[d] = tpl_coord(x[d], A.radius[k], A.tab->off[t][d]);
+            m = A.mdiff[k];
+        } else {
+            for (int d = 0; d < 3; d++) s[d] = tpl_coord(x[d], dlen, A.tab->off[t][d]);
+            m = mh[k - kDiffuse];
+        }
+        const Level& lv = mv.lev[m];
+        const int nm = lv.n;
+        const float r = tpl_rho(mv, m, s);
+        // path density at s (sheared lookup, index-clamped trilinear)
+        double g[3];
+        for (int d = 0; d < 3; d++) g[d] = s[d] * nm - 0.5;
+        const double Jf = mv.sigma > 0 ? (nm - 1) - g[mv.a] : g[mv.a];
+        const double Uf = g[mv.b] + Jf * mv.sb, Vf = g[mv.c] + Jf * mv.sc;
+        const double fu = floor(Uf), fv = floor(Vf), fj = floor(Jf);
+        const float Dv = sample_D(mv.dpairs + lv.q_off, lv, (int)fu, (int)fv, (int)fj, (float)(Uf - fu),
+                                  (float)(Vf - fv), (float)(Jf - fj));
+        const float T = __builtin_amdgcn_exp2f(-A.coef[m] * 1.44269504088896341f * Dv);
+        const bool at_p = s[0] == x[0] && s[1] == x[1] && s[2] == x[2];
+        const float4 e = at_p ? centre : A.tab->site[t];
+        float P = lobe(0, e);
+        for (int i = 1; i < mv.nl; i++) P += lobe(i, e);
+        const float ph = __logf(1.f + P);
+        vals[wave][0][t] = T;
+        vals[wave][1][t] = r;
+        vals[wave][2][t] = ph;
+        if (DBG && live) {
+            A.dbg_tbar[p * kTplSites + t] = T;
+            A.dbg_rho[p * kTplSites + t] = r;
+            A.dbg_phi[p * kTplSites + t] = ph;
+        }
+    }
+    __syncthreads();
+    // squeeze vector of eq. (24) per layer, one lane per layer
+    if (lane < kLayers) {
+        const int k = lane, f = tpl_first(k), n = tpl_count(k);
+        float ts = 0.f, rs = 0.f, ps = 0.f, tm = -INFINITY, rm = -INFINITY, pm = -INFINITY;
+        for (int j = 0; j < n; j++) {
+            const float T = vals[wave][0][f + j], r = vals[wave][1][f + j], ph = vals[wave][2][f + j];
+            ts += T, rs += r, ps += ph;
+            tm = fmaxf(tm, T), rm = fmaxf(rm, r), pm = fmaxf(pm, ph);
+        }
+        const float inv = 1.f / (float)n;
+        const float v[kStats] = {rs * inv, ps * inv, ts * inv, rm, pm, tm, mv.g,
+                                 (float)acos(fmin(1.0, fmax(-1.0, wl)))};
+        for (int i = 0; i < kStats; i++) {
+            stv[wave][k][i] = v[i];
+            if (DBG && live) A.dbg_stats[(p * kLayers + k) * kStats + i] = v[i];
+        }
+    }
+    if (lane == kLayers && live) {
+        // single-scatter term f(w.l) T(p) (eq. 19, eq. 15)
+        const Level& l0 = mv.lev[0];
+        double g[3];
+        for (int d = 0; d < 3; d++) g[d] = x[d] * l0.n - 0.5;
+        const double Jf = mv.sigma > 0 ? (l0.n - 1) - g[mv.a] : g[mv.a];
+        const double Uf = g[mv.b] + Jf * mv.sb, Vf = g[mv.c] + Jf * mv.sc;
+        const double fu = floor(Uf), fv = floor(Vf), fj = floor(Jf);
+        const float D0 = sample_D(mv.dpairs + l0.q_off, l0, (int)fu, (int)fv, (int)fj, (float)(Uf - fu),
+                                  (float)(Vf - fv), (float)(Jf - fj));
+        A.f0[p] = (float)(hg64(mv, wl) * (double)expf(-mv.sigma_t * D0));
+    }
+    __syncthreads();
+    if (!live) return;
+    // the descriptor row: per layer tbar, rho, phi (template order), squeeze vector
+    const int rowlen = F8 ? kDescF8 : kDescPad;
+    for (int e = lane; e < rowlen; e += 64) {
+        float v = 0.f;
+        if (e < kTplFeat) {
+            int k = 0, base = 0;
+            while (e >= base + 3 * tpl_count(k) + kStats) {
+                base += 3 * tpl_count(k) + kStats;
+                k++;
+            }
+            const int o = e - base, n = tpl_count(k);
+            v = o < 3 * n ? vals[wave][o / n][tpl_first(k) + o % n] : stv[wave][k][o - 3 * n];
+        } else if (e == kDesc - 1) {
+            v = mv.albedo;
+        }
+        if constexpr (F8) {
+            reinterpret_cast<uint8_t*>(A.desc)[p * kDescF8 + e] = e < kTplFeat || e == kDesc - 1 ? fp8_code(v * A.desc_inv_scale) : 0;
+        } else {
+            reinterpret_cast<E*>(A.desc)[p * kDescPad + e] = M::cvt(v);
+        }
+    }
+}
+
+hipError_t launch_template_features(int prec, const TplArgs& a, hipStream_t s)
+{
+    if (a.npts <= 0) return hipSuccess;
+    const int64_t blocks = (a.npts + kTplWaves - 1) / kTplWaves;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const bool dbg = a.dbg_tbar || a.dbg_rho || a.dbg_phi || a.dbg_stats;
+    if (dbg && !(a.dbg_tbar && a.dbg_rho && a.dbg_phi && a.dbg_stats)) return hipErrorInvalidValue;
+    const dim3 g((int)blocks), b(64 * kTplWaves);
+    if (prec == kPrecFP8) {
+        if (dbg) hipLaunchKernelGGL((k_template_features<kPrecBF16, true, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_template_features<kPrecBF16, false, true>), g, b, 0, s, a);
+    } else if (prec == kPrecBF16) {
+        if (dbg) hipLaunchKernelGGL((k_template_features<kPrecBF16, true, false>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_template_features<kPrecBF16, false, false>), g, b, 0, s, a);
+    } else {
+        if (dbg) hipLaunchKernelGGL((k_template_features<kPrecFP32, true, false>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_template_features<kPrecFP32, false, false>), g, b, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
 // Rewrites the albedo entry of n descriptor rows: the channels of a coloured
 // albedo share every other entry.  eta is the entry's value as stored (for
 // the FP8 descriptor, already divided by its scale).

@@ -30,6 +30,28 @@ struct FeatArgs {
     int64_t count_off;           // min(npts, *count - count_off) points
 };
 
+// The gather at the paper's templates (k_template_features).
+struct TplArgs {
+    MediumView mv;
+    const TplTables* tab;
+    const float* pts;
+    const float* dirs;
+    int64_t npts;
+    float coef[kMaxLevels];      // lambda^(m+1) * sigma_t per level m
+    double radius[kDiffuse];     // diffuse layer radii (eq. 4), unit-cube lengths
+    int mdiff[kDiffuse];         // diffuse layer levels
+    double dh[kLayers - kDiffuse];   // highlight layers' eq. (3) measure of the unit cone sets
+    void* desc;                  // [npts][kDescPad] (FP8 output: [npts][kDescF8] E4M3 codes)
+    float desc_inv_scale;        // FP8 output only: 1 / the backbone's first input scale
+    float* f0;                   // [npts] f(w.l) T(p)
+    float* dbg_tbar;             // optional [npts][kTplSites]
+    float* dbg_rho;              // optional [npts][kTplSites]
+    float* dbg_phi;              // optional [npts][kTplSites]
+    float* dbg_stats;            // optional [npts][12][8]
+    const int* count;            // optional device point count, as in FeatArgs
+    int64_t count_off;
+};
+
 struct MlpArgs {
     const void* x;                   // [npts][kDescPad] descriptor ([npts][kDescF8] codes for FP8)
     int64_t npts;
@@ -89,6 +111,7 @@ struct GaussLegendre64 {
 hipError_t launch_volume_tables(const MediumView& mv, const GaussLegendre64& gl, SiteTables* tab, float* vtab,
                                 hipStream_t s);
 hipError_t launch_features(int prec, const FeatArgs& a, hipStream_t s);
+hipError_t launch_template_features(int prec, const TplArgs& a, hipStream_t s);
 hipError_t launch_desc_to_f32(int prec, const void* src, float* dst, int64_t n, float scale, hipStream_t s);
 hipError_t launch_mlp(int prec, const MlpArgs& a, hipStream_t s);
 // eta: the albedo entry as stored (FP8: already divided by the descriptor's scale)

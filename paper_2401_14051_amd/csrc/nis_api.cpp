@@ -238,6 +238,167 @@ void refresh_tables(const Medium* M, LightState* ls, const Phase& ph, bool volum
     ls->tab_volume = volume;
 }
 
+// ---- the paper's templates (Sec. III.B.2, eq. 2-4) -------------------------
+//
+// Unit templates (the paper leaves the construction open; these readings are
+// shared with the checks of this library):
+//  * diffuse layer 0: the centre and 5 points on the unit sphere; layer i >= 1:
+//    n_i points in the shell 1/2 <= |u| <= 1.  Directions are spherical
+//    Fibonacci points (z stratified, golden-angle azimuth), and in the shell
+//    each point takes an equal-volume radial stratum from the additive
+//    sequence frac(1/2 + k c), c = 0.5698402909980532 (decorrelated from the
+//    golden angle);
+//  * highlight layer h (cone with apex at the point, axis l, unit length and
+//    unit base radius): axial t dividing the layer's frustum volume at
+//    (k + 1/2)/n, radius sqrt(frac(1/2 + k c)) t, golden-angle azimuth, in the
+//    orthonormal frame of l of Duff et al. (2017);
+//  * eq. (3): D(S) is the mean nearest-neighbour distance of a unit set;
+//    eq. (4): r_i = 2^(i-1) xi_i / (2^8 D(S_i)), xi_i = 1 - 0.08 min(i, 5).
+// All in double precision, built with contraction off (each product and sum
+// rounded once), so that the sampled positions' in-cube decisions are those
+// of the definition.
+namespace {
+
+struct TplGeometry {
+    double unit[kTplSites][3];   // diffuse: world axes; highlight: (t, x1, x2) in the frame of l
+    double D[kLayers];
+    double radius[kDiffuse];
+};
+
+void tpl_unit_point(int layer, int k, double u[3])
+{
+    const double golden = 2.39996322972865332, step = 0.5698402909980532;
+    const int n = tpl_count(layer);
+    if (layer < kDiffuse) {
+        int kk = k, nn = n;
+        double rad;
+        if (layer == 0) {
+            if (k == 0) {
+                u[0] = u[1] = u[2] = 0.0;
+                return;
+            }
+            kk = k - 1;
+            nn = n - 1;
+            rad = 1.0;
+        } else {
+            const double a = 0.5 + kk * step;
+            const double wv = a - std::floor(a);
+            rad = std::cbrt(0.125 + wv * 0.875);
+        }
+        const double z = 1.0 - (2.0 * kk + 1.0) / nn;
+        const double rxy = std::sqrt(1.0 - z * z);
+        const double az = kk * golden;
+        u[0] = rad * (rxy * std::cos(az));
+        u[1] = rad * (rxy * std::sin(az));
+        u[2] = rad * z;
+    } else {
+        const int h = layer - kDiffuse;
+        const double lo = h / 4.0, hi = (h + 1) / 4.0;
+        const double t = std::cbrt(lo * lo * lo + ((k + 0.5) / n) * (hi * hi * hi - lo * lo * lo));
+        const double a = 0.5 + k * step;
+        const double wv = a - std::floor(a);
+        const double rad = std::sqrt(wv) * t;
+        const double az = k * golden;
+        u[0] = t;
+        u[1] = rad * std::cos(az);
+        u[2] = rad * std::sin(az);
+    }
+}
+
+const TplGeometry& tpl_geometry()
+{
+    static const TplGeometry G = [] {
+        TplGeometry g;
+        for (int k = 0; k < kLayers; k++)
+            for (int j = 0; j < tpl_count(k); j++) tpl_unit_point(k, j, g.unit[tpl_first(k) + j]);
+        for (int k = 0; k < kLayers; k++) {
+            const int n = tpl_count(k), f = tpl_first(k);
+            double sum = 0.0;
+            for (int j = 0; j < n; j++) {
+                double best = INFINITY;
+                for (int i = 0; i < n; i++) {
+                    if (i == j) continue;
+                    const double dx = g.unit[f + j][0] - g.unit[f + i][0];
+                    const double dy = g.unit[f + j][1] - g.unit[f + i][1];
+                    const double dz = g.unit[f + j][2] - g.unit[f + i][2];
+                    const double d = std::sqrt(dx * dx + dy * dy + dz * dz);
+                    if (d < best) best = d;
+                }
+                sum += best;
+            }
+            g.D[k] = sum / n;
+        }
+        for (int i = 0; i < kDiffuse; i++) {
+            const double xi = 1.0 - 0.08 * (i < 5 ? i : 5);
+            g.radius[i] = std::ldexp(1.0, i - 1) * xi / (256.0 * g.D[i]);
+        }
+        return g;
+    }();
+    return G;
+}
+
+// level whose voxel matches a point spacing on an n^3 grid (below L)
+int tpl_level_host(double spacing, int n, int L)
+{
+    const double x = spacing * n;
+    int m = 0;
+    while (m < L - 1 && x >= 1.4142135623730951 * std::ldexp(1.0, m)) m++;
+    return m;
+}
+
+// the medium's phase (its lobes summed with their weights) in double precision
+double phase_value(const Phase& ph, double mu)
+{
+    double v = 0.0;
+    for (int i = 0; i < ph.n; i++) {
+        const double g = ph.g[i];
+        const double den = 1.0 + g * g - 2.0 * g * mu;
+        v += ph.w[i] * ((1.0 - g * g) / (4.0 * M_PI)) / (den * std::sqrt(den));
+    }
+    return v;
+}
+
+}  // namespace
+
+// Template tables of a light and phase: the highlight points in world axes
+// (o = t l + x1 e1 + x2 e2) and every point's unit direction and f(d . l).
+void refresh_tpl_tables(LightState* ls, const Phase& ph, hipStream_t s, bool may_alloc)
+{
+    if (ls->tpl_valid && same_phase(ls->tpl_phase, ph)) return;
+    if (!may_alloc && ls->tpl.bytes < sizeof(TplTables))
+        fail(NIS_E_STATE, "the light's template tables are not allocated: set the light first");
+    ls->tpl.reserve(sizeof(TplTables), "template tables");
+    const TplGeometry& G = tpl_geometry();
+    const double* l = ls->l;
+    // orthonormal frame of l (Duff et al. 2017)
+    const double sg = l[2] >= 0.0 ? 1.0 : -1.0;
+    const double a = -1.0 / (sg + l[2]);
+    const double b = l[0] * l[1] * a;
+    const double e1[3] = {1.0 + sg * l[0] * l[0] * a, sg * b, -sg * l[0]};
+    const double e2[3] = {b, sg + l[1] * l[1] * a, -l[1]};
+    if (ls->tpl_host.size() != 1) ls->tpl_host.resize(1);
+    TplTables& T = ls->tpl_host[0];
+    for (int k = 0; k < kLayers; k++)
+        for (int j = 0; j < tpl_count(k); j++) {
+            const int t = tpl_first(k) + j;
+            const double* u = G.unit[t];
+            double o[3];
+            for (int d = 0; d < 3; d++) o[d] = k < kDiffuse ? u[d] : u[0] * l[d] + u[1] * e1[d] + u[2] * e2[d];
+            for (int d = 0; d < 3; d++) T.off[t][d] = o[d];
+            const double on = std::sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+            if (on > 0.0) {
+                const double dd[3] = {o[0] / on, o[1] / on, o[2] / on};
+                const double mu = dd[0] * l[0] + dd[1] * l[1] + dd[2] * l[2];
+                T.site[t] = make_float4((float)dd[0], (float)dd[1], (float)dd[2], (float)phase_value(ph, mu));
+            } else {
+                T.site[t] = make_float4((float)l[0], (float)l[1], (float)l[2], 1.f);   // the centre: f(w.l)
+            }
+        }
+    hip_check(hipMemcpyAsync(ls->tpl.p, &T, sizeof(TplTables), hipMemcpyHostToDevice, s), "template tables");
+    ls->tpl_valid = true;
+    ls->tpl_phase = ph;
+}
+
 void ensure_sweep(const Medium* M, LightState* ls, hipStream_t s)
 {
     if (!ls->valid) fail(NIS_E_STATE, "no light set for this medium");
@@ -541,6 +702,13 @@ Params rgb_params(const Medium* M)
     return P;
 }
 
+// The parameters of a query through the context: its template choice added.
+Params with_templates(const nis_ctx* ctx, Params P)
+{
+    P.templates = ctx->templates;
+    return P;
+}
+
 void light_layout(const Medium* M, const double l[3], LightState* ls)
 {
     for (int d = 0; d < 3; d++) ls->l[d] = l[d];
@@ -592,12 +760,14 @@ void set_light_state(const Medium* M, const double l[3], LightState* ls)
         ls->RT.release();
     ls->P.reserve((size_t)ls->pair_count * sizeof(float2), "light-axis density pairs");
     ls->DP.reserve((size_t)ls->dpair_count * sizeof(float2), "path-density pairs");
-    // the site tables too, so that a query under this light allocates nothing
+    // the site and template tables too, so that a query under this light allocates nothing
     ls->tab.reserve(sizeof(SiteTables), "site tables");
+    ls->tpl.reserve(sizeof(TplTables), "template tables");
     if (M->volume_phase) ls->vtab.reserve((size_t)kSites * kVBins * sizeof(float), "volume phase tables");
     ls->valid = true;
     ls->stale = true;
     ls->tab_valid = false;
+    ls->tpl_valid = false;
 }
 
 const char* precision_name(int prec) { return prec == kPrecFP32 ? "fp32" : prec == kPrecBF16 ? "bf16" : "fp8"; }
@@ -683,8 +853,11 @@ void run_query_in(const WsView& ws, const Net* net, int prec, const Medium* M, L
     if (ws.chunk <= 0 || !ws.desc || !ws.f0) fail(NIS_E_INTERNAL, "no scratch");
     if (prec == kPrecFP8 && !net->has_fp8)
         fail(NIS_E_UNSUPPORTED, "FP8 needs the activation scales: pass them in the weight blob or call nis_calibrate_fp8");
+    if (Pm.templates && Pm.volume)
+        fail(NIS_E_UNSUPPORTED, "volume phases are not available with the paper's templates");
     ensure_sweep(M, ls, s);
-    refresh_tables(M, ls, Pm.phase, Pm.volume, s, may_alloc);
+    if (Pm.templates) refresh_tpl_tables(ls, Pm.phase, s, may_alloc);
+    else refresh_tables(M, ls, Pm.phase, Pm.volume, s, may_alloc);
     const PackedNet& P = net->packed[prec];
     const int64_t chunk = ws.chunk;
     MediumView mv = make_view(M, ls, Pm, net);
@@ -718,7 +891,35 @@ void run_query_in(const WsView& ws, const Net* net, int prec, const Medium* M, L
         fa.dbg_phi = off(o.phi, kSites);
         fa.dbg_stats = off(o.stats, kLayers * kStats);
         fa.dbg_tp = off(o.tp, 1);
-        timed("features", s, [&] { return launch_features(prec, fa, s); });
+        if (Pm.templates) {
+            TplArgs ta;
+            std::memset(&ta, 0, sizeof(ta));
+            const TplGeometry& G = tpl_geometry();
+            ta.mv = mv;
+            ta.tab = ls->tpl.as<TplTables>();
+            ta.pts = fa.pts;
+            ta.dirs = fa.dirs;
+            ta.npts = cn;
+            for (int m = 0; m < M->levels; m++)
+                ta.coef[m] = (float)(std::pow((double)net->lam, m + 1) * (double)Pm.sigma_t);
+            for (int k = 0; k < kDiffuse; k++) {
+                ta.radius[k] = G.radius[k];
+                ta.mdiff[k] = tpl_level_host(G.radius[k] * G.D[k], M->n, M->levels);
+            }
+            for (int h = 0; h < kLayers - kDiffuse; h++) ta.dh[h] = G.D[kDiffuse + h];
+            ta.desc = fa.desc;
+            ta.desc_inv_scale = fa.desc_inv_scale;
+            ta.f0 = fa.f0;
+            ta.dbg_tbar = o.tbar ? o.tbar + p0 * kTplSites : nullptr;
+            ta.dbg_rho = o.rho ? o.rho + p0 * kTplSites : nullptr;
+            ta.dbg_phi = o.phi ? o.phi + p0 * kTplSites : nullptr;
+            ta.dbg_stats = fa.dbg_stats;
+            ta.count = d_count;
+            ta.count_off = p0;
+            timed("features", s, [&] { return launch_template_features(prec, ta, s); });
+        } else {
+            timed("features", s, [&] { return launch_features(prec, fa, s); });
+        }
         if (o.desc) {
             size_t eb = desc_row_bytes(prec);
             hip_check(hipMemcpyAsync((char*)o.desc + p0 * eb, ws.desc, cn * eb, hipMemcpyDeviceToDevice, s),
@@ -911,7 +1112,7 @@ void query_host(nis_ctx* ctx, int32_t medium, const float* points, const float* 
         if (d[0] == 0.f && d[1] == 0.f && d[2] == 0.f) fail(NIS_E_INVALID, "zero view direction");
     }
     Medium* M = get_medium(ctx, medium);
-    const Params P = channels == 3 ? rgb_params(M) : grey_params(M);
+    const Params P = with_templates(ctx, channels == 3 ? rgb_params(M) : grey_params(M));
     if (!ctx->net) fail(NIS_E_STATE, "no weights set");
     if (!M->light.valid) fail(NIS_E_STATE, "no light set for this medium");
     const size_t bytes = (size_t)n * (6 + channels) * sizeof(float);
@@ -1236,8 +1437,43 @@ int32_t nis_query_device(nis_ctx* ctx, int32_t medium, const float* d_points, co
         hipStream_t s = su.s;
         QueryOut o;
         o.radiance = d_out;
-        run_query(ctx->ws, ctx->net, ctx->precision, M, &M->light, grey_params(M), d_points, d_dirs, n, nullptr,
+        run_query(ctx->ws, ctx->net, ctx->precision, M, &M->light, with_templates(ctx, grey_params(M)), d_points, d_dirs, n, nullptr,
                   o, s);
+    });
+}
+
+int32_t nis_set_templates(nis_ctx* ctx, int32_t kind)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (kind != NIS_TEMPLATES_LATTICE && kind != NIS_TEMPLATES_PAPER) fail(NIS_E_INVALID, "unknown template kind");
+        ctx->templates = kind;
+    });
+}
+
+int32_t nis_debug_template_features(nis_ctx* ctx, int32_t medium, const float* d_points, const float* d_dirs,
+                                    int64_t n, float* d_tbar, float* d_rho, float* d_phi, float* d_stats,
+                                    float* d_f0)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (!d_points || !d_dirs || n <= 0 || !d_tbar || !d_rho || !d_phi || !d_stats)
+            fail(NIS_E_INVALID, "bad arguments");
+        Medium* M = get_medium(ctx, medium);
+        hip_check(hipDeviceSynchronize(), "sync");
+        QueryOut o;
+        o.tbar = d_tbar;
+        o.rho = d_rho;
+        o.phi = d_phi;
+        o.stats = d_stats;
+        o.f0 = d_f0;
+        o.run_mlp = false;
+        Params P = grey_params(M);
+        P.templates = NIS_TEMPLATES_PAPER;
+        run_query(ctx->ws, ctx->net, ctx->precision, M, &M->light, P, d_points, d_dirs, n, nullptr, o, ctx->stream);
+        hip_check(hipStreamSynchronize(ctx->stream), "template features");
     });
 }
 
@@ -1252,7 +1488,7 @@ int32_t nis_calibrate_fp8(nis_ctx* ctx, int32_t medium, const float* d_points, c
         Medium* M = get_medium(ctx, medium);
         if (!ctx->net) fail(NIS_E_STATE, "no weights set");
         Net* net = ctx->net;
-        const Params P = grey_params(M);
+        const Params P = with_templates(ctx, grey_params(M));
         DevBuf amax;
         amax.reserve((size_t)net->n_linear * sizeof(float), "calibration maxima");
         std::vector<float> h(net->n_linear, 0.f);
@@ -1295,7 +1531,7 @@ int32_t nis_query_device_noalloc(nis_ctx* ctx, int32_t medium, const float* d_po
             fail(NIS_E_INVALID, "the allocation-free query takes at most " + std::to_string(NIS_NOALLOC_MAX_POINTS) +
                                     " points per call");
         Medium* M = get_medium(ctx, medium);
-        const Params P = grey_params(M);
+        const Params P = with_templates(ctx, grey_params(M));
         if (!M->light.valid) fail(NIS_E_STATE, "no light set for this medium");
         const WsView w = scratch_view(ctx->device, ctx->precision, n);
         StreamUse su(ctx, (hipStream_t)hip_stream);
@@ -1328,7 +1564,7 @@ int32_t nis_query_rgb_device(nis_ctx* ctx, int32_t medium, const float* d_points
         StreamUse su(ctx, (hipStream_t)hip_stream);
         QueryOut o;
         o.radiance = d_out;
-        run_query(ctx->ws, ctx->net, ctx->precision, M, &M->light, rgb_params(M), d_points, d_dirs, n, nullptr, o,
+        run_query(ctx->ws, ctx->net, ctx->precision, M, &M->light, with_templates(ctx, rgb_params(M)), d_points, d_dirs, n, nullptr, o,
                   su.s);
     });
 }
@@ -1359,7 +1595,7 @@ int32_t nis_render(nis_ctx* ctx, int32_t medium, const nis_camera* camera, uint6
         CamArgs C = camera_args(camera);
         StreamUse su(ctx, (hipStream_t)hip_stream);
         hipStream_t s = su.s;
-        render_frame(ctx->ws, ctx->fw, ctx->net, ctx->precision, M, &M->light, grey_params(M), C, seed, d_image,
+        render_frame(ctx->ws, ctx->fw, ctx->net, ctx->precision, M, &M->light, with_templates(ctx, grey_params(M)), C, seed, d_image,
                      s);
     });
 }
@@ -1374,7 +1610,7 @@ int32_t nis_render_rgb(nis_ctx* ctx, int32_t medium, const nis_camera* camera, u
         Medium* M = get_medium(ctx, medium);
         CamArgs C = camera_args(camera);
         StreamUse su(ctx, (hipStream_t)hip_stream);
-        render_frame(ctx->ws, ctx->fw, ctx->net, ctx->precision, M, &M->light, rgb_params(M), C, seed, d_image,
+        render_frame(ctx->ws, ctx->fw, ctx->net, ctx->precision, M, &M->light, with_templates(ctx, rgb_params(M)), C, seed, d_image,
                      su.s);
     });
 }
@@ -1542,7 +1778,7 @@ int32_t nis_debug_network(nis_ctx* ctx, int32_t medium, const float* d_points, c
             o.desc = raw.p;
         }
         try {
-            run_query(ctx->ws, ctx->net, prec, M, &M->light, grey_params(M), d_points, d_dirs, n, nullptr, o,
+            run_query(ctx->ws, ctx->net, prec, M, &M->light, with_templates(ctx, grey_params(M)), d_points, d_dirs, n, nullptr, o,
                       ctx->stream);
             const float dscale = prec == kPrecFP8 ? ctx->net->fp8_scales[2] : 1.f;
             if (d_desc) hip_check(launch_desc_to_f32(prec, raw.p, d_desc, n, dscale, ctx->stream), "descriptor convert");

@@ -79,6 +79,31 @@ struct MediumView {
     float ph_a[kMaxLobes], ph_s[kMaxLobes], ph_c[kMaxLobes], ph_k[kMaxLobes];   // |g|, sign g, (1-|g|)^2, float(hg_k)
 };
 
+// The paper's own templates (Sec. III.B.2): 8 diffuse sphere layers and 4
+// highlight cone layers, kTplSites points in all.
+constexpr int kTplSites = 266;
+constexpr int kTplFeat = 3 * kTplSites + kLayers * kStats;   // descriptor entries before the zero gap (894)
+__host__ __device__ constexpr int tpl_count(int k)
+{
+    return k == 0 ? 6 : k == 1 ? 8 : k == 2 ? 12 : k == 3 ? 16 : k == 4 ? 24 : k == 5 ? 32 : k < 8 ? 48
+         : k == 8 ? 32 : k < 11 ? 16 : 8;
+}
+__host__ __device__ constexpr int tpl_first(int k)
+{
+    int f = 0;
+    for (int i = 0; i < k; i++) f += tpl_count(i);
+    return f;
+}
+
+// Per-light template tables: each point's offset (diffuse layers: the unit
+// template point, scaled per layer by its radius; highlight layers: the unit
+// cone point in world axes, scaled per query point by its light extent) and
+// its (direction from the centre, f(direction . l)) for the phase feature.
+struct TplTables {
+    double off[kTplSites][3];
+    float4 site[kTplSites];
+};
+
 // Per-light constant tables for the gather (one copy per medium).
 struct SiteTables {
     // (d_t, f(d_t . l)) per site: the unit lattice offset direction and the

@@ -75,13 +75,16 @@ struct LightState {
     int64_t rt_floats = 0;                  // transposed pyramid (x-dominant lights only)
     int64_t pair_count = 0;                 // light-axis density pairs of all levels
     int64_t dpair_count = 0;                // path-density pairs of all levels
-    DevBuf RT, P, DP, tab, vtab;
+    DevBuf RT, P, DP, tab, vtab, tpl;
+    std::vector<TplTables> tpl_host;        // host copy of the template tables (kept while a copy may run)
+    bool tpl_valid = false;
+    Phase tpl_phase = {};                   // phase the template tables were computed for
     bool stale = true;                      // D, P and DP must be recomputed
     uint64_t swept_version = 0;             // pyramid version they were computed from
     bool tab_valid = false;
     Phase tab_phase = {};                   // phase the site tables were computed for
     bool tab_volume = false;                // ... and whether as volume phases (then vtab too)
-    size_t bytes() const { return RT.bytes + P.bytes + DP.bytes + tab.bytes + vtab.bytes; }
+    size_t bytes() const { return RT.bytes + P.bytes + DP.bytes + tab.bytes + vtab.bytes + tpl.bytes; }
     void release()
     {
         RT.release();
@@ -89,7 +92,9 @@ struct LightState {
         DP.release();
         tab.release();
         vtab.release();
+        tpl.release();
         tab_valid = false;
+        tpl_valid = false;
         stale = true;
     }
 };
@@ -117,6 +122,7 @@ struct Params {
     bool volume = false;   // volume phases (eq. 9) in the phase features
     int channels = 1;      // 3: one radiance per colour channel, albedo rgb[c]
     float rgb[3] = {0, 0, 0};
+    int templates = 0;     // NIS_TEMPLATES_LATTICE or NIS_TEMPLATES_PAPER
 };
 
 inline bool grey_albedo(const Medium* M)
@@ -265,6 +271,7 @@ struct nis_ctx {
     int32_t next_id = 1;
     nis::Net* net = nullptr;
     int precision = nis::kPrecFP32;
+    int templates = 0;                 // NIS_TEMPLATES_LATTICE (default) or NIS_TEMPLATES_PAPER
     nis::Workspace ws;
     nis::FrameWork fw;
     nis::DevBuf io;

@@ -31,6 +31,8 @@ NIS_E_INTERNAL = -6
 NIS_FP32, NIS_BF16, NIS_FP8 = 0, 1, 2
 NIS_EAGER = 1
 NOALLOC_MAX_POINTS = 8192   # NIS_NOALLOC_MAX_POINTS
+NIS_TEMPLATES_LATTICE, NIS_TEMPLATES_PAPER = 0, 1
+TPL_SITES = 266
 NIS_QUEUED, NIS_RUNNING = 1, 2
 LAYERS, SITES, STATS, DESCRIPTOR = 12, 225, 8, 1057
 PRECISIONS = {"fp32": NIS_FP32, "bf16": NIS_BF16, "fp8": NIS_FP8}
@@ -84,6 +86,8 @@ _SIGNATURES = {
     "nis_query_device": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
     "nis_query_device_noalloc": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
     "nis_calibrate_fp8": [_vp, _i32, _vp, _vp, _i64, _vp],
+    "nis_set_templates": [_vp, _i32],
+    "nis_debug_template_features": [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp],
     "nis_query_rgb": [_vp, _i32, _vp, _vp, _i64, _vp],
     "nis_query_rgb_device": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
     "nis_medium_info": [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i64)],
@@ -491,6 +495,23 @@ class Context:
         _check(_lib.nis_debug_features(self.h, medium, _dptr(points), _dptr(dirs), n,
                                        *[_dptr(out[k]) for k in ("tbar", "rho", "phi", "stats",
                                                                  "tp", "f0")]))
+        return out
+
+    def set_templates(self, kind):
+        """"lattice" (default) or "paper" (the sphere and cone templates)."""
+        if isinstance(kind, str):
+            kind = {"lattice": NIS_TEMPLATES_LATTICE, "paper": NIS_TEMPLATES_PAPER}[kind]
+        _check(_lib.nis_set_templates(self.h, kind))
+
+    def template_features(self, medium, points, dirs):
+        """Gather-stage outputs at the paper's templates (torch tensors)."""
+        import torch
+        n = points.shape[0]
+        z = lambda *s: torch.zeros(*s, dtype=torch.float32, device=points.device)
+        out = {"tbar": z(n, TPL_SITES), "rho": z(n, TPL_SITES), "phi": z(n, TPL_SITES),
+               "stats": z(n, LAYERS, STATS), "f0": z(n)}
+        _check(_lib.nis_debug_template_features(self.h, medium, _dptr(points), _dptr(dirs), n,
+                                                *[_dptr(out[k]) for k in ("tbar", "rho", "phi", "stats", "f0")]))
         return out
 
     def network(self, medium, points, dirs, want_desc=True):

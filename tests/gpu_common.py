@@ -59,6 +59,13 @@ class Scene:
         return self.om.query(oracle_params(params), pts, dirs, f32(self.sigma_t), f32(self.albedo),
                              self.phase(), f32(self.radiance), want_desc=want_desc, volume=self.volume)
 
+    def oracle_tpl_features(self, params, pts, dirs):
+        return self.om.tpl_features(f32(self.sigma_t), self.phase(), f32(params["lam"]), pts, dirs)
+
+    def oracle_tpl_query(self, params, pts, dirs, want_desc=False):
+        return self.om.tpl_query(oracle_params(params), pts, dirs, f32(self.sigma_t), f32(self.albedo),
+                                 self.phase(), f32(self.radiance), want_desc=want_desc)
+
     def oracle_features(self, params, pts, dirs):
         return self.om.features(f32(self.sigma_t), self.phase(), f32(params["lam"]), pts, dirs, volume=self.volume)
 
