@@ -889,3 +889,144 @@ void om_tpl_query(const om_medium *M, double sigma_t, double albedo, int nl, con
         if (!desc_out) free(desc);
     }
 }
+
+/* ------------------------------------------------------------------ */
+/* The paper's backbone (Sec. III.C.2, Fig. 6) over the template features:
+ * six identical modules, one per feature type tau (0 graded transmittance,
+ * 1 density, 2 phase) and template group G (diffuse layers 0-7, highlight
+ * layers 8-11).  Readings (the paper names the blocks, not their shapes):
+ *  - a module carries h, the features of its current layer (h = x_k0, the
+ *    n_k0 values of type tau at the group's first layer); step k (k0 <= k <
+ *    k1) fuses h with the configuration parameters c = (g, alpha) into
+ *    u = [h; c] (n_k + 2 entries) and applies the attention of eq. (24)-(26)
+ *    with the standard two-FC excitation: the squeeze is the layer's
+ *    8-entry vector v_k of eq. (24), e = sigmoid(S2 ReLU(S1 v_k + e1) + e2)
+ *    (S1 2x8, S2 (n_k+2)x2), a = e * u;
+ *  - FC-1 brings a to the next layer's size and it is fused (added) with the
+ *    next layer's features: y = x_{k+1} + F1 a + f1 (F1 n_{k+1} x (n_k+2));
+ *  - FC-2, then fused with that layer's features again:
+ *    h = ReLU(F2 y + f2) + x_{k+1} (F2 n_{k+1} x n_{k+1});
+ *  - after its last step a module holds n_k1 values (48 diffuse, 8
+ *    highlight); per type the two groups merge through a full connection:
+ *    m_tau = ReLU(M_tau [h_diffuse; h_highlight] + mb_tau) (64 x 56);
+ *  - the multi-layer perceptron is the backbone MLP of the lattice path, its
+ *    input [m_T; m_rho; m_phi; g; alpha] (194 entries), zeros up to the
+ *    albedo entry at index 1056 (so the albedo enters once, as before).
+ * Parameter block (this file's own order): for tau = 0..2, for G = 0..1, for
+ * each step: S1[2][8], e1[2], S2[a][2], e2[a], F1[b][a], f1[b], F2[b][b],
+ * f2[b] (a = n_k + 2, b = n_{k+1}); then for tau = 0..2: M[64][56], mb[64]. */
+#define OM_MOD_HIDDEN 64
+
+static double om_sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+/* number of doubles of the module block */
+int64_t om_modules_size(void)
+{
+    int64_t sz = 0;
+    for (int tau = 0; tau < 3; tau++)
+        for (int G = 0; G < 2; G++) {
+            int k0 = G ? OM_DIFFUSE : 0, k1 = G ? OM_LAYERS - 1 : OM_DIFFUSE - 1;
+            for (int k = k0; k < k1; k++) {
+                int a = om_tpl_count[k] + 2, b = om_tpl_count[k + 1];
+                sz += 16 + 2 + 2 * a + a + (int64_t)b * a + b + (int64_t)b * b + b;
+            }
+        }
+    return sz + 3 * (OM_MOD_HIDDEN * (om_tpl_count[OM_DIFFUSE - 1] + om_tpl_count[OM_LAYERS - 1]) + OM_MOD_HIDDEN);
+}
+
+/* One module (type tau, group G) over the template features; writes the
+ * n_k1 values it ends with and returns the parameter pointer past its steps. */
+static const double *om_module(const double *w, int tau, int G, const double *feat, const int *base,
+                               double g, double alpha, double *hout)
+{
+    int k0 = G ? OM_DIFFUSE : 0, k1 = G ? OM_LAYERS - 1 : OM_DIFFUSE - 1;
+    double h[64], u[64], av[64], y[64];
+    int n0 = om_tpl_count[k0];
+    for (int j = 0; j < n0; j++) h[j] = feat[base[k0] + tau * n0 + j];
+    for (int k = k0; k < k1; k++) {
+        int n = om_tpl_count[k], a = n + 2, b = om_tpl_count[k + 1];
+        const double *v = feat + base[k] + 3 * n;              /* squeeze vector of layer k (eq. 24) */
+        const double *xn = feat + base[k + 1] + tau * b;       /* next layer's features of type tau */
+        const double *S1 = w, *e1 = S1 + 16, *S2 = e1 + 2, *e2 = S2 + 2 * a;
+        const double *F1 = e2 + a, *f1 = F1 + (int64_t)b * a, *F2 = f1 + b, *f2 = F2 + (int64_t)b * b;
+        w = f2 + b;
+        /* fusion with the configuration parameters */
+        for (int j = 0; j < n; j++) u[j] = h[j];
+        u[n] = g;
+        u[n + 1] = alpha;
+        /* attention: excitation of the squeeze vector, gate on u */
+        double z[2];
+        for (int r = 0; r < 2; r++) {
+            double acc = e1[r];
+            for (int i = 0; i < 8; i++) acc += S1[r * 8 + i] * v[i];
+            z[r] = acc > 0.0 ? acc : 0.0;
+        }
+        for (int i = 0; i < a; i++) av[i] = om_sigmoid(e2[i] + S2[i * 2] * z[0] + S2[i * 2 + 1] * z[1]) * u[i];
+        /* FC-1 to the next layer's size, fused with that layer's features */
+        for (int o = 0; o < b; o++) {
+            double acc = f1[o];
+            for (int i = 0; i < a; i++) acc += F1[(int64_t)o * a + i] * av[i];
+            y[o] = xn[o] + acc;
+        }
+        /* FC-2, fused with that layer's features again */
+        for (int o = 0; o < b; o++) {
+            double acc = f2[o];
+            for (int i = 0; i < b; i++) acc += F2[(int64_t)o * b + i] * y[i];
+            h[o] = (acc > 0.0 ? acc : 0.0) + xn[o];
+        }
+    }
+    for (int j = 0; j < om_tpl_count[k1]; j++) hout[j] = h[j];
+    return w;
+}
+
+/* Template features (per layer: tbar, rho, phi in template order, then the
+ * squeeze vector, as om_tpl_descriptor lays them out) -> the modules'
+ * descriptor: [m_T; m_rho; m_phi; g; alpha], zeros, albedo at OM_DESC - 1. */
+void om_modules(const double *mp, const double *feat, double albedo, double *desc)
+{
+    int base[OM_LAYERS + 1];
+    base[0] = 0;
+    for (int k = 0; k < OM_LAYERS; k++) base[k + 1] = base[k] + 3 * om_tpl_count[k] + OM_STATS;
+    const double g = feat[3 * om_tpl_count[0] + 6], alpha = feat[3 * om_tpl_count[0] + 7];
+    const int nd = om_tpl_count[OM_DIFFUSE - 1], nh = om_tpl_count[OM_LAYERS - 1];
+    double cat[3][64];
+    const double *w = mp;
+    for (int tau = 0; tau < 3; tau++) {
+        w = om_module(w, tau, 0, feat, base, g, alpha, cat[tau]);
+        w = om_module(w, tau, 1, feat, base, g, alpha, cat[tau] + nd);
+    }
+    for (int i = 0; i < OM_DESC; i++) desc[i] = 0.0;
+    for (int tau = 0; tau < 3; tau++) {
+        const double *M = w, *mb = M + OM_MOD_HIDDEN * (nd + nh);
+        w = mb + OM_MOD_HIDDEN;
+        for (int o = 0; o < OM_MOD_HIDDEN; o++) {
+            double acc = mb[o];
+            for (int i = 0; i < nd + nh; i++) acc += M[o * (nd + nh) + i] * cat[tau][i];
+            desc[tau * OM_MOD_HIDDEN + o] = acc > 0.0 ? acc : 0.0;
+        }
+    }
+    desc[3 * OM_MOD_HIDDEN] = g;
+    desc[3 * OM_MOD_HIDDEN + 1] = alpha;
+    desc[OM_DESC - 1] = albedo;
+}
+
+/* Whole query with the paper's templates and backbone: the template
+ * features, the six modules and merges, then the backbone MLP and decode. */
+void om_tpl_modules_query(const om_medium *M, double sigma_t, double albedo, int nl, const double *lw,
+                          const double *lg, double lam, double gamma, double radiance, const double *params,
+                          int width, int n_linear, const double *mp, const float *pts, const float *dirs,
+                          int64_t np, double *L_out, double *y_out, double *desc_out)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t p = 0; p < np; p++) {
+        double tb[OM_TPL_SITES], rh[OM_TPL_SITES], ph[OM_TPL_SITES], st[OM_LAYERS * OM_STATS], f0;
+        double feat[OM_DESC], desc[OM_DESC];
+        om_tpl_features(M, sigma_t, nl, lw, lg, lam, pts + 3 * p, dirs + 3 * p, 1, tb, rh, ph, st, &f0);
+        om_tpl_descriptor(tb, rh, ph, st, albedo, feat);
+        om_modules(mp, feat, albedo, desc);
+        double y = om_mlp(params, width, n_linear, desc);
+        L_out[p] = radiance * (f0 + pow(albedo, gamma) * expm1(y));
+        if (y_out) y_out[p] = y;
+        if (desc_out) memcpy(desc_out + p * OM_DESC, desc, sizeof(desc));
+    }
+}

@@ -94,8 +94,32 @@ def lib():
         L.om_tpl_query.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp, _dp,
                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, ctypes.c_int,
                                    ctypes.c_int, _fp, _fp, ctypes.c_int64, _dp, _dp, _dp, _dp]
+        L.om_modules_size.restype = ctypes.c_int64
+        L.om_modules_size.argtypes = []
+        L.om_modules.argtypes = [_dp, _dp, ctypes.c_double, _dp]
+        L.om_tpl_modules_query.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp,
+                                           _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp,
+                                           ctypes.c_int, ctypes.c_int, _dp, _fp, _fp, ctypes.c_int64, _dp, _dp, _dp]
         _lib = L
     return _lib
+
+
+def flatten_modules(modules):
+    """The oracle's FP64 block of the modules' weights (workloads.weights.he_init_modules order)."""
+    flat = np.concatenate([np.asarray(a, np.float64).ravel() for a in modules])
+    if flat.size != lib().om_modules_size():
+        raise ValueError("module block has %d values, expected %d" % (flat.size, lib().om_modules_size()))
+    return flat
+
+
+def modules(mods, feat, albedo):
+    """The paper's backbone modules: template features (894, descriptor
+    layout) -> the modules' descriptor (1057)."""
+    out = np.zeros(DESC)
+    f = np.zeros(DESC)
+    f[:len(feat)] = feat
+    lib().om_modules(_ptr(flatten_modules(mods), _dp), _ptr(f, _dp), float(albedo), _ptr(out, _dp))
+    return out
 
 
 # ---- the paper's templates (Sec. III.B.2, eq. 2-4) ----
@@ -321,6 +345,24 @@ class Medium:
                            int(params["width"]), int(params["n_linear"]), _ptr(pts, _fp), _ptr(dirs, _fp), P,
                            _ptr(L, _dp), _ptr(y, _dp), _ptr(F, _dp), _ptr(desc, _dp))
         out = {"L": L, "y": y, "F": F}
+        if want_desc:
+            out["desc"] = desc
+        return out
+
+    def tpl_modules_query(self, params, mods, pts, dirs, sigma_t, albedo, g, radiance=1.0, want_desc=False):
+        """The paper's templates and backbone modules, then the MLP and decode."""
+        pts, dirs = _f32(pts), _f32(dirs)
+        P = pts.shape[0]
+        flat = flatten_params(params)
+        mp = flatten_modules(mods)
+        L, y = np.zeros(P), np.zeros(P)
+        desc = np.zeros((P, DESC)) if want_desc else None
+        lw, lg = lobes(g)
+        lib().om_tpl_modules_query(self.h, float(sigma_t), float(albedo), len(lw), _ptr(lw, _dp), _ptr(lg, _dp),
+                                   float(params["lam"]), float(params["gamma"]), float(radiance), _ptr(flat, _dp),
+                                   int(params["width"]), int(params["n_linear"]), _ptr(mp, _dp), _ptr(pts, _fp),
+                                   _ptr(dirs, _fp), P, _ptr(L, _dp), _ptr(y, _dp), _ptr(desc, _dp))
+        out = {"L": L, "y": y}
         if want_desc:
             out["desc"] = desc
         return out

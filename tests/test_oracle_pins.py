@@ -977,3 +977,85 @@ def test_template_descriptor_layout_and_probes():
         s["A"][2][0, 0] = 1.0
         y = M.tpl_query(s, pts, dirs, 8.0, 0.9, 0.85, 1.0)["y"]
         np.testing.assert_allclose(y, np.maximum(q["desc"][:, entry], 0.0), rtol=1e-14)
+
+
+# ---- the paper's backbone modules (Sec. III.C.2, Fig. 6) ---------------------
+
+def _tpl_setup():
+    d = medium.fbm_cloud(16, seed=4)
+    M = oracle.Medium(d)
+    M.set_light((0.3, 0.9, 0.3))
+    pts, dirs = camera.random_points(10, seed=6, lo=0.1, hi=0.9)
+    f = M.tpl_features(8.0, 0.85, 0.6, pts, dirs)
+    params = weights.he_init(16, 3, seed=1)
+    feats = M.tpl_query(params, pts, dirs, 8.0, 0.9, 0.85, 1.0, want_desc=True)["desc"]
+    return M, pts, dirs, f, feats[:, :894]
+
+
+def _layer_slice(k, tau):
+    counts = oracle.tpl_counts()
+    base = sum(3 * c + 8 for c in counts[:k])
+    return slice(base + tau * counts[k], base + (tau + 1) * counts[k])
+
+
+def test_modules_with_zero_weights_carry_the_last_layers():
+    # zero weights: every step's FC-2 term vanishes, so a module ends with its
+    # group's last layer features; a merge selecting entry j returns it
+    M, pts, dirs, f, feats = _tpl_setup()
+    mods = [np.zeros_like(a) for a in weights.he_init_modules(2)]
+    for p in range(len(pts)):
+        d0 = oracle.modules(mods, feats[p], 0.9)
+        assert np.all(d0[:192] == 0.0) and d0[192] == feats[p, 3 * 6 + 6] and d0[193] == feats[p, 3 * 6 + 7]
+        assert d0[1056] == 0.9 and np.all(d0[194:1056] == 0.0)
+    sel = [np.zeros_like(a) for a in weights.he_init_modules(2)]
+    merges = sel[-6:]
+    for tau in range(3):
+        Mt = merges[2 * tau]
+        Mt[0, 5] = 1.0          # a diffuse entry of the last diffuse layer (48 points)
+        Mt[1, 48 + 3] = 1.0     # a highlight entry of the last highlight layer (8 points)
+    for p in range(len(pts)):
+        d1 = oracle.modules(sel, feats[p], 0.9)
+        for tau in range(3):
+            assert d1[tau * 64] == pytest.approx(feats[p, _layer_slice(7, tau)][5], rel=1e-15)
+            assert d1[tau * 64 + 1] == pytest.approx(feats[p, _layer_slice(11, tau)][3], rel=1e-15)
+
+
+@pytest.mark.parametrize("isel,vsel", [(0, 2), (16, 5), (17, 0)])
+def test_module_last_step_closed_form(isel, vsel):
+    # last highlight step (layer 10 -> 11; a = 16 + 2, b = 8) of type 1 (density):
+    # S1[0][vsel] = 1 and S2[isel][0] = 1 gate entry isel of u = [h; g; alpha]
+    # by sigmoid(ReLU(v_vsel)); F1 sends it to output 0, F2 = I, so
+    # h_0 = ReLU(x11_0 + gate * u_isel) + x11_0 and h_o = ReLU(x11_o) + x11_o
+    M, pts, dirs, f, feats = _tpl_setup()
+    mods = [np.zeros_like(a) for a in weights.he_init_modules(2)]
+    # index of the last highlight step of type 1 in the flat list: 8 arrays per step
+    steps_per_type = 7 + 3
+    step = 1 * steps_per_type + 7 + 2
+    S1, e1, S2, e2, F1, f1, F2, f2 = mods[8 * step: 8 * step + 8]
+    assert S2.shape == (18, 2) and F1.shape == (8, 18) and F2.shape == (8, 8)
+    S1[0, vsel] = 1.0
+    S2[isel, 0] = 1.0
+    F1[0, isel] = 1.0
+    F2[:, :] = np.eye(8)
+    merges = mods[-6:]
+    for o in range(8):
+        merges[2 * 1][o, 48 + o] = 1.0
+    counts = oracle.tpl_counts()
+    for p in range(len(pts)):
+        d = oracle.modules(mods, feats[p], 0.9)
+        x10 = feats[p, _layer_slice(10, 1)]
+        x11 = feats[p, _layer_slice(11, 1)]
+        v10 = feats[p, sum(3 * c + 8 for c in counts[:10]) + 3 * 16:][:8]
+        u = np.r_[x10, v10[6], v10[7]]
+        gate = 1.0 / (1.0 + math.exp(-max(v10[vsel], 0.0)))
+        h = np.maximum(x11, 0.0) + x11
+        h[0] = max(x11[0] + gate * u[isel], 0.0) + x11[0]
+        np.testing.assert_allclose(d[64:72], np.maximum(h, 0.0), rtol=1e-14)
+
+
+def test_modules_query_zero_weights_give_single_scatter():
+    M, pts, dirs, f, feats = _tpl_setup()
+    params = weights.zeros_like(weights.he_init(16, 3, seed=1))
+    mods = [np.zeros_like(a) for a in weights.he_init_modules(2)]
+    q = M.tpl_modules_query(params, mods, pts, dirs, 8.0, 0.9, 0.85, 2.0)
+    np.testing.assert_allclose(q["L"], 2.0 * f["f0"], rtol=1e-14)

@@ -65,3 +65,37 @@ def zeros_like(params):
     out["A"] = [np.zeros_like(a) for a in params["A"]]
     out["beta"] = [np.zeros_like(b) for b in params["beta"]]
     return out
+
+
+# Point counts of the paper's template layers (8 diffuse sphere layers, 4
+# highlight cone layers) and the width of the modules' merges.
+TEMPLATE_COUNTS = (6, 8, 12, 16, 24, 32, 48, 48, 32, 16, 16, 8)
+MODULE_MERGE = 64
+
+
+def he_init_modules(seed=2, bias_scale=0.0):
+    """Weights of the six layer-by-layer modules and three merges of the
+    paper's backbone, He-normal from default_rng(seed), as a list of float32
+    arrays in the blob order: for type 0..2 (graded transmittance, density,
+    phase), for group 0..1 (diffuse layers 0-7, highlight 8-11), for each
+    step k (from each group layer but its last): S1 [2][8], e1 [2], S2 [a][2],
+    e2 [a], F1 [b][a], f1 [b], F2 [b][b], f2 [b] with a = n_k + 2 and
+    b = n_(k+1); then for type 0..2: M [64][56], mb [64].  Biases are zero
+    unless bias_scale is given."""
+    rng = np.random.default_rng(seed)
+    out = []
+
+    def bias(n):
+        return (bias_scale * rng.standard_normal(n)).astype(np.float32) if bias_scale else np.zeros(n, np.float32)
+
+    for _tau in range(3):
+        for grp in range(2):
+            k0, k1 = (0, 7) if grp == 0 else (8, 11)
+            for k in range(k0, k1):
+                a, b = TEMPLATE_COUNTS[k] + 2, TEMPLATE_COUNTS[k + 1]
+                out += [_he(rng, (2, 8), 8), bias(2), _he(rng, (a, 2), 2), bias(a),
+                        _he(rng, (b, a), a), bias(b), _he(rng, (b, b), b), bias(b)]
+    cat = TEMPLATE_COUNTS[7] + TEMPLATE_COUNTS[11]
+    for _tau in range(3):
+        out += [_he(rng, (MODULE_MERGE, cat), cat), bias(MODULE_MERGE)]
+    return out
