@@ -88,6 +88,7 @@ template <class E> struct FeatShared {
     float cb[kCbFloats];                       // the group's conv biases and attention weights
     uint16_t smask[kTP][kLayers][9];           // in-cube bits of every slab of every layer
     uint16_t posoff[kY1Pos];                   // conv1: lattice offset of output position p (the 64th = the 63rd)
+    uint16_t goff[24];                         // conv1 (BF16): lattice offset of 4-slot K group g
     double qo[3][9];                           // the light's lattice offsets, per axis and slab
 };
 
@@ -261,6 +262,14 @@ k_features(FeatArgs A)
     {
         const int pc = lane < 63 ? lane : 62;
         sh.posoff[lane] = (uint16_t)(((pc / 9) * 5 + (pc / 3) % 3) * kLatRow + (pc % 3) * 4);
+        // BF16 conv1 reads the 4-slot groups g of its K steps: g < 8 is
+        // tap-row g of the pair's first point, 8 <= g < 16 tap-row g - 8 of
+        // the second, g = 16 tap-row 8 of the first and g = 17 of the second;
+        // groups g >= 18 meet zero weights and read any entry (offset 0)
+        const int g = lane;
+        if (g < 24)
+            sh.goff[g] = (uint16_t)(g < 16 ? (g >= 8 ? kLatStride : 0) + taprow_off(g % 8)
+                                    : g == 16 ? taprow_off(8) : g == 17 ? kLatStride + taprow_off(8) : 0);
     }
     __syncthreads();
 
@@ -703,11 +712,7 @@ k_features(FeatArgs A)
 #pragma unroll
             for (int kc = 0; kc < (KC1 < 3 ? KC1 : 3); kc++)
 #pragma unroll
-                for (int h = 0; h < 2; h++) {
-                    const int g = kc * 8 + 2 * (ln >> 4) + h;
-                    goff[kc][h] = g < 16 ? (g >= 8 ? kLatStride : 0) + taprow_off(g % 8)
-                                : g == 16 ? taprow_off(8) : g == 17 ? kLatStride + taprow_off(8) : 0;
-                }
+                for (int h = 0; h < 2; h++) goff[kc][h] = sh.goff[kc * 8 + 2 * (ln >> 4) + h];
 #pragma unroll 1
             for (int tp0 = 0; tp0 < kTP; tp0 += 2)
 #pragma unroll
