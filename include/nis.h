@@ -175,7 +175,15 @@ int32_t nis_set_light(nis_ctx *ctx, int32_t medium, const float dir[3], float ra
  *     i = 0 and width otherwise, out = width except 1 for the last layer;
  *   then, if has_fp8_scales, float32 activation scales (x = E4M3 code *
  *     scale, each > 0): conv1 input, conv2 input, and one per backbone layer
- *     input (2 + n_linear values).
+ *     input (2 + n_linear values);
+ *   then, if has_modules (the header word after has_fp8_scales, 0 or 1), the
+ *     56,706 float32 weights of the paper's backbone modules (Sec. III.C.2,
+ *     Fig. 6; see nis_set_backbone): for type 0..2 (graded transmittance,
+ *     density, phase), for group 0..1 (diffuse template layers 0-7, highlight
+ *     8-11), for each step from layer k to k+1 of the group: S1[2][8], e1[2],
+ *     S2[a][2], e2[a], F1[b][a], f1[b], F2[b][b], f2[b] with a = n_k + 2,
+ *     b = n_(k+1) (n_k: the template layer's point count); then for type
+ *     0..2: M[64][56], mb[64].
  * Errors: NIS_E_INVALID on a malformed blob, NIS_E_NOMEM, NIS_E_DEVICE.
  */
 int32_t nis_set_weights(nis_ctx *ctx, const void *blob, size_t nbytes);
@@ -204,6 +212,35 @@ int32_t nis_set_weights(nis_ctx *ctx, const void *blob, size_t nbytes);
  * Errors: NIS_E_INVALID for an unknown kind.
  */
 int32_t nis_set_templates(nis_ctx *ctx, int32_t kind);
+
+/* backbone kinds (nis_set_backbone) */
+#define NIS_BACKBONE_MLP 0    /* the template features go straight into the MLP (default) */
+#define NIS_BACKBONE_PAPER 1  /* the paper's layer-by-layer modules before the MLP (Fig. 6) */
+
+/*
+ * nis_set_backbone -- NIS_BACKBONE_PAPER puts the paper's backbone modules
+ * (Sec. III.C.2, Fig. 6, eq. 24-26) between the paper's templates and the
+ * MLP: per feature type (graded transmittance, density, phase) and template
+ * group (diffuse layers 0-7, highlight layers 8-11) one module carries the
+ * features h of its current layer from layer to layer.  A step from layer k
+ * fuses h with the configuration (g, alpha = acos(w.l)) into u = [h; g;
+ * alpha], gates it with the attention of eq. (24)-(26) excited by the
+ * layer's squeeze vector v_k (a = sigmoid(S2 ReLU(S1 v_k + e1) + e2) * u),
+ * maps it to the next layer's size and fuses that layer's features x:
+ * y = x + F1 a + f1, h = ReLU(F2 y + f2) + x.  Per type the two groups'
+ * final states (48 + 8 values) merge, m = ReLU(M [h_D; h_H] + mb) (64
+ * values), and the MLP reads [m_T; m_rho; m_phi; g; alpha] (194 entries),
+ * zeros, and the albedo at index 1056.  The template features are gathered
+ * in FP32 and the modules run in FP32 whatever the precision; the
+ * precision sets the descriptor's format and the MLP.  Queries in this mode
+ * need NIS_TEMPLATES_PAPER and weights with the module block (NIS_E_STATE
+ * otherwise) and pass at most 65,536 points at a time.
+ * nis_query_device_noalloc refuses it (NIS_E_UNSUPPORTED); the frame server
+ * keeps the lattices.
+ * Errors: NIS_E_INVALID for an unknown kind; NIS_E_STATE for
+ * NIS_BACKBONE_PAPER when the current weights hold no modules.
+ */
+int32_t nis_set_backbone(nis_ctx *ctx, int32_t kind);
 
 /* NIS_FP32 (default), NIS_BF16 or NIS_FP8.  FP8 needs the activation scales
  * of the weight blob's fp8 block (x = code * scale, entries > 0) or of

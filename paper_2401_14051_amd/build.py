@@ -30,6 +30,7 @@ SOURCES = {
     "k_volume.hip": ["-O3"],
     "k_features.hip": ["-O3"],
     "k_mlp.hip": ["-O3"],
+    "k_modules.hip": ["-O3"],
 }
 
 

@@ -418,7 +418,8 @@ struct BlobHeader {
     uint32_t version, din, width, n_linear, groups;
     float lam, gamma;
     uint32_t has_fp8_scales;
-    uint32_t reserved[7];
+    uint32_t has_modules;
+    uint32_t reserved[6];
 };
 static_assert(sizeof(BlobHeader) == 64, "blob header is 64 bytes");
 
@@ -645,6 +646,7 @@ void free_net(Net* net)
         for (auto& b : P.wexp) b.release();
         P.wout.release();
     }
+    net->mod.release();
     delete net;
 }
 
@@ -702,10 +704,12 @@ Params rgb_params(const Medium* M)
     return P;
 }
 
-// The parameters of a query through the context: its template choice added.
+// The parameters of a query through the context: its template and backbone
+// choices added.
 Params with_templates(const nis_ctx* ctx, Params P)
 {
     P.templates = ctx->templates;
+    P.modules = ctx->backbone == NIS_BACKBONE_PAPER ? 1 : 0;
     return P;
 }
 
@@ -829,18 +833,27 @@ size_t workspace_bytes(int prec, int64_t npts)
     return (size_t)chunk * desc_row_bytes(prec) + (size_t)chunk * 4;
 }
 
+namespace {
+size_t module_feat_bytes(int64_t chunk) { return (size_t)chunk * kDescPad * sizeof(float); }
+}  // namespace
+
 void run_query(Workspace& ws, const Net* net, int prec, const Medium* M, LightState* ls, const Params& Pm,
                const float* d_pts, const float* d_dirs, int64_t n, const int* d_count, const QueryOut& o,
                hipStream_t s)
 {
     if (!net) fail(NIS_E_STATE, "no weights set");
-    const int64_t chunk = n < kChunk ? n : kChunk;
+    const int64_t cap = Pm.modules ? kModuleChunk : kChunk;
+    const int64_t chunk = n < cap ? n : cap;
     ws.desc.reserve((size_t)chunk * desc_row_bytes(prec), "descriptor workspace");
     ws.f0.reserve((size_t)chunk * sizeof(float), "single-scatter workspace");
     WsView w;
     w.desc = ws.desc.p;
     w.f0 = ws.f0.as<float>();
     w.chunk = chunk;
+    if (Pm.modules) {
+        ws.feat.reserve(module_feat_bytes(chunk), "template feature workspace");
+        w.feat = ws.feat.as<float>();
+    }
     run_query_in(w, net, prec, M, ls, Pm, d_pts, d_dirs, n, d_count, o, s, true);
 }
 
@@ -855,6 +868,12 @@ void run_query_in(const WsView& ws, const Net* net, int prec, const Medium* M, L
         fail(NIS_E_UNSUPPORTED, "FP8 needs the activation scales: pass them in the weight blob or call nis_calibrate_fp8");
     if (Pm.templates && Pm.volume)
         fail(NIS_E_UNSUPPORTED, "volume phases are not available with the paper's templates");
+    if (Pm.modules) {
+        if (!Pm.templates) fail(NIS_E_STATE, "the paper's backbone reads the paper's templates (nis_set_templates)");
+        if (!net->has_modules) fail(NIS_E_STATE, "the weights hold no backbone modules");
+        if (!ws.feat) fail(NIS_E_UNSUPPORTED, "the paper's backbone needs a template feature workspace");
+        if (ws.chunk > kModuleChunk) fail(NIS_E_INTERNAL, "module pass too large");
+    }
     ensure_sweep(M, ls, s);
     if (Pm.templates) refresh_tpl_tables(ls, Pm.phase, s, may_alloc);
     else refresh_tables(M, ls, Pm.phase, Pm.volume, s, may_alloc);
@@ -907,8 +926,9 @@ void run_query_in(const WsView& ws, const Net* net, int prec, const Medium* M, L
                 ta.mdiff[k] = tpl_level_host(G.radius[k] * G.D[k], M->n, M->levels);
             }
             for (int h = 0; h < kLayers - kDiffuse; h++) ta.dh[h] = G.D[kDiffuse + h];
-            ta.desc = fa.desc;
-            ta.desc_inv_scale = fa.desc_inv_scale;
+            // with the backbone modules the features go to the FP32 rows they read
+            ta.desc = Pm.modules ? (void*)ws.feat : fa.desc;
+            ta.desc_inv_scale = Pm.modules ? 1.f : fa.desc_inv_scale;
             ta.f0 = fa.f0;
             ta.dbg_tbar = o.tbar ? o.tbar + p0 * kTplSites : nullptr;
             ta.dbg_rho = o.rho ? o.rho + p0 * kTplSites : nullptr;
@@ -916,7 +936,13 @@ void run_query_in(const WsView& ws, const Net* net, int prec, const Medium* M, L
             ta.dbg_stats = fa.dbg_stats;
             ta.count = d_count;
             ta.count_off = p0;
-            timed("features", s, [&] { return launch_template_features(prec, ta, s); });
+            const int tprec = Pm.modules ? kPrecFP32 : prec;
+            timed("features", s, [&] { return launch_template_features(tprec, ta, s); });
+            if (Pm.modules)
+                timed("modules", s, [&] {
+                    return launch_modules(prec, ws.feat, net->mod.as<float>(), cn, d_count, p0, ws.desc,
+                                          fa.desc_inv_scale, Pm.albedo, s);
+                });
         } else {
             timed("features", s, [&] { return launch_features(prec, fa, s); });
         }
@@ -1368,6 +1394,8 @@ int32_t nis_set_weights(nis_ctx* ctx, const void* blob, size_t nbytes)
             need += (size_t)din[i] * dout[i] + dout[i];
         }
         if (h.has_fp8_scales) need += 2 + h.n_linear;
+        if (h.has_modules > 1) fail(NIS_E_INVALID, "has_modules must be 0 or 1");
+        if (h.has_modules) need += (size_t)module_floats_total();
         if (nbytes != sizeof(BlobHeader) + need * sizeof(float)) fail(NIS_E_INVALID, "blob size mismatch");
         const float* f = reinterpret_cast<const float*>((const char*)blob + sizeof(BlobHeader));
         std::vector<float> all(f, f + need);
@@ -1381,6 +1409,7 @@ int32_t nis_set_weights(nis_ctx* ctx, const void* blob, size_t nbytes)
             net->lam = h.lam;
             net->gamma = h.gamma;
             net->has_fp8 = h.has_fp8_scales != 0;
+            net->has_modules = h.has_modules != 0;
             size_t pos = 0;
             for (int gi = 0; gi < 2; gi++) {
                 net->groups[gi].assign(all.begin() + pos, all.begin() + pos + kGroupFloats);
@@ -1394,9 +1423,14 @@ int32_t nis_set_weights(nis_ctx* ctx, const void* blob, size_t nbytes)
                 pos += dout[i];
             }
             if (net->has_fp8) {
-                net->fp8_scales.assign(all.begin() + pos, all.end());
+                net->fp8_scales.assign(all.begin() + pos, all.begin() + pos + 2 + net->n_linear);
+                pos += 2 + net->n_linear;
                 for (float v : net->fp8_scales)
                     if (!(v > 0.f)) fail(NIS_E_INVALID, "FP8 activation scales must be > 0");
+            }
+            if (net->has_modules) {
+                net->modules.assign(all.begin() + pos, all.end());
+                upload_vec(net->mod, net->modules, "backbone modules");
             }
             pack_net(net, kPrecFP32);
             pack_net(net, kPrecBF16);
@@ -1449,6 +1483,18 @@ int32_t nis_set_templates(nis_ctx* ctx, int32_t kind)
         std::lock_guard<std::mutex> lk(ctx->mu);
         if (kind != NIS_TEMPLATES_LATTICE && kind != NIS_TEMPLATES_PAPER) fail(NIS_E_INVALID, "unknown template kind");
         ctx->templates = kind;
+    });
+}
+
+int32_t nis_set_backbone(nis_ctx* ctx, int32_t kind)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (kind != NIS_BACKBONE_MLP && kind != NIS_BACKBONE_PAPER) fail(NIS_E_INVALID, "unknown backbone kind");
+        if (kind == NIS_BACKBONE_PAPER && ctx->net && !ctx->net->has_modules)
+            fail(NIS_E_STATE, "the weights hold no backbone modules");
+        ctx->backbone = kind;
     });
 }
 

@@ -123,6 +123,7 @@ struct Params {
     int channels = 1;      // 3: one radiance per colour channel, albedo rgb[c]
     float rgb[3] = {0, 0, 0};
     int templates = 0;     // NIS_TEMPLATES_LATTICE or NIS_TEMPLATES_PAPER
+    int modules = 0;       // 1: the paper's backbone modules between the templates and the MLP
 };
 
 inline bool grey_albedo(const Medium* M)
@@ -157,6 +158,9 @@ struct Net {
     int width = 0, n_linear = 0, wpad = 0;
     float lam = 0.6f, gamma = 4.f;
     bool has_fp8 = false;              // activation scales known (blob or calibration); FP8 packed
+    bool has_modules = false;          // the blob holds the paper's backbone modules
+    std::vector<float> modules;        // their weights, blob order
+    DevBuf mod;                        // ... on the device (FP32)
     std::vector<float> groups[2];      // 3844 floats each, blob order
     std::vector<std::vector<float>> A, beta;
     // dequantisation scales of the FP8 activations (x = code * scale): conv1
@@ -188,16 +192,19 @@ extern thread_local Profiler* g_prof;   // profiler of the context this thread i
 constexpr int64_t kChunk = 1 << 21;   // points per feature/backbone pass
 constexpr int kRenderBand = 8;         // rows per band of a rendered frame's collision order
 
-// Descriptor and single-scatter scratch of one stream.
+// Descriptor and single-scatter scratch of one stream (and, for the paper's
+// backbone modules, the FP32 template feature rows they read).
 struct Workspace {
-    DevBuf desc, f0;
-    size_t bytes() const { return desc.bytes + f0.bytes; }
+    DevBuf desc, f0, feat;
+    size_t bytes() const { return desc.bytes + f0.bytes + feat.bytes; }
     void release()
     {
         desc.release();
         f0.release();
+        feat.release();
     }
 };
+constexpr int64_t kModuleChunk = 1 << 16;   // points per pass with the backbone modules
 
 // Per-pixel buffers of one frame on one stream.
 struct FrameWork {
@@ -232,7 +239,8 @@ struct QueryOut {
 struct WsView {
     void* desc = nullptr;
     float* f0 = nullptr;
-    int64_t chunk = 0;   // points per pass
+    float* feat = nullptr;   // backbone modules only: FP32 template feature rows [chunk][kDescPad]
+    int64_t chunk = 0;       // points per pass
 };
 
 // Sweep if stale, refresh the site tables, then features and backbone over
@@ -272,6 +280,7 @@ struct nis_ctx {
     nis::Net* net = nullptr;
     int precision = nis::kPrecFP32;
     int templates = 0;                 // NIS_TEMPLATES_LATTICE (default) or NIS_TEMPLATES_PAPER
+    int backbone = 0;                  // NIS_BACKBONE_MLP (default) or NIS_BACKBONE_PAPER
     nis::Workspace ws;
     nis::FrameWork fw;
     nis::DevBuf io;

@@ -32,6 +32,8 @@ NIS_FP32, NIS_BF16, NIS_FP8 = 0, 1, 2
 NIS_EAGER = 1
 NOALLOC_MAX_POINTS = 8192   # NIS_NOALLOC_MAX_POINTS
 NIS_TEMPLATES_LATTICE, NIS_TEMPLATES_PAPER = 0, 1
+NIS_BACKBONE_MLP, NIS_BACKBONE_PAPER = 0, 1
+MODULE_FLOATS = 56706      # floats of the backbone-module block of the weight blob
 TPL_SITES = 266
 NIS_QUEUED, NIS_RUNNING = 1, 2
 LAYERS, SITES, STATS, DESCRIPTOR = 12, 225, 8, 1057
@@ -87,6 +89,7 @@ _SIGNATURES = {
     "nis_query_device_noalloc": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
     "nis_calibrate_fp8": [_vp, _i32, _vp, _vp, _i64, _vp],
     "nis_set_templates": [_vp, _i32],
+    "nis_set_backbone": [_vp, _i32],
     "nis_debug_template_features": [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp],
     "nis_query_rgb": [_vp, _i32, _vp, _vp, _i64, _vp],
     "nis_query_rgb_device": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
@@ -169,14 +172,20 @@ for _n in _SIGNATURES:
 _GROUP_ORDER = ("w1", "b1", "w2", "b2", "s1", "c1", "s2", "c2")
 
 
-def pack_weights(params, fp8_scales=None):
+def pack_weights(params, fp8_scales=None, modules=None):
     """Serialise a parameter dict (see ``workloads.weights``) into the blob
-    layout documented at nis_set_weights."""
+    layout documented at nis_set_weights; ``modules`` is the list of arrays
+    of the backbone modules (``workloads.weights.he_init_modules``)."""
     width, n_linear = int(params["width"]), int(params["n_linear"])
     has_fp8 = fp8_scales is not None
-    header = struct.pack("<4s5I2fI7I", b"NISW", 1, DESCRIPTOR, width, n_linear, 2,
+    mod = None
+    if modules is not None:
+        mod = np.concatenate([np.asarray(a, np.float32).ravel() for a in modules])
+        if mod.size != MODULE_FLOATS:
+            raise ValueError("the module block holds %d floats, not %d" % (mod.size, MODULE_FLOATS))
+    header = struct.pack("<4s5I2f2I6I", b"NISW", 1, DESCRIPTOR, width, n_linear, 2,
                          float(params["lam"]), float(params["gamma"]), 1 if has_fp8 else 0,
-                         *([0] * 7))
+                         0 if mod is None else 1, *([0] * 6))
     parts = []
     for g in ("diffuse", "highlight"):
         for k in _GROUP_ORDER:
@@ -186,6 +195,8 @@ def pack_weights(params, fp8_scales=None):
         parts.append(np.asarray(b, np.float32).ravel())
     if has_fp8:
         parts.append(np.asarray(fp8_scales, np.float32).ravel())
+    if mod is not None:
+        parts.append(mod)
     return header + np.concatenate(parts).astype("<f4").tobytes()
 
 
@@ -278,9 +289,9 @@ class Context:
         d = np.ascontiguousarray(direction, dtype=np.float32)
         _check(_lib.nis_set_light(self.h, medium, _ptr(d), radiance, NIS_EAGER if eager else 0))
 
-    def set_weights(self, params=None, blob=None, fp8_scales=None):
+    def set_weights(self, params=None, blob=None, fp8_scales=None, modules=None):
         if blob is None:
-            blob = pack_weights(params, fp8_scales)
+            blob = pack_weights(params, fp8_scales, modules)
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(_lib.nis_set_weights(self.h, buf, len(blob)))
 
@@ -502,6 +513,13 @@ class Context:
         if isinstance(kind, str):
             kind = {"lattice": NIS_TEMPLATES_LATTICE, "paper": NIS_TEMPLATES_PAPER}[kind]
         _check(_lib.nis_set_templates(self.h, kind))
+
+    def set_backbone(self, kind):
+        """"mlp" (default) or "paper" (the layer-by-layer modules before the
+        MLP; needs the paper's templates and weights with the module block)."""
+        if isinstance(kind, str):
+            kind = {"mlp": NIS_BACKBONE_MLP, "paper": NIS_BACKBONE_PAPER}[kind]
+        _check(_lib.nis_set_backbone(self.h, kind))
 
     def template_features(self, medium, points, dirs):
         """Gather-stage outputs at the paper's templates (torch tensors)."""

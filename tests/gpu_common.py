@@ -66,6 +66,10 @@ class Scene:
         return self.om.tpl_query(oracle_params(params), pts, dirs, f32(self.sigma_t), f32(self.albedo),
                                  self.phase(), f32(self.radiance), want_desc=want_desc)
 
+    def oracle_tpl_modules_query(self, params, mods, pts, dirs, want_desc=False):
+        return self.om.tpl_modules_query(oracle_params(params), mods, pts, dirs, f32(self.sigma_t),
+                                         f32(self.albedo), self.phase(), f32(self.radiance), want_desc=want_desc)
+
     def oracle_features(self, params, pts, dirs):
         return self.om.features(f32(self.sigma_t), self.phase(), f32(params["lam"]), pts, dirs, volume=self.volume)
 
