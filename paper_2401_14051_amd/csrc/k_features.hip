@@ -921,12 +921,12 @@ __device__ __forceinline__ double tpl_coord(double x, double scale, double o)
     return x + scale * o;
 }
 
-// density of level m at s: zero outside the closed unit cube, else index-clamped trilinear
-__device__ __forceinline__ float tpl_rho(const MediumView& mv, int m, const double s[3])
+// density of level lv at s: zero outside the closed unit cube, else index-clamped trilinear
+__device__ __forceinline__ float tpl_rho(const MediumView& mv, const Level& lv, const double s[3])
 {
     if (s[0] < 0.0 || s[0] > 1.0 || s[1] < 0.0 || s[1] > 1.0 || s[2] < 0.0 || s[2] > 1.0) return 0.f;
-    const int nm = mv.lev[m].n;
-    const float* R = mv.rho + mv.lev[m].rho_off;
+    const int nm = lv.n;
+    const float* R = mv.rho + lv.rho_off;
     int i0[3], i1[3];
     float w[3];
     for (int d = 0; d < 3; d++) {
@@ -951,8 +951,29 @@ k_template_features(TplArgs A)
     typedef typename M::elem E;
     __shared__ float vals[kTplWaves][3][kTplSites];   // tbar, rho, phi of each template point
     __shared__ float stv[kTplWaves][kLayers][kStats];
+    // per-level and per-layer parameters a site picks by a run-time index
+    // (dynamic indices into the kernel arguments would go through private
+    // memory): levels and their coefficients, diffuse radii and levels, and
+    // each wave's highlight levels
+    __shared__ Level slev[kMaxLevels];
+    __shared__ float scoef[kMaxLevels];
+    __shared__ double srad[kDiffuse];
+    __shared__ int smd[kDiffuse];
+    __shared__ int smh[kTplWaves][kLayers - kDiffuse];
     const MediumView& mv = A.mv;
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kMaxLevels; i++) {
+            slev[i] = mv.lev[i];
+            scoef[i] = A.coef[i];
+        }
+#pragma unroll
+        for (int i = 0; i < kDiffuse; i++) {
+            srad[i] = A.radius[i];
+            smd[i] = A.mdiff[i];
+        }
+    }
     const int64_t npts = A.count ? min(max((int64_t)*A.count - A.count_off, (int64_t)0), A.npts) : A.npts;
     const int64_t p = (int64_t)blockIdx.x * kTplWaves + wave;
     if ((int64_t)blockIdx.x * kTplWaves >= npts) return;
@@ -969,8 +990,11 @@ k_template_features(TplArgs A)
     const double wl = w[0] * mv.l[0] + w[1] * mv.l[1] + w[2] * mv.l[2];
     const float wf[3] = {(float)w[0], (float)w[1], (float)w[2]};
     const double dlen = tpl_light_extent(mv.l, x);
-    int mh[kLayers - kDiffuse];
-    for (int h = 0; h < kLayers - kDiffuse; h++) mh[h] = tpl_level(A.dh[h] * dlen, mv.n0, mv.levels);
+    if (lane == 0) {
+#pragma unroll
+        for (int h = 0; h < kLayers - kDiffuse; h++) smh[wave][h] = tpl_level(A.dh[h] * dlen, mv.n0, mv.levels);
+    }
+    __syncthreads();
     // one lobe's term of the phase at w . d for a site table entry (as in k_features)
     auto lobe = [&](int i, const float4& e) __attribute__((always_inline)) {
         const float gs = mv.ph_s[i];
@@ -983,18 +1007,14 @@ k_template_features(TplArgs A)
 
     for (int t = lane; t < kTplSites; t += 64) {
         const int k = tpl_layer_of(t);
+        const bool diffuse = k < kDiffuse;
+        const double scale = diffuse ? srad[k] : dlen;
+        const int m = diffuse ? smd[k] : smh[wave][k - kDiffuse];
         double s[3];
-        int m;
-        if (k < kDiffuse) {
-            for (int d = 0; d < 3; d++) s[d] = tpl_coord(x[d], A.radius[k], A.tab->off[t][d]);
-            m = A.mdiff[k];
-        } else {
-            for (int d = 0; d < 3; d++) s[d] = tpl_coord(x[d], dlen, A.tab->off[t][d]);
-            m = mh[k - kDiffuse];
-        }
-        const Level& lv = mv.lev[m];
+        for (int d = 0; d < 3; d++) s[d] = tpl_coord(x[d], scale, A.tab->off[t][d]);
+        const Level lv = slev[m];
         const int nm = lv.n;
-        const float r = tpl_rho(mv, m, s);
+        const float r = tpl_rho(mv, lv, s);
         // path density at s (sheared lookup, index-clamped trilinear)
         double g[3];
         for (int d = 0; d < 3; d++) g[d] = s[d] * nm - 0.5;
@@ -1003,7 +1023,7 @@ k_template_features(TplArgs A)
         const double fu = floor(Uf), fv = floor(Vf), fj = floor(Jf);
         const float Dv = sample_D(mv.dpairs + lv.q_off, lv, (int)fu, (int)fv, (int)fj, (float)(Uf - fu),
                                   (float)(Vf - fv), (float)(Jf - fj));
-        const float T = __builtin_amdgcn_exp2f(-A.coef[m] * 1.44269504088896341f * Dv);
+        const float T = __builtin_amdgcn_exp2f(-scoef[m] * 1.44269504088896341f * Dv);
         const bool at_p = s[0] == x[0] && s[1] == x[1] && s[2] == x[2];
         const float4 e = at_p ? centre : A.tab->site[t];
         float P = lobe(0, e);

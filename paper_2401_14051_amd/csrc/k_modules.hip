@@ -14,14 +14,29 @@
 // m = ReLU(M [h_diffuse; h_highlight] + mb), and the descriptor the backbone
 // MLP reads is [m_T; m_rho; m_phi; g; alpha], zeros, albedo at index 1056.
 //
-// Work split: one lane per point; every weight is the same for all lanes of
-// a wave (scalar loads), so the contractions are per-lane FMA chains with a
-// scalar operand.  The layers' sizes are compile-time constants, so the
-// per-point state stays in registers.
+// Work split: a wave takes 32 points and runs every contraction as a chain
+// of 32x32x2 FP32 MFMAs with the points as the N dimension (lane l holds
+// point l % 32).  A vector of R rows per point lives in the accumulator
+// layout: tile t (32 rows), register r, lane half hh = l / 32 hold row
+// 32 t + 8 (r / 4) + 4 hh + r % 4.  One register of that layout is exactly a
+// B operand (its two K entries are the rows of the two lane halves), so a
+// layer's output feeds the next contraction without any data movement: the
+// host packs each weight matrix's columns in that order.  The attention's
+// excitation is one more MFMA pair per input tile whose B operand is
+// (z_0 | z_1) and (1 | 0) and whose A holds S2 and e2, which yields the gate
+// logits in the same layout.  Only the registers holding a row below R take
+// part in the K loop; the rest are zero.
+//
+// A workgroup of 4 waves (128 points) copies one feature type's packed
+// weights (108 KiB) into LDS at a time and reads every A fragment from there,
+// one 4-byte word per lane; the chains would otherwise wait on L2 for each
+// fragment at one wave per SIMD.
 #include "launch_args.h"
 #include "mfma.h"
 
 namespace nis {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 template <int V> using ICm = std::integral_constant<int, V>;
 
@@ -33,161 +48,417 @@ template <int I, int N, class F> __device__ __forceinline__ void static_loop(F&&
     }
 }
 
-__device__ __forceinline__ float sigmoidf_(float x) { return 1.f / (1.f + __expf(-x)); }
+constexpr int kMerge = 64;                 // width of a type's merge
+constexpr int kCat = 48 + 8;               // last diffuse layer + last highlight layer
+constexpr int kModPts = 32;                // points per wave
+constexpr int kModWaves = 4;
+
+// ---- layout of a per-point vector over the accumulator registers -----------
+
+__host__ __device__ constexpr int mtiles(int rows) { return (rows + 31) / 32; }
+__host__ __device__ constexpr int mrow(int t, int r, int hh) { return 32 * t + 8 * (r / 4) + 4 * hh + r % 4; }
+// registers of tile t holding some row below `rows` (a prefix: rows grow with r)
+__host__ __device__ constexpr int muse(int t, int rows)
+{
+    int c = 0;
+    for (int r = 0; r < 16; r++) c += mrow(t, r, 0) < rows ? 1 : 0;
+    return c;
+}
+// K steps of a contraction over a vector of `rows` rows
+__host__ __device__ constexpr int mksteps(int rows)
+{
+    int c = 0;
+    for (int t = 0; t < mtiles(rows); t++) c += muse(t, rows);
+    return c;
+}
+
+// ---- packed weights ----------------------------------------------------------
+// Per step: S1 (16) and e1 (2), padded to 32 floats; per input tile the two
+// gate fragments (S2 columns, e2); f1 as [out tile][hh][16]; F1's fragments
+// [out tile][K step][64 lanes]; f2; F2's fragments.  Per type after its two
+// modules: mb as [tile][hh][16], then M's fragments [tile][K step][64].
+constexpr int kHdr = 32;
+
+__host__ __device__ constexpr int pk_step_floats(int k)
+{
+    const int a = tpl_count(k) + 2, b = tpl_count(k + 1), tb = mtiles(b);
+    return kHdr + mtiles(a) * 128 + tb * 32 + tb * mksteps(a) * 64 + tb * 32 + tb * mksteps(b) * 64;
+}
+constexpr int kMergeK = mksteps(48) + mksteps(8);
+__host__ __device__ constexpr int pk_merge_floats() { return 2 * 32 + 2 * kMergeK * 64; }
+__host__ __device__ constexpr int pk_type_floats()
+{
+    int s = pk_merge_floats();
+    for (int k = 0; k < kLayers - 1; k++)
+        if (k != kDiffuse - 1) s += pk_step_floats(k);
+    return s;
+}
 
 // offset (in floats) of a layer's block in a feature row: per layer its
 // tbar, rho, phi (n each) and squeeze vector (8)
-constexpr int feat_base(int k)
+__host__ __device__ constexpr int feat_base(int k)
 {
     int b = 0;
     for (int i = 0; i < k; i++) b += 3 * tpl_count(i) + kStats;
     return b;
 }
 
-// floats of one step's weights from layer k
-constexpr int step_floats(int k)
+// floats of one step's weights in the weight blob (from layer k)
+constexpr int raw_step_floats(int k)
 {
-    return 16 + 2 + 2 * (tpl_count(k) + 2) + (tpl_count(k) + 2) + tpl_count(k + 1) * (tpl_count(k) + 2) +
-           tpl_count(k + 1) + tpl_count(k + 1) * tpl_count(k + 1) + tpl_count(k + 1);
+    const int n = tpl_count(k), a = n + 2, b = tpl_count(k + 1);
+    return 16 + 2 + 2 * a + a + b * a + b + b * b + b;
 }
-
-// floats of a module's steps (group 0: layers 0..7, group 1: 8..11)
-constexpr int module_floats(int grp)
+constexpr int raw_total()
 {
     int s = 0;
-    for (int k = grp ? kDiffuse : 0; k < (grp ? kLayers - 1 : kDiffuse - 1); k++) s += step_floats(k);
-    return s;
+    for (int k = 0; k < kLayers - 1; k++)
+        if (k != kDiffuse - 1) s += raw_step_floats(k);
+    return 3 * s + 3 * (kMerge * kCat + kMerge);
 }
 
-constexpr int kMerge = 64;
-constexpr int kCat = 48 + 8;   // last diffuse layer + last highlight layer
-constexpr int kModuleFloats = 3 * (module_floats(0) + module_floats(1)) + 3 * (kMerge * kCat + kMerge);
+__device__ __forceinline__ f32x16 mma(float a, float b, f32x16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
 
-// One module: h (the group's first layer's features of type tau on entry,
-// its final state on exit); w points at its first step's weights.
+__device__ __forceinline__ float sigmoidf_(float x) { return __builtin_amdgcn_rcpf(1.f + __expf(-x)); }
+
+// One step from layer K: h (tiles of n_K rows) -> h (tiles of n_{K+1} rows).
+// row: the lane's point's feature row; wp: the step's packed weights.
+template <int K>
+__device__ __forceinline__ void mod_step(const float* __restrict__& wp, const float* __restrict__ row, int tau,
+                                         float g, float alpha, int lane, f32x16 (&h)[2])
+{
+    constexpr int n = tpl_count(K), a = n + 2, b = tpl_count(K + 1);
+    constexpr int TA = mtiles(a), TB = mtiles(b);
+    const int hh = lane >> 5;
+    // excitation of the layer's squeeze vector (eq. 25)
+    const float* v = row + feat_base(K) + 3 * n;
+    float z0 = wp[16], z1 = wp[17];
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const float vi = v[i];
+        z0 += wp[i] * vi;
+        z1 += wp[8 + i] * vi;
+    }
+    z0 = fmaxf(z0, 0.f);
+    z1 = fmaxf(z1, 0.f);
+    wp += kHdr;
+    // u = [h; g; alpha]: rows n and n + 1 (zero so far) take g and alpha
+    f32x16 u[TA];
+#pragma unroll
+    for (int t = 0; t < TA; t++) u[t] = t < mtiles(n) ? h[t < 2 ? t : 0] : f32x16{};
+    {
+        constexpr int tg = n / 32, rg = 4 * ((n % 32) / 8) + n % 4, hg = (n % 8) / 4;
+        constexpr int ta = (n + 1) / 32, ra = 4 * (((n + 1) % 32) / 8) + (n + 1) % 4, ha = ((n + 1) % 8) / 4;
+        if (hh == hg) u[tg][rg] = g;
+        if (hh == ha) u[ta][ra] = alpha;
+    }
+    // gate (eq. 26): logits S2 z + e2 in the same layout, then a = sigmoid * u
+    const float bz0 = hh ? z1 : z0, bz1 = hh ? 0.f : 1.f;
+#pragma unroll
+    for (int t = 0; t < TA; t++) {
+        f32x16 gl = mma(wp[t * 128 + lane], bz0, f32x16{});
+        gl = mma(wp[t * 128 + 64 + lane], bz1, gl);
+#pragma unroll
+        for (int r = 0; r < muse(t, a); r++) u[t][r] *= sigmoidf_(gl[r]);
+    }
+    wp += TA * 128;
+    // FC-1, fused with the next layer's features: y = x + F1 a + f1
+    const float* xr = row + feat_base(K + 1) + tau * b;
+    f32x16 x[TB], y[TB];
+#pragma unroll
+    for (int mt = 0; mt < TB; mt++) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int r0 = 32 * mt + 8 * q + 4 * hh;   // rows r0 .. r0 + 3 (in the row: always readable)
+            const float2 lo = *reinterpret_cast<const float2*>(xr + r0);
+            const float2 hi = *reinterpret_cast<const float2*>(xr + r0 + 2);
+            const float e[4] = {lo.x, lo.y, hi.x, hi.y};
+#pragma unroll
+            for (int i = 0; i < 4; i++) x[mt][4 * q + i] = r0 + i < b ? e[i] : 0.f;
+        }
+        const float* b1 = wp + mt * 32 + hh * 16;
+#pragma unroll
+        for (int r = 0; r < 16; r++) y[mt][r] = x[mt][r] + b1[r];
+    }
+    wp += TB * 32;
+#pragma unroll
+    for (int mt = 0; mt < TB; mt++) {
+        int s = 0;
+#pragma unroll
+        for (int t = 0; t < TA; t++)
+#pragma unroll
+            for (int r = 0; r < muse(t, a); r++, s++)
+                y[mt] = mma(wp[(mt * mksteps(a) + s) * 64 + lane], u[t][r], y[mt]);
+    }
+    wp += TB * mksteps(a) * 64;
+    // FC-2, fused again: h = ReLU(F2 y + f2) + x
+    f32x16 acc[TB];
+#pragma unroll
+    for (int mt = 0; mt < TB; mt++) {
+        const float* b2 = wp + mt * 32 + hh * 16;
+#pragma unroll
+        for (int r = 0; r < 16; r++) acc[mt][r] = b2[r];
+    }
+    wp += TB * 32;
+#pragma unroll
+    for (int mt = 0; mt < TB; mt++) {
+        int s = 0;
+#pragma unroll
+        for (int t = 0; t < TB; t++)
+#pragma unroll
+            for (int r = 0; r < muse(t, b); r++, s++)
+                acc[mt] = mma(wp[(mt * mksteps(b) + s) * 64 + lane], y[t][r], acc[mt]);
+    }
+    wp += TB * mksteps(b) * 64;
+#pragma unroll
+    for (int mt = 0; mt < 2; mt++) {
+        if (mt < TB) {
+#pragma unroll
+            for (int r = 0; r < 16; r++) h[mt][r] = fmaxf(acc[mt < TB ? mt : 0][r], 0.f) + x[mt < TB ? mt : 0][r];
+        } else {
+            h[mt] = f32x16{};
+        }
+    }
+}
+
+// A module of group G over its layers: h enters as the group's first layer's
+// features of type tau and leaves as its final state.
 template <int G>
-__device__ __forceinline__ void run_module(const float* __restrict__ w, int tau, const float* __restrict__ row,
-                                           float g, float alpha, float (&h)[48])
+__device__ __forceinline__ void run_module(const float* __restrict__& wp, const float* __restrict__ row, int tau,
+                                           float g, float alpha, int lane, f32x16 (&h)[2])
 {
     constexpr int k0 = G ? kDiffuse : 0, k1 = G ? kLayers - 1 : kDiffuse - 1;
+    constexpr int n0 = tpl_count(k0);
+    const int hh = lane >> 5;
+    const float* x0 = row + feat_base(k0) + tau * n0;
+    h[0] = f32x16{};
+    h[1] = f32x16{};
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        const int rr = mrow(0, r, hh);
+        const float e = x0[rr < n0 ? rr : 0];
+        h[0][r] = rr < n0 ? e : 0.f;
+    }
     static_loop<k0, k1>([&](auto kc) __attribute__((always_inline)) {
-        constexpr int k = decltype(kc)::value;
-        constexpr int n = tpl_count(k), a = n + 2, b = tpl_count(k + 1);
-        const float* S1 = w;
-        const float* e1 = S1 + 16;
-        const float* S2 = e1 + 2;
-        const float* e2 = S2 + 2 * a;
-        const float* F1 = e2 + a;
-        const float* f1 = F1 + b * a;
-        const float* F2 = f1 + b;
-        const float* f2 = F2 + b * b;
-        w = f2 + b;
-        const float* v = row + feat_base(k) + 3 * n;
-        const float* xn = row + feat_base(k + 1) + tau * b;
-        float z[2];
-#pragma unroll
-        for (int r = 0; r < 2; r++) {
-            float acc = e1[r];
-#pragma unroll
-            for (int i = 0; i < 8; i++) acc += S1[r * 8 + i] * v[i];
-            z[r] = fmaxf(acc, 0.f);
-        }
-        float av[a];
-#pragma unroll
-        for (int i = 0; i < a; i++) {
-            const float ui = i < n ? h[i < n ? i : 0] : i == n ? g : alpha;
-            av[i] = sigmoidf_(e2[i] + S2[2 * i] * z[0] + S2[2 * i + 1] * z[1]) * ui;
-        }
-        float x[b], y[b];
-#pragma unroll
-        for (int o = 0; o < b; o++) {
-            x[o] = xn[o];
-            float acc = f1[o];
-#pragma unroll
-            for (int i = 0; i < a; i++) acc += F1[o * a + i] * av[i];
-            y[o] = x[o] + acc;
-        }
-#pragma unroll
-        for (int o = 0; o < b; o++) {
-            float acc = f2[o];
-#pragma unroll
-            for (int i = 0; i < b; i++) acc += F2[o * b + i] * y[i];
-            h[o] = fmaxf(acc, 0.f) + x[o];
-        }
+        mod_step<decltype(kc)::value>(wp, row, tau, g, alpha, lane, h);
     });
 }
 
 template <int PREC, bool F8>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * kModWaves)
 k_modules(const float* __restrict__ feat, const float* __restrict__ wm, int64_t npts, const int* count,
           int64_t count_off, void* desc, float desc_inv_scale, float albedo)
 {
     typedef typename Mfma<PREC>::elem E;
+    __shared__ __attribute__((aligned(16))) float wl[pk_type_floats()];
     const int64_t nv = count ? min(max((int64_t)*count - count_off, (int64_t)0), npts) : npts;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= nv) return;
-    const float* row = feat + p * kDescPad;
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, hh = lane >> 5;
+    // the whole workgroup leaves together (it shares barriers); a wave past
+    // the last point computes on that point and writes nothing
+    if ((int64_t)blockIdx.x * kModWaves * kModPts >= nv) return;
+    const int64_t p0 = ((int64_t)blockIdx.x * kModWaves + wave) * kModPts;
+    const int64_t p = p0 + (lane & 31);
+    const bool live = p < nv;
+    const float* row = feat + (live ? p : nv - 1) * kDescPad;
     const float g = row[3 * tpl_count(0) + 6], alpha = row[3 * tpl_count(0) + 7];
-    // a descriptor entry in the backbone's precision
-    auto put = [&](int e, float x) __attribute__((always_inline)) {
+    const int rowlen = F8 ? kDescF8 : kDescPad;
+    // four consecutive descriptor entries e .. e + 3 of the lane's point
+    auto put4 = [&](int e, float v0, float v1, float v2, float v3) __attribute__((always_inline)) {
+        if (!live) return;
         if constexpr (F8) {
-            x = __builtin_amdgcn_fmed3f(x * desc_inv_scale, -448.f, 448.f);
-            reinterpret_cast<uint8_t*>(desc)[p * kDescF8 + e] =
-                (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false) & 0xff);
+            const float s = desc_inv_scale;
+            auto q = [&](float x) { return __builtin_amdgcn_fmed3f(x * s, -448.f, 448.f); };
+            int w = __builtin_amdgcn_cvt_pk_fp8_f32(q(v0), q(v1), 0, false);
+            w = __builtin_amdgcn_cvt_pk_fp8_f32(q(v2), q(v3), w, true);
+            *reinterpret_cast<int*>(reinterpret_cast<uint8_t*>(desc) + p * kDescF8 + e) = w;
+        } else if constexpr (PREC == kPrecBF16) {
+            typedef float f32x2 __attribute__((ext_vector_type(2)));
+            typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+            const uint32_t a = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{v0, v1}, bf16x2v));
+            const uint32_t c = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{v2, v3}, bf16x2v));
+            *reinterpret_cast<uint2*>(reinterpret_cast<E*>(desc) + p * kDescPad + e) = make_uint2(a, c);
         } else {
-            reinterpret_cast<E*>(desc)[p * kDescPad + e] = Mfma<PREC>::cvt(x);
+            *reinterpret_cast<float4*>(reinterpret_cast<float*>(desc) + p * kDescPad + e) = make_float4(v0, v1, v2, v3);
         }
     };
-    const float* w = wm;
-    const float* wmerge = wm + 3 * (module_floats(0) + module_floats(1));
 #pragma unroll 1
     for (int tau = 0; tau < 3; tau++) {
-        float cat[kCat];
+        // this type's weights into LDS
+        __syncthreads();
         {
-            float h[48];
-#pragma unroll
-            for (int j = 0; j < tpl_count(0); j++) h[j] = row[feat_base(0) + tau * tpl_count(0) + j];
-            run_module<0>(w, tau, row, g, alpha, h);
-            w += module_floats(0);
-#pragma unroll
-            for (int j = 0; j < 48; j++) cat[j] = h[j];
+            const float4* src = reinterpret_cast<const float4*>(wm + (size_t)tau * pk_type_floats());
+            float4* dst = reinterpret_cast<float4*>(wl);
+            constexpr int n4 = pk_type_floats() / 4;
+#pragma unroll 9
+            for (int e = threadIdx.x; e < n4; e += 64 * kModWaves) dst[e] = src[e];
         }
-        {
-            float h[48];
+        __syncthreads();
+        const float* wp = wl;
+        f32x16 hd[2], hl[2];
+        run_module<0>(wp, row, tau, g, alpha, lane, hd);
+        run_module<1>(wp, row, tau, g, alpha, lane, hl);
+        // the type's merge of its two groups
+        f32x16 acc[2];
 #pragma unroll
-            for (int j = 0; j < tpl_count(kDiffuse); j++) h[j] = row[feat_base(kDiffuse) + tau * tpl_count(kDiffuse) + j];
-            run_module<1>(w, tau, row, g, alpha, h);
-            w += module_floats(1);
+        for (int mt = 0; mt < 2; mt++) {
+            const float* bm = wp + mt * 32 + hh * 16;
 #pragma unroll
-            for (int j = 0; j < 8; j++) cat[48 + j] = h[j];
+            for (int r = 0; r < 16; r++) acc[mt][r] = bm[r];
         }
-        // the type's merge of its two groups, written as it is formed
-        const float* M = wmerge + tau * (kMerge * kCat + kMerge);
-        const float* mb = M + kMerge * kCat;
-#pragma unroll 4
-        for (int o = 0; o < kMerge; o++) {
-            float acc = mb[o];
+        wp += 64;
 #pragma unroll
-            for (int i = 0; i < kCat; i++) acc += M[o * kCat + i] * cat[i];
-            put(tau * kMerge + o, fmaxf(acc, 0.f));
+        for (int mt = 0; mt < 2; mt++) {
+            int s = 0;
+#pragma unroll
+            for (int t = 0; t < 2; t++)
+#pragma unroll
+                for (int r = 0; r < muse(t, 48); r++, s++) acc[mt] = mma(wp[(mt * kMergeK + s) * 64 + lane], hd[t][r], acc[mt]);
+#pragma unroll
+            for (int r = 0; r < muse(0, 8); r++, s++) acc[mt] = mma(wp[(mt * kMergeK + s) * 64 + lane], hl[0][r], acc[mt]);
+        }
+        wp += 2 * kMergeK * 64;
+#pragma unroll
+        for (int mt = 0; mt < 2; mt++)
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                put4(tau * kMerge + mrow(mt, 4 * q, hh), fmaxf(acc[mt][4 * q], 0.f), fmaxf(acc[mt][4 * q + 1], 0.f),
+                     fmaxf(acc[mt][4 * q + 2], 0.f), fmaxf(acc[mt][4 * q + 3], 0.f));
+    }
+    // then g, alpha, zeros up to the albedo entry at 1056, and zero padding:
+    // the wave writes the tails of its points one row after another, four
+    // entries per lane
+    const int64_t pend = max(min(p0 + kModPts, nv), p0);
+    for (int64_t pp = p0; pp < pend; pp++) {
+        const float gp = __shfl(g, (int)(pp - p0)), ap = __shfl(alpha, (int)(pp - p0));
+        for (int e = 3 * kMerge + 4 * lane; e < rowlen; e += 256) {
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int ei = e + i;
+                v[i] = ei == 3 * kMerge ? gp : ei == 3 * kMerge + 1 ? ap : ei == kDesc - 1 ? albedo : 0.f;
+            }
+            if constexpr (F8) {
+                const float s = desc_inv_scale;
+                auto q = [&](float x) { return __builtin_amdgcn_fmed3f(x * s, -448.f, 448.f); };
+                int w = __builtin_amdgcn_cvt_pk_fp8_f32(q(v[0]), q(v[1]), 0, false);
+                w = __builtin_amdgcn_cvt_pk_fp8_f32(q(v[2]), q(v[3]), w, true);
+                *reinterpret_cast<int*>(reinterpret_cast<uint8_t*>(desc) + pp * kDescF8 + e) = w;
+            } else if constexpr (PREC == kPrecBF16) {
+                typedef float f32x2 __attribute__((ext_vector_type(2)));
+                typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+                const uint32_t a = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{v[0], v[1]}, bf16x2v));
+                const uint32_t c = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{v[2], v[3]}, bf16x2v));
+                *reinterpret_cast<uint2*>(reinterpret_cast<E*>(desc) + pp * kDescPad + e) = make_uint2(a, c);
+            } else {
+                *reinterpret_cast<float4*>(reinterpret_cast<float*>(desc) + pp * kDescPad + e) =
+                    make_float4(v[0], v[1], v[2], v[3]);
+            }
         }
     }
-    // then g, alpha, zeros, the albedo entry at 1056 and zero padding
-    put(3 * kMerge, g);
-    put(3 * kMerge + 1, alpha);
-    const int rowlen = F8 ? kDescF8 : kDescPad;
-    for (int e = 3 * kMerge + 2; e < rowlen; e++) put(e, e == kDesc - 1 ? albedo : 0.f);
 }
 
-int module_floats_total() { return kModuleFloats; }
+static_assert(raw_total() == 56706, "module block size (documented at nis_set_weights)");
+
+int module_floats_total() { return raw_total(); }
+int module_packed_floats() { return 3 * pk_type_floats(); }
+
+// The blob's module block (its own order) -> the kernel's packed layout.
+void pack_modules(const float* raw, float* out)
+{
+    int step_off[3][kLayers] = {}, merge_off[3] = {};
+    int o = 0;
+    for (int tau = 0; tau < 3; tau++)
+        for (int k = 0; k < kLayers - 1; k++)
+            if (k != kDiffuse - 1) {
+                step_off[tau][k] = o;
+                o += raw_step_floats(k);
+            }
+    for (int tau = 0; tau < 3; tau++) merge_off[tau] = o + tau * (kMerge * kCat + kMerge);
+    float* w = out;
+    for (int tau = 0; tau < 3; tau++) {
+        for (int k = 0; k < kLayers - 1; k++) {
+            if (k == kDiffuse - 1) continue;
+            const int n = tpl_count(k), a = n + 2, b = tpl_count(k + 1), ta = mtiles(a), tb = mtiles(b);
+            const float* S1 = raw + step_off[tau][k];
+            const float* e1 = S1 + 16;
+            const float* S2 = e1 + 2;
+            const float* e2 = S2 + 2 * a;
+            const float* F1 = e2 + a;
+            const float* f1 = F1 + b * a;
+            const float* F2 = f1 + b;
+            const float* f2 = F2 + b * b;
+            for (int i = 0; i < kHdr; i++) w[i] = i < 16 ? S1[i] : i < 18 ? e1[i - 16] : 0.f;
+            w += kHdr;
+            for (int t = 0; t < ta; t++) {
+                for (int l = 0; l < 64; l++) {
+                    const int rr = 32 * t + l % 32, hh = l / 32;
+                    w[l] = rr < a ? S2[rr * 2 + hh] : 0.f;
+                    w[64 + l] = rr < a && hh == 0 ? e2[rr] : 0.f;
+                }
+                w += 128;
+            }
+            auto bias = [&](const float* f) {
+                for (int mt = 0; mt < tb; mt++)
+                    for (int hh = 0; hh < 2; hh++)
+                        for (int r = 0; r < 16; r++) {
+                            const int rr = mrow(mt, r, hh);
+                            w[(mt * 2 + hh) * 16 + r] = rr < b ? f[rr] : 0.f;
+                        }
+                w += tb * 32;
+            };
+            // fragments of W (b rows, `cols` columns) over a K vector of `cols` rows
+            auto frags = [&](const float* W, int cols) {
+                for (int mt = 0; mt < tb; mt++) {
+                    int s = 0;
+                    for (int t = 0; t < mtiles(cols); t++)
+                        for (int r = 0; r < muse(t, cols); r++, s++)
+                            for (int l = 0; l < 64; l++) {
+                                const int orow = 32 * mt + l % 32, c = mrow(t, r, l / 32);
+                                w[(mt * mksteps(cols) + s) * 64 + l] = orow < b && c < cols ? W[orow * cols + c] : 0.f;
+                            }
+                }
+                w += tb * mksteps(cols) * 64;
+            };
+            bias(f1);
+            frags(F1, a);
+            bias(f2);
+            frags(F2, b);
+        }
+        const float* M = raw + merge_off[tau];
+        const float* mb = M + kMerge * kCat;
+        for (int mt = 0; mt < 2; mt++)
+            for (int hh = 0; hh < 2; hh++)
+                for (int r = 0; r < 16; r++) w[(mt * 2 + hh) * 16 + r] = mb[mrow(mt, r, hh)];
+        w += 64;
+        for (int mt = 0; mt < 2; mt++) {
+            int s = 0;
+            for (int t = 0; t < 2; t++)
+                for (int r = 0; r < muse(t, 48); r++, s++)
+                    for (int l = 0; l < 64; l++) {
+                        const int c = mrow(t, r, l / 32);
+                        w[(mt * kMergeK + s) * 64 + l] = c < 48 ? M[(32 * mt + l % 32) * kCat + c] : 0.f;
+                    }
+            for (int r = 0; r < muse(0, 8); r++, s++)
+                for (int l = 0; l < 64; l++) {
+                    const int c = mrow(0, r, l / 32);
+                    w[(mt * kMergeK + s) * 64 + l] = c < 8 ? M[(32 * mt + l % 32) * kCat + 48 + c] : 0.f;
+                }
+        }
+        w += 2 * kMergeK * 64;
+    }
+}
 
 hipError_t launch_modules(int prec, const float* feat, const float* wm, int64_t npts, const int* count,
                           int64_t count_off, void* desc, float desc_inv_scale, float albedo, hipStream_t s)
 {
     if (npts <= 0) return hipSuccess;
-    const int64_t blocks = (npts + 255) / 256;
+    const int64_t per = (int64_t)kModWaves * kModPts;
+    const int64_t blocks = (npts + per - 1) / per;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    const dim3 g((int)blocks), b(256);
+    const dim3 g((int)blocks), b(64 * kModWaves);
     if (prec == kPrecFP8)
         hipLaunchKernelGGL((k_modules<kPrecBF16, true>), g, b, 0, s, feat, wm, npts, count, count_off, desc,
                            desc_inv_scale, albedo);

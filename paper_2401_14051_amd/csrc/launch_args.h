@@ -117,6 +117,8 @@ hipError_t launch_template_features(int prec, const TplArgs& a, hipStream_t s);
 hipError_t launch_modules(int prec, const float* feat, const float* wm, int64_t npts, const int* count,
                           int64_t count_off, void* desc, float desc_inv_scale, float albedo, hipStream_t s);
 int module_floats_total();   // floats of the module block of the weight blob
+int module_packed_floats();  // floats of that block in the kernel's packed layout
+void pack_modules(const float* raw, float* out);   // blob order -> packed layout
 hipError_t launch_desc_to_f32(int prec, const void* src, float* dst, int64_t n, float scale, hipStream_t s);
 hipError_t launch_mlp(int prec, const MlpArgs& a, hipStream_t s);
 // eta: the albedo entry as stored (FP8: already divided by the descriptor's scale)

@@ -1430,7 +1430,9 @@ int32_t nis_set_weights(nis_ctx* ctx, const void* blob, size_t nbytes)
             }
             if (net->has_modules) {
                 net->modules.assign(all.begin() + pos, all.end());
-                upload_vec(net->mod, net->modules, "backbone modules");
+                std::vector<float> packed((size_t)module_packed_floats());
+                pack_modules(net->modules.data(), packed.data());
+                upload_vec(net->mod, packed, "backbone modules");
             }
             pack_net(net, kPrecFP32);
             pack_net(net, kPrecBF16);

@@ -160,7 +160,7 @@ struct Net {
     bool has_fp8 = false;              // activation scales known (blob or calibration); FP8 packed
     bool has_modules = false;          // the blob holds the paper's backbone modules
     std::vector<float> modules;        // their weights, blob order
-    DevBuf mod;                        // ... on the device (FP32)
+    DevBuf mod;                        // ... on the device, in the module kernel's packed layout (FP32)
     std::vector<float> groups[2];      // 3844 floats each, blob order
     std::vector<std::vector<float>> A, beta;
     // dequantisation scales of the FP8 activations (x = code * scale): conv1
