@@ -943,14 +943,36 @@ __device__ __forceinline__ float tpl_rho(const MediumView& mv, const Level& lv, 
     return lerpf(lerpf(c00, c10, w[1]), lerpf(c01, c11, w[1]), w[2]);
 }
 
+// Where each descriptor entry below kTplFeat comes from in a wave's staged
+// values [tbar (266), rho (266), phi (266), squeeze vectors (12 x 8)].
+struct TplDescMap {
+    uint16_t src[kTplFeat];
+};
+constexpr TplDescMap make_tpl_desc_map()
+{
+    TplDescMap m{};
+    int e = 0;
+    for (int k = 0; k < kLayers; k++) {
+        const int n = tpl_count(k), f = tpl_first(k);
+        for (int ty = 0; ty < 3; ty++)
+            for (int j = 0; j < n; j++) m.src[e++] = (uint16_t)(ty * kTplSites + f + j);
+        for (int i = 0; i < kStats; i++) m.src[e++] = (uint16_t)(3 * kTplSites + k * kStats + i);
+    }
+    return m;
+}
+__constant__ TplDescMap kTplMap = make_tpl_desc_map();
+constexpr int kTplStage = 3 * kTplSites + kLayers * kStats;
+
 template <int PREC, bool DBG, bool F8>
 __global__ void __launch_bounds__(64 * kTplWaves)
 k_template_features(TplArgs A)
 {
     typedef Mfma<PREC> M;
     typedef typename M::elem E;
-    __shared__ float vals[kTplWaves][3][kTplSites];   // tbar, rho, phi of each template point
-    __shared__ float stv[kTplWaves][kLayers][kStats];
+    // per wave: tbar, rho, phi of each template point, then the squeeze vectors
+    __shared__ float stage[kTplWaves][kTplStage];
+    float* vals = stage[threadIdx.x / 64];
+    float* stv = vals + 3 * kTplSites;
     // per-level and per-layer parameters a site picks by a run-time index
     // (dynamic indices into the kernel arguments would go through private
     // memory): levels and their coefficients, diffuse radii and levels, and
@@ -1029,9 +1051,9 @@ k_template_features(TplArgs A)
         float P = lobe(0, e);
         for (int i = 1; i < mv.nl; i++) P += lobe(i, e);
         const float ph = __logf(1.f + P);
-        vals[wave][0][t] = T;
-        vals[wave][1][t] = r;
-        vals[wave][2][t] = ph;
+        vals[t] = T;
+        vals[kTplSites + t] = r;
+        vals[2 * kTplSites + t] = ph;
         if (DBG && live) {
             A.dbg_tbar[p * kTplSites + t] = T;
             A.dbg_rho[p * kTplSites + t] = r;
@@ -1039,24 +1061,36 @@ k_template_features(TplArgs A)
         }
     }
     __syncthreads();
-    // squeeze vector of eq. (24) per layer, one lane per layer
-    if (lane < kLayers) {
-        const int k = lane, f = tpl_first(k), n = tpl_count(k);
+    // squeeze vector of eq. (24) per layer: four lanes per layer, each over
+    // every fourth point, then summed over the four
+    {
+        const int k = min(lane >> 2, kLayers - 1), sub = lane & 3, f = tpl_first(k), n = tpl_count(k);
         float ts = 0.f, rs = 0.f, ps = 0.f, tm = -INFINITY, rm = -INFINITY, pm = -INFINITY;
-        for (int j = 0; j < n; j++) {
-            const float T = vals[wave][0][f + j], r = vals[wave][1][f + j], ph = vals[wave][2][f + j];
+        for (int j = sub; j < n; j += 4) {
+            const float T = vals[f + j], r = vals[kTplSites + f + j], ph = vals[2 * kTplSites + f + j];
             ts += T, rs += r, ps += ph;
             tm = fmaxf(tm, T), rm = fmaxf(rm, r), pm = fmaxf(pm, ph);
         }
-        const float inv = 1.f / (float)n;
-        const float v[kStats] = {rs * inv, ps * inv, ts * inv, rm, pm, tm, mv.g,
-                                 (float)acos(fmin(1.0, fmax(-1.0, wl)))};
-        for (int i = 0; i < kStats; i++) {
-            stv[wave][k][i] = v[i];
-            if (DBG && live) A.dbg_stats[(p * kLayers + k) * kStats + i] = v[i];
+#pragma unroll
+        for (int o = 1; o < 4; o <<= 1) {
+            ts += __shfl_xor(ts, o);
+            rs += __shfl_xor(rs, o);
+            ps += __shfl_xor(ps, o);
+            tm = fmaxf(tm, __shfl_xor(tm, o));
+            rm = fmaxf(rm, __shfl_xor(rm, o));
+            pm = fmaxf(pm, __shfl_xor(pm, o));
+        }
+        if (lane < 4 * kLayers && sub == 0) {
+            const float inv = 1.f / (float)n;
+            const float v[kStats] = {rs * inv, ps * inv, ts * inv, rm, pm, tm, mv.g,
+                                     (float)acos(fmin(1.0, fmax(-1.0, wl)))};
+            for (int i = 0; i < kStats; i++) {
+                stv[k * kStats + i] = v[i];
+                if (DBG && live) A.dbg_stats[(p * kLayers + k) * kStats + i] = v[i];
+            }
         }
     }
-    if (lane == kLayers && live) {
+    if (lane == 4 * kLayers && live) {
         // single-scatter term f(w.l) T(p) (eq. 19, eq. 15)
         const Level& l0 = mv.lev[0];
         double g[3];
@@ -1071,20 +1105,9 @@ k_template_features(TplArgs A)
     __syncthreads();
     if (!live) return;
     // the descriptor row: per layer tbar, rho, phi (template order), squeeze vector
-    const int rowlen = F8 ? kDescF8 : kDescPad;
+    const int rowlen = F8 ? kDescF8 : A.feat_only ? kTplFeat : kDescPad;
     for (int e = lane; e < rowlen; e += 64) {
-        float v = 0.f;
-        if (e < kTplFeat) {
-            int k = 0, base = 0;
-            while (e >= base + 3 * tpl_count(k) + kStats) {
-                base += 3 * tpl_count(k) + kStats;
-                k++;
-            }
-            const int o = e - base, n = tpl_count(k);
-            v = o < 3 * n ? vals[wave][o / n][tpl_first(k) + o % n] : stv[wave][k][o - 3 * n];
-        } else if (e == kDesc - 1) {
-            v = mv.albedo;
-        }
+        const float v = e < kTplFeat ? vals[kTplMap.src[e]] : e == kDesc - 1 ? mv.albedo : 0.f;
         if constexpr (F8) {
             reinterpret_cast<uint8_t*>(A.desc)[p * kDescF8 + e] = e < kTplFeat || e == kDesc - 1 ? fp8_code(v * A.desc_inv_scale) : 0;
         } else {

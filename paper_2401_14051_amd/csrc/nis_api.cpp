@@ -929,6 +929,7 @@ void run_query_in(const WsView& ws, const Net* net, int prec, const Medium* M, L
             // with the backbone modules the features go to the FP32 rows they read
             ta.desc = Pm.modules ? (void*)ws.feat : fa.desc;
             ta.desc_inv_scale = Pm.modules ? 1.f : fa.desc_inv_scale;
+            ta.feat_only = Pm.modules ? 1 : 0;
             ta.f0 = fa.f0;
             ta.dbg_tbar = o.tbar ? o.tbar + p0 * kTplSites : nullptr;
             ta.dbg_rho = o.rho ? o.rho + p0 * kTplSites : nullptr;
