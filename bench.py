@@ -54,6 +54,11 @@ def parse():
                     help="seeded subset of the frame's collisions checked against the oracle at the workload's g")
     ap.add_argument("--parity-sample-by-g", type=int, default=16384,
                     help="seeded subset checked at each g of the precision workload")
+    ap.add_argument("--paper-path", action="store_true", default=True,
+                    help="also time the paper's templates and backbone modules on the frame's collisions")
+    ap.add_argument("--no-paper-path", dest="paper_path", action="store_false")
+    ap.add_argument("--paper-sample", type=int, default=16384,
+                    help="seeded subset of the collisions checked against the oracle on the paper's path")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size (for scaling HBM counters)")
     ap.add_argument("--compare-fp32", action="store_true", default=True)
@@ -106,6 +111,102 @@ def kernel_work(wl, levels, level_geom, npix, npts, width, n_linear, prec):
         "backbone": {"bytes": npts * (row_bytes + 8), "flops": npts * mlp_flop},
         "image": {"bytes": npix * 4 + npts * 12},
     }
+
+
+TPL_COUNTS = (6, 8, 12, 16, 24, 32, 48, 48, 32, 16, 16, 8)
+
+
+def module_flop_per_point():
+    """Useful FLOPs of the paper's backbone modules per point: per type, each
+    step's excitation (S1 2x8, S2 (n+2)x2), FC-1 (n'x(n+2)) and FC-2 (n'xn'),
+    then the 64x56 merge; two FLOPs per multiply-add."""
+    macs = 0
+    for k in list(range(0, 7)) + list(range(8, 11)):
+        a, b = TPL_COUNTS[k] + 2, TPL_COUNTS[k + 1]
+        macs += 16 + 2 * a + b * a + b * b
+    return 2 * 3 * (macs + 64 * 56)
+
+
+def paper_path(ctx, mid, wl, params, pts, dirs, tp, td, stream, prec, om, sample, rng):
+    """The frame's collisions through the paper's templates, then either the
+    MLP directly or the six backbone modules and the MLP: per-kernel times,
+    algorithmic rates, and the radiance against the FP64 oracle on a seeded
+    subset."""
+    import torch
+    from workloads import weights
+    mods = weights.he_init_modules(seed=2)
+    ctx.set_weights(params, modules=mods)
+    out = {}
+    f32 = lambda x: float(np.float32(x))
+    op = dict(params)
+    op["lam"] = f32(params["lam"])
+    op["gamma"] = f32(params["gamma"])
+    sidx = np.sort(rng.choice(len(pts), min(sample, len(pts)), replace=False))
+    sp = torch.from_numpy(np.ascontiguousarray(pts[sidx], np.float32)).cuda()
+    sd = torch.from_numpy(np.ascontiguousarray(dirs[sidx], np.float32)).cuda()
+    tl = torch.empty(len(pts), dtype=torch.float32, device="cuda")
+    b_row = {"fp32": 4, "bf16": 2, "fp8": 1}[prec]
+    ctx.set_templates("paper")
+    for name, bb in (("templates_mlp", "mlp"), ("templates_modules_mlp", "paper")):
+        ctx.set_backbone(bb)
+        ent = {}
+        for pr in sorted({prec, "fp32"}):
+            if pr == "fp8":
+                ctx.calibrate_fp8(mid, sp[:65536], sd[:65536])
+            ctx.set_precision(pr)
+            for _ in range(2):
+                ctx.query_device(mid, tp, td, tl, stream=stream.cuda_stream)
+            torch.cuda.synchronize()
+            ctx.profile(True)
+            for _ in range(5):
+                ctx.query_device(mid, tp, td, tl, stream=stream.cuda_stream)
+            torch.cuda.synchronize()
+            rep = ctx.profile_report()
+            ctx.profile(False)
+            ks = {k: v[1] / 5 for k, v in rep.items()}
+            sl = torch.empty(len(sidx), dtype=torch.float32, device="cuda")
+            ctx.query_device(mid, sp, sd, sl)
+            _, y = ctx.network(mid, sp, sd, want_desc=False)
+            torch.cuda.synchronize()
+            ent[pr] = {"ms": sum(ks.values()), "kernels_ms": ks, "L": sl.cpu().numpy().astype(np.float64),
+                       "y": y.cpu().numpy().astype(np.float64)}
+        if bb == "mlp":
+            ref = om.tpl_query(op, pts[sidx], dirs[sidx], f32(wl.sigma_t), f32(wl.albedo), f32(wl.g), f32(wl.radiance))
+        else:
+            ref = om.tpl_modules_query(op, mods, pts[sidx], dirs[sidx], f32(wl.sigma_t), f32(wl.albedo), f32(wl.g),
+                                       f32(wl.radiance))
+        res = {}
+        for pr, e in ent.items():
+            res[pr] = {"ms": e["ms"], "kernels_ms": e["kernels_ms"],
+                       "points_per_s": len(pts) / (e["ms"] * 1e-3),
+                       "rel_l2_vs_fp64_oracle": float(np.linalg.norm(e["L"] - ref["L"]) / np.linalg.norm(ref["L"])),
+                       "max_abs_dy": float(np.abs(e["y"] - ref["y"]).max())}
+        # algorithmic rates at the headline precision
+        ks = ent[prec]["kernels_ms"]
+        n = len(pts)
+        if "features" in ks:
+            row = (894 * 4) if bb == "paper" else 894 * b_row
+            byt = n * (24 + row + 4)
+            valu = n * (266 * (2 * 14 + 2 + 4 + 12))
+            t = ks["features"] * 1e-3
+            res["template_features_rates"] = {"bytes_per_point": 24 + row + 4, "GBps": byt / t / 1e9,
+                                              "hbm_frac": byt / t / 1e9 / HBM_PEAK_GBS,
+                                              "valu_flop_per_point": valu / n,
+                                              "valu_frac": valu / t / 1e12 / VALU_FP32_TFLOPS}
+        if "modules" in ks:
+            fl = n * module_flop_per_point()
+            t = ks["modules"] * 1e-3
+            res["modules_rates"] = {"flop_per_point": module_flop_per_point(), "TFLOPs": fl / t / 1e12,
+                                    "mfma_frac_fp32": fl / t / 1e12 / MFMA_PEAK_TFLOPS["fp32"]}
+        out[name] = res
+        log("paper path %s: %s" % (name, {pr: round(r["ms"], 3) for pr, r in res.items() if "ms" in r}))
+    ctx.set_templates("lattice")
+    ctx.set_backbone("mlp")
+    ctx.set_precision(prec)
+    ctx.set_weights(params)
+    out["sample_points"] = int(len(sidx))
+    out["weights"] = "He-normal backbone (workload's) and modules (seed 2); FP8 scales calibrated on the sample"
+    return out
 
 
 def measured_traffic(kernel, prec, workload):
@@ -471,6 +572,15 @@ def main():
     ctx.set_medium_params(mid, wl.sigma_t, wl.albedo, wl.g)
     ctx.set_precision(args.precision)
 
+    # the paper's own templates and backbone modules over the same collisions
+    paper = None
+    if args.paper_path and args.workload == "frame":
+        paper = paper_path(ctx, mid, wl, params, pts, dirs, tp, td, stream, args.precision, om,
+                           args.paper_sample, np.random.default_rng(321))
+        if args.precision == "fp8":
+            ctx.calibrate_fp8(mid, torch.from_numpy(np.ascontiguousarray(pts[cidx], np.float32)).cuda(),
+                              torch.from_numpy(np.ascontiguousarray(dirs[cidx], np.float32)).cuda())
+
     # oracle throughput on the host cores (bounded sample, median of runs)
     cpu = None
     if args.cpu_sample > 0:
@@ -553,6 +663,7 @@ def main():
                      for p in precs},
         "fps_modes": fps_modes,
         "template_batch": template_batch,
+        "paper_templates_and_modules": paper,
         "misses_are_zero": misses_zero,
         "per_precision": {p: {"ms_per_step": res[p]["ms"], "points_per_s": len(pts) / (res[p]["ms"] * 1e-3),
                               "fps": 1000.0 / res[p]["ms"], "kernels_ms": res[p]["kernels"]} for p in precs},
