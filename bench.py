@@ -344,8 +344,12 @@ def serving(ctx, nis, args):
                "offered_rps": len(measured) / max(trace[-1]["t"] - t_from, 1e-9),
                "frames_per_s": len(ok) / span, "points_per_s": sum(x[4] for x in ok) / span,
                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+               "mean_ms": float(np.mean(lat)),
                "mean_queue_ms": float(np.mean([(x[2] - x[1]) * 1e3 for x in ok])),
-               "mean_service_ms": float(np.mean([(x[3] - x[2]) * 1e3 for x in ok]))}
+               "mean_service_ms": float(np.mean([(x[3] - x[2]) * 1e3 for x in ok])),
+               "service_mean_s": float(np.mean([x[3] - x[2] for x in ok])),
+               "service_m2_s2": float(np.mean([(x[3] - x[2]) ** 2 for x in ok])),
+               "service_p99_ms": float(np.percentile([(x[3] - x[2]) * 1e3 for x in ok], 99))}
         # latency by request class (medium edge, resolution): queueing
         # (submission to admission) and service (admission to completion)
         by = {}
@@ -366,6 +370,12 @@ def serving(ctx, nis, args):
         warm = [dict(t=0.0, n=512, res=(1920, 1080), light=(0.3, 0.9, 0.3), g=0.85, seed=i)
                 for i in range(args.serve_inflight)]
         run(warm)
+        # service times of requests that never share the device (one every
+        # 50 ms, the same mix): the moments of the M/G/1 estimate below
+        iso = configs.serving_trace(4.0, rate=60.0, seed=9)
+        for i, r in enumerate(iso):
+            r["t"] = 0.05 * i
+        isolated = run(iso)
         trace = configs.serving_trace(args.serve_warmup + args.serve_seconds, rate=args.serve_rate, seed=7)
         log("serving: %d requests over %.1fs (%.1fs warm-up) at %.0f req/s"
             % (len(trace), args.serve_warmup + args.serve_seconds, args.serve_warmup, args.serve_rate))
@@ -377,6 +387,15 @@ def serving(ctx, nis, args):
         trace2 = configs.serving_trace(args.serve_warmup + args.serve_sustained_seconds, rate=rate, seed=8)
         sustained = run(trace2, args.serve_warmup)
         log("serving: sustained %s" % json.dumps(sustained))
+        # Pollaczek-Khinchine: a single server fed Poisson arrivals at rate
+        # lambda waits lambda E[S^2] / (2 (1 - rho)) on average, rho = lambda E[S]
+        es, es2 = isolated["service_mean_s"], isolated["service_m2_s2"]
+        rho = rate * es
+        mg1 = {"isolated_service_mean_ms": es * 1e3, "isolated_service_p99_ms": isolated["service_p99_ms"],
+               "isolated_service_m2_ms2": es2 * 1e6, "rho": rho,
+               "predicted_mean_wait_ms": rate * es2 / (2 * (1 - rho)) * 1e3 if rho < 1 else None,
+               "measured_mean_latency_minus_isolated_service_ms": sustained["mean_ms"] - es * 1e3}
+        log("serving: M/G/1 %s" % json.dumps(mg1))
     finally:
         ctx.server_stop()
     for m in mids.values():
@@ -387,7 +406,8 @@ def serving(ctx, nis, args):
                       % (args.serve_seconds, args.serve_warmup, args.serve_inflight, args.serve_budget_gb),
             "latency": "submission to observed completion, host steady clock",
             "at_%g_rps" % args.serve_rate: offered,
-            "at_70pct_capacity": dict(sustained, rate_rps=rate)}
+            "at_70pct_capacity": dict(sustained, rate_rps=rate),
+            "mg1_at_70pct": mg1}
 
 
 def main():
