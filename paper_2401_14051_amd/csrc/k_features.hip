@@ -602,14 +602,14 @@ k_features(FeatArgs A)
         // evaluates the slab's 5 site rows (c, then b) and accumulates their
         // statistics.  The single-voxel level reads its voxel once.
         float rs = 0.f, rmx = -INFINITY;
-        auto accum = [&](int r, int mask, const float* Rv) __attribute__((always_inline)) {
-            // in-cube bits of the row's sites: the slab, the lateral j, then each i
-            const int jj = r % 5;
-            const int m5 = ((mask >> 10) & (mask >> (jj + 5)) & 1) ? (mask & 31) : 0;
+        // row jj of slab r / 5 = qi (r = 5 qi + jj): a site is inside the
+        // cube when its slab, its lateral j (bit 5 + jj) and its i (bit i) are
+        auto accum = [&](int r, int jj, int mask, const float* Rv) __attribute__((always_inline)) {
+            const bool row_in = (mask >> 10) & (mask >> (jj + 5)) & 1;
             const int64_t p = tile0 + pt;
 #pragma unroll
             for (int i = 0; i < 5; i++) {
-                const float rv = (m5 >> i) & 1 ? Rv[i] : 0.f;
+                const float rv = row_in && ((mask >> i) & 1) ? Rv[i] : 0.f;
                 rs += rv;
                 rmx = fmaxf(rmx, rv);
                 if (DBG && p < npts) A.dbg_rho[(p * kLayers + k) * kSites + r * 5 + i] = rv;
@@ -618,7 +618,7 @@ k_features(FeatArgs A)
         if (nm == 1) {
             const float r0 = ldR(0);
             const float Rv[5] = {r0, r0, r0, r0, r0};
-            for (int r = lrl; r < kRows; r += 16) accum(r, sp[pt][r / 5].mask, Rv);
+            for (int r = lrl; r < kRows; r += 16) accum(r, r % 5, sp[pt][r / 5].mask, Rv);
         } else if (lrl < 9) {
             const int qi = lrl;
             const SlabParams S = sp[pt][qi];
@@ -660,7 +660,7 @@ k_features(FeatArgs A)
                 for (int u = 0; u < 6; u++) bb[u] = lerpf(R[jj][u], R[jj + 1][u], S.wc);
 #pragma unroll
                 for (int i = 0; i < 5; i++) Rv[i] = lerpf(bb[i], bb[i + 1], S.wb);
-                accum(qi * 5 + jj, S.mask, Rv);
+                accum(qi * 5 + jj, jj, S.mask, Rv);
             }
         }
 
