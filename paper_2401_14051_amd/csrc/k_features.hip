@@ -575,21 +575,26 @@ k_features(FeatArgs A)
                 emit(r, Dv);
             }
         } else {
-            // c > 1 only on the single-voxel level (one slice): sites are c apart
+            // c > 1 only on the single-voxel level (one slice, so no
+            // interpolation along J): sites are c apart; the U samples of a
+            // site are the same in every row
             const float* sl = &brick[0][0];   // the whole slice, staged above
+            int u0[5], u1[5];
+#pragma unroll
+            for (int i = 0; i < 5; i++) {
+                u0[i] = clampi(P.iu + c * (i - 2) - lv.ulo, 0, lv.nu - 1);
+                u1[i] = clampi(P.iu + c * (i - 2) + 1 - lv.ulo, 0, lv.nu - 1);
+            }
             for (int r = lrl; r < kRows; r += 16) {
                 const int j = r % 5 - 2;
-                const int v0 = clampi(P.iv + c * j - lv.vlo, 0, lv.nv - 1) * lv.nu;
-                const int v1 = clampi(P.iv + c * j + 1 - lv.vlo, 0, lv.nv - 1) * lv.nu;
+                const float* s0 = sl + clampi(P.iv + c * j - lv.vlo, 0, lv.nv - 1) * lv.nu;
+                const float* s1 = sl + clampi(P.iv + c * j + 1 - lv.vlo, 0, lv.nv - 1) * lv.nu;
                 float Dv[5];
 #pragma unroll
                 for (int i = 0; i < 5; i++) {
-                    const int u0 = clampi(P.iu + c * (i - 2) - lv.ulo, 0, lv.nu - 1);
-                    const int u1 = clampi(P.iu + c * (i - 2) + 1 - lv.ulo, 0, lv.nu - 1);
-                    const float e0 = lerpf(sl[v0 + u0], sl[v0 + u1], P.wu);
-                    const float e1 = lerpf(sl[v1 + u0], sl[v1 + u1], P.wu);
-                    const float dd = lerpf(e0, e1, P.wv);
-                    Dv[i] = lerpf(dd, dd, P.wj);
+                    const float e0 = lerpf(s0[u0[i]], s0[u1[i]], P.wu);
+                    const float e1 = lerpf(s1[u0[i]], s1[u1[i]], P.wu);
+                    Dv[i] = lerpf(e0, e1, P.wv);
                 }
                 emit(r, Dv);
             }

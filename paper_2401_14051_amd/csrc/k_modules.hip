@@ -50,7 +50,8 @@ template <int I, int N, class F> __device__ __forceinline__ void static_loop(F&&
 
 constexpr int kMerge = 64;                 // width of a type's merge
 constexpr int kCat = 48 + 8;               // last diffuse layer + last highlight layer
-constexpr int kModPts = 32;                // points per wave
+constexpr int kNT = 2;                     // groups of 32 points per wave (the MFMAs' N tiles)
+constexpr int kModPts = 32 * kNT;          // points per wave
 constexpr int kModWaves = 4;
 
 // ---- layout of a per-point vector over the accumulator registers -----------
@@ -124,64 +125,70 @@ __device__ __forceinline__ f32x16 mma(float a, float b, f32x16 c)
 
 __device__ __forceinline__ float sigmoidf_(float x) { return __builtin_amdgcn_rcpf(1.f + __expf(-x)); }
 
-// One step from layer K: h (tiles of n_K rows) -> h (tiles of n_{K+1} rows).
-// row: the lane's point's feature row; wp: the step's packed weights.
+// One step from layer K for the wave's kNT groups of 32 points: h (tiles of
+// n_K rows) -> h (tiles of n_{K+1} rows).  row[tn]: the lane's point's
+// feature row in group tn; wp: the step's packed weights.  Every A fragment
+// read from LDS feeds one MFMA per group.
 template <int K>
-__device__ __forceinline__ void mod_step(const float* __restrict__& wp, const float* __restrict__ row, int tau,
-                                         float g, float alpha, int lane, f32x16 (&h)[2])
+__device__ __forceinline__ void mod_step(const float* __restrict__& wp, const float* const (&row)[kNT], int tau,
+                                         const float (&g)[kNT], const float (&alpha)[kNT], int lane,
+                                         f32x16 (&h)[2][kNT])
 {
     constexpr int n = tpl_count(K), a = n + 2, b = tpl_count(K + 1);
     constexpr int TA = mtiles(a), TB = mtiles(b);
     const int hh = lane >> 5;
-    // excitation of the layer's squeeze vector (eq. 25)
-    const float* v = row + feat_base(K) + 3 * n;
-    float z0 = wp[16], z1 = wp[17];
+    // u = [h; g; alpha] (rows n and n + 1, zero so far, take g and alpha),
+    // gated by the excitation of the layer's squeeze vector (eq. 25, 26):
+    // logits S2 z + e2 in the same layout, then a = sigmoid * u
+    f32x16 u[TA][kNT];
 #pragma unroll
-    for (int i = 0; i < 8; i++) {
-        const float vi = v[i];
-        z0 += wp[i] * vi;
-        z1 += wp[8 + i] * vi;
-    }
-    z0 = fmaxf(z0, 0.f);
-    z1 = fmaxf(z1, 0.f);
-    wp += kHdr;
-    // u = [h; g; alpha]: rows n and n + 1 (zero so far) take g and alpha
-    f32x16 u[TA];
+    for (int tn = 0; tn < kNT; tn++) {
+        const float* v = row[tn] + feat_base(K) + 3 * n;
+        float z0 = wp[16], z1 = wp[17];
 #pragma unroll
-    for (int t = 0; t < TA; t++) u[t] = t < mtiles(n) ? h[t < 2 ? t : 0] : f32x16{};
-    {
+        for (int i = 0; i < 8; i++) {
+            const float vi = v[i];
+            z0 += wp[i] * vi;
+            z1 += wp[8 + i] * vi;
+        }
+        z0 = fmaxf(z0, 0.f);
+        z1 = fmaxf(z1, 0.f);
+#pragma unroll
+        for (int t = 0; t < TA; t++) u[t][tn] = t < mtiles(n) ? h[t < 2 ? t : 0][tn] : f32x16{};
         constexpr int tg = n / 32, rg = 4 * ((n % 32) / 8) + n % 4, hg = (n % 8) / 4;
         constexpr int ta = (n + 1) / 32, ra = 4 * (((n + 1) % 32) / 8) + (n + 1) % 4, ha = ((n + 1) % 8) / 4;
-        if (hh == hg) u[tg][rg] = g;
-        if (hh == ha) u[ta][ra] = alpha;
-    }
-    // gate (eq. 26): logits S2 z + e2 in the same layout, then a = sigmoid * u
-    const float bz0 = hh ? z1 : z0, bz1 = hh ? 0.f : 1.f;
+        if (hh == hg) u[tg][tn][rg] = g[tn];
+        if (hh == ha) u[ta][tn][ra] = alpha[tn];
+        const float bz0 = hh ? z1 : z0, bz1 = hh ? 0.f : 1.f;
 #pragma unroll
-    for (int t = 0; t < TA; t++) {
-        f32x16 gl = mma(wp[t * 128 + lane], bz0, f32x16{});
-        gl = mma(wp[t * 128 + 64 + lane], bz1, gl);
+        for (int t = 0; t < TA; t++) {
+            f32x16 gl = mma(wp[kHdr + t * 128 + lane], bz0, f32x16{});
+            gl = mma(wp[kHdr + t * 128 + 64 + lane], bz1, gl);
 #pragma unroll
-        for (int r = 0; r < muse(t, a); r++) u[t][r] *= sigmoidf_(gl[r]);
-    }
-    wp += TA * 128;
-    // FC-1, fused with the next layer's features: y = x + F1 a + f1
-    const float* xr = row + feat_base(K + 1) + tau * b;
-    f32x16 x[TB], y[TB];
-#pragma unroll
-    for (int mt = 0; mt < TB; mt++) {
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const int r0 = 32 * mt + 8 * q + 4 * hh;   // rows r0 .. r0 + 3 (in the row: always readable)
-            const float2 lo = *reinterpret_cast<const float2*>(xr + r0);
-            const float2 hi = *reinterpret_cast<const float2*>(xr + r0 + 2);
-            const float e[4] = {lo.x, lo.y, hi.x, hi.y};
-#pragma unroll
-            for (int i = 0; i < 4; i++) x[mt][4 * q + i] = r0 + i < b ? e[i] : 0.f;
+            for (int r = 0; r < muse(t, a); r++) u[t][tn][r] *= sigmoidf_(gl[r]);
         }
-        const float* b1 = wp + mt * 32 + hh * 16;
+    }
+    wp += kHdr + TA * 128;
+    // FC-1, fused with the next layer's features: y = x + F1 a + f1
+    f32x16 x[TB][kNT], y[TB][kNT];
 #pragma unroll
-        for (int r = 0; r < 16; r++) y[mt][r] = x[mt][r] + b1[r];
+    for (int tn = 0; tn < kNT; tn++) {
+        const float* xr = row[tn] + feat_base(K + 1) + tau * b;
+#pragma unroll
+        for (int mt = 0; mt < TB; mt++) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int r0 = 32 * mt + 8 * q + 4 * hh;   // rows r0 .. r0 + 3 (in the row: always readable)
+                const float2 lo = *reinterpret_cast<const float2*>(xr + r0);
+                const float2 hi = *reinterpret_cast<const float2*>(xr + r0 + 2);
+                const float e[4] = {lo.x, lo.y, hi.x, hi.y};
+#pragma unroll
+                for (int i = 0; i < 4; i++) x[mt][tn][4 * q + i] = r0 + i < b ? e[i] : 0.f;
+            }
+            const float* b1 = wp + mt * 32 + hh * 16;
+#pragma unroll
+            for (int r = 0; r < 16; r++) y[mt][tn][r] = x[mt][tn][r] + b1[r];
+        }
     }
     wp += TB * 32;
 #pragma unroll
@@ -190,17 +197,24 @@ __device__ __forceinline__ void mod_step(const float* __restrict__& wp, const fl
 #pragma unroll
         for (int t = 0; t < TA; t++)
 #pragma unroll
-            for (int r = 0; r < muse(t, a); r++, s++)
-                y[mt] = mma(wp[(mt * mksteps(a) + s) * 64 + lane], u[t][r], y[mt]);
+            for (int r = 0; r < muse(t, a); r++, s++) {
+                const float w = wp[(mt * mksteps(a) + s) * 64 + lane];
+#pragma unroll
+                for (int tn = 0; tn < kNT; tn++) y[mt][tn] = mma(w, u[t][tn][r], y[mt][tn]);
+            }
     }
     wp += TB * mksteps(a) * 64;
     // FC-2, fused again: h = ReLU(F2 y + f2) + x
-    f32x16 acc[TB];
+    f32x16 acc[TB][kNT];
 #pragma unroll
     for (int mt = 0; mt < TB; mt++) {
         const float* b2 = wp + mt * 32 + hh * 16;
 #pragma unroll
-        for (int r = 0; r < 16; r++) acc[mt][r] = b2[r];
+        for (int r = 0; r < 16; r++) {
+            const float bv = b2[r];
+#pragma unroll
+            for (int tn = 0; tn < kNT; tn++) acc[mt][tn][r] = bv;
+        }
     }
     wp += TB * 32;
 #pragma unroll
@@ -209,38 +223,48 @@ __device__ __forceinline__ void mod_step(const float* __restrict__& wp, const fl
 #pragma unroll
         for (int t = 0; t < TB; t++)
 #pragma unroll
-            for (int r = 0; r < muse(t, b); r++, s++)
-                acc[mt] = mma(wp[(mt * mksteps(b) + s) * 64 + lane], y[t][r], acc[mt]);
+            for (int r = 0; r < muse(t, b); r++, s++) {
+                const float w = wp[(mt * mksteps(b) + s) * 64 + lane];
+#pragma unroll
+                for (int tn = 0; tn < kNT; tn++) acc[mt][tn] = mma(w, y[t][tn][r], acc[mt][tn]);
+            }
     }
     wp += TB * mksteps(b) * 64;
 #pragma unroll
-    for (int mt = 0; mt < 2; mt++) {
-        if (mt < TB) {
+    for (int mt = 0; mt < 2; mt++)
 #pragma unroll
-            for (int r = 0; r < 16; r++) h[mt][r] = fmaxf(acc[mt < TB ? mt : 0][r], 0.f) + x[mt < TB ? mt : 0][r];
-        } else {
-            h[mt] = f32x16{};
+        for (int tn = 0; tn < kNT; tn++) {
+            if (mt < TB) {
+#pragma unroll
+                for (int r = 0; r < 16; r++)
+                    h[mt][tn][r] = fmaxf(acc[mt < TB ? mt : 0][tn][r], 0.f) + x[mt < TB ? mt : 0][tn][r];
+            } else {
+                h[mt][tn] = f32x16{};
+            }
         }
-    }
 }
 
 // A module of group G over its layers: h enters as the group's first layer's
 // features of type tau and leaves as its final state.
 template <int G>
-__device__ __forceinline__ void run_module(const float* __restrict__& wp, const float* __restrict__ row, int tau,
-                                           float g, float alpha, int lane, f32x16 (&h)[2])
+__device__ __forceinline__ void run_module(const float* __restrict__& wp, const float* const (&row)[kNT], int tau,
+                                           const float (&g)[kNT], const float (&alpha)[kNT], int lane,
+                                           f32x16 (&h)[2][kNT])
 {
     constexpr int k0 = G ? kDiffuse : 0, k1 = G ? kLayers - 1 : kDiffuse - 1;
     constexpr int n0 = tpl_count(k0);
     const int hh = lane >> 5;
-    const float* x0 = row + feat_base(k0) + tau * n0;
-    h[0] = f32x16{};
-    h[1] = f32x16{};
 #pragma unroll
-    for (int r = 0; r < 16; r++) {
-        const int rr = mrow(0, r, hh);
-        const float e = x0[rr < n0 ? rr : 0];
-        h[0][r] = rr < n0 ? e : 0.f;
+    for (int tn = 0; tn < kNT; tn++) {
+        const float* x0 = row[tn] + feat_base(k0) + tau * n0;
+        h[0][tn] = f32x16{};
+        h[1][tn] = f32x16{};
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int rr = mrow(0, r, hh);
+            const float e = x0[rr < n0 ? rr : 0];
+            h[0][tn][r] = rr < n0 ? e : 0.f;
+        }
     }
     static_loop<k0, k1>([&](auto kc) __attribute__((always_inline)) {
         mod_step<decltype(kc)::value>(wp, row, tau, g, alpha, lane, h);
@@ -260,28 +284,36 @@ k_modules(const float* __restrict__ feat, const float* __restrict__ wm, int64_t 
     // the last point computes on that point and writes nothing
     if ((int64_t)blockIdx.x * kModWaves * kModPts >= nv) return;
     const int64_t p0 = ((int64_t)blockIdx.x * kModWaves + wave) * kModPts;
-    const int64_t p = p0 + (lane & 31);
-    const bool live = p < nv;
-    const float* row = feat + (live ? p : nv - 1) * kDescPad;
-    const float g = row[3 * tpl_count(0) + 6], alpha = row[3 * tpl_count(0) + 7];
+    int64_t p[kNT];
+    bool live[kNT];
+    const float* row[kNT];
+    float g[kNT], alpha[kNT];
+#pragma unroll
+    for (int tn = 0; tn < kNT; tn++) {
+        p[tn] = p0 + 32 * tn + (lane & 31);
+        live[tn] = p[tn] < nv;
+        row[tn] = feat + (live[tn] ? p[tn] : nv - 1) * kDescPad;
+        g[tn] = row[tn][3 * tpl_count(0) + 6];
+        alpha[tn] = row[tn][3 * tpl_count(0) + 7];
+    }
     const int rowlen = F8 ? kDescF8 : kDescPad;
-    // four consecutive descriptor entries e .. e + 3 of the lane's point
-    auto put4 = [&](int e, float v0, float v1, float v2, float v3) __attribute__((always_inline)) {
-        if (!live) return;
+    // four consecutive entries e .. e + 3 of descriptor row pp
+    auto put4 = [&](int64_t pp, int e, const float (&v)[4]) __attribute__((always_inline)) {
         if constexpr (F8) {
             const float s = desc_inv_scale;
             auto q = [&](float x) { return __builtin_amdgcn_fmed3f(x * s, -448.f, 448.f); };
-            int w = __builtin_amdgcn_cvt_pk_fp8_f32(q(v0), q(v1), 0, false);
-            w = __builtin_amdgcn_cvt_pk_fp8_f32(q(v2), q(v3), w, true);
-            *reinterpret_cast<int*>(reinterpret_cast<uint8_t*>(desc) + p * kDescF8 + e) = w;
+            int w = __builtin_amdgcn_cvt_pk_fp8_f32(q(v[0]), q(v[1]), 0, false);
+            w = __builtin_amdgcn_cvt_pk_fp8_f32(q(v[2]), q(v[3]), w, true);
+            *reinterpret_cast<int*>(reinterpret_cast<uint8_t*>(desc) + pp * kDescF8 + e) = w;
         } else if constexpr (PREC == kPrecBF16) {
             typedef float f32x2 __attribute__((ext_vector_type(2)));
             typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
-            const uint32_t a = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{v0, v1}, bf16x2v));
-            const uint32_t c = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{v2, v3}, bf16x2v));
-            *reinterpret_cast<uint2*>(reinterpret_cast<E*>(desc) + p * kDescPad + e) = make_uint2(a, c);
+            const uint32_t a = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{v[0], v[1]}, bf16x2v));
+            const uint32_t c = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{v[2], v[3]}, bf16x2v));
+            *reinterpret_cast<uint2*>(reinterpret_cast<E*>(desc) + pp * kDescPad + e) = make_uint2(a, c);
         } else {
-            *reinterpret_cast<float4*>(reinterpret_cast<float*>(desc) + p * kDescPad + e) = make_float4(v0, v1, v2, v3);
+            *reinterpret_cast<float4*>(reinterpret_cast<float*>(desc) + pp * kDescPad + e) =
+                make_float4(v[0], v[1], v[2], v[3]);
         }
     };
 #pragma unroll 1
@@ -297,16 +329,20 @@ k_modules(const float* __restrict__ feat, const float* __restrict__ wm, int64_t 
         }
         __syncthreads();
         const float* wp = wl;
-        f32x16 hd[2], hl[2];
+        f32x16 hd[2][kNT], hl[2][kNT];
         run_module<0>(wp, row, tau, g, alpha, lane, hd);
         run_module<1>(wp, row, tau, g, alpha, lane, hl);
         // the type's merge of its two groups
-        f32x16 acc[2];
+        f32x16 acc[2][kNT];
 #pragma unroll
         for (int mt = 0; mt < 2; mt++) {
             const float* bm = wp + mt * 32 + hh * 16;
 #pragma unroll
-            for (int r = 0; r < 16; r++) acc[mt][r] = bm[r];
+            for (int r = 0; r < 16; r++) {
+                const float bv = bm[r];
+#pragma unroll
+                for (int tn = 0; tn < kNT; tn++) acc[mt][tn][r] = bv;
+            }
         }
         wp += 64;
 #pragma unroll
@@ -315,24 +351,44 @@ k_modules(const float* __restrict__ feat, const float* __restrict__ wm, int64_t 
 #pragma unroll
             for (int t = 0; t < 2; t++)
 #pragma unroll
-                for (int r = 0; r < muse(t, 48); r++, s++) acc[mt] = mma(wp[(mt * kMergeK + s) * 64 + lane], hd[t][r], acc[mt]);
+                for (int r = 0; r < muse(t, 48); r++, s++) {
+                    const float w = wp[(mt * kMergeK + s) * 64 + lane];
 #pragma unroll
-            for (int r = 0; r < muse(0, 8); r++, s++) acc[mt] = mma(wp[(mt * kMergeK + s) * 64 + lane], hl[0][r], acc[mt]);
+                    for (int tn = 0; tn < kNT; tn++) acc[mt][tn] = mma(w, hd[t][tn][r], acc[mt][tn]);
+                }
+#pragma unroll
+            for (int r = 0; r < muse(0, 8); r++, s++) {
+                const float w = wp[(mt * kMergeK + s) * 64 + lane];
+#pragma unroll
+                for (int tn = 0; tn < kNT; tn++) acc[mt][tn] = mma(w, hl[0][tn][r], acc[mt][tn]);
+            }
         }
-        wp += 2 * kMergeK * 64;
 #pragma unroll
-        for (int mt = 0; mt < 2; mt++)
+        for (int tn = 0; tn < kNT; tn++)
+            if (live[tn]) {
 #pragma unroll
-            for (int q = 0; q < 4; q++)
-                put4(tau * kMerge + mrow(mt, 4 * q, hh), fmaxf(acc[mt][4 * q], 0.f), fmaxf(acc[mt][4 * q + 1], 0.f),
-                     fmaxf(acc[mt][4 * q + 2], 0.f), fmaxf(acc[mt][4 * q + 3], 0.f));
+                for (int mt = 0; mt < 2; mt++)
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const float v[4] = {fmaxf(acc[mt][tn][4 * q], 0.f), fmaxf(acc[mt][tn][4 * q + 1], 0.f),
+                                            fmaxf(acc[mt][tn][4 * q + 2], 0.f), fmaxf(acc[mt][tn][4 * q + 3], 0.f)};
+                        put4(p[tn], tau * kMerge + mrow(mt, 4 * q, hh), v);
+                    }
+            }
     }
     // then g, alpha, zeros up to the albedo entry at 1056, and zero padding:
     // the wave writes the tails of its points one row after another, four
     // entries per lane
     const int64_t pend = max(min(p0 + kModPts, nv), p0);
     for (int64_t pp = p0; pp < pend; pp++) {
-        const float gp = __shfl(g, (int)(pp - p0)), ap = __shfl(alpha, (int)(pp - p0));
+        const int src = (int)((pp - p0) & 31), grp = (int)((pp - p0) >> 5);
+        float gp = __shfl(g[0], src), ap = __shfl(alpha[0], src);
+#pragma unroll
+        for (int tn = 1; tn < kNT; tn++) {
+            const float gt = __shfl(g[tn], src), at = __shfl(alpha[tn], src);
+            gp = grp == tn ? gt : gp;
+            ap = grp == tn ? at : ap;
+        }
         for (int e = 3 * kMerge + 4 * lane; e < rowlen; e += 256) {
             float v[4];
 #pragma unroll
@@ -340,22 +396,7 @@ k_modules(const float* __restrict__ feat, const float* __restrict__ wm, int64_t 
                 const int ei = e + i;
                 v[i] = ei == 3 * kMerge ? gp : ei == 3 * kMerge + 1 ? ap : ei == kDesc - 1 ? albedo : 0.f;
             }
-            if constexpr (F8) {
-                const float s = desc_inv_scale;
-                auto q = [&](float x) { return __builtin_amdgcn_fmed3f(x * s, -448.f, 448.f); };
-                int w = __builtin_amdgcn_cvt_pk_fp8_f32(q(v[0]), q(v[1]), 0, false);
-                w = __builtin_amdgcn_cvt_pk_fp8_f32(q(v[2]), q(v[3]), w, true);
-                *reinterpret_cast<int*>(reinterpret_cast<uint8_t*>(desc) + pp * kDescF8 + e) = w;
-            } else if constexpr (PREC == kPrecBF16) {
-                typedef float f32x2 __attribute__((ext_vector_type(2)));
-                typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
-                const uint32_t a = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{v[0], v[1]}, bf16x2v));
-                const uint32_t c = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{v[2], v[3]}, bf16x2v));
-                *reinterpret_cast<uint2*>(reinterpret_cast<E*>(desc) + pp * kDescPad + e) = make_uint2(a, c);
-            } else {
-                *reinterpret_cast<float4*>(reinterpret_cast<float*>(desc) + pp * kDescPad + e) =
-                    make_float4(v[0], v[1], v[2], v[3]);
-            }
+            put4(pp, e, v);
         }
     }
 }
