@@ -966,6 +966,24 @@ constexpr TplDescMap make_tpl_desc_map()
     return m;
 }
 __constant__ TplDescMap kTplMap = make_tpl_desc_map();
+
+// The same for the backbone modules' feature rows (0xffff: padding, zero).
+struct TplModMap {
+    uint16_t src[kModFeat];
+};
+constexpr TplModMap make_tpl_mod_map()
+{
+    TplModMap m{};
+    for (int f = 0; f < kModFeat; f++) m.src[f] = 0xffff;
+    for (int k = 0; k < kLayers; k++) {
+        const int n = tpl_count(k), f = tpl_first(k);
+        for (int ty = 0; ty < 3; ty++)
+            for (int j = 0; j < n; j++) m.src[mf_block(ty, k) + j] = (uint16_t)(ty * kTplSites + f + j);
+        for (int i = 0; i < kStats; i++) m.src[mf_stats(k) + i] = (uint16_t)(3 * kTplSites + k * kStats + i);
+    }
+    return m;
+}
+__constant__ TplModMap kTplModMap = make_tpl_mod_map();
 constexpr int kTplStage = 3 * kTplSites + kLayers * kStats;
 
 template <int PREC, bool DBG, bool F8>
@@ -1110,7 +1128,15 @@ k_template_features(TplArgs A)
     __syncthreads();
     if (!live) return;
     // the descriptor row: per layer tbar, rho, phi (template order), squeeze vector
-    const int rowlen = F8 ? kDescF8 : A.feat_only ? kTplFeat : kDescPad;
+    if (A.feat_only) {
+        // the backbone modules' feature row (FP32)
+        for (int e = lane; e < kModFeat; e += 64) {
+            const int src = kTplModMap.src[e];
+            reinterpret_cast<float*>(A.desc)[p * kDescPad + e] = src == 0xffff ? 0.f : vals[src];
+        }
+        return;
+    }
+    const int rowlen = F8 ? kDescF8 : kDescPad;
     for (int e = lane; e < rowlen; e += 64) {
         const float v = e < kTplFeat ? vals[kTplMap.src[e]] : e == kDesc - 1 ? mv.albedo : 0.f;
         if constexpr (F8) {

@@ -27,10 +27,16 @@
 // logits in the same layout.  Only the registers holding a row below R take
 // part in the K loop; the rest are zero.
 //
-// A workgroup of 4 waves (128 points) copies one feature type's packed
-// weights (108 KiB) into LDS at a time and reads every A fragment from there,
-// one 4-byte word per lane; the chains would otherwise wait on L2 for each
-// fragment at one wave per SIMD.
+// A workgroup of 8 waves (256 points, two waves per SIMD) copies one feature
+// type's packed weights (108 KiB) into LDS at a time and reads every A
+// fragment from there, one 4-byte word per lane.  Each step issues its reads
+// of the next layer's features and squeeze vector before its MFMAs, and the
+// feature rows are laid out by type (mf_block), so that a module reads one
+// contiguous third of its points' rows with 16-byte loads.  The kernel fits
+// 256 registers, so the second wave of a SIMD covers the first one's
+// dependency stalls (gate, FC-1, FC-2 each wait for the previous result);
+// two groups of 32 points per wave (sharing each A fragment) measured the
+// same at one wave per SIMD, and three waves per SIMD spill.
 #include "launch_args.h"
 #include "mfma.h"
 
@@ -50,9 +56,9 @@ template <int I, int N, class F> __device__ __forceinline__ void static_loop(F&&
 
 constexpr int kMerge = 64;                 // width of a type's merge
 constexpr int kCat = 48 + 8;               // last diffuse layer + last highlight layer
-constexpr int kNT = 2;                     // groups of 32 points per wave (the MFMAs' N tiles)
+constexpr int kNT = 1;                     // groups of 32 points per wave (the MFMAs' N tiles)
 constexpr int kModPts = 32 * kNT;          // points per wave
-constexpr int kModWaves = 4;
+constexpr int kModWaves = 8;
 
 // ---- layout of a per-point vector over the accumulator registers -----------
 
@@ -95,15 +101,6 @@ __host__ __device__ constexpr int pk_type_floats()
     return s;
 }
 
-// offset (in floats) of a layer's block in a feature row: per layer its
-// tbar, rho, phi (n each) and squeeze vector (8)
-__host__ __device__ constexpr int feat_base(int k)
-{
-    int b = 0;
-    for (int i = 0; i < k; i++) b += 3 * tpl_count(i) + kStats;
-    return b;
-}
-
 // floats of one step's weights in the weight blob (from layer k)
 constexpr int raw_step_floats(int k)
 {
@@ -132,24 +129,39 @@ __device__ __forceinline__ float sigmoidf_(float x) { return __builtin_amdgcn_rc
 template <int K>
 __device__ __forceinline__ void mod_step(const float* __restrict__& wp, const float* const (&row)[kNT], int tau,
                                          const float (&g)[kNT], const float (&alpha)[kNT], int lane,
-                                         f32x16 (&h)[2][kNT])
+                                         f32x16 (&h)[2][kNT], float4 (&vsq)[kNT][2])
 {
     constexpr int n = tpl_count(K), a = n + 2, b = tpl_count(K + 1);
     constexpr int TA = mtiles(a), TB = mtiles(b);
     const int hh = lane >> 5;
+    // the step's reads from memory first, so that their latency passes under
+    // the MFMAs: the next layer's features of this type and its squeeze
+    // vector (the next step's)
+    float4 xq[TB][4][kNT], vn[kNT][2];
+#pragma unroll
+    for (int tn = 0; tn < kNT; tn++) {
+        const float* xr = row[tn] + mf_block(0, K + 1) + tau * mf_type_len();
+#pragma unroll
+        for (int mt = 0; mt < TB; mt++)
+#pragma unroll
+            for (int q = 0; q < 4; q++)   // rows 32 mt + 8 q + 4 hh .. + 3 (in the row: always readable)
+                xq[mt][q][tn] = *reinterpret_cast<const float4*>(xr + 32 * mt + 8 * q + 4 * hh);
+        vn[tn][0] = *reinterpret_cast<const float4*>(row[tn] + mf_stats(K + 1));
+        vn[tn][1] = *reinterpret_cast<const float4*>(row[tn] + mf_stats(K + 1) + 4);
+    }
     // u = [h; g; alpha] (rows n and n + 1, zero so far, take g and alpha),
     // gated by the excitation of the layer's squeeze vector (eq. 25, 26):
     // logits S2 z + e2 in the same layout, then a = sigmoid * u
     f32x16 u[TA][kNT];
 #pragma unroll
     for (int tn = 0; tn < kNT; tn++) {
-        const float* v = row[tn] + feat_base(K) + 3 * n;
+        const float v[8] = {vsq[tn][0].x, vsq[tn][0].y, vsq[tn][0].z, vsq[tn][0].w,
+                            vsq[tn][1].x, vsq[tn][1].y, vsq[tn][1].z, vsq[tn][1].w};
         float z0 = wp[16], z1 = wp[17];
 #pragma unroll
         for (int i = 0; i < 8; i++) {
-            const float vi = v[i];
-            z0 += wp[i] * vi;
-            z1 += wp[8 + i] * vi;
+            z0 += wp[i] * v[i];
+            z1 += wp[8 + i] * v[i];
         }
         z0 = fmaxf(z0, 0.f);
         z1 = fmaxf(z1, 0.f);
@@ -169,25 +181,16 @@ __device__ __forceinline__ void mod_step(const float* __restrict__& wp, const fl
         }
     }
     wp += kHdr + TA * 128;
-    // FC-1, fused with the next layer's features: y = x + F1 a + f1
+    // FC-1, fused with the next layer's features: y = x + (F1 a + f1)
     f32x16 x[TB][kNT], y[TB][kNT];
 #pragma unroll
-    for (int tn = 0; tn < kNT; tn++) {
-        const float* xr = row[tn] + feat_base(K + 1) + tau * b;
+    for (int mt = 0; mt < TB; mt++) {
+        const float* b1 = wp + mt * 32 + hh * 16;
 #pragma unroll
-        for (int mt = 0; mt < TB; mt++) {
+        for (int r = 0; r < 16; r++) {
+            const float bv = b1[r];
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const int r0 = 32 * mt + 8 * q + 4 * hh;   // rows r0 .. r0 + 3 (in the row: always readable)
-                const float2 lo = *reinterpret_cast<const float2*>(xr + r0);
-                const float2 hi = *reinterpret_cast<const float2*>(xr + r0 + 2);
-                const float e[4] = {lo.x, lo.y, hi.x, hi.y};
-#pragma unroll
-                for (int i = 0; i < 4; i++) x[mt][tn][4 * q + i] = r0 + i < b ? e[i] : 0.f;
-            }
-            const float* b1 = wp + mt * 32 + hh * 16;
-#pragma unroll
-            for (int r = 0; r < 16; r++) y[mt][tn][r] = x[mt][tn][r] + b1[r];
+            for (int tn = 0; tn < kNT; tn++) y[mt][tn][r] = bv;
         }
     }
     wp += TB * 32;
@@ -204,6 +207,25 @@ __device__ __forceinline__ void mod_step(const float* __restrict__& wp, const fl
             }
     }
     wp += TB * mksteps(a) * 64;
+#pragma unroll
+    for (int mt = 0; mt < TB; mt++)
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+            for (int tn = 0; tn < kNT; tn++) {
+                const int r0 = 32 * mt + 8 * q + 4 * hh;
+                const float e[4] = {xq[mt][q][tn].x, xq[mt][q][tn].y, xq[mt][q][tn].z, xq[mt][q][tn].w};
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    x[mt][tn][4 * q + i] = r0 + i < b ? e[i] : 0.f;
+                    y[mt][tn][4 * q + i] = x[mt][tn][4 * q + i] + y[mt][tn][4 * q + i];
+                }
+            }
+#pragma unroll
+    for (int tn = 0; tn < kNT; tn++) {
+        vsq[tn][0] = vn[tn][0];
+        vsq[tn][1] = vn[tn][1];
+    }
     // FC-2, fused again: h = ReLU(F2 y + f2) + x
     f32x16 acc[TB][kNT];
 #pragma unroll
@@ -256,18 +278,26 @@ __device__ __forceinline__ void run_module(const float* __restrict__& wp, const 
     const int hh = lane >> 5;
 #pragma unroll
     for (int tn = 0; tn < kNT; tn++) {
-        const float* x0 = row[tn] + feat_base(k0) + tau * n0;
+        const float* x0 = row[tn] + mf_block(0, k0) + tau * mf_type_len();
         h[0][tn] = f32x16{};
         h[1][tn] = f32x16{};
 #pragma unroll
-        for (int r = 0; r < 16; r++) {
-            const int rr = mrow(0, r, hh);
-            const float e = x0[rr < n0 ? rr : 0];
-            h[0][tn][r] = rr < n0 ? e : 0.f;
+        for (int q = 0; q < 4; q++) {
+            const int r0 = 8 * q + 4 * hh;
+            const float4 x4 = *reinterpret_cast<const float4*>(x0 + r0);
+            const float e[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+            for (int i = 0; i < 4; i++) h[0][tn][4 * q + i] = r0 + i < n0 ? e[i] : 0.f;
         }
     }
+    float4 vsq[kNT][2];   // the current layer's squeeze vector
+#pragma unroll
+    for (int tn = 0; tn < kNT; tn++) {
+        vsq[tn][0] = *reinterpret_cast<const float4*>(row[tn] + mf_stats(k0));
+        vsq[tn][1] = *reinterpret_cast<const float4*>(row[tn] + mf_stats(k0) + 4);
+    }
     static_loop<k0, k1>([&](auto kc) __attribute__((always_inline)) {
-        mod_step<decltype(kc)::value>(wp, row, tau, g, alpha, lane, h);
+        mod_step<decltype(kc)::value>(wp, row, tau, g, alpha, lane, h, vsq);
     });
 }
 
@@ -293,8 +323,8 @@ k_modules(const float* __restrict__ feat, const float* __restrict__ wm, int64_t 
         p[tn] = p0 + 32 * tn + (lane & 31);
         live[tn] = p[tn] < nv;
         row[tn] = feat + (live[tn] ? p[tn] : nv - 1) * kDescPad;
-        g[tn] = row[tn][3 * tpl_count(0) + 6];
-        alpha[tn] = row[tn][3 * tpl_count(0) + 7];
+        g[tn] = row[tn][mf_stats(0) + 6];
+        alpha[tn] = row[tn][mf_stats(0) + 7];
     }
     const int rowlen = F8 ? kDescF8 : kDescPad;
     // four consecutive entries e .. e + 3 of descriptor row pp

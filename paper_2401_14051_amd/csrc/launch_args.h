@@ -43,7 +43,7 @@ struct TplArgs {
     double dh[kLayers - kDiffuse];   // highlight layers' eq. (3) measure of the unit cone sets
     void* desc;                  // [npts][kDescPad] (FP8 output: [npts][kDescF8] E4M3 codes)
     float desc_inv_scale;        // FP8 output only: 1 / the backbone's first input scale
-    int feat_only;               // write entries 0 .. kTplFeat-1 only (the backbone modules' input)
+    int feat_only;               // FP32 rows in the backbone modules' layout (mf_block, mf_stats) instead
     float* f0;                   // [npts] f(w.l) T(p)
     float* dbg_tbar;             // optional [npts][kTplSites]
     float* dbg_rho;              // optional [npts][kTplSites]

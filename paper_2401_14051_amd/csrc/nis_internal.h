@@ -95,6 +95,27 @@ __host__ __device__ constexpr int tpl_first(int k)
     return f;
 }
 
+// The feature rows the paper's backbone modules read, written by the
+// template gather: per feature type (graded transmittance, density, phase)
+// the layers' values, each layer's block padded to a multiple of 4 floats
+// (16-byte loads), then the 12 squeeze vectors.  A module of one type reads
+// one contiguous third of the row.
+__host__ __device__ constexpr int mf_pad4(int n) { return (n + 3) / 4 * 4; }
+__host__ __device__ constexpr int mf_type_len()
+{
+    int s = 0;
+    for (int k = 0; k < kLayers; k++) s += mf_pad4(tpl_count(k));
+    return s;
+}
+__host__ __device__ constexpr int mf_block(int tau, int k)
+{
+    int s = tau * mf_type_len();
+    for (int i = 0; i < k; i++) s += mf_pad4(tpl_count(i));
+    return s;
+}
+__host__ __device__ constexpr int mf_stats(int k) { return 3 * mf_type_len() + kStats * k; }
+constexpr int kModFeat = 3 * mf_type_len() + kLayers * kStats;   // 900 floats
+
 // Per-light template tables: each point's offset (diffuse layers: the unit
 // template point, scaled per layer by its radius; highlight layers: the unit
 // cone point in world axes, scaled per query point by its light extent) and
