@@ -926,26 +926,23 @@ __device__ __forceinline__ double tpl_coord(double x, double scale, double o)
     return x + scale * o;
 }
 
-// density of level lv at s: zero outside the closed unit cube, else index-clamped trilinear
+// density of level lv at s: zero outside the closed unit cube, else
+// index-clamped trilinear, from the light-axis density pairs (four 8-byte
+// loads: rows c, c+1 by samples b, b+1, each holding a and a+1)
 __device__ __forceinline__ float tpl_rho(const MediumView& mv, const Level& lv, const double s[3])
 {
     if (s[0] < 0.0 || s[0] > 1.0 || s[1] < 0.0 || s[1] > 1.0 || s[2] < 0.0 || s[2] > 1.0) return 0.f;
-    const int nm = lv.n;
-    const float* R = mv.rho + lv.rho_off;
-    int i0[3], i1[3];
-    float w[3];
-    for (int d = 0; d < 3; d++) {
-        const double g = s[d] * nm - 0.5, f = floor(g);
-        i0[d] = clampi((int)f, 0, nm - 1);
-        i1[d] = clampi((int)f + 1, 0, nm - 1);
-        w[d] = (float)(g - f);
-    }
-    auto at = [&](int x, int y, int z) { return R[((int64_t)z * nm + y) * nm + x]; };
-    const float c00 = lerpf(at(i0[0], i0[1], i0[2]), at(i1[0], i0[1], i0[2]), w[0]);
-    const float c10 = lerpf(at(i0[0], i1[1], i0[2]), at(i1[0], i1[1], i0[2]), w[0]);
-    const float c01 = lerpf(at(i0[0], i0[1], i1[2]), at(i1[0], i0[1], i1[2]), w[0]);
-    const float c11 = lerpf(at(i0[0], i1[1], i1[2]), at(i1[0], i1[1], i1[2]), w[0]);
-    return lerpf(lerpf(c00, c10, w[1]), lerpf(c01, c11, w[1]), w[2]);
+    const int nm = lv.n, nb = nm + 2 * kPairPad;
+    const double ga = s[mv.a] * nm - 0.5, gb = s[mv.b] * nm - 0.5, gc = s[mv.c] * nm - 0.5;
+    const double fa = floor(ga), fb = floor(gb), fc = floor(gc);
+    const float wa = (float)(ga - fa), wb = (float)(gb - fb), wc = (float)(gc - fc);
+    const int ia = (int)fa, ib = (int)fb, ic = (int)fc;
+    const float2* P = mv.pairs + lv.p_off + (int64_t)clampi(ia + 1, 0, nm) * nm * nb + kPairPad;
+    auto pr = [&](int c, int b) { return P[(int64_t)clampi(c, 0, nm - 1) * nb + clampi(b, 0, nm - 1)]; };
+    const float2 p00 = pr(ic, ib), p01 = pr(ic, ib + 1), p10 = pr(ic + 1, ib), p11 = pr(ic + 1, ib + 1);
+    const float r00 = lerpf(p00.x, p00.y, wa), r01 = lerpf(p01.x, p01.y, wa);
+    const float r10 = lerpf(p10.x, p10.y, wa), r11 = lerpf(p11.x, p11.y, wa);
+    return lerpf(lerpf(r00, r01, wb), lerpf(r10, r11, wb), wc);
 }
 
 // Where each descriptor entry below kTplFeat comes from in a wave's staged
