@@ -117,6 +117,7 @@ __device__ __forceinline__ double hg64(const MediumView& mv, double mu)
 
 __device__ __forceinline__ float lerpf(float a, float b, float w) { return a + w * (b - a); }
 
+
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
 // The value unchanged, but opaque to the optimiser: per-lane index arithmetic
@@ -152,6 +153,30 @@ __device__ __forceinline__ float sample_D(const float2* __restrict__ Q, const Le
     const float2* q0 = Q + j0 * qplane + (int64_t)vp * lv.nu;
     const float2* q1 = Q + j1 * qplane + (int64_t)vp * lv.nu;
     const float2 p00 = q0[u0], p10 = q0[u1], p01 = q1[u0], p11 = q1[u1];
+    float a00 = lerpf(p00.x, p10.x, wu);
+    float a01 = lerpf(p00.y, p10.y, wu);
+    float a10 = lerpf(p01.x, p11.x, wu);
+    float a11 = lerpf(p01.y, p11.y, wu);
+    return lerpf(lerpf(a00, a01, wv), lerpf(a10, a11, wv), wj);
+}
+
+// As sample_D, with the pairs at U and U + 1 of each slice read as one
+// 16-byte load (from U clamped to n_U - 2, the two members picked to match
+// the index clamping).
+__device__ __forceinline__ float sample_D2(const float2* __restrict__ Q, const Level& lv, int U, int V, int J,
+                                           float wu, float wv, float wj)
+{
+    const int u0 = clampi(U - lv.ulo, 0, lv.nu - 1), u1 = clampi(U + 1 - lv.ulo, 0, lv.nu - 1);
+    const int ub = min(u0, lv.nu - 2);
+    const int vp = clampi(V + 1 - lv.vlo, 0, lv.nv);
+    const int j0 = clampi(J, 0, lv.n - 1), j1 = clampi(J + 1, 0, lv.n - 1);
+    const int64_t qplane = (int64_t)lv.nu * (lv.nv + 1);
+    const float4 a = *reinterpret_cast<const float4*>(Q + j0 * qplane + (int64_t)vp * lv.nu + ub);
+    const float4 b = *reinterpret_cast<const float4*>(Q + j1 * qplane + (int64_t)vp * lv.nu + ub);
+    const float2 p00 = u0 == ub ? make_float2(a.x, a.y) : make_float2(a.z, a.w);
+    const float2 p10 = u1 == ub ? make_float2(a.x, a.y) : make_float2(a.z, a.w);
+    const float2 p01 = u0 == ub ? make_float2(b.x, b.y) : make_float2(b.z, b.w);
+    const float2 p11 = u1 == ub ? make_float2(b.x, b.y) : make_float2(b.z, b.w);
     float a00 = lerpf(p00.x, p10.x, wu);
     float a01 = lerpf(p00.y, p10.y, wu);
     float a10 = lerpf(p01.x, p11.x, wu);
@@ -927,8 +952,10 @@ __device__ __forceinline__ double tpl_coord(double x, double scale, double o)
 }
 
 // density of level lv at s: zero outside the closed unit cube, else
-// index-clamped trilinear, from the light-axis density pairs (four 8-byte
-// loads: rows c, c+1 by samples b, b+1, each holding a and a+1)
+// index-clamped trilinear, from the light-axis density pairs: rows c and
+// c + 1, each one 16-byte load of the pairs at b and b + 1 (each pair holds
+// a and a + 1).  An in-cube site has -1 <= b <= n - 1, inside the stored
+// row's padding of index-clamped copies.
 __device__ __forceinline__ float tpl_rho(const MediumView& mv, const Level& lv, const double s[3])
 {
     if (s[0] < 0.0 || s[0] > 1.0 || s[1] < 0.0 || s[1] > 1.0 || s[2] < 0.0 || s[2] > 1.0) return 0.f;
@@ -936,10 +963,12 @@ __device__ __forceinline__ float tpl_rho(const MediumView& mv, const Level& lv, 
     const double ga = s[mv.a] * nm - 0.5, gb = s[mv.b] * nm - 0.5, gc = s[mv.c] * nm - 0.5;
     const double fa = floor(ga), fb = floor(gb), fc = floor(gc);
     const float wa = (float)(ga - fa), wb = (float)(gb - fb), wc = (float)(gc - fc);
-    const int ia = (int)fa, ib = (int)fb, ic = (int)fc;
-    const float2* P = mv.pairs + lv.p_off + (int64_t)clampi(ia + 1, 0, nm) * nm * nb + kPairPad;
-    auto pr = [&](int c, int b) { return P[(int64_t)clampi(c, 0, nm - 1) * nb + clampi(b, 0, nm - 1)]; };
-    const float2 p00 = pr(ic, ib), p01 = pr(ic, ib + 1), p10 = pr(ic + 1, ib), p11 = pr(ic + 1, ib + 1);
+    const int ia = (int)fa, ib = clampi((int)fb, -1, nm - 1), ic = (int)fc;
+    const float2* P = mv.pairs + lv.p_off + (int64_t)clampi(ia + 1, 0, nm) * nm * nb + kPairPad + ib;
+    const float4 q0 = *reinterpret_cast<const float4*>(P + (int64_t)clampi(ic, 0, nm - 1) * nb);
+    const float4 q1 = *reinterpret_cast<const float4*>(P + (int64_t)clampi(ic + 1, 0, nm - 1) * nb);
+    const float2 p00 = make_float2(q0.x, q0.y), p01 = make_float2(q0.z, q0.w);
+    const float2 p10 = make_float2(q1.x, q1.y), p11 = make_float2(q1.z, q1.w);
     const float r00 = lerpf(p00.x, p00.y, wa), r01 = lerpf(p01.x, p01.y, wa);
     const float r10 = lerpf(p10.x, p10.y, wa), r11 = lerpf(p11.x, p11.y, wa);
     return lerpf(lerpf(r00, r01, wb), lerpf(r10, r11, wb), wc);
@@ -1063,8 +1092,8 @@ k_template_features(TplArgs A)
         const double Jf = mv.sigma > 0 ? (nm - 1) - g[mv.a] : g[mv.a];
         const double Uf = g[mv.b] + Jf * mv.sb, Vf = g[mv.c] + Jf * mv.sc;
         const double fu = floor(Uf), fv = floor(Vf), fj = floor(Jf);
-        const float Dv = sample_D(mv.dpairs + lv.q_off, lv, (int)fu, (int)fv, (int)fj, (float)(Uf - fu),
-                                  (float)(Vf - fv), (float)(Jf - fj));
+        const float Dv = sample_D2(mv.dpairs + lv.q_off, lv, (int)fu, (int)fv, (int)fj, (float)(Uf - fu),
+                                   (float)(Vf - fv), (float)(Jf - fj));
         const float T = __builtin_amdgcn_exp2f(-scoef[m] * 1.44269504088896341f * Dv);
         const bool at_p = s[0] == x[0] && s[1] == x[1] && s[2] == x[2];
         const float4 e = at_p ? centre : A.tab->site[t];
