@@ -524,6 +524,32 @@ def main():
     ms_tpl_light = timed_mode(tpl_light)
     template_batch = {"points": len(cp), "ms_static_light": ms_tpl, "ms_light_change": ms_tpl_light}
     log("4129 template centres: %.3f ms (static light), %.3f ms (light change)" % (ms_tpl, ms_tpl_light))
+    # the same across media: 4129 centres in each of four media (this frame's
+    # 256^3 cloud twice, with other centres, and 128^3 and 64^3 clouds, seeds
+    # 102 and 101, each under its own light), as one batched query and as
+    # four single queries (static lights)
+    from workloads import medium as wmedium
+    extra = [ctx.load_medium(wmedium.fbm_cloud(nn, seed=sd), wl.sigma_t, wl.albedo, wl.g) for nn, sd in ((128, 102), (64, 101))]
+    ctx.set_light(extra[0], (-0.7, 0.2, 0.4), 1.0)
+    ctx.set_light(extra[1], (0.1, -0.3, -0.95), 1.0)
+    bq = []
+    for i, m in enumerate([mid, extra[0], extra[1], mid]):
+        q, qd = camera.random_points(4129, seed=31 + i, lo=0.0, hi=1.0)
+        bq.append((m, torch.from_numpy(np.ascontiguousarray(q, np.float32)).cuda(),
+                   torch.from_numpy(np.ascontiguousarray(qd, np.float32)).cuda(),
+                   torch.empty(4129, dtype=torch.float32, device="cuda")))
+    ms_batch = timed_mode(lambda: ctx.query_batch(bq, stream=stream.cuda_stream))
+
+    def singles():
+        for m, q, qd, o in bq:
+            ctx.query_device(m, q, qd, o, stream=stream.cuda_stream)
+
+    ms_singles = timed_mode(singles)
+    template_batch["four_media"] = {"points": 4 * 4129, "ms_one_batched_query": ms_batch,
+                                    "ms_four_single_queries": ms_singles}
+    log("4 x 4129 centres over 4 media: %.3f ms batched, %.3f ms as single queries" % (ms_batch, ms_singles))
+    for m in extra:
+        ctx.unload_medium(m)
     fps_modes = {"light_change_full_frame": 1000.0 / res[args.precision]["ms"],
                  "static_light_full_frame": 1000.0 / ms_static,
                  "static_light_query_only": 1000.0 / ms_query}

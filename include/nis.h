@@ -287,6 +287,35 @@ int32_t nis_query(nis_ctx *ctx, int32_t medium, const float *points, const float
 int32_t nis_query_rgb(nis_ctx *ctx, int32_t medium, const float *points, const float *view_dirs,
                       int64_t n, float *radiance_out);
 
+/* One query of a batch (nis_query_batch): n points of `medium` under its
+ * light, device arrays as for nis_query_device. */
+typedef struct nis_query_item {
+    int32_t medium;
+    int32_t reserved;           /* 0 */
+    const float *d_points;      /* [n][3] */
+    const float *d_view_dirs;   /* [n][3] */
+    int64_t n;                  /* >= 0 */
+    float *d_radiance_out;      /* [n] */
+} nis_query_item;
+
+/*
+ * nis_query_batch -- `count` (1..64) queries, possibly over different media
+ * each under its own light and phase, as one gather launch and one backbone
+ * launch (Sec. III.C.2: the network is evaluated for many template positions
+ * in parallel; the paper's own use queries 4129 template centres per
+ * medium).  Each query's radiance equals, bit for bit, what
+ * nis_query_device gives it alone.  The light fields and site tables of each
+ * medium are brought up to date first, then the gather reads each query's
+ * medium from a table (its workgroups a contiguous range of the grid), the
+ * backbone runs once over all rows, and each query's decode writes its
+ * output.  At most 2^21 points in all; the lattice templates and a grey
+ * albedo only.  Queued on `hip_stream` like nis_query_device.
+ * Errors: NIS_E_INVALID (count, an item, more than 2^21 points),
+ * NIS_E_STATE (no weights, unknown medium, a coloured medium),
+ * NIS_E_UNSUPPORTED (the paper's templates; FP8 without scales).
+ */
+int32_t nis_query_batch(nis_ctx *ctx, const nis_query_item *items, int32_t count, void *hip_stream);
+
 /* nis_query_rgb_device -- nis_query_rgb on device arrays (d_radiance_out
  * float32 [n][3]), queued on `hip_stream` as nis_query_device. */
 int32_t nis_query_rgb_device(nis_ctx *ctx, int32_t medium, const float *d_points,

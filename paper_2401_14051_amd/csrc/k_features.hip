@@ -246,9 +246,11 @@ __device__ __forceinline__ uint8_t fp8_code(float x)
 
 // F8: the descriptor is stored as E4M3 codes of the entries divided by the
 // backbone's first input scale (the CNN itself runs in BF16).
+//
+// The body takes the workgroup's index within its query's grid, so that one
+// launch can serve several queries (k_features_multi).
 template <int PREC, bool DBG, bool F8>
-__global__ void __launch_bounds__(64, 3)
-k_features(FeatArgs A)
+__device__ __forceinline__ void features_body(const FeatArgs& A, int64_t block)
 {
     typedef Mfma<PREC> M;
     typedef typename M::elem E;
@@ -273,9 +275,9 @@ k_features(FeatArgs A)
     // that neighbouring points share an L2.  The grid is a multiple of 8.
     const int64_t npts = A.count ? min(max((int64_t)*A.count - A.count_off, (int64_t)0), A.npts) : A.npts;
     const int64_t per_xcd = ((npts + kTP - 1) / kTP + kXcds - 1) / kXcds;   // of the live tiles
-    const int64_t slot = blockIdx.x / kXcds;
+    const int64_t slot = block / kXcds;
     if (slot >= per_xcd) return;
-    const int64_t tile0 = ((int64_t)(blockIdx.x % kXcds) * per_xcd + slot) * kTP;
+    const int64_t tile0 = ((block % kXcds) * per_xcd + slot) * kTP;
     // (the point count may live in device memory: frames whose hit count the
     // device computed; workgroups past it leave at once)
     if (tile0 >= npts) return;
@@ -887,6 +889,25 @@ k_features(FeatArgs A)
     }
 }
 
+template <int PREC, bool DBG, bool F8>
+__global__ void __launch_bounds__(64, 3)
+k_features(FeatArgs A)
+{
+    features_body<PREC, DBG, F8>(A, blockIdx.x);
+}
+
+// Several queries in one launch: query r's workgroups are first[r] ..
+// first[r + 1] - 1 (each count a multiple of 8, so that a workgroup's XCD is
+// the one its own grid would give it); its arguments are read from the table.
+template <int PREC, bool F8>
+__global__ void __launch_bounds__(64, 3)
+k_features_multi(FeatMulti M)
+{
+    int r = 0;
+    for (int i = 1; i < M.n; i++) r = (int)blockIdx.x >= M.first[i] ? i : r;
+    features_body<PREC, false, F8>(M.table[r], (int64_t)blockIdx.x - M.first[r]);
+}
+
 // ---- the gather at the paper's own templates (Sec. III.B.2, eq. 2-4) -----
 //
 // Diffuse layer k < 8: point s = p + r_k u (u its unit template point, r_k its
@@ -1257,6 +1278,22 @@ hipError_t launch_desc_to_f32(int prec, const void* src, float* dst, int64_t n, 
         hipLaunchKernelGGL(k_desc_to_f32<kPrecBF16>, dim3(blocks), dim3(256), 0, s, src, dst, n, scale);
     else
         hipLaunchKernelGGL(k_desc_to_f32<kPrecFP32>, dim3(blocks), dim3(256), 0, s, src, dst, n, scale);
+    return hipGetLastError();
+}
+
+int64_t features_blocks(int64_t npts) { return ((npts + kTP - 1) / kTP + kXcds - 1) / kXcds * kXcds; }
+
+hipError_t launch_features_multi(int prec, const FeatMulti& m, hipStream_t s)
+{
+    if (m.n <= 0 || m.n > kMaxBatch) return hipErrorInvalidValue;
+    const int blocks = m.first[m.n];
+    if (blocks <= 0) return hipSuccess;
+    if (prec == kPrecFP8)
+        hipLaunchKernelGGL((k_features_multi<kPrecBF16, true>), dim3(blocks), dim3(64), 0, s, m);
+    else if (prec == kPrecBF16)
+        hipLaunchKernelGGL((k_features_multi<kPrecBF16, false>), dim3(blocks), dim3(64), 0, s, m);
+    else
+        hipLaunchKernelGGL((k_features_multi<kPrecFP32, false>), dim3(blocks), dim3(64), 0, s, m);
     return hipGetLastError();
 }
 

@@ -130,7 +130,7 @@ k_mlp(MlpArgs A)
         for (int k = 0; k < W; k++) y += (float)h[rr][k] * A.wout[k];
         if (row < npts) {
             if (A.y_out) A.y_out[row] = y;
-            if (A.out) A.out[row * A.out_stride] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
+            if (A.out) A.out[row * A.out_stride] = decode_radiance(A.radiance, A.f0[row], A.albedo_gamma, y);
         }
     }
 }
@@ -533,7 +533,7 @@ k_mlp_bf16(MlpArgs A)
         if (lg == 0 && row < npts) {
             const float y = A.bout + s;
             if (A.y_out) A.y_out[row] = y;
-            if (A.out) A.out[row * A.out_stride] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
+            if (A.out) A.out[row * A.out_stride] = decode_radiance(A.radiance, A.f0[row], A.albedo_gamma, y);
         }
     }
 }
@@ -900,7 +900,7 @@ k_mlp_f8(MlpArgs A)
         if (lg == 0 && row < npts) {
             const float y = A.bout + s;
             if (A.y_out) A.y_out[row] = y;
-            if (A.out) A.out[row * A.out_stride] = A.radiance * (A.f0[row] + A.albedo_gamma * expm1f(y));
+            if (A.out) A.out[row * A.out_stride] = decode_radiance(A.radiance, A.f0[row], A.albedo_gamma, y);
         }
     }
 }
@@ -980,6 +980,23 @@ int mlp_padded_width(int width)
     for (int s : sizes)
         if (width <= s) return s;
     return -1;
+}
+
+__global__ void k_decode(const float* __restrict__ y, const float* __restrict__ f0, int64_t n, float radiance,
+                         float albedo_gamma, float* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = decode_radiance(radiance, f0[i], albedo_gamma, y[i]);
+}
+
+hipError_t launch_decode(const float* y, const float* f0, int64_t n, float radiance, float albedo_gamma, float* out,
+                         hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_decode, dim3((int)blocks), dim3(256), 0, s, y, f0, n, radiance, albedo_gamma, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_mlp(int prec, const MlpArgs& a, hipStream_t s)

@@ -30,6 +30,16 @@ struct FeatArgs {
     int64_t count_off;           // min(npts, *count - count_off) points
 };
 
+// Several gathers in one launch (nis_query_batch): query r's arguments are
+// table[r] (device memory) and its workgroups first[r] .. first[r + 1] - 1,
+// features_blocks(npts) of them.
+constexpr int kMaxBatch = 64;
+struct FeatMulti {
+    const FeatArgs* table;
+    int n;
+    int first[kMaxBatch + 1];
+};
+
 // The gather at the paper's templates (k_template_features).
 struct TplArgs {
     MediumView mv;
@@ -112,6 +122,11 @@ struct GaussLegendre64 {
 hipError_t launch_volume_tables(const MediumView& mv, const GaussLegendre64& gl, SiteTables* tab, float* vtab,
                                 hipStream_t s);
 hipError_t launch_features(int prec, const FeatArgs& a, hipStream_t s);
+int64_t features_blocks(int64_t npts);   // workgroups launch_features uses for npts points
+hipError_t launch_features_multi(int prec, const FeatMulti& m, hipStream_t s);
+// L[i] = radiance (f0[i] + albedo_gamma expm1(y[i])) for n points (the backbone's decode)
+hipError_t launch_decode(const float* y, const float* f0, int64_t n, float radiance, float albedo_gamma, float* out,
+                         hipStream_t s);
 hipError_t launch_template_features(int prec, const TplArgs& a, hipStream_t s);
 // The paper's backbone modules: FP32 template feature rows [npts][kDescPad]
 // -> descriptor rows in the precision's layout.

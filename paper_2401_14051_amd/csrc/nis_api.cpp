@@ -857,6 +857,30 @@ void run_query(Workspace& ws, const Net* net, int prec, const Medium* M, LightSt
     run_query_in(w, net, prec, M, ls, Pm, d_pts, d_dirs, n, d_count, o, s, true);
 }
 
+// The gather's arguments that do not depend on the points: medium view,
+// light tables, layer coefficients, CNN weights, descriptor scale.
+FeatArgs feat_args(const Net* net, int prec, const Medium* M, const LightState* ls, const Params& Pm,
+                   const MediumView& mv)
+{
+    const PackedNet& P = net->packed[prec];
+    FeatArgs fa;
+    std::memset(&fa, 0, sizeof(fa));
+    fa.mv = mv;
+    fa.tab = ls->tab.as<SiteTables>();
+    fa.vtab = Pm.volume ? ls->vtab.as<float>() : nullptr;
+    for (int k = 0; k < kLayers; k++) {
+        int m = k < M->levels - 1 ? k : M->levels - 1;
+        fa.coef[k] = (float)(std::pow((double)net->lam, m + 1) * (double)Pm.sigma_t);
+    }
+    for (int gi = 0; gi < 2; gi++) {
+        fa.w1t[gi] = P.w1t[gi].p;
+        fa.w2t[gi] = P.w2t[gi].p;
+        fa.cb[gi] = P.cb[gi].as<float>();
+    }
+    fa.desc_inv_scale = prec == kPrecFP8 ? 1.f / net->fp8_scales[2] : 1.f;
+    return fa;
+}
+
 void run_query_in(const WsView& ws, const Net* net, int prec, const Medium* M, LightState* ls, const Params& Pm,
                   const float* d_pts, const float* d_dirs, int64_t n, const int* d_count, const QueryOut& o,
                   hipStream_t s, bool may_alloc)
@@ -882,27 +906,13 @@ void run_query_in(const WsView& ws, const Net* net, int prec, const Medium* M, L
     MediumView mv = make_view(M, ls, Pm, net);
     for (int64_t p0 = 0; p0 < n; p0 += chunk) {
         const int64_t cn = (n - p0) < chunk ? (n - p0) : chunk;
-        FeatArgs fa;
-        std::memset(&fa, 0, sizeof(fa));
-        fa.mv = mv;
-        fa.tab = ls->tab.as<SiteTables>();
-        fa.vtab = Pm.volume ? ls->vtab.as<float>() : nullptr;
+        FeatArgs fa = feat_args(net, prec, M, ls, Pm, mv);
         fa.pts = d_pts + 3 * p0;
         fa.dirs = d_dirs + 3 * p0;
         fa.npts = cn;
         fa.count = d_count;
         fa.count_off = p0;
-        for (int k = 0; k < kLayers; k++) {
-            int m = k < M->levels - 1 ? k : M->levels - 1;
-            fa.coef[k] = (float)(std::pow((double)net->lam, m + 1) * (double)Pm.sigma_t);
-        }
-        for (int gi = 0; gi < 2; gi++) {
-            fa.w1t[gi] = P.w1t[gi].p;
-            fa.w2t[gi] = P.w2t[gi].p;
-            fa.cb[gi] = P.cb[gi].as<float>();
-        }
         fa.desc = ws.desc;
-        fa.desc_inv_scale = prec == kPrecFP8 ? 1.f / net->fp8_scales[2] : 1.f;
         fa.f0 = o.f0 ? o.f0 + p0 : ws.f0;
         auto off = [&](float* base, int64_t per) { return base ? base + p0 * per : nullptr; };
         fa.dbg_tbar = off(o.tbar, kLayers * kSites);
@@ -1205,6 +1215,8 @@ int32_t nis_destroy(nis_ctx* ctx)
         ctx->ws.release();
         ctx->fw.release();
         ctx->io.release();
+        ctx->batch_y.release();
+        ctx->batch_tab.release();
         (void)hipEventDestroy(ctx->order);
         (void)hipStreamDestroy(ctx->stream);
         delete ctx;
@@ -1587,6 +1599,99 @@ int32_t nis_query_device_noalloc(nis_ctx* ctx, int32_t medium, const float* d_po
         QueryOut o;
         o.radiance = d_out;
         run_query_in(w, ctx->net, ctx->precision, M, &M->light, P, d_points, d_dirs, n, nullptr, o, su.s, false);
+    });
+}
+
+int32_t nis_query_batch(nis_ctx* ctx, const nis_query_item* items, int32_t count, void* hip_stream)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (!items || count <= 0 || count > kMaxBatch) fail(NIS_E_INVALID, "a batch holds 1 to 64 queries");
+        const Net* net = ctx->net;
+        if (!net) fail(NIS_E_STATE, "no weights set");
+        const int prec = ctx->precision;
+        if (prec == kPrecFP8 && !net->has_fp8)
+            fail(NIS_E_UNSUPPORTED, "FP8 needs the activation scales: pass them in the weight blob or call nis_calibrate_fp8");
+        if (ctx->templates != NIS_TEMPLATES_LATTICE)
+            fail(NIS_E_UNSUPPORTED, "batched queries sample the lattice templates");
+        int64_t total = 0;
+        std::vector<Medium*> media(count);
+        for (int32_t i = 0; i < count; i++) {
+            const nis_query_item& it = items[i];
+            if (it.n < 0 || it.reserved != 0 || (it.n > 0 && (!it.d_points || !it.d_view_dirs || !it.d_radiance_out)))
+                fail(NIS_E_INVALID, "bad batch item");
+            media[i] = get_medium(ctx, it.medium);
+            if (!grey_albedo(media[i])) fail(NIS_E_STATE, "a coloured medium needs the RGB query");
+            total += it.n;
+        }
+        if (total > kChunk) fail(NIS_E_INVALID, "a batch holds at most 2^21 points");
+        if (total == 0) return;
+        StreamUse su(ctx, (hipStream_t)hip_stream);
+        const hipStream_t s = su.s;
+        Workspace& ws = ctx->ws;
+        const size_t rb = desc_row_bytes(prec);
+        ws.desc.reserve((size_t)total * rb, "descriptor workspace");
+        ws.f0.reserve((size_t)total * sizeof(float), "single-scatter workspace");
+        ctx->batch_y.reserve((size_t)total * sizeof(float), "batch network outputs");
+        // each query's light fields and tables, then its gather arguments
+        std::vector<FeatArgs> tab(count);
+        FeatMulti fm;
+        std::memset(&fm, 0, sizeof(fm));
+        fm.n = count;
+        int64_t base = 0, blocks = 0;
+        for (int32_t i = 0; i < count; i++) {
+            Medium* M = media[i];
+            const Params P = grey_params(M);
+            ensure_sweep(M, &M->light, s);
+            refresh_tables(M, &M->light, P.phase, P.volume, s, true);
+            tab[i] = feat_args(net, prec, M, &M->light, P, make_view(M, &M->light, P, net));
+            tab[i].pts = items[i].d_points;
+            tab[i].dirs = items[i].d_view_dirs;
+            tab[i].npts = items[i].n;
+            tab[i].desc = static_cast<char*>(ws.desc.p) + (size_t)base * rb;
+            tab[i].f0 = ws.f0.as<float>() + base;
+            fm.first[i] = (int)blocks;
+            blocks += items[i].n > 0 ? features_blocks(items[i].n) : 0;
+            base += items[i].n;
+        }
+        if (blocks > 0x7fffffff) fail(NIS_E_INVALID, "batch too large");
+        fm.first[count] = (int)blocks;
+        // the table from pageable memory: the copy has read it when the call returns
+        ctx->batch_tab.reserve(sizeof(FeatArgs) * count, "batch table");
+        hip_check(hipMemcpyAsync(ctx->batch_tab.p, tab.data(), sizeof(FeatArgs) * count, hipMemcpyHostToDevice, s),
+                  "batch table");
+        fm.table = ctx->batch_tab.as<FeatArgs>();
+        timed("features", s, [&] { return launch_features_multi(prec, fm, s); });
+        // one backbone pass over every query's rows, then each query's decode
+        const PackedNet& PN = net->packed[prec];
+        MlpArgs ma;
+        std::memset(&ma, 0, sizeof(ma));
+        ma.x = ws.desc.p;
+        ma.npts = total;
+        for (int li = 0; li + 1 < net->n_linear; li++) {
+            ma.W[li] = PN.W[li].p;
+            ma.bias[li] = PN.bias[li].as<float>();
+            ma.wexp[li] = PN.wexp[li].as<uint32_t>();
+        }
+        ma.wout = PN.wout.as<float>();
+        ma.bout = net->beta[net->n_linear - 1][0];
+        ma.n_linear = net->n_linear;
+        ma.wpad = net->wpad;
+        ma.f0 = ws.f0.as<float>();
+        ma.out_stride = 1;
+        ma.y_out = ctx->batch_y.as<float>();
+        timed("backbone", s, [&] { return launch_mlp(prec, ma, s); });
+        base = 0;
+        for (int32_t i = 0; i < count; i++) {
+            const Medium* M = media[i];
+            const float ag = (float)std::pow((double)M->albedo, (double)net->gamma);
+            timed("decode", s, [&] {
+                return launch_decode(ctx->batch_y.as<float>() + base, ws.f0.as<float>() + base, items[i].n,
+                                     M->radiance, ag, items[i].d_radiance_out, s);
+            });
+            base += items[i].n;
+        }
     });
 }
 

@@ -95,6 +95,13 @@ __host__ __device__ constexpr int tpl_first(int k)
     return f;
 }
 
+// The decode of eq. (21) and the radiance of eq. (19): L = I (f(w.l) T + F),
+// F = eta^gamma expm1(y); one definition for every kernel that decodes.
+__device__ __forceinline__ float decode_radiance(float radiance, float f0, float albedo_gamma, float y)
+{
+    return radiance * __builtin_fmaf(albedo_gamma, expm1f(y), f0);
+}
+
 // The feature rows the paper's backbone modules read, written by the
 // template gather: per feature type (graded transmittance, density, phase)
 // the layers' values, each layer's block padded to a multiple of 4 floats

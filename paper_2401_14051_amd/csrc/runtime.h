@@ -284,6 +284,7 @@ struct nis_ctx {
     nis::Workspace ws;
     nis::FrameWork fw;
     nis::DevBuf io;
+    nis::DevBuf batch_y, batch_tab;    // nis_query_batch: network outputs, gather argument table
     nis::Profiler prof;
     std::mutex mu;             // taken by every ABI call and by the server's scheduler
     Server* server = nullptr;

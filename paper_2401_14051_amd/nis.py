@@ -68,6 +68,11 @@ class nis_frame_result(ctypes.Structure):
                 ("t_done", ctypes.c_double)]
 
 
+class nis_query_item(ctypes.Structure):
+    _fields_ = [("medium", ctypes.c_int32), ("reserved", ctypes.c_int32), ("d_points", ctypes.c_void_p),
+                ("d_view_dirs", ctypes.c_void_p), ("n", ctypes.c_int64), ("d_radiance_out", ctypes.c_void_p)]
+
+
 _u64 = ctypes.c_uint64
 
 _SIGNATURES = {
@@ -87,6 +92,7 @@ _SIGNATURES = {
     "nis_query": [_vp, _i32, _vp, _vp, _i64, _vp],
     "nis_query_device": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
     "nis_query_device_noalloc": [_vp, _i32, _vp, _vp, _i64, _vp, _vp],
+    "nis_query_batch": [_vp, _vp, _i32, _vp],
     "nis_calibrate_fp8": [_vp, _i32, _vp, _vp, _i64, _vp],
     "nis_set_templates": [_vp, _i32],
     "nis_set_backbone": [_vp, _i32],
@@ -316,6 +322,24 @@ class Context:
             stream = torch.cuda.current_stream(points.device).cuda_stream
         _check(_lib.nis_query_device(self.h, medium, _dptr(points), _dptr(dirs), points.shape[0],
                                      _dptr(out), _vp(stream)))
+
+    def query_batch(self, queries, stream=None):
+        """Several device queries in one launch: ``queries`` is a list of
+        (medium, points, dirs, out) with torch device tensors; queued on
+        ``stream`` (None = the current torch stream)."""
+        import torch
+        items = (nis_query_item * len(queries))()
+        for it, (medium, points, dirs, out) in zip(items, queries):
+            it.medium = medium
+            it.reserved = 0
+            it.d_points = points.data_ptr()
+            it.d_view_dirs = dirs.data_ptr()
+            it.n = points.shape[0]
+            it.d_radiance_out = out.data_ptr()
+        if stream is None:
+            dev = queries[0][1].device if queries else torch.device("cuda", self.device)
+            stream = torch.cuda.current_stream(dev).cuda_stream
+        _check(_lib.nis_query_batch(self.h, items, len(queries), _vp(stream)))
 
     def calibrate_fp8(self, medium, points, dirs, stream=None):
         """Static FP8 activation scales from the FP32 path over these points

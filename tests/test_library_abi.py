@@ -82,7 +82,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     import subprocess
     from paper_2401_14051_amd import nis
     structs = {"nis_camera": nis.nis_camera, "nis_server_cfg": nis.nis_server_cfg,
-               "nis_frame_req": nis.nis_frame_req, "nis_frame_result": nis.nis_frame_result}
+               "nis_frame_req": nis.nis_frame_req, "nis_frame_result": nis.nis_frame_result,
+               "nis_query_item": nis.nis_query_item}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "nis.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (name, name))
