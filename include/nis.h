@@ -433,6 +433,9 @@ typedef struct nis_server_cfg {
                                    fields and workspaces plus every unreleased image */
     int32_t precision;          /* NIS_FP32, NIS_BF16 or NIS_FP8 */
     int32_t max_inflight;       /* frames on the device at once, 1..16 */
+    int32_t batch_gather;       /* 1: small grey frames (<= 2^18 pixels) admitted together
+                                   share one gather launch (results unchanged); 0: off */
+    int32_t reserved;           /* 0 */
 } nis_server_cfg;
 
 typedef struct nis_frame_req {

@@ -881,6 +881,33 @@ FeatArgs feat_args(const Net* net, int prec, const Medium* M, const LightState* 
     return fa;
 }
 
+// The backbone's arguments that do not depend on the points: its weights.
+MlpArgs mlp_args(const Net* net, int prec)
+{
+    const PackedNet& P = net->packed[prec];
+    MlpArgs ma;
+    std::memset(&ma, 0, sizeof(ma));
+    for (int li = 0; li + 1 < net->n_linear; li++) {
+        ma.W[li] = P.W[li].p;
+        ma.bias[li] = P.bias[li].as<float>();
+        ma.wexp[li] = P.wexp[li].as<uint32_t>();
+    }
+    ma.wout = P.wout.as<float>();
+    ma.bout = net->beta[net->n_linear - 1][0];
+    ma.n_linear = net->n_linear;
+    ma.wpad = net->wpad;
+    ma.out_stride = 1;
+    return ma;
+}
+
+FeatArgs prepare_feat_args(const Net* net, int prec, const Medium* M, LightState* ls, const Params& P,
+                           hipStream_t s)
+{
+    ensure_sweep(M, ls, s);
+    refresh_tables(M, ls, P.phase, P.volume, s, true);
+    return feat_args(net, prec, M, ls, P, make_view(M, ls, P, net));
+}
+
 void run_query_in(const WsView& ws, const Net* net, int prec, const Medium* M, LightState* ls, const Params& Pm,
                   const float* d_pts, const float* d_dirs, int64_t n, const int* d_count, const QueryOut& o,
                   hipStream_t s, bool may_alloc)
@@ -901,7 +928,6 @@ void run_query_in(const WsView& ws, const Net* net, int prec, const Medium* M, L
     ensure_sweep(M, ls, s);
     if (Pm.templates) refresh_tpl_tables(ls, Pm.phase, s, may_alloc);
     else refresh_tables(M, ls, Pm.phase, Pm.volume, s, may_alloc);
-    const PackedNet& P = net->packed[prec];
     const int64_t chunk = ws.chunk;
     MediumView mv = make_view(M, ls, Pm, net);
     for (int64_t p0 = 0; p0 < n; p0 += chunk) {
@@ -963,22 +989,12 @@ void run_query_in(const WsView& ws, const Net* net, int prec, const Medium* M, L
                       "descriptor copy");
         }
         if (!o.run_mlp) continue;
-        MlpArgs ma;
-        std::memset(&ma, 0, sizeof(ma));
+        MlpArgs ma = mlp_args(net, prec);
         ma.x = ws.desc;
         ma.npts = cn;
         ma.count = d_count;
         ma.count_off = p0;
-        for (int li = 0; li + 1 < net->n_linear; li++) {
-            ma.W[li] = P.W[li].p;
-            ma.bias[li] = P.bias[li].as<float>();
-            ma.wexp[li] = P.wexp[li].as<uint32_t>();
-        }
         ma.absmax = o.absmax;
-        ma.wout = P.wout.as<float>();
-        ma.bout = net->beta[net->n_linear - 1][0];
-        ma.n_linear = net->n_linear;
-        ma.wpad = net->wpad;
         ma.f0 = fa.f0;
         ma.radiance = Pm.radiance;
         ma.out_stride = Pm.channels;
@@ -1642,10 +1658,7 @@ int32_t nis_query_batch(nis_ctx* ctx, const nis_query_item* items, int32_t count
         int64_t base = 0, blocks = 0;
         for (int32_t i = 0; i < count; i++) {
             Medium* M = media[i];
-            const Params P = grey_params(M);
-            ensure_sweep(M, &M->light, s);
-            refresh_tables(M, &M->light, P.phase, P.volume, s, true);
-            tab[i] = feat_args(net, prec, M, &M->light, P, make_view(M, &M->light, P, net));
+            tab[i] = prepare_feat_args(net, prec, M, &M->light, grey_params(M), s);
             tab[i].pts = items[i].d_points;
             tab[i].dirs = items[i].d_view_dirs;
             tab[i].npts = items[i].n;
@@ -1664,22 +1677,10 @@ int32_t nis_query_batch(nis_ctx* ctx, const nis_query_item* items, int32_t count
         fm.table = ctx->batch_tab.as<FeatArgs>();
         timed("features", s, [&] { return launch_features_multi(prec, fm, s); });
         // one backbone pass over every query's rows, then each query's decode
-        const PackedNet& PN = net->packed[prec];
-        MlpArgs ma;
-        std::memset(&ma, 0, sizeof(ma));
+        MlpArgs ma = mlp_args(net, prec);
         ma.x = ws.desc.p;
         ma.npts = total;
-        for (int li = 0; li + 1 < net->n_linear; li++) {
-            ma.W[li] = PN.W[li].p;
-            ma.bias[li] = PN.bias[li].as<float>();
-            ma.wexp[li] = PN.wexp[li].as<uint32_t>();
-        }
-        ma.wout = PN.wout.as<float>();
-        ma.bout = net->beta[net->n_linear - 1][0];
-        ma.n_linear = net->n_linear;
-        ma.wpad = net->wpad;
         ma.f0 = ws.f0.as<float>();
-        ma.out_stride = 1;
         ma.y_out = ctx->batch_y.as<float>();
         timed("backbone", s, [&] { return launch_mlp(prec, ma, s); });
         base = 0;

@@ -254,6 +254,13 @@ void run_query_in(const WsView& w, const Net* net, int prec, const Medium* M, Li
                   const float* d_pts, const float* d_dirs, int64_t n, const int* d_count, const QueryOut& o,
                   hipStream_t s, bool may_alloc);
 
+// The gather's arguments for a query of medium M under light state ls (its
+// points, count, outputs not set), after bringing the light's fields and
+// site tables up to date on stream s; the backbone's weight arguments.
+FeatArgs prepare_feat_args(const Net* net, int prec, const Medium* M, LightState* ls, const Params& P,
+                           hipStream_t s);
+MlpArgs mlp_args(const Net* net, int prec);
+
 // Validates a camera and converts it to kernel arguments.
 CamArgs camera_args(const nis_camera* cam);
 

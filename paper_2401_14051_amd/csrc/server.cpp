@@ -10,6 +10,16 @@
 // slots.  A slot keeps its light fields between frames and skips the sweep
 // when the next frame has the same medium, pyramid and light.  Completion is
 // observed by polling an event per slot.
+//
+// With batch_gather, the small grey frames (at most 2^18 pixels) admitted in
+// one scheduling pass share their gather: each runs its light fields, camera
+// rays and collisions on its own slot's stream, then one launch of the
+// gather on the first frame's stream covers every frame's collisions
+// (k_features_multi, each frame's medium and light from a table), after
+// which each frame's backbone and image run on its own stream again.  Two
+// sets of batch buffers let one batch gather while the previous one's
+// backbones still read theirs.  Larger frames run alone as before.  A
+// frame's image is bit for bit the one it gets alone.
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -27,6 +37,8 @@ using Clock = std::chrono::steady_clock;
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    hipEvent_t pre = nullptr;        // batch mode: the frame's collisions and light fields are ready
+    hipEvent_t read = nullptr;       // batch mode: the frame's backbone has read the batch buffers
     int* pinned_count = nullptr;     // host copy of the frame's collision count
     Workspace ws;
     FrameWork fw;
@@ -65,6 +77,12 @@ struct Server {
     std::deque<uint64_t> queue;
     std::map<uint64_t, Request> reqs;
     std::vector<DevBuf> spare_images;
+    // batch mode, two sets: descriptors, single-scatter terms, gather table;
+    // an event recorded once every backbone of the set's last batch read it
+    DevBuf bdesc[2], bf0[2], btab[2];
+    hipEvent_t gathered = nullptr, bdone[2] = {nullptr, nullptr};
+    bool bdone_rec[2] = {false, false};
+    int bset = 0;
     uint64_t next_id = 1;
     bool stop = false;
     std::thread thread;
@@ -80,6 +98,7 @@ struct Server {
         for (const Slot& s : slots) b += s.bytes();
         for (const auto& kv : reqs) b += kv.second.image.bytes;
         for (const DevBuf& d : spare_images) b += d.bytes;
+        for (int i = 0; i < 2; i++) b += bdesc[i].bytes + bf0[i].bytes + btab[i].bytes;
         return b;
     }
 };
@@ -153,8 +172,8 @@ void retire(nis_ctx* ctx, Server* S)
     }
 }
 
-// Queues the whole frame of request `id` on slot k.
-void launch(nis_ctx* ctx, Server* S, int k, uint64_t id)
+// Light state and image of request `id` on slot k.
+Medium* begin(nis_ctx* ctx, Server* S, int k, uint64_t id)
 {
     Slot& s = S->slots[k];
     Request& r = S->reqs[id];
@@ -175,20 +194,141 @@ void launch(nis_ctx* ctx, Server* S, int k, uint64_t id)
     } else {
         r.image.reserve(ib, "frame image");
     }
-    render_frame(s.ws, s.fw, ctx->net, S->cfg.precision, M, &s.ls, r.P, r.C, r.req.seed, r.image.as<float>(),
-                 s.stream);
-    hip_check(hipMemcpyAsync(s.pinned_count, s.fw.count.p, sizeof(int), hipMemcpyDeviceToHost, s.stream),
+    return M;
+}
+
+// The frame of request `id` on slot k is queued up to its image on stream st:
+// its count comes back and its completion is recorded there.
+void finish(Server* S, int k, uint64_t id, hipStream_t st)
+{
+    Slot& s = S->slots[k];
+    Request& r = S->reqs[id];
+    hip_check(hipMemcpyAsync(s.pinned_count, s.fw.count.p, sizeof(int), hipMemcpyDeviceToHost, st),
               "count download");
-    hip_check(hipEventRecord(s.done, s.stream), "hipEventRecord");
+    hip_check(hipEventRecord(s.done, st), "hipEventRecord");
     r.status = NIS_RUNNING;
     r.slot = k;
     r.t_start = S->now();
     s.req = id;
 }
 
+// Queues the whole frame of request `id` on slot k.
+void launch(nis_ctx* ctx, Server* S, int k, uint64_t id)
+{
+    Slot& s = S->slots[k];
+    Request& r = S->reqs[id];
+    Medium* M = begin(ctx, S, k, id);
+    render_frame(s.ws, s.fw, ctx->net, S->cfg.precision, M, &s.ls, r.P, r.C, r.req.seed, r.image.as<float>(),
+                 s.stream);
+    finish(S, k, id, s.stream);
+}
+
+// Queues the frames of `batch` (slot, request) with one gather launch.
+constexpr int64_t kBatchPix = 1 << 18;   // the largest frame that shares its gather
+
+void launch_batch(nis_ctx* ctx, Server* S, const std::vector<std::pair<int, uint64_t>>& batch)
+{
+    const int prec = S->cfg.precision;
+    const Net* net = ctx->net;
+    const int n = (int)batch.size();
+    std::vector<FeatArgs> tab(n);
+    FeatMulti fm;
+    std::memset(&fm, 0, sizeof(fm));
+    fm.n = n;
+    int64_t rows = 0, blocks = 0;
+    for (int i = 0; i < n; i++) {
+        const int k = batch[i].first;
+        Slot& s = S->slots[k];
+        Request& r = S->reqs[batch[i].second];
+        Medium* M = begin(ctx, S, k, batch[i].second);
+        CamArgs Cb = r.C;
+        Cb.band = kRenderBand;   // as render_frame: collisions in bands of rows
+        frame_points(s.fw, M, r.P, Cb, r.req.seed, nullptr, nullptr, nullptr, nullptr, s.stream);
+        tab[i] = prepare_feat_args(net, prec, M, &s.ls, r.P, s.stream);
+        const FrameBuffers fb = s.fw.view();
+        tab[i].pts = fb.cpts;
+        tab[i].dirs = fb.cdirs;
+        tab[i].npts = (int64_t)r.C.width * r.C.height;
+        tab[i].count = fb.count;
+        fm.first[i] = (int)blocks;
+        blocks += features_blocks(tab[i].npts);
+        rows += tab[i].npts;
+        hip_check(hipEventRecord(s.pre, s.stream), "hipEventRecord");
+    }
+    fm.first[n] = (int)blocks;
+    const int b = S->bset;
+    S->bset ^= 1;
+    const hipStream_t bs = S->slots[batch[0].first].stream;
+    for (int i = 1; i < n; i++) hip_check(hipStreamWaitEvent(bs, S->slots[batch[i].first].pre, 0), "wait");
+    // this buffer set's previous batch: its backbones have read it
+    if (S->bdone_rec[b]) hip_check(hipStreamWaitEvent(bs, S->bdone[b], 0), "wait");
+    const size_t rb = desc_row_bytes(prec);
+    S->bdesc[b].reserve((size_t)rows * rb, "batch descriptors");
+    S->bf0[b].reserve((size_t)rows * sizeof(float), "batch single-scatter terms");
+    S->btab[b].reserve(sizeof(FeatArgs) * n, "batch table");
+    int64_t base = 0;
+    for (int i = 0; i < n; i++) {
+        tab[i].desc = static_cast<char*>(S->bdesc[b].p) + (size_t)base * rb;
+        tab[i].f0 = S->bf0[b].as<float>() + base;
+        base += tab[i].npts;
+    }
+    // the table from pageable memory: the copy has read it when the call returns
+    hip_check(hipMemcpyAsync(S->btab[b].p, tab.data(), sizeof(FeatArgs) * n, hipMemcpyHostToDevice, bs),
+              "batch table");
+    fm.table = S->btab[b].as<FeatArgs>();
+    hip_check(launch_features_multi(prec, fm, bs), "features");
+    hip_check(hipEventRecord(S->gathered, bs), "hipEventRecord");
+    // each frame's backbone and image on its own stream
+    for (int i = 0; i < n; i++) {
+        const int k = batch[i].first;
+        Slot& s = S->slots[k];
+        Request& r = S->reqs[batch[i].second];
+        const FrameBuffers fb = s.fw.view();
+        if (i > 0) hip_check(hipStreamWaitEvent(s.stream, S->gathered, 0), "wait");
+        MlpArgs ma = mlp_args(net, prec);
+        ma.x = tab[i].desc;
+        ma.npts = tab[i].npts;
+        ma.count = fb.count;
+        ma.f0 = tab[i].f0;
+        ma.radiance = r.P.radiance;
+        ma.out = s.fw.L.as<float>();
+        ma.albedo_gamma = (float)std::pow((double)r.P.albedo, (double)net->gamma);
+        hip_check(launch_mlp(prec, ma, s.stream), "backbone");
+        hip_check(hipEventRecord(s.read, s.stream), "hipEventRecord");
+        hip_check(launch_image(fb, tab[i].npts, s.fw.L.as<float>(), r.P.albedo, r.image.as<float>(), s.stream),
+                  "image");
+        finish(S, k, batch[i].second, s.stream);
+    }
+    for (int i = 1; i < n; i++) hip_check(hipStreamWaitEvent(bs, S->slots[batch[i].first].read, 0), "wait");
+    hip_check(hipEventRecord(S->bdone[b], bs), "hipEventRecord");
+    S->bdone_rec[b] = true;
+}
+
 // Admits queued requests in order while a slot is idle and memory allows.
 void admit(nis_ctx* ctx, Server* S)
 {
+    std::vector<std::pair<int, uint64_t>> batch;   // batch mode: the pass's grey frames
+    int64_t batch_pix = 0;
+    auto flush = [&] {
+        if (batch.empty()) return;
+        try {
+            launch_batch(ctx, S, batch);
+        } catch (const Error& e) {
+            for (auto& b : batch) {
+                (void)hipStreamSynchronize(S->slots[b.first].stream);   // nothing may still write the image
+                S->slots[b.first].req = 0;
+                fail_request(S, S->reqs[b.second], e.code, e.msg);
+            }
+        } catch (...) {
+            for (auto& b : batch) {
+                (void)hipStreamSynchronize(S->slots[b.first].stream);
+                S->slots[b.first].req = 0;
+                fail_request(S, S->reqs[b.second], NIS_E_INTERNAL, "internal error");
+            }
+        }
+        batch.clear();
+        batch_pix = 0;
+    };
     while (!S->queue.empty()) {
         const uint64_t id = S->queue.front();
         Request& r = S->reqs[id];
@@ -209,7 +349,7 @@ void admit(nis_ctx* ctx, Server* S)
                 break;
             }
         }
-        if (k < 0) return;
+        if (k < 0) break;
         size_t ib = image_bytes(r), img_growth = ib;
         for (const DevBuf& d : S->spare_images)
             if (d.bytes >= ib) img_growth = 0;
@@ -229,9 +369,17 @@ void admit(nis_ctx* ctx, Server* S)
             // chosen slot too if it holds oversized buffers, else wait
             S->slots[k].release_buffers();
             need = slot_growth(S, S->slots[k], M, r) + img_growth;
-            if (S->held() + need > S->cfg.hbm_budget_bytes) return;
+            if (S->held() + need > S->cfg.hbm_budget_bytes) break;
         }
         S->queue.pop_front();
+        const int64_t npix = (int64_t)r.C.width * r.C.height;
+        if (S->cfg.batch_gather && r.P.channels == 1 && npix <= kBatchPix) {
+            if (batch_pix + npix > kChunk || (int)batch.size() == kMaxBatch) flush();
+            batch.emplace_back(k, id);
+            batch_pix += npix;
+            S->slots[k].req = id;   // taken; begin() and finish() fill in the rest
+            continue;
+        }
         try {
             launch(ctx, S, k, id);
         } catch (const Error& e) {
@@ -242,6 +390,7 @@ void admit(nis_ctx* ctx, Server* S)
             fail_request(S, r, NIS_E_INTERNAL, "internal error");
         }
     }
+    flush();
 }
 
 void scheduler(nis_ctx* ctx, Server* S)
@@ -326,11 +475,20 @@ void free_server(Server* S)
         if (s.stream) (void)hipStreamSynchronize(s.stream);
         s.release_buffers();
         if (s.done) (void)hipEventDestroy(s.done);
+        if (s.pre) (void)hipEventDestroy(s.pre);
+        if (s.read) (void)hipEventDestroy(s.read);
         if (s.pinned_count) (void)hipHostFree(s.pinned_count);
         if (s.stream) (void)hipStreamDestroy(s.stream);
     }
     for (auto& kv : S->reqs) kv.second.image.release();
     for (DevBuf& d : S->spare_images) d.release();
+    for (int i = 0; i < 2; i++) {
+        S->bdesc[i].release();
+        S->bf0[i].release();
+        S->btab[i].release();
+        if (S->bdone[i]) (void)hipEventDestroy(S->bdone[i]);
+    }
+    if (S->gathered) (void)hipEventDestroy(S->gathered);
     delete S;
 }
 
@@ -376,6 +534,8 @@ int32_t nis_server_start(nis_ctx* ctx, const nis_server_cfg* cfg)
                                     "nis_calibrate_fp8");
         if (cfg->max_inflight < 1 || cfg->max_inflight > 16) fail(NIS_E_INVALID, "max_inflight must be in [1,16]");
         if (cfg->hbm_budget_bytes == 0) fail(NIS_E_INVALID, "budget is zero");
+        if (cfg->batch_gather != 0 && cfg->batch_gather != 1) fail(NIS_E_INVALID, "batch_gather must be 0 or 1");
+        if (cfg->reserved != 0) fail(NIS_E_INVALID, "reserved must be 0");
         Server* S = new Server();
         S->cfg = *cfg;
         S->t0 = Clock::now();
@@ -384,9 +544,14 @@ int32_t nis_server_start(nis_ctx* ctx, const nis_server_cfg* cfg)
             for (Slot& s : S->slots) {
                 hip_check(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking), "hipStreamCreate");
                 hip_check(hipEventCreateWithFlags(&s.done, hipEventDisableTiming), "hipEventCreate");
+                hip_check(hipEventCreateWithFlags(&s.pre, hipEventDisableTiming), "hipEventCreate");
+                hip_check(hipEventCreateWithFlags(&s.read, hipEventDisableTiming), "hipEventCreate");
                 hip_check(hipHostMalloc((void**)&s.pinned_count, sizeof(int), hipHostMallocDefault), "hipHostMalloc");
                 *s.pinned_count = 0;
             }
+            for (int i = 0; i < 2; i++)
+                hip_check(hipEventCreateWithFlags(&S->bdone[i], hipEventDisableTiming), "hipEventCreate");
+            hip_check(hipEventCreateWithFlags(&S->gathered, hipEventDisableTiming), "hipEventCreate");
             S->thread = std::thread(scheduler, ctx, S);
         } catch (...) {
             free_server(S);

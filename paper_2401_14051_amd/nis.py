@@ -52,7 +52,7 @@ class nis_camera(ctypes.Structure):
 
 class nis_server_cfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("precision", ctypes.c_int32),
-                ("max_inflight", ctypes.c_int32)]
+                ("max_inflight", ctypes.c_int32), ("batch_gather", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class nis_frame_req(ctypes.Structure):
@@ -416,8 +416,9 @@ class Context:
 
     # -- frame server --
 
-    def server_start(self, budget_bytes, precision="bf16", max_inflight=4):
-        cfg = nis_server_cfg(int(budget_bytes), PRECISIONS.get(precision, precision), int(max_inflight))
+    def server_start(self, budget_bytes, precision="bf16", max_inflight=4, batch_gather=False):
+        cfg = nis_server_cfg(int(budget_bytes), PRECISIONS.get(precision, precision), int(max_inflight),
+                             1 if batch_gather else 0, 0)
         _check(_lib.nis_server_start(self.h, ctypes.byref(cfg)))
 
     @staticmethod

@@ -206,8 +206,8 @@ def _requests(m32, m64):
     ]
 
 
-def _serve(ctx, reqs, max_inflight, budget=1 << 32, precision="bf16"):
-    ctx.server_start(budget, precision, max_inflight)
+def _serve(ctx, reqs, max_inflight, budget=1 << 32, precision="bf16", batch_gather=False):
+    ctx.server_start(budget, precision, max_inflight, batch_gather=batch_gather)
     try:
         ids = [ctx.submit(m, cam, l, rad, g, seed) for m, cam, l, rad, g, seed in reqs]
         out = []
@@ -243,6 +243,35 @@ def test_server_frames_alone_and_in_a_mix_are_identical(ctx):
         np.testing.assert_array_equal(img, a)
         assert np.count_nonzero(img) <= na
     ctx.set_precision("fp32")
+    ctx.unload_medium(m64)
+    ctx.unload_medium(m32)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp32", "fp8"])
+def test_server_batch_gather_equals_frames_alone(ctx, precision):
+    """With batch_gather, the frames admitted together share one gather
+    launch; each image equals, bit for bit, the frame served alone without
+    batching.  The mix includes volume phases and a frame too large to batch
+    (1500 x 1500 pixels, more than 2^21), which runs on its own."""
+    print("server batch gather %s" % precision, flush=True)
+    nis = nis_mod()
+    w = configs.SMALL
+    ctx.set_weights(w.params())
+    m32 = ctx.load_medium(w.density(), 8.0, 0.99, 0.85)
+    m64 = ctx.load_medium(medium.fbm_cloud(64, seed=4), 6.0, 0.95, 0.85)
+    ctx.set_volume_phase(m64, True)
+    if precision == "fp8":
+        p, d = camera.random_points(4096, seed=3)
+        ctx.set_light(m32, (0.3, 0.9, 0.3), 1.0)
+        ctx.calibrate_fp8(m32, torch.from_numpy(p).cuda(), torch.from_numpy(d).cuda())
+    reqs = _requests(m32, m64) + [(m32, nis.camera(1500, 1500, 30.0, eye=(0.5, 0.5, 2.5)), (0.2, 0.9, -0.3),
+                                   1.0, 0.8, 9)]
+    alone = [_serve(ctx, [r], 1, budget=1 << 36, precision=precision)[0] for r in reqs]
+    for inflight in (4, 7):
+        mix = _serve(ctx, reqs, inflight, budget=1 << 36, precision=precision, batch_gather=True)
+        for (a, na, _), (b, nb, _) in zip(alone, mix):
+            assert na == nb
+            np.testing.assert_array_equal(a, b)
     ctx.unload_medium(m64)
     ctx.unload_medium(m32)
 
