@@ -157,9 +157,32 @@ int32_t nis_unload_medium(nis_ctx *ctx, int32_t medium);
  * intensity `radiance`.  Marks the graded transmittance fields (eq. 1) stale;
  * they are recomputed by the sweep at the next query, or now with NIS_EAGER
  * (then queued on the context's own stream, ordered before later calls).
+ * NIS_E_UNSUPPORTED when the light's state passes the kernels' offset limits
+ * (see nis_light_footprint), NIS_E_NOMEM when it does not fit in HBM.
  */
 int32_t nis_set_light(nis_ctx *ctx, int32_t medium, const float dir[3], float radiance,
                       int32_t flags);
+
+/*
+ * nis_light_footprint -- the device memory one light's state takes for an n^3
+ * medium, computed on the host (no context, no GPU): the path-density pairs of
+ * every level (the sheared rays of the transmittance fields of eq. 1, stored
+ * as pairs along V), the light-axis density pairs, and, for a light whose
+ * dominant axis is x, a transposed copy of the density pyramid.  The per-light
+ * tables (under 1 MiB) are not counted.  The state is held by every medium
+ * under a light, and by each frame-server slot for its frame's light.
+ * `n`: the medium's edge, a power of two in [1,1024]; `dir`: towards the light,
+ * any non-zero finite length.  Writes the total to *bytes_out and, when
+ * `level_bytes` is not NULL, the path-density pair bytes of each level m
+ * (edge n >> m) to level_bytes[m], for log2(n) + 1 levels (at most 11).
+ * A finest level's path-density pairs may pass 4 GiB (a 512^3 medium under a
+ * light near a cube diagonal); the kernels need each slice of them, the
+ * light-axis pairs and the densities of a level below 4 GiB.
+ * Errors: NIS_E_INVALID (bytes_out NULL, bad n or direction), NIS_E_UNSUPPORTED
+ * (the light's layout passes those limits: every light at n = 1024), the same
+ * code nis_set_light returns for that medium and light.
+ */
+int32_t nis_light_footprint(int32_t n, const float dir[3], int64_t *bytes_out, int64_t *level_bytes);
 
 /*
  * nis_set_weights -- network parameters (Fig. 3, Fig. 6, eq. 24-26) as one

@@ -249,7 +249,7 @@ __device__ __forceinline__ uint8_t fp8_code(float x)
 //
 // The body takes the workgroup's index within its query's grid, so that one
 // launch can serve several queries (k_features_multi).
-template <int PREC, bool DBG, bool F8>
+template <int PREC, bool DBG, bool F8, bool BIG>
 __device__ __forceinline__ void features_body(const FeatArgs& A, int64_t block)
 {
     typedef Mfma<PREC> M;
@@ -433,9 +433,13 @@ __device__ __forceinline__ void features_body(const FeatArgs& A, int64_t block)
         const int rsize = nm * nm * nm;
         const __amdgpu_buffer_rsrc_t rR =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(mv.rho + lv.rho_off), 0, rsize * 4, kBufferFlags);
-        // the path-density pairs of the level: below 2^32 bytes (the light's
-        // layout refuses larger fields), so sizes and offsets are unsigned
+        // the path-density pairs of the level: below 2^32 bytes but for the
+        // finest level of a 512^3 medium under a light near a diagonal (BIG
+        // launches, where such a level is read through 64-bit addresses);
+        // sizes and offsets are unsigned
         const uint32_t qrow = (uint32_t)lv.nu * (lv.nv + 1);
+        const bool qbig = BIG && (uint64_t)qrow * nm * 8 >= ((uint64_t)1 << 32);
+        const float* qbase = reinterpret_cast<const float*>(mv.dpairs + lv.q_off);
         const __amdgpu_buffer_rsrc_t rQ =
             __builtin_amdgcn_make_buffer_rsrc(mv.dpairs + lv.q_off, 0, (int)(qrow * nm * 8), kBufferFlags);
         auto ldQ = [&](uint32_t o) {
@@ -523,7 +527,15 @@ __device__ __forceinline__ void features_body(const FeatArgs& A, int64_t block)
                     const int J = clampi(Q.ij - 4 + loc / 3, 0, nm - 1);
                     const int Vp = clampi(Q.iv - 1 + 2 * (loc % 3) - lv.vlo, 0, lv.nv);
                     const int U0 = Q.iu - 2 - lv.ulo;
-                    if (U0 >= 0 && U0 + 5 < lv.nu) {
+                    if (qbig) {
+                        const float* q = qbase + ((int64_t)J * qrow + (int64_t)Vp * lv.nu) * 2;
+#pragma unroll
+                        for (int u = 0; u < 6; u++) {
+                            const int64_t o = (int64_t)clampi(U0 + u, 0, lv.nu - 1) * 2;
+                            dv[it][2 * u] = q[o];
+                            dv[it][2 * u + 1] = q[o + 1];
+                        }
+                    } else if (U0 >= 0 && U0 + 5 < lv.nu) {
                         const uint32_t o = ((uint32_t)J * qrow + (uint32_t)Vp * lv.nu + U0) * 2;
 #pragma unroll
                         for (int e = 0; e < 12; e++) dv[it][e] = ldQ(o + e);
@@ -889,23 +901,33 @@ __device__ __forceinline__ void features_body(const FeatArgs& A, int64_t block)
     }
 }
 
-template <int PREC, bool DBG, bool F8>
+template <int PREC, bool DBG, bool F8, bool BIG>
 __global__ void __launch_bounds__(64, 3)
 k_features(FeatArgs A)
 {
-    features_body<PREC, DBG, F8>(A, blockIdx.x);
+    features_body<PREC, DBG, F8, BIG>(A, blockIdx.x);
 }
 
 // Several queries in one launch: query r's workgroups are first[r] ..
 // first[r + 1] - 1 (each count a multiple of 8, so that a workgroup's XCD is
 // the one its own grid would give it); its arguments are read from the table.
-template <int PREC, bool F8>
+template <int PREC, bool F8, bool BIG>
 __global__ void __launch_bounds__(64, 3)
 k_features_multi(FeatMulti M)
 {
     int r = 0;
     for (int i = 1; i < M.n; i++) r = (int)blockIdx.x >= M.first[i] ? i : r;
-    features_body<PREC, false, F8>(M.table[r], (int64_t)blockIdx.x - M.first[r]);
+    features_body<PREC, false, F8, BIG>(M.table[r], (int64_t)blockIdx.x - M.first[r]);
+}
+
+// whether a level of mv holds path-density pairs of 4 GiB or more
+bool big_fields(const MediumView& mv)
+{
+    for (int m = 0; m < mv.levels; m++) {
+        const Level& lv = mv.lev[m];
+        if ((uint64_t)lv.nu * (lv.nv + 1) * lv.n * 8 >= ((uint64_t)1 << 32)) return true;
+    }
+    return false;
 }
 
 // ---- the gather at the paper's own templates (Sec. III.B.2, eq. 2-4) -----
@@ -1283,17 +1305,15 @@ hipError_t launch_desc_to_f32(int prec, const void* src, float* dst, int64_t n, 
 
 int64_t features_blocks(int64_t npts) { return ((npts + kTP - 1) / kTP + kXcds - 1) / kXcds * kXcds; }
 
-hipError_t launch_features_multi(int prec, const FeatMulti& m, hipStream_t s)
+hipError_t launch_features_multi(int prec, const FeatMulti& m, bool big, hipStream_t s)
 {
     if (m.n <= 0 || m.n > kMaxBatch) return hipErrorInvalidValue;
     const int blocks = m.first[m.n];
     if (blocks <= 0) return hipSuccess;
-    if (prec == kPrecFP8)
-        hipLaunchKernelGGL((k_features_multi<kPrecBF16, true>), dim3(blocks), dim3(64), 0, s, m);
-    else if (prec == kPrecBF16)
-        hipLaunchKernelGGL((k_features_multi<kPrecBF16, false>), dim3(blocks), dim3(64), 0, s, m);
-    else
-        hipLaunchKernelGGL((k_features_multi<kPrecFP32, false>), dim3(blocks), dim3(64), 0, s, m);
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(blocks), dim3(64), 0, s, m); };
+    if (prec == kPrecFP8) big ? go(k_features_multi<kPrecBF16, true, true>) : go(k_features_multi<kPrecBF16, true, false>);
+    else if (prec == kPrecBF16) big ? go(k_features_multi<kPrecBF16, false, true>) : go(k_features_multi<kPrecBF16, false, false>);
+    else big ? go(k_features_multi<kPrecFP32, false, true>) : go(k_features_multi<kPrecFP32, false, false>);
     return hipGetLastError();
 }
 
@@ -1306,15 +1326,17 @@ hipError_t launch_features(int prec, const FeatArgs& a, hipStream_t s)
     if (dbg && !(a.dbg_tbar && a.dbg_rho && a.dbg_phi && a.dbg_stats && a.dbg_tp))
         return hipErrorInvalidValue;   // the debug variant writes every stage output
     // the FP8 path runs the CNN in BF16 and stores the descriptor as E4M3 codes
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3((int)blocks), dim3(64), 0, s, a); };
+    const bool big = big_fields(a.mv);
     if (prec == kPrecFP8) {
-        if (dbg) hipLaunchKernelGGL((k_features<kPrecBF16, true, true>), dim3((int)blocks), dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_features<kPrecBF16, false, true>), dim3((int)blocks), dim3(64), 0, s, a);
+        if (dbg) big ? go(k_features<kPrecBF16, true, true, true>) : go(k_features<kPrecBF16, true, true, false>);
+        else big ? go(k_features<kPrecBF16, false, true, true>) : go(k_features<kPrecBF16, false, true, false>);
     } else if (prec == kPrecBF16) {
-        if (dbg) hipLaunchKernelGGL((k_features<kPrecBF16, true, false>), dim3((int)blocks), dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_features<kPrecBF16, false, false>), dim3((int)blocks), dim3(64), 0, s, a);
+        if (dbg) big ? go(k_features<kPrecBF16, true, false, true>) : go(k_features<kPrecBF16, true, false, false>);
+        else big ? go(k_features<kPrecBF16, false, false, true>) : go(k_features<kPrecBF16, false, false, false>);
     } else {
-        if (dbg) hipLaunchKernelGGL((k_features<kPrecFP32, true, false>), dim3((int)blocks), dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_features<kPrecFP32, false, false>), dim3((int)blocks), dim3(64), 0, s, a);
+        if (dbg) big ? go(k_features<kPrecFP32, true, false, true>) : go(k_features<kPrecFP32, true, false, false>);
+        else big ? go(k_features<kPrecFP32, false, false, true>) : go(k_features<kPrecFP32, false, false, false>);
     }
     return hipGetLastError();
 }

@@ -122,14 +122,17 @@ k_sweep(MediumView mv, SweepArgs sa)
     const double hi = n - 0.5;
     const double dU = (double)(lv.ulo + iu), dV = (double)(lv.vlo + V0 - 1);   // sampled ray k is V = dV + k
     const bool lane_out = iu < nu;
-    // byte sizes and offsets within a level stay below 2^32 (the light's
-    // layout refuses larger fields); unsigned, so that they wrap as the
-    // hardware's 32-bit buffer offsets do rather than overflow
+    // byte sizes and offsets within a level's density and within one slice
+    // of its path-density pairs stay below 2^32 (the light's layout refuses
+    // larger ones); a level's pairs may pass 4 GiB (512^3 under a light near
+    // a diagonal), so each slice's stores use a resource based at the slice
     const uint32_t qplane = (uint32_t)nu * (nv + 1) * 8;
     const __amdgpu_buffer_rsrc_t rR = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<float*>(mv.rho_s + lv.rho_off), 0, (int)((uint32_t)n * n * n * 4), kBufFlags);
-    const __amdgpu_buffer_rsrc_t rQ =
-        __builtin_amdgcn_make_buffer_rsrc(mv.dpairs + lv.q_off, 0, (int)(n * qplane), kBufFlags);
+    auto slice_rsrc = [&](int J) {
+        return __builtin_amdgcn_make_buffer_rsrc(mv.dpairs + lv.q_off + (int64_t)J * nu * (nv + 1), 0, (int)qplane,
+                                                 kBufFlags);
+    };
     auto ld = [&](int off) { return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rR, off, 0, 0)); };
     // When the lateral axis b is x, the two samples u0, u0+1 of a density row
     // are adjacent floats: one 8-byte load from clamp(u0, 0, n-2) then holds
@@ -256,12 +259,13 @@ k_sweep(MediumView mv, SweepArgs sa)
                     neumaier(sm[k], cp[k], rs[j][k]);
                 }
                 if (lane_out) {
+                    const __amdgpu_buffer_rsrc_t rQ = slice_rsrc(J);   // J is the same on every lane
 #pragma unroll
                     for (int k = 1; k < K; k++) {
                         const int iv = V0 + k - 1;
                         if (iv < nv) {
                             const float dm = iv == 0 ? d[k] : d[k - 1];
-                            const uint32_t oq = J * qplane + o0 + (uint32_t)(k - 1) * nu * 8;
+                            const uint32_t oq = o0 + (uint32_t)(k - 1) * nu * 8;
                             __builtin_amdgcn_raw_buffer_store_b64(u32x2{__float_as_uint(dm), __float_as_uint(d[k])},
                                                                   rQ, (int)oq, 0, kStream);
                             if (iv == nv - 1)

@@ -123,7 +123,9 @@ hipError_t launch_volume_tables(const MediumView& mv, const GaussLegendre64& gl,
                                 hipStream_t s);
 hipError_t launch_features(int prec, const FeatArgs& a, hipStream_t s);
 int64_t features_blocks(int64_t npts);   // workgroups launch_features uses for npts points
-hipError_t launch_features_multi(int prec, const FeatMulti& m, hipStream_t s);
+// big: some query's medium holds a level of path-density pairs of 4 GiB or more
+hipError_t launch_features_multi(int prec, const FeatMulti& m, bool big, hipStream_t s);
+bool big_fields(const MediumView& mv);
 // L[i] = radiance (f0[i] + albedo_gamma expm1(y[i])) for n points (the backbone's decode)
 hipError_t launch_decode(const float* y, const float* f0, int64_t n, float radiance, float albedo_gamma, float* out,
                          hipStream_t s);

@@ -713,6 +713,35 @@ Params with_templates(const nis_ctx* ctx, Params P)
     return P;
 }
 
+// The levels of an n^3 medium's pyramid (edge n >> m, densities at rho_off);
+// returns their count.
+int pyramid_levels(Medium* M, int n)
+{
+    int L = 1;
+    while ((1 << (L - 1)) < n) L++;
+    M->n = n;
+    M->levels = L;
+    int64_t off = 0;
+    for (int m = 0; m < L; m++) {
+        M->lev[m].n = n >> m;
+        M->lev[m].rho_off = off;
+        const int64_t nm = n >> m;
+        off += nm * nm * nm;
+    }
+    M->rho_floats = off;
+    return L;
+}
+
+// A light direction normalised, or NIS_E_INVALID.
+void unit_light(const float dir[3], double l[3])
+{
+    if (!dir || !finite3(dir)) fail(NIS_E_INVALID, "light must be finite");
+    for (int d = 0; d < 3; d++) l[d] = dir[d];
+    const double nrm = std::sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]);
+    if (!(nrm > 0.0)) fail(NIS_E_INVALID, "light direction is zero");
+    for (int d = 0; d < 3; d++) l[d] /= nrm;
+}
+
 void light_layout(const Medium* M, const double l[3], LightState* ls)
 {
     for (int d = 0; d < 3; d++) ls->l[d] = l[d];
@@ -742,11 +771,15 @@ void light_layout(const Medium* M, const double l[3], LightState* ls)
         lv.p_off = poff;
         lv.q_off = qoff;
         lv.ds = (float)((1.0 / lv.n) / ls->la);
-        // the gather addresses each level's fields with 32-bit byte offsets
+        // the kernels address a level's density and light-axis pairs, and one
+        // slice of its path-density pairs, with 32-bit byte offsets (a whole
+        // level of path-density pairs may pass 4 GiB: the gather then reads it
+        // through 64-bit addresses)
         const int64_t pn = (int64_t)(lv.n + 1) * lv.n * (lv.n + 2 * kPairPad);
         const int64_t qn = (int64_t)lv.nu * (lv.nv + 1) * lv.n;
-        if (qn * 8 >= ((int64_t)1 << 32) || pn * 8 >= ((int64_t)1 << 32) || (int64_t)lv.n * lv.n * lv.n * 4 >= ((int64_t)1 << 32))
-            fail(NIS_E_UNSUPPORTED, "a level's fields exceed 4 GiB for this light (media up to 512^3 are served)");
+        if ((int64_t)lv.nu * (lv.nv + 1) * 8 >= ((int64_t)1 << 32) || pn * 8 >= ((int64_t)1 << 32) ||
+            (int64_t)lv.n * lv.n * lv.n * 4 >= ((int64_t)1 << 32))
+            fail(NIS_E_UNSUPPORTED, "a level's fields exceed the 32-bit offsets for this light (media up to 512^3 are served)");
         poff += pn;
         qoff += qn;
     }
@@ -1262,17 +1295,8 @@ int32_t nis_load_medium(nis_ctx* ctx, const float* density, int32_t n, float sig
             for (int c = 0; c < 3; c++) M->albedo_rgb[c] = albedo;
             M->phase = single_lobe(g);
             M->rmax = rmax;
-            int L = 1;
-            while ((1 << (L - 1)) < n) L++;
-            M->levels = L;
-            int64_t off = 0;
-            for (int m = 0; m < L; m++) {
-                M->lev[m].n = n >> m;
-                M->lev[m].rho_off = off;
-                int64_t nm = n >> m;
-                off += nm * nm * nm;
-            }
-            M->rho_floats = off;
+            const int L = pyramid_levels(M, n);
+            const int64_t off = M->rho_floats;
             M->rho.reserve((size_t)off * sizeof(float), "density pyramid");
             hip_check(hipMemcpyAsync(M->rho.p, density, (size_t)n3 * sizeof(float), hipMemcpyHostToDevice,
                                      ctx->stream), "density upload");
@@ -1386,17 +1410,37 @@ int32_t nis_set_light(nis_ctx* ctx, int32_t medium, const float dir[3], float ra
         check_ctx(ctx);
         std::lock_guard<std::mutex> lk(ctx->mu);
         Medium* M = get_medium(ctx, medium);
-        if (!dir || !finite3(dir) || !std::isfinite(radiance)) fail(NIS_E_INVALID, "light must be finite");
-        double l[3] = {dir[0], dir[1], dir[2]};
-        double nrm = std::sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]);
-        if (!(nrm > 0.0)) fail(NIS_E_INVALID, "light direction is zero");
-        for (int d = 0; d < 3; d++) l[d] /= nrm;
+        if (!std::isfinite(radiance)) fail(NIS_E_INVALID, "light must be finite");
+        double l[3];
+        unit_light(dir, l);
         set_light_state(M, l, &M->light);
         M->radiance = radiance;
         if (flags & NIS_EAGER) {
             StreamUse su(ctx, ctx->stream);
             ensure_sweep(M, &M->light, su.s);
         }
+    });
+}
+
+int32_t nis_light_footprint(int32_t n, const float dir[3], int64_t* bytes_out, int64_t* level_bytes)
+{
+    return guard([&] {
+        if (!bytes_out) fail(NIS_E_INVALID, "bytes_out is NULL");
+        if (n < 1 || n > 1024 || (n & (n - 1)) != 0) fail(NIS_E_INVALID, "n must be a power of two in [1,1024]");
+        double l[3];
+        unit_light(dir, l);
+        // the layout alone: no device memory is touched
+        Medium M;
+        pyramid_levels(&M, n);
+        LightState ls;
+        light_layout(&M, l, &ls);
+        *bytes_out = ls.dpair_count * (int64_t)sizeof(float2) + ls.pair_count * (int64_t)sizeof(float2) +
+                     ls.rt_floats * (int64_t)sizeof(float);
+        if (level_bytes)
+            for (int m = 0; m < M.levels; m++) {
+                const Level& lv = ls.lev[m];
+                level_bytes[m] = (int64_t)lv.nu * (lv.nv + 1) * lv.n * (int64_t)sizeof(float2);
+            }
     });
 }
 
@@ -1675,7 +1719,9 @@ int32_t nis_query_batch(nis_ctx* ctx, const nis_query_item* items, int32_t count
         hip_check(hipMemcpyAsync(ctx->batch_tab.p, tab.data(), sizeof(FeatArgs) * count, hipMemcpyHostToDevice, s),
                   "batch table");
         fm.table = ctx->batch_tab.as<FeatArgs>();
-        timed("features", s, [&] { return launch_features_multi(prec, fm, s); });
+        bool big = false;
+        for (int32_t i = 0; i < count; i++) big |= big_fields(tab[i].mv);
+        timed("features", s, [&] { return launch_features_multi(prec, fm, big, s); });
         // one backbone pass over every query's rows, then each query's decode
         MlpArgs ma = mlp_args(net, prec);
         ma.x = ws.desc.p;

@@ -276,7 +276,9 @@ void launch_batch(nis_ctx* ctx, Server* S, const std::vector<std::pair<int, uint
     hip_check(hipMemcpyAsync(S->btab[b].p, tab.data(), sizeof(FeatArgs) * n, hipMemcpyHostToDevice, bs),
               "batch table");
     fm.table = S->btab[b].as<FeatArgs>();
-    hip_check(launch_features_multi(prec, fm, bs), "features");
+    bool big = false;
+    for (int i = 0; i < n; i++) big |= big_fields(tab[i].mv);
+    hip_check(launch_features_multi(prec, fm, big, bs), "features");
     hip_check(hipEventRecord(S->gathered, bs), "hipEventRecord");
     // each frame's backbone and image on its own stream
     for (int i = 0; i < n; i++) {

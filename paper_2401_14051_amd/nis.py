@@ -84,6 +84,7 @@ _SIGNATURES = {
     "nis_set_medium_params": [_vp, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float],
     "nis_unload_medium": [_vp, _i32],
     "nis_set_light": [_vp, _i32, _vp, ctypes.c_float, _i32],
+    "nis_light_footprint": [_i32, _vp, ctypes.POINTER(_i64), _vp],
     "nis_set_phase_lobes": [_vp, _i32, _i32, _vp, _vp],
     "nis_set_volume_phase": [_vp, _i32, _i32],
     "nis_set_albedo_rgb": [_vp, _i32, _vp],
@@ -220,6 +221,17 @@ def camera(width, height, vfov_deg=45.0, eye=(0.5, 0.5, 2.0), target=(0.5, 0.5, 
     c.ortho_z = float(ortho_z)
     c.width, c.height = int(width), int(height)
     return c
+
+
+def light_footprint(n, direction):
+    """Device bytes of one light's state for an n^3 medium: {"total": bytes,
+    "levels": path-density pair bytes of each level}.  Host-only."""
+    d = np.ascontiguousarray(direction, np.float32)
+    total = _i64()
+    levels = np.zeros(11, np.int64)
+    _check(_lib.nis_light_footprint(int(n), _ptr(d), ctypes.byref(total), _ptr(levels)))
+    L = int(n).bit_length()
+    return {"total": total.value, "levels": [int(v) for v in levels[:L]]}
 
 
 def _memcpy_d2d(dst, src, nbytes):

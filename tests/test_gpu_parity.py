@@ -539,3 +539,61 @@ def test_device_query_on_a_torch_stream(ctx):
     stream.synchronize()
     np.testing.assert_array_equal(out.cpu().numpy(), host)
     s.close()
+
+
+def test_diagonal_light_past_4gib_at_512(ctx):
+    """A 512^3 medium under a light along the cube's diagonal: its finest
+    level's path-density pairs take 4.3 GB, past what one 32-bit buffer offset
+    reaches.  The sweep's slices beyond the 4 GiB mark hold the oracle's path
+    density (rel 2e-6 of the maximum), and the gather reads them: features,
+    FP32 radiance (rel-L2 1e-4) and the paper templates' FP32 radiance at points
+    near the face away from the light, whose lattices reach those slices, match
+    the oracle."""
+    from paper_2401_14051_amd import nis
+    light = (1.0, 1.0, 1.0)
+    fp = nis.light_footprint(512, light)
+    assert fp["levels"][0] >= 1 << 32
+    print("diagonal light 512^3: level 0 pairs %d bytes" % fp["levels"][0], flush=True)
+    s = Scene(ctx, configs.LARGE.density(), light)
+    got, grng = ctx.path_density(s.mid, 0)
+    ref, rng = s.om.path_density(0)
+    assert grng == rng and got.shape == ref.shape
+    row_bytes = (got.shape[2] + 4) * (got.shape[1] + 1) * 8
+    assert row_bytes * 512 == fp["levels"][0]
+    first = (1 << 32) // row_bytes             # the slice that straddles the mark
+    assert first < 511
+    scale = float(ref.max())
+    for J in [0, 200] + list(range(first - 2, 512)):
+        np.testing.assert_allclose(got[J], ref[J], rtol=0, atol=2e-6 * scale, err_msg="slice %d" % J)
+    del got, ref
+    print("diagonal light 512^3: path density ok (slices from %d)" % first, flush=True)
+    # the light's dominant axis is x and points towards +x: slices of large J
+    # lie at small x
+    r = np.random.default_rng(17)
+    pts = np.concatenate([np.column_stack([r.uniform(0.0, 0.012, 384), r.uniform(0.05, 0.95, (384, 2))]),
+                          r.uniform(0.0, 1.0, (128, 3))]).astype(np.float32)
+    dirs = r.standard_normal((512, 3))
+    dirs = (dirs / np.linalg.norm(dirs, axis=1, keepdims=True)).astype(np.float32)
+    params = weights.he_init(16, 3, seed=1)
+    ctx.set_weights(params)
+    ref = s.oracle_features(params, pts, dirs)
+    got = {k: v.cpu().numpy().astype(np.float64) for k, v in ctx.features(s.mid, dev(pts), dev(dirs)).items()}
+    np.testing.assert_array_equal(got["rho"] == 0, ref["rho"] == 0)
+    np.testing.assert_allclose(got["rho"], ref["rho"], rtol=0, atol=2e-6)
+    np.testing.assert_allclose(got["tbar"], ref["tbar"], rtol=2e-5, atol=1e-6)
+    np.testing.assert_allclose(got["stats"], ref["stats"], rtol=2e-5, atol=2e-6)
+    np.testing.assert_allclose(got["tp"], ref["tp"], rtol=2e-5, atol=1e-7)
+    # the points' sites reach the slices past the mark
+    assert ref["tbar"].min() < 0.99
+    ctx.set_precision("fp32")
+    L = ctx.query(s.mid, pts, dirs)
+    err = rel_l2(L, s.oracle_query(params, pts, dirs)["L"])
+    ctx.set_templates("paper")
+    try:
+        Lt = ctx.query(s.mid, pts, dirs)
+    finally:
+        ctx.set_templates("lattice")
+    err_t = rel_l2(Lt, s.oracle_tpl_query(params, pts, dirs)["L"])
+    print("diagonal light 512^3: rel-L2 lattice %.3g templates %.3g" % (err, err_t), flush=True)
+    assert err <= 1e-4 and err_t <= 1e-4
+    s.close()

@@ -101,3 +101,43 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert int(got[name]) == ctypes.sizeof(cls), name
         for field, _ in cls._fields_:
             assert int(got[name + "." + field]) == getattr(cls, field).offset, (name, field)
+
+
+def test_light_footprint_on_the_host():
+    """The layout of one light's state, computed without a device.  Each
+    level's path-density pairs cover the oracle's ray ranges (its own ray
+    geometry) with 2 padding rays each side along U and one extra pair row
+    along V; a 512^3 medium under a diagonal light, whose finest level's pairs
+    pass 4 GiB, is served; 1024^3 media are not."""
+    from paper_2401_14051_amd import nis
+    from oracle import oracle
+    rho = np.random.default_rng(0).random((16, 16, 16)).astype(np.float32)
+    om = oracle.Medium(rho)
+    for light in [(0.3, 0.9, 0.3), (1.0, 1.0, 1.0), (0.0, 0.0, -1.0), (-0.7, 0.2, 0.4), (0.1, -0.3, -0.95)]:
+        om.set_light(np.asarray(light, np.float32))
+        fp = nis.light_footprint(16, light)
+        assert len(fp["levels"]) == om.levels == 5
+        for m in range(om.levels):
+            D, (u0, u1, v0, v1) = om.path_density(m)
+            nu, nv, nj = u1 - u0 + 1 + 4, v1 - v0 + 1, 16 >> m
+            assert D.shape == (nj, v1 - v0 + 1, u1 - u0 + 1)
+            assert fp["levels"][m] == nu * (nv + 1) * nj * 8, (light, m)
+    # a light dominated by x adds a transposed copy of the pyramid
+    pyramid = sum((512 >> m) ** 3 for m in range(10)) * 4
+    fx, fy = nis.light_footprint(512, (1.0, 0.2, 0.3)), nis.light_footprint(512, (0.2, 1.0, 0.3))
+    assert fx["levels"] == fy["levels"]
+    assert fx["total"] - fy["total"] == pyramid
+    diag = nis.light_footprint(512, (1.0, 1.0, 1.0))
+    assert diag["levels"][0] >= 1 << 32
+    assert diag["total"] > sum(diag["levels"])
+    for bad_n in (0, 3, 2048):
+        with pytest.raises(nis.NisError) as e:
+            nis.light_footprint(bad_n, (0.0, 1.0, 0.0))
+        assert e.value.code == nis.NIS_E_INVALID
+    for bad_dir in ((0.0, 0.0, 0.0), (float("nan"), 1.0, 0.0)):
+        with pytest.raises(nis.NisError) as e:
+            nis.light_footprint(64, bad_dir)
+        assert e.value.code == nis.NIS_E_INVALID
+    with pytest.raises(nis.NisError) as e:
+        nis.light_footprint(1024, (0.0, 1.0, 0.0))
+    assert e.value.code == nis.NIS_E_UNSUPPORTED
