@@ -46,7 +46,8 @@ namespace nis {
 
 constexpr int kTP = 4;                    // points per workgroup (one wave)
 constexpr int kXcds = 8;                  // accelerator complex dies of the MI355X
-constexpr int kCbFloats = 8 + 16 + 64 + 4 + 64 + 16;   // b1 b2 s1 c1 s2 c2
+constexpr int kCbFloats = 8 + 16 + 64 + 4 + 64 + 16;   // b1 b2 s1 c1 s2 c2 (in memory)
+constexpr int kCbLds = 8 + 16 + 4 + 16;                 // b1 b2 c1 c2 (in LDS)
 constexpr int kRows = 45;                 // site rows per point and layer
 constexpr int kLatRow = 12;               // three 4-wide windows of a 5-site row
 constexpr int kLatStride = kRows * kLatRow + 4;
@@ -61,8 +62,10 @@ struct PointLayer {           // per point and layer (path-density lookups)
 };
 
 struct SlabParams {           // per point, layer and slab q (density lookups)
-    int ia, cbase, bbase, mask;   // a base of the slab, first c and b of its brick; in-cube bits
-    float wa, wc, wb, pad;        // (0-4 i, 5-9 j, 10 slab) and the weights along a, c, b
+    int16_t ia, cbase, bbase;     // a base of the slab, first c and b of its brick (clamped to
+                                  // [-1, n], [-6, n], [-6, n]: the reads they give do not change)
+    uint16_t mask;                // in-cube bits (0-4 i, 5-9 j, 10 slab)
+    float wa, wc, wb;             // the weights along a, c, b
 };
 
 // Shared memory of one wave.  The lattice is dead once conv1 has read it, so
@@ -85,7 +88,7 @@ template <class E> struct FeatShared {
     double px[kTP][3];
     PointLayer pl[kTP];
     SlabParams sp[kTP][9];
-    float cb[kCbFloats];                       // the group's conv biases and attention weights
+    float cb[kCbLds];                          // the group's conv and attention biases
     uint16_t smask[kTP][kLayers][9];           // in-cube bits of every slab of every layer
     uint16_t posoff[kY1Pos];                   // conv1: lattice offset of output position p (the 64th = the 63rd)
     uint16_t goff[24];                         // conv1 (BF16): lattice offset of 4-slot K group g
@@ -115,7 +118,9 @@ __device__ __forceinline__ double hg64(const MediumView& mv, double mu)
     return v;
 }
 
-__device__ __forceinline__ float lerpf(float a, float b, float w) { return a + w * (b - a); }
+__device__ __forceinline__ float lerpf(float a, float b, float w) { return __builtin_fmaf(w, b - a, a); }
+// the same value from a and its step d = b - a (rounded as lerpf rounds it)
+__device__ __forceinline__ float lerp_step(float a, float d, float w) { return __builtin_fmaf(w, d, a); }
 
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
@@ -452,7 +457,7 @@ __device__ __forceinline__ void features_body(const FeatArgs& A, int64_t block)
             const E* w1 = reinterpret_cast<const E*>(A.w1t[grp]);
 #pragma unroll
             for (int kc = 0; kc < KC1; kc++) aw[kc] = M::load(w1 + lr * kConv1K + kc * M::KS + lg * M::KPL);
-            for (int e = ln; e < kCbFloats; e += 64) cbl[e] = A.cb[grp][e];
+            if (ln < kCbLds) cbl[ln] = A.cb[grp][ln < 24 ? ln : ln < 28 ? 88 + (ln - 24) : 156 + (ln - 28)];
         }
 
         // ---- set-up: sheared path-density bases (one lane per point) and the
@@ -475,14 +480,13 @@ __device__ __forceinline__ void features_body(const FeatArgs& A, int64_t block)
             const float w0 = (float)(t0 - f0), w1 = (float)(t1 - f1), w2 = (float)(t2 - f2);
             if (slab) {
                 SlabParams sp1;
-                sp1.ia = i0 + (qi - 4) * mv.sigma;
-                sp1.cbase = i2 - 2;
-                sp1.bbase = i1 - 2;
+                sp1.ia = (int16_t)clampi(i0 + (qi - 4) * mv.sigma, -1, nm);
+                sp1.cbase = (int16_t)clampi(i2 - 2, -6, nm);
+                sp1.bbase = (int16_t)clampi(i1 - 2, -6, nm);
                 sp1.mask = smask[spt][k][qi];
                 sp1.wa = w0;
                 sp1.wc = w2;
                 sp1.wb = w1;
-                sp1.pad = 0.f;
                 sp[spt][qi] = sp1;
             } else {
                 PointLayer q;
@@ -640,9 +644,10 @@ __device__ __forceinline__ void features_body(const FeatArgs& A, int64_t block)
         }
         // ---- densities and their statistics: lane q < 9 of each point's 16
         // takes slab q.  It loads the slab's brick rows c = cbase..+5 of 6
-        // samples b = bbase..+5 straight into registers, both a-planes side by
-        // side from the light-axis pairs (a row is 6 pairs, 48 contiguous
-        // bytes), interpolates along a with the slab's shared weight, then
+        // samples b = bbase..+5 straight into registers, an a-plane and its
+        // step to the next side by side from the light-axis pairs (a row is 6
+        // pairs, 48 contiguous bytes), interpolates along a with the slab's
+        // shared weight, then
         // evaluates the slab's 5 site rows (c, then b) and accumulates their
         // statistics.  The single-voxel level reads its voxel once.
         float rs = 0.f, rmx = -INFINITY;
@@ -696,16 +701,32 @@ __device__ __forceinline__ void features_body(const FeatArgs& A, int64_t block)
 #pragma unroll
             for (int cc = 0; cc < kBrickV; cc++)
 #pragma unroll
-                for (int u = 0; u < 6; u++) R[cc][u] = lerpf(pr[cc][2 * u], pr[cc][2 * u + 1], S.wa);
+                for (int u = 0; u < 6; u++) R[cc][u] = lerp_step(pr[cc][2 * u], pr[cc][2 * u + 1], S.wa);
+            auto rows = [&](bool masked) __attribute__((always_inline)) {
 #pragma unroll
-            for (int jj = 0; jj < 5; jj++) {
-                float bb[6], Rv[5];
+                for (int jj = 0; jj < 5; jj++) {
+                    float bb[6], Rv[5];
 #pragma unroll
-                for (int u = 0; u < 6; u++) bb[u] = lerpf(R[jj][u], R[jj + 1][u], S.wc);
+                    for (int u = 0; u < 6; u++) bb[u] = lerpf(R[jj][u], R[jj + 1][u], S.wc);
 #pragma unroll
-                for (int i = 0; i < 5; i++) Rv[i] = lerpf(bb[i], bb[i + 1], S.wb);
-                accum(qi * 5 + jj, jj, S.mask, Rv);
-            }
+                    for (int i = 0; i < 5; i++) Rv[i] = lerpf(bb[i], bb[i + 1], S.wb);
+                    if (masked) {
+                        accum(qi * 5 + jj, jj, S.mask, Rv);
+                    } else {
+                        const int64_t p = tile0 + pt;
+#pragma unroll
+                        for (int i = 0; i < 5; i++) {
+                            rs += Rv[i];
+                            rmx = fmaxf(rmx, Rv[i]);
+                            if (DBG && p < npts) A.dbg_rho[(p * kLayers + k) * kSites + (qi * 5 + jj) * 5 + i] = Rv[i];
+                        }
+                    }
+                }
+            };
+            // when every site of every slab lane is inside the cube (interior
+            // points on the finer layers), the wave skips the in-cube selects
+            if (__ballot((S.mask & 0x7ff) != 0x7ff) == 0) rows(false);
+            else rows(true);
         }
 
         // ---- per-point statistics (eq. 24) over the point's 16 lanes ------------
@@ -795,6 +816,12 @@ __device__ __forceinline__ void features_body(const FeatArgs& A, int64_t block)
         }
         __syncthreads();
 
+        // the attention weights this lane needs (a row of 4 of s1, one of s2),
+        // from memory: requested now so that conv2 covers their latency, and
+        // kept out of LDS, which limits the waves per compute unit
+        const float4 s1v = *reinterpret_cast<const float4*>(A.cb[grp] + 24 + (lr & 3) * 16 + (lr & ~3));
+        const float4 s2v = *reinterpret_cast<const float4*>(A.cb[grp] + 92 + lr * 4);
+
         // ---- conv2: [rows = (point, z)] x [K = 27 taps x 8 channels] x [16 channels]
         {
             const float* b2 = cbl + 8;
@@ -825,7 +852,7 @@ __device__ __forceinline__ void features_body(const FeatArgs& A, int64_t block)
 
         // ---- squeeze-excitation gate and the layer's descriptor entries ---------
         {
-            const float *s1 = cbl + 24, *c1 = cbl + 88, *s2 = cbl + 92, *c2 = cbl + 156;
+            const float *c1 = cbl + 24, *c2 = cbl + 28;
             const int o = lr, pbase = lane & ~15;
             float hv[5];
 #pragma unroll
@@ -834,15 +861,16 @@ __device__ __forceinline__ void features_body(const FeatArgs& A, int64_t block)
             // hidden unit h = o % 4 over the inputs 4 (o/4) .. +3, summed over the
             // point's four lanes with the same h: every lane then holds unit o % 4
             const int h = o & 3, i0 = o & ~3;
+            const float s1r[4] = {s1v.x, s1v.y, s1v.z, s1v.w}, s2r[4] = {s2v.x, s2v.y, s2v.z, s2v.w};
             float part = 0.f;
 #pragma unroll
-            for (int d = 0; d < 4; d++) part += s1[h * 16 + i0 + d] * __shfl(zo, pbase | (i0 + d));
+            for (int d = 0; d < 4; d++) part += s1r[d] * __shfl(zo, pbase | (i0 + d));
             part += __shfl_xor(part, 4);
             part += __shfl_xor(part, 8);
             const float hid_h = fmaxf(part + c1[h], 0.f);
             float s = c2[o];
 #pragma unroll
-            for (int hh = 0; hh < 4; hh++) s += s2[o * 4 + hh] * __shfl(hid_h, pbase | hh);
+            for (int hh = 0; hh < 4; hh++) s += s2r[hh] * __shfl(hid_h, pbase | hh);
             // sigmoid with the hardware exponential and reciprocal (each about 1 ulp)
             const float gate = __builtin_amdgcn_rcpf(1.f + __expf(-s));
             // stage the 88 entries of the layer in the (now free) conv1 output
@@ -997,8 +1025,8 @@ __device__ __forceinline__ double tpl_coord(double x, double scale, double o)
 // density of level lv at s: zero outside the closed unit cube, else
 // index-clamped trilinear, from the light-axis density pairs: rows c and
 // c + 1, each one 16-byte load of the pairs at b and b + 1 (each pair holds
-// a and a + 1).  An in-cube site has -1 <= b <= n - 1, inside the stored
-// row's padding of index-clamped copies.
+// the density at a and its step to a + 1).  An in-cube site has
+// -1 <= b <= n - 1, inside the stored row's padding of index-clamped copies.
 __device__ __forceinline__ float tpl_rho(const MediumView& mv, const Level& lv, const double s[3])
 {
     if (s[0] < 0.0 || s[0] > 1.0 || s[1] < 0.0 || s[1] > 1.0 || s[2] < 0.0 || s[2] > 1.0) return 0.f;
@@ -1012,8 +1040,8 @@ __device__ __forceinline__ float tpl_rho(const MediumView& mv, const Level& lv, 
     const float4 q1 = *reinterpret_cast<const float4*>(P + (int64_t)clampi(ic + 1, 0, nm - 1) * nb);
     const float2 p00 = make_float2(q0.x, q0.y), p01 = make_float2(q0.z, q0.w);
     const float2 p10 = make_float2(q1.x, q1.y), p11 = make_float2(q1.z, q1.w);
-    const float r00 = lerpf(p00.x, p00.y, wa), r01 = lerpf(p01.x, p01.y, wa);
-    const float r10 = lerpf(p10.x, p10.y, wa), r11 = lerpf(p11.x, p11.y, wa);
+    const float r00 = lerp_step(p00.x, p00.y, wa), r01 = lerp_step(p01.x, p01.y, wa);
+    const float r10 = lerp_step(p10.x, p10.y, wa), r11 = lerp_step(p11.x, p11.y, wa);
     return lerpf(lerpf(r00, r01, wb), lerpf(r10, r11, wb), wc);
 }
 

@@ -388,10 +388,12 @@ hipError_t launch_volume_tables(const MediumView& mv, const GaussLegendre64& gl,
 
 // Light-axis density pairs (a layout of the pyramid for the gather): for each
 // level, entry (A', c, b), A' = 0..n, b = -kPairPad..n-1+kPairPad, holds the
-// densities at a = A'-1 and a = A' along the light's dominant axis, each
-// index (b too) clamped into [0, n-1], stored with b fastest; so the two
-// a-planes of a density row sit side by side and a row of 6 pairs is 48
-// contiguous bytes whatever the light.
+// density at a = A'-1 and its step to a = A' along the light's dominant axis,
+// (rho(A'-1), rho(A') - rho(A'-1)), each index (b too) clamped into [0, n-1],
+// stored with b fastest; so the two a-planes of a density row sit side by
+// side, a row of 6 pairs is 48 contiguous bytes whatever the light, and the
+// gather's interpolation along a is one fused multiply-add (the same
+// rounding as rho0 + w (rho1 - rho0) evaluated there).
 // One thread per four neighbouring entries along b (n >= 4; smaller levels
 // one entry per thread): 16-byte loads of the two a-planes when b is x, two
 // 16-byte stores.
@@ -415,6 +417,8 @@ k_pairs(const float* __restrict__ rho, float2* __restrict__ out, int n, int lg, 
 #pragma unroll
         for (int e = 0; e < E; e++) v0[e] = r0[e * sb], v1[e] = r1[e * sb];
     }
+#pragma unroll
+    for (int e = 0; e < E; e++) v1[e] -= v0[e];   // the step along a
     // non-temporal stores: the pairs are read back only by the gather, long
     // after this pass, so they should not displace cached lines on the way
     const int nb = n + 2 * kPairPad;

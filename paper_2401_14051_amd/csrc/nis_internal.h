@@ -58,7 +58,7 @@ struct MediumView {
     const float* rho;   // density pyramid, each level [z][y][x]
     const float* rho_s; // the pyramid in the layout the sweep and the light-axis pairs read
     int se[3];          // its stride along axis d (0 = x, 1 = y, 2 = z) is n_m^se[d]
-    float2* pairs;      // per level [A' = 0..n][c][b + kPairPad < n + 2 kPairPad]: (rho(a = A'-1), rho(a = A')), index-clamped
+    float2* pairs;      // per level [A' = 0..n][c][b + kPairPad < n + 2 kPairPad]: (rho(a = A'-1), rho(a = A') - rho(a = A'-1)), index-clamped
     float2* dpairs;     // per level [J][V' = 0..nv][U]: (D(V'-1), D(V')), index-clamped
     Level lev[kMaxLevels];
     int levels;
