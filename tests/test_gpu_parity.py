@@ -541,20 +541,40 @@ def test_device_query_on_a_torch_stream(ctx):
     s.close()
 
 
-def test_diagonal_light_past_4gib_at_512(ctx):
-    """A 512^3 medium under a light along the cube's diagonal: its finest
-    level's path-density pairs take 4.3 GB, past what one 32-bit buffer offset
-    reaches.  The sweep's slices beyond the 4 GiB mark hold the oracle's path
-    density (rel 2e-6 of the maximum), and the gather reads them: features,
-    FP32 radiance (rel-L2 1e-4) and the paper templates' FP32 radiance at points
-    near the face away from the light, whose lattices reach those slices, match
-    the oracle."""
+@pytest.fixture(scope="module")
+def diag512(ctx):
+    """A 512^3 medium under a light along the cube's diagonal, loaded on both
+    sides; its finest level's path-density pairs take 4.3 GB."""
     from paper_2401_14051_amd import nis
     light = (1.0, 1.0, 1.0)
     fp = nis.light_footprint(512, light)
     assert fp["levels"][0] >= 1 << 32
     print("diagonal light 512^3: level 0 pairs %d bytes" % fp["levels"][0], flush=True)
     s = Scene(ctx, configs.LARGE.density(), light)
+    yield s, fp
+    s.close()
+
+
+def diag_points(n_face=384, n_any=128, seed=17):
+    """Points near the face away from the light (1,1,1), whose lattices reach
+    the finest level's last slices, and points anywhere in the cube."""
+    r = np.random.default_rng(seed)
+    pts = np.concatenate([np.column_stack([r.uniform(0.0, 0.012, n_face), r.uniform(0.05, 0.95, (n_face, 2))]),
+                          r.uniform(0.0, 1.0, (n_any, 3))]).astype(np.float32)
+    dirs = r.standard_normal((n_face + n_any, 3))
+    dirs = (dirs / np.linalg.norm(dirs, axis=1, keepdims=True)).astype(np.float32)
+    return pts, dirs
+
+
+def test_diagonal_light_past_4gib_at_512(ctx, diag512):
+    """The 512^3 medium under the diagonal light: its finest level's
+    path-density pairs pass what one 32-bit buffer offset reaches.  The
+    sweep's slices beyond the 4 GiB mark hold the oracle's path density (rel
+    2e-6 of the maximum), and the gather reads them: features, FP32 radiance
+    (rel-L2 1e-4) and the paper templates' FP32 radiance at points near the
+    face away from the light, whose lattices reach those slices, match the
+    oracle."""
+    s, fp = diag512
     got, grng = ctx.path_density(s.mid, 0)
     ref, rng = s.om.path_density(0)
     assert grng == rng and got.shape == ref.shape
@@ -569,11 +589,7 @@ def test_diagonal_light_past_4gib_at_512(ctx):
     print("diagonal light 512^3: path density ok (slices from %d)" % first, flush=True)
     # the light's dominant axis is x and points towards +x: slices of large J
     # lie at small x
-    r = np.random.default_rng(17)
-    pts = np.concatenate([np.column_stack([r.uniform(0.0, 0.012, 384), r.uniform(0.05, 0.95, (384, 2))]),
-                          r.uniform(0.0, 1.0, (128, 3))]).astype(np.float32)
-    dirs = r.standard_normal((512, 3))
-    dirs = (dirs / np.linalg.norm(dirs, axis=1, keepdims=True)).astype(np.float32)
+    pts, dirs = diag_points()
     params = weights.he_init(16, 3, seed=1)
     ctx.set_weights(params)
     ref = s.oracle_features(params, pts, dirs)
@@ -596,4 +612,55 @@ def test_diagonal_light_past_4gib_at_512(ctx):
     err_t = rel_l2(Lt, s.oracle_tpl_query(params, pts, dirs)["L"])
     print("diagonal light 512^3: rel-L2 lattice %.3g templates %.3g" % (err, err_t), flush=True)
     assert err <= 1e-4 and err_t <= 1e-4
-    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_diagonal_light_512_in_batches_and_frames(ctx, diag512, prec):
+    """The gather's 64-bit path inside shared launches: a query batch over the
+    diagonal-light 512^3 medium and a 32^3 medium equals their single queries,
+    and frames of both from the frame server with batch_gather (small frames
+    admitted together share one gather) equal their synchronous renders, bit
+    for bit."""
+    s, _ = diag512
+    print("diagonal light 512^3 in batches and frames %s" % prec, flush=True)
+    params = weights.he_init(16, 3, seed=1)
+    ctx.set_weights(params)
+    set_precision(ctx, prec)
+    small = ctx.load_medium(medium.fbm_cloud(32, seed=9), 8.0, 0.99, 0.85)
+    ctx.set_light(small, (0.3, 0.9, 0.3), 1.0)
+    try:
+        pts, dirs = diag_points(96, 64, seed=23)
+        qp, qd = dev(pts), dev(dirs)
+        singles = []
+        for m in (s.mid, small):
+            out = torch.empty(len(pts), dtype=torch.float32, device="cuda")
+            ctx.query_device(m, qp, qd, out)
+            singles.append(out)
+        outs = [torch.full((len(pts),), -1.0, device="cuda") for _ in range(2)]
+        ctx.query_batch([(s.mid, qp, qd, outs[0]), (small, qp, qd, outs[1])])
+        torch.cuda.synchronize()
+        for a, b in zip(outs, singles):
+            assert torch.equal(a, b)
+        # frames of both media through the server
+        from paper_2401_14051_amd import nis
+        cam = nis.camera(96, 96, 45.0)
+        reqs = [(s.mid, (1.0, 1.0, 1.0), 11), (small, (0.3, 0.9, 0.3), 12)]
+        ctx.server_start(1 << 36, prec, 4, batch_gather=True)
+        try:
+            ids = [ctx.submit(m, cam, l, 1.0, 0.85, seed) for m, l, seed in reqs]
+            served = []
+            for fid in ids:
+                r = ctx.wait(fid)
+                assert r.status == 0, r.status
+                served.append(ctx.frame_image(r).cpu().numpy())
+                ctx.release(fid)
+        finally:
+            ctx.server_stop()
+        for (m, l, seed), img in zip(reqs, served):
+            ctx.set_light(m, l, 1.0)
+            ref = ctx.render(m, cam, seed).cpu().numpy()
+            assert np.count_nonzero(ref) > 100
+            np.testing.assert_array_equal(img, ref)
+    finally:
+        ctx.set_precision("fp32")
+        ctx.unload_medium(small)
