@@ -1102,6 +1102,7 @@ k_template_features(TplArgs A)
     __shared__ double srad[kDiffuse];
     __shared__ int smd[kDiffuse];
     __shared__ int smh[kTplWaves][kLayers - kDiffuse];
+    __shared__ uint8_t slayer[kTplSites];      // the layer of each template site
     const MediumView& mv = A.mv;
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     if (threadIdx.x == 0) {
@@ -1116,6 +1117,7 @@ k_template_features(TplArgs A)
             smd[i] = A.mdiff[i];
         }
     }
+    for (int t = threadIdx.x; t < kTplSites; t += 64 * kTplWaves) slayer[t] = (uint8_t)tpl_layer_of(t);
     const int64_t npts = A.count ? min(max((int64_t)*A.count - A.count_off, (int64_t)0), A.npts) : A.npts;
     const int64_t p = (int64_t)blockIdx.x * kTplWaves + wave;
     if ((int64_t)blockIdx.x * kTplWaves >= npts) return;
@@ -1148,7 +1150,7 @@ k_template_features(TplArgs A)
     const float4 centre = make_float4((float)mv.l[0], (float)mv.l[1], (float)mv.l[2], 1.f);
 
     for (int t = lane; t < kTplSites; t += 64) {
-        const int k = tpl_layer_of(t);
+        const int k = slayer[t];
         const bool diffuse = k < kDiffuse;
         const double scale = diffuse ? srad[k] : dlen;
         const int m = diffuse ? smd[k] : smh[wave][k - kDiffuse];
