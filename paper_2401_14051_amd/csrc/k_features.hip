@@ -1084,7 +1084,7 @@ __constant__ TplModMap kTplModMap = make_tpl_mod_map();
 constexpr int kTplStage = 3 * kTplSites + kLayers * kStats;
 
 template <int PREC, bool DBG, bool F8>
-__global__ void __launch_bounds__(64 * kTplWaves)
+__global__ void __launch_bounds__(64 * kTplWaves) __attribute__((amdgpu_waves_per_eu(8)))
 k_template_features(TplArgs A)
 {
     typedef Mfma<PREC> M;
