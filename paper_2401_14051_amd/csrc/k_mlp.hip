@@ -74,10 +74,22 @@ k_mlp(MlpArgs A)
                 xr[rt] = x + r * kDescPad + lg * M::KPL;
             }
             float imx = 0.f;
-            for (int kc = 0; kc < KC; kc++) {
-                typename M::frag a[RT];
+            // the fragments of K step kc + 1 are requested before the MFMAs of
+            // step kc, so that their latency overlaps them
+            typename M::frag a[RT], b[NT], an[RT], bn[NT];
+            auto fetch = [&](int kc, typename M::frag* af, typename M::frag* bf) __attribute__((always_inline)) {
 #pragma unroll
-                for (int rt = 0; rt < RT; rt++) a[rt] = M::load(xr[rt] + kc * M::KS);
+                for (int rt = 0; rt < RT; rt++) af[rt] = M::load(xr[rt] + kc * M::KS);
+#pragma unroll
+                for (int ct = 0; ct < NT; ct++) bf[ct] = M::load(Wf + (ct * KC + kc) * FRAG);
+            };
+            fetch(0, an, bn);
+            for (int kc = 0; kc < KC; kc++) {
+#pragma unroll
+                for (int rt = 0; rt < RT; rt++) a[rt] = an[rt];
+#pragma unroll
+                for (int ct = 0; ct < NT; ct++) b[ct] = bn[ct];
+                if (kc + 1 < KC) fetch(kc + 1, an, bn);
                 if constexpr (PREC == kPrecFP32) {
                     if (track) {
 #pragma unroll
@@ -85,24 +97,30 @@ k_mlp(MlpArgs A)
                     }
                 }
 #pragma unroll
-                for (int ct = 0; ct < NT; ct++) {
-                    typename M::frag b = M::load(Wf + (ct * KC + kc) * FRAG);
+                for (int ct = 0; ct < NT; ct++)
 #pragma unroll
-                    for (int rt = 0; rt < RT; rt++) acc[rt][ct] = M::mma(a[rt], b, acc[rt][ct]);
-                }
+                    for (int rt = 0; rt < RT; rt++) acc[rt][ct] = M::mma(a[rt], b[ct], acc[rt][ct]);
             }
             if (track) publish(imx, 0);
         } else {
+            typename M::frag a[RT], b[NT], an[RT], bn[NT];
+            auto fetch = [&](int kc, typename M::frag* af, typename M::frag* bf) __attribute__((always_inline)) {
+#pragma unroll
+                for (int rt = 0; rt < RT; rt++) af[rt] = M::load(&h[rt * 16 + lr][kc * M::KS + lg * M::KPL]);
+#pragma unroll
+                for (int ct = 0; ct < NT; ct++) bf[ct] = M::load(Wf + (ct * KC + kc) * FRAG);
+            };
+            fetch(0, an, bn);
             for (int kc = 0; kc < KC; kc++) {
-                typename M::frag a[RT];
 #pragma unroll
-                for (int rt = 0; rt < RT; rt++) a[rt] = M::load(&h[rt * 16 + lr][kc * M::KS + lg * M::KPL]);
+                for (int rt = 0; rt < RT; rt++) a[rt] = an[rt];
 #pragma unroll
-                for (int ct = 0; ct < NT; ct++) {
-                    typename M::frag b = M::load(Wf + (ct * KC + kc) * FRAG);
+                for (int ct = 0; ct < NT; ct++) b[ct] = bn[ct];
+                if (kc + 1 < KC) fetch(kc + 1, an, bn);
 #pragma unroll
-                    for (int rt = 0; rt < RT; rt++) acc[rt][ct] = M::mma(a[rt], b, acc[rt][ct]);
-                }
+                for (int ct = 0; ct < NT; ct++)
+#pragma unroll
+                    for (int rt = 0; rt < RT; rt++) acc[rt][ct] = M::mma(a[rt], b[ct], acc[rt][ct]);
             }
         }
         __syncthreads();   // every lane's reads of h precede the in-place overwrite
